@@ -1,0 +1,184 @@
+/*
+ * uf.h -- C ABI of the MI355X (gfx950) implementation of one time step of
+ * the UrbanFlow incompressible RANS solver (Liu, Rist, Pottmann, Michels,
+ * "UrbanFlow: Designing Comfortable Outdoor Areas", arXiv 2204.01117).
+ *
+ * The library advances the mean flow (u, v, w, p) and the k-omega turbulence
+ * fields on a uniform staggered (MAC) grid.  Buildings and trees enter only
+ * through a per-cell porosity field (Sec. 3, unified porosity model), so the
+ * pressure Poisson matrix depends on the grid and boundary kinds alone and
+ * is set up once per grid.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array layouts are z fastest: element (i, j, k) of an (ex, ey, ez) array
+ *    sits at (i * ey + j) * ez + k.  Cell fields have extent (nx, ny, nz);
+ *    the face velocities u, v, w have (nx+1, ny, nz), (nx, ny+1, nz) and
+ *    (nx, ny, nz+1).  Face u(i, j, k) lies at (i dx, (j+1/2) dy, (k+1/2) dz).
+ *  - Every pointer named *_dev is a device pointer (hipMalloc'd or a torch
+ *    CUDA tensor) holding values in the grid's dtype (float for UF_F32,
+ *    double for UF_F64).  The library only borrows it for the duration of
+ *    the call; reads and writes are enqueued on the grid's stream, so the
+ *    caller must keep the memory alive until the stream reaches them.
+ *  - The handle owns all of its internal device buffers.
+ *  - Functions return a uf_status.  On an error the thread-local message is
+ *    available from uf_last_error().  Argument errors (UF_EINVAL) are
+ *    detected before anything is enqueued and leave the state unchanged.
+ *  - A handle must not be used from two host threads at once.
+ */
+#ifndef UF_H
+#define UF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct uf_grid_s* uf_grid;
+
+typedef enum {
+  UF_OK = 0,
+  UF_EINVAL = 1,      /* bad argument or configuration; nothing was enqueued   */
+  UF_ENOMEM = 2,      /* device allocation failed                               */
+  UF_EDEVICE = 3,     /* a HIP runtime call failed                              */
+  UF_ENOCONV = 4,     /* pressure CG stopped at cg_maxit; the step completed    */
+  UF_ENONFINITE = 5,  /* a NaN/Inf appeared in the pressure solve; step completed */
+  UF_ESTATE = 6,      /* call not valid in the handle's current state          */
+  UF_ENOTIMPL = 7     /* entry point declared but not provided by this build    */
+} uf_status;
+
+/* Boundary kind of each domain side, sides ordered -x, +x, -y, +y, -z, +z
+ * (-z is the ground).  Sec. 3 "Porosity Model vs. Solid-wall Boundary
+ * Conditions": Dirichlet velocity at an inlet, zero normal derivative at an
+ * outlet with zero pressure in the outlet ghost cells, no-slip at walls,
+ * zero normal pressure derivative at inlets and walls.  SLIP is a
+ * free-slip wall (zero normal velocity, zero tangential stress).
+ * UF_BC_AUTO: a vertical side is an inlet if the wind enters through it,
+ * an outlet otherwise; ground WALL, sky SLIP. */
+enum { UF_BC_AUTO = -1, UF_BC_INLET = 0, UF_BC_OUTLET = 1, UF_BC_WALL = 2, UF_BC_SLIP = 3 };
+enum { UF_F32 = 0, UF_F64 = 1 };
+enum { UF_TURB_OFF = 0, UF_TURB_KOMEGA = 1 };
+/* Pressure CG preconditioner: none, Jacobi, the first-order approximate
+ * inverse M^-1 = K^T K of Sec. 3 (full product, see uf_config.ai_omega),
+ * or a geometric multigrid V-cycle. */
+enum { UF_PC_NONE = 0, UF_PC_JACOBI = 1, UF_PC_AI1 = 2, UF_PC_MG = 4 };
+/* Inflow profile: uniform speed, the log-law of Sec. 5.1, or a table. */
+enum { UF_INFLOW_UNIFORM = 0, UF_INFLOW_LOGLAW = 1, UF_INFLOW_PROFILE = 2 };
+/* Stages of a step (Sec. 3 time splitting); all on by default. */
+enum { UF_STAGE_ADVECT = 1, UF_STAGE_DIFFUSE = 2, UF_STAGE_DRAG = 4,
+       UF_STAGE_PROJECT = 8, UF_STAGE_TURB = 16, UF_STAGE_ALL = 31 };
+
+typedef enum { UF_U = 0, UF_V = 1, UF_W = 2, UF_P = 3, UF_K = 4, UF_OMEGA = 5,
+               UF_NUT = 6, UF_PHI = 7 } uf_field;
+
+typedef struct {
+  int32_t nx, ny, nz;           /* cells per axis, each >= 1; nx, ny >= 2       */
+  double dx, dy, dz;            /* cell size in metres, > 0                     */
+  double dt;                    /* time step in seconds, > 0                    */
+  int32_t dtype;                /* UF_F32 or UF_F64 (storage and arithmetic)    */
+  int32_t bc[6];                /* side kinds; at least one side must be OUTLET */
+  int32_t inflow_kind;          /* UF_INFLOW_*                                  */
+  double u_ref, z_ref, z0, karman; /* log-law: u(z) = (u_fr / karman) ln(z/z0),
+                                    friction speed u_fr = u_ref karman /
+                                    ln(z_ref / z0); zero for z <= z0            */
+  double wind_dir_deg;          /* wind direction in the horizontal plane,
+                                   0 = +x, 90 = +y                              */
+  const double* inflow_profile; /* host array of nz speeds (UF_INFLOW_PROFILE);
+                                   copied during uf_create_grid                 */
+  double nu, rho;               /* kinematic viscosity, density                 */
+  int32_t turb_model;           /* UF_TURB_OFF keeps nu_t = 0                   */
+  double turb_I, turb_L;        /* inlet intensity and length scale (Sec. 3);
+                                   turb_L <= 0 selects 0.1 x domain height      */
+  double k_min, omega_min;      /* floors of k and omega                        */
+  double Cd, a, b, e;           /* drag law C_d a ((1 - phi)/(phi + e))^b       */
+  int32_t precond;              /* UF_PC_*                                      */
+  double ai_omega;              /* relaxation of the AI preconditioner, (0, 2)  */
+  double cg_tol;                /* stop at ||r|| <= cg_tol ||b|| (criterion 0)
+                                   or (M^-1 r . r) < cg_tol ||b||^2 (criterion 1,
+                                   the paper's appendix A.3 test)               */
+  int32_t cg_maxit;
+  int32_t cg_criterion;
+  int32_t stages;               /* UF_STAGE_* mask                              */
+  void* stream;                 /* hipStream_t used for all work; NULL = null stream */
+} uf_config;
+
+typedef struct {
+  int32_t cg_iters;             /* CG iterations of the last step               */
+  int32_t cg_iters_total;       /* summed over the steps of the call            */
+  double cg_rel_residual;       /* ||r|| / ||b|| at exit of the last solve      */
+  int32_t converged;            /* 1 if every solve of the call converged       */
+  int32_t nonfinite;            /* 1 if a NaN/Inf was seen in a solve           */
+  float ms;                     /* wall time of the call on the stream          */
+} uf_step_stats;
+
+/* Create a grid and its state.  The initial state has the inflow profile on
+ * every face, k and omega at their inlet values (Sec. 3: k = 1.5 (I U_ref)^2,
+ * omega = k^(1/2) / (C_mu^(1/4) L)), p = 0, nu_t from k and omega, and
+ * porosity 1 everywhere.  Errors: UF_EINVAL for a bad configuration (sizes,
+ * dt <= 0, no outlet side, nu above the explicit-diffusion bound, unknown
+ * enums), UF_ENOMEM, UF_EDEVICE.  *out is set only on success. */
+uf_status uf_create_grid(const uf_config* cfg, uf_grid* out);
+
+/* Release a grid and all of its device memory (synchronises its stream). */
+uf_status uf_destroy_grid(uf_grid g);
+
+/* Set the cell porosity phi in [0, 1] (1 = air, 0 = solid; Sec. 3 unified
+ * porosity model, appendix A.2 phi = 1 - V_s/V) from nx*ny*nz device
+ * values, and derive the drag coefficient C_d a ((1-phi)/(phi+e))^b of each
+ * cell.  Synchronises the stream to validate: UF_EINVAL (state unchanged)
+ * if any value is NaN or outside [0, 1]. */
+uf_status uf_set_porosity(uf_grid g, const void* phi_dev);
+
+/* Overwrite one state field from a device array in the layout given by
+ * uf_field_extent (checkpoint restore, parity tests).  Boundary values are
+ * re-imposed after the copy.  UF_PHI is the same as uf_set_porosity. */
+uf_status uf_set_field(uf_grid g, int32_t field, const void* src_dev);
+
+/* Copy one state field to a device array (asynchronous on the stream). */
+uf_status uf_get_field(uf_grid g, int32_t field, void* dst_dev);
+
+/* Extent of a field for a configuration; returns the element count, or -1
+ * for an unknown field.  dims may be NULL. */
+int64_t uf_field_extent(const uf_config* cfg, int32_t field, int32_t dims[3]);
+
+/* Advance nsteps time steps: advection (MacCormack), explicit diffusion,
+ * porosity drag, pressure projection, then the k-omega update (Sec. 3
+ * "Discretization and Numerical Integration": terms integrated one by one,
+ * turbulence after the projection).  The pressure solve starts from the
+ * previous pressure.  The call returns after the last step's solve has
+ * been observed to finish; later kernels may still be in flight unless
+ * stats is non-NULL, which synchronises and fills it.  Returns UF_ENOCONV or
+ * UF_ENONFINITE if some solve did not converge or saw a non-finite value;
+ * the state has advanced in either case. */
+uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats);
+
+/* Solve A x = b with the grid's pressure operator (A = -L_h with the
+ * boundary rows described above; SPD), preconditioner and tolerance; x_dev
+ * holds the initial guess on entry and the solution on exit.  b_dev and
+ * x_dev are nx*ny*nz device arrays.  Synchronises; stats may be NULL. */
+uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_stats* stats);
+
+/* Apply a fixed linear operator of the pressure solve to a cell array:
+ * op 0 = A (the Poisson matrix), op 1 = the configured preconditioner M^-1.
+ * x_dev and y_dev are nx*ny*nz device arrays and must not overlap. */
+enum { UF_OP_POISSON = 0, UF_OP_PRECOND = 1 };
+uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_dev);
+
+/* Design objective and its adjoint (Sec. 4.2 objective L(u) and the
+ * gradient-based design optimisation).  Not provided by this build: both
+ * return UF_ENOTIMPL. */
+uf_status uf_objective(uf_grid g, const void* spec, double* J_host, void* dJ_dstate_dev);
+uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
+                          void* const* adj_n_dev, void* dJ_dphi_accum_dev);
+
+/* Replace the stream used by the grid (e.g. torch's current stream). */
+uf_status uf_set_stream(uf_grid g, void* stream);
+
+/* Human-readable message of the last error on this host thread. */
+const char* uf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UF_H */

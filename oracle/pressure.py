@@ -81,7 +81,8 @@ def ai_preconditioner(A, omega, order=1):
 
 class PressureSolver:
     """Solves A p = b.  ``method`` 'direct' factors A once (sparse LU);
-    'cg' runs preconditioned CG from the warm start to ||r|| <= tol ||b||."""
+    'cg' runs preconditioned CG from the warm start to ||r|| <= tol ||b||;
+    'none' only builds A (for checks that never solve)."""
 
     def __init__(self, g, method="auto", tol=1e-12, maxit=20000, precond="ai1", ai_omega=1.6):
         self.A = poisson_matrix(g)
@@ -93,10 +94,14 @@ class PressureSolver:
         self.M = None
         if method == "direct":
             self.lu = spla.splu(self.A.tocsc())
+        elif method == "none":
+            pass
         elif precond == "ai1":
             self.M, _ = ai_preconditioner(self.A, ai_omega)
 
     def solve(self, b, x0):
+        if self.method == "none":
+            raise RuntimeError("this oracle grid was built without a pressure solver")
         if self.method == "direct":
             x = self.lu.solve(b)
             return x, 0

@@ -1,0 +1,23 @@
+"""MI355X (gfx950) implementation of one UrbanFlow RANS time step.
+
+Thin Python binding of the C ABI in ``include/uf.h`` (libuf.so, built from
+``csrc/`` by ``build.py``).  The functions ``uf_*`` are the C entry points
+with the same names; :class:`Grid` marshals torch CUDA tensors (used for
+device memory and streams only) into them.  Every stage of the step runs in
+the library's HIP kernels; there is no Python or CPU fallback, and importing
+this package fails when libuf.so is missing.
+"""
+from ._lib import (lib, LIB_PATH, UFError, uf_config, uf_step_stats, make_config,
+                   STATUS, FIELDS, FIELD_IDS)
+from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_field,
+                   uf_get_field, uf_field_extent, uf_step, uf_pressure_solve,
+                   uf_apply_operator, uf_objective, uf_adjoint_step, uf_set_stream,
+                   uf_last_error)
+from .grid import Grid
+
+__all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_config",
+           "STATUS", "FIELDS", "FIELD_IDS", "Grid",
+           "uf_create_grid", "uf_destroy_grid", "uf_set_porosity", "uf_set_field",
+           "uf_get_field", "uf_field_extent", "uf_step", "uf_pressure_solve",
+           "uf_apply_operator", "uf_objective", "uf_adjoint_step", "uf_set_stream",
+           "uf_last_error"]

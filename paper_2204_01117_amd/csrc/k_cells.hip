@@ -1,0 +1,197 @@
+// Cell-centred kernels: the k-omega turbulence update (Sec. 3, solved after
+// the projection), the porosity -> drag-coefficient map (Sec. 3 drag law),
+// boundary refresh of cell fields and packing between the padded storage
+// and the compact layouts of the C ABI.
+#include "uf_internal.h"
+
+namespace uf {
+
+constexpr int kCellBlock = 256;
+
+// Table 1 of the paper.
+constexpr double kCmu = 0.09, kAlpha = 0.52, kBeta = 0.0708, kSigma = 0.5, kSigmaStar = 0.6;
+
+#define UF_CELL_THREAD(L)                                            \
+  const int i = blockIdx.y;                                          \
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;               \
+  if (p >= (L).ny * (L).nz) return;                                  \
+  const int j = p / (L).nz;                                          \
+  const int k = p - j * (L).nz;
+
+// k-omega step at one cell.  Velocity gradients: normal derivatives from the
+// cell's two faces, cross derivatives as central differences of cell-centred
+// velocities (face means; ghost faces beyond the domain).  Strain rate
+// S = (grad u + grad u^T)/2, |S|^2 = S_ij S_ij.  Limiter omega~ = max(omega,
+// C_lim |S| / sqrt(C_mu/2)) (Wilcox 2006, cited in Sec. 3); eddy viscosity
+// nu_t = k / omega~ limited to [0, nu_max - nu] (the paper's von Neumann
+// viscosity limiter).  Forward Euler with first-order upwind advection and
+// central Laplacians.
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T* __restrict__ U,
+                                                           const T* __restrict__ V, const T* __restrict__ W,
+                                                           const T* __restrict__ K0, const T* __restrict__ W0,
+                                                           T* __restrict__ K1, T* __restrict__ W1,
+                                                           T* __restrict__ NUT, int update_kw) {
+  const Layout& L = P.L;
+  UF_CELL_THREAD(L);
+  const long long SX = L.SX, PZ = L.PZ;
+  const long long o = L.at(i, j, k);
+  const T h0 = T(0.5) * P.ih[0], h1 = T(0.5) * P.ih[1], h2 = T(0.5) * P.ih[2];
+  // gradients G[c][d] = d u_c / d x_d
+  const T g00 = (U[o + SX] - U[o]) * P.ih[0];
+  const T g11 = (V[o + PZ] - V[o]) * P.ih[1];
+  const T g22 = (W[o + 1] - W[o]) * P.ih[2];
+  auto uc = [&](long long q) { return T(0.5) * (U[q] + U[q + SX]); };
+  auto vc = [&](long long q) { return T(0.5) * (V[q] + V[q + PZ]); };
+  auto wc = [&](long long q) { return T(0.5) * (W[q] + W[q + 1]); };
+  const T g01 = (uc(o + PZ) - uc(o - PZ)) * h1;
+  const T g02 = (uc(o + 1) - uc(o - 1)) * h2;
+  const T g10 = (vc(o + SX) - vc(o - SX)) * h0;
+  const T g12 = (vc(o + 1) - vc(o - 1)) * h2;
+  const T g20 = (wc(o + SX) - wc(o - SX)) * h0;
+  const T g21 = (wc(o + PZ) - wc(o - PZ)) * h1;
+  const T s01 = T(0.5) * (g01 + g10), s02 = T(0.5) * (g02 + g20), s12 = T(0.5) * (g12 + g21);
+  const T S2 = g00 * g00 + g11 * g11 + g22 * g22 + T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
+  const T lim = P.lim_coef * sqrt(S2);
+  const T kk = K0[o], ww = W0[o];
+  const T nut = nmin(nmax(kk / nmax(ww, lim), T(0)), P.cap);
+  if (!update_kw) {
+    store_cell(NUT, P, i, j, k, nut, false, T(0));
+    return;
+  }
+  const T u0 = uc(o), u1 = vc(o), u2 = wc(o);
+  auto adv = [&](const T* q) {
+    const T c = q[o];
+    T a = (nmax(u0, T(0)) * (c - q[o - SX]) + nmin(u0, T(0)) * (q[o + SX] - c)) * P.ih[0];
+    a += (nmax(u1, T(0)) * (c - q[o - PZ]) + nmin(u1, T(0)) * (q[o + PZ] - c)) * P.ih[1];
+    a += (nmax(u2, T(0)) * (c - q[o - 1]) + nmin(u2, T(0)) * (q[o + 1] - c)) * P.ih[2];
+    return a;
+  };
+  auto lap = [&](const T* q) {
+    const T c = q[o];
+    return (q[o + SX] - T(2) * c + q[o - SX]) * P.ih2[0] + (q[o + PZ] - T(2) * c + q[o - PZ]) * P.ih2[1] +
+           (q[o + 1] - T(2) * c + q[o - 1]) * P.ih2[2];
+  };
+  T kn = kk + P.dt * (-adv(K0) + T(2) * nut * S2 - T(kCmu) * kk * ww + (P.nu + T(kSigmaStar) * nut) * lap(K0));
+  T wn = ww + P.dt * (-adv(W0) + T(2 * kAlpha) * S2 - T(kBeta) * ww * ww + (P.nu + T(kSigma) * nut) * lap(W0));
+  kn = nmax(kn, P.k_min);
+  wn = nmax(wn, P.w_min);
+  const T nut_new = nmin(nmax(kn / nmax(wn, lim), T(0)), P.cap);
+  store_cell(K1, P, i, j, k, kn, true, P.k_in);
+  store_cell(W1, P, i, j, k, wn, true, P.w_in);
+  store_cell(NUT, P, i, j, k, nut_new, false, T(0));
+}
+
+// Drag coefficient of each cell: C_d a ((1 - phi)/(phi + e))^b (Sec. 3 drag
+// law with the porosity form of its footnote); also keeps phi (compact).
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_porosity(Params<T> P, const T* __restrict__ phi, T* __restrict__ Cc,
+                                                         T* __restrict__ PHI, T coef, T e, T b) {
+  const Layout& L = P.L;
+  UF_CELL_THREAD(L);
+  const size_t c = ((size_t)i * L.ny + j) * L.nz + k;
+  const T f = phi[c];
+  PHI[c] = f;
+  store_cell(Cc, P, i, j, k, coef * pow((T(1) - f) / (f + e), b), false, T(0));
+}
+
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_cell_bc(Params<T> P, T* __restrict__ q, int use_inlet, T inlet) {
+  const Layout& L = P.L;
+  UF_CELL_THREAD(L);
+  store_cell(q, P, i, j, k, q[L.at(i, j, k)], use_inlet != 0, inlet);
+}
+
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_cell_fill(Params<T> P, T* __restrict__ q, T value, int use_inlet,
+                                                          T inlet) {
+  const Layout& L = P.L;
+  UF_CELL_THREAD(L);
+  store_cell(q, P, i, j, k, value, use_inlet != 0, inlet);
+}
+
+// Copy between the compact layout of a field and the padded storage.
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_pack(Layout L, int ex, int ey, int ez, const T* __restrict__ src,
+                                                     T* __restrict__ dst, int unpack) {
+  const size_t n = (size_t)ex * ey * ez;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(c % ez);
+    const size_t r = c / ez;
+    const int j = (int)(r % ey);
+    const int i = (int)(r / ey);
+    const long long o = L.at(i, j, k);
+    if (unpack) dst[o] = src[c];
+    else dst[c] = src[o];
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_check_range(const T* __restrict__ phi, size_t n, int* flag) {
+  int bad = 0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+    const T f = phi[c];
+    if (!(f >= T(0) && f <= T(1))) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+static inline dim3 cell_grid(const Layout& L) {
+  return dim3((L.ny * L.nz + kCellBlock - 1) / kCellBlock, L.nx);
+}
+
+template <class T>
+void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1,
+                 void* NUT, int update_kw) {
+  hipLaunchKernelGGL(k_turbulence<T>, cell_grid(P.L), dim3(kCellBlock), 0, g.stream, P, (const T*)Q[0],
+                     (const T*)Q[1], (const T*)Q[2], (const T*)K0, (const T*)W0, (T*)K1, (T*)W1, (T*)NUT, update_kw);
+}
+
+template <class T>
+void launch_porosity(Grid& g, const Params<T>& P, const void* phi) {
+  const uf_config& c = g.cfg;
+  hipLaunchKernelGGL(k_porosity<T>, cell_grid(P.L), dim3(kCellBlock), 0, g.stream, P, (const T*)phi, (T*)g.C,
+                     (T*)g.PHI, T(c.Cd * c.a), T(c.e), T(c.b));
+}
+
+template <class T>
+void launch_cell_bc(Grid& g, const Params<T>& P, void* q, int use_inlet, double inlet_value) {
+  hipLaunchKernelGGL(k_cell_bc<T>, cell_grid(P.L), dim3(kCellBlock), 0, g.stream, P, (T*)q, use_inlet,
+                     T(inlet_value));
+}
+
+template <class T>
+void launch_cell_fill(Grid& g, const Params<T>& P, void* q, double value, int use_inlet, double inlet_value) {
+  hipLaunchKernelGGL(k_cell_fill<T>, cell_grid(P.L), dim3(kCellBlock), 0, g.stream, P, (T*)q, T(value), use_inlet,
+                     T(inlet_value));
+}
+
+template <class T>
+void launch_pack(Grid& g, const Params<T>& P, const void* src, void* dst, int field, int unpack) {
+  int e[3] = {P.L.nx, P.L.ny, P.L.nz};
+  if (field >= 0 && field < 3) e[field] += 1;
+  const size_t n = (size_t)e[0] * e[1] * e[2];
+  const int blocks = (int)std::min<size_t>((n + kCellBlock - 1) / kCellBlock, 8192);
+  hipLaunchKernelGGL(k_pack<T>, dim3(blocks), dim3(kCellBlock), 0, g.stream, P.L, e[0], e[1], e[2], (const T*)src,
+                     (T*)dst, unpack);
+}
+
+template <class T>
+void launch_check_range(Grid& g, const void* phi, size_t n) {
+  const int blocks = (int)std::min<size_t>((n + kCellBlock - 1) / kCellBlock, 4096);
+  hipLaunchKernelGGL(k_check_range<T>, dim3(blocks), dim3(kCellBlock), 0, g.stream, (const T*)phi, n, g.flag);
+}
+
+#define UF_INST(T)                                                                                            \
+  template void launch_turb<T>(Grid&, const Params<T>&, void* const[3], const void*, const void*, void*, void*, \
+                               void*, int);                                                                 \
+  template void launch_porosity<T>(Grid&, const Params<T>&, const void*);                                    \
+  template void launch_cell_bc<T>(Grid&, const Params<T>&, void*, int, double);                              \
+  template void launch_pack<T>(Grid&, const Params<T>&, const void*, void*, int, int);                       \
+  template void launch_check_range<T>(Grid&, const void*, size_t);                                           \
+  template void launch_cell_fill<T>(Grid&, const Params<T>&, void*, double, int, double);
+UF_INST(float)
+UF_INST(double)
+#undef UF_INST
+
+}  // namespace uf

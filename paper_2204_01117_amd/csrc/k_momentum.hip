@@ -1,0 +1,317 @@
+// Momentum stages of the RANS step on the staggered grid (Sec. 3): MacCormack
+// semi-Lagrangian advection, explicit (nu + nu_t) diffusion, the porosity drag
+// and the pressure-gradient correction of the projection.
+//
+// Each kernel handles the three face components: a thread owns the faces
+// u(i,j,k), v(i,j,k), w(i,j,k) of the cell corner (i,j,k), i in [0, nx],
+// (j, k) in [0, ny] x [0, nz], flattened z fastest so that a wavefront
+// reads consecutive memory.  Fixed boundary normal faces get their
+// Dirichlet value; ghosts are written by store_face.
+#include "uf_internal.h"
+
+namespace uf {
+
+constexpr int kFaceBlock = 256;
+
+template <int C, class T>
+__device__ __forceinline__ bool owns_face(const Layout& L, int i, int j, int k) {
+  if (C == 0) return j < L.ny && k < L.nz;
+  if (C == 1) return i < L.nx && k < L.nz;
+  return i < L.nx && j < L.ny;
+}
+
+template <int C>
+__device__ __forceinline__ long long stride(const Layout& L) {
+  return C == 0 ? L.SX : (C == 1 ? (long long)L.PZ : 1LL);
+}
+
+// Velocity vector at face (i,j,k) of component C: the stored component, and
+// for each other component the mean of its four nearest faces (offsets
+// {-1, 0} along C and {0, +1} along that component's own axis).
+template <int C, class T>
+__device__ __forceinline__ void face_velocity(const Layout& L, const T* __restrict__ U, const T* __restrict__ V,
+                                              const T* __restrict__ W, long long o, T vel[3]) {
+  const T* Qs[3] = {U, V, W};
+  const long long st[3] = {L.SX, (long long)L.PZ, 1LL};
+  const long long sc = st[C];
+#pragma unroll
+  for (int cp = 0; cp < 3; ++cp) {
+    if (cp == C) {
+      vel[cp] = Qs[cp][o];
+    } else {
+      const T* q = Qs[cp];
+      const long long s2 = st[cp];
+      vel[cp] = T(0.25) * (q[o - sc] + q[o - sc + s2] + q[o] + q[o + s2]);
+    }
+  }
+}
+
+// Trilinear interpolation of component C's padded array at continuous
+// (unpadded) index (fi, fj, fk), positions clamped to the padded extent.
+// Optionally returns the min and max of the eight samples.
+template <int C, bool MINMAX, class T>
+__device__ __forceinline__ T sample(const Layout& L, const T* __restrict__ q, T fi, T fj, T fk, T* mn, T* mx) {
+  int ext[3];
+  face_ext<C>(L, ext);
+  // a NaN position (NaN velocity) yields NaN; the index clamp below keeps
+  // every access inside the padded array in any case
+  const bool nan_pos = fi != fi || fj != fj || fk != fk;
+  fi = fmin(fmax(fi, T(-1)), T(ext[0]));
+  fj = fmin(fmax(fj, T(-1)), T(ext[1]));
+  fk = fmin(fmax(fk, T(-1)), T(ext[2]));
+  const T i0f = fmin(floor(fi), T(ext[0] - 1));
+  const T j0f = fmin(floor(fj), T(ext[1] - 1));
+  const T k0f = fmin(floor(fk), T(ext[2] - 1));
+  const T ti = fi - i0f, tj = fj - j0f, tk = fk - k0f;
+  const long long o = L.at((int)i0f, (int)j0f, (int)k0f);
+  const long long SX = L.SX, PZ = L.PZ;
+  const T s000 = q[o], s100 = q[o + SX], s010 = q[o + PZ], s110 = q[o + SX + PZ];
+  const T s001 = q[o + 1], s101 = q[o + SX + 1], s011 = q[o + PZ + 1], s111 = q[o + SX + PZ + 1];
+  const T c00 = s000 + ti * (s100 - s000);
+  const T c10 = s010 + ti * (s110 - s010);
+  const T c01 = s001 + ti * (s101 - s001);
+  const T c11 = s011 + ti * (s111 - s011);
+  const T c0 = c00 + tj * (c10 - c00);
+  const T c1 = c01 + tj * (c11 - c01);
+  if (MINMAX) {
+    *mn = fmin(fmin(fmin(s000, s100), fmin(s010, s110)), fmin(fmin(s001, s101), fmin(s011, s111)));
+    *mx = fmax(fmax(fmax(s000, s100), fmax(s010, s110)), fmax(fmax(s001, s101), fmax(s011, s111)));
+  }
+  const T val = c0 + tk * (c1 - c0);
+  return nan_pos ? fi + fj + fk : val;
+}
+
+#define UF_FACE_THREAD(L)                                            \
+  const int i = blockIdx.y;                                          \
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;               \
+  if (p >= ((L).ny + 1) * ((L).nz + 1)) return;                      \
+  const int j = p / ((L).nz + 1);                                    \
+  const int k = p - j * ((L).nz + 1);
+
+// ------------------------------------------------------------- advection --
+template <int C, class T>
+__device__ __forceinline__ void advect_fwd_face(const Params<T>& P, const T* U, const T* V, const T* W,
+                                                T* __restrict__ out, int i, int j, int k) {
+  T val;
+  if (face_dirichlet<C>(P, i, j, k, &val)) {
+    store_face<C>(out, P, i, j, k, val);
+    return;
+  }
+  const long long o = P.L.at(i, j, k);
+  T vel[3];
+  face_velocity<C>(P.L, U, V, W, o, vel);
+  const T* q = C == 0 ? U : (C == 1 ? V : W);
+  T mn, mx;
+  const T qh = sample<C, false>(P.L, q, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1],
+                                T(k) - vel[2] * P.dth[2], &mn, &mx);
+  store_face<C>(out, P, i, j, k, qh);
+}
+
+template <int C, class T>
+__device__ __forceinline__ void advect_corr_face(const Params<T>& P, const T* U, const T* V, const T* W,
+                                                 const T* __restrict__ qhat, T* __restrict__ out, int i, int j, int k) {
+  T val;
+  if (face_dirichlet<C>(P, i, j, k, &val)) {
+    store_face<C>(out, P, i, j, k, val);
+    return;
+  }
+  const long long o = P.L.at(i, j, k);
+  T vel[3];
+  face_velocity<C>(P.L, U, V, W, o, vel);
+  const T* q = C == 0 ? U : (C == 1 ? V : W);
+  const T di = vel[0] * P.dth[0], dj = vel[1] * P.dth[1], dk = vel[2] * P.dth[2];
+  T mn, mx;
+  // forward trace again: same value as stored in qhat, plus the sample range
+  const T qh = sample<C, true>(P.L, q, T(i) - di, T(j) - dj, T(k) - dk, &mn, &mx);
+  T d0, d1;
+  const T qc = sample<C, false>(P.L, qhat, T(i) + di, T(j) + dj, T(k) + dk, &d0, &d1);
+  T qt = qh + T(0.5) * (q[o] - qc);
+  qt = nmin(nmax(qt, mn), mx);
+  store_face<C>(out, P, i, j, k, qt);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_fwd(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                           const T* __restrict__ W, T* __restrict__ Uh,
+                                                           T* __restrict__ Vh, T* __restrict__ Wh) {
+  UF_FACE_THREAD(P.L);
+  if (owns_face<0, T>(P.L, i, j, k)) advect_fwd_face<0>(P, U, V, W, Uh, i, j, k);
+  if (owns_face<1, T>(P.L, i, j, k)) advect_fwd_face<1>(P, U, V, W, Vh, i, j, k);
+  if (owns_face<2, T>(P.L, i, j, k)) advect_fwd_face<2>(P, U, V, W, Wh, i, j, k);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_corr(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                            const T* __restrict__ W, const T* __restrict__ Uh,
+                                                            const T* __restrict__ Vh, const T* __restrict__ Wh,
+                                                            T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  UF_FACE_THREAD(P.L);
+  if (owns_face<0, T>(P.L, i, j, k)) advect_corr_face<0>(P, U, V, W, Uh, Uo, i, j, k);
+  if (owns_face<1, T>(P.L, i, j, k)) advect_corr_face<1>(P, U, V, W, Vh, Vo, i, j, k);
+  if (owns_face<2, T>(P.L, i, j, k)) advect_corr_face<2>(P, U, V, W, Wh, Wo, i, j, k);
+}
+
+// ------------------------------------------------------------- diffusion --
+template <int C, class T>
+__device__ __forceinline__ void diffuse_face(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ nut,
+                                             T* __restrict__ out, int i, int j, int k) {
+  T val;
+  if (face_dirichlet<C>(P, i, j, k, &val)) {
+    store_face<C>(out, P, i, j, k, val);
+    return;
+  }
+  const Layout& L = P.L;
+  const long long o = L.at(i, j, k);
+  const T qc = q[o];
+  const T lap = (q[o + L.SX] - T(2) * qc + q[o - L.SX]) * P.ih2[0] +
+                (q[o + L.PZ] - T(2) * qc + q[o - L.PZ]) * P.ih2[1] +
+                (q[o + 1] - T(2) * qc + q[o - 1]) * P.ih2[2];
+  const T nuf = P.nu + T(0.5) * (nut[o - stride<C>(L)] + nut[o]);
+  store_face<C>(out, P, i, j, k, qc + P.dt * nuf * lap);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_diffuse(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                        const T* __restrict__ W, const T* __restrict__ NUT,
+                                                        T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  UF_FACE_THREAD(P.L);
+  if (owns_face<0, T>(P.L, i, j, k)) diffuse_face<0>(P, U, NUT, Uo, i, j, k);
+  if (owns_face<1, T>(P.L, i, j, k)) diffuse_face<1>(P, V, NUT, Vo, i, j, k);
+  if (owns_face<2, T>(P.L, i, j, k)) diffuse_face<2>(P, W, NUT, Wo, i, j, k);
+}
+
+// ------------------------------------------------------------ porosity drag
+template <int C, class T>
+__device__ __forceinline__ void drag_face(const Params<T>& P, const T* U, const T* V, const T* W,
+                                          const T* __restrict__ Cc, T* __restrict__ out, int i, int j, int k) {
+  T val;
+  if (face_dirichlet<C>(P, i, j, k, &val)) {
+    store_face<C>(out, P, i, j, k, val);
+    return;
+  }
+  const long long o = P.L.at(i, j, k);
+  T vel[3];
+  face_velocity<C>(P.L, U, V, W, o, vel);
+  const T speed = sqrt(vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]);
+  const T cf = T(0.5) * (Cc[o - stride<C>(P.L)] + Cc[o]);
+  const T fac = nmax(T(0), T(1) - P.dt * cf * speed);
+  store_face<C>(out, P, i, j, k, fac * vel[C]);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                     const T* __restrict__ W, const T* __restrict__ Cc,
+                                                     T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  UF_FACE_THREAD(P.L);
+  if (owns_face<0, T>(P.L, i, j, k)) drag_face<0>(P, U, V, W, Cc, Uo, i, j, k);
+  if (owns_face<1, T>(P.L, i, j, k)) drag_face<1>(P, U, V, W, Cc, Vo, i, j, k);
+  if (owns_face<2, T>(P.L, i, j, k)) drag_face<2>(P, U, V, W, Cc, Wo, i, j, k);
+}
+
+// ------------------------------------------------ projection (velocity part)
+template <int C, class T>
+__device__ __forceinline__ void project_face(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ p,
+                                             T* __restrict__ out, int i, int j, int k) {
+  T val;
+  if (face_dirichlet<C>(P, i, j, k, &val)) {
+    store_face<C>(out, P, i, j, k, val);
+    return;
+  }
+  const long long o = P.L.at(i, j, k);
+  const T grad = (p[o] - p[o - stride<C>(P.L)]) * P.ih[C];
+  store_face<C>(out, P, i, j, k, q[o] - P.dt_rho * grad);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                        const T* __restrict__ W, const T* __restrict__ Pp,
+                                                        T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  UF_FACE_THREAD(P.L);
+  if (owns_face<0, T>(P.L, i, j, k)) project_face<0>(P, U, Pp, Uo, i, j, k);
+  if (owns_face<1, T>(P.L, i, j, k)) project_face<1>(P, V, Pp, Vo, i, j, k);
+  if (owns_face<2, T>(P.L, i, j, k)) project_face<2>(P, W, Pp, Wo, i, j, k);
+}
+
+// ------------------------------------------------ boundary refresh (in place)
+template <int C, class T>
+__global__ __launch_bounds__(kFaceBlock) void k_face_bc(Params<T> P, T* __restrict__ q) {
+  UF_FACE_THREAD(P.L);
+  if (!owns_face<C, T>(P.L, i, j, k)) return;
+  T val;
+  if (!face_dirichlet<C>(P, i, j, k, &val)) val = q[P.L.at(i, j, k)];
+  store_face<C>(q, P, i, j, k, val);
+}
+
+// Initial state: the inflow profile on every face (fixed faces keep their
+// boundary value).
+template <int C, class T>
+__global__ __launch_bounds__(kFaceBlock) void k_face_init(Params<T> P, T* __restrict__ q) {
+  UF_FACE_THREAD(P.L);
+  if (!owns_face<C, T>(P.L, i, j, k)) return;
+  T val;
+  if (!face_dirichlet<C>(P, i, j, k, &val)) val = inflow_comp(P, C, k);
+  store_face<C>(q, P, i, j, k, val);
+}
+
+// ----------------------------------------------------------------- launchers
+static inline dim3 face_grid(const Layout& L) {
+  const int plane = (L.ny + 1) * (L.nz + 1);
+  return dim3((plane + kFaceBlock - 1) / kFaceBlock, L.nx + 1);
+}
+
+template <class T>
+void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Qout[3]) {
+  const dim3 grid = face_grid(P.L);
+  hipLaunchKernelGGL(k_advect_fwd<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0], (const T*)Qin[1],
+                     (const T*)Qin[2], (T*)Qhat[0], (T*)Qhat[1], (T*)Qhat[2]);
+  hipLaunchKernelGGL(k_advect_corr<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0], (const T*)Qin[1],
+                     (const T*)Qin[2], (const T*)Qhat[0], (const T*)Qhat[1], (const T*)Qhat[2], (T*)Qout[0],
+                     (T*)Qout[1], (T*)Qout[2]);
+}
+
+template <class T>
+void launch_diffuse(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
+  hipLaunchKernelGGL(k_diffuse<T>, face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)g.NUT, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
+}
+
+template <class T>
+void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
+  hipLaunchKernelGGL(k_drag<T>, face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0], (const T*)Qin[1],
+                     (const T*)Qin[2], (const T*)g.C, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
+}
+
+template <class T>
+void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
+  hipLaunchKernelGGL(k_project<T>, face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)g.X, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
+}
+
+template <class T>
+void launch_face_bc(Grid& g, const Params<T>& P, void* q, int comp) {
+  const dim3 grid = face_grid(P.L);
+  if (comp == 0) hipLaunchKernelGGL((k_face_bc<0, T>), grid, dim3(kFaceBlock), 0, g.stream, P, (T*)q);
+  if (comp == 1) hipLaunchKernelGGL((k_face_bc<1, T>), grid, dim3(kFaceBlock), 0, g.stream, P, (T*)q);
+  if (comp == 2) hipLaunchKernelGGL((k_face_bc<2, T>), grid, dim3(kFaceBlock), 0, g.stream, P, (T*)q);
+}
+
+template <class T>
+void launch_face_init(Grid& g, const Params<T>& P, void* const Q[3]) {
+  const dim3 grid = face_grid(P.L);
+  hipLaunchKernelGGL((k_face_init<0, T>), grid, dim3(kFaceBlock), 0, g.stream, P, (T*)Q[0]);
+  hipLaunchKernelGGL((k_face_init<1, T>), grid, dim3(kFaceBlock), 0, g.stream, P, (T*)Q[1]);
+  hipLaunchKernelGGL((k_face_init<2, T>), grid, dim3(kFaceBlock), 0, g.stream, P, (T*)Q[2]);
+}
+
+#define UF_INST(T)                                                                                   \
+  template void launch_advect<T>(Grid&, const Params<T>&, void* const[3], void* const[3], void* const[3]); \
+  template void launch_diffuse<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);          \
+  template void launch_drag<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);             \
+  template void launch_project<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);          \
+  template void launch_face_bc<T>(Grid&, const Params<T>&, void*, int);                             \
+  template void launch_face_init<T>(Grid&, const Params<T>&, void* const[3]);
+UF_INST(float)
+UF_INST(double)
+#undef UF_INST
+
+}  // namespace uf

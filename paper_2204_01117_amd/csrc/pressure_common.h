@@ -1,0 +1,86 @@
+// Helpers shared by the pressure-solve kernels (CG and multigrid).
+//
+// Cell vectors of the solve keep zero ghosts; the operator at a cell is
+//   (A x)_c = D_c x_c - sum_a w_a (x_{c+a} + x_{c-a})
+// with per-axis weights w_a (1/h_a^2 on the fine grid) and D_c = sum of w_a
+// over the neighbours that are cells or outlet ghosts (zero pressure);
+// Neumann sides drop out.
+#pragma once
+#include "uf_internal.h"
+
+namespace uf {
+
+// Partial-sum slots of the solve: every block of a reducing kernel writes
+// its FP64 partial into part[slot * nb + block]; later kernels add the nb
+// partials in block order (no atomics, no intra-kernel cross-block traffic).
+enum CgSlot { S_BB = 0, S_RR = 1, S_DQ = 2, S_RZ0 = 3, S_RZ1 = 4, S_NSLOT = 5 };
+
+template <class T>
+__device__ __forceinline__ T diag_w(const int bc[6], const Layout& L, const T w[3], int i, int j, int k) {
+  T d = T(0);
+  d += ((i > 0 || bc[0] == OUTLET) ? w[0] : T(0)) + ((i < L.nx - 1 || bc[1] == OUTLET) ? w[0] : T(0));
+  d += ((j > 0 || bc[2] == OUTLET) ? w[1] : T(0)) + ((j < L.ny - 1 || bc[3] == OUTLET) ? w[1] : T(0));
+  d += ((k > 0 || bc[4] == OUTLET) ? w[2] : T(0)) + ((k < L.nz - 1 || bc[5] == OUTLET) ? w[2] : T(0));
+  return d;
+}
+
+template <class T>
+__device__ __forceinline__ T apply_w(const int bc[6], const Layout& L, const T w[3], const T* __restrict__ x, int i,
+                                     int j, int k, long long o) {
+  return diag_w(bc, L, w, i, j, k) * x[o] - (x[o + L.SX] + x[o - L.SX]) * w[0] - (x[o + L.PZ] + x[o - L.PZ]) * w[1] -
+         (x[o + 1] + x[o - 1]) * w[2];
+}
+
+// Sum of one partial-sum slot, identical in every thread of the block.
+__device__ __forceinline__ double slot_sum(const double* __restrict__ part, int nb) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < nw; ++q) s += sh[q];
+  __syncthreads();
+  return s;
+}
+
+// Write the block's partial sums of NV values into consecutive slots.
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double* __restrict__ part, int nb, const int slot[NV]) {
+  block_sum<NV>(v);
+  if (threadIdx.x == 0) {
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) part[(size_t)slot[m] * nb + bid] = v[m];
+  }
+}
+
+// State of the solve shared by the kernels (passed by value).
+struct CgCtl {
+  double* part;    // S_NSLOT * nb partial sums
+  int nb;          // blocks of the fine-grid reducing kernels
+  int* flags;      // flags[m]: the solve finished before iteration m
+  int* exec;       // exec[t]: iteration t performed its update
+  CgState* st;
+  int criterion;
+  int maxit;
+};
+
+struct Grid;
+CgCtl make_ctl(Grid& g);
+
+// Has the solve finished before the preconditioner application that
+// follows iteration t (m = t + 1)?  Evaluated by the first kernel of that
+// application; its block 0 publishes the answer in flags[m].
+__device__ __forceinline__ bool precond_skip(const CgCtl& c, int m) {
+  if (m == 0) return c.flags[0] != 0;
+  if (!c.exec[m - 1]) return true;
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.nb, c.nb);
+  if (!isfinite(rr)) return true;
+  return c.criterion == 0 && rr <= c.st->tol2_bb;
+}
+
+}  // namespace uf

@@ -1,0 +1,621 @@
+// C ABI of the RANS step library: grid creation and validation, state I/O,
+// the time-step driver and the pressure-CG host loop.  See include/uf.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "uf_internal.h"
+
+namespace uf {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& m) { g_last_error = m; }
+
+template <class T> void launch_face_init(Grid& g, const Params<T>& P, void* const Q[3]);
+template <class T> void launch_cell_fill(Grid& g, const Params<T>& P, void* q, double value, int use_inlet,
+                                         double inlet_value);
+
+static const double kCmu = 0.09, kClim = 7.0 / 8.0;
+static const size_t S_NSLOT_HOST = 5;   // partial-sum slots of the pressure solve
+
+template <class T>
+Params<T> make_params(const Grid& g) {
+  Params<T> P{};
+  P.L = g.L;
+  for (int s = 0; s < 6; ++s) P.bc[s] = g.bc[s];
+  const double h[3] = {g.cfg.dx, g.cfg.dy, g.cfg.dz};
+  for (int a = 0; a < 3; ++a) {
+    P.h[a] = T(h[a]);
+    P.ih[a] = T(1.0 / h[a]);
+    P.ih2[a] = T(1.0 / (h[a] * h[a]));
+    P.dth[a] = T(g.cfg.dt / h[a]);
+  }
+  P.dt = T(g.cfg.dt);
+  P.nu = T(g.cfg.nu);
+  P.rho = T(g.cfg.rho);
+  P.dt_rho = T(g.cfg.dt / g.cfg.rho);
+  P.rho_dt = T(g.cfg.rho / g.cfg.dt);
+  P.cap = T(g.nu_max - g.cfg.nu);
+  P.k_in = T(g.k_in);
+  P.w_in = T(g.w_in);
+  P.k_min = T(g.cfg.k_min);
+  P.w_min = T(g.cfg.omega_min);
+  P.lim_coef = T(kClim / std::sqrt(kCmu / 2.0));
+  P.inflow = (const T*)g.inflow;
+  return P;
+}
+
+}  // namespace uf
+
+using namespace uf;
+
+struct uf_grid_s : public Grid {};
+
+namespace {
+
+uf_status fail(uf_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+#define UF_GUARD_BEGIN try {
+#define UF_GUARD_END                                          \
+  }                                                           \
+  catch (const HipError& e) {                                 \
+    return fail(UF_EDEVICE, e.msg);                           \
+  }                                                           \
+  catch (const std::exception& e) {                           \
+    return fail(UF_EDEVICE, e.what());                        \
+  }
+
+void check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw HipError(std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+// Resolve UF_BC_AUTO: a vertical side is an inlet when the wind blows into
+// the domain through it, an outlet otherwise; ground wall, sky slip.
+void resolve_bc(const uf_config& c, int out[6]) {
+  const double th = c.wind_dir_deg * (M_PI / 180.0);
+  const double wx = std::cos(th), wy = std::sin(th);
+  const double inward[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+  for (int s = 0; s < 6; ++s) {
+    if (c.bc[s] != UF_BC_AUTO) {
+      out[s] = c.bc[s];
+    } else if (s < 4) {
+      out[s] = (inward[s][0] * wx + inward[s][1] * wy > 1e-12) ? UF_BC_INLET : UF_BC_OUTLET;
+    } else {
+      out[s] = s == 4 ? UF_BC_WALL : UF_BC_SLIP;
+    }
+  }
+}
+
+double nu_max_of(const uf_config& c) {
+  return 1.0 / (2.0 * c.dt * (1.0 / (c.dx * c.dx) + 1.0 / (c.dy * c.dy) + 1.0 / (c.dz * c.dz)));
+}
+
+std::string validate(const uf_config& c) {
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1) return "grid sizes must be >= 1";
+  if (c.nx > 32768 || c.ny > 32768 || c.nz > 32768) return "grid size above 32768";
+  if ((double)(c.nx + 3) * (c.ny + 3) * (c.nz + 3) > 2.0e9) return "grid too large";
+  if (!finite_pos(c.dx) || !finite_pos(c.dy) || !finite_pos(c.dz)) return "dx, dy, dz must be finite and > 0";
+  if (!finite_pos(c.dt)) return "dt must be finite and > 0";
+  if (c.dtype != UF_F32 && c.dtype != UF_F64) return "dtype must be UF_F32 or UF_F64";
+  for (int s = 0; s < 6; ++s)
+    if (c.bc[s] < UF_BC_AUTO || c.bc[s] > UF_BC_SLIP) return "unknown boundary kind";
+  int bc[6];
+  resolve_bc(c, bc);
+  bool outlet = false;
+  for (int s = 0; s < 6; ++s) outlet |= bc[s] == UF_BC_OUTLET;
+  if (!outlet) return "at least one side must be an outlet (the pressure matrix is singular otherwise)";
+  if (c.inflow_kind < UF_INFLOW_UNIFORM || c.inflow_kind > UF_INFLOW_PROFILE) return "unknown inflow kind";
+  if (!std::isfinite(c.u_ref) || !std::isfinite(c.wind_dir_deg)) return "u_ref and wind_dir_deg must be finite";
+  if (c.inflow_kind == UF_INFLOW_LOGLAW &&
+      (!finite_pos(c.z0) || !finite_pos(c.karman) || !finite_pos(c.z_ref) || c.z_ref <= c.z0))
+    return "log-law inflow needs 0 < z0 < z_ref and karman > 0";
+  if (c.inflow_kind == UF_INFLOW_PROFILE) {
+    if (!c.inflow_profile) return "inflow_profile is NULL";
+    for (int k = 0; k < c.nz; ++k)
+      if (!std::isfinite(c.inflow_profile[k])) return "inflow_profile holds a non-finite value";
+  }
+  if (!std::isfinite(c.nu) || c.nu < 0) return "nu must be finite and >= 0";
+  if (!finite_pos(c.rho)) return "rho must be finite and > 0";
+  if (c.nu > nu_max_of(c)) return "nu exceeds the explicit-diffusion stability bound 1/(2 dt sum h^-2)";
+  if (c.turb_model != UF_TURB_OFF && c.turb_model != UF_TURB_KOMEGA) return "unknown turbulence model";
+  if (c.turb_model == UF_TURB_KOMEGA) {
+    if (!finite_pos(c.turb_I) || !finite_pos(std::fabs(c.u_ref))) return "k-omega needs turb_I > 0 and u_ref != 0";
+    if (!std::isfinite(c.turb_L)) return "turb_L must be finite";
+    if (!std::isfinite(c.k_min) || !std::isfinite(c.omega_min) || c.k_min < 0 || c.omega_min < 0)
+      return "k_min and omega_min must be finite and >= 0";
+  }
+  if (!std::isfinite(c.Cd) || !std::isfinite(c.a) || !std::isfinite(c.b) || c.Cd < 0 || c.a < 0)
+    return "drag constants must be finite, Cd and a >= 0";
+  if (!finite_pos(c.e)) return "e must be finite and > 0";
+  if (c.precond != UF_PC_NONE && c.precond != UF_PC_JACOBI && c.precond != UF_PC_AI1 && c.precond != UF_PC_MG)
+    return "unknown preconditioner";
+  if (!(c.ai_omega > 0 && c.ai_omega < 2)) return "ai_omega must lie in (0, 2)";
+  if (!finite_pos(c.cg_tol)) return "cg_tol must be finite and > 0";
+  if (c.cg_maxit < 1 || c.cg_maxit > 1000000) return "cg_maxit must be in [1, 1e6]";
+  if (c.cg_criterion != 0 && c.cg_criterion != 1) return "cg_criterion must be 0 or 1";
+  if (c.stages < 0 || c.stages > UF_STAGE_ALL) return "unknown stage bits";
+  return "";
+}
+
+void* dalloc(size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw HipError(std::string("hipMalloc: ") + hipGetErrorString(e));
+  return p;
+}
+
+void free_grid(Grid* g) {
+  auto f = [](void*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  };
+  for (auto& s : g->Q)
+    for (auto& q : s) f(q);
+  for (auto& q : g->K) f(q);
+  for (auto& q : g->Wo) f(q);
+  f(g->NUT);
+  f(g->C);
+  f(g->PHI);
+  f(g->inflow);
+  f(g->X);
+  f(g->R);
+  f(g->Z);
+  f(g->D[0]);
+  f(g->D[1]);
+  f(g->Qv);
+  void* pp = g->partials;
+  f(pp);
+  g->partials = nullptr;
+  void* pfl = g->flags;
+  f(pfl);
+  g->flags = nullptr;
+  void* pex = g->exec;
+  f(pex);
+  g->exec = nullptr;
+  void* ps = g->st;
+  f(ps);
+  g->st = nullptr;
+  void* pf = g->flag;
+  f(pf);
+  g->flag = nullptr;
+  if (g->st_host) (void)hipHostFree(g->st_host);
+  if (g->flag_host) (void)hipHostFree(g->flag_host);
+  g->st_host = nullptr;
+  g->flag_host = nullptr;
+  if (g->ev_status) (void)hipEventDestroy(g->ev_status);
+  if (g->ev0) (void)hipEventDestroy(g->ev0);
+  if (g->ev1) (void)hipEventDestroy(g->ev1);
+  g->ev_status = g->ev0 = g->ev1 = nullptr;
+  mg_free(*g);
+}
+
+void sync_status(Grid& g) {
+  UF_HIP_CHECK(hipMemcpyAsync(g.st_host, g.st, sizeof(CgState), hipMemcpyDeviceToHost, g.stream));
+  UF_HIP_CHECK(hipEventRecord(g.ev_status, g.stream));
+  UF_HIP_CHECK(hipEventSynchronize(g.ev_status));
+}
+
+struct SolveResult {
+  int iters = 0;
+  double rel = 0;
+  int noconv = 0, nonfinite = 0;
+};
+
+// Pressure solve: r0 = b - A x0 and the stopping threshold, the first
+// preconditioner application, then iterations enqueued in chunks with the
+// device status read after each chunk.  The first chunk is as long as the
+// previous solve, so a steady run needs one host round trip per solve;
+// iterations enqueued past convergence return at once.
+template <class T>
+SolveResult solve_pressure(Grid& g, const Params<T>& P, void* const Qs[3], const void* b) {
+  launch_cg_start<T>(g, P, Qs, b);
+  launch_cg_precond<T>(g, P, 0);
+  check_launch();
+  const int maxit = g.cfg.cg_maxit;
+  int t = 0;
+  while (true) {
+    int m = t == 0 ? (g.last_iters > 0 ? g.last_iters : 4) : std::max(1, t / 8);
+    if (t + m > maxit) m = maxit - t;
+    if (m < 1) m = 1;
+    for (int q = 0; q < m; ++q, ++t) launch_cg_iteration<T>(g, P, t);
+    launch_cg_status(g, t);
+    check_launch();
+    sync_status(g);
+    if (g.st_host->done || t >= maxit) break;
+  }
+  SolveResult res;
+  const CgState& s = *g.st_host;
+  res.iters = s.iter;
+  res.rel = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
+  res.noconv = s.noconv;
+  res.nonfinite = s.nonfinite;
+  g.last_iters = s.iter;
+  return res;
+}
+
+struct StepAccum {
+  int iters_total = 0, last_iters = 0, noconv = 0, nonfinite = 0;
+  double last_rel = 0;
+};
+
+int free_set(const Grid& g, int avoid) {
+  for (int s = 0; s < 3; ++s)
+    if (s != g.cur && s != avoid) return s;
+  return -1;
+}
+
+template <class T>
+void run_steps(Grid& g, int nsteps, StepAccum& acc) {
+  const Params<T> P = make_params<T>(g);
+  const int st = g.cfg.stages;
+  for (int n = 0; n < nsteps; ++n) {
+    if (st & UF_STAGE_ADVECT) {
+      const int hat = free_set(g, -1), out = free_set(g, hat);
+      launch_advect<T>(g, P, g.Q[g.cur], g.Q[hat], g.Q[out]);
+      g.cur = out;
+    }
+    if (st & UF_STAGE_DIFFUSE) {
+      const int out = free_set(g, -1);
+      launch_diffuse<T>(g, P, g.Q[g.cur], g.Q[out]);
+      g.cur = out;
+    }
+    if (st & UF_STAGE_DRAG) {
+      const int out = free_set(g, -1);
+      launch_drag<T>(g, P, g.Q[g.cur], g.Q[out]);
+      g.cur = out;
+    }
+    check_launch();
+    if (st & UF_STAGE_PROJECT) {
+      SolveResult r = solve_pressure<T>(g, P, g.Q[g.cur], nullptr);
+      acc.iters_total += r.iters;
+      acc.last_iters = r.iters;
+      acc.last_rel = r.rel;
+      acc.noconv |= r.noconv;
+      acc.nonfinite |= r.nonfinite;
+      const int out = free_set(g, -1);
+      launch_project<T>(g, P, g.Q[g.cur], g.Q[out]);
+      g.cur = out;
+    }
+    if ((st & UF_STAGE_TURB) && g.cfg.turb_model == UF_TURB_KOMEGA) {
+      const int kn = g.kcur ^ 1;
+      launch_turb<T>(g, P, g.Q[g.cur], g.K[g.kcur], g.Wo[g.kcur], g.K[kn], g.Wo[kn], g.NUT, 1);
+      g.kcur = kn;
+    }
+    check_launch();
+  }
+}
+
+template <class T>
+void init_state(Grid& g) {
+  const Params<T> P = make_params<T>(g);
+  launch_face_init<T>(g, P, g.Q[g.cur]);
+  launch_cell_fill<T>(g, P, g.K[g.kcur], g.k_in, 1, g.k_in);
+  launch_cell_fill<T>(g, P, g.Wo[g.kcur], g.w_in, 1, g.w_in);
+  if (g.cfg.turb_model == UF_TURB_KOMEGA)
+    launch_turb<T>(g, P, g.Q[g.cur], g.K[g.kcur], g.Wo[g.kcur], nullptr, nullptr, g.NUT, 0);
+  check_launch();
+}
+
+template <class T>
+void upload_inflow(Grid& g) {
+  const uf_config& c = g.cfg;
+  const int nz = c.nz;
+  std::vector<T> tab(2 * (nz + 2));
+  const double th = c.wind_dir_deg * (M_PI / 180.0);
+  const double dir[2] = {std::cos(th), std::sin(th)};
+  for (int k = -1; k <= nz; ++k) {
+    double s = 0;
+    if (c.inflow_kind == UF_INFLOW_UNIFORM) {
+      s = c.u_ref;
+    } else if (c.inflow_kind == UF_INFLOW_LOGLAW) {
+      // Sec. 5.1: u(z) = (u*/kappa) ln(z/z0), u* fixed by u(z_ref) = u_ref
+      const double ustar = c.u_ref * c.karman / std::log(c.z_ref / c.z0);
+      const double z = (k + 0.5) * c.dz;
+      s = z > c.z0 ? ustar / c.karman * std::log(z / c.z0) : 0.0;
+    } else {
+      const int kk = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
+      s = g.profile[kk];
+    }
+    tab[0 * (nz + 2) + (k + 1)] = T(s * dir[0]);
+    tab[1 * (nz + 2) + (k + 1)] = T(s * dir[1]);
+  }
+  UF_HIP_CHECK(hipMemcpy(g.inflow, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <class T>
+void fill_phi_one(Grid& g) {
+  std::vector<T> ones((size_t)g.L.nx * g.L.ny * g.L.nz, T(1));
+  UF_HIP_CHECK(hipMemcpy(g.PHI, ones.data(), ones.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+int64_t extent(const uf_config* c, int32_t f, int32_t d[3]) {
+  int e[3] = {c->nx, c->ny, c->nz};
+  if (f < 0 || f > UF_PHI) return -1;
+  if (f < 3) e[f] += 1;
+  if (d) {
+    d[0] = e[0];
+    d[1] = e[1];
+    d[2] = e[2];
+  }
+  return (int64_t)e[0] * e[1] * e[2];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* uf_last_error(void) { return g_last_error.c_str(); }
+
+int64_t uf_field_extent(const uf_config* cfg, int32_t field, int32_t dims[3]) {
+  if (!cfg) return -1;
+  return extent(cfg, field, dims);
+}
+
+uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
+  if (!cfg || !out) return fail(UF_EINVAL, "NULL argument");
+  const std::string err = validate(*cfg);
+  if (!err.empty()) return fail(UF_EINVAL, err);
+  uf_grid_s* g = new uf_grid_s();
+  UF_GUARD_BEGIN
+  g->cfg = *cfg;
+  if (cfg->inflow_kind == UF_INFLOW_PROFILE) g->profile.assign(cfg->inflow_profile, cfg->inflow_profile + cfg->nz);
+  g->cfg.inflow_profile = nullptr;
+  resolve_bc(*cfg, g->bc);
+  for (int s = 0; s < 6; ++s) g->cfg.bc[s] = g->bc[s];
+  g->stream = (hipStream_t)cfg->stream;
+  Layout& L = g->L;
+  L.nx = cfg->nx;
+  L.ny = cfg->ny;
+  L.nz = cfg->nz;
+  L.PZ = cfg->nz + 3;
+  L.SX = (long long)(cfg->ny + 3) * L.PZ;
+  g->nelem = (size_t)(cfg->nx + 3) * L.SX;
+  g->esize = cfg->dtype == UF_F64 ? 8 : 4;
+  g->nu_max = nu_max_of(*cfg);
+  const double I = cfg->turb_I, U = std::fabs(cfg->u_ref);
+  const double Lt = cfg->turb_L > 0 ? cfg->turb_L : 0.1 * cfg->nz * cfg->dz;
+  g->k_in = 1.5 * (I * U) * (I * U);
+  g->w_in = std::sqrt(g->k_in) / (std::pow(kCmu, 0.25) * Lt);
+  const size_t bytes = g->nelem * g->esize;
+  std::vector<void**> bufs;
+  for (auto& s : g->Q)
+    for (auto& q : s) bufs.push_back(&q);
+  for (auto& q : g->K) bufs.push_back(&q);
+  for (auto& q : g->Wo) bufs.push_back(&q);
+  for (void** q : {&g->NUT, &g->C, &g->X, &g->R, &g->Z, &g->D[0], &g->D[1], &g->Qv}) bufs.push_back(q);
+  try {
+    for (void** q : bufs) {
+      *q = dalloc(bytes);
+      UF_HIP_CHECK(hipMemsetAsync(*q, 0, bytes, g->stream));
+    }
+    g->PHI = dalloc((size_t)cfg->nx * cfg->ny * cfg->nz * g->esize);
+    g->inflow = dalloc(2 * (cfg->nz + 2) * g->esize);
+    const CgLaunch cl = cg_launch(L);
+    g->cg_nb = (size_t)cl.grid.x * cl.grid.y;
+    g->partials = (double*)dalloc(S_NSLOT_HOST * g->cg_nb * sizeof(double));
+    g->flags = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
+    g->exec = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
+    UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->cg_nb * sizeof(double), g->stream));
+    UF_HIP_CHECK(hipMemsetAsync(g->flags, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
+    UF_HIP_CHECK(hipMemsetAsync(g->exec, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
+    g->st = (CgState*)dalloc(sizeof(CgState));
+    g->flag = (int*)dalloc(sizeof(int));
+  } catch (const HipError& e) {
+    free_grid(g);
+    delete g;
+    return fail(UF_ENOMEM, e.msg);
+  }
+  UF_HIP_CHECK(hipMemsetAsync(g->st, 0, sizeof(CgState), g->stream));
+  UF_HIP_CHECK(hipHostMalloc((void**)&g->st_host, sizeof(CgState), hipHostMallocDefault));
+  UF_HIP_CHECK(hipHostMalloc((void**)&g->flag_host, sizeof(int), hipHostMallocDefault));
+  UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_status, hipEventDisableTiming));
+  UF_HIP_CHECK(hipEventCreate(&g->ev0));
+  UF_HIP_CHECK(hipEventCreate(&g->ev1));
+  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+  if (g->esize == 4) {
+    upload_inflow<float>(*g);
+    fill_phi_one<float>(*g);
+    if (cfg->precond == UF_PC_MG) mg_setup<float>(*g);
+    init_state<float>(*g);
+  } else {
+    upload_inflow<double>(*g);
+    fill_phi_one<double>(*g);
+    if (cfg->precond == UF_PC_MG) mg_setup<double>(*g);
+    init_state<double>(*g);
+  }
+  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+  *out = g;
+  return UF_OK;
+  }
+  catch (const HipError& e) {
+    free_grid(g);
+    delete g;
+    return fail(UF_EDEVICE, e.msg);
+  }
+}
+
+uf_status uf_destroy_grid(uf_grid g) {
+  if (!g) return fail(UF_EINVAL, "NULL grid");
+  (void)hipStreamSynchronize(g->stream);
+  free_grid(g);
+  delete g;
+  return UF_OK;
+}
+
+uf_status uf_set_stream(uf_grid g, void* stream) {
+  if (!g) return fail(UF_EINVAL, "NULL grid");
+  g->stream = (hipStream_t)stream;
+  return UF_OK;
+}
+
+uf_status uf_set_porosity(uf_grid g, const void* phi_dev) {
+  if (!g || !phi_dev) return fail(UF_EINVAL, "NULL argument");
+  UF_GUARD_BEGIN
+  const size_t n = (size_t)g->L.nx * g->L.ny * g->L.nz;
+  UF_HIP_CHECK(hipMemsetAsync(g->flag, 0, sizeof(int), g->stream));
+  if (g->esize == 4) launch_check_range<float>(*g, phi_dev, n);
+  else launch_check_range<double>(*g, phi_dev, n);
+  check_launch();
+  UF_HIP_CHECK(hipMemcpyAsync(g->flag_host, g->flag, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+  if (*g->flag_host) return fail(UF_EINVAL, "porosity must be finite and in [0, 1]");
+  if (g->esize == 4) launch_porosity<float>(*g, make_params<float>(*g), phi_dev);
+  else launch_porosity<double>(*g, make_params<double>(*g), phi_dev);
+  check_launch();
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_set_field(uf_grid g, int32_t field, const void* src) {
+  if (!g || !src) return fail(UF_EINVAL, "NULL argument");
+  if (field < 0 || field > UF_PHI) return fail(UF_EINVAL, "unknown field");
+  if (field == UF_PHI) return uf_set_porosity(g, src);
+  UF_GUARD_BEGIN
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    const Params<T> P = make_params<T>(*g);
+    void* dst = nullptr;
+    switch (field) {
+      case UF_U: case UF_V: case UF_W: dst = g->Q[g->cur][field]; break;
+      case UF_P: dst = g->X; break;
+      case UF_K: dst = g->K[g->kcur]; break;
+      case UF_OMEGA: dst = g->Wo[g->kcur]; break;
+      case UF_NUT: dst = g->NUT; break;
+    }
+    launch_pack<T>(*g, P, src, dst, field, 1);
+    if (field <= UF_W) launch_face_bc<T>(*g, P, dst, field);
+    else if (field == UF_K) launch_cell_bc<T>(*g, P, dst, 1, g->k_in);
+    else if (field == UF_OMEGA) launch_cell_bc<T>(*g, P, dst, 1, g->w_in);
+    else if (field == UF_NUT) launch_cell_bc<T>(*g, P, dst, 0, 0.0);
+  };
+  if (g->esize == 4) go(float());
+  else go(double());
+  check_launch();
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_get_field(uf_grid g, int32_t field, void* dst) {
+  if (!g || !dst) return fail(UF_EINVAL, "NULL argument");
+  if (field < 0 || field > UF_PHI) return fail(UF_EINVAL, "unknown field");
+  UF_GUARD_BEGIN
+  if (field == UF_PHI) {
+    UF_HIP_CHECK(hipMemcpyAsync(dst, g->PHI, (size_t)g->L.nx * g->L.ny * g->L.nz * g->esize,
+                                hipMemcpyDeviceToDevice, g->stream));
+    return UF_OK;
+  }
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    const Params<T> P = make_params<T>(*g);
+    const void* src = nullptr;
+    switch (field) {
+      case UF_U: case UF_V: case UF_W: src = g->Q[g->cur][field]; break;
+      case UF_P: src = g->X; break;
+      case UF_K: src = g->K[g->kcur]; break;
+      case UF_OMEGA: src = g->Wo[g->kcur]; break;
+      case UF_NUT: src = g->NUT; break;
+    }
+    launch_pack<T>(*g, P, src, dst, field, 0);
+  };
+  if (g->esize == 4) go(float());
+  else go(double());
+  check_launch();
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats) {
+  if (!g) return fail(UF_EINVAL, "NULL grid");
+  if (nsteps < 0) return fail(UF_EINVAL, "nsteps must be >= 0");
+  UF_GUARD_BEGIN
+  StepAccum acc;
+  UF_HIP_CHECK(hipEventRecord(g->ev0, g->stream));
+  if (g->esize == 4) run_steps<float>(*g, nsteps, acc);
+  else run_steps<double>(*g, nsteps, acc);
+  UF_HIP_CHECK(hipEventRecord(g->ev1, g->stream));
+  if (stats) {
+    UF_HIP_CHECK(hipEventSynchronize(g->ev1));
+    float ms = 0;
+    UF_HIP_CHECK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
+    stats->cg_iters = acc.last_iters;
+    stats->cg_iters_total = acc.iters_total;
+    stats->cg_rel_residual = acc.last_rel;
+    stats->converged = !(acc.noconv || acc.nonfinite);
+    stats->nonfinite = acc.nonfinite;
+    stats->ms = ms;
+  }
+  if (acc.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the pressure solve");
+  if (acc.noconv) return fail(UF_ENOCONV, "pressure CG reached cg_maxit");
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_stats* stats) {
+  if (!g || !b_dev || !x_dev) return fail(UF_EINVAL, "NULL argument");
+  UF_GUARD_BEGIN
+  SolveResult r;
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    const Params<T> P = make_params<T>(*g);
+    launch_pack<T>(*g, P, b_dev, g->Qv, UF_P, 1);
+    launch_pack<T>(*g, P, x_dev, g->X, UF_P, 1);
+    check_launch();
+    r = solve_pressure<T>(*g, P, g->Q[g->cur], g->Qv);
+    launch_pack<T>(*g, P, g->X, x_dev, UF_P, 0);
+    check_launch();
+  };
+  if (g->esize == 4) go(float());
+  else go(double());
+  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->cg_iters = r.iters;
+    stats->cg_iters_total = r.iters;
+    stats->cg_rel_residual = r.rel;
+    stats->converged = !(r.noconv || r.nonfinite);
+    stats->nonfinite = r.nonfinite;
+  }
+  if (r.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the pressure solve");
+  if (r.noconv) return fail(UF_ENOCONV, "pressure CG reached cg_maxit");
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_dev) {
+  if (!g || !x_dev || !y_dev) return fail(UF_EINVAL, "NULL argument");
+  if (op != UF_OP_POISSON && op != UF_OP_PRECOND) return fail(UF_EINVAL, "unknown operator");
+  UF_GUARD_BEGIN
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    const Params<T> P = make_params<T>(*g);
+    launch_pack<T>(*g, P, x_dev, g->R, UF_P, 1);
+    if (op == UF_OP_PRECOND && g->cfg.precond == UF_PC_MG) mg_apply<T>(*g, P, g->R, g->Z);
+    else launch_apply<T>(*g, P, op, g->R, g->Z);
+    launch_pack<T>(*g, P, g->Z, y_dev, UF_P, 0);
+  };
+  if (g->esize == 4) go(float());
+  else go(double());
+  check_launch();
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_objective(uf_grid g, const void*, double*, void*) {
+  (void)g;
+  return fail(UF_ENOTIMPL, "uf_objective is not provided by this build");
+}
+
+uf_status uf_adjoint_step(uf_grid g, const void* const*, const void* const*, void* const*, void*) {
+  (void)g;
+  return fail(UF_ENOTIMPL, "uf_adjoint_step is not provided by this build");
+}
+
+}  // extern "C"

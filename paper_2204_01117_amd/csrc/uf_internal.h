@@ -1,0 +1,136 @@
+// Host-side grid object and the launchers of the step kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/uf.h"
+#include "uf_device.h"
+
+namespace uf {
+
+// State of one pressure solve, kept in device memory and updated by the last
+// block of each CG kernel (deterministic FP64 reductions).
+struct CgState {
+  double bb;         // ||b||^2
+  double rr;         // ||r||^2 after the last update
+  double rz;         // r . M^-1 r of the current iterate
+  double alpha, beta;
+  double tol2_bb;    // stopping threshold on ||r||^2 (criterion 0) or r.z (criterion 1)
+  int iter;          // iterations done
+  int done;          // 1 once converged, stopped at maxit, or non-finite
+  int noconv;        // stopped at maxit
+  int nonfinite;     // NaN/Inf seen
+  int zero_rhs;      // b == 0: the solution is 0
+  int maxit;
+  int criterion;
+  int pad;
+  unsigned counter[8];
+};
+
+// One level of the multigrid hierarchy (level 0 is the fine grid).
+struct MgLevel {
+  Layout L;
+  double w[3] = {0, 0, 0};   // stencil weight per axis (1/h^2 on level 0)
+  int coarsen[3] = {0, 0, 0};// 1 if this axis is halved towards the next level
+  void* x = nullptr;         // correction
+  void* r = nullptr;         // right-hand side (restricted residual)
+  void* t = nullptr;         // scratch
+};
+
+struct CgLaunch {
+  dim3 grid;
+  int ilen;
+};
+
+struct Grid {
+  uf_config cfg{};
+  std::vector<double> profile;
+  int bc[6];
+  Layout L{};
+  size_t nelem = 0;          // padded elements per field
+  size_t esize = 4;          // bytes per element
+  hipStream_t stream = nullptr;
+  // device buffers (element type = dtype)
+  void* Q[3][3] = {};        // three sets of (u, v, w)
+  int cur = 0;               // set holding the state
+  void* K[2] = {};
+  void* Wo[2] = {};
+  int kcur = 0;
+  void* NUT = nullptr;
+  void* C = nullptr;         // drag coefficient per cell
+  void* PHI = nullptr;       // porosity, compact nx*ny*nz
+  void* inflow = nullptr;    // [2][nz+2]
+  // pressure solve
+  void* X = nullptr;         // pressure (the CG iterate)
+  void* R = nullptr;
+  void* Z = nullptr;
+  void* D[2] = {};
+  void* Qv = nullptr;
+  int dpar = 0;
+  double* partials = nullptr;   // S_NSLOT * cg_nb partial sums
+  size_t cg_nb = 0;             // blocks of the fine-grid CG kernels
+  int* flags = nullptr;         // [cg_maxit + 2]
+  int* exec = nullptr;          // [cg_maxit + 2]
+  CgState* st = nullptr;     // device
+  CgState* st_host = nullptr;  // pinned
+  int* flag = nullptr;       // device int used by validation kernels
+  int* flag_host = nullptr;  // pinned
+  hipEvent_t ev_status = nullptr, ev0 = nullptr, ev1 = nullptr;
+  std::vector<MgLevel> mg;
+  int mg_lt = 0;                // first level of the single-workgroup kernel
+  int mg_nc = 0;                // cells of the coarsest level
+  void* mg_cinv = nullptr;      // dense inverse of the coarsest operator
+  void* mg_table = nullptr;     // device copy of the level descriptors
+  double mg_omega = 0.9;        // Jacobi weight of the smoother
+  double mg_alpha = 1.5;        // scaling of the coarse-grid correction
+  int last_iters = 0;
+  int k_in_valid = 1;
+  double k_in = 0, w_in = 0, nu_max = 0;
+};
+
+// Launchers (T = float or double), defined in the kernel sources.
+template <class T> Params<T> make_params(const Grid& g);
+template <class T> void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Qout[3]);
+template <class T> void launch_diffuse(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
+template <class T> void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
+template <class T> void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
+template <class T> void launch_face_bc(Grid& g, const Params<T>& P, void* q, int comp);
+template <class T> void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1, void* NUT, int update_kw);
+template <class T> void launch_cell_bc(Grid& g, const Params<T>& P, void* q, int use_inlet, double inlet_value);
+template <class T> void launch_porosity(Grid& g, const Params<T>& P, const void* phi);
+template <class T> void launch_pack(Grid& g, const Params<T>& P, const void* src_padded, void* dst, int field, int unpack);
+template <class T> void launch_check_range(Grid& g, const void* phi, size_t n);
+// pressure solve
+CgLaunch cg_launch(const Layout& L);
+template <class T> void launch_cg_start(Grid& g, const Params<T>& P, void* const Qs[3], const void* b);
+template <class T> void launch_cg_precond(Grid& g, const Params<T>& P, int m);
+template <class T> void launch_cg_iteration(Grid& g, const Params<T>& P, int t);
+void launch_cg_status(Grid& g, int t_end);
+template <class T> void launch_apply(Grid& g, const Params<T>& P, int op, const void* x, void* y);
+template <class T> void mg_setup(Grid& g);
+template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
+template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);
+void mg_free(Grid& g);
+
+size_t padded_bytes(const Grid& g);
+void set_error(const std::string& msg);
+const char* hip_error_name(hipError_t e);
+
+}  // namespace uf
+
+#define UF_HIP_CHECK(expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess) {                                                       \
+      throw uf::HipError(std::string(#expr) + ": " + hipGetErrorString(_e));      \
+    }                                                                             \
+  } while (0)
+
+namespace uf {
+struct HipError {
+  std::string msg;
+  explicit HipError(std::string m) : msg(std::move(m)) {}
+};
+}  // namespace uf

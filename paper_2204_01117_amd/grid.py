@@ -1,0 +1,99 @@
+"""Grid: a handle of the C ABI with torch CUDA tensors as device buffers."""
+import ctypes
+from ctypes import byref, c_int32, c_void_p
+
+from . import _lib as L
+
+
+class Grid:
+    """One simulation grid on a GPU.  ``cfg`` is a configuration dictionary
+    (see ``uf_layouts.default_config``).  All work is enqueued on torch's
+    current stream of ``device``."""
+
+    def __init__(self, cfg, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.cfg = dict(cfg)
+        self.dtype = torch.float64 if str(cfg["dtype"]) in ("f64", "1") else torch.float32
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device).cuda_stream
+        c, keep = L.make_config(self.cfg, self.stream)
+        self._cstruct = c
+        h = c_void_p()
+        L.check(L.uf_create_grid(byref(c), byref(h)))
+        del keep
+        self.handle = h
+        self.n = (int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"]))
+
+    # ------------------------------------------------------------------ util
+    def extent(self, name):
+        d = (c_int32 * 3)()
+        L.uf_field_extent(byref(self._cstruct), L.FIELD_IDS[name], d)
+        return tuple(d)
+
+    def _dev(self, t, shape):
+        torch = self.torch
+        t = torch.as_tensor(t).to(device=self.device, dtype=self.dtype).contiguous()
+        if tuple(t.shape) != tuple(shape):
+            t = t.reshape(shape)
+        return t
+
+    # ------------------------------------------------------------------- API
+    def set_porosity(self, phi):
+        t = self._dev(phi, self.n)
+        L.check(L.uf_set_porosity(self.handle, c_void_p(t.data_ptr())))
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def set_field(self, name, arr):
+        t = self._dev(arr, self.extent(name))
+        L.check(L.uf_set_field(self.handle, L.FIELD_IDS[name], c_void_p(t.data_ptr())))
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def get_field(self, name):
+        out = self.torch.empty(self.extent(name), dtype=self.dtype, device=self.device)
+        L.check(L.uf_get_field(self.handle, L.FIELD_IDS[name], c_void_p(out.data_ptr())))
+        return out
+
+    def state(self):
+        return {f: self.get_field(f) for f in ("u", "v", "w", "p", "k", "omega", "nut")}
+
+    def set_state(self, st):
+        for f, a in st.items():
+            if f != "phi":
+                self.set_field(f, a)
+
+    def step(self, nsteps=1, stats=True, allow=()):
+        s = L.uf_step_stats()
+        rc = L.uf_step(self.handle, int(nsteps), byref(s) if stats else None)
+        L.check(rc, allow)
+        d = s.as_dict() if stats else {}
+        d["status"] = L.STATUS[rc]
+        return d
+
+    def pressure_solve(self, b, x0=None, allow=()):
+        b = self._dev(b, self.n)
+        x = self._dev(x0 if x0 is not None else self.torch.zeros(self.n), self.n).clone()
+        s = L.uf_step_stats()
+        rc = L.uf_pressure_solve(self.handle, c_void_p(b.data_ptr()), c_void_p(x.data_ptr()), byref(s))
+        L.check(rc, allow)
+        d = s.as_dict()
+        d["status"] = L.STATUS[rc]
+        return x, d
+
+    def apply_operator(self, op, x):
+        x = self._dev(x, self.n)
+        y = self.torch.empty(self.n, dtype=self.dtype, device=self.device)
+        L.check(L.uf_apply_operator(self.handle, int(op), c_void_p(x.data_ptr()), c_void_p(y.data_ptr())))
+        return y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.uf_destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,378 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle.
+
+Tolerances: FP32 relative L2 <= 1e-5 for one step from an identical state
+and <= 1e-4 after 100 free-running steps, per field group (velocity u, v, w
+stacked; p; k; omega); the FP64 build of the same kernels must agree with
+the oracle to <= 1e-11 per step, which separates logic errors from FP32
+rounding.  CG dot products and norms are FP64 in both precisions.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from uf_layouts import default_config, preset, preset_porosity
+from uf_layouts.configs import (BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP, INFLOW_UNIFORM, INFLOW_PROFILE,
+                                TURB_OFF, PC_NONE, PC_JACOBI, PC_AI1, PC_MG, STAGE_ALL)
+from oracle import OracleGrid, Geometry
+from oracle import step as S
+from oracle import bc as B
+from oracle.pressure import poisson_matrix, ai_preconditioner
+from helpers import rel, to_np, state_errors, random_small_config, random_porosity
+
+import paper_2204_01117_amd as U
+
+TOL = {"f64": 1e-11, "f32": 1e-5}
+CG_TOL = {"f64": 1e-13, "f32": 1e-7}
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_grid(cfg, phi=None, state=None):
+    g = U.Grid(cfg)
+    if phi is not None:
+        g.set_porosity(torch.as_tensor(phi))
+    if state is not None:
+        g.set_state({f: torch.as_tensor(v) for f, v in state.items()})
+    return g
+
+
+def assert_close(errs, tol, fields=("vel", "p", "k", "omega", "nut"), what=""):
+    bad = {f: e for f, e in errs.items() if f in fields and not e <= tol}
+    assert not bad, "%s errors above %.1e: %s (all: %s)" % (what, tol, bad, errs)
+
+
+# ------------------------------------------------------------- operators ---
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_poisson_operator_matches_matrix(seed, dtype):
+    cfg = random_small_config(seed, dtype=dtype, precond=PC_AI1)
+    log("case", seed, dtype, cfg["nx"], cfg["ny"], cfg["nz"], cfg["bc"])
+    g = gpu_grid(cfg)
+    A = poisson_matrix(Geometry(cfg))
+    x = np.random.default_rng(seed).normal(size=g.n)
+    y = to_np(g.apply_operator(0, torch.tensor(x)))
+    assert rel(y.ravel(), A @ x.ravel()) < (1e-14 if dtype == "f64" else 2e-6)
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("pc", [PC_AI1, PC_JACOBI, PC_NONE])
+def test_preconditioner_matches_matrix(seed, pc):
+    cfg = random_small_config(seed, dtype="f64", precond=pc, ai_omega=1.6)
+    g = gpu_grid(cfg)
+    A = poisson_matrix(Geometry(cfg))
+    if pc == PC_AI1:
+        M, _ = ai_preconditioner(A, 1.6)
+    elif pc == PC_JACOBI:
+        M = np.diag(1.0 / A.diagonal())
+    else:
+        M = np.eye(A.shape[0])
+    x = np.random.default_rng(seed + 7).normal(size=g.n)
+    y = to_np(g.apply_operator(1, torch.tensor(x)))
+    assert rel(y.ravel(), M @ x.ravel()) < 1e-14
+    g.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 32, 16), (12, 10, 6), (13, 7, 5), (40, 24, 3), (16, 16, 1), (3, 3, 3)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_multigrid_is_symmetric_positive_definite(shape, dtype):
+    cfg = default_config(*shape, 2.0, dtype=dtype, precond=PC_MG, dt=0.1)
+    g = gpu_grid(cfg)
+    rng = np.random.default_rng(sum(shape))
+    tol = 1e-12 if dtype == "f64" else 2e-5
+    for _ in range(3):
+        x = rng.normal(size=g.n)
+        y = rng.normal(size=g.n)
+        Mx = to_np(g.apply_operator(1, torch.tensor(x)))
+        My = to_np(g.apply_operator(1, torch.tensor(y)))
+        a, b = float((y * Mx).sum()), float((x * My).sum())
+        assert abs(a - b) <= tol * math.sqrt(float((x * Mx).sum()) * float((y * My).sum()))
+        assert float((x * Mx).sum()) > 0
+    # applying twice gives the identical result (a fixed linear operator)
+    x = rng.normal(size=g.n)
+    assert np.array_equal(to_np(g.apply_operator(1, torch.tensor(x))), to_np(g.apply_operator(1, torch.tensor(x))))
+    g.close()
+
+
+@pytest.mark.parametrize("pc", [PC_MG, PC_AI1, PC_JACOBI, PC_NONE])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pressure_solve_matches_direct(pc, dtype):
+    cfg = default_config(24, 16, 10, 2.0, dtype=dtype, precond=pc, cg_tol=CG_TOL[dtype], cg_maxit=5000,
+                         bc=[BC_INLET, BC_OUTLET, BC_WALL, BC_OUTLET, BC_WALL, BC_SLIP])
+    g = gpu_grid(cfg)
+    og = OracleGrid(cfg, solver="direct")
+    b = np.random.default_rng(3).normal(size=g.n)
+    x, st = g.pressure_solve(torch.tensor(b))
+    xd, _ = og.pressure.solve(b.ravel(), np.zeros(b.size))
+    assert st["converged"] == 1 and st["cg_rel_residual"] <= CG_TOL[dtype]
+    assert rel(to_np(x).ravel(), xd) < (1e-10 if dtype == "f64" else 5e-5)
+    g.close()
+
+
+# -------------------------------------------------- one step, stage by stage
+def _prepared_pair(cfg, phi, nsteps, prep_stages=STAGE_ALL):
+    og = OracleGrid(dict(cfg, stages=prep_stages))
+    og.set_porosity(phi)
+    og.step(nsteps)
+    return og
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("stages", [1, 2, 4, 8, 16, 31])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_step_parity_random_grids(seed, stages, dtype):
+    cfg = random_small_config(seed, dtype=dtype, precond=PC_MG, cg_tol=CG_TOL[dtype], cg_maxit=5000)
+    n = (cfg["nx"], cfg["ny"], cfg["nz"])
+    phi = random_porosity(seed, n)
+    log("case", seed, stages, dtype, n, cfg["bc"], "%.1f deg" % cfg["wind_dir_deg"])
+    og = _prepared_pair(cfg, phi, 2)
+    if stages == 8:
+        # the projection alone needs a field that is not divergence free
+        og.cfg["stages"] = 7
+        og.step(1)
+    og.cfg["stages"] = stages
+    g = gpu_grid(dict(cfg, stages=stages), phi, og.state())
+    og.step(1)
+    g.step(1)
+    assert_close(state_errors(g.state(), og.state()), TOL[dtype], what="stages=%d" % stages)
+    g.close()
+
+
+@pytest.mark.parametrize("pc", [PC_MG, PC_AI1])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_step_parity_c0(pc, dtype):
+    p = preset("C0")
+    phi, cfg = preset_porosity(p)
+    cfg = dict(cfg, dtype=dtype, precond=pc, cg_tol=CG_TOL[dtype], cg_maxit=5000)
+    og = _prepared_pair(cfg, phi, 5)
+    g = gpu_grid(cfg, phi, og.state())
+    og.step(1)
+    st = g.step(1)
+    assert st["converged"] == 1
+    assert_close(state_errors(g.state(), og.state()), TOL[dtype], what="C0 one step")
+    g.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_hundred_steps_c0(dtype, tol):
+    p = preset("C0")
+    phi, cfg = preset_porosity(p)
+    cfg = dict(cfg, dtype=dtype, precond=PC_MG, cg_tol=CG_TOL[dtype] if dtype == "f64" else 1e-6, cg_maxit=5000)
+    og = OracleGrid(cfg)
+    og.set_porosity(phi)
+    g = gpu_grid(cfg, phi)
+    for _ in range(10):
+        og.step(10)
+        st = g.step(10)
+        assert st["converged"] == 1
+    errs = state_errors(g.state(), og.state())
+    log("C0 100 steps", dtype, errs)
+    assert_close(errs, tol, fields=("vel", "p", "k", "omega"), what="C0 100 steps")
+    g.close()
+
+
+# ------------------------------------------------------- physics on the GPU
+def test_uniform_flow_preserved_gpu():
+    cfg = default_config(12, 6, 5, 2.0, dt=0.3, inflow_kind=INFLOW_UNIFORM, u_ref=4.0, dtype="f32",
+                         bc=[BC_INLET, BC_OUTLET, BC_SLIP, BC_OUTLET, BC_SLIP, BC_SLIP])
+    g = gpu_grid(cfg)
+    s0 = {f: to_np(v) for f, v in g.state().items()}
+    g.step(5)
+    s1 = {f: to_np(v) for f, v in g.state().items()}
+    for f in ("u", "v", "w", "p"):
+        assert np.abs(s1[f] - s0[f]).max() <= 4e-6, f
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-4)])
+def test_darcy_slab_gpu(dtype, tol):
+    U0, dt, dx, rho, nx, n, i0, phs = 1.5, 0.05, 1.0, 1.225, 16, 4, 6, 0.6
+    cfg = default_config(nx, 3, 3, dx, dt=dt, inflow_kind=INFLOW_UNIFORM, u_ref=U0, turb_model=TURB_OFF,
+                         dtype=dtype, cg_tol=CG_TOL[dtype], cg_maxit=2000,
+                         bc=[BC_INLET, BC_OUTLET, BC_SLIP, BC_SLIP, BC_SLIP, BC_SLIP])
+    phi = np.ones((nx, 3, 3))
+    phi[i0:i0 + n] = phs
+    g = gpu_grid(cfg, phi)
+    g.step(1)
+    c = 0.62 * ((1 - phs) / (phs + 1e-10)) ** 2.5
+    p = to_np(g.get_field("p"))[:, 1, 1]
+    drop = p[i0 - 1] - p[i0 + n]
+    assert abs(drop - rho * c * U0 ** 2 * n * dx) <= tol * abs(drop)
+    assert np.abs(to_np(g.get_field("u")) - U0).max() <= tol * U0
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_poiseuille_gpu(dtype, tol):
+    nx, ny, nz, h, A, nu, dt, rho = 10, 3, 8, 0.5, 0.3, 0.02, 0.05, 1.225
+    H = nz * h
+    z = (np.arange(nz) + 0.5) * h
+    prof = A * (z * (H - z) + h * h / 4.0)
+    cfg = default_config(nx, ny, nz, h, dt=dt, nu=nu, turb_model=TURB_OFF, dtype=dtype,
+                         inflow_kind=INFLOW_PROFILE, inflow_profile=list(prof),
+                         cg_tol=CG_TOL[dtype], cg_maxit=2000,
+                         bc=[BC_INLET, BC_OUTLET, BC_SLIP, BC_SLIP, BC_WALL, BC_WALL])
+    g = gpu_grid(cfg)
+    g.step(100)
+    u = to_np(g.get_field("u"))
+    assert np.abs(u - prof[None, None, :]).max() <= tol * prof.max()
+    p = to_np(g.get_field("p"))
+    expect = 2 * A * rho * nu * h * (nx - np.arange(nx))
+    assert np.abs(p - expect[:, None, None]).max() <= tol * expect.max() * 10
+
+
+def test_mirror_symmetry_gpu_f64():
+    p = preset("C0")
+    phi, cfg = preset_porosity(p)
+    g = gpu_grid(dict(cfg, dtype="f64", cg_tol=1e-13, cg_maxit=5000), phi)
+    g.step(10)
+    s = {f: to_np(v) for f, v in g.state().items()}
+    for f in ("u", "w", "p", "k", "omega", "nut"):
+        assert rel(s[f][:, ::-1, :], s[f]) < 1e-11, f
+    assert rel(-s["v"][:, ::-1, :], s["v"]) < 1e-11
+
+
+# ------------------------------------------------------------ error paths ---
+def test_invalid_porosity_is_rejected_and_state_kept():
+    cfg = default_config(8, 6, 4, 2.0, dt=0.2, dtype="f32")
+    g = gpu_grid(cfg, np.full((8, 6, 4), 0.5))
+    before = to_np(g.get_field("phi"))
+    for bad in (np.full((8, 6, 4), 1.5), np.where(np.arange(192).reshape(8, 6, 4) == 5, np.nan, 0.5),
+                np.full((8, 6, 4), -0.1)):
+        with pytest.raises(U.UFError) as e:
+            g.set_porosity(bad)
+        assert e.value.name == "UF_EINVAL"
+    assert np.array_equal(to_np(g.get_field("phi")), before)
+    g.step(1)
+
+
+def test_maxit_reports_noconv_and_advances():
+    p = preset("C0")
+    phi, cfg = preset_porosity(p)
+    g = gpu_grid(dict(cfg, dtype="f32", cg_maxit=1, precond=PC_NONE), phi)
+    u0 = to_np(g.get_field("u"))
+    st = g.step(1, allow=(4,))
+    assert st["status"] == "UF_ENOCONV" and st["converged"] == 0 and st["cg_iters"] == 1
+    assert not np.array_equal(to_np(g.get_field("u")), u0)
+
+
+def test_nonfinite_state_reports_enonfinite():
+    cfg = default_config(8, 6, 4, 2.0, dt=0.2, dtype="f32")
+    g = gpu_grid(cfg)
+    u = to_np(g.get_field("u"))
+    u[3, 2, 1] = np.nan
+    g.set_field("u", u)
+    st = g.step(1, allow=(5,))
+    assert st["status"] == "UF_ENONFINITE" and st["nonfinite"] == 1
+
+
+# ------------------------------------------------ determinism and restart ---
+def test_bitwise_determinism_and_checkpoint_restart():
+    p = preset("C0")
+    phi, cfg = preset_porosity(p)
+    cfg = dict(cfg, dtype="f32")
+    a = gpu_grid(cfg, phi)
+    b = gpu_grid(cfg, phi)
+    a.step(10)
+    b.step(5)
+    snap = {f: v.clone() for f, v in b.state().items()}
+    c = gpu_grid(cfg, phi, snap)
+    c.step(5)
+    b.step(5)
+    sa, sb, sc = a.state(), b.state(), c.state()
+    for f in sa:
+        assert torch.equal(sa[f], sb[f]), f
+        assert torch.equal(sa[f], sc[f]), f
+
+
+# ---------------------------------------------------- full size (C1 shape) --
+def _np_state(g):
+    return {f: to_np(v) for f, v in g.state().items()}
+
+
+def test_full_size_c1_stages_against_oracle():
+    """At the 256x256x64 workload, in the launch configuration the benchmark
+    times: local stages element by element against the oracle (full arrays),
+    the projection through the properties that define it."""
+    p = preset("C1")
+    phi, cfg = preset_porosity(p)
+    g = gpu_grid(cfg, phi)
+    g.step(3)
+    s0 = _np_state(g)
+    og = OracleGrid(dict(cfg, stages=7), solver="none")
+    og.set_porosity(phi)
+    for f, v in s0.items():
+        og.set_field(f, v)
+    # advection + diffusion + drag
+    g7 = gpu_grid(dict(cfg, stages=7), phi, s0)
+    g7.step(1)
+    s1 = _np_state(g7)
+    og.step(1)
+    so = og.state()
+    errs = state_errors(s1, so)
+    log("C1 stages 7", errs)
+    assert errs["vel"] <= 1e-5
+    # projection: the solve's residual and the divergence it leaves
+    g8 = gpu_grid(dict(cfg, stages=8), phi, s1)
+    st = g8.step(1)
+    s2 = _np_state(g8)
+    geo = og.g
+    Qp = []
+    for c, f in enumerate("uvw"):
+        q = np.zeros(geo.face_pshape(c))
+        B.win(q, geo.face_ext(c))[...] = s1[f]
+        Qp.append(geo.apply_face_bc(q, c))
+    bvec = -(cfg["rho"] / cfg["dt"]) * S.divergence(geo, Qp)
+    A = og.pressure.A
+    res = rel(A @ s2["p"].ravel(), bvec.ravel())
+    log("C1 projection residual", res, st)
+    # CG stops on its recursive FP64-accumulated residual (<= cg_tol); the
+    # residual recomputed here in FP64 from the FP32 pressure is bounded by
+    # what an FP32 iterate can represent (about eps32 * kappa(A) * ||b||)
+    assert st["converged"] == 1 and st["cg_rel_residual"] <= cfg["cg_tol"] and res <= 1e-4
+    Qn = S.project(geo, Qp, s2["p"], cfg["rho"])
+    for c, f in enumerate("uvw"):
+        assert rel(s2[f], B.win(Qn[c], geo.face_ext(c))) <= 1e-5, f
+    div = S.divergence(geo, Qn)
+    assert np.linalg.norm(div) <= 1e-4 * np.linalg.norm(bvec) * cfg["dt"] / cfg["rho"]
+    # turbulence
+    g16 = gpu_grid(dict(cfg, stages=16), phi, s2)
+    g16.step(1)
+    s3 = _np_state(g16)
+    og.cfg["stages"] = 16
+    for f, v in s2.items():
+        og.set_field(f, v)
+    og.step(1)
+    errs = state_errors(s3, og.state())
+    log("C1 stage 16", errs)
+    assert_close(errs, 1e-5, fields=("k", "omega", "nut"), what="C1 turbulence")
+    for gg in (g, g7, g8, g16):
+        gg.close()
+
+
+def test_full_size_c2_step_is_finite_and_projected():
+    p = preset("C2")
+    phi, cfg = preset_porosity(p)
+    g = gpu_grid(cfg, phi)
+    st = g.step(2)
+    assert st["converged"] == 1 and st["nonfinite"] == 0
+    s = _np_state(g)
+    for f, v in s.items():
+        assert np.isfinite(v).all(), f
+    geo = Geometry(cfg)
+    Q = []
+    for c, f in enumerate("uvw"):
+        q = np.zeros(geo.face_pshape(c))
+        B.win(q, geo.face_ext(c))[...] = s[f]
+        Q.append(geo.apply_face_bc(q, c))
+    # the turbulence stage does not touch u, so the state is the projected one
+    div = S.divergence(geo, Q)
+    assert np.abs(div).max() * cfg["dx"] / cfg["u_ref"] < 1e-3
+    g.close()
