@@ -12,7 +12,7 @@ from ._lib import (lib, LIB_PATH, UFError, uf_config, uf_step_stats, make_config
 from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_field,
                    uf_get_field, uf_field_extent, uf_step, uf_pressure_solve,
                    uf_apply_operator, uf_objective, uf_adjoint_step, uf_set_stream,
-                   uf_last_error)
+                   uf_kernel_timer_enable, uf_kernel_timer_read, uf_last_error, TIMED_KERNELS)
 from .grid import Grid
 
 __all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_config",
@@ -20,4 +20,4 @@ __all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_con
            "uf_create_grid", "uf_destroy_grid", "uf_set_porosity", "uf_set_field",
            "uf_get_field", "uf_field_extent", "uf_step", "uf_pressure_solve",
            "uf_apply_operator", "uf_objective", "uf_adjoint_step", "uf_set_stream",
-           "uf_last_error"]
+           "uf_kernel_timer_enable", "uf_kernel_timer_read", "uf_last_error", "TIMED_KERNELS"]

@@ -65,6 +65,8 @@ _SIGS = {
     "uf_objective": (c_int32, [c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "uf_adjoint_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "uf_kernel_timer_enable": (c_int32, [c_void_p, ctypes.c_uint32]),
+    "uf_kernel_timer_read": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "uf_last_error": (c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -84,6 +86,10 @@ uf_apply_operator = lib.uf_apply_operator
 uf_objective = lib.uf_objective
 uf_adjoint_step = lib.uf_adjoint_step
 uf_set_stream = lib.uf_set_stream
+uf_kernel_timer_enable = lib.uf_kernel_timer_enable
+uf_kernel_timer_read = lib.uf_kernel_timer_read
+TIMED_KERNELS = ("cg_Ad", "cg_axpy", "cg_precond", "mg_down0", "mg_up0", "mg_coarse", "cg_init",
+                 "advect_fwd", "advect_corr", "diffuse", "drag", "project", "turbulence")
 uf_last_error = lib.uf_last_error
 
 

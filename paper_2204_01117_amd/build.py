@@ -1,6 +1,7 @@
 """Build libuf.so (the HIP kernels and the C ABI) for gfx950, in-tree.
 
-Usage: python -m paper_2204_01117_amd.build   (or build() from Python)
+Usage: python paper_2204_01117_amd/build.py
+(run by path: importing the package loads libuf.so, which may be stale).
 Objects go to paper_2204_01117_amd/_build/, the library next to this file.
 """
 import concurrent.futures

@@ -2,20 +2,25 @@
 //
 // Cell-centred hierarchy: an axis is halved while its cell count is even
 // and at least 4; levels stop at <= 256 cells (or when no axis halves).
-// Restriction averages the children (R = P^T / m, m children per coarse
-// cell) and prolongation copies the parent (piecewise constant P).  The
-// coarse operator is the Galerkin product R A P, which for this pair is
-// again a 7-point stencil with the same boundary rows and per-axis weights
-// halved on every halved axis.  Smoothing: one damped-Jacobi sweep before
-// (from zero) and one after the coarse correction, so the V-cycle is a
-// fixed symmetric positive-definite operator as PCG requires.  The coarsest
-// level is solved with its exact dense inverse (<= 512 cells) or, failing
-// that, with a fixed number of Jacobi sweeps.
+// Prolongation P is trilinear between cell centres (per halved axis: 3/4 of
+// the parent and 1/4 of the parent's neighbour on the child's side; past a
+// domain side the neighbour is the parent's mirror image, + for a Neumann
+// side and - for an outlet, where the correction vanishes).  Restriction is
+// its transpose R = P^T / m (m = children per coarse cell), so interior
+// weights are (1, 3, 3, 1)/8 per halved axis.  Coarse operators are the
+// 7-point stencil re-discretised with the coarse spacing (weights / 4 per
+// halved axis) and the same boundary rows.  Smoothing: one damped-Jacobi
+// sweep before (from zero) and one after the coarse correction, so the
+// V-cycle is a fixed symmetric positive-definite operator, as PCG requires.
+// The coarsest level is solved with its exact dense inverse (<= 512 cells)
+// or, failing that, with a fixed number of Jacobi sweeps.
 //
-// Kernels per application: restrict level 0 -> 1 (and decide whether the
-// solve has already finished), restrict down to the first small level, one
-// single-workgroup kernel for all small levels, prolongate + smooth back up,
-// and the fine-level prolongation + smoothing that writes z and r.z.
+// Kernels of one application (the fine-level residual of the pre-smoothed
+// problem comes from the CG update kernel, see k_mg_axpy): restrict level
+// 0 -> 1 (block 0 also decides whether the solve has finished), restrict
+// down to the first small level, one single-workgroup kernel for all small
+// levels, prolongate + smooth back up, and the fine-level prolongation +
+// smoothing that writes z and the partials of r.z.
 #include <cmath>
 #include <cstdlib>
 #include <vector>
@@ -26,18 +31,12 @@ namespace uf {
 
 constexpr int kMgMaxLevels = 16;
 constexpr int kTailThreads = 1024;
-constexpr int kMgFineBlock = 512;   // must match the CG kernels' block (cg_launch)
+constexpr int kMgFineBlock = 512;        // must match the CG kernels' block (cg_launch)
 constexpr long long kTailCells = 1024;   // levels this small run in the single-workgroup kernel
 constexpr int kDenseMax = 512;           // largest coarsest level with an exact inverse
 constexpr int kCoarseSweeps = 10;        // Jacobi sweeps when there is no exact inverse
-// Smoother weight and coarse-correction scaling, chosen by measured PCG
-// iteration counts on the 256x256x64 and 512x512x128 workloads (alpha in
-// [1.4, 1.7] and omega 0.9 are within a few percent of each other; alpha = 1
-// needs 40-75% more iterations).  A scaled coarse correction keeps the
-// V-cycle symmetric; it compensates the low accuracy of piecewise-constant
-// prolongation for smooth error.
-constexpr double kJacobiOmega = 0.9;
-constexpr double kCoarseAlpha = 1.5;
+// Jacobi weight, chosen by PCG iteration counts (0.8 and 0.9 within 10%).
+constexpr double kJacobiOmega = 0.8;
 
 template <class T>
 struct MgLvl {
@@ -45,10 +44,9 @@ struct MgLvl {
   T w[3];
   T omd_in;   // om / D of an interior cell
   int c[3];   // axis halved towards the next level
-  int m;      // children per next-level cell
-  T* r;
-  T* x;
-  T* t;       // scratch (coarsest-level Jacobi)
+  T* r;       // right-hand side
+  T* x;       // result (z on level 0)
+  T* t;       // scratch: level 0 = residual of the pre-smoothed problem
 };
 
 // Scalars shared by every level.  Kernels get these and the descriptors of
@@ -58,14 +56,20 @@ template <class T>
 struct MgCommon {
   int bc[6];
   T om;       // Jacobi weight
-  T alpha;    // scaling of the coarse-grid correction
+  T sgn[6];   // mirror sign of a correction across each side: -1 outlet, +1 otherwise
 };
+
+__host__ __device__ static inline long long ncells(const Layout& L) { return (long long)L.nx * L.ny * L.nz; }
 
 __device__ __forceinline__ void decode(int idx, const Layout& L, int& i, int& j, int& k) {
   k = idx % L.nz;
   const int r = idx / L.nz;
   j = r % L.ny;
   i = r / L.ny;
+}
+
+__device__ __forceinline__ bool deep_inside(const Layout& L, int i, int j, int k) {
+  return i >= 2 && i < L.nx - 2 && j >= 2 && j < L.ny - 2 && k >= 2 && k < L.nz - 2;
 }
 
 // om / D at a cell of level F; 0 outside the level, so that a ghost (whose
@@ -78,93 +82,316 @@ __device__ __forceinline__ T omd(const MgCommon<T>& K, const MgLvl<T>& F, int i,
   return K.om / diag_w(K.bc, L, F.w, i, j, k);
 }
 
-// Residual of the pre-smoothed level-F problem averaged over the children
-// of next-level cell (I, J, K): mean over children f of r_f - (A e)_f with
-// e = om D^-1 r (one Jacobi sweep from zero), i.e.
-//   r_f - om r_f + sum_a w_a (e_{f+a} + e_{f-a}).
+// Residual of the pre-smoothed problem at cell (i,j,k) of level F:
+// r - A e with e = om D^-1 r (one Jacobi sweep from zero), i.e.
+//   (1 - om) r + sum_a w_a (e_{+a} + e_{-a}).
 template <class T>
-__device__ __forceinline__ T down_body(const MgCommon<T>& K, const MgLvl<T>& F, int I, int J, int Kc) {
+__device__ __forceinline__ T smoothed_residual(const MgCommon<T>& K, const MgLvl<T>& F, const T* __restrict__ r, int i,
+                                               int j, int k) {
   const Layout& L = F.L;
-  const T* __restrict__ r = F.r;
-  auto e_at = [&](int i, int j, int k) -> T { return omd(K, F, i, j, k) * r[L.at(i, j, k)]; };
-  T acc = T(0);
-  for (int a0 = 0; a0 <= F.c[0]; ++a0)
-    for (int a1 = 0; a1 <= F.c[1]; ++a1)
-      for (int a2 = 0; a2 <= F.c[2]; ++a2) {
-        const int i = (I << F.c[0]) + a0, j = (J << F.c[1]) + a1, k = (Kc << F.c[2]) + a2;
-        const T rf = r[L.at(i, j, k)];
-        const T s = F.w[0] * (e_at(i + 1, j, k) + e_at(i - 1, j, k)) + F.w[1] * (e_at(i, j + 1, k) + e_at(i, j - 1, k)) +
-                    F.w[2] * (e_at(i, j, k + 1) + e_at(i, j, k - 1));
-        acc += (T(1) - K.om) * rf + s;
-      }
-  return acc / T(F.m);
+  const long long o = L.at(i, j, k);
+  T s;
+  if (deep_inside(L, i, j, k)) {
+    s = F.omd_in * (F.w[0] * (r[o + L.SX] + r[o - L.SX]) + F.w[1] * (r[o + L.PZ] + r[o - L.PZ]) +
+                    F.w[2] * (r[o + 1] + r[o - 1]));
+  } else {
+    auto e_at = [&](int ii, int jj, int kk) -> T { return omd(K, F, ii, jj, kk) * r[L.at(ii, jj, kk)]; };
+    s = F.w[0] * (e_at(i + 1, j, k) + e_at(i - 1, j, k)) + F.w[1] * (e_at(i, j + 1, k) + e_at(i, j - 1, k)) +
+        F.w[2] * (e_at(i, j, k + 1) + e_at(i, j, k - 1));
+  }
+  return (T(1) - K.om) * r[o] + s;
 }
 
-// Value before post-smoothing at a cell of level F: the pre-smoothed
-// om D^-1 r plus the prolongated, scaled coarse correction.  Zero outside
-// the level (r and the coarse correction have zero ghosts).
+// Trilinear prolongation along one axis: a child f takes w0 x[i0] + w1 x[i1].
+template <class T>
+struct Tap2 {
+  int i0, i1;
+  T w0, w1;
+};
+
+template <class T>
+__device__ __forceinline__ Tap2<T> ptap(int f, int c, int nc, T slo, T shi) {
+  if (!c) return Tap2<T>{f, f, T(1), T(0)};
+  const int I = f >> 1;
+  const int J = (f & 1) ? I + 1 : I - 1;
+  if (J < 0) return Tap2<T>{I, I, T(0.75) + T(0.25) * slo, T(0)};
+  if (J >= nc) return Tap2<T>{I, I, T(0.75) + T(0.25) * shi, T(0)};
+  return Tap2<T>{I, J, T(0.75), T(0.25)};
+}
+
+// (P x_c) at cell (i, j, k) of level F (inside the level).
+template <class T>
+__device__ __forceinline__ T prolong(const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, int i, int j, int k) {
+  const Tap2<T> a = ptap(i, F.c[0], C.L.nx, K.sgn[0], K.sgn[1]);
+  const Tap2<T> b = ptap(j, F.c[1], C.L.ny, K.sgn[2], K.sgn[3]);
+  const Tap2<T> c = ptap(k, F.c[2], C.L.nz, K.sgn[4], K.sgn[5]);
+  const T* __restrict__ x = C.x;
+  const Layout& L = C.L;
+  auto row = [&](int I, int J) { return c.w0 * x[L.at(I, J, c.i0)] + c.w1 * x[L.at(I, J, c.i1)]; };
+  return a.w0 * (b.w0 * row(a.i0, b.i0) + b.w1 * row(a.i0, b.i1)) +
+         a.w1 * (b.w0 * row(a.i1, b.i0) + b.w1 * row(a.i1, b.i1));
+}
+
+// Restriction weights along one axis for coarse index I: fine cells
+// f = 2I-1 .. 2I+2 with weight P(f, I) / 2 on a halved axis (taps past the
+// level get weight 0 and a clamped index), or f = I alone.  Fixed tap
+// positions keep the arrays in registers.
+template <class T>
+__device__ __forceinline__ int rtaps(int I, int c, int nc, int nf, T slo, T shi, int f[4], T w[4]) {
+  if (!c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      f[q] = I;
+      w[q] = q == 0 ? T(1) : T(0);
+    }
+    return 1;
+  }
+  f[0] = 2 * I - 1 >= 0 ? 2 * I - 1 : 2 * I;
+  w[0] = 2 * I - 1 >= 0 ? T(0.125) : T(0);
+  f[1] = 2 * I;
+  w[1] = T(0.5) * (T(0.75) + (I == 0 ? T(0.25) * slo : T(0)));
+  f[2] = 2 * I + 1;
+  w[2] = T(0.5) * (T(0.75) + (I == nc - 1 ? T(0.25) * shi : T(0)));
+  f[3] = 2 * I + 2 < nf ? 2 * I + 2 : 2 * I + 1;
+  w[3] = 2 * I + 2 < nf ? T(0.125) : T(0);
+  return 4;
+}
+
+// (R res)(I, J, Kc) = sum over fine f of P(f, I)/m res_f.
+template <class T, class Res>
+__device__ __forceinline__ T restrict_at(const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, int I, int J,
+                                         int Kc, Res res) {
+  int fi[4], fj[4], fk[4];
+  T wi[4], wj[4], wk[4];
+  const int ni = rtaps(I, F.c[0], C.L.nx, F.L.nx, K.sgn[0], K.sgn[1], fi, wi);
+  const int nj = rtaps(J, F.c[1], C.L.ny, F.L.ny, K.sgn[2], K.sgn[3], fj, wj);
+  const int nk = rtaps(Kc, F.c[2], C.L.nz, F.L.nz, K.sgn[4], K.sgn[5], fk, wk);
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    if (a >= ni) break;
+    T sa = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b >= nj) break;
+      T sb = T(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q >= nk) break;
+        sb += wk[q] * res(fi[a], fj[b], fk[q]);
+      }
+      sa += wj[b] * sb;
+    }
+    acc += wi[a] * sa;
+  }
+  return acc;
+}
+
+// t = om D^-1 r + P x_c at a cell of level F; 0 outside the level.
 template <bool COARSE, class T>
 __device__ __forceinline__ T pre_plus_coarse(const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, int i, int j,
                                              int k) {
-  T v = omd(K, F, i, j, k) * F.r[F.L.at(i, j, k)];
-  if (COARSE) v += K.alpha * C.x[C.L.at(i >> F.c[0], j >> F.c[1], k >> F.c[2])];
+  const Layout& L = F.L;
+  if ((unsigned)i >= (unsigned)L.nx || (unsigned)j >= (unsigned)L.ny || (unsigned)k >= (unsigned)L.nz) return T(0);
+  T v = omd(K, F, i, j, k) * F.r[L.at(i, j, k)];
+  if (COARSE) v += prolong(K, F, C, i, j, k);
   return v;
 }
 
-// t = om D^-1 r + alpha P x_c; one Jacobi sweep: x = t + om D^-1 (r - A t).
-template <bool COARSE, class T>
-__device__ __forceinline__ T up_body(const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, int i, int j, int k) {
+// ----------------------------------------------------------------- kernels
+
+// CG update with the multigrid's first step fused in: x += alpha d,
+// r -= alpha q, partials of ||r||^2, and the residual of the pre-smoothed
+// problem (1 - om) r + sum_a w_a om/D r_neighbours from the updated r
+// (neighbours' updated r recomputed from r and q).  Marches along x.
+template <class T>
+__global__ __launch_bounds__(kMgFineBlock) void k_mg_axpy(MgCommon<T> K, MgLvl<T> F, T* __restrict__ X,
+                                                          const T* __restrict__ Rin, T* __restrict__ R,
+                                                          const T* __restrict__ Dv, const T* __restrict__ Qv,
+                                                          T* __restrict__ RES, CgCtl c, int t, int ilen) {
   const Layout& L = F.L;
-  const T D = diag_w(K.bc, L, F.w, i, j, k);
-  const T tc = pre_plus_coarse<COARSE>(K, F, C, i, j, k);
-  const T At = D * tc -
-               F.w[0] * (pre_plus_coarse<COARSE>(K, F, C, i + 1, j, k) + pre_plus_coarse<COARSE>(K, F, C, i - 1, j, k)) -
-               F.w[1] * (pre_plus_coarse<COARSE>(K, F, C, i, j + 1, k) + pre_plus_coarse<COARSE>(K, F, C, i, j - 1, k)) -
-               F.w[2] * (pre_plus_coarse<COARSE>(K, F, C, i, j, k + 1) + pre_plus_coarse<COARSE>(K, F, C, i, j, k - 1));
-  return tc + omd(K, F, i, j, k) * (F.r[L.at(i, j, k)] - At);
+  double rz = 0.0, dq = 0.0;
+  bool run = iteration_runs(c, t, &rz);
+  if (run) {
+    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb);
+    run = dq > 0.0 && isfinite(dq);
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    c.exec[t] = run;
+    if (run) c.st->iter = t + 1;
+  }
+  if (!run) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = p < L.ny * L.nz;
+  const int j = active ? p / L.nz : 0;
+  const int k = active ? p - j * L.nz : 0;
+  const int i0 = blockIdx.y * ilen;
+  const int i1 = active ? min(L.nx, i0 + ilen) : i0;
+  const T alpha = (T)(rz / dq);
+  double v[1] = {0.0};
+  if (i0 < i1) {
+    const long long SX = L.SX, PZ = L.PZ;
+    // updated residual at any cell, from the untouched input buffer
+    auto rn = [&](long long q) { return Rin[q] - alpha * Qv[q]; };
+    long long o = L.at(i0, j, k);
+    T rm = rn(o - SX), rc = rn(o);
+    for (int i = i0; i < i1; ++i, o += SX) {
+      const T rp = rn(o + SX);
+      X[o] += alpha * Dv[o];
+      R[o] = rc;
+      v[0] += (double)rc * (double)rc;
+      T s;
+      if (deep_inside(L, i, j, k)) {
+        s = F.omd_in * (F.w[0] * (rp + rm) + F.w[1] * (rn(o + PZ) + rn(o - PZ)) + F.w[2] * (rn(o + 1) + rn(o - 1)));
+      } else {
+        // zero ghosts of r and q make out-of-range neighbours vanish; omd is 0 there
+        s = F.w[0] * (omd(K, F, i + 1, j, k) * rp + omd(K, F, i - 1, j, k) * rm) +
+            F.w[1] * (omd(K, F, i, j + 1, k) * rn(o + PZ) + omd(K, F, i, j - 1, k) * rn(o - PZ)) +
+            F.w[2] * (omd(K, F, i, j, k + 1) * rn(o + 1) + omd(K, F, i, j, k - 1) * rn(o - 1));
+      }
+      RES[o] = (T(1) - K.om) * rc + s;
+      rm = rc;
+      rc = rp;
+    }
+  }
+  const int slots[1] = {S_RR};
+  write_partials<1>(v, c.part, c.stride, slots);
 }
 
-__host__ __device__ static inline long long ncells(const Layout& L) { return (long long)L.nx * L.ny * L.nz; }
-
-// Restrict level 0 -> 1; also decides whether the solve finished before
-// this preconditioner application (block 0 publishes it in flags[m]).
+// Tiles of the level kernels.  Restriction: a block owns RT_I x RT_J x RT_K
+// next-level cells (one per thread); up/smoothing: a block owns
+// UT_I x UT_J x UT_K cells of its level.
 template <class T>
-__global__ __launch_bounds__(256) void k_mg_down0(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, int has_coarse, CgCtl c,
-                                                  int m, int decide) {
-  const bool skip = decide ? precond_skip(c, m) : false;
-  if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[m] = skip;
-  if (skip || !has_coarse) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ncells(C.L)) return;
-  int I, J, Kc;
-  decode(idx, C.L, I, J, Kc);
-  C.r[C.L.at(I, J, Kc)] = down_body(K, F, I, J, Kc);
+struct MgTiles {
+  static constexpr int RT_I = 4, RT_J = 4, RT_K = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int RES_N = (2 * RT_I + 2) * (2 * RT_J + 2) * (2 * RT_K + 2);  // fine residual region
+  static constexpr int R_N = (2 * RT_I + 4) * (2 * RT_J + 4) * (2 * RT_K + 4);    // r region (+1 halo)
+  static constexpr int UT_I = 8, UT_J = 8, UT_K = 32;
+  static constexpr int T_N = (UT_I + 2) * (UT_J + 2) * (UT_K + 2);
+};
+
+__device__ __forceinline__ bool inside(const Layout& L, int i, int j, int k) {
+  return (unsigned)i < (unsigned)L.nx && (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz;
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_mg_down(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, const int* __restrict__ flags,
-                                                 int m) {
-  if (flags[m]) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ncells(C.L)) return;
-  int I, J, Kc;
-  decode(idx, C.L, I, J, Kc);
-  C.r[C.L.at(I, J, Kc)] = down_body(K, F, I, J, Kc);
+// Restriction of one tile of next-level cells.  The fine residual of the
+// pre-smoothed problem over the tile's footprint comes either from a stored
+// array (HAS_RES: level 0, written by the CG update) or is computed here from
+// r staged in LDS.  mode 0: skip when flags[m] is set; 1: block 0 decides
+// whether the solve has finished and publishes flags[m] (first kernel of a
+// preconditioner application; after convergence the work here is wasted,
+// not wrong); 2: unconditional.
+template <bool HAS_RES, class T>
+__global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, int has_coarse, CgCtl c,
+                                                     int m, int mode) {
+  using Tl = MgTiles<T>;
+  __shared__ T sres[Tl::RES_N];
+  __shared__ T sr[HAS_RES ? 1 : Tl::R_N];
+  if (mode == 1) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+      const bool skip = precond_skip(c, m);
+      if (threadIdx.x == 0) c.flags[m] = skip;
+    }
+  } else if (mode == 0) {
+    if (c.flags[m]) return;
+  }
+  if (!has_coarse) return;
+  const int X0[3] = {(int)blockIdx.z * Tl::RT_I, (int)blockIdx.y * Tl::RT_J, (int)blockIdx.x * Tl::RT_K};
+  const int TT[3] = {Tl::RT_I, Tl::RT_J, Tl::RT_K};
+  int lo[3], len[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = F.c[a] ? 2 * X0[a] - 1 : X0[a];
+    len[a] = F.c[a] ? 2 * TT[a] + 2 : TT[a];
+  }
+  const Layout& L = F.L;
+  const int nres = len[0] * len[1] * len[2];
+  if (HAS_RES) {
+    for (int idx = threadIdx.x; idx < nres; idx += blockDim.x) {
+      const int kk = idx % len[2], jj = (idx / len[2]) % len[1], ii = idx / (len[2] * len[1]);
+      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
+      sres[idx] = inside(L, i, j, k) ? F.t[L.at(i, j, k)] : T(0);
+    }
+  } else {
+    const int q1 = len[1] + 2, q2 = len[2] + 2;
+    const int nq = (len[0] + 2) * q1 * q2;
+    for (int idx = threadIdx.x; idx < nq; idx += blockDim.x) {
+      const int kk = idx % q2, jj = (idx / q2) % q1, ii = idx / (q2 * q1);
+      const int i = lo[0] - 1 + ii, j = lo[1] - 1 + jj, k = lo[2] - 1 + kk;
+      sr[idx] = inside(L, i, j, k) ? F.r[L.at(i, j, k)] : T(0);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nres; idx += blockDim.x) {
+      const int kk = idx % len[2], jj = (idx / len[2]) % len[1], ii = idx / (len[2] * len[1]);
+      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
+      T res = T(0);
+      if (inside(L, i, j, k)) {
+        const int q = ((ii + 1) * q1 + (jj + 1)) * q2 + (kk + 1);
+        const int sI = q1 * q2;
+        if (deep_inside(L, i, j, k)) {
+          res = (T(1) - K.om) * sr[q] + F.omd_in * (F.w[0] * (sr[q + sI] + sr[q - sI]) + F.w[1] * (sr[q + q2] + sr[q - q2]) +
+                                                    F.w[2] * (sr[q + 1] + sr[q - 1]));
+        } else {
+          res = (T(1) - K.om) * sr[q] +
+                F.w[0] * (omd(K, F, i + 1, j, k) * sr[q + sI] + omd(K, F, i - 1, j, k) * sr[q - sI]) +
+                F.w[1] * (omd(K, F, i, j + 1, k) * sr[q + q2] + omd(K, F, i, j - 1, k) * sr[q - q2]) +
+                F.w[2] * (omd(K, F, i, j, k + 1) * sr[q + 1] + omd(K, F, i, j, k - 1) * sr[q - 1]);
+        }
+      }
+      sres[idx] = res;
+    }
+  }
+  __syncthreads();
+  const int tk = threadIdx.x % Tl::RT_K, tj = (threadIdx.x / Tl::RT_K) % Tl::RT_J, ti = threadIdx.x / (Tl::RT_K * Tl::RT_J);
+  if (ti >= Tl::RT_I) return;
+  const int I = X0[0] + ti, J = X0[1] + tj, Kc = X0[2] + tk;
+  if (!inside(C.L, I, J, Kc)) return;
+  C.r[C.L.at(I, J, Kc)] = restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) {
+    return sres[((i - lo[0]) * len[1] + (j - lo[1])) * len[2] + (k - lo[2])];
+  });
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_mg_up(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, const int* __restrict__ flags,
-                                               int m) {
-  if (flags[m]) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= ncells(F.L)) return;
-  int i, j, k;
-  decode(idx, F.L, i, j, k);
-  F.x[F.L.at(i, j, k)] = up_body<true>(K, F, C, i, j, k);
+// Prolongation + post-smoothing of one tile of level F: t = om D^-1 r + P x_c
+// over the tile and a one-cell halo (LDS), then x = t + om D^-1 (r - A t).
+// FINE: level 0, also writes the partials of r.z for the CG.
+template <bool FINE, bool COARSE, class T>
+__global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m) {
+  using Tl = MgTiles<T>;
+  __shared__ T st[Tl::T_N];
+  if (c.flags[m]) return;
+  const Layout& L = F.L;
+  const int i0 = blockIdx.z * Tl::UT_I, j0 = blockIdx.y * Tl::UT_J, k0 = blockIdx.x * Tl::UT_K;
+  constexpr int HI = Tl::UT_I + 2, HJ = Tl::UT_J + 2, HK = Tl::UT_K + 2;
+  for (int idx = threadIdx.x; idx < HI * HJ * HK; idx += blockDim.x) {
+    const int kk = idx % HK, jj = (idx / HK) % HJ, ii = idx / (HK * HJ);
+    st[idx] = pre_plus_coarse<COARSE>(K, F, C, i0 - 1 + ii, j0 - 1 + jj, k0 - 1 + kk);
+  }
+  __syncthreads();
+  double v[1] = {0.0};
+  for (int idx = threadIdx.x; idx < Tl::UT_I * Tl::UT_J * Tl::UT_K; idx += blockDim.x) {
+    const int kk = idx % Tl::UT_K, jj = (idx / Tl::UT_K) % Tl::UT_J, ii = idx / (Tl::UT_K * Tl::UT_J);
+    const int i = i0 + ii, j = j0 + jj, k = k0 + kk;
+    if (!inside(L, i, j, k)) continue;
+    const int q = ((ii + 1) * HJ + (jj + 1)) * HK + (kk + 1);
+    const T tc = st[q];
+    const T D = diag_w(K.bc, L, F.w, i, j, k);
+    const T At = D * tc - F.w[0] * (st[q + HJ * HK] + st[q - HJ * HK]) - F.w[1] * (st[q + HK] + st[q - HK]) -
+                 F.w[2] * (st[q + 1] + st[q - 1]);
+    const long long o = L.at(i, j, k);
+    const T rr = F.r[o];
+    const T z = tc + omd(K, F, i, j, k) * (rr - At);
+    F.x[o] = z;
+    if (FINE) v[0] += (double)rr * (double)z;
+  }
+  if (FINE) {
+    const int slots[1] = {S_RZ0 + (m & 1)};
+    write_partials<1>(v, c.part, c.stride, slots);
+  }
 }
 
-// All levels from lt down to the coarsest and back, in one workgroup.  The
-// level descriptors are read from a device table.
+// All levels from lt down to the coarsest and back, in one workgroup, as
+// phases separated by barriers over arrays that stay in the L2.  The level
+// descriptors are read from a device table.
 template <class T>
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const MgLvl<T>* __restrict__ lv, int lt,
                                                           int nl, const T* __restrict__ cinv,
@@ -174,11 +401,19 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const M
   for (int l = lt; l < nl - 1; ++l) {
     const MgLvl<T> F = lv[l];
     const MgLvl<T> C = lv[l + 1];
-    const int n = (int)ncells(C.L);
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int nf = (int)ncells(F.L), nc = (int)ncells(C.L);
+    for (int idx = threadIdx.x; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      F.t[F.L.at(i, j, k)] = smoothed_residual(K, F, F.r, i, j, k);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nc; idx += blockDim.x) {
       int I, J, Kc;
       decode(idx, C.L, I, J, Kc);
-      C.r[C.L.at(I, J, Kc)] = down_body(K, F, I, J, Kc);
+      const T* __restrict__ res = F.t;
+      C.r[C.L.at(I, J, Kc)] =
+          restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) { return res[F.L.at(i, j, k)]; });
     }
     __syncthreads();
   }
@@ -237,59 +472,33 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const M
   for (int l = nl - 2; l >= lt; --l) {
     const MgLvl<T> F = lv[l];
     const MgLvl<T> C = lv[l + 1];
-    const int n = (int)ncells(F.L);
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int nf = (int)ncells(F.L);
+    for (int idx = threadIdx.x; idx < nf; idx += blockDim.x) {
       int i, j, k;
       decode(idx, F.L, i, j, k);
-      F.x[F.L.at(i, j, k)] = up_body<true>(K, F, C, i, j, k);
+      F.t[F.L.at(i, j, k)] = pre_plus_coarse<true>(K, F, C, i, j, k);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      const long long o = F.L.at(i, j, k);
+      // t has zero ghosts: apply_w gives A t directly
+      F.x[o] = F.t[o] + omd(K, F, i, j, k) * (F.r[o] - apply_w(K.bc, F.L, F.w, F.t, i, j, k, o));
     }
     __syncthreads();
   }
-}
-
-// Fine level: z = (prolongation + post-smoothing) and partials of r.z.
-// Marches along x keeping the x-neighbours' values in registers.
-template <bool COARSE, class T>
-__global__ __launch_bounds__(kMgFineBlock) void k_mg_up0(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m,
-                                                         int ilen) {
-  if (c.flags[m]) return;
-  const Layout& L = F.L;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = p < L.ny * L.nz;
-  const int j = active ? p / L.nz : 0;
-  const int k = active ? p - j * L.nz : 0;
-  const int i0 = blockIdx.y * ilen;
-  const int i1 = active ? min(L.nx, i0 + ilen) : i0;
-  double v[1] = {0.0};
-  if (i0 < i1) {
-    T tm = pre_plus_coarse<COARSE>(K, F, C, i0 - 1, j, k);
-    T tc = pre_plus_coarse<COARSE>(K, F, C, i0, j, k);
-    for (int i = i0; i < i1; ++i) {
-      const T tp = pre_plus_coarse<COARSE>(K, F, C, i + 1, j, k);
-      const T D = diag_w(K.bc, L, F.w, i, j, k);
-      const T At = D * tc - F.w[0] * (tp + tm) -
-                   F.w[1] * (pre_plus_coarse<COARSE>(K, F, C, i, j + 1, k) + pre_plus_coarse<COARSE>(K, F, C, i, j - 1, k)) -
-                   F.w[2] * (pre_plus_coarse<COARSE>(K, F, C, i, j, k + 1) + pre_plus_coarse<COARSE>(K, F, C, i, j, k - 1));
-      const long long o = L.at(i, j, k);
-      const T rr = F.r[o];
-      const T z = tc + omd(K, F, i, j, k) * (rr - At);
-      F.x[o] = z;
-      v[0] += (double)rr * (double)z;
-      tm = tc;
-      tc = tp;
-    }
-  }
-  const int slots[1] = {S_RZ0 + (m & 1)};
-  write_partials<1>(v, c.part, c.nb, slots);
 }
 
 // ------------------------------------------------------------------- host
 template <class T>
 static MgCommon<T> mg_common(const Grid& g) {
   MgCommon<T> K{};
-  for (int q = 0; q < 6; ++q) K.bc[q] = g.bc[q];
+  for (int q = 0; q < 6; ++q) {
+    K.bc[q] = g.bc[q];
+    K.sgn[q] = g.bc[q] == OUTLET ? T(-1) : T(1);
+  }
   K.om = T(g.mg_omega);
-  K.alpha = T(g.mg_alpha);
   return K;
 }
 
@@ -302,7 +511,6 @@ static MgLvl<T> mg_level(const Grid& g, int l) {
     D.w[a] = T(S.w[a]);
     D.c[a] = S.coarsen[a];
   }
-  D.m = 1 << (S.coarsen[0] + S.coarsen[1] + S.coarsen[2]);
   D.omd_in = T(g.mg_omega / (2.0 * (S.w[0] + S.w[1] + S.w[2])));
   D.r = (T*)S.r;
   D.x = (T*)S.x;
@@ -416,7 +624,7 @@ void mg_setup(Grid& g) {
     C.L = level_layout(n[0] >> c[0], n[1] >> c[1], n[2] >> c[2]);
     for (int a = 0; a < 3; ++a) {
       F.coarsen[a] = c[a];
-      C.w[a] = F.w[a] / (c[a] ? 2.0 : 1.0);   // Galerkin weight of R A P
+      C.w[a] = F.w[a] / (c[a] ? 4.0 : 1.0);   // re-discretised with the doubled spacing
     }
     const size_t bytes = (size_t)(C.L.nx + 3) * C.L.SX * es;
     for (void** q : {&C.r, &C.x, &C.t}) {
@@ -440,7 +648,6 @@ void mg_setup(Grid& g) {
   g.mg_cinv = nullptr;
   g.mg_nc = (int)ncells(last.L);
   g.mg_omega = kJacobiOmega;
-  g.mg_alpha = kCoarseAlpha;
   {
     std::vector<MgLvl<T>> tab(nl);
     for (int l = 0; l < nl; ++l) tab[l] = mg_level<T>(g, l);
@@ -457,6 +664,24 @@ void mg_setup(Grid& g) {
   }
 }
 
+size_t mg_fine_blocks(const Layout& L) {
+  using Tl = MgTiles<float>;   // the up/smoothing tile does not depend on the dtype
+  return (size_t)((L.nz + Tl::UT_K - 1) / Tl::UT_K) * ((L.ny + Tl::UT_J - 1) / Tl::UT_J) *
+         ((L.nx + Tl::UT_I - 1) / Tl::UT_I);
+}
+
+template <class T>
+static dim3 restrict_grid(const Layout& C) {
+  using Tl = MgTiles<T>;
+  return dim3((C.nz + Tl::RT_K - 1) / Tl::RT_K, (C.ny + Tl::RT_J - 1) / Tl::RT_J, (C.nx + Tl::RT_I - 1) / Tl::RT_I);
+}
+
+template <class T>
+static dim3 up_grid(const Layout& F) {
+  using Tl = MgTiles<T>;
+  return dim3((F.nz + Tl::UT_K - 1) / Tl::UT_K, (F.ny + Tl::UT_J - 1) / Tl::UT_J, (F.nx + Tl::UT_I - 1) / Tl::UT_I);
+}
+
 template <class T>
 void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int decide) {
   (void)P;
@@ -466,34 +691,61 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   MgLvl<T> L0 = mg_level<T>(g, 0);
   L0.r = (T*)r;
   L0.x = (T*)z;
+  L0.t = (T*)z;   // the fine residual from the CG update lives in z until z is written
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
-  const int nb1 = nl > 1 ? (int)((ncells(L1.L) + 255) / 256) : 1;
-  hipLaunchKernelGGL(k_mg_down0<T>, dim3(nb1), dim3(256), 0, g.stream, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide);
+  // level 0 -> 1: the stored residual exists only after a CG update
+  const bool stored = decide && m > 0;
+  const int mode0 = decide ? 1 : 2;
+  {
+    TimedLaunch tl(g, UF_TK_MG_DOWN0);
+    const dim3 grid = nl > 1 ? restrict_grid<T>(L1.L) : dim3(1);
+    if (stored)
+      hipLaunchKernelGGL((k_mg_restrict<true, T>), grid, dim3(256), 0, g.stream, K, L0, L1, nl > 1 ? 1 : 0, c, m, mode0);
+    else
+      hipLaunchKernelGGL((k_mg_restrict<false, T>), grid, dim3(256), 0, g.stream, K, L0, L1, nl > 1 ? 1 : 0, c, m, mode0);
+  }
   const int lt = std::min(g.mg_lt, nl - 1);
   for (int l = 1; l < lt; ++l) {
     const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);
-    const int nb = (int)((ncells(C.L) + 255) / 256);
-    hipLaunchKernelGGL(k_mg_down<T>, dim3(nb), dim3(256), 0, g.stream, K, F, C, (const int*)c.flags, m);
+    TimedLaunch tl(g, UF_TK_MG_COARSE);
+    hipLaunchKernelGGL((k_mg_restrict<false, T>), restrict_grid<T>(C.L), dim3(256), 0, g.stream, K, F, C, 1, c, m, 0);
   }
   if (nl > 1) {
-    hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K, (const MgLvl<T>*)g.mg_table, lt, nl,
-                       (const T*)g.mg_cinv, (const int*)c.flags, m);
+    {
+      TimedLaunch tl(g, UF_TK_MG_COARSE);
+      hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K, (const MgLvl<T>*)g.mg_table, lt,
+                         nl, (const T*)g.mg_cinv, (const int*)c.flags, m);
+    }
     for (int l = lt - 1; l >= 1; --l) {
       const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);
-      const int nb = (int)((ncells(F.L) + 255) / 256);
-      hipLaunchKernelGGL(k_mg_up<T>, dim3(nb), dim3(256), 0, g.stream, K, F, C, (const int*)c.flags, m);
+      TimedLaunch tl(g, UF_TK_MG_COARSE);
+      hipLaunchKernelGGL((k_mg_upsmooth<false, true, T>), up_grid<T>(F.L), dim3(256), 0, g.stream, K, F, C, c, m);
     }
   }
-  const CgLaunch cl = cg_launch(g.L);
+  TimedLaunch tl(g, UF_TK_MG_UP0);
   if (nl > 1)
-    hipLaunchKernelGGL((k_mg_up0<true, T>), cl.grid, dim3(kMgFineBlock), 0, g.stream, K, L0, L1, c, m, cl.ilen);
+    hipLaunchKernelGGL((k_mg_upsmooth<true, true, T>), up_grid<T>(L0.L), dim3(256), 0, g.stream, K, L0, L1, c, m);
   else
-    hipLaunchKernelGGL((k_mg_up0<false, T>), cl.grid, dim3(kMgFineBlock), 0, g.stream, K, L0, L1, c, m, cl.ilen);
+    hipLaunchKernelGGL((k_mg_upsmooth<true, false, T>), up_grid<T>(L0.L), dim3(256), 0, g.stream, K, L0, L1, c, m);
 }
 
 template <class T>
 void mg_precond(Grid& g, const Params<T>& P, int m) {
-  mg_launch<T>(g, P, m, g.R, g.Z, 1);
+  mg_launch<T>(g, P, m, resid(g, m), g.Z, 1);
+}
+
+// CG update fused with the fine residual of the next preconditioner
+// application (written into Z, which the application overwrites last).
+template <class T>
+void mg_axpy(Grid& g, const Params<T>& P, int t) {
+  (void)P;
+  const MgCommon<T> K = mg_common<T>(g);
+  MgLvl<T> L0 = mg_level<T>(g, 0);
+  const CgLaunch cl = cg_launch(g.L);
+  TimedLaunch tl(g, UF_TK_CG_AXPY);
+  hipLaunchKernelGGL(k_mg_axpy<T>, cl.grid, dim3(kMgFineBlock), 0, g.stream, K, L0, (T*)g.X,
+                     (const T*)resid(g, t), (T*)resid(g, t + 1), (const T*)g.D[(t + 1) & 1], (const T*)g.Qv,
+                     (T*)g.Z, make_ctl(g), t, cl.ilen);
 }
 
 // Stand-alone application z = M^-1 r: uses the spare flag slot past the
@@ -510,5 +762,7 @@ template void mg_precond<float>(Grid&, const Params<float>&, int);
 template void mg_precond<double>(Grid&, const Params<double>&, int);
 template void mg_apply<float>(Grid&, const Params<float>&, const void*, void*);
 template void mg_apply<double>(Grid&, const Params<double>&, const void*, void*);
+template void mg_axpy<float>(Grid&, const Params<float>&, int);
+template void mg_axpy<double>(Grid&, const Params<double>&, int);
 
 }  // namespace uf

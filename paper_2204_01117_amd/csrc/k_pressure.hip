@@ -104,13 +104,13 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_init(Params<T> P, const T* __re
     }
   }
   const int slots[2] = {S_BB, S_RR};
-  write_partials<2>(v, c.part, c.nb, slots);
+  write_partials<2>(v, c.part, c.stride, slots);
 }
 
 // One block: ||b||, the stopping threshold and whether x0 already solves.
 __global__ __launch_bounds__(256) void k_cg_start(CgCtl c, double tol) {
-  const double bb = slot_sum(c.part + (size_t)S_BB * c.nb, c.nb);
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.nb, c.nb);
+  const double bb = slot_sum(c.part + (size_t)S_BB * c.stride, c.nb);
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb);
   if (threadIdx.x != 0) return;
   CgState* st = c.st;
   st->bb = bb;
@@ -144,16 +144,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_precond(Params<T> P, const T* _
     v[0] += (double)R[o] * (double)z;
   }
   const int slots[1] = {S_RZ0 + (m & 1)};
-  write_partials<1>(v, c.part, c.nb, slots);
-}
-
-// Does iteration t run?  Same answer in Ad(t) and axpy(t).
-__device__ __forceinline__ bool iteration_runs(const CgCtl& c, int t, double* rz) {
-  if (c.flags[t] || t >= c.maxit) return false;
-  *rz = slot_sum(c.part + (size_t)(S_RZ0 + (t & 1)) * c.nb, c.nb);
-  if (!isfinite(*rz)) return false;
-  if (c.criterion == 1 && *rz < c.st->tol2_bb) return false;
-  return true;
+  write_partials<1>(v, c.part, c.stride, slots);
 }
 
 // d = z + beta d_old; q = A d; partials of d.q.  Marches along x with the
@@ -171,17 +162,44 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __rest
   }
   double rz;
   if (!iteration_runs(c, t, &rz)) return;
-  const T beta = t == 0 ? T(0) : (T)(rz / slot_sum(c.part + (size_t)(S_RZ0 + ((t + 1) & 1)) * c.nb, c.nb));
+  const T beta = t == 0 ? T(0) : (T)(rz / slot_sum(c.part + (size_t)(S_RZ0 + ((t + 1) & 1)) * c.stride, c.nb_rz));
   double v[1] = {0.0};
   if (i0 < i1) {
     const bool first = t == 0;
     auto dn = [&](long long q) { return first ? Z[q] : Z[q] + beta * Dold[q]; };
     const T dyz = diag_yz(P, j, k);
+    const long long SX = L.SX, PZ = L.PZ;
     long long o = L.at(i0, j, k);
-    T dm = dn(o - L.SX), dc = dn(o);
-    for (int i = i0; i < i1; ++i, o += L.SX) {
-      const T dp = dn(o + L.SX);
-      const T q = (dyz + diag_x(P, i)) * dc - (dp + dm) * P.ih2[0] - (dn(o + L.PZ) + dn(o - L.PZ)) * P.ih2[1] -
+    T dm = dn(o - SX), dc = dn(o);
+    int i = i0;
+    // four cells per pass so that each wave keeps four cells' loads in flight
+    for (; i + 4 <= i1; i += 4, o += 4 * SX) {
+      T d[5];
+      d[0] = dc;
+#pragma unroll
+      for (int u = 1; u <= 4; ++u) d[u] = dn(o + u * SX);
+      T lat_y[4], lat_z[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long q = o + u * SX;
+        lat_y[u] = dn(q + PZ) + dn(q - PZ);
+        lat_z[u] = dn(q + 1) + dn(q - 1);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T prev = u == 0 ? dm : d[u - 1];
+        const T qv = (dyz + diag_x(P, i + u)) * d[u] - (d[u + 1] + prev) * P.ih2[0] - lat_y[u] * P.ih2[1] -
+                     lat_z[u] * P.ih2[2];
+        Dnew[o + u * SX] = d[u];
+        Qv[o + u * SX] = qv;
+        v[0] += (double)d[u] * (double)qv;
+      }
+      dm = d[3];
+      dc = d[4];
+    }
+    for (; i < i1; ++i, o += SX) {
+      const T dp = dn(o + SX);
+      const T q = (dyz + diag_x(P, i)) * dc - (dp + dm) * P.ih2[0] - (dn(o + PZ) + dn(o - PZ)) * P.ih2[1] -
                   (dn(o + 1) + dn(o - 1)) * P.ih2[2];
       Dnew[o] = dc;
       Qv[o] = q;
@@ -191,19 +209,19 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __rest
     }
   }
   const int slots[1] = {S_DQ};
-  write_partials<1>(v, c.part, c.nb, slots);
+  write_partials<1>(v, c.part, c.stride, slots);
 }
 
 // x += alpha d; r -= alpha q; partials of ||r||^2.
 template <class T>
-__global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict__ X, T* __restrict__ R,
-                                                      const T* __restrict__ D, const T* __restrict__ Qv, CgCtl c,
-                                                      int t, int ilen) {
+__global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict__ X, const T* __restrict__ Rin,
+                                                      T* __restrict__ R, const T* __restrict__ D,
+                                                      const T* __restrict__ Qv, CgCtl c, int t, int ilen) {
   const Layout& L = P.L;
   double rz = 0.0, dq = 0.0;
   bool run = iteration_runs(c, t, &rz);
   if (run) {
-    dq = slot_sum(c.part + (size_t)S_DQ * c.nb, c.nb);
+    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb);
     run = dq > 0.0 && isfinite(dq);
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
@@ -218,21 +236,21 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
   for (int i = i0; i < i1; ++i) {
     const long long o = L.at(i, j, k);
     X[o] += alpha * D[o];
-    const T r = R[o] - alpha * Qv[o];
+    const T r = Rin[o] - alpha * Qv[o];
     R[o] = r;
     v[0] += (double)r * (double)r;
   }
   const int slots[1] = {S_RR};
-  write_partials<1>(v, c.part, c.nb, slots);
+  write_partials<1>(v, c.part, c.stride, slots);
 }
 
 // One block, after a chunk of iterations ending at t_end: publish the
 // status for the host.
 __global__ __launch_bounds__(256) void k_cg_status(CgCtl c, int t_end) {
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.nb, c.nb);
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb);
   CgState* st = c.st;
   const int it = st->iter;
-  const double rz = slot_sum(c.part + (size_t)(S_RZ0 + (it & 1)) * c.nb, c.nb);
+  const double rz = slot_sum(c.part + (size_t)(S_RZ0 + (it & 1)) * c.stride, c.nb_rz);
   if (threadIdx.x != 0) return;
   st->rr = rr;
   st->nonfinite = st->nonfinite || !isfinite(rr);
@@ -269,7 +287,9 @@ CgLaunch cg_launch(const Layout& L) {
 CgCtl make_ctl(Grid& g) {
   CgCtl c;
   c.part = g.partials;
+  c.stride = (int)g.part_stride;
   c.nb = (int)g.cg_nb;
+  c.nb_rz = (int)g.cg_nb_rz;
   c.flags = g.flags;
   c.exec = g.exec;
   c.st = g.st;
@@ -282,8 +302,11 @@ template <class T>
 void launch_cg_start(Grid& g, const Params<T>& P, void* const Qs[3], const void* b) {
   const CgLaunch cl = cg_launch(P.L);
   const CgCtl c = make_ctl(g);
-  hipLaunchKernelGGL(k_cg_init<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)Qs[0], (const T*)Qs[1],
-                     (const T*)Qs[2], (const T*)b, (const T*)g.X, (T*)g.R, c, cl.ilen);
+  {
+    TimedLaunch tl(g, UF_TK_CG_INIT);
+    hipLaunchKernelGGL(k_cg_init<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)Qs[0], (const T*)Qs[1],
+                     (const T*)Qs[2], (const T*)b, (const T*)g.X, (T*)resid(g, 0), c, cl.ilen);
+  }
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, g.stream, c, g.cfg.cg_tol);
 }
 
@@ -294,8 +317,9 @@ void launch_cg_precond(Grid& g, const Params<T>& P, int m) {
     return;
   }
   const CgLaunch cl = cg_launch(P.L);
-  hipLaunchKernelGGL(k_cg_precond<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)g.R, (T*)g.Z, make_ctl(g),
-                     m, g.cfg.precond, T(g.cfg.ai_omega), cl.ilen);
+  TimedLaunch tl(g, UF_TK_CG_PRECOND);
+  hipLaunchKernelGGL(k_cg_precond<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)resid(g, m), (T*)g.Z,
+                     make_ctl(g), m, g.cfg.precond, T(g.cfg.ai_omega), cl.ilen);
 }
 
 template <class T>
@@ -304,10 +328,18 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
   const CgCtl c = make_ctl(g);
   void* Dold = g.D[t & 1];
   void* Dnew = g.D[(t + 1) & 1];
-  hipLaunchKernelGGL(k_cg_Ad<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)g.Z, (const T*)Dold, (T*)Dnew,
-                     (T*)g.Qv, (T*)g.X, c, t, cl.ilen);
-  hipLaunchKernelGGL(k_cg_axpy<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (T*)g.X, (T*)g.R, (const T*)Dnew,
-                     (const T*)g.Qv, c, t, cl.ilen);
+  {
+    TimedLaunch tl(g, UF_TK_CG_AD);
+    hipLaunchKernelGGL(k_cg_Ad<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)g.Z, (const T*)Dold, (T*)Dnew,
+                       (T*)g.Qv, (T*)g.X, c, t, cl.ilen);
+  }
+  if (g.cfg.precond == UF_PC_MG) {
+    mg_axpy<T>(g, P, t);
+  } else {
+    TimedLaunch tl(g, UF_TK_CG_AXPY);
+    hipLaunchKernelGGL(k_cg_axpy<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (T*)g.X, (const T*)resid(g, t),
+                       (T*)resid(g, t + 1), (const T*)Dnew, (const T*)g.Qv, c, t, cl.ilen);
+  }
   launch_cg_precond<T>(g, P, t + 1);
 }
 

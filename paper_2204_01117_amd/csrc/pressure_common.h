@@ -47,21 +47,25 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int 
   return s;
 }
 
-// Write the block's partial sums of NV values into consecutive slots.
+// Write the block's partial sums of NV values into their slots (slot s
+// starts at part + s * stride; block index over a 1-, 2- or 3-D grid).
 template <int NV>
-__device__ __forceinline__ void write_partials(double (&v)[NV], double* __restrict__ part, int nb, const int slot[NV]) {
+__device__ __forceinline__ void write_partials(double (&v)[NV], double* __restrict__ part, int stride,
+                                               const int slot[NV]) {
   block_sum<NV>(v);
   if (threadIdx.x == 0) {
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
-    for (int m = 0; m < NV; ++m) part[(size_t)slot[m] * nb + bid] = v[m];
+    for (int m = 0; m < NV; ++m) part[(size_t)slot[m] * stride + bid] = v[m];
   }
 }
 
 // State of the solve shared by the kernels (passed by value).
 struct CgCtl {
-  double* part;    // S_NSLOT * nb partial sums
-  int nb;          // blocks of the fine-grid reducing kernels
+  double* part;    // S_NSLOT slots of partial sums, slot s at part + s * stride
+  int stride;
+  int nb;          // blocks of the CG kernels (slots BB, RR, DQ)
+  int nb_rz;       // blocks of the kernel writing r.z (slots RZ0, RZ1)
   int* flags;      // flags[m]: the solve finished before iteration m
   int* exec;       // exec[t]: iteration t performed its update
   CgState* st;
@@ -78,9 +82,18 @@ CgCtl make_ctl(Grid& g);
 __device__ __forceinline__ bool precond_skip(const CgCtl& c, int m) {
   if (m == 0) return c.flags[0] != 0;
   if (!c.exec[m - 1]) return true;
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.nb, c.nb);
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb);
   if (!isfinite(rr)) return true;
   return c.criterion == 0 && rr <= c.st->tol2_bb;
+}
+
+// Does iteration t run?  Same answer in Ad(t) and axpy(t).
+__device__ __forceinline__ bool iteration_runs(const CgCtl& c, int t, double* rz) {
+  if (c.flags[t] || t >= c.maxit) return false;
+  *rz = slot_sum(c.part + (size_t)(S_RZ0 + (t & 1)) * c.stride, c.nb_rz);
+  if (!isfinite(*rz)) return false;
+  if (c.criterion == 1 && *rz < c.st->tol2_bb) return false;
+  return true;
 }
 
 }  // namespace uf

@@ -1,5 +1,6 @@
 // C ABI of the RANS step library: grid creation and validation, state I/O,
 // the time-step driver and the pressure-CG host loop.  See include/uf.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -13,11 +14,38 @@ namespace uf {
 static thread_local std::string g_last_error;
 void set_error(const std::string& m) { g_last_error = m; }
 
+size_t mg_fine_blocks(const Layout& L);
 template <class T> void launch_face_init(Grid& g, const Params<T>& P, void* const Q[3]);
 template <class T> void launch_cell_fill(Grid& g, const Params<T>& P, void* q, double value, int use_inlet,
                                          double inlet_value);
 
 static const double kCmu = 0.09, kClim = 7.0 / 8.0;
+
+TimedLaunch::TimedLaunch(Grid& g_, int id_) : g(g_), id(id_), on(((g_.timer_mask >> id_) & 1u) != 0) {
+  if (!on) return;
+  if (2 * g.timer_used + 2 > g.timer_pool.size()) timer_flush(g);
+  UF_HIP_CHECK(hipEventRecord(g.timer_pool[2 * g.timer_used], g.stream));
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (!on) return;
+  (void)hipEventRecord(g.timer_pool[2 * g.timer_used + 1], g.stream);
+  g.timer_id[g.timer_used] = id;
+  g.timer_used++;
+}
+
+// Wait for the recorded events and add their intervals to the totals.
+void timer_flush(Grid& g) {
+  if (!g.timer_used) return;
+  UF_HIP_CHECK(hipEventSynchronize(g.timer_pool[2 * g.timer_used - 1]));
+  for (size_t q = 0; q < g.timer_used; ++q) {
+    float ms = 0;
+    UF_HIP_CHECK(hipEventElapsedTime(&ms, g.timer_pool[2 * q], g.timer_pool[2 * q + 1]));
+    g.timer_ms[g.timer_id[q]] += ms;
+    g.timer_n[g.timer_id[q]] += 1;
+  }
+  g.timer_used = 0;
+}
 static const size_t S_NSLOT_HOST = 5;   // partial-sum slots of the pressure solve
 
 template <class T>
@@ -167,6 +195,7 @@ void free_grid(Grid* g) {
   f(g->inflow);
   f(g->X);
   f(g->R);
+  f(g->R2);
   f(g->Z);
   f(g->D[0]);
   f(g->D[1]);
@@ -194,6 +223,8 @@ void free_grid(Grid* g) {
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
   g->ev_status = g->ev0 = g->ev1 = nullptr;
+  for (hipEvent_t e : g->timer_pool) (void)hipEventDestroy(e);
+  g->timer_pool.clear();
   mg_free(*g);
 }
 
@@ -390,7 +421,7 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     for (auto& q : s) bufs.push_back(&q);
   for (auto& q : g->K) bufs.push_back(&q);
   for (auto& q : g->Wo) bufs.push_back(&q);
-  for (void** q : {&g->NUT, &g->C, &g->X, &g->R, &g->Z, &g->D[0], &g->D[1], &g->Qv}) bufs.push_back(q);
+  for (void** q : {&g->NUT, &g->C, &g->X, &g->R, &g->R2, &g->Z, &g->D[0], &g->D[1], &g->Qv}) bufs.push_back(q);
   try {
     for (void** q : bufs) {
       *q = dalloc(bytes);
@@ -400,10 +431,12 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     g->inflow = dalloc(2 * (cfg->nz + 2) * g->esize);
     const CgLaunch cl = cg_launch(L);
     g->cg_nb = (size_t)cl.grid.x * cl.grid.y;
-    g->partials = (double*)dalloc(S_NSLOT_HOST * g->cg_nb * sizeof(double));
+    g->cg_nb_rz = cfg->precond == UF_PC_MG ? mg_fine_blocks(L) : g->cg_nb;
+    g->part_stride = std::max(g->cg_nb, g->cg_nb_rz);
+    g->partials = (double*)dalloc(S_NSLOT_HOST * g->part_stride * sizeof(double));
     g->flags = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
     g->exec = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
-    UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->cg_nb * sizeof(double), g->stream));
+    UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->part_stride * sizeof(double), g->stream));
     UF_HIP_CHECK(hipMemsetAsync(g->flags, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
     UF_HIP_CHECK(hipMemsetAsync(g->exec, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
     g->st = (CgState*)dalloc(sizeof(CgState));
@@ -448,6 +481,39 @@ uf_status uf_destroy_grid(uf_grid g) {
   free_grid(g);
   delete g;
   return UF_OK;
+}
+
+uf_status uf_kernel_timer_enable(uf_grid g, uint32_t mask) {
+  if (!g) return fail(UF_EINVAL, "NULL grid");
+  if (mask >> UF_TK_COUNT) return fail(UF_EINVAL, "unknown kernel bit in the timer mask");
+  UF_GUARD_BEGIN
+  timer_flush(*g);
+  if (mask && g->timer_pool.empty()) {
+    const size_t pairs = 4096;
+    g->timer_pool.resize(2 * pairs);
+    g->timer_id.assign(pairs, 0);
+    // no system-scope release on each event: only device timestamps are needed
+    for (auto& e : g->timer_pool) UF_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  }
+  g->timer_mask = mask;
+  g->timer_used = 0;
+  for (int q = 0; q < UF_TK_COUNT; ++q) {
+    g->timer_ms[q] = 0.0;
+    g->timer_n[q] = 0;
+  }
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_kernel_timer_read(uf_grid g, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!g || !total_ms || !launches) return fail(UF_EINVAL, "NULL argument");
+  if (kernel < 0 || kernel >= UF_TK_COUNT) return fail(UF_EINVAL, "unknown kernel id");
+  UF_GUARD_BEGIN
+  timer_flush(*g);
+  *total_ms = g->timer_ms[kernel];
+  *launches = g->timer_n[kernel];
+  return UF_OK;
+  UF_GUARD_END
 }
 
 uf_status uf_set_stream(uf_grid g, void* stream) {

@@ -64,13 +64,16 @@ struct Grid {
   void* inflow = nullptr;    // [2][nz+2]
   // pressure solve
   void* X = nullptr;         // pressure (the CG iterate)
-  void* R = nullptr;
+  void* R = nullptr;         // residual after an even number of updates
+  void* R2 = nullptr;        // ... after an odd number (the update reads one, writes the other)
   void* Z = nullptr;
   void* D[2] = {};
   void* Qv = nullptr;
   int dpar = 0;
-  double* partials = nullptr;   // S_NSLOT * cg_nb partial sums
+  double* partials = nullptr;   // 5 slots of part_stride partial sums
+  size_t part_stride = 0;
   size_t cg_nb = 0;             // blocks of the fine-grid CG kernels
+  size_t cg_nb_rz = 0;          // blocks of the kernel that writes the r.z partials
   int* flags = nullptr;         // [cg_maxit + 2]
   int* exec = nullptr;          // [cg_maxit + 2]
   CgState* st = nullptr;     // device
@@ -83,12 +86,21 @@ struct Grid {
   int mg_nc = 0;                // cells of the coarsest level
   void* mg_cinv = nullptr;      // dense inverse of the coarsest operator
   void* mg_table = nullptr;     // device copy of the level descriptors
-  double mg_omega = 0.9;        // Jacobi weight of the smoother
-  double mg_alpha = 1.5;        // scaling of the coarse-grid correction
+  double mg_omega = 0.8;        // Jacobi weight of the smoother
   int last_iters = 0;
+  // kernel timer (see uf_kernel_timer_enable)
+  uint32_t timer_mask = 0;
+  std::vector<hipEvent_t> timer_pool;
+  std::vector<int> timer_id;       // kernel of each recorded pair
+  size_t timer_used = 0;           // pairs recorded since the last flush
+  double timer_ms[UF_TK_COUNT] = {};
+  long long timer_n[UF_TK_COUNT] = {};
   int k_in_valid = 1;
   double k_in = 0, w_in = 0, nu_max = 0;
 };
+
+// Residual buffer after m CG updates.
+inline void* resid(const Grid& g, int m) { return (m & 1) ? g.R2 : g.R; }
 
 // Launchers (T = float or double), defined in the kernel sources.
 template <class T> Params<T> make_params(const Grid& g);
@@ -112,7 +124,18 @@ template <class T> void launch_apply(Grid& g, const Params<T>& P, int op, const 
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);
+template <class T> void mg_axpy(Grid& g, const Params<T>& P, int t);
 void mg_free(Grid& g);
+
+// Brackets one kernel launch with timer events when that kernel is timed.
+struct TimedLaunch {
+  Grid& g;
+  int id;
+  bool on;
+  TimedLaunch(Grid& g_, int id_);
+  ~TimedLaunch();
+};
+void timer_flush(Grid& g);
 
 size_t padded_bytes(const Grid& g);
 void set_error(const std::string& msg);

@@ -87,6 +87,20 @@ class Grid:
         L.check(L.uf_apply_operator(self.handle, int(op), c_void_p(x.data_ptr()), c_void_p(y.data_ptr())))
         return y
 
+    def timer_enable(self, kernels=()):
+        """Time every launch of the named kernels (see TIMED_KERNELS)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << L.TIMED_KERNELS.index(k)
+        L.check(L.uf_kernel_timer_enable(self.handle, mask))
+
+    def timer_read(self, kernel):
+        """(total milliseconds, launches) of one timed kernel."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        L.check(L.uf_kernel_timer_read(self.handle, L.TIMED_KERNELS.index(kernel), byref(ms), byref(n)))
+        return ms.value, n.value
+
     def close(self):
         if getattr(self, "handle", None):
             L.uf_destroy_grid(self.handle)
