@@ -12,8 +12,23 @@ around each of its launches, and the FP64 oracle timed on this host on a
 bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Profiling helpers (the commands are recorded in the files they write):
+    python bench.py --traffic-probe
+        a few steps of the workload, then a plain copy of COPY_BYTES: the
+        program run under rocprofv3 --pmc FETCH_SIZE and, separately,
+        --pmc WRITE_SIZE (csv output under <dir>/fetch and <dir>/write)
+    python bench.py --traffic-summary <dir>
+        HBM bytes per launch of each kernel from those two runs, scaled by
+        what the counters read for the copy, into
+        profiles/traffic_<kernel>_256x256x64.json
+    python bench.py --stats-summary <dir> --command "<rocprofv3 command>"
+        profiles/kernels_256x256x64.md from a rocprofv3 --kernel-trace
+        --stats csv run
 """
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
@@ -40,6 +55,26 @@ ALG_BYTES_PER_CELL = {
     "project": 28.0,      # read u*, v*, w*, p; write u, v, w
     "turbulence": 32.0,   # read u, v, w, k, omega; write k, omega, nu_t
 }
+
+# Kernels of the library by their profiler names (first match wins) and
+# the names the kernel timer and ALG_BYTES_PER_CELL use.
+PROFILE_NAMES = [
+    ("k_cg_Ad<", "cg_Ad"),
+    ("k_mg_axpy<", "cg_axpy"),
+    ("k_cg_axpy<", "cg_axpy"),
+    ("k_mg_upsmooth<true", "mg_up0"),
+    ("k_mg_restrict<true", "mg_down0"),
+    ("k_cg_init<", "cg_init"),
+    ("k_advect_fwd<", "advect_fwd"),
+    ("k_advect_corr<", "advect_corr"),
+    ("k_diffuse<", "diffuse"),
+    ("k_drag<", "drag"),
+    ("k_project<", "project"),
+    ("k_turbulence<", "turbulence"),
+]
+
+# Calibration copy of the counter runs: bytes read (and written) once.
+COPY_BYTES = 1 << 30
 
 # Oracle CPU baseline: PCG iterations its solver (AI1-preconditioned, FP64)
 # needs for one warm-started pressure solve of this workload at relative
@@ -79,6 +114,110 @@ def sources_hash():
         h.update(name.encode())
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
+
+
+def profile_name(kernel_name):
+    for pat, name in PROFILE_NAMES:
+        if pat in kernel_name:
+            return name
+    return None
+
+
+def _counter_rows(run_dir):
+    files = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no *counter_collection.csv under %s" % run_dir)
+    for f in files:
+        for row in csv.DictReader(open(f)):
+            yield row
+
+
+def _per_kernel(run_dir, counter):
+    """Average counter value per dispatch, by kernel name."""
+    acc = {}
+    for row in _counter_rows(run_dir):
+        if row.get("Counter_Name") != counter:
+            continue
+        key = (row["Kernel_Name"], row.get("Dispatch_Id"))
+        acc[key] = acc.get(key, 0.0) + float(row["Counter_Value"])
+    per = {}
+    for (name, _), v in acc.items():
+        per.setdefault(name, []).append(v)
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def traffic_probe():
+    """The program profiled for the traffic counters: the workload for a
+    few steps, then a plain device copy of COPY_BYTES (the calibration)."""
+    import torch
+    import paper_2204_01117_amd as U
+    _, phi, cfg = workload()
+    g = U.Grid(cfg, device="cuda:0")
+    g.set_porosity(torch.as_tensor(phi))
+    g.step(3)
+    g.step(3)
+    torch.cuda.synchronize()
+    g.close()
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("traffic probe done: 6 steps, 3 copies of %d bytes" % COPY_BYTES)
+
+
+def traffic_summary(run_dir, command):
+    fetch = _per_kernel(os.path.join(run_dir, "fetch"), "FETCH_SIZE")
+    write = _per_kernel(os.path.join(run_dir, "write"), "WRITE_SIZE")
+    copy = [k for k in fetch if "copy" in k.lower() and k in write]
+    if not copy:
+        raise SystemExit("no copy kernel in the counter runs")
+    ck = max(copy, key=lambda k: fetch[k])
+    f_fetch = fetch[ck] * 1024.0 / COPY_BYTES
+    f_write = write[ck] * 1024.0 / COPY_BYTES
+    out = {}
+    for name in fetch:
+        bn = profile_name(name)
+        if bn is None or bn in out or name not in write:
+            continue
+        fb = fetch[name] * 1024.0 / f_fetch
+        wb = write[name] * 1024.0 / f_write
+        out[bn] = {
+            "kernel": bn, "profiler_name": name.split("(")[0], "workload": "256x256x64",
+            "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+            "fetch_kib_raw": fetch[name], "write_kib_raw": write[name],
+            "calibration": {"copy_kernel": ck.split("(")[0], "copy_bytes": COPY_BYTES,
+                            "fetch_factor": f_fetch, "write_factor": f_write},
+            "alg_bytes_per_launch": ALG_BYTES_PER_CELL[bn] * 256 * 256 * 64,
+            "source_sha256": sources_hash(),
+            "command": command,
+        }
+    for bn, rec in out.items():
+        path = os.path.join(ROOT, "profiles", "traffic_%s_256x256x64.json" % bn)
+        with open(path, "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+        log("%-12s traffic %.3e B/launch (alg %.3e), fetch factor %.3f write factor %.3f"
+            % (bn, rec["bytes_per_launch"], rec["alg_bytes_per_launch"], f_fetch, f_write))
+
+
+def stats_summary(run_dir, command):
+    files = glob.glob(os.path.join(run_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no *kernel_stats.csv under %s" % run_dir)
+    rows = list(csv.DictReader(open(files[0])))
+    lines = ["# Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)", "",
+             "Command (from the repository root):", "", "    " + command, "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        name = r["Name"].split("(")[0].replace("void ", "").replace("uf::", "")
+        lines.append("| `%s` | %s | %.2f | %.3f | %.1f |" % (
+            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
+            float(r["Percentage"])))
+    path = os.path.join(ROOT, "profiles", "kernels_256x256x64.md")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    log("wrote", path)
 
 
 def cpu_baseline(phi, cfg, state):
@@ -145,12 +284,23 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true")
+    ap.add_argument("--traffic-summary", metavar="DIR")
+    ap.add_argument("--stats-summary", metavar="DIR")
+    ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
     args = ap.parse_args()
+    if args.traffic_summary:
+        return traffic_summary(args.traffic_summary, args.command)
+    if args.stats_summary:
+        return stats_summary(args.stats_summary, args.command)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(independent cases or x-slabs would shard across GPUs, see the design notes)" % args.gpus,
+        print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
+              "(multi-GPU runs would shard independent cases or x-slabs of the grid)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.traffic_probe:
+        return traffic_probe()
 
     import torch
     import paper_2204_01117_amd as U

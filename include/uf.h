@@ -45,7 +45,7 @@ typedef enum {
   UF_ENOCONV = 4,     /* pressure CG stopped at cg_maxit; the step completed    */
   UF_ENONFINITE = 5,  /* a NaN/Inf appeared in the pressure solve; step completed */
   UF_ESTATE = 6,      /* call not valid in the handle's current state          */
-  UF_ENOTIMPL = 7     /* entry point declared but not provided by this build    */
+  UF_ENOTIMPL = 7     /* entry point declared but not implemented in this version */
 } uf_status;
 
 /* Boundary kind of each domain side, sides ordered -x, +x, -y, +y, -z, +z
@@ -166,7 +166,7 @@ enum { UF_OP_POISSON = 0, UF_OP_PRECOND = 1 };
 uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_dev);
 
 /* Design objective and its adjoint (Sec. 4.2 objective L(u) and the
- * gradient-based design optimisation).  Not provided by this build: both
+ * gradient-based design optimisation).  Not implemented in this version: both
  * return UF_ENOTIMPL. */
 uf_status uf_objective(uf_grid g, const void* spec, double* J_host, void* dJ_dstate_dev);
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,

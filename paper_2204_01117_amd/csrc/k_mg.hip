@@ -1,7 +1,7 @@
 // Geometric multigrid V-cycle used as the CG preconditioner.
 //
 // Cell-centred hierarchy: an axis is halved while its cell count is even
-// and at least 4; levels stop at <= 256 cells (or when no axis halves).
+// and at least 4; levels stop at <= 64 cells (or when no axis halves).
 // Prolongation P is trilinear between cell centres (per halved axis: 3/4 of
 // the parent and 1/4 of the parent's neighbour on the child's side; past a
 // domain side the neighbour is the parent's mirror image, + for a Neumann
@@ -15,12 +15,11 @@
 // The coarsest level is solved with its exact dense inverse (<= 512 cells)
 // or, failing that, with a fixed number of Jacobi sweeps.
 //
-// Kernels of one application (the fine-level residual of the pre-smoothed
-// problem comes from the CG update kernel, see k_mg_axpy): restrict level
-// 0 -> 1 (block 0 also decides whether the solve has finished), restrict
-// down to the first small level, one single-workgroup kernel for all small
-// levels, prolongate + smooth back up, and the fine-level prolongation +
-// smoothing that writes z and the partials of r.z.
+// Kernels of one application: restrict level 0 -> 1 (block 0 also decides
+// whether the solve has finished), restrict down to the first small level,
+// one single-workgroup kernel for all small levels, prolongate + smooth back
+// up, and the fine-level prolongation + smoothing that writes z and the
+// partials of r.z.  The level kernels stage their tiles in LDS.
 #include <cmath>
 #include <cstdlib>
 #include <vector>
@@ -31,9 +30,9 @@ namespace uf {
 
 constexpr int kMgMaxLevels = 16;
 constexpr int kTailThreads = 1024;
-constexpr int kMgFineBlock = 512;        // must match the CG kernels' block (cg_launch)
 constexpr long long kTailCells = 1024;   // levels this small run in the single-workgroup kernel
 constexpr int kDenseMax = 512;           // largest coarsest level with an exact inverse
+constexpr long long kCoarsestCells = 64; // coarsening stops at levels this small
 constexpr int kCoarseSweeps = 10;        // Jacobi sweeps when there is no exact inverse
 // Jacobi weight, chosen by PCG iteration counts (0.8 and 0.9 within 10%).
 constexpr double kJacobiOmega = 0.8;
@@ -167,7 +166,7 @@ __device__ __forceinline__ T restrict_at(const MgCommon<T>& K, const MgLvl<T>& F
   const int nj = rtaps(J, F.c[1], C.L.ny, F.L.ny, K.sgn[2], K.sgn[3], fj, wj);
   const int nk = rtaps(Kc, F.c[2], C.L.nz, F.L.nz, K.sgn[4], K.sgn[5], fk, wk);
   T acc = T(0);
-#pragma unroll
+#pragma unroll 1
   for (int a = 0; a < 4; ++a) {
     if (a >= ni) break;
     T sa = T(0);
@@ -200,95 +199,153 @@ __device__ __forceinline__ T pre_plus_coarse(const MgCommon<T>& K, const MgLvl<T
 
 // ----------------------------------------------------------------- kernels
 
-// CG update with the multigrid's first step fused in: x += alpha d,
-// r -= alpha q, partials of ||r||^2, and the residual of the pre-smoothed
-// problem (1 - om) r + sum_a w_a om/D r_neighbours from the updated r
-// (neighbours' updated r recomputed from r and q).  Marches along x.
-template <class T>
-__global__ __launch_bounds__(kMgFineBlock) void k_mg_axpy(MgCommon<T> K, MgLvl<T> F, T* __restrict__ X,
-                                                          const T* __restrict__ Rin, T* __restrict__ R,
-                                                          const T* __restrict__ Dv, const T* __restrict__ Qv,
-                                                          T* __restrict__ RES, CgCtl c, int t, int ilen) {
-  const Layout& L = F.L;
-  double rz = 0.0, dq = 0.0;
-  bool run = iteration_runs(c, t, &rz);
-  if (run) {
-    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb);
-    run = dq > 0.0 && isfinite(dq);
-  }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    c.exec[t] = run;
-    if (run) c.st->iter = t + 1;
-  }
-  if (!run) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = p < L.ny * L.nz;
-  const int j = active ? p / L.nz : 0;
-  const int k = active ? p - j * L.nz : 0;
-  const int i0 = blockIdx.y * ilen;
-  const int i1 = active ? min(L.nx, i0 + ilen) : i0;
-  const T alpha = (T)(rz / dq);
-  double v[1] = {0.0};
-  if (i0 < i1) {
-    const long long SX = L.SX, PZ = L.PZ;
-    // updated residual at any cell, from the untouched input buffer
-    auto rn = [&](long long q) { return Rin[q] - alpha * Qv[q]; };
-    long long o = L.at(i0, j, k);
-    T rm = rn(o - SX), rc = rn(o);
-    for (int i = i0; i < i1; ++i, o += SX) {
-      const T rp = rn(o + SX);
-      X[o] += alpha * Dv[o];
-      R[o] = rc;
-      v[0] += (double)rc * (double)rc;
-      T s;
-      if (deep_inside(L, i, j, k)) {
-        s = F.omd_in * (F.w[0] * (rp + rm) + F.w[1] * (rn(o + PZ) + rn(o - PZ)) + F.w[2] * (rn(o + 1) + rn(o - 1)));
-      } else {
-        // zero ghosts of r and q make out-of-range neighbours vanish; omd is 0 there
-        s = F.w[0] * (omd(K, F, i + 1, j, k) * rp + omd(K, F, i - 1, j, k) * rm) +
-            F.w[1] * (omd(K, F, i, j + 1, k) * rn(o + PZ) + omd(K, F, i, j - 1, k) * rn(o - PZ)) +
-            F.w[2] * (omd(K, F, i, j, k + 1) * rn(o + 1) + omd(K, F, i, j, k - 1) * rn(o - 1));
-      }
-      RES[o] = (T(1) - K.om) * rc + s;
-      rm = rc;
-      rc = rp;
-    }
-  }
-  const int slots[1] = {S_RR};
-  write_partials<1>(v, c.part, c.stride, slots);
-}
-
-// Tiles of the level kernels.  Restriction: a block owns RT_I x RT_J x RT_K
-// next-level cells (one per thread); up/smoothing: a block owns
-// UT_I x UT_J x UT_K cells of its level.
-template <class T>
-struct MgTiles {
-  static constexpr int RT_I = 4, RT_J = 4, RT_K = sizeof(T) == 4 ? 16 : 8;
-  static constexpr int RES_N = (2 * RT_I + 2) * (2 * RT_J + 2) * (2 * RT_K + 2);  // fine residual region
-  static constexpr int R_N = (2 * RT_I + 4) * (2 * RT_J + 4) * (2 * RT_K + 4);    // r region (+1 halo)
-  static constexpr int UT_I = 8, UT_J = 8, UT_K = 32;
-  static constexpr int T_N = (UT_I + 2) * (UT_J + 2) * (UT_K + 2);
-};
-
 __device__ __forceinline__ bool inside(const Layout& L, int i, int j, int k) {
   return (unsigned)i < (unsigned)L.nx && (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz;
 }
 
-// Restriction of one tile of next-level cells.  The fine residual of the
-// pre-smoothed problem over the tile's footprint comes either from a stored
-// array (HAS_RES: level 0, written by the CG update) or is computed here from
-// r staged in LDS.  mode 0: skip when flags[m] is set; 1: block 0 decides
+// Index clamped into the padded extent [-1, n + 1] of an axis.  Every
+// vector the level kernels read this way (CG residuals, level right-hand
+// sides and corrections) has zero ghosts, so positions past the level read
+// as 0 without a branch.
+__device__ __forceinline__ int clampg(int i, int n) { return min(max(i, -1), n + 1); }
+
+// Walk of a DI x DJ x DK box (k fastest) by NT threads: a thread takes a
+// (jj, kk) column of the plane and the entries ii = g, g + STEP, ... of it
+// (STEP > 1 only when the plane has fewer entries than threads).
+template <int DI, int DJ, int DK, int NT>
+struct BoxWalk {
+  static constexpr int P = DJ * DK;
+  static constexpr int STEP = P >= NT ? 1 : NT / P;
+  static constexpr int U = (DI + STEP - 1) / STEP;   // entries per column and thread
+  template <class Fn>
+  __device__ __forceinline__ static void run(Fn f) {
+    if (P >= NT) {
+      for (int pidx = threadIdx.x; pidx < P; pidx += NT) f(pidx / DK, pidx % DK, 0);
+    } else {
+      const int g = threadIdx.x / P;
+      if (g < STEP) {
+        const int pidx = threadIdx.x - g * P;
+        f(pidx / DK, pidx % DK, g);
+      }
+    }
+  }
+};
+
+// LDS copy of a DI x DJ x DK box of a level vector from (lo0, lo1, lo2),
+// each entry scaled by scale(ii, jj, kk) (positions past the level read 0).
+template <int DI, int DJ, int DK, int NT, class T, class Scale>
+__device__ __forceinline__ void stage_box(T* __restrict__ s, const T* __restrict__ src, const Layout& L, int lo0,
+                                          int lo1, int lo2, Scale scale) {
+  using W = BoxWalk<DI, DJ, DK, NT>;
+  W::run([&](int jj, int kk, int g) {
+    const long long base = (long long)(clampg(lo1 + jj, L.ny) + 1) * L.PZ + (clampg(lo2 + kk, L.nz) + 1);
+    T v[W::U];
+#pragma unroll
+    for (int u = 0; u < W::U; ++u) {
+      const int ii = g + u * W::STEP;
+      v[u] = ii < DI ? src[(long long)(clampg(lo0 + ii, L.nx) + 1) * L.SX + base] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < W::U; ++u) {
+      const int ii = g + u * W::STEP;
+      if (ii < DI) s[(ii * DJ + jj) * DK + kk] = scale(ii, jj, kk) * v[u];
+    }
+  });
+}
+
+// Boundary class of a position along one axis of n cells: bit 0 = first
+// cell (or before), bit 1 = last cell (or after).  A cell's D and om/D
+// depend only on its three classes (64 combinations).
+__device__ __forceinline__ int bclass(int i, int n) { return (i <= 0 ? 1 : 0) | (i >= n - 1 ? 2 : 0); }
+
+__device__ __forceinline__ int cls3(const Layout& L, int i, int j, int k) {
+  return (bclass(i, L.nx) << 4) | (bclass(j, L.ny) << 2) | bclass(k, L.nz);
+}
+
+// D of class c of level F: per axis, the weight once for each side that is
+// not a domain side, or is an outlet side.
+template <class T>
+__device__ __forceinline__ T class_diag(const MgCommon<T>& K, const MgLvl<T>& F, int c) {
+  const int cx = c >> 4, cy = (c >> 2) & 3, cz = c & 3;
+  const T dx = F.w[0] * (T(!(cx & 1) || K.bc[0] == OUTLET) + T(!(cx & 2) || K.bc[1] == OUTLET));
+  const T dy = F.w[1] * (T(!(cy & 1) || K.bc[2] == OUTLET) + T(!(cy & 2) || K.bc[3] == OUTLET));
+  const T dz = F.w[2] * (T(!(cz & 1) || K.bc[4] == OUTLET) + T(!(cz & 2) || K.bc[5] == OUTLET));
+  return dx + dy + dz;
+}
+
+// Tables of D and om/D by class, filled by threads 0..63 of the block.
+template <class T>
+__device__ __forceinline__ void fill_class_tables(const MgCommon<T>& K, const MgLvl<T>& F, T* tab_d, T* tab_omd) {
+  if (threadIdx.x < 64) {
+    const T D = class_diag(K, F, threadIdx.x);
+    if (tab_d) tab_d[threadIdx.x] = D;
+    tab_omd[threadIdx.x] = D > T(0) ? K.om / D : T(0);
+  }
+}
+
+// Persistent level kernels: a block walks tiles xcd * per + lid + it * nbx
+// (workgroups are dealt to the 8 XCDs round-robin), so the tiles in flight
+// on one XCD are neighbours and their halos meet in that XCD's L2.  The
+// next tile's box is loaded into registers while the current one is
+// processed.
+struct TileWalk {
+  int t, end, step;
+  __device__ __forceinline__ explicit TileWalk(int nt) {
+    const int G = gridDim.x;
+    if (G >= 8 && (G & 7) == 0) {
+      const int xcd = blockIdx.x & 7, lid = blockIdx.x >> 3, per = (nt + 7) >> 3;
+      t = xcd * per + lid;
+      end = min(nt, (xcd + 1) * per);
+      step = G >> 3;
+    } else {
+      t = blockIdx.x;
+      end = nt;
+      step = G;
+    }
+  }
+};
+
+// Tile origin (first cell per axis) of tile t; tiles are numbered with k
+// fastest.
+__device__ __forceinline__ void tile_origin(int t, int3 nt3, int3 tile, int& x0, int& y0, int& z0) {
+  z0 = (t % nt3.x) * tile.z;
+  y0 = ((t / nt3.x) % nt3.y) * tile.y;
+  x0 = (t / (nt3.x * nt3.y)) * tile.x;
+}
+
+constexpr int kLevelBlocksPerCU = 4;   // resident blocks per CU targeted by the level kernels
+constexpr int kCUs = 256;
+
+// Coarse tile of the restriction kernel: one next-level cell per thread.
+template <class T>
+struct RTile {
+  static constexpr int CI = 4, CJ = 4, CK = sizeof(T) == 4 ? 16 : 8;
+  // fine residual box: 2C + 2 cells per axis (halved axis: from 2X - 1;
+  // an axis that is not halved uses its first C entries, from X)
+  static constexpr int EI = 2 * CI + 2, EJ = 2 * CJ + 2, EK = 2 * CK + 2;
+};
+
+// Restriction, tile by tile of next-level cells: e = om D^-1 r (the
+// pre-smoothing sweep from zero) over the tile's footprint and a one-cell
+// halo is staged in LDS, the residual of the pre-smoothed problem
+//   r - A e = (1 - om) r + sum_a w_a (e_{+a} + e_{-a}),  (1 - om) r = a_c e
+// (a_c = (1 - om) D / om by boundary class) is formed over the footprint,
+// then restricted.  mode 0: skip when flags[m] is set; 1: block 0 decides
 // whether the solve has finished and publishes flags[m] (first kernel of a
 // preconditioner application; after convergence the work here is wasted,
 // not wrong); 2: unconditional.
-template <bool HAS_RES, class T>
+template <class T>
 __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, int has_coarse, CgCtl c,
-                                                     int m, int mode) {
-  using Tl = MgTiles<T>;
-  __shared__ T sres[Tl::RES_N];
-  __shared__ T sr[HAS_RES ? 1 : Tl::R_N];
+                                                     int m, int mode, int3 nt3) {
+  using Rt = RTile<T>;
+  constexpr int EI = Rt::EI, EJ = Rt::EJ, EK = Rt::EK;
+  constexpr int QI = EI + 2, QJ = EJ + 2, QK = EK + 2;   // e box: the residual box and a 1-cell halo
+  __shared__ T sres[EI * EJ * EK];
+  __shared__ T se[QI * QJ * QK];
+  __shared__ T tab_omd[64];
+  __shared__ T tab_a[64];
   if (mode == 1) {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    if (blockIdx.x == 0) {
       const bool skip = precond_skip(c, m);
       if (threadIdx.x == 0) c.flags[m] = skip;
     }
@@ -296,104 +353,319 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
     if (c.flags[m]) return;
   }
   if (!has_coarse) return;
-  const int X0[3] = {(int)blockIdx.z * Tl::RT_I, (int)blockIdx.y * Tl::RT_J, (int)blockIdx.x * Tl::RT_K};
-  const int TT[3] = {Tl::RT_I, Tl::RT_J, Tl::RT_K};
-  int lo[3], len[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = F.c[a] ? 2 * X0[a] - 1 : X0[a];
-    len[a] = F.c[a] ? 2 * TT[a] + 2 : TT[a];
+  if (threadIdx.x < 64) {
+    const T D = class_diag(K, F, threadIdx.x);
+    tab_omd[threadIdx.x] = D > T(0) ? K.om / D : T(0);
+    tab_a[threadIdx.x] = (T(1) - K.om) * D / K.om;
   }
   const Layout& L = F.L;
-  const int nres = len[0] * len[1] * len[2];
-  if (HAS_RES) {
-    for (int idx = threadIdx.x; idx < nres; idx += blockDim.x) {
-      const int kk = idx % len[2], jj = (idx / len[2]) % len[1], ii = idx / (len[2] * len[1]);
-      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
-      sres[idx] = inside(L, i, j, k) ? F.t[L.at(i, j, k)] : T(0);
-    }
-  } else {
-    const int q1 = len[1] + 2, q2 = len[2] + 2;
-    const int nq = (len[0] + 2) * q1 * q2;
-    for (int idx = threadIdx.x; idx < nq; idx += blockDim.x) {
-      const int kk = idx % q2, jj = (idx / q2) % q1, ii = idx / (q2 * q1);
-      const int i = lo[0] - 1 + ii, j = lo[1] - 1 + jj, k = lo[2] - 1 + kk;
-      sr[idx] = inside(L, i, j, k) ? F.r[L.at(i, j, k)] : T(0);
-    }
+  const int3 ct = make_int3(Rt::CI, Rt::CJ, Rt::CK);
+  const int nt = nt3.x * nt3.y * nt3.z;
+  // first fine cell of the residual box of a tile with coarse origin X0
+  auto box_lo = [&](int X0, int a) { return F.c[a] ? 2 * X0 - 1 : X0; };
+  for (TileWalk w(nt); w.t < w.end; w.t += w.step) {
+    int X0, Y0, Z0;
+    tile_origin(w.t, nt3, ct, X0, Y0, Z0);
+    const int lo0 = box_lo(X0, 0), lo1 = box_lo(Y0, 1), lo2 = box_lo(Z0, 2);
+    __syncthreads();   // the previous tile is done with the LDS; tables are in place
+    stage_box<QI, QJ, QK, 256>(se, F.r, L, lo0 - 1, lo1 - 1, lo2 - 1, [&](int ii, int jj, int kk) {
+      return tab_omd[cls3(L, lo0 - 1 + ii, lo1 - 1 + jj, lo2 - 1 + kk)];
+    });
     __syncthreads();
-    for (int idx = threadIdx.x; idx < nres; idx += blockDim.x) {
-      const int kk = idx % len[2], jj = (idx / len[2]) % len[1], ii = idx / (len[2] * len[1]);
-      const int i = lo[0] + ii, j = lo[1] + jj, k = lo[2] + kk;
-      T res = T(0);
-      if (inside(L, i, j, k)) {
-        const int q = ((ii + 1) * q1 + (jj + 1)) * q2 + (kk + 1);
-        const int sI = q1 * q2;
-        if (deep_inside(L, i, j, k)) {
-          res = (T(1) - K.om) * sr[q] + F.omd_in * (F.w[0] * (sr[q + sI] + sr[q - sI]) + F.w[1] * (sr[q + q2] + sr[q - q2]) +
-                                                    F.w[2] * (sr[q + 1] + sr[q - 1]));
-        } else {
-          res = (T(1) - K.om) * sr[q] +
-                F.w[0] * (omd(K, F, i + 1, j, k) * sr[q + sI] + omd(K, F, i - 1, j, k) * sr[q - sI]) +
-                F.w[1] * (omd(K, F, i, j + 1, k) * sr[q + q2] + omd(K, F, i, j - 1, k) * sr[q - q2]) +
-                F.w[2] * (omd(K, F, i, j, k + 1) * sr[q + 1] + omd(K, F, i, j, k - 1) * sr[q - 1]);
-        }
+    // residual over the footprint; entries outside the level are never
+    // restricted from
+    using WR = BoxWalk<EI, EJ, EK, 256>;
+    WR::run([&](int jj, int kk, int g) {
+      const int cyz = (bclass(lo1 + jj, L.ny) << 2) | bclass(lo2 + kk, L.nz);
+      constexpr int sI = QJ * QK, sJ = QK;
+#pragma unroll
+      for (int u = 0; u < WR::U; ++u) {
+        const int ii = g + u * WR::STEP;
+        if (ii >= EI) break;
+        const int q = ((ii + 1) * QJ + (jj + 1)) * QK + (kk + 1);
+        sres[(ii * EJ + jj) * EK + kk] = tab_a[(bclass(lo0 + ii, L.nx) << 4) | cyz] * se[q] +
+                                         F.w[0] * (se[q + sI] + se[q - sI]) + F.w[1] * (se[q + sJ] + se[q - sJ]) +
+                                         F.w[2] * (se[q + 1] + se[q - 1]);
       }
-      sres[idx] = res;
-    }
+    });
+    __syncthreads();
+    const int tk = threadIdx.x % Rt::CK, tj = (threadIdx.x / Rt::CK) % Rt::CJ, ti = threadIdx.x / (Rt::CK * Rt::CJ);
+    const int I = X0 + ti, J = Y0 + tj, Kc = Z0 + tk;
+    if (ti < Rt::CI && inside(C.L, I, J, Kc))
+      C.r[C.L.at(I, J, Kc)] = restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) {
+        return sres[((i - lo0) * EJ + (j - lo1)) * EK + (k - lo2)];
+      });
   }
-  __syncthreads();
-  const int tk = threadIdx.x % Tl::RT_K, tj = (threadIdx.x / Tl::RT_K) % Tl::RT_J, ti = threadIdx.x / (Tl::RT_K * Tl::RT_J);
-  if (ti >= Tl::RT_I) return;
-  const int I = X0[0] + ti, J = X0[1] + tj, Kc = X0[2] + tk;
-  if (!inside(C.L, I, J, Kc)) return;
-  C.r[C.L.at(I, J, Kc)] = restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) {
-    return sres[((i - lo[0]) * len[1] + (j - lo[1])) * len[2] + (k - lo[2])];
-  });
 }
 
-// Prolongation + post-smoothing of one tile of level F: t = om D^-1 r + P x_c
-// over the tile and a one-cell halo (LDS), then x = t + om D^-1 (r - A t).
-// FINE: level 0, also writes the partials of r.z for the CG.
-template <bool FINE, bool COARSE, class T>
-__global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m) {
-  using Tl = MgTiles<T>;
-  __shared__ T st[Tl::T_N];
+// Tile of the up/smoothing kernel (cells of its level per block of 256).
+template <int TI_, int TJ_, int TK_>
+struct UpTile {
+  static constexpr int TI = TI_, TJ = TJ_, TK = TK_;
+};
+using UpBig = UpTile<8, 8, 32>;     // levels of >= kUpBigCells cells
+using UpSmall = UpTile<4, 4, 16>;   // smaller levels: more tiles to spread
+constexpr long long kUpBigCells = 1LL << 20;
+
+// Prolongation + post-smoothing, tile by tile of level F: t = om D^-1 r +
+// P x_c over the tile and a one-cell halo (LDS), then x = t + om D^-1
+// (r - A t).  r of the box and the coarse values it needs are staged in LDS
+// first.  HALF: every axis is halved towards C (the coarse box is then
+// TI/2 + 4 wide per axis).  FINE: level 0, also writes the block's partial
+// of r.z for the CG.
+template <bool FINE, bool COARSE, bool HALF, class Tile, class T>
+__global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m, int3 nt3) {
+  constexpr int TI = Tile::TI, TJ = Tile::TJ, TK = Tile::TK;
+  constexpr int HI = TI + 2, HJ = TJ + 2, HK = TK + 2, HN = HI * HJ * HK;
+  // coarse box: parents of the fine box and their prolongation neighbours
+  // (halved axis: from i0/2 - 2, TI/2 + 4 entries; otherwise the fine box)
+  constexpr int XI = HALF ? TI / 2 + 4 : HI, XJ = HALF ? TJ / 2 + 4 : HJ, XK = HALF ? TK / 2 + 4 : HK;
+  __shared__ T sr[HN];
+  __shared__ T st[HN];
+  __shared__ T sx[COARSE ? XI * XJ * XK : 1];
+  __shared__ T tab_d[64];
+  __shared__ T tab_omd[64];
   if (c.flags[m]) return;
+  fill_class_tables<T>(K, F, tab_d, tab_omd);
   const Layout& L = F.L;
-  const int i0 = blockIdx.z * Tl::UT_I, j0 = blockIdx.y * Tl::UT_J, k0 = blockIdx.x * Tl::UT_K;
-  constexpr int HI = Tl::UT_I + 2, HJ = Tl::UT_J + 2, HK = Tl::UT_K + 2;
-  for (int idx = threadIdx.x; idx < HI * HJ * HK; idx += blockDim.x) {
-    const int kk = idx % HK, jj = (idx / HK) % HJ, ii = idx / (HK * HJ);
-    st[idx] = pre_plus_coarse<COARSE>(K, F, C, i0 - 1 + ii, j0 - 1 + jj, k0 - 1 + kk);
-  }
-  __syncthreads();
-  double v[1] = {0.0};
-  for (int idx = threadIdx.x; idx < Tl::UT_I * Tl::UT_J * Tl::UT_K; idx += blockDim.x) {
-    const int kk = idx % Tl::UT_K, jj = (idx / Tl::UT_K) % Tl::UT_J, ii = idx / (Tl::UT_K * Tl::UT_J);
-    const int i = i0 + ii, j = j0 + jj, k = k0 + kk;
-    if (!inside(L, i, j, k)) continue;
-    const int q = ((ii + 1) * HJ + (jj + 1)) * HK + (kk + 1);
-    const T tc = st[q];
-    const T D = diag_w(K.bc, L, F.w, i, j, k);
-    const T At = D * tc - F.w[0] * (st[q + HJ * HK] + st[q - HJ * HK]) - F.w[1] * (st[q + HK] + st[q - HK]) -
-                 F.w[2] * (st[q + 1] + st[q - 1]);
-    const long long o = L.at(i, j, k);
-    const T rr = F.r[o];
-    const T z = tc + omd(K, F, i, j, k) * (rr - At);
-    F.x[o] = z;
-    if (FINE) v[0] += (double)rr * (double)z;
+  const int3 tt = make_int3(TI, TJ, TK);
+  const int nt = nt3.x * nt3.y * nt3.z;
+  auto clo = [&](int x0, int a) { return F.c[a] ? (x0 >> 1) - 2 : x0 - 1; };
+  auto one = [](int, int, int) { return T(1); };
+  double acc[1] = {0.0};
+  for (TileWalk w(nt); w.t < w.end; w.t += w.step) {
+    int i0, j0, k0;
+    tile_origin(w.t, nt3, tt, i0, j0, k0);
+    const int cl0 = clo(i0, 0), cl1 = clo(j0, 1), cl2 = clo(k0, 2);
+    __syncthreads();   // the previous tile is done with the LDS; tables are in place
+    stage_box<HI, HJ, HK, 256>(sr, F.r, L, i0 - 1, j0 - 1, k0 - 1, one);
+    if (COARSE) stage_box<XI, XJ, XK, 256>(sx, C.x, C.L, cl0, cl1, cl2, one);
+    __syncthreads();
+    // t = om D^-1 r + P x_c over the box, 0 outside the level
+    using WT = BoxWalk<HI, HJ, HK, 256>;
+    WT::run([&](int jj, int kk, int g) {
+      const int j = j0 - 1 + jj, k = k0 - 1 + kk;
+      const bool in_jk = (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz;
+      const int cyz = (bclass(j, L.ny) << 2) | bclass(k, L.nz);
+      const Tap2<T> b = ptap(j, F.c[1], C.L.ny, K.sgn[2], K.sgn[3]);
+      const Tap2<T> e = ptap(k, F.c[2], C.L.nz, K.sgn[4], K.sgn[5]);
+#pragma unroll
+      for (int u = 0; u < WT::U; ++u) {
+        const int ii = g + u * WT::STEP;
+        if (ii >= HI) break;
+        const int i = i0 - 1 + ii;
+        const int idx = (ii * HJ + jj) * HK + kk;
+        T v = T(0);
+        if (in_jk && (unsigned)i < (unsigned)L.nx) {
+          v = tab_omd[(bclass(i, L.nx) << 4) | cyz] * sr[idx];
+          if (COARSE) {
+            const Tap2<T> a = ptap(i, F.c[0], C.L.nx, K.sgn[0], K.sgn[1]);
+            auto row = [&](int I, int J) {
+              const int base = ((I - cl0) * XJ + (J - cl1)) * XK - cl2;
+              return e.w0 * sx[base + e.i0] + e.w1 * sx[base + e.i1];
+            };
+            v += a.w0 * (b.w0 * row(a.i0, b.i0) + b.w1 * row(a.i0, b.i1)) +
+                 a.w1 * (b.w0 * row(a.i1, b.i0) + b.w1 * row(a.i1, b.i1));
+          }
+        }
+        st[idx] = v;
+      }
+    });
+    __syncthreads();
+    // x = t + om D^-1 (r - A t) on the tile
+    using WZ = BoxWalk<TI, TJ, TK, 256>;
+    WZ::run([&](int jj, int kk, int g) {
+      const int j = j0 + jj, k = k0 + kk;
+      if ((unsigned)j >= (unsigned)L.ny || (unsigned)k >= (unsigned)L.nz) return;
+      const int cyz = (bclass(j, L.ny) << 2) | bclass(k, L.nz);
+#pragma unroll
+      for (int u = 0; u < WZ::U; ++u) {
+        const int ii = g + u * WZ::STEP;
+        const int i = i0 + ii;
+        if (ii >= TI || i >= L.nx) break;
+        const int q = ((ii + 1) * HJ + (jj + 1)) * HK + (kk + 1);
+        const int cl = (bclass(i, L.nx) << 4) | cyz;
+        const T tc = st[q];
+        const T At = tab_d[cl] * tc - F.w[0] * (st[q + HJ * HK] + st[q - HJ * HK]) -
+                     F.w[1] * (st[q + HK] + st[q - HK]) - F.w[2] * (st[q + 1] + st[q - 1]);
+        const T rr = sr[q];
+        const T z = tc + tab_omd[cl] * (rr - At);
+        F.x[L.at(i, j, k)] = z;
+        if (FINE) acc[0] += (double)rr * (double)z;
+      }
+    });
   }
   if (FINE) {
     const int slots[1] = {S_RZ0 + (m & 1)};
-    write_partials<1>(v, c.part, c.stride, slots);
+    write_partials<1>(acc, c.part, c.stride, slots);
   }
 }
 
-// All levels from lt down to the coarsest and back, in one workgroup, as
-// phases separated by barriers over arrays that stay in the L2.  The level
-// descriptors are read from a device table.
+// LDS cells for the levels of the single-workgroup kernel (each level there
+// has at most kTailCells cells and at least halves the previous one).
+constexpr int kTailPool = 2 * (int)kTailCells;
+
+// All levels from lt down to the coarsest and back in one workgroup, with
+// every level's r, x and t in LDS (compact k-fastest order, no ghosts;
+// neighbours outside a level read as 0).  Level lt's r comes from and its x
+// goes to global memory.  Level descriptors are read from a device table.
 template <class T>
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const MgLvl<T>* __restrict__ lv, int lt,
+                                                          int nl, const T* __restrict__ cinv,
+                                                          const int* __restrict__ flags, int m) {
+  if (flags[m]) return;
+  __shared__ T pr[kTailPool];
+  __shared__ T px[kTailPool];
+  __shared__ T pt[kTailPool];
+  __shared__ T tab_d[kMgMaxLevels * 64];
+  __shared__ T tab_omd[kMgMaxLevels * 64];
+  const int tid = threadIdx.x;
+  auto offset = [&](int l) {
+    int o = 0;
+    for (int q = lt; q < l; ++q) o += (int)ncells(lv[q].L);
+    return o;
+  };
+  auto cid = [](const Layout& L, int i, int j, int k) { return (i * L.ny + j) * L.nz + k; };
+  // value of a compact level array at (i, j, k); 0 outside the level
+  auto at = [&](const T* a, const Layout& L, int i, int j, int k) {
+    return inside(L, i, j, k) ? a[cid(L, i, j, k)] : T(0);
+  };
+  for (int e = tid; e < (nl - lt) * 64; e += blockDim.x) {
+    const MgLvl<T> F = lv[lt + e / 64];
+    const T D = class_diag(K, F, e % 64);
+    tab_d[e] = D;
+    tab_omd[e] = D > T(0) ? K.om / D : T(0);
+  }
+  {
+    const MgLvl<T> F = lv[lt];
+    const int nf = (int)ncells(F.L);
+    for (int idx = tid; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      pr[idx] = F.r[F.L.at(i, j, k)];
+    }
+  }
+  __syncthreads();
+  for (int l = lt; l < nl - 1; ++l) {
+    const MgLvl<T> F = lv[l];
+    const MgLvl<T> C = lv[l + 1];
+    const T* om_l = tab_omd + (l - lt) * 64;
+    const int of = offset(l), oc = of + (int)ncells(F.L);
+    const int nf = (int)ncells(F.L), nc = (int)ncells(C.L);
+    const T* r = pr + of;
+    T* t = pt + of;
+    for (int idx = tid; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      // e = om D^-1 r, 0 outside the level
+      auto e = [&](int a, int b, int q) { return om_l[cls3(F.L, a, b, q)] * at(r, F.L, a, b, q); };
+      t[idx] = (T(1) - K.om) * r[idx] + F.w[0] * (e(i + 1, j, k) + e(i - 1, j, k)) +
+               F.w[1] * (e(i, j + 1, k) + e(i, j - 1, k)) + F.w[2] * (e(i, j, k + 1) + e(i, j, k - 1));
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nc; idx += blockDim.x) {
+      int I, J, Kc;
+      decode(idx, C.L, I, J, Kc);
+      pr[oc + idx] = restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) { return t[cid(F.L, i, j, k)]; });
+    }
+    __syncthreads();
+  }
+  {
+    const MgLvl<T> B = lv[nl - 1];
+    const T* d_b = tab_d + (nl - 1 - lt) * 64;
+    const T* om_b = tab_omd + (nl - 1 - lt) * 64;
+    const int ob = offset(nl - 1);
+    const int nb = (int)ncells(B.L);
+    const T* r = pr + ob;
+    if (cinv) {
+      // x = Ainv r: tpr lanes per row (power of two <= 64), partial sums
+      // combined with lane shuffles
+      int tpr = 1;
+      while (tpr < 64 && tpr * 2 * nb <= (int)blockDim.x) tpr *= 2;
+      for (int base = 0; base < nb * tpr; base += blockDim.x) {
+        const int row = (base + tid) / tpr, lane = (base + tid) % tpr;
+        T s = T(0);
+        if (row < nb)
+          for (int col = lane; col < nb; col += tpr) s += cinv[(size_t)row * nb + col] * r[col];
+        for (int w = 1; w < tpr; w *= 2) s += __shfl_xor(s, w, 64);
+        if (row < nb && lane == 0) px[ob + row] = s;
+      }
+      __syncthreads();
+    } else {
+      // fixed Jacobi sweeps from zero (symmetric, positive definite for om <= 1)
+      T* xa = px + ob;
+      T* xb = pt + ob;
+      for (int idx = tid; idx < nb; idx += blockDim.x) xa[idx] = T(0);
+      __syncthreads();
+      for (int sw = 0; sw < kCoarseSweeps; ++sw) {
+        for (int idx = tid; idx < nb; idx += blockDim.x) {
+          int i, j, k;
+          decode(idx, B.L, i, j, k);
+          const int cl = cls3(B.L, i, j, k);
+          const T Ax = d_b[cl] * xa[idx] - B.w[0] * (at(xa, B.L, i + 1, j, k) + at(xa, B.L, i - 1, j, k)) -
+                       B.w[1] * (at(xa, B.L, i, j + 1, k) + at(xa, B.L, i, j - 1, k)) -
+                       B.w[2] * (at(xa, B.L, i, j, k + 1) + at(xa, B.L, i, j, k - 1));
+          xb[idx] = xa[idx] + om_b[cl] * (r[idx] - Ax);
+        }
+        __syncthreads();
+        T* tmp = xa;
+        xa = xb;
+        xb = tmp;
+      }
+      if (xa != px + ob) {
+        for (int idx = tid; idx < nb; idx += blockDim.x) px[ob + idx] = xa[idx];
+        __syncthreads();
+      }
+    }
+  }
+  for (int l = nl - 2; l >= lt; --l) {
+    const MgLvl<T> F = lv[l];
+    const MgLvl<T> C = lv[l + 1];
+    const T* d_l = tab_d + (l - lt) * 64;
+    const T* om_l = tab_omd + (l - lt) * 64;
+    const int of = offset(l), oc = of + (int)ncells(F.L);
+    const int nf = (int)ncells(F.L);
+    const T* r = pr + of;
+    const T* xc = px + oc;
+    T* t = pt + of;
+    for (int idx = tid; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      const Tap2<T> a = ptap(i, F.c[0], C.L.nx, K.sgn[0], K.sgn[1]);
+      const Tap2<T> b = ptap(j, F.c[1], C.L.ny, K.sgn[2], K.sgn[3]);
+      const Tap2<T> e = ptap(k, F.c[2], C.L.nz, K.sgn[4], K.sgn[5]);
+      auto row = [&](int I, int J) { return e.w0 * xc[cid(C.L, I, J, e.i0)] + e.w1 * xc[cid(C.L, I, J, e.i1)]; };
+      t[idx] = om_l[cls3(F.L, i, j, k)] * r[idx] + a.w0 * (b.w0 * row(a.i0, b.i0) + b.w1 * row(a.i0, b.i1)) +
+               a.w1 * (b.w0 * row(a.i1, b.i0) + b.w1 * row(a.i1, b.i1));
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      const int cl = cls3(F.L, i, j, k);
+      const T At = d_l[cl] * t[idx] - F.w[0] * (at(t, F.L, i + 1, j, k) + at(t, F.L, i - 1, j, k)) -
+                   F.w[1] * (at(t, F.L, i, j + 1, k) + at(t, F.L, i, j - 1, k)) -
+                   F.w[2] * (at(t, F.L, i, j, k + 1) + at(t, F.L, i, j, k - 1));
+      px[of + idx] = t[idx] + om_l[cl] * (r[idx] - At);
+    }
+    __syncthreads();
+  }
+  {
+    const MgLvl<T> F = lv[lt];
+    const int nf = (int)ncells(F.L);
+    for (int idx = tid; idx < nf; idx += blockDim.x) {
+      int i, j, k;
+      decode(idx, F.L, i, j, k);
+      F.x[F.L.at(i, j, k)] = px[idx];
+    }
+  }
+}
+
+// The same in global memory (arrays that stay in the L2), for hierarchies
+// whose small levels do not fit the LDS pool (a coarsest level above
+// kTailCells cells, left when no axis can be halved).
+template <class T>
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail_global(MgCommon<T> K, const MgLvl<T>* __restrict__ lv, int lt,
                                                           int nl, const T* __restrict__ cinv,
                                                           const int* __restrict__ flags, int m) {
   if (flags[m]) return;
@@ -613,7 +885,7 @@ void mg_setup(Grid& g) {
   while ((int)g.mg.size() < kMgMaxLevels) {
     MgLevel& F = g.mg.back();
     const int n[3] = {F.L.nx, F.L.ny, F.L.nz};
-    if (ncells(F.L) <= 256) break;
+    if (ncells(F.L) <= kCoarsestCells) break;
     int c[3], any = 0;
     for (int a = 0; a < 3; ++a) {
       c[a] = (n[a] % 2 == 0 && n[a] >= 4) ? 1 : 0;
@@ -645,6 +917,11 @@ void mg_setup(Grid& g) {
     }
   // the coarsest level is always solved by the single-workgroup kernel
   if (nl > 1 && g.mg_lt > nl - 1) g.mg_lt = nl - 1;
+  {
+    long long pool = 0;
+    for (int l = std::min(g.mg_lt, nl - 1); l < nl; ++l) pool += ncells(g.mg[l].L);
+    g.mg_tail_lds = pool <= kTailPool;
+  }
   g.mg_cinv = nullptr;
   g.mg_nc = (int)ncells(last.L);
   g.mg_omega = kJacobiOmega;
@@ -664,22 +941,57 @@ void mg_setup(Grid& g) {
   }
 }
 
+static bool big_tile(const Layout& L) { return ncells(L) >= kUpBigCells; }
+
+template <class Tile>
+static int3 up_tiles(const Layout& F) {
+  return make_int3((F.nz + Tile::TK - 1) / Tile::TK, (F.ny + Tile::TJ - 1) / Tile::TJ, (F.nx + Tile::TI - 1) / Tile::TI);
+}
+
+// Blocks of a persistent level kernel over nt tiles.
+static int level_blocks(long long nt) {
+  const long long cap = (long long)kCUs * kLevelBlocksPerCU;
+  return (int)std::max(1LL, std::min(nt, cap));
+}
+
+// Blocks of the fine up/smoothing kernel (one r.z partial each).
 size_t mg_fine_blocks(const Layout& L) {
-  using Tl = MgTiles<float>;   // the up/smoothing tile does not depend on the dtype
-  return (size_t)((L.nz + Tl::UT_K - 1) / Tl::UT_K) * ((L.ny + Tl::UT_J - 1) / Tl::UT_J) *
-         ((L.nx + Tl::UT_I - 1) / Tl::UT_I);
+  const int3 t = big_tile(L) ? up_tiles<UpBig>(L) : up_tiles<UpSmall>(L);
+  return (size_t)level_blocks((long long)t.x * t.y * t.z);
 }
 
 template <class T>
-static dim3 restrict_grid(const Layout& C) {
-  using Tl = MgTiles<T>;
-  return dim3((C.nz + Tl::RT_K - 1) / Tl::RT_K, (C.ny + Tl::RT_J - 1) / Tl::RT_J, (C.nx + Tl::RT_I - 1) / Tl::RT_I);
+static int3 restrict_tiles(const Layout& C) {
+  using Rt = RTile<T>;
+  return make_int3((C.nz + Rt::CK - 1) / Rt::CK, (C.ny + Rt::CJ - 1) / Rt::CJ, (C.nx + Rt::CI - 1) / Rt::CI);
 }
 
 template <class T>
-static dim3 up_grid(const Layout& F) {
-  using Tl = MgTiles<T>;
-  return dim3((F.nz + Tl::UT_K - 1) / Tl::UT_K, (F.ny + Tl::UT_J - 1) / Tl::UT_J, (F.nx + Tl::UT_I - 1) / Tl::UT_I);
+static void launch_restrict(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, int has_coarse,
+                            const CgCtl& c, int m, int mode) {
+  const int3 nt3 = has_coarse ? restrict_tiles<T>(C.L) : make_int3(1, 1, 1);
+  const int G = has_coarse ? level_blocks((long long)nt3.x * nt3.y * nt3.z) : 1;
+  hipLaunchKernelGGL(k_mg_restrict<T>, dim3(G), dim3(256), 0, g.stream, K, F, C, has_coarse, c, m, mode, nt3);
+}
+
+template <bool FINE, bool COARSE, class Tile, class T>
+static void launch_up_t(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, const CgCtl& c, int m) {
+  const int3 nt3 = up_tiles<Tile>(F.L);
+  const int G = level_blocks((long long)nt3.x * nt3.y * nt3.z);
+  if (COARSE && F.c[0] && F.c[1] && F.c[2])
+    hipLaunchKernelGGL((k_mg_upsmooth<FINE, COARSE, true, Tile, T>), dim3(G), dim3(256), 0, g.stream, K, F, C, c, m,
+                       nt3);
+  else
+    hipLaunchKernelGGL((k_mg_upsmooth<FINE, COARSE, false, Tile, T>), dim3(G), dim3(256), 0, g.stream, K, F, C, c, m,
+                       nt3);
+}
+
+template <bool FINE, bool COARSE, class T>
+static void launch_up(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, const CgCtl& c, int m) {
+  if (big_tile(F.L))
+    launch_up_t<FINE, COARSE, UpBig, T>(g, K, F, C, c, m);
+  else
+    launch_up_t<FINE, COARSE, UpSmall, T>(g, K, F, C, c, m);
 }
 
 template <class T>
@@ -691,61 +1003,43 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   MgLvl<T> L0 = mg_level<T>(g, 0);
   L0.r = (T*)r;
   L0.x = (T*)z;
-  L0.t = (T*)z;   // the fine residual from the CG update lives in z until z is written
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
-  // level 0 -> 1: the stored residual exists only after a CG update
-  const bool stored = decide && m > 0;
-  const int mode0 = decide ? 1 : 2;
   {
     TimedLaunch tl(g, UF_TK_MG_DOWN0);
-    const dim3 grid = nl > 1 ? restrict_grid<T>(L1.L) : dim3(1);
-    if (stored)
-      hipLaunchKernelGGL((k_mg_restrict<true, T>), grid, dim3(256), 0, g.stream, K, L0, L1, nl > 1 ? 1 : 0, c, m, mode0);
-    else
-      hipLaunchKernelGGL((k_mg_restrict<false, T>), grid, dim3(256), 0, g.stream, K, L0, L1, nl > 1 ? 1 : 0, c, m, mode0);
+    launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2);
   }
   const int lt = std::min(g.mg_lt, nl - 1);
   for (int l = 1; l < lt; ++l) {
     const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);
     TimedLaunch tl(g, UF_TK_MG_COARSE);
-    hipLaunchKernelGGL((k_mg_restrict<false, T>), restrict_grid<T>(C.L), dim3(256), 0, g.stream, K, F, C, 1, c, m, 0);
+    launch_restrict<T>(g, K, F, C, 1, c, m, 0);
   }
   if (nl > 1) {
     {
       TimedLaunch tl(g, UF_TK_MG_COARSE);
-      hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K, (const MgLvl<T>*)g.mg_table, lt,
-                         nl, (const T*)g.mg_cinv, (const int*)c.flags, m);
+      if (g.mg_tail_lds)
+        hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K, (const MgLvl<T>*)g.mg_table, lt,
+                           nl, (const T*)g.mg_cinv, (const int*)c.flags, m);
+      else
+        hipLaunchKernelGGL(k_mg_tail_global<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K,
+                           (const MgLvl<T>*)g.mg_table, lt, nl, (const T*)g.mg_cinv, (const int*)c.flags, m);
     }
     for (int l = lt - 1; l >= 1; --l) {
       const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);
       TimedLaunch tl(g, UF_TK_MG_COARSE);
-      hipLaunchKernelGGL((k_mg_upsmooth<false, true, T>), up_grid<T>(F.L), dim3(256), 0, g.stream, K, F, C, c, m);
+      launch_up<false, true, T>(g, K, F, C, c, m);
     }
   }
   TimedLaunch tl(g, UF_TK_MG_UP0);
   if (nl > 1)
-    hipLaunchKernelGGL((k_mg_upsmooth<true, true, T>), up_grid<T>(L0.L), dim3(256), 0, g.stream, K, L0, L1, c, m);
+    launch_up<true, true, T>(g, K, L0, L1, c, m);
   else
-    hipLaunchKernelGGL((k_mg_upsmooth<true, false, T>), up_grid<T>(L0.L), dim3(256), 0, g.stream, K, L0, L1, c, m);
+    launch_up<true, false, T>(g, K, L0, L1, c, m);
 }
 
 template <class T>
 void mg_precond(Grid& g, const Params<T>& P, int m) {
   mg_launch<T>(g, P, m, resid(g, m), g.Z, 1);
-}
-
-// CG update fused with the fine residual of the next preconditioner
-// application (written into Z, which the application overwrites last).
-template <class T>
-void mg_axpy(Grid& g, const Params<T>& P, int t) {
-  (void)P;
-  const MgCommon<T> K = mg_common<T>(g);
-  MgLvl<T> L0 = mg_level<T>(g, 0);
-  const CgLaunch cl = cg_launch(g.L);
-  TimedLaunch tl(g, UF_TK_CG_AXPY);
-  hipLaunchKernelGGL(k_mg_axpy<T>, cl.grid, dim3(kMgFineBlock), 0, g.stream, K, L0, (T*)g.X,
-                     (const T*)resid(g, t), (T*)resid(g, t + 1), (const T*)g.D[(t + 1) & 1], (const T*)g.Qv,
-                     (T*)g.Z, make_ctl(g), t, cl.ilen);
 }
 
 // Stand-alone application z = M^-1 r: uses the spare flag slot past the
@@ -762,7 +1056,5 @@ template void mg_precond<float>(Grid&, const Params<float>&, int);
 template void mg_precond<double>(Grid&, const Params<double>&, int);
 template void mg_apply<float>(Grid&, const Params<float>&, const void*, void*);
 template void mg_apply<double>(Grid&, const Params<double>&, const void*, void*);
-template void mg_axpy<float>(Grid&, const Params<float>&, int);
-template void mg_axpy<double>(Grid&, const Params<double>&, int);
 
 }  // namespace uf

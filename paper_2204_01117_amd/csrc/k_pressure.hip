@@ -160,9 +160,12 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __rest
     for (int i = i0; i < i1; ++i) X[L.at(i, j, k)] = T(0);
     return;
   }
-  double rz;
-  if (!iteration_runs(c, t, &rz)) return;
-  const T beta = t == 0 ? T(0) : (T)(rz / slot_sum(c.part + (size_t)(S_RZ0 + ((t + 1) & 1)) * c.stride, c.nb_rz));
+  if (!iteration_open(c, t)) return;
+  const double rz = rz_of(c, t);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) c.st->rzh[t & 1] = rz;
+  if (!rz_allows(c, rz)) return;
+  // r.z of iteration t - 1 was published by this kernel's previous launch
+  const T beta = t == 0 ? T(0) : (T)(rz / c.st->rzh[(t + 1) & 1]);
   double v[1] = {0.0};
   if (i0 < i1) {
     const bool first = t == 0;
@@ -219,7 +222,11 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
                                                       const T* __restrict__ Qv, CgCtl c, int t, int ilen) {
   const Layout& L = P.L;
   double rz = 0.0, dq = 0.0;
-  bool run = iteration_runs(c, t, &rz);
+  bool run = iteration_open(c, t);
+  if (run) {
+    rz = c.st->rzh[t & 1];
+    run = rz_allows(c, rz);
+  }
   if (run) {
     dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb);
     run = dq > 0.0 && isfinite(dq);
@@ -333,9 +340,7 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
     hipLaunchKernelGGL(k_cg_Ad<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)g.Z, (const T*)Dold, (T*)Dnew,
                        (T*)g.Qv, (T*)g.X, c, t, cl.ilen);
   }
-  if (g.cfg.precond == UF_PC_MG) {
-    mg_axpy<T>(g, P, t);
-  } else {
+  {
     TimedLaunch tl(g, UF_TK_CG_AXPY);
     hipLaunchKernelGGL(k_cg_axpy<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (T*)g.X, (const T*)resid(g, t),
                        (T*)resid(g, t + 1), (const T*)Dnew, (const T*)g.Qv, c, t, cl.ilen);

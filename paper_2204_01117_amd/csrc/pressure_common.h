@@ -11,8 +11,9 @@
 namespace uf {
 
 // Partial-sum slots of the solve: every block of a reducing kernel writes
-// its FP64 partial into part[slot * nb + block]; later kernels add the nb
-// partials in block order (no atomics, no intra-kernel cross-block traffic).
+// its FP64 partial into part[slot * stride + block]; later kernels add the
+// block partials in block order (no atomics, no intra-kernel cross-block
+// traffic).
 enum CgSlot { S_BB = 0, S_RR = 1, S_DQ = 2, S_RZ0 = 3, S_RZ1 = 4, S_NSLOT = 5 };
 
 template <class T>
@@ -87,12 +88,19 @@ __device__ __forceinline__ bool precond_skip(const CgCtl& c, int m) {
   return c.criterion == 0 && rr <= c.st->tol2_bb;
 }
 
-// Does iteration t run?  Same answer in Ad(t) and axpy(t).
-__device__ __forceinline__ bool iteration_runs(const CgCtl& c, int t, double* rz) {
-  if (c.flags[t] || t >= c.maxit) return false;
-  *rz = slot_sum(c.part + (size_t)(S_RZ0 + (t & 1)) * c.stride, c.nb_rz);
-  if (!isfinite(*rz)) return false;
-  if (c.criterion == 1 && *rz < c.st->tol2_bb) return false;
+// Does iteration t run?  The d/q kernel of iteration t adds the r.z
+// partials (rz_of) and block 0 publishes the sum in st->rzh[t & 1]; the
+// update kernel reads it back (rz_published), so both take the same
+// decision from the same value.
+__device__ __forceinline__ bool iteration_open(const CgCtl& c, int t) { return !c.flags[t] && t < c.maxit; }
+
+__device__ __forceinline__ double rz_of(const CgCtl& c, int t) {
+  return slot_sum(c.part + (size_t)(S_RZ0 + (t & 1)) * c.stride, c.nb_rz);
+}
+
+__device__ __forceinline__ bool rz_allows(const CgCtl& c, double rz) {
+  if (!isfinite(rz)) return false;
+  if (c.criterion == 1 && rz < c.st->tol2_bb) return false;
   return true;
 }
 

@@ -676,12 +676,12 @@ uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_de
 
 uf_status uf_objective(uf_grid g, const void*, double*, void*) {
   (void)g;
-  return fail(UF_ENOTIMPL, "uf_objective is not provided by this build");
+  return fail(UF_ENOTIMPL, "uf_objective is not implemented in this library version");
 }
 
 uf_status uf_adjoint_step(uf_grid g, const void* const*, const void* const*, void* const*, void*) {
   (void)g;
-  return fail(UF_ENOTIMPL, "uf_adjoint_step is not provided by this build");
+  return fail(UF_ENOTIMPL, "uf_adjoint_step is not implemented in this library version");
 }
 
 }  // extern "C"

@@ -15,8 +15,7 @@ namespace uf {
 struct CgState {
   double bb;         // ||b||^2
   double rr;         // ||r||^2 after the last update
-  double rz;         // r . M^-1 r of the current iterate
-  double alpha, beta;
+  double rzh[2];     // r.z of iteration t in rzh[t & 1], published by block 0 of the d/q kernel
   double tol2_bb;    // stopping threshold on ||r||^2 (criterion 0) or r.z (criterion 1)
   int iter;          // iterations done
   int done;          // 1 once converged, stopped at maxit, or non-finite
@@ -26,7 +25,6 @@ struct CgState {
   int maxit;
   int criterion;
   int pad;
-  unsigned counter[8];
 };
 
 // One level of the multigrid hierarchy (level 0 is the fine grid).
@@ -83,6 +81,7 @@ struct Grid {
   hipEvent_t ev_status = nullptr, ev0 = nullptr, ev1 = nullptr;
   std::vector<MgLevel> mg;
   int mg_lt = 0;                // first level of the single-workgroup kernel
+  bool mg_tail_lds = true;      // the small levels fit the LDS pool of the single-workgroup kernel
   int mg_nc = 0;                // cells of the coarsest level
   void* mg_cinv = nullptr;      // dense inverse of the coarsest operator
   void* mg_table = nullptr;     // device copy of the level descriptors
@@ -124,7 +123,6 @@ template <class T> void launch_apply(Grid& g, const Params<T>& P, int op, const 
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);
-template <class T> void mg_axpy(Grid& g, const Params<T>& P, int t);
 void mg_free(Grid& g);
 
 // Brackets one kernel launch with timer events when that kernel is timed.
