@@ -63,7 +63,6 @@ PROFILE_NAMES = [
     ("k_mg_axpy<", "cg_axpy"),
     ("k_cg_axpy<", "cg_axpy"),
     ("k_mg_upsmooth<true", "mg_up0"),
-    ("k_mg_restrict<true", "mg_down0"),
     ("k_cg_init<", "cg_init"),
     ("k_advect_fwd<", "advect_fwd"),
     ("k_advect_corr<", "advect_corr"),
@@ -132,18 +131,35 @@ def _counter_rows(run_dir):
             yield row
 
 
-def _per_kernel(run_dir, counter):
-    """Average counter value per dispatch, by kernel name."""
+def _dispatches(run_dir, counter):
+    """(kernel name, grid size, value) of every dispatch for one counter."""
     acc = {}
     for row in _counter_rows(run_dir):
         if row.get("Counter_Name") != counter:
             continue
-        key = (row["Kernel_Name"], row.get("Dispatch_Id"))
+        key = (row["Kernel_Name"], int(row.get("Grid_Size") or 0), row.get("Dispatch_Id"))
         acc[key] = acc.get(key, 0.0) + float(row["Counter_Value"])
+    return [(k[0], k[1], v) for k, v in acc.items()]
+
+
+def _per_kernel(disp):
+    """Average per dispatch by (kernel name, grid size)."""
     per = {}
-    for (name, _), v in acc.items():
-        per.setdefault(name, []).append(v)
+    for name, grid, v in disp:
+        per.setdefault((name, grid), []).append(v)
     return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def _copy_calibration(disp):
+    """Average counter value of the calibration copies: the copy-kernel
+    dispatches within 10% of the largest one (smaller runtime copies of the
+    set-up are left out)."""
+    vals = [v for name, _, v in disp if "copy" in name.lower()]
+    if not vals:
+        raise SystemExit("no copy kernel in the counter runs")
+    top = max(vals)
+    big = [v for v in vals if v >= 0.9 * top]
+    return sum(big) / len(big), len(big)
 
 
 def traffic_probe():
@@ -167,26 +183,36 @@ def traffic_probe():
 
 
 def traffic_summary(run_dir, command):
-    fetch = _per_kernel(os.path.join(run_dir, "fetch"), "FETCH_SIZE")
-    write = _per_kernel(os.path.join(run_dir, "write"), "WRITE_SIZE")
-    copy = [k for k in fetch if "copy" in k.lower() and k in write]
-    if not copy:
-        raise SystemExit("no copy kernel in the counter runs")
-    ck = max(copy, key=lambda k: fetch[k])
-    f_fetch = fetch[ck] * 1024.0 / COPY_BYTES
-    f_write = write[ck] * 1024.0 / COPY_BYTES
-    out = {}
-    for name in fetch:
+    fd = _dispatches(os.path.join(run_dir, "fetch"), "FETCH_SIZE")
+    wd = _dispatches(os.path.join(run_dir, "write"), "WRITE_SIZE")
+    c_fetch, n_fetch = _copy_calibration(fd)
+    c_write, n_write = _copy_calibration(wd)
+    f_fetch = c_fetch * 1024.0 / COPY_BYTES
+    f_write = c_write * 1024.0 / COPY_BYTES
+    fetch, write = _per_kernel(fd), _per_kernel(wd)
+    # one entry per timer name: the group with the largest grid (the finest
+    # level for the multigrid kernels)
+    best = {}
+    for (name, grid) in fetch:
         bn = profile_name(name)
-        if bn is None or bn in out or name not in write:
+        if bn is None or (name, grid) not in write:
             continue
-        fb = fetch[name] * 1024.0 / f_fetch
-        wb = write[name] * 1024.0 / f_write
+        if bn not in best or grid > best[bn][1]:
+            best[bn] = (name, grid)
+    if "mg_down0" not in best:
+        cands = [(n, gr) for (n, gr) in fetch if "k_mg_restrict<" in n and (n, gr) in write]
+        if cands:
+            best["mg_down0"] = max(cands, key=lambda k: k[1])
+    out = {}
+    for bn, key in best.items():
+        fb = fetch[key] * 1024.0 / f_fetch
+        wb = write[key] * 1024.0 / f_write
         out[bn] = {
-            "kernel": bn, "profiler_name": name.split("(")[0], "workload": "256x256x64",
+            "kernel": bn, "profiler_name": key[0].split("(")[0], "grid_size": key[1], "workload": "256x256x64",
             "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
-            "fetch_kib_raw": fetch[name], "write_kib_raw": write[name],
-            "calibration": {"copy_kernel": ck.split("(")[0], "copy_bytes": COPY_BYTES,
+            "fetch_kib_raw": fetch[key], "write_kib_raw": write[key],
+            "calibration": {"copy_bytes": COPY_BYTES, "copies": [n_fetch, n_write],
+                            "fetch_kib_raw": c_fetch, "write_kib_raw": c_write,
                             "fetch_factor": f_fetch, "write_factor": f_write},
             "alg_bytes_per_launch": ALG_BYTES_PER_CELL[bn] * 256 * 256 * 64,
             "source_sha256": sources_hash(),
@@ -197,8 +223,9 @@ def traffic_summary(run_dir, command):
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
             f.write("\n")
-        log("%-12s traffic %.3e B/launch (alg %.3e), fetch factor %.3f write factor %.3f"
-            % (bn, rec["bytes_per_launch"], rec["alg_bytes_per_launch"], f_fetch, f_write))
+        log("%-12s traffic %.3e B/launch (alg %.3e, ratio %.2f), fetch factor %.3f write factor %.3f"
+            % (bn, rec["bytes_per_launch"], rec["alg_bytes_per_launch"],
+               rec["bytes_per_launch"] / rec["alg_bytes_per_launch"], f_fetch, f_write))
 
 
 def stats_summary(run_dir, command):
@@ -214,6 +241,20 @@ def stats_summary(run_dir, command):
         lines.append("| `%s` | %s | %.2f | %.3f | %.1f |" % (
             name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
             float(r["Percentage"])))
+    traces = glob.glob(os.path.join(run_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if traces:
+        groups = {}
+        for r in csv.DictReader(open(traces[0])):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("uf::", "")
+            threads = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
+            key = (name, threads // max(1, wg))
+            groups.setdefault(key, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        lines += ["", "By launch shape (the multigrid kernels run once per level):", "",
+                  "| kernel | blocks | calls | avg us | total ms |", "|---|---:|---:|---:|---:|"]
+        for (name, blocks), d in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:24]:
+            lines.append("| `%s` | %d | %d | %.2f | %.3f |" % (name, blocks, len(d), sum(d) / len(d) / 1e3,
+                                                               sum(d) / 1e6))
     path = os.path.join(ROOT, "profiles", "kernels_256x256x64.md")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -249,7 +290,7 @@ def cpu_baseline(phi, cfg, state):
     z = M @ r
     d = z.copy()
     rz = float(r @ z)
-    n_it = 12
+    n_it = 150
     t1 = time.perf_counter()
     for _ in range(n_it):
         q = A @ d

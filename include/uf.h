@@ -172,12 +172,15 @@ uf_status uf_objective(uf_grid g, const void* spec, double* J_host, void* dJ_dst
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
                           void* const* adj_n_dev, void* dJ_dphi_accum_dev);
 
-/* Kernel timer.  While enabled, the library brackets every launch of the
- * selected kernels with HIP events on the grid's stream and accumulates
- * their elapsed time (for the benchmark's per-kernel bandwidth figures).
- * mask: bit UF_TK_* per kernel; 0 disables.  Enabling resets the totals.
- * uf_kernel_timer_read synchronises and returns the total milliseconds and
- * the number of launches of one kernel since the timer was enabled. */
+/* Kernel timer.  While enabled, every launch of the selected kernels carries
+ * a pair of HIP events in its own dispatch (hipExtLaunchKernel start/stop
+ * events: the kernel's begin and end, no separate marker packets), and the
+ * elapsed times are accumulated (for the benchmark's per-kernel bandwidth
+ * figures).  UF_TK_MG_COARSE covers every multigrid kernel below the finest
+ * level.  mask: bit UF_TK_* per kernel; 0 disables.  Enabling resets the
+ * totals.  uf_kernel_timer_read synchronises and returns the total
+ * milliseconds and the number of launches of one kernel since the timer
+ * was enabled. */
 enum { UF_TK_CG_AD = 0, UF_TK_CG_AXPY = 1, UF_TK_CG_PRECOND = 2, UF_TK_MG_DOWN0 = 3, UF_TK_MG_UP0 = 4,
        UF_TK_MG_COARSE = 5, UF_TK_CG_INIT = 6, UF_TK_ADVECT_FWD = 7, UF_TK_ADVECT_CORR = 8,
        UF_TK_DIFFUSE = 9, UF_TK_DRAG = 10, UF_TK_PROJECT = 11, UF_TK_TURB = 12, UF_TK_COUNT = 13 };

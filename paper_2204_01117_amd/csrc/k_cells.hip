@@ -144,7 +144,7 @@ template <class T>
 void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1,
                  void* NUT, int update_kw) {
   TimedLaunch tl(g, UF_TK_TURB);
-  hipLaunchKernelGGL(k_turbulence<T>, cell_grid(P.L), dim3(kCellBlock), 0, g.stream, P, (const T*)Q[0],
+  launch_k(g, k_turbulence<T>, cell_grid(P.L), dim3(kCellBlock), P, (const T*)Q[0],
                      (const T*)Q[1], (const T*)Q[2], (const T*)K0, (const T*)W0, (T*)K1, (T*)W1, (T*)NUT, update_kw);
 }
 

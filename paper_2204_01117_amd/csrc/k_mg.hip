@@ -971,7 +971,7 @@ static void launch_restrict(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, co
                             const CgCtl& c, int m, int mode) {
   const int3 nt3 = has_coarse ? restrict_tiles<T>(C.L) : make_int3(1, 1, 1);
   const int G = has_coarse ? level_blocks((long long)nt3.x * nt3.y * nt3.z) : 1;
-  hipLaunchKernelGGL(k_mg_restrict<T>, dim3(G), dim3(256), 0, g.stream, K, F, C, has_coarse, c, m, mode, nt3);
+  launch_k(g, k_mg_restrict<T>, dim3(G), dim3(256), K, F, C, has_coarse, c, m, mode, nt3);
 }
 
 template <bool FINE, bool COARSE, class Tile, class T>
@@ -979,11 +979,9 @@ static void launch_up_t(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const 
   const int3 nt3 = up_tiles<Tile>(F.L);
   const int G = level_blocks((long long)nt3.x * nt3.y * nt3.z);
   if (COARSE && F.c[0] && F.c[1] && F.c[2])
-    hipLaunchKernelGGL((k_mg_upsmooth<FINE, COARSE, true, Tile, T>), dim3(G), dim3(256), 0, g.stream, K, F, C, c, m,
-                       nt3);
+    launch_k(g, k_mg_upsmooth<FINE, COARSE, true, Tile, T>, dim3(G), dim3(256), K, F, C, c, m, nt3);
   else
-    hipLaunchKernelGGL((k_mg_upsmooth<FINE, COARSE, false, Tile, T>), dim3(G), dim3(256), 0, g.stream, K, F, C, c, m,
-                       nt3);
+    launch_k(g, k_mg_upsmooth<FINE, COARSE, false, Tile, T>, dim3(G), dim3(256), K, F, C, c, m, nt3);
 }
 
 template <bool FINE, bool COARSE, class T>
@@ -1018,11 +1016,11 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
     {
       TimedLaunch tl(g, UF_TK_MG_COARSE);
       if (g.mg_tail_lds)
-        hipLaunchKernelGGL(k_mg_tail<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K, (const MgLvl<T>*)g.mg_table, lt,
-                           nl, (const T*)g.mg_cinv, (const int*)c.flags, m);
+        launch_k(g, k_mg_tail<T>, dim3(1), dim3(kTailThreads), K, (const MgLvl<T>*)g.mg_table, lt, nl,
+                 (const T*)g.mg_cinv, (const int*)c.flags, m);
       else
-        hipLaunchKernelGGL(k_mg_tail_global<T>, dim3(1), dim3(kTailThreads), 0, g.stream, K,
-                           (const MgLvl<T>*)g.mg_table, lt, nl, (const T*)g.mg_cinv, (const int*)c.flags, m);
+        launch_k(g, k_mg_tail_global<T>, dim3(1), dim3(kTailThreads), K, (const MgLvl<T>*)g.mg_table, lt, nl,
+                 (const T*)g.mg_cinv, (const int*)c.flags, m);
     }
     for (int l = lt - 1; l >= 1; --l) {
       const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);

@@ -264,11 +264,11 @@ void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const 
   const dim3 grid = face_grid(P.L);
   {
     TimedLaunch tl(g, UF_TK_ADVECT_FWD);
-    hipLaunchKernelGGL(k_advect_fwd<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0], (const T*)Qin[1],
+    launch_k(g, k_advect_fwd<T>, grid, dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
                        (const T*)Qin[2], (T*)Qhat[0], (T*)Qhat[1], (T*)Qhat[2]);
   }
   TimedLaunch tl(g, UF_TK_ADVECT_CORR);
-  hipLaunchKernelGGL(k_advect_corr<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0], (const T*)Qin[1],
+  launch_k(g, k_advect_corr<T>, grid, dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
                      (const T*)Qin[2], (const T*)Qhat[0], (const T*)Qhat[1], (const T*)Qhat[2], (T*)Qout[0],
                      (T*)Qout[1], (T*)Qout[2]);
 }
@@ -276,21 +276,21 @@ void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const 
 template <class T>
 void launch_diffuse(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
   TimedLaunch tl(g, UF_TK_DIFFUSE);
-  hipLaunchKernelGGL(k_diffuse<T>, face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+  launch_k(g, k_diffuse<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)g.NUT, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
 }
 
 template <class T>
 void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
   TimedLaunch tl(g, UF_TK_DRAG);
-  hipLaunchKernelGGL(k_drag<T>, face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0], (const T*)Qin[1],
+  launch_k(g, k_drag<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
                      (const T*)Qin[2], (const T*)g.C, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
 }
 
 template <class T>
 void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
   TimedLaunch tl(g, UF_TK_PROJECT);
-  hipLaunchKernelGGL(k_project<T>, face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+  launch_k(g, k_project<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)g.X, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
 }
 

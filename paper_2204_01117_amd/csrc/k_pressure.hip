@@ -311,7 +311,7 @@ void launch_cg_start(Grid& g, const Params<T>& P, void* const Qs[3], const void*
   const CgCtl c = make_ctl(g);
   {
     TimedLaunch tl(g, UF_TK_CG_INIT);
-    hipLaunchKernelGGL(k_cg_init<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)Qs[0], (const T*)Qs[1],
+    launch_k(g, k_cg_init<T>, cl.grid, dim3(kCgBlock), P, (const T*)Qs[0], (const T*)Qs[1],
                      (const T*)Qs[2], (const T*)b, (const T*)g.X, (T*)resid(g, 0), c, cl.ilen);
   }
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, g.stream, c, g.cfg.cg_tol);
@@ -325,7 +325,7 @@ void launch_cg_precond(Grid& g, const Params<T>& P, int m) {
   }
   const CgLaunch cl = cg_launch(P.L);
   TimedLaunch tl(g, UF_TK_CG_PRECOND);
-  hipLaunchKernelGGL(k_cg_precond<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)resid(g, m), (T*)g.Z,
+  launch_k(g, k_cg_precond<T>, cl.grid, dim3(kCgBlock), P, (const T*)resid(g, m), (T*)g.Z,
                      make_ctl(g), m, g.cfg.precond, T(g.cfg.ai_omega), cl.ilen);
 }
 
@@ -337,12 +337,12 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
   void* Dnew = g.D[(t + 1) & 1];
   {
     TimedLaunch tl(g, UF_TK_CG_AD);
-    hipLaunchKernelGGL(k_cg_Ad<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)g.Z, (const T*)Dold, (T*)Dnew,
+    launch_k(g, k_cg_Ad<T>, cl.grid, dim3(kCgBlock), P, (const T*)g.Z, (const T*)Dold, (T*)Dnew,
                        (T*)g.Qv, (T*)g.X, c, t, cl.ilen);
   }
   {
     TimedLaunch tl(g, UF_TK_CG_AXPY);
-    hipLaunchKernelGGL(k_cg_axpy<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (T*)g.X, (const T*)resid(g, t),
+    launch_k(g, k_cg_axpy<T>, cl.grid, dim3(kCgBlock), P, (T*)g.X, (const T*)resid(g, t),
                        (T*)resid(g, t + 1), (const T*)Dnew, (const T*)g.Qv, c, t, cl.ilen);
   }
   launch_cg_precond<T>(g, P, t + 1);

@@ -21,17 +21,20 @@ template <class T> void launch_cell_fill(Grid& g, const Params<T>& P, void* q, d
 
 static const double kCmu = 0.09, kClim = 7.0 / 8.0;
 
-TimedLaunch::TimedLaunch(Grid& g_, int id_) : g(g_), id(id_), on(((g_.timer_mask >> id_) & 1u) != 0) {
-  if (!on) return;
-  if (2 * g.timer_used + 2 > g.timer_pool.size()) timer_flush(g);
-  UF_HIP_CHECK(hipEventRecord(g.timer_pool[2 * g.timer_used], g.stream));
-}
+TimedLaunch::TimedLaunch(Grid& g_, int id_) : g(g_), prev(g_.timer_cur) { g.timer_cur = id_; }
 
-TimedLaunch::~TimedLaunch() {
-  if (!on) return;
-  (void)hipEventRecord(g.timer_pool[2 * g.timer_used + 1], g.stream);
+TimedLaunch::~TimedLaunch() { g.timer_cur = prev; }
+
+bool timer_pair(Grid& g, hipEvent_t* e0, hipEvent_t* e1) {
+  const int id = g.timer_cur;
+  if (id < 0 || !((g.timer_mask >> id) & 1u)) return false;
+  if (2 * g.timer_used + 2 > g.timer_pool.size()) timer_flush(g);
+  *e0 = g.timer_pool[2 * g.timer_used];
+  *e1 = g.timer_pool[2 * g.timer_used + 1];
   g.timer_id[g.timer_used] = id;
   g.timer_used++;
+  g.timer_cur = -1;   // one launch per scope
+  return true;
 }
 
 // Wait for the recorded events and add their intervals to the totals.

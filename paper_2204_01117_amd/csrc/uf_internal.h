@@ -1,5 +1,6 @@
 // Host-side grid object and the launchers of the step kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -10,8 +11,8 @@
 
 namespace uf {
 
-// State of one pressure solve, kept in device memory and updated by the last
-// block of each CG kernel (deterministic FP64 reductions).
+// State of one pressure solve, kept in device memory and updated by block 0
+// of the CG kernels (deterministic FP64 reductions).
 struct CgState {
   double bb;         // ||b||^2
   double rr;         // ||r||^2 after the last update
@@ -92,6 +93,7 @@ struct Grid {
   std::vector<hipEvent_t> timer_pool;
   std::vector<int> timer_id;       // kernel of each recorded pair
   size_t timer_used = 0;           // pairs recorded since the last flush
+  int timer_cur = -1;              // timer id of the launch in the current TimedLaunch scope
   double timer_ms[UF_TK_COUNT] = {};
   long long timer_n[UF_TK_COUNT] = {};
   int k_in_valid = 1;
@@ -125,15 +127,23 @@ template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);
 void mg_free(Grid& g);
 
-// Brackets one kernel launch with timer events when that kernel is timed.
+// Marks the one kernel launched (through launch_k) in its scope as kernel
+// id of the timer.
 struct TimedLaunch {
   Grid& g;
-  int id;
-  bool on;
+  int prev;
   TimedLaunch(Grid& g_, int id_);
   ~TimedLaunch();
 };
 void timer_flush(Grid& g);
+// Start/stop events for the launch being made, when the kernel timer covers
+// it (the pair is then recorded for the next timer_flush); else false.
+bool timer_pair(Grid& g, hipEvent_t* e0, hipEvent_t* e1);
+
+// Launch on g.stream.  A timed launch carries its events in the dispatch
+// itself, so they time the kernel alone (no separate marker packets).
+template <typename... Args, typename... A>
+inline void launch_k(Grid& g, void (*kernel)(Args...), dim3 grid, dim3 block, A... args);
 
 size_t padded_bytes(const Grid& g);
 void set_error(const std::string& msg);
@@ -154,4 +164,11 @@ struct HipError {
   std::string msg;
   explicit HipError(std::string m) : msg(std::move(m)) {}
 };
+template <typename... Args, typename... A>
+inline void launch_k(Grid& g, void (*kernel)(Args...), dim3 grid, dim3 block, A... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)timer_pair(g, &e0, &e1);
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, g.stream, e0, e1, 0, static_cast<Args>(args)...);
+}
+
 }  // namespace uf
