@@ -11,9 +11,14 @@ constexpr int kCellBlock = 256;
 // Table 1 of the paper.
 constexpr double kCmu = 0.09, kAlpha = 0.52, kBeta = 0.0708, kSigma = 0.5, kSigmaStar = 0.6;
 
+__host__ __device__ inline int cell_gx(const Layout& L) { return (L.ny * L.nz + kCellBlock - 1) / kCellBlock; }
+
+// A thread owns cell (i, j, k); logical block (bx, i).
 #define UF_CELL_THREAD(L)                                            \
-  const int i = blockIdx.y;                                          \
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;               \
+  int c_bx, c_by;                                                    \
+  if (!xcd_block(cell_gx(L), (L).nx, c_bx, c_by)) return;            \
+  const int i = c_by;                                                \
+  const int p = c_bx * kCellBlock + threadIdx.x;                     \
   if (p >= (L).ny * (L).nz) return;                                  \
   const int j = p / (L).nz;                                          \
   const int k = p - j * (L).nz;
@@ -136,9 +141,7 @@ __global__ __launch_bounds__(kCellBlock) void k_check_range(const T* __restrict_
   if (bad) atomicOr(flag, 1);
 }
 
-static inline dim3 cell_grid(const Layout& L) {
-  return dim3((L.ny * L.nz + kCellBlock - 1) / kCellBlock, L.nx);
-}
+static inline dim3 cell_grid(const Layout& L) { return xcd_grid(cell_gx(L), L.nx); }
 
 template <class T>
 void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1,

@@ -443,6 +443,49 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
     __syncthreads();
     // t = om D^-1 r + P x_c over the box, 0 outside the level
     using WT = BoxWalk<HI, HJ, HK, 256>;
+    if constexpr (COARSE && HALF && WT::STEP == 1 && TI % 2 == 0) {
+      // Every axis halved and one thread per (jj, kk) column: the column's
+      // coarse values are interpolated in (j, k) once (cv, by coarse x
+      // index - cl0); a fine cell then takes its parent and x-neighbour
+      // from cv.  The tile origin i0 is even, so for the box entry ii the
+      // parent is cv[((ii - 1) >> 1) + 2] and the neighbour lies on the
+      // child's side (+1 for odd i, i.e. even ii).
+      WT::run([&](int jj, int kk, int) {
+        const int j = j0 - 1 + jj, k = k0 - 1 + kk;
+        const bool in_jk = (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz;
+        const int cyz = (bclass(j, L.ny) << 2) | bclass(k, L.nz);
+        const Tap2<T> b = ptap(j, 1, C.L.ny, K.sgn[2], K.sgn[3]);
+        const Tap2<T> e = ptap(k, 1, C.L.nz, K.sgn[4], K.sgn[5]);
+        const int r0 = (b.i0 - cl1) * XK, r1 = (b.i1 - cl1) * XK;
+        const int q0 = e.i0 - cl2, q1 = e.i1 - cl2;
+        T cv[XI];
+#pragma clang loop unroll(full)
+        for (int I = 1; I <= 6; ++I) {
+          const T* sp = sx + I * XJ * XK;
+          cv[I] = b.w0 * (e.w0 * sp[r0 + q0] + e.w1 * sp[r0 + q1]) + b.w1 * (e.w0 * sp[r1 + q0] + e.w1 * sp[r1 + q1]);
+        }
+#pragma clang loop unroll(full)
+        for (int ii = 0; ii < HI; ++ii) {
+          const int i = i0 - 1 + ii;
+          const int Ir = ((ii - 1) >> 1) + 2;
+          const int Jr = (ii % 2 == 0) ? Ir + 1 : Ir - 1;
+          const int J = cl0 + Jr;   // neighbour's coarse x index
+          T w0 = T(0.75), w1 = T(0.25);
+          if (J < 0) {
+            w0 = T(0.75) + T(0.25) * K.sgn[0];
+            w1 = T(0);
+          } else if (J >= C.L.nx) {
+            w0 = T(0.75) + T(0.25) * K.sgn[1];
+            w1 = T(0);
+          }
+          const int idx = (ii * HJ + jj) * HK + kk;
+          T v = T(0);
+          if (in_jk && (unsigned)i < (unsigned)L.nx)
+            v = tab_omd[(bclass(i, L.nx) << 4) | cyz] * sr[idx] + w0 * cv[Ir] + w1 * cv[Jr];
+          st[idx] = v;
+        }
+      });
+    } else
     WT::run([&](int jj, int kk, int g) {
       const int j = j0 - 1 + jj, k = k0 - 1 + kk;
       const bool in_jk = (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz;
@@ -497,7 +540,7 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
   }
   if (FINE) {
     const int slots[1] = {S_RZ0 + (m & 1)};
-    write_partials<1>(acc, c.part, c.stride, slots);
+    write_partials<1>(acc, c.part, c.stride, slots, (int)blockIdx.x);
   }
 }
 

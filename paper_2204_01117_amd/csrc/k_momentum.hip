@@ -81,41 +81,47 @@ __device__ __forceinline__ T sample(const Layout& L, const T* __restrict__ q, T 
   return nan_pos ? fi + fj + fk : val;
 }
 
+__host__ __device__ inline int face_gx(const Layout& L) { return ((L.ny + 1) * (L.nz + 1) + kFaceBlock - 1) / kFaceBlock; }
+
+// A thread owns the three faces at corner (i, j, k); logical block (bx, i).
 #define UF_FACE_THREAD(L)                                            \
-  const int i = blockIdx.y;                                          \
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;               \
+  int f_bx, f_by;                                                    \
+  if (!xcd_block(face_gx(L), (L).nx + 1, f_bx, f_by)) return;        \
+  const int i = f_by;                                                \
+  const int p = f_bx * kFaceBlock + threadIdx.x;                     \
   if (p >= ((L).ny + 1) * ((L).nz + 1)) return;                      \
   const int j = p / ((L).nz + 1);                                    \
   const int k = p - j * ((L).nz + 1);
 
+// Each kernel computes the values of the thread's three faces first, with
+// every load unconditional (all positions read lie in the padded arrays,
+// ghosts included), and only then stores the faces the thread owns; fixed
+// boundary normal faces get their Dirichlet value.  Independent loads of
+// the three components are then in flight together.
+template <int C, class T>
+__device__ __forceinline__ void finish_face(const Params<T>& P, T* __restrict__ out, int i, int j, int k, T v) {
+  if (!owns_face<C, T>(P.L, i, j, k)) return;
+  T val;
+  if (face_dirichlet<C>(P, i, j, k, &val)) v = val;
+  store_face<C>(out, P, i, j, k, v);
+}
+
 // ------------------------------------------------------------- advection --
 template <int C, class T>
-__device__ __forceinline__ void advect_fwd_face(const Params<T>& P, const T* U, const T* V, const T* W,
-                                                T* __restrict__ out, int i, int j, int k) {
-  T val;
-  if (face_dirichlet<C>(P, i, j, k, &val)) {
-    store_face<C>(out, P, i, j, k, val);
-    return;
-  }
-  const long long o = P.L.at(i, j, k);
+__device__ __forceinline__ T advect_fwd_value(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                              const T* __restrict__ W, long long o, int i, int j, int k) {
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
   T mn, mx;
-  const T qh = sample<C, false>(P.L, q, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1],
-                                T(k) - vel[2] * P.dth[2], &mn, &mx);
-  store_face<C>(out, P, i, j, k, qh);
+  return sample<C, false>(P.L, q, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], &mn,
+                          &mx);
 }
 
 template <int C, class T>
-__device__ __forceinline__ void advect_corr_face(const Params<T>& P, const T* U, const T* V, const T* W,
-                                                 const T* __restrict__ qhat, T* __restrict__ out, int i, int j, int k) {
-  T val;
-  if (face_dirichlet<C>(P, i, j, k, &val)) {
-    store_face<C>(out, P, i, j, k, val);
-    return;
-  }
-  const long long o = P.L.at(i, j, k);
+__device__ __forceinline__ T advect_corr_value(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                               const T* __restrict__ W, const T* __restrict__ qhat, long long o, int i,
+                                               int j, int k) {
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
@@ -125,9 +131,8 @@ __device__ __forceinline__ void advect_corr_face(const Params<T>& P, const T* U,
   const T qh = sample<C, true>(P.L, q, T(i) - di, T(j) - dj, T(k) - dk, &mn, &mx);
   T d0, d1;
   const T qc = sample<C, false>(P.L, qhat, T(i) + di, T(j) + dj, T(k) + dk, &d0, &d1);
-  T qt = qh + T(0.5) * (q[o] - qc);
-  qt = nmin(nmax(qt, mn), mx);
-  store_face<C>(out, P, i, j, k, qt);
+  const T qt = qh + T(0.5) * (q[o] - qc);
+  return nmin(nmax(qt, mn), mx);
 }
 
 template <class T>
@@ -135,9 +140,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_fwd(Params<T> P, const T*
                                                            const T* __restrict__ W, T* __restrict__ Uh,
                                                            T* __restrict__ Vh, T* __restrict__ Wh) {
   UF_FACE_THREAD(P.L);
-  if (owns_face<0, T>(P.L, i, j, k)) advect_fwd_face<0>(P, U, V, W, Uh, i, j, k);
-  if (owns_face<1, T>(P.L, i, j, k)) advect_fwd_face<1>(P, U, V, W, Vh, i, j, k);
-  if (owns_face<2, T>(P.L, i, j, k)) advect_fwd_face<2>(P, U, V, W, Wh, i, j, k);
+  const long long o = P.L.at(i, j, k);
+  const T a0 = advect_fwd_value<0>(P, U, V, W, o, i, j, k);
+  const T a1 = advect_fwd_value<1>(P, U, V, W, o, i, j, k);
+  const T a2 = advect_fwd_value<2>(P, U, V, W, o, i, j, k);
+  finish_face<0>(P, Uh, i, j, k, a0);
+  finish_face<1>(P, Vh, i, j, k, a1);
+  finish_face<2>(P, Wh, i, j, k, a2);
 }
 
 template <class T>
@@ -146,28 +155,26 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_corr(Params<T> P, const T
                                                             const T* __restrict__ Vh, const T* __restrict__ Wh,
                                                             T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
   UF_FACE_THREAD(P.L);
-  if (owns_face<0, T>(P.L, i, j, k)) advect_corr_face<0>(P, U, V, W, Uh, Uo, i, j, k);
-  if (owns_face<1, T>(P.L, i, j, k)) advect_corr_face<1>(P, U, V, W, Vh, Vo, i, j, k);
-  if (owns_face<2, T>(P.L, i, j, k)) advect_corr_face<2>(P, U, V, W, Wh, Wo, i, j, k);
+  const long long o = P.L.at(i, j, k);
+  const T a0 = advect_corr_value<0>(P, U, V, W, Uh, o, i, j, k);
+  const T a1 = advect_corr_value<1>(P, U, V, W, Vh, o, i, j, k);
+  const T a2 = advect_corr_value<2>(P, U, V, W, Wh, o, i, j, k);
+  finish_face<0>(P, Uo, i, j, k, a0);
+  finish_face<1>(P, Vo, i, j, k, a1);
+  finish_face<2>(P, Wo, i, j, k, a2);
 }
 
 // ------------------------------------------------------------- diffusion --
 template <int C, class T>
-__device__ __forceinline__ void diffuse_face(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ nut,
-                                             T* __restrict__ out, int i, int j, int k) {
-  T val;
-  if (face_dirichlet<C>(P, i, j, k, &val)) {
-    store_face<C>(out, P, i, j, k, val);
-    return;
-  }
+__device__ __forceinline__ T diffuse_value(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ nut,
+                                           long long o) {
   const Layout& L = P.L;
-  const long long o = L.at(i, j, k);
   const T qc = q[o];
   const T lap = (q[o + L.SX] - T(2) * qc + q[o - L.SX]) * P.ih2[0] +
                 (q[o + L.PZ] - T(2) * qc + q[o - L.PZ]) * P.ih2[1] +
                 (q[o + 1] - T(2) * qc + q[o - 1]) * P.ih2[2];
   const T nuf = P.nu + T(0.5) * (nut[o - stride<C>(L)] + nut[o]);
-  store_face<C>(out, P, i, j, k, qc + P.dt * nuf * lap);
+  return qc + P.dt * nuf * lap;
 }
 
 template <class T>
@@ -175,27 +182,25 @@ __global__ __launch_bounds__(kFaceBlock) void k_diffuse(Params<T> P, const T* __
                                                         const T* __restrict__ W, const T* __restrict__ NUT,
                                                         T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
   UF_FACE_THREAD(P.L);
-  if (owns_face<0, T>(P.L, i, j, k)) diffuse_face<0>(P, U, NUT, Uo, i, j, k);
-  if (owns_face<1, T>(P.L, i, j, k)) diffuse_face<1>(P, V, NUT, Vo, i, j, k);
-  if (owns_face<2, T>(P.L, i, j, k)) diffuse_face<2>(P, W, NUT, Wo, i, j, k);
+  const long long o = P.L.at(i, j, k);
+  const T a0 = diffuse_value<0>(P, U, NUT, o);
+  const T a1 = diffuse_value<1>(P, V, NUT, o);
+  const T a2 = diffuse_value<2>(P, W, NUT, o);
+  finish_face<0>(P, Uo, i, j, k, a0);
+  finish_face<1>(P, Vo, i, j, k, a1);
+  finish_face<2>(P, Wo, i, j, k, a2);
 }
 
 // ------------------------------------------------------------ porosity drag
 template <int C, class T>
-__device__ __forceinline__ void drag_face(const Params<T>& P, const T* U, const T* V, const T* W,
-                                          const T* __restrict__ Cc, T* __restrict__ out, int i, int j, int k) {
-  T val;
-  if (face_dirichlet<C>(P, i, j, k, &val)) {
-    store_face<C>(out, P, i, j, k, val);
-    return;
-  }
-  const long long o = P.L.at(i, j, k);
+__device__ __forceinline__ T drag_value(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                        const T* __restrict__ W, const T* __restrict__ Cc, long long o) {
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T speed = sqrt(vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]);
   const T cf = T(0.5) * (Cc[o - stride<C>(P.L)] + Cc[o]);
   const T fac = nmax(T(0), T(1) - P.dt * cf * speed);
-  store_face<C>(out, P, i, j, k, fac * vel[C]);
+  return fac * vel[C];
 }
 
 template <class T>
@@ -203,23 +208,21 @@ __global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __res
                                                      const T* __restrict__ W, const T* __restrict__ Cc,
                                                      T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
   UF_FACE_THREAD(P.L);
-  if (owns_face<0, T>(P.L, i, j, k)) drag_face<0>(P, U, V, W, Cc, Uo, i, j, k);
-  if (owns_face<1, T>(P.L, i, j, k)) drag_face<1>(P, U, V, W, Cc, Vo, i, j, k);
-  if (owns_face<2, T>(P.L, i, j, k)) drag_face<2>(P, U, V, W, Cc, Wo, i, j, k);
+  const long long o = P.L.at(i, j, k);
+  const T a0 = drag_value<0>(P, U, V, W, Cc, o);
+  const T a1 = drag_value<1>(P, U, V, W, Cc, o);
+  const T a2 = drag_value<2>(P, U, V, W, Cc, o);
+  finish_face<0>(P, Uo, i, j, k, a0);
+  finish_face<1>(P, Vo, i, j, k, a1);
+  finish_face<2>(P, Wo, i, j, k, a2);
 }
 
 // ------------------------------------------------ projection (velocity part)
 template <int C, class T>
-__device__ __forceinline__ void project_face(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ p,
-                                             T* __restrict__ out, int i, int j, int k) {
-  T val;
-  if (face_dirichlet<C>(P, i, j, k, &val)) {
-    store_face<C>(out, P, i, j, k, val);
-    return;
-  }
-  const long long o = P.L.at(i, j, k);
+__device__ __forceinline__ T project_value(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ p,
+                                           long long o) {
   const T grad = (p[o] - p[o - stride<C>(P.L)]) * P.ih[C];
-  store_face<C>(out, P, i, j, k, q[o] - P.dt_rho * grad);
+  return q[o] - P.dt_rho * grad;
 }
 
 template <class T>
@@ -227,9 +230,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __
                                                         const T* __restrict__ W, const T* __restrict__ Pp,
                                                         T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
   UF_FACE_THREAD(P.L);
-  if (owns_face<0, T>(P.L, i, j, k)) project_face<0>(P, U, Pp, Uo, i, j, k);
-  if (owns_face<1, T>(P.L, i, j, k)) project_face<1>(P, V, Pp, Vo, i, j, k);
-  if (owns_face<2, T>(P.L, i, j, k)) project_face<2>(P, W, Pp, Wo, i, j, k);
+  const long long o = P.L.at(i, j, k);
+  const T a0 = project_value<0>(P, U, Pp, o);
+  const T a1 = project_value<1>(P, V, Pp, o);
+  const T a2 = project_value<2>(P, W, Pp, o);
+  finish_face<0>(P, Uo, i, j, k, a0);
+  finish_face<1>(P, Vo, i, j, k, a1);
+  finish_face<2>(P, Wo, i, j, k, a2);
 }
 
 // ------------------------------------------------ boundary refresh (in place)
@@ -254,10 +261,7 @@ __global__ __launch_bounds__(kFaceBlock) void k_face_init(Params<T> P, T* __rest
 }
 
 // ----------------------------------------------------------------- launchers
-static inline dim3 face_grid(const Layout& L) {
-  const int plane = (L.ny + 1) * (L.nz + 1);
-  return dim3((plane + kFaceBlock - 1) / kFaceBlock, L.nx + 1);
-}
+static inline dim3 face_grid(const Layout& L) { return xcd_grid(face_gx(L), L.nx + 1); }
 
 template <class T>
 void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Qout[3]) {

@@ -18,11 +18,15 @@ namespace uf {
 constexpr int kCgBlock = 512;
 
 #define UF_CG_RANGE(L, ilen)                                                 \
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;                       \
+  const int cg_gx = ((L).ny * (L).nz + kCgBlock - 1) / kCgBlock;             \
+  int cg_bx, cg_by;                                                          \
+  if (!xcd_block(cg_gx, ((L).nx + (ilen) - 1) / (ilen), cg_bx, cg_by)) return; \
+  const int cg_bid = cg_by * cg_gx + cg_bx;                                  \
+  const int p = cg_bx * kCgBlock + threadIdx.x;                              \
   const bool active = p < (L).ny * (L).nz;                                   \
   const int j = active ? p / (L).nz : 0;                                     \
   const int k = active ? p - j * (L).nz : 0;                                 \
-  const int i0 = blockIdx.y * (ilen);                                        \
+  const int i0 = cg_by * (ilen);                                             \
   const int i1 = active ? min((L).nx, i0 + (ilen)) : i0;
 
 // First-order approximate inverse (Sec. 3): M^-1 = K^T K with
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_init(Params<T> P, const T* __re
     }
   }
   const int slots[2] = {S_BB, S_RR};
-  write_partials<2>(v, c.part, c.stride, slots);
+  write_partials<2>(v, c.part, c.stride, slots, cg_bid);
 }
 
 // One block: ||b||, the stopping threshold and whether x0 already solves.
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_precond(Params<T> P, const T* _
                                                          CgCtl c, int m, int pc, T om, int ilen) {
   const Layout& L = P.L;
   const bool skip = precond_skip(c, m);
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) c.flags[m] = skip;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[m] = skip;
   if (skip) return;
   UF_CG_RANGE(L, ilen);
   double v[1] = {0.0};
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_precond(Params<T> P, const T* _
     v[0] += (double)R[o] * (double)z;
   }
   const int slots[1] = {S_RZ0 + (m & 1)};
-  write_partials<1>(v, c.part, c.stride, slots);
+  write_partials<1>(v, c.part, c.stride, slots, cg_bid);
 }
 
 // d = z + beta d_old; q = A d; partials of d.q.  Marches along x with the
@@ -161,33 +165,48 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __rest
     return;
   }
   if (!iteration_open(c, t)) return;
+  const bool first = t == 0;
+  const long long SX = L.SX, PZ = L.PZ;
+  const bool work = i0 < i1;
+  const bool pass0 = i0 + 4 <= i1;
+  long long o = work ? L.at(i0, j, k) : 0;
+  // Raw z and d_old of the first pass (cells i0 .. i0+3, their x-neighbours
+  // and their y/z-neighbours) are loaded before beta is known, so that the
+  // sum of the r.z partials overlaps those loads.  Entry p: 0 = i0-1,
+  // 1..5 = i0..i0+4, then four groups of four (+y, -y, +z, -z).
+  const int sx = (int)SX, pz = (int)PZ;   // a plane of the padded layout is far below 2^31 elements
+  auto off = [&](int p) -> int {
+    if (p == 0) return -sx;
+    if (p < 6) return (p - 1) * sx;
+    const int u = (p - 6) & 3, g = (p - 6) >> 2;
+    return u * sx + (g == 0 ? pz : (g == 1 ? -pz : (g == 2 ? 1 : -1)));
+  };
+  T zr[22], dr[22];
+  const T* __restrict__ zo = Z + o;
+  const T* __restrict__ d0 = Dold + o;
+#pragma unroll
+  for (int p = 0; p < 22; ++p) {
+    zr[p] = T(0);
+    dr[p] = T(0);
+    if (work && (p < 2 || pass0)) {
+      zr[p] = zo[off(p)];
+      if (!first) dr[p] = d0[off(p)];
+    }
+  }
   const double rz = rz_of(c, t);
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) c.st->rzh[t & 1] = rz;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c.st->rzh[t & 1] = rz;
   if (!rz_allows(c, rz)) return;
   // r.z of iteration t - 1 was published by this kernel's previous launch
-  const T beta = t == 0 ? T(0) : (T)(rz / c.st->rzh[(t + 1) & 1]);
+  const T beta = first ? T(0) : (T)(rz / c.st->rzh[(t + 1) & 1]);
   double v[1] = {0.0};
-  if (i0 < i1) {
-    const bool first = t == 0;
+  if (work) {
     auto dn = [&](long long q) { return first ? Z[q] : Z[q] + beta * Dold[q]; };
+    auto dv = [&](int p) { return first ? zr[p] : zr[p] + beta * dr[p]; };
     const T dyz = diag_yz(P, j, k);
-    const long long SX = L.SX, PZ = L.PZ;
-    long long o = L.at(i0, j, k);
-    T dm = dn(o - SX), dc = dn(o);
+    T dm = dv(0), dc = dv(1);
     int i = i0;
     // four cells per pass so that each wave keeps four cells' loads in flight
-    for (; i + 4 <= i1; i += 4, o += 4 * SX) {
-      T d[5];
-      d[0] = dc;
-#pragma unroll
-      for (int u = 1; u <= 4; ++u) d[u] = dn(o + u * SX);
-      T lat_y[4], lat_z[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const long long q = o + u * SX;
-        lat_y[u] = dn(q + PZ) + dn(q - PZ);
-        lat_z[u] = dn(q + 1) + dn(q - 1);
-      }
+    auto pass = [&](const T (&d)[5], const T (&lat_y)[4], const T (&lat_z)[4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const T prev = u == 0 ? dm : d[u - 1];
@@ -199,6 +218,32 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __rest
       }
       dm = d[3];
       dc = d[4];
+      i += 4;
+      o += 4 * SX;
+    };
+    if (pass0) {
+      T d[5], lat_y[4], lat_z[4];
+#pragma unroll
+      for (int u = 0; u < 5; ++u) d[u] = dv(1 + u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        lat_y[u] = dv(6 + u) + dv(10 + u);
+        lat_z[u] = dv(14 + u) + dv(18 + u);
+      }
+      pass(d, lat_y, lat_z);
+    }
+    while (i + 4 <= i1) {
+      T d[5], lat_y[4], lat_z[4];
+      d[0] = dc;
+#pragma unroll
+      for (int u = 1; u <= 4; ++u) d[u] = dn(o + u * SX);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long q = o + u * SX;
+        lat_y[u] = dn(q + PZ) + dn(q - PZ);
+        lat_z[u] = dn(q + 1) + dn(q - 1);
+      }
+      pass(d, lat_y, lat_z);
     }
     for (; i < i1; ++i, o += SX) {
       const T dp = dn(o + SX);
@@ -212,7 +257,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __rest
     }
   }
   const int slots[1] = {S_DQ};
-  write_partials<1>(v, c.part, c.stride, slots);
+  write_partials<1>(v, c.part, c.stride, slots, cg_bid);
 }
 
 // x += alpha d; r -= alpha q; partials of ||r||^2.
@@ -231,7 +276,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
     dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb);
     run = dq > 0.0 && isfinite(dq);
   }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     c.exec[t] = run;
     if (run) c.st->iter = t + 1;
   }
@@ -248,7 +293,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
     v[0] += (double)r * (double)r;
   }
   const int slots[1] = {S_RR};
-  write_partials<1>(v, c.part, c.stride, slots);
+  write_partials<1>(v, c.part, c.stride, slots, cg_bid);
 }
 
 // One block, after a chunk of iterations ending at t_end: publish the
@@ -288,7 +333,7 @@ CgLaunch cg_launch(const Layout& L) {
   if (nchunk < 1) nchunk = 1;
   const int ilen = (L.nx + nchunk - 1) / nchunk;
   const int gy = (L.nx + ilen - 1) / ilen;
-  return CgLaunch{dim3(bp, gy), ilen};
+  return CgLaunch{xcd_grid(bp, gy), ilen, bp, gy};
 }
 
 CgCtl make_ctl(Grid& g) {

@@ -49,13 +49,12 @@ __device__ __forceinline__ double slot_sum(const double* __restrict__ part, int 
 }
 
 // Write the block's partial sums of NV values into their slots (slot s
-// starts at part + s * stride; block index over a 1-, 2- or 3-D grid).
+// starts at part + s * stride; bid = the block's logical index).
 template <int NV>
 __device__ __forceinline__ void write_partials(double (&v)[NV], double* __restrict__ part, int stride,
-                                               const int slot[NV]) {
+                                               const int slot[NV], int bid) {
   block_sum<NV>(v);
   if (threadIdx.x == 0) {
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 #pragma unroll
     for (int m = 0; m < NV; ++m) part[(size_t)slot[m] * stride + bid] = v[m];
   }

@@ -433,7 +433,7 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     g->PHI = dalloc((size_t)cfg->nx * cfg->ny * cfg->nz * g->esize);
     g->inflow = dalloc(2 * (cfg->nz + 2) * g->esize);
     const CgLaunch cl = cg_launch(L);
-    g->cg_nb = (size_t)cl.grid.x * cl.grid.y;
+    g->cg_nb = (size_t)cl.gx * cl.gy;
     g->cg_nb_rz = cfg->precond == UF_PC_MG ? mg_fine_blocks(L) : g->cg_nb;
     g->part_stride = std::max(g->cg_nb, g->cg_nb_rz);
     g->partials = (double*)dalloc(S_NSLOT_HOST * g->part_stride * sizeof(double));

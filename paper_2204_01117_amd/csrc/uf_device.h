@@ -101,24 +101,33 @@ __device__ __forceinline__ bool face_dirichlet(const Params<T>& P, int i, int j,
 }
 
 // Store the value of interior face (i,j,k) of component C and every ghost
-// derived from it.
+// derived from it.  Ghosts across one side are written straight-line (the
+// common case: faces next to one domain side); ghosts across an edge or a
+// corner compose the side rules x, then y, then z.
 template <int C, class T>
 __device__ __forceinline__ void store_face(T* __restrict__ q, const Params<T>& P, int i, int j, int k, T v) {
   const Layout& L = P.L;
-  q[L.at(i, j, k)] = v;
+  const long long o = L.at(i, j, k);
+  q[o] = v;
   int ext[3];
   face_ext<C>(L, ext);
   const bool lo0 = i == 0, hi0 = i == ext[0] - 1;
   const bool lo1 = j == 0, hi1 = j == ext[1] - 1;
   const bool lo2 = k == 0, hi2 = k == ext[2] - 1;
-  if (!(lo0 | hi0 | lo1 | hi1 | lo2 | hi2)) return;
+  if (lo2) q[o - 1] = face_rule(P, C, 2, 0, v, k - 1);
+  if (hi2) q[o + 1] = face_rule(P, C, 2, 1, v, k + 1);
+  if (lo1) q[o - L.PZ] = face_rule(P, C, 1, 0, v, k);
+  if (hi1) q[o + L.PZ] = face_rule(P, C, 1, 1, v, k);
+  if (lo0) q[o - L.SX] = face_rule(P, C, 0, 0, v, k);
+  if (hi0) q[o + L.SX] = face_rule(P, C, 0, 1, v, k);
+  if (int(lo0 | hi0) + int(lo1 | hi1) + int(lo2 | hi2) < 2) return;
   for (int ox = -1; ox <= 1; ++ox) {
     if ((ox == -1 && !lo0) || (ox == 1 && !hi0)) continue;
     for (int oy = -1; oy <= 1; ++oy) {
       if ((oy == -1 && !lo1) || (oy == 1 && !hi1)) continue;
       for (int oz = -1; oz <= 1; ++oz) {
         if ((oz == -1 && !lo2) || (oz == 1 && !hi2)) continue;
-        if ((ox | oy | oz) == 0) continue;
+        if (int(ox != 0) + int(oy != 0) + int(oz != 0) < 2) continue;
         T g = v;
         if (ox) g = face_rule(P, C, 0, ox > 0, g, k);
         if (oy) g = face_rule(P, C, 1, oy > 0, g, k);
@@ -193,40 +202,23 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
   }
 }
 
-// Grid-wide deterministic sum: each block publishes its partial sums; the
-// last block to arrive adds the partials in block order and returns true
-// (totals in thread 0's v).  counter must be zero on entry and is reset.
-template <int NV>
-__device__ __forceinline__ bool grid_sum(double (&v)[NV], double* partials, unsigned* counter) {
-  __shared__ int is_last;
-  const unsigned nb = gridDim.x * gridDim.y;
-  const unsigned bid = blockIdx.y * gridDim.x + blockIdx.x;
-  block_sum<NV>(v);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int m = 0; m < NV; ++m) partials[(size_t)m * nb + bid] = v[m];
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == nb - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  double acc[NV];
-#pragma unroll
-  for (int m = 0; m < NV; ++m) acc[m] = 0.0;
-  for (unsigned b = threadIdx.x; b < nb; b += blockDim.x) {
-#pragma unroll
-    for (int m = 0; m < NV; ++m)
-      acc[m] += __hip_atomic_load(&partials[(size_t)m * nb + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  block_sum<NV>(acc);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-    for (int m = 0; m < NV; ++m) v[m] = acc[m];
-  }
+// Launch shape of the stencil kernels: a logical gx x gy grid of blocks (bx
+// fastest) launched as a 1-D grid of 8 * ceil(gx gy / 8) blocks.  Workgroups
+// are dealt to the 8 XCDs round-robin; remapped this way each XCD takes one
+// contiguous range of the logical order, so blocks whose halos overlap (the
+// neighbouring x-planes) share that XCD's L2.  False for padding blocks.
+__device__ __forceinline__ bool xcd_block(int gx, int gy, int& bx, int& by) {
+  const int per = (int)(gridDim.x >> 3);
+  const int b = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (b >= gx * gy) return false;
+  by = b / gx;
+  bx = b - by * gx;
   return true;
+}
+
+inline dim3 xcd_grid(int gx, int gy) {
+  const long long n = (long long)gx * gy;
+  return dim3((unsigned)(8 * ((n + 7) / 8)));
 }
 
 }  // namespace uf

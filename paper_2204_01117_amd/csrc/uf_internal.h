@@ -39,8 +39,9 @@ struct MgLevel {
 };
 
 struct CgLaunch {
-  dim3 grid;
-  int ilen;
+  dim3 grid;   // 1-D launch of the logical gx x gy blocks (see xcd_block)
+  int ilen;    // x-planes marched by each block
+  int gx, gy;
 };
 
 struct Grid {
