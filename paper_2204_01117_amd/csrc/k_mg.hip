@@ -344,13 +344,14 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
   __shared__ T se[QI * QJ * QK];
   __shared__ T tab_omd[64];
   __shared__ T tab_a[64];
+  // mode 0: the flag is loaded now and tested once the first box is staged,
+  // so that its latency overlaps the box loads
+  const int skip = mode == 0 ? c.flags[m] : 0;
   if (mode == 1) {
     if (blockIdx.x == 0) {
-      const bool skip = precond_skip(c, m);
-      if (threadIdx.x == 0) c.flags[m] = skip;
+      const bool done = precond_skip(c, m);
+      if (threadIdx.x == 0) c.flags[m] = done;
     }
-  } else if (mode == 0) {
-    if (c.flags[m]) return;
   }
   if (!has_coarse) return;
   if (threadIdx.x < 64) {
@@ -371,6 +372,7 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
     stage_box<QI, QJ, QK, 256>(se, F.r, L, lo0 - 1, lo1 - 1, lo2 - 1, [&](int ii, int jj, int kk) {
       return tab_omd[cls3(L, lo0 - 1 + ii, lo1 - 1 + jj, lo2 - 1 + kk)];
     });
+    if (skip) return;   // the solve has finished (uniform over the grid)
     __syncthreads();
     // residual over the footprint; entries outside the level are never
     // restricted from
@@ -391,10 +393,41 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
     __syncthreads();
     const int tk = threadIdx.x % Rt::CK, tj = (threadIdx.x / Rt::CK) % Rt::CJ, ti = threadIdx.x / (Rt::CK * Rt::CJ);
     const int I = X0 + ti, J = Y0 + tj, Kc = Z0 + tk;
-    if (ti < Rt::CI && inside(C.L, I, J, Kc))
-      C.r[C.L.at(I, J, Kc)] = restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) {
-        return sres[((i - lo0) * EJ + (j - lo1)) * EK + (k - lo2)];
-      });
+    if (ti < Rt::CI && inside(C.L, I, J, Kc)) {
+      T out;
+      if (F.c[0] && F.c[1] && F.c[2]) {
+        // every axis halved: the 4 x 4 x 4 fine taps of (I, J, Kc) start at
+        // box entry (2 ti, 2 tj, 2 tk); taps past the level have weight 0
+        // (their box entries hold finite values)
+        T wi[4], wj[4], wk[4];
+        auto wts = [&](int X, int nc, int nf, T slo, T shi, T (&w)[4]) {
+          w[0] = 2 * X - 1 >= 0 ? T(0.125) : T(0);
+          w[1] = T(0.5) * (T(0.75) + (X == 0 ? T(0.25) * slo : T(0)));
+          w[2] = T(0.5) * (T(0.75) + (X == nc - 1 ? T(0.25) * shi : T(0)));
+          w[3] = 2 * X + 2 < nf ? T(0.125) : T(0);
+        };
+        wts(I, C.L.nx, L.nx, K.sgn[0], K.sgn[1], wi);
+        wts(J, C.L.ny, L.ny, K.sgn[2], K.sgn[3], wj);
+        wts(Kc, C.L.nz, L.nz, K.sgn[4], K.sgn[5], wk);
+        const T* base = sres + ((2 * ti) * EJ + 2 * tj) * EK + 2 * tk;
+        out = T(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          T sa = T(0);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const T* row = base + (a * EJ + b) * EK;
+            sa += wj[b] * (wk[0] * row[0] + wk[1] * row[1] + wk[2] * row[2] + wk[3] * row[3]);
+          }
+          out += wi[a] * sa;
+        }
+      } else {
+        out = restrict_at(K, F, C, I, J, Kc, [&](int i, int j, int k) {
+          return sres[((i - lo0) * EJ + (j - lo1)) * EK + (k - lo2)];
+        });
+      }
+      C.r[C.L.at(I, J, Kc)] = out;
+    }
   }
 }
 
@@ -425,7 +458,7 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
   __shared__ T sx[COARSE ? XI * XJ * XK : 1];
   __shared__ T tab_d[64];
   __shared__ T tab_omd[64];
-  if (c.flags[m]) return;
+  const int skip = c.flags[m];   // tested once the first boxes are staged
   fill_class_tables<T>(K, F, tab_d, tab_omd);
   const Layout& L = F.L;
   const int3 tt = make_int3(TI, TJ, TK);
@@ -440,6 +473,7 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
     __syncthreads();   // the previous tile is done with the LDS; tables are in place
     stage_box<HI, HJ, HK, 256>(sr, F.r, L, i0 - 1, j0 - 1, k0 - 1, one);
     if (COARSE) stage_box<XI, XJ, XK, 256>(sx, C.x, C.L, cl0, cl1, cl2, one);
+    if (skip) return;   // the solve has finished (uniform over the grid)
     __syncthreads();
     // t = om D^-1 r + P x_c over the box, 0 outside the level
     using WT = BoxWalk<HI, HJ, HK, 256>;
@@ -538,7 +572,7 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
       }
     });
   }
-  if (FINE) {
+  if (FINE && !skip) {
     const int slots[1] = {S_RZ0 + (m & 1)};
     write_partials<1>(acc, c.part, c.stride, slots, (int)blockIdx.x);
   }
@@ -556,7 +590,7 @@ template <class T>
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const MgLvl<T>* __restrict__ lv, int lt,
                                                           int nl, const T* __restrict__ cinv,
                                                           const int* __restrict__ flags, int m) {
-  if (flags[m]) return;
+  const int skip = flags[m];   // tested once level lt is staged
   __shared__ T pr[kTailPool];
   __shared__ T px[kTailPool];
   __shared__ T pt[kTailPool];
@@ -588,6 +622,7 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const M
       pr[idx] = F.r[F.L.at(i, j, k)];
     }
   }
+  if (skip) return;
   __syncthreads();
   for (int l = lt; l < nl - 1; ++l) {
     const MgLvl<T> F = lv[l];

@@ -151,121 +151,138 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_precond(Params<T> P, const T* _
   write_partials<1>(v, c.part, c.stride, slots, cg_bid);
 }
 
-// d = z + beta d_old; q = A d; partials of d.q.  Marches along x with the
-// x-neighbours of d in registers.
-template <class T>
-__global__ __launch_bounds__(kCgBlock) void k_cg_Ad(Params<T> P, const T* __restrict__ Z, const T* __restrict__ Dold,
-                                                    T* __restrict__ Dnew, T* __restrict__ Qv, T* __restrict__ X,
-                                                    CgCtl c, int t, int ilen) {
+// d = z + beta d_old; q = A d; partials of d.q.
+//
+// A block owns a JT x KT tile of (j, k) columns (KT = z extent of the tile,
+// JT = 512 / KT) and marches its x-range in passes of four planes.  Each
+// thread loads z and d_old of its own column and, at the tile's edge, of the
+// halo cell beside it; d of the pass's four planes is staged in LDS, so the
+// y and z neighbours come from LDS (about 2.5 global loads per cell instead
+// of 10) and the x neighbours stay in registers.  The next pass's loads are
+// issued before the current pass is computed, and the first pass's before
+// the flags and beta are known.
+template <int KT, class T>
+__global__ __launch_bounds__(512) void k_cg_Ad(Params<T> P, const T* __restrict__ Z, const T* __restrict__ Dold,
+                                              T* __restrict__ Dnew, T* __restrict__ Qv, T* __restrict__ X, CgCtl c,
+                                              int t, int ilen, int njt, int nkt) {
+  constexpr int JT = 512 / KT, PW = KT + 2, PN = (JT + 2) * PW;
+  __shared__ T sd[4 * PN];
   const Layout& L = P.L;
-  UF_CG_RANGE(L, ilen);
-  if (t == 0 && c.flags[0] && c.st->zero_rhs) {
+  const int ntile = njt * nkt;
+  int bx, by;
+  if (!xcd_block(ntile, (L.nx + ilen - 1) / ilen, bx, by)) return;
+  const int bid = by * ntile + bx;
+  const int jtile = bx / nkt, ktile = bx - jtile * nkt;
+  const int tk = threadIdx.x % KT, tj = threadIdx.x / KT;
+  const int j = jtile * JT + tj, k = ktile * KT + tk;
+  const bool act = j < L.ny && k < L.nz;
+  const int i0 = by * ilen, i1 = min(L.nx, i0 + ilen);
+  const bool first = t == 0;
+  const int sx = (int)L.SX, pz = (int)L.PZ;   // a plane of the padded layout is far below 2^31 elements
+  // halo roles at the tile's edge: the neighbouring row (y) and column (z)
+  const int rrole = tj == 0 ? -1 : (tj == JT - 1 ? 1 : 0);
+  const int crole = tk == 0 ? -1 : (tk == KT - 1 ? 1 : 0);
+  const T* __restrict__ zc = Z + (act ? L.at(0, j, k) : 0);
+  const T* __restrict__ dc0 = Dold + (act ? L.at(0, j, k) : 0);
+  // raw values of a pass starting at plane p0: own planes p0-1 .. p0+4 and
+  // the halo cells of planes p0 .. p0+3
+  T zo[6], dz[6], zr[4], dr[4], zcol[4], dcol[4];
+  auto load_pass = [&](int p0, bool with_prev) {
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int pl = p0 - 1 + u;
+      const bool ok = act && (u >= 2 || with_prev) && pl <= i1;
+      zo[u] = ok ? zc[pl * sx] : T(0);
+      dz[u] = ok && !first ? dc0[pl * sx] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int pl = p0 + u;
+      const bool ok = act && pl < i1;
+      zr[u] = ok && rrole ? zc[pl * sx + rrole * pz] : T(0);
+      dr[u] = ok && rrole && !first ? dc0[pl * sx + rrole * pz] : T(0);
+      zcol[u] = ok && crole ? zc[pl * sx + crole] : T(0);
+      dcol[u] = ok && crole && !first ? dc0[pl * sx + crole] : T(0);
+    }
+  };
+  load_pass(i0, true);
+  if (first && c.flags[0] && c.st->zero_rhs) {
     // b = 0: the solution is x = 0
-    for (int i = i0; i < i1; ++i) X[L.at(i, j, k)] = T(0);
+    if (act)
+      for (int i = i0; i < i1; ++i) X[L.at(i, j, k)] = T(0);
     return;
   }
   if (!iteration_open(c, t)) return;
-  const bool first = t == 0;
-  const long long SX = L.SX, PZ = L.PZ;
-  const bool work = i0 < i1;
-  const bool pass0 = i0 + 4 <= i1;
-  long long o = work ? L.at(i0, j, k) : 0;
-  // Raw z and d_old of the first pass (cells i0 .. i0+3, their x-neighbours
-  // and their y/z-neighbours) are loaded before beta is known, so that the
-  // sum of the r.z partials overlaps those loads.  Entry p: 0 = i0-1,
-  // 1..5 = i0..i0+4, then four groups of four (+y, -y, +z, -z).
-  const int sx = (int)SX, pz = (int)PZ;   // a plane of the padded layout is far below 2^31 elements
-  auto off = [&](int p) -> int {
-    if (p == 0) return -sx;
-    if (p < 6) return (p - 1) * sx;
-    const int u = (p - 6) & 3, g = (p - 6) >> 2;
-    return u * sx + (g == 0 ? pz : (g == 1 ? -pz : (g == 2 ? 1 : -1)));
-  };
-  T zr[22], dr[22];
-  const T* __restrict__ zo = Z + o;
-  const T* __restrict__ d0 = Dold + o;
-#pragma unroll
-  for (int p = 0; p < 22; ++p) {
-    zr[p] = T(0);
-    dr[p] = T(0);
-    if (work && (p < 2 || pass0)) {
-      zr[p] = zo[off(p)];
-      if (!first) dr[p] = d0[off(p)];
-    }
-  }
   const double rz = rz_of(c, t);
   if (blockIdx.x == 0 && threadIdx.x == 0) c.st->rzh[t & 1] = rz;
   if (!rz_allows(c, rz)) return;
   // r.z of iteration t - 1 was published by this kernel's previous launch
   const T beta = first ? T(0) : (T)(rz / c.st->rzh[(t + 1) & 1]);
-  double v[1] = {0.0};
-  if (work) {
-    auto dn = [&](long long q) { return first ? Z[q] : Z[q] + beta * Dold[q]; };
-    auto dv = [&](int p) { return first ? zr[p] : zr[p] + beta * dr[p]; };
-    const T dyz = diag_yz(P, j, k);
-    T dm = dv(0), dc = dv(1);
-    int i = i0;
-    // four cells per pass so that each wave keeps four cells' loads in flight
-    auto pass = [&](const T (&d)[5], const T (&lat_y)[4], const T (&lat_z)[4]) {
+  auto dv = [&](T z, T d) { return first ? z : z + beta * d; };
+  const T dyz = act ? diag_yz(P, j, k) : T(0);
+  const int own = (tj + 1) * PW + tk + 1;
+  double acc[1] = {0.0};
+  T dm = dv(zo[0], dz[0]), dcur = dv(zo[1], dz[1]);
+  for (int p0 = i0; p0 < i1; p0 += 4) {
+    T d[6];
+    d[0] = dm;
+    d[1] = dcur;
+#pragma unroll
+    for (int u = 2; u < 6; ++u) d[u] = dv(zo[u], dz[u]);
+    __syncthreads();   // the previous pass is done with the LDS
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      T* s = sd + u * PN;
+      s[own] = d[u + 1];
+      if (rrole) s[own + rrole * PW] = dv(zr[u], dr[u]);
+      if (crole) s[own + crole] = dv(zcol[u], dcol[u]);
+    }
+    if (p0 + 4 < i1) load_pass(p0 + 4, false);
+    __syncthreads();
+    if (act) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const T prev = u == 0 ? dm : d[u - 1];
-        const T qv = (dyz + diag_x(P, i + u)) * d[u] - (d[u + 1] + prev) * P.ih2[0] - lat_y[u] * P.ih2[1] -
-                     lat_z[u] * P.ih2[2];
-        Dnew[o + u * SX] = d[u];
-        Qv[o + u * SX] = qv;
-        v[0] += (double)d[u] * (double)qv;
+        const int i = p0 + u;
+        if (i >= i1) break;
+        const T* s = sd + u * PN;
+        const T q = (dyz + diag_x(P, i)) * d[u + 1] - (d[u] + d[u + 2]) * P.ih2[0] -
+                    (s[own - PW] + s[own + PW]) * P.ih2[1] - (s[own - 1] + s[own + 1]) * P.ih2[2];
+        const long long o = L.at(i, j, k);
+        Dnew[o] = d[u + 1];
+        Qv[o] = q;
+        acc[0] += (double)d[u + 1] * (double)q;
       }
-      dm = d[3];
-      dc = d[4];
-      i += 4;
-      o += 4 * SX;
-    };
-    if (pass0) {
-      T d[5], lat_y[4], lat_z[4];
-#pragma unroll
-      for (int u = 0; u < 5; ++u) d[u] = dv(1 + u);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        lat_y[u] = dv(6 + u) + dv(10 + u);
-        lat_z[u] = dv(14 + u) + dv(18 + u);
-      }
-      pass(d, lat_y, lat_z);
     }
-    while (i + 4 <= i1) {
-      T d[5], lat_y[4], lat_z[4];
-      d[0] = dc;
-#pragma unroll
-      for (int u = 1; u <= 4; ++u) d[u] = dn(o + u * SX);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const long long q = o + u * SX;
-        lat_y[u] = dn(q + PZ) + dn(q - PZ);
-        lat_z[u] = dn(q + 1) + dn(q - 1);
-      }
-      pass(d, lat_y, lat_z);
-    }
-    for (; i < i1; ++i, o += SX) {
-      const T dp = dn(o + SX);
-      const T q = (dyz + diag_x(P, i)) * dc - (dp + dm) * P.ih2[0] - (dn(o + PZ) + dn(o - PZ)) * P.ih2[1] -
-                  (dn(o + 1) + dn(o - 1)) * P.ih2[2];
-      Dnew[o] = dc;
-      Qv[o] = q;
-      v[0] += (double)dc * (double)q;
-      dm = dc;
-      dc = dp;
-    }
+    dm = d[4];
+    dcur = d[5];
   }
   const int slots[1] = {S_DQ};
-  write_partials<1>(v, c.part, c.stride, slots, cg_bid);
+  write_partials<1>(acc, c.part, c.stride, slots, bid);
 }
 
-// x += alpha d; r -= alpha q; partials of ||r||^2.
+// x += alpha d; r -= alpha q; partials of ||r||^2.  The first four
+// x-planes of the thread's column are loaded before the scalars are known.
 template <class T>
 __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict__ X, const T* __restrict__ Rin,
                                                       T* __restrict__ R, const T* __restrict__ D,
                                                       const T* __restrict__ Qv, CgCtl c, int t, int ilen) {
   const Layout& L = P.L;
+  UF_CG_RANGE(L, ilen);
+  const bool pass0 = i0 + 4 <= i1;
+  const long long SX = L.SX;
+  const long long o0 = pass0 ? L.at(i0, j, k) : 0;
+  T x4[4], r4[4], d4[4], q4[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    x4[u] = r4[u] = d4[u] = q4[u] = T(0);
+    if (pass0) {
+      const long long o = o0 + u * SX;
+      x4[u] = X[o];
+      r4[u] = Rin[o];
+      d4[u] = D[o];
+      q4[u] = Qv[o];
+    }
+  }
   double rz = 0.0, dq = 0.0;
   bool run = iteration_open(c, t);
   if (run) {
@@ -273,7 +290,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
     run = rz_allows(c, rz);
   }
   if (run) {
-    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb);
+    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb_dq);
     run = dq > 0.0 && isfinite(dq);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -281,11 +298,22 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
     if (run) c.st->iter = t + 1;
   }
   if (!run) return;
-  UF_CG_RANGE(L, ilen);
   const T alpha = (T)(rz / dq);
   double v[1] = {0.0};
+  int i = i0;
+  if (pass0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long o = o0 + u * SX;
+      X[o] = x4[u] + alpha * d4[u];
+      const T r = r4[u] - alpha * q4[u];
+      R[o] = r;
+      v[0] += (double)r * (double)r;
+    }
+    i += 4;
+  }
 #pragma unroll 4
-  for (int i = i0; i < i1; ++i) {
+  for (; i < i1; ++i) {
     const long long o = L.at(i, j, k);
     X[o] += alpha * D[o];
     const T r = Rin[o] - alpha * Qv[o];
@@ -336,12 +364,30 @@ CgLaunch cg_launch(const Layout& L) {
   return CgLaunch{xcd_grid(bp, gy), ilen, bp, gy};
 }
 
+AdLaunch ad_launch(const Layout& L) {
+  AdLaunch a;
+  a.kt = L.nz >= 64 ? 64 : (L.nz > 16 ? 32 : 16);
+  a.njt = (L.ny + 512 / a.kt - 1) / (512 / a.kt);
+  a.nkt = (L.nz + a.kt - 1) / a.kt;
+  const int tiles = a.njt * a.nkt;
+  // about 512 blocks, as the other CG kernels
+  int nchunk = (512 + tiles - 1) / tiles;
+  if (nchunk > L.nx) nchunk = L.nx;
+  if (nchunk < 1) nchunk = 1;
+  a.ilen = (L.nx + nchunk - 1) / nchunk;
+  a.gy = (L.nx + a.ilen - 1) / a.ilen;
+  a.blocks = tiles * a.gy;
+  a.grid = xcd_grid(tiles, a.gy);
+  return a;
+}
+
 CgCtl make_ctl(Grid& g) {
   CgCtl c;
   c.part = g.partials;
   c.stride = (int)g.part_stride;
   c.nb = (int)g.cg_nb;
   c.nb_rz = (int)g.cg_nb_rz;
+  c.nb_dq = (int)g.cg_nb_dq;
   c.flags = g.flags;
   c.exec = g.exec;
   c.st = g.st;
@@ -382,8 +428,16 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
   void* Dnew = g.D[(t + 1) & 1];
   {
     TimedLaunch tl(g, UF_TK_CG_AD);
-    launch_k(g, k_cg_Ad<T>, cl.grid, dim3(kCgBlock), P, (const T*)g.Z, (const T*)Dold, (T*)Dnew,
-                       (T*)g.Qv, (T*)g.X, c, t, cl.ilen);
+    const AdLaunch al = ad_launch(P.L);
+    if (al.kt == 64)
+      launch_k(g, k_cg_Ad<64, T>, al.grid, dim3(512), P, (const T*)g.Z, (const T*)Dold, (T*)Dnew, (T*)g.Qv, (T*)g.X,
+               c, t, al.ilen, al.njt, al.nkt);
+    else if (al.kt == 32)
+      launch_k(g, k_cg_Ad<32, T>, al.grid, dim3(512), P, (const T*)g.Z, (const T*)Dold, (T*)Dnew, (T*)g.Qv, (T*)g.X,
+               c, t, al.ilen, al.njt, al.nkt);
+    else
+      launch_k(g, k_cg_Ad<16, T>, al.grid, dim3(512), P, (const T*)g.Z, (const T*)Dold, (T*)Dnew, (T*)g.Qv, (T*)g.X,
+               c, t, al.ilen, al.njt, al.nkt);
   }
   {
     TimedLaunch tl(g, UF_TK_CG_AXPY);

@@ -66,6 +66,7 @@ struct CgCtl {
   int stride;
   int nb;          // blocks of the CG kernels (slots BB, RR, DQ)
   int nb_rz;       // blocks of the kernel writing r.z (slots RZ0, RZ1)
+  int nb_dq;       // blocks of the d/q kernel (slot DQ)
   int* flags;      // flags[m]: the solve finished before iteration m
   int* exec;       // exec[t]: iteration t performed its update
   CgState* st;

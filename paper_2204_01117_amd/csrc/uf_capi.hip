@@ -435,7 +435,8 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     const CgLaunch cl = cg_launch(L);
     g->cg_nb = (size_t)cl.gx * cl.gy;
     g->cg_nb_rz = cfg->precond == UF_PC_MG ? mg_fine_blocks(L) : g->cg_nb;
-    g->part_stride = std::max(g->cg_nb, g->cg_nb_rz);
+    g->cg_nb_dq = (size_t)ad_launch(L).blocks;
+    g->part_stride = std::max(g->cg_nb, std::max(g->cg_nb_rz, g->cg_nb_dq));
     g->partials = (double*)dalloc(S_NSLOT_HOST * g->part_stride * sizeof(double));
     g->flags = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
     g->exec = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));

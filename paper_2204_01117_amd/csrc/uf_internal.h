@@ -38,6 +38,14 @@ struct MgLevel {
   void* t = nullptr;         // scratch
 };
 
+// Launch shape of the d/q kernel: tiles of (512 / kt) x kt columns, njt x nkt
+// of them per plane, gy chunks of ilen planes.
+struct AdLaunch {
+  dim3 grid;
+  int kt, njt, nkt, ilen, gy, blocks;
+};
+AdLaunch ad_launch(const Layout& L);
+
 struct CgLaunch {
   dim3 grid;   // 1-D launch of the logical gx x gy blocks (see xcd_block)
   int ilen;    // x-planes marched by each block
@@ -74,6 +82,7 @@ struct Grid {
   size_t part_stride = 0;
   size_t cg_nb = 0;             // blocks of the fine-grid CG kernels
   size_t cg_nb_rz = 0;          // blocks of the kernel that writes the r.z partials
+  size_t cg_nb_dq = 0;          // blocks of the d/q kernel
   int* flags = nullptr;         // [cg_maxit + 2]
   int* exec = nullptr;          // [cg_maxit + 2]
   CgState* st = nullptr;     // device
