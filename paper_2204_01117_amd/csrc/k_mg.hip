@@ -30,7 +30,6 @@ namespace uf {
 
 constexpr int kMgMaxLevels = 16;
 constexpr int kTailThreads = 1024;
-constexpr long long kTailCells = 1024;   // levels this small run in the single-workgroup kernel
 constexpr int kDenseMax = 512;           // largest coarsest level with an exact inverse
 constexpr long long kCoarsestCells = 64; // coarsening stops at levels this small
 constexpr int kCoarseSweeps = 10;        // Jacobi sweeps when there is no exact inverse
@@ -578,9 +577,23 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
   }
 }
 
-// LDS cells for the levels of the single-workgroup kernel (each level there
-// has at most kTailCells cells and at least halves the previous one).
-constexpr int kTailPool = 2 * (int)kTailCells;
+// Levels of at most `cells` cells run in the single-workgroup kernel, with
+// r, x and t of all of them in an LDS pool of `pool` cells per array (a
+// hierarchy whose small levels need more takes the global-memory variant).
+template <class T>
+struct TailCfg;
+template <>
+struct TailCfg<float> {
+  // larger small levels are faster as separate multi-block kernels (one
+  // workgroup took 40 us for 8192 cells and below, the kernels 22 us)
+  static constexpr long long cells = 1024;
+  static constexpr int pool = 2048;
+};
+template <>
+struct TailCfg<double> {
+  static constexpr long long cells = 1024;
+  static constexpr int pool = 2048;
+};
 
 // All levels from lt down to the coarsest and back in one workgroup, with
 // every level's r, x and t in LDS (compact k-fastest order, no ghosts;
@@ -591,6 +604,7 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const M
                                                           int nl, const T* __restrict__ cinv,
                                                           const int* __restrict__ flags, int m) {
   const int skip = flags[m];   // tested once level lt is staged
+  constexpr int kTailPool = TailCfg<T>::pool;
   __shared__ T pr[kTailPool];
   __shared__ T px[kTailPool];
   __shared__ T pt[kTailPool];
@@ -740,8 +754,8 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(MgCommon<T> K, const M
 }
 
 // The same in global memory (arrays that stay in the L2), for hierarchies
-// whose small levels do not fit the LDS pool (a coarsest level above
-// kTailCells cells, left when no axis can be halved).
+// whose small levels do not fit the LDS pool (e.g. a large coarsest level
+// left where no axis can be halved).
 template <class T>
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail_global(MgCommon<T> K, const MgLvl<T>* __restrict__ lv, int lt,
                                                           int nl, const T* __restrict__ cinv,
@@ -989,7 +1003,7 @@ void mg_setup(Grid& g) {
   // first small level (>= 1) for the single-workgroup kernel
   g.mg_lt = nl;
   for (int l = 1; l < nl; ++l)
-    if (ncells(g.mg[l].L) <= kTailCells) {
+    if (ncells(g.mg[l].L) <= TailCfg<T>::cells) {
       g.mg_lt = l;
       break;
     }
@@ -998,7 +1012,7 @@ void mg_setup(Grid& g) {
   {
     long long pool = 0;
     for (int l = std::min(g.mg_lt, nl - 1); l < nl; ++l) pool += ncells(g.mg[l].L);
-    g.mg_tail_lds = pool <= kTailPool;
+    g.mg_tail_lds = pool <= TailCfg<T>::pool;
   }
   g.mg_cinv = nullptr;
   g.mg_nc = (int)ncells(last.L);
