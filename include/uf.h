@@ -59,10 +59,11 @@ typedef enum {
 enum { UF_BC_AUTO = -1, UF_BC_INLET = 0, UF_BC_OUTLET = 1, UF_BC_WALL = 2, UF_BC_SLIP = 3 };
 enum { UF_F32 = 0, UF_F64 = 1 };
 enum { UF_TURB_OFF = 0, UF_TURB_KOMEGA = 1 };
-/* Pressure CG preconditioner: none, Jacobi, the first-order approximate
- * inverse M^-1 = K^T K of Sec. 3 (full product, see uf_config.ai_omega),
- * or a geometric multigrid V-cycle. */
-enum { UF_PC_NONE = 0, UF_PC_JACOBI = 1, UF_PC_AI1 = 2, UF_PC_MG = 4 };
+/* Pressure CG preconditioner: none, Jacobi, the first- or second-order
+ * approximate inverse M^-1 = K^T K of Sec. 3 (full products, see
+ * uf_config.ai_omega; AI2 takes two passes through the grid's scratch
+ * vector), or a geometric multigrid V-cycle. */
+enum { UF_PC_NONE = 0, UF_PC_JACOBI = 1, UF_PC_AI1 = 2, UF_PC_AI2 = 3, UF_PC_MG = 4 };
 /* Inflow profile: uniform speed, the log-law of Sec. 5.1, or a table. */
 enum { UF_INFLOW_UNIFORM = 0, UF_INFLOW_LOGLAW = 1, UF_INFLOW_PROFILE = 2 };
 /* Stages of a step (Sec. 3 time splitting); all on by default. */

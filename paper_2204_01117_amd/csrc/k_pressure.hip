@@ -61,6 +61,55 @@ __device__ __forceinline__ T precond_apply(const Params<T>& P, int pc, T om, con
   return r[o];
 }
 
+// Second-order approximate inverse (Sec. 3): M^-1 = K^T K with
+// K = sqrt(2-w) Dbar^-1/2 (I - L Dbar^-1 + (L Dbar^-1)^2), applied in two
+// passes through a scratch vector v:
+//   v_c = (w/D_c) (r_c + sum_{lower n} (w/D_n) (r_n + sum_{lower m of n} (w/D_m) r_m / h_m^2) / h_n^2)
+//   z_c = (2-w) (v_c + (w/D_c) sum_{upper m} (v_m + (w/D_m) sum_{upper p of m} v_p / h_p^2) / h_m^2)
+// (the off-diagonal entries of A are -1/h^2; every hop stays inside the grid).
+template <class T>
+__device__ __forceinline__ T ai2_lower(const Params<T>& P, const T* __restrict__ r, int i, int j, int k, T om) {
+  // r_n + sum over the in-grid lower neighbours m of n of (w/D_m) r_m / h^2
+  const Layout& L = P.L;
+  const long long o = L.at(i, j, k);
+  T s = r[o];
+  if (i > 0) s += om / poisson_diag(P, i - 1, j, k) * r[o - L.SX] * P.ih2[0];
+  if (j > 0) s += om / poisson_diag(P, i, j - 1, k) * r[o - L.PZ] * P.ih2[1];
+  if (k > 0) s += om / poisson_diag(P, i, j, k - 1) * r[o - 1] * P.ih2[2];
+  return s;
+}
+
+template <class T>
+__device__ __forceinline__ T ai2_v(const Params<T>& P, const T* __restrict__ r, int i, int j, int k, T om) {
+  T s = r[P.L.at(i, j, k)];
+  if (i > 0) s += om / poisson_diag(P, i - 1, j, k) * ai2_lower(P, r, i - 1, j, k, om) * P.ih2[0];
+  if (j > 0) s += om / poisson_diag(P, i, j - 1, k) * ai2_lower(P, r, i, j - 1, k, om) * P.ih2[1];
+  if (k > 0) s += om / poisson_diag(P, i, j, k - 1) * ai2_lower(P, r, i, j, k - 1, om) * P.ih2[2];
+  return om / poisson_diag(P, i, j, k) * s;
+}
+
+template <class T>
+__device__ __forceinline__ T ai2_upper(const Params<T>& P, const T* __restrict__ v, int i, int j, int k, T om) {
+  // v_m + (w/D_m) sum over the in-grid upper neighbours p of m of v_p / h^2
+  const Layout& L = P.L;
+  const long long o = L.at(i, j, k);
+  T s = T(0);
+  if (i + 1 < L.nx) s += v[o + L.SX] * P.ih2[0];
+  if (j + 1 < L.ny) s += v[o + L.PZ] * P.ih2[1];
+  if (k + 1 < L.nz) s += v[o + 1] * P.ih2[2];
+  return v[o] + om / poisson_diag(P, i, j, k) * s;
+}
+
+template <class T>
+__device__ __forceinline__ T ai2_z(const Params<T>& P, const T* __restrict__ v, int i, int j, int k, T om) {
+  const Layout& L = P.L;
+  T s = T(0);
+  if (i + 1 < L.nx) s += ai2_upper(P, v, i + 1, j, k, om) * P.ih2[0];
+  if (j + 1 < L.ny) s += ai2_upper(P, v, i, j + 1, k, om) * P.ih2[1];
+  if (k + 1 < L.nz) s += ai2_upper(P, v, i, j, k + 1, om) * P.ih2[2];
+  return (T(2) - om) * (v[L.at(i, j, k)] + om / poisson_diag(P, i, j, k) * s);
+}
+
 // Diagonal of A split as the part from the y and z axes (fixed along a
 // thread's x-march) and the x part at cell i.
 template <class T>
@@ -149,6 +198,41 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_precond(Params<T> P, const T* _
   }
   const int slots[1] = {S_RZ0 + (m & 1)};
   write_partials<1>(v, c.part, c.stride, slots, cg_bid);
+}
+
+// First pass of the second-order approximate inverse: v from r (all cells).
+template <class T>
+__global__ __launch_bounds__(kCgBlock) void k_ai2_v(Params<T> P, const T* __restrict__ R, T* __restrict__ V, T om,
+                                                   int ilen) {
+  const Layout& L = P.L;
+  UF_CG_RANGE(L, ilen);
+  for (int i = i0; i < i1; ++i) V[L.at(i, j, k)] = ai2_v(P, R, i, j, k, om);
+}
+
+// Second pass: z from v.  In a solve (cg != 0) it is preconditioner
+// application m: it decides whether the solve has finished (as
+// k_cg_precond) and writes the partials of r.z.
+template <class T>
+__global__ __launch_bounds__(kCgBlock) void k_ai2_z(Params<T> P, const T* __restrict__ R, const T* __restrict__ V,
+                                                   T* __restrict__ Z, CgCtl c, int m, T om, int ilen, int cg) {
+  const Layout& L = P.L;
+  if (cg) {
+    const bool skip = precond_skip(c, m);
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[m] = skip;
+    if (skip) return;
+  }
+  UF_CG_RANGE(L, ilen);
+  double v[1] = {0.0};
+  for (int i = i0; i < i1; ++i) {
+    const long long o = L.at(i, j, k);
+    const T z = ai2_z(P, V, i, j, k, om);
+    Z[o] = z;
+    v[0] += (double)R[o] * (double)z;
+  }
+  if (cg) {
+    const int slots[1] = {S_RZ0 + (m & 1)};
+    write_partials<1>(v, c.part, c.stride, slots, cg_bid);
+  }
 }
 
 // d = z + beta d_old; q = A d; partials of d.q.
@@ -415,6 +499,15 @@ void launch_cg_precond(Grid& g, const Params<T>& P, int m) {
     return;
   }
   const CgLaunch cl = cg_launch(P.L);
+  if (g.cfg.precond == UF_PC_AI2) {
+    // Qv holds q only between the d/q kernel and the update: free here
+    hipLaunchKernelGGL(k_ai2_v<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)resid(g, m), (T*)g.Qv,
+                       T(g.cfg.ai_omega), cl.ilen);
+    TimedLaunch tl(g, UF_TK_CG_PRECOND);
+    launch_k(g, k_ai2_z<T>, cl.grid, dim3(kCgBlock), P, (const T*)resid(g, m), (const T*)g.Qv, (T*)g.Z, make_ctl(g),
+             m, T(g.cfg.ai_omega), cl.ilen, 1);
+    return;
+  }
   TimedLaunch tl(g, UF_TK_CG_PRECOND);
   launch_k(g, k_cg_precond<T>, cl.grid, dim3(kCgBlock), P, (const T*)resid(g, m), (T*)g.Z,
                      make_ctl(g), m, g.cfg.precond, T(g.cfg.ai_omega), cl.ilen);
@@ -454,6 +547,13 @@ void launch_cg_status(Grid& g, int t_end) {
 template <class T>
 void launch_apply(Grid& g, const Params<T>& P, int op, const void* x, void* y) {
   const CgLaunch cl = cg_launch(P.L);
+  if (op == UF_OP_PRECOND && g.cfg.precond == UF_PC_AI2) {
+    hipLaunchKernelGGL(k_ai2_v<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)x, (T*)g.Qv,
+                       T(g.cfg.ai_omega), cl.ilen);
+    hipLaunchKernelGGL(k_ai2_z<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)x, (const T*)g.Qv, (T*)y,
+                       make_ctl(g), 0, T(g.cfg.ai_omega), cl.ilen, 0);
+    return;
+  }
   hipLaunchKernelGGL(k_apply<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, op, g.cfg.precond, T(g.cfg.ai_omega),
                      (const T*)x, (T*)y, cl.ilen);
 }

@@ -166,7 +166,8 @@ std::string validate(const uf_config& c) {
   if (!std::isfinite(c.Cd) || !std::isfinite(c.a) || !std::isfinite(c.b) || c.Cd < 0 || c.a < 0)
     return "drag constants must be finite, Cd and a >= 0";
   if (!finite_pos(c.e)) return "e must be finite and > 0";
-  if (c.precond != UF_PC_NONE && c.precond != UF_PC_JACOBI && c.precond != UF_PC_AI1 && c.precond != UF_PC_MG)
+  if (c.precond != UF_PC_NONE && c.precond != UF_PC_JACOBI && c.precond != UF_PC_AI1 && c.precond != UF_PC_AI2 &&
+      c.precond != UF_PC_MG)
     return "unknown preconditioner";
   if (!(c.ai_omega > 0 && c.ai_omega < 2)) return "ai_omega must lie in (0, 2)";
   if (!finite_pos(c.cg_tol)) return "cg_tol must be finite and > 0";

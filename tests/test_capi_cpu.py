@@ -55,7 +55,7 @@ def _create(cfg):
     (dict(bc=[0, 0, 0, 0, 2, 3]), "outlet"),
     (dict(bc=[9, 1, 1, 1, 2, 3]), "boundary kind"),
     (dict(nu=1e3), "stability"),
-    (dict(precond=3), "preconditioner"),
+    (dict(precond=5), "preconditioner"),
     (dict(ai_omega=2.0), "ai_omega"),
     (dict(cg_tol=0.0), "cg_tol"),
     (dict(cg_maxit=0), "cg_maxit"),

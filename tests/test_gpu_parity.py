@@ -18,11 +18,12 @@ pytestmark = [pytest.mark.gpu,
 
 from uf_layouts import default_config, preset, preset_porosity
 from uf_layouts.configs import (BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP, INFLOW_UNIFORM, INFLOW_PROFILE,
-                                TURB_OFF, PC_NONE, PC_JACOBI, PC_AI1, PC_MG, STAGE_ALL)
+                                TURB_OFF, PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG, STAGE_ALL)
 from oracle import OracleGrid, Geometry
 from oracle import step as S
 from oracle import bc as B
-from oracle.pressure import poisson_matrix, ai_preconditioner
+from oracle.pressure import poisson_matrix, ai_preconditioner, pcg
+import scipy.sparse as sp
 from helpers import rel, to_np, state_errors, random_small_config, random_porosity
 
 import paper_2204_01117_amd as U
@@ -65,13 +66,13 @@ def test_poisson_operator_matches_matrix(seed, dtype):
 
 
 @pytest.mark.parametrize("seed", range(4))
-@pytest.mark.parametrize("pc", [PC_AI1, PC_JACOBI, PC_NONE])
+@pytest.mark.parametrize("pc", [PC_AI1, PC_AI2, PC_JACOBI, PC_NONE])
 def test_preconditioner_matches_matrix(seed, pc):
     cfg = random_small_config(seed, dtype="f64", precond=pc, ai_omega=1.6)
     g = gpu_grid(cfg)
     A = poisson_matrix(Geometry(cfg))
-    if pc == PC_AI1:
-        M, _ = ai_preconditioner(A, 1.6)
+    if pc in (PC_AI1, PC_AI2):
+        M, _ = ai_preconditioner(A, 1.6, order=1 if pc == PC_AI1 else 2)
     elif pc == PC_JACOBI:
         M = np.diag(1.0 / A.diagonal())
     else:
@@ -103,7 +104,7 @@ def test_multigrid_is_symmetric_positive_definite(shape, dtype):
     g.close()
 
 
-@pytest.mark.parametrize("pc", [PC_MG, PC_AI1, PC_JACOBI, PC_NONE])
+@pytest.mark.parametrize("pc", [PC_MG, PC_AI1, PC_AI2, PC_JACOBI, PC_NONE])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pressure_solve_matches_direct(pc, dtype):
     cfg = default_config(24, 16, 10, 2.0, dtype=dtype, precond=pc, cg_tol=CG_TOL[dtype], cg_maxit=5000,
@@ -116,6 +117,34 @@ def test_pressure_solve_matches_direct(pc, dtype):
     assert st["converged"] == 1 and st["cg_rel_residual"] <= CG_TOL[dtype]
     assert rel(to_np(x).ravel(), xd) < (1e-10 if dtype == "f64" else 5e-5)
     g.close()
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.6])
+def test_preconditioner_ordering_and_iterations(omega):
+    """Sec. 3 / appendix A.3: with the paper's stopping rule (M^-1 r . r /
+    ||b||^2 < 1e-5) the approximate inverses beat Jacobi, which is no worse
+    than plain CG (the order of Tables 2-3), and each GPU solve takes the
+    same number of iterations as the oracle's FP64 PCG with the same M."""
+    cfg = default_config(40, 24, 12, 2.0, dtype="f64", cg_criterion=1, cg_tol=1e-5, cg_maxit=5000,
+                         ai_omega=omega, bc=[BC_INLET, BC_OUTLET, BC_WALL, BC_OUTLET, BC_WALL, BC_SLIP])
+    A = poisson_matrix(Geometry(cfg))
+    b = np.random.default_rng(11).normal(size=A.shape[0])
+    iters = {}
+    for pc in (PC_NONE, PC_JACOBI, PC_AI1, PC_AI2):
+        g = gpu_grid(dict(cfg, precond=pc))
+        x, st = g.pressure_solve(torch.tensor(b))
+        g.close()
+        assert st["converged"] == 1
+        iters[pc] = st["cg_iters"]
+        if pc in (PC_AI1, PC_AI2):
+            M, _ = ai_preconditioner(A, omega, order=1 if pc == PC_AI1 else 2)
+        elif pc == PC_JACOBI:
+            M = sp.diags(1.0 / A.diagonal())
+        else:
+            M = None
+        _, it = pcg(A, b, np.zeros_like(b), M, tol=1e-5, maxit=5000, criterion=1)
+        assert abs(it - st["cg_iters"]) <= 1, (pc, it, st["cg_iters"])
+    assert iters[PC_AI2] <= iters[PC_AI1] < iters[PC_JACOBI] <= iters[PC_NONE], iters
 
 
 # -------------------------------------------------- one step, stage by stage

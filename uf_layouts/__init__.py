@@ -10,7 +10,7 @@ resolved by uniform sub-sampling.
 from .configs import (BC_AUTO, BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP,
                       INFLOW_UNIFORM, INFLOW_LOGLAW, INFLOW_PROFILE,
                       TURB_OFF, TURB_KOMEGA,
-                      PC_NONE, PC_JACOBI, PC_AI1, PC_MG,
+                      PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG,
                       STAGE_ADVECT, STAGE_DIFFUSE, STAGE_DRAG, STAGE_PROJECT,
                       STAGE_TURB, STAGE_ALL,
                       default_config, preset, PRESETS)

@@ -19,7 +19,7 @@ import math
 BC_AUTO, BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP = -1, 0, 1, 2, 3
 INFLOW_UNIFORM, INFLOW_LOGLAW, INFLOW_PROFILE = 0, 1, 2
 TURB_OFF, TURB_KOMEGA = 0, 1
-PC_NONE, PC_JACOBI, PC_AI1, PC_MG = 0, 1, 2, 4
+PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG = 0, 1, 2, 3, 4
 STAGE_ADVECT, STAGE_DIFFUSE, STAGE_DRAG, STAGE_PROJECT, STAGE_TURB = 1, 2, 4, 8, 16
 STAGE_ALL = 31
 
