@@ -22,6 +22,9 @@ Profiling helpers (the commands are recorded in the files they write):
         HBM bytes per launch of each kernel from those two runs, scaled by
         what the counters read for the copy, into
         profiles/traffic_<kernel>_256x256x64.json
+    python bench.py --precond-study
+        the pressure system of the workload solved with each preconditioner
+        (iterations and solve time per case, one JSON line each)
     python bench.py --stats-summary <dir> --command "<rocprofv3 command>"
         profiles/kernels_256x256x64.md from a rocprofv3 --kernel-trace
         --stats csv run
@@ -261,6 +264,40 @@ def stats_summary(run_dir, command):
     log("wrote", path)
 
 
+def precond_study():
+    """Pressure solves on the 256x256x64 system for each preconditioner (the
+    paper's comparison, Sec. 3 and its Tables 2-3, on this grid): seeded
+    normal right-hand side, zero initial guess, the paper's stopping rule
+    (M^-1 r . r / ||b||^2 < 1e-5) and the default one (||r|| <= 1e-6 ||b||).
+    One JSON line per case: iterations and GPU time of the solve."""
+    import numpy as np
+    import torch
+    import paper_2204_01117_amd as U
+    from uf_layouts.configs import PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG
+    _, _, cfg = workload()
+    shape = (cfg["nx"], cfg["ny"], cfg["nz"])
+    b = torch.tensor(np.random.default_rng(7).normal(size=shape), dtype=torch.float32, device="cuda:0")
+    cases = [("CG", PC_NONE, 1.6), ("Jacobi", PC_JACOBI, 1.6), ("AI1", PC_AI1, 1.0), ("AI1", PC_AI1, 1.6),
+             ("AI1", PC_AI1, 1.8), ("AI2", PC_AI2, 1.0), ("AI2", PC_AI2, 1.6), ("AI2", PC_AI2, 1.8),
+             ("MG", PC_MG, 1.6)]
+    for crit, tol in ((1, 1e-5), (0, 1e-6)):
+        for name, pc, om in cases:
+            g = U.Grid(dict(cfg, precond=pc, ai_omega=om, cg_criterion=crit, cg_tol=tol, cg_maxit=20000),
+                       device="cuda:0")
+            g.pressure_solve(b)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            _, st = g.pressure_solve(b)
+            e1.record()
+            torch.cuda.synchronize()
+            g.close()
+            print(json.dumps({"precond": name, "omega": om if pc in (PC_AI1, PC_AI2) else None,
+                              "criterion": "paper (Mr.r/|b|^2 < 1e-5)" if crit else "|r| <= 1e-6 |b|",
+                              "iterations": st["cg_iters"], "ms": e0.elapsed_time(e1),
+                              "converged": st["converged"], "grid": list(shape)}), flush=True)
+
+
 def cpu_baseline(phi, cfg, state):
     """The FP64 oracle on a bounded sample of the same workload: from the
     GPU's state, the oracle's advection, diffusion, drag and k-omega stages
@@ -326,6 +363,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
+    ap.add_argument("--precond-study", action="store_true")
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
@@ -342,6 +380,8 @@ def main():
 
     if args.traffic_probe:
         return traffic_probe()
+    if args.precond_study:
+        return precond_study()
 
     import torch
     import paper_2204_01117_amd as U
