@@ -89,11 +89,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload():
+def workload(name="C1"):
+    """C1: the 256x256x64 city (the default).  C2: the 512x512x128 city.
+    slab: one GPU's share of C2 split eight ways along x (64x512x128, the
+    first slab of C2's layout, with the domain's own side conditions where
+    a split run would exchange halos)."""
     from uf_layouts import preset, preset_porosity
-    p = preset("C1")
+    if name == "slab":
+        p = preset("C2")
+        phi, cfg = preset_porosity(p)
+        nx = cfg["nx"] // 8
+        phi = phi[:nx].copy()
+        cfg = dict(cfg, nx=nx)
+        p = dict(p, workload="64x512x128 x-slab (1/8) of " + p["workload"])
+        return p, phi, cfg
+    p = preset(name)
     phi, cfg = preset_porosity(p)
     return p, phi, cfg
+
+
+def copy_ceiling_gbs(torch, nbytes=1 << 30, reps=5):
+    """Read + write bandwidth of a plain device copy (the practical ceiling
+    of the streaming kernels)."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del x, y
+    return gbs
 
 
 def traffic_for(kernel, ncells):
@@ -364,6 +394,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--precond-study", action="store_true")
+    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab"])
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
@@ -386,7 +417,7 @@ def main():
     import torch
     import paper_2204_01117_amd as U
 
-    p, phi, cfg = workload()
+    p, phi, cfg = workload(args.workload)
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
     ncells = nx * ny * nz
     dev = torch.device("cuda:0")
@@ -420,8 +451,10 @@ def main():
     alg_bytes = ALG_BYTES_PER_CELL[dominant] * ncells
     avg_s = k_ms / 1e3 / max(k_n, 1)        # over every launch, as rocprof averages
     achieved = alg_bytes / avg_s / 1e9
-    traffic = traffic_for(dominant, ncells)
+    # counter figures exist for the default workload only
+    traffic = traffic_for(dominant, ncells) if args.workload == "C1" else None
 
+    st_state = g.state() if (not args.no_cpu_baseline and args.workload == "C1") else {}
     result = {
         "metric": "cell-updates/s per full RANS step (incl. pressure solve)",
         "value": ncells * args.steps / secs,
@@ -444,10 +477,11 @@ def main():
                      "avg_launch_us": avg_s * 1e6, "launches": k_n,
                      "alg_bytes_per_launch": alg_bytes},
     }
-    if not args.no_cpu_baseline:
-        state = {f: v.double().cpu().numpy() for f, v in g.state().items()}
-        result["cpu_baseline"] = cpu_baseline(phi, cfg, state)
     g.close()
+    result["stream_copy_GBs"] = copy_ceiling_gbs(torch)
+    if not args.no_cpu_baseline and args.workload == "C1":
+        state = {f: v.double().cpu().numpy() for f, v in st_state.items()}
+        result["cpu_baseline"] = cpu_baseline(phi, cfg, state)
     print(json.dumps(result), flush=True)
 
 
