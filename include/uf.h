@@ -166,10 +166,28 @@ uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_s
 enum { UF_OP_POISSON = 0, UF_OP_PRECOND = 1 };
 uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_dev);
 
-/* Design objective and its adjoint (Sec. 4.2 objective L(u) and the
- * gradient-based design optimisation).  Not implemented in this version: both
- * return UF_ENOTIMPL. */
-uf_status uf_objective(uf_grid g, const void* spec, double* J_host, void* dJ_dstate_dev);
+/* Design objective of the optimisation routine (Sec. 4, the target-region
+ * objective of the Nurnberg study): L = sum_i (s_i - u_target)^2 with s_i the
+ * mean wind speed over the cells of target region i, the speed of a cell
+ * being |u| of its cell-centre velocity (the mean of its two faces per
+ * component).  Regions are boxes of cell indices, half-open:
+ * i0 <= i < i1, j0 <= j < j1, k0 <= k < k1. */
+typedef struct {
+  int32_t nregions;            /* 1 .. UF_MAX_REGIONS                           */
+  const int32_t* boxes;        /* host, 6 per region: i0, i1, j0, j1, k0, k1     */
+  double u_target;             /* ideal mean speed (0.55 m/s in the paper)       */
+} uf_objective_spec;
+enum { UF_MAX_REGIONS = 64 };
+
+/* Evaluates L on the current state into *J_host (synchronises the grid's
+ * stream).  Speeds are summed in FP64 in a fixed order (deterministic).
+ * UF_EINVAL for a NULL argument, a region count out of range, an empty box,
+ * a box outside the grid or a non-finite target, before any work.
+ * dJ_dstate_dev (the adjoint seed) must be NULL: the adjoint is not
+ * implemented in this version (UF_ENOTIMPL, like uf_adjoint_step). */
+uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev);
+/* One reverse step of the discrete adjoint: not implemented in this
+ * version (returns UF_ENOTIMPL). */
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
                           void* const* adj_n_dev, void* dJ_dphi_accum_dev);
 

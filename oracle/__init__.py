@@ -12,6 +12,7 @@ everything else is pinned by tests under ``tests/test_oracle_*.py``.
 """
 from .bc import (INLET, OUTLET, WALL, SLIP, Geometry, resolve_bc)
 from .solver import OracleGrid, FIELDS
+from .objective import cell_speed, region_means, region_objective, fd_gradient
 
 __all__ = ["INLET", "OUTLET", "WALL", "SLIP", "Geometry", "resolve_bc",
-           "OracleGrid", "FIELDS"]
+           "OracleGrid", "FIELDS", "cell_speed", "region_means", "region_objective", "fd_gradient"]

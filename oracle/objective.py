@@ -1,0 +1,50 @@
+"""Design objective of the optimisation routine -- TEST INFRASTRUCTURE ONLY.
+
+Sec. 4 (the Nurnberg study) scores a design by the mean wind speed over N
+target regions: L = sum_i (s_i - u_t)^2, where s_i averages the wind speed
+over region i and u_t is the ideal speed (0.55 m/s there).  The speed of a
+cell is the norm of its cell-centre velocity, each component the mean of the
+cell's two faces on the staggered grid (Sec. 3.1).  Regions are boxes of
+cell indices, half-open on each axis.
+
+Pinned by tests/test_oracle_objective.py (uniform-flow closed form, linear
+profiles with known means, brute force on a tiny grid).
+"""
+import numpy as np
+
+
+def cell_speed(u, v, w):
+    """Cell-centre speed |(u_c, v_c, w_c)| from face arrays of extents
+    (nx+1, ny, nz), (nx, ny+1, nz), (nx, ny, nz+1)."""
+    uc = 0.5 * (u[:-1, :, :] + u[1:, :, :])
+    vc = 0.5 * (v[:, :-1, :] + v[:, 1:, :])
+    wc = 0.5 * (w[:, :, :-1] + w[:, :, 1:])
+    return np.sqrt(uc * uc + vc * vc + wc * wc)
+
+
+def region_means(u, v, w, regions):
+    """Mean cell speed over each box ((i0, i1), (j0, j1), (k0, k1))."""
+    s = cell_speed(np.asarray(u, np.float64), np.asarray(v, np.float64), np.asarray(w, np.float64))
+    out = []
+    for (i0, i1), (j0, j1), (k0, k1) in regions:
+        out.append(float(np.mean(s[i0:i1, j0:j1, k0:k1])))
+    return np.array(out)
+
+
+def region_objective(u, v, w, regions, u_target):
+    """L = sum over regions of (mean speed - u_target)^2."""
+    m = region_means(u, v, w, regions)
+    return float(np.sum((m - u_target) ** 2))
+
+
+def fd_gradient(J, theta, eps):
+    """Forward-difference gradient of J at theta (Sec. 4: one extra
+    simulation per parameter, step eps)."""
+    theta = np.asarray(theta, np.float64)
+    j0 = J(theta)
+    g = np.zeros_like(theta)
+    for n in range(theta.size):
+        t = theta.copy()
+        t[n] += eps
+        g[n] = (J(t) - j0) / eps
+    return j0, g

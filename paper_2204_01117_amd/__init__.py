@@ -8,7 +8,7 @@ the library's HIP kernels; there is no Python or CPU fallback, and importing
 this package fails when libuf.so is missing.
 """
 from ._lib import (lib, LIB_PATH, UFError, uf_config, uf_step_stats, make_config,
-                   STATUS, FIELDS, FIELD_IDS)
+                   uf_objective_spec, make_objective_spec, STATUS, FIELDS, FIELD_IDS)
 from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_field,
                    uf_get_field, uf_field_extent, uf_step, uf_pressure_solve,
                    uf_apply_operator, uf_objective, uf_adjoint_step, uf_set_stream,
@@ -16,6 +16,7 @@ from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_fiel
 from .grid import Grid
 
 __all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_config",
+           "uf_objective_spec", "make_objective_spec",
            "STATUS", "FIELDS", "FIELD_IDS", "Grid",
            "uf_create_grid", "uf_destroy_grid", "uf_set_porosity", "uf_set_field",
            "uf_get_field", "uf_field_extent", "uf_step", "uf_pressure_solve",

@@ -36,6 +36,22 @@ class uf_step_stats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class uf_objective_spec(ctypes.Structure):
+    _fields_ = [("nregions", c_int32), ("boxes", POINTER(c_int32)), ("u_target", c_double)]
+
+
+def make_objective_spec(regions, u_target):
+    """uf_objective_spec from a list of boxes ((i0, i1), (j0, j1), (k0, k1)), half-open.
+    Returns (struct, keepalive)."""
+    flat = [int(v) for box in regions for lohi in box for v in lohi]
+    keep = (c_int32 * max(len(flat), 1))(*flat)
+    s = uf_objective_spec()
+    s.nregions = len(regions)
+    s.boxes = ctypes.cast(keep, POINTER(c_int32))
+    s.u_target = float(u_target)
+    return s, keep
+
+
 class UFError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (STATUS.get(status, status), message))

@@ -131,6 +131,36 @@ __global__ __launch_bounds__(kCellBlock) void k_pack(Layout L, int ex, int ey, i
   }
 }
 
+// Sum of the cell-centre wind speed over a box of cells (one FP64 partial per
+// block; the caller adds the partials in block order).
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_region_speed(Layout L, const T* __restrict__ U, const T* __restrict__ V,
+                                                            const T* __restrict__ W, int i0, int j0, int k0, int ni,
+                                                            int nj, int nk, double* __restrict__ part) {
+  const long long n = (long long)ni * nj * nk;
+  double v[1] = {0.0};
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = k0 + (int)(c % nk);
+    const long long r = c / nk;
+    const int j = j0 + (int)(r % nj);
+    const int i = i0 + (int)(r / nj);
+    const long long o = L.at(i, j, k);
+    const double uc = 0.5 * ((double)U[o] + (double)U[o + L.SX]);
+    const double vc = 0.5 * ((double)V[o] + (double)V[o + L.PZ]);
+    const double wc = 0.5 * ((double)W[o] + (double)W[o + 1]);
+    v[0] += sqrt(uc * uc + vc * vc + wc * wc);
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <class T>
+void launch_region_speed(Grid& g, const int box[6], double* part, int nblocks) {
+  hipLaunchKernelGGL(k_region_speed<T>, dim3(nblocks), dim3(kCellBlock), 0, g.stream, g.L, (const T*)g.Q[g.cur][0],
+                     (const T*)g.Q[g.cur][1], (const T*)g.Q[g.cur][2], box[0], box[2], box[4], box[1] - box[0],
+                     box[3] - box[2], box[5] - box[4], part);
+}
+
 template <class T>
 __global__ __launch_bounds__(kCellBlock) void k_check_range(const T* __restrict__ phi, size_t n, int* flag) {
   int bad = 0;
@@ -185,6 +215,9 @@ void launch_check_range(Grid& g, const void* phi, size_t n) {
   const int blocks = (int)std::min<size_t>((n + kCellBlock - 1) / kCellBlock, 4096);
   hipLaunchKernelGGL(k_check_range<T>, dim3(blocks), dim3(kCellBlock), 0, g.stream, (const T*)phi, n, g.flag);
 }
+
+template void launch_region_speed<float>(Grid&, const int[6], double*, int);
+template void launch_region_speed<double>(Grid&, const int[6], double*, int);
 
 #define UF_INST(T)                                                                                            \
   template void launch_turb<T>(Grid&, const Params<T>&, void* const[3], const void*, const void*, void*, void*, \

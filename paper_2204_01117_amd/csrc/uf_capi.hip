@@ -207,6 +207,9 @@ void free_grid(Grid* g) {
   void* pp = g->partials;
   f(pp);
   g->partials = nullptr;
+  void* po = g->obj_part;
+  f(po);
+  g->obj_part = nullptr;
   void* pfl = g->flags;
   f(pfl);
   g->flags = nullptr;
@@ -679,9 +682,46 @@ uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_de
   UF_GUARD_END
 }
 
-uf_status uf_objective(uf_grid g, const void*, double*, void*) {
-  (void)g;
-  return fail(UF_ENOTIMPL, "uf_objective is not implemented in this library version");
+uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev) {
+  if (!g || !spec || !J_host) return fail(UF_EINVAL, "NULL argument");
+  if (dJ_dstate_dev)
+    return fail(UF_ENOTIMPL, "the state gradient of the objective (adjoint seed) is not implemented in this version");
+  const int nr = spec->nregions;
+  if (nr < 1 || nr > UF_MAX_REGIONS || !spec->boxes) return fail(UF_EINVAL, "region count out of range");
+  if (!std::isfinite(spec->u_target)) return fail(UF_EINVAL, "non-finite target speed");
+  const int n[3] = {g->L.nx, g->L.ny, g->L.nz};
+  for (int r = 0; r < nr; ++r)
+    for (int a = 0; a < 3; ++a) {
+      const int lo = spec->boxes[6 * r + 2 * a], hi = spec->boxes[6 * r + 2 * a + 1];
+      if (lo < 0 || hi > n[a] || lo >= hi) return fail(UF_EINVAL, "target region empty or outside the grid");
+    }
+  UF_GUARD_BEGIN
+  constexpr int kBlocks = 256;
+  if (!g->obj_part) g->obj_part = (double*)dalloc(sizeof(double) * kBlocks * UF_MAX_REGIONS);
+  std::vector<int> nb(nr);
+  for (int r = 0; r < nr; ++r) {
+    const int* b = spec->boxes + 6 * r;
+    const long long cells = (long long)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]);
+    nb[r] = (int)std::min<long long>(kBlocks, (cells + 255) / 256);
+    if (g->esize == 4) launch_region_speed<float>(*g, b, g->obj_part + (size_t)r * kBlocks, nb[r]);
+    else launch_region_speed<double>(*g, b, g->obj_part + (size_t)r * kBlocks, nb[r]);
+  }
+  check_launch();
+  std::vector<double> host((size_t)kBlocks * nr);
+  UF_HIP_CHECK(hipMemcpyAsync(host.data(), g->obj_part, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              g->stream));
+  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+  double J = 0.0;
+  for (int r = 0; r < nr; ++r) {
+    const int* b = spec->boxes + 6 * r;
+    double s = 0.0;
+    for (int q = 0; q < nb[r]; ++q) s += host[(size_t)r * kBlocks + q];
+    const double mean = s / ((double)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]));
+    J += (mean - spec->u_target) * (mean - spec->u_target);
+  }
+  *J_host = J;
+  return UF_OK;
+  UF_GUARD_END
 }
 
 uf_status uf_adjoint_step(uf_grid g, const void* const*, const void* const*, void* const*, void*) {

@@ -79,6 +79,7 @@ struct Grid {
   void* Qv = nullptr;
   int dpar = 0;
   double* partials = nullptr;   // 5 slots of part_stride partial sums
+  double* obj_part = nullptr;   // objective partials (allocated on first use)
   size_t part_stride = 0;
   size_t cg_nb = 0;             // blocks of the fine-grid CG kernels
   size_t cg_nb_rz = 0;          // blocks of the kernel that writes the r.z partials
@@ -132,6 +133,7 @@ template <class T> void launch_cg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void launch_cg_iteration(Grid& g, const Params<T>& P, int t);
 void launch_cg_status(Grid& g, int t_end);
 template <class T> void launch_apply(Grid& g, const Params<T>& P, int op, const void* x, void* y);
+template <class T> void launch_region_speed(Grid& g, const int box[6], double* part, int nblocks);
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);

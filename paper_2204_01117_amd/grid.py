@@ -87,6 +87,15 @@ class Grid:
         L.check(L.uf_apply_operator(self.handle, int(op), c_void_p(x.data_ptr()), c_void_p(y.data_ptr())))
         return y
 
+    def objective(self, regions, u_target):
+        """Target-region objective sum_i (mean speed of region i - u_target)^2 of
+        the current state; regions are boxes ((i0, i1), (j0, j1), (k0, k1))."""
+        spec, keep = L.make_objective_spec(regions, u_target)
+        J = ctypes.c_double()
+        L.check(L.uf_objective(self.handle, byref(spec), byref(J), None))
+        del keep
+        return J.value
+
     def timer_enable(self, kernels=()):
         """Time every launch of the named kernels (see TIMED_KERNELS)."""
         mask = 0

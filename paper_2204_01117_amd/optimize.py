@@ -1,0 +1,73 @@
+"""Forward-difference gradient descent over design parameters (Sec. 4).
+
+The paper's optimisation routine evaluates the objective by simulating the
+flow for a design, estimates each partial derivative from one more
+simulation with that parameter moved by eps (forward differences, so N + 1
+simulations per iteration for N parameters), and moves the parameters by
+lam times that gradient.  Printed with a plus sign, the update only
+decreases the objective with a minus sign; ``gradient_descent`` takes the
+descent form.  Defaults are the paper's eps = 0.1 and lam = 1.0.
+
+Every simulation runs on the GPU through :class:`Grid`; this module is host
+control flow only.
+"""
+import numpy as np
+
+
+class SimulationObjective:
+    """theta -> objective of the flow after ``nsteps`` steps.
+
+    Each call restores the state the grid held at construction (or
+    ``initial_state``), sets the porosity ``porosity_of(theta)`` (an
+    (nx, ny, nz) array, host or device), runs the steps and evaluates the
+    target-region objective on the GPU.
+    """
+
+    def __init__(self, grid, porosity_of, regions, u_target, nsteps, initial_state=None):
+        self.grid = grid
+        self.porosity_of = porosity_of
+        self.regions = [tuple(tuple(int(x) for x in lohi) for lohi in box) for box in regions]
+        self.u_target = float(u_target)
+        self.nsteps = int(nsteps)
+        st = initial_state if initial_state is not None else grid.state()
+        self.initial = {f: a.clone() if hasattr(a, "clone") else np.array(a) for f, a in st.items()}
+        self.calls = 0
+
+    def __call__(self, theta):
+        g = self.grid
+        g.set_state(self.initial)
+        g.set_porosity(self.porosity_of(np.asarray(theta, dtype=np.float64)))
+        if self.nsteps:
+            g.step(self.nsteps, stats=False)
+        self.calls += 1
+        return g.objective(self.regions, self.u_target)
+
+
+def forward_difference_gradient(J, theta, eps=0.1):
+    """(J(theta), dJ/dtheta) by forward differences: N + 1 evaluations."""
+    theta = np.array(theta, dtype=np.float64)
+    base = float(J(theta))
+    grad = np.empty_like(theta)
+    for n in range(theta.size):
+        moved = theta.copy()
+        moved.flat[n] += eps
+        grad.flat[n] = (float(J(moved)) - base) / eps
+    return base, grad
+
+
+def gradient_descent(J, theta0, eps=0.1, lam=1.0, iters=10, lower=None, upper=None, callback=None):
+    """Descent theta <- theta - lam * grad with forward-difference gradients,
+    optionally clipped to [lower, upper] (porosity parameters live in [0, 1]).
+    Returns (final theta, history), the history a list of (theta, J(theta),
+    grad) per iteration."""
+    theta = np.array(theta0, dtype=np.float64)
+    history = []
+    for it in range(int(iters)):
+        value, grad = forward_difference_gradient(J, theta, eps)
+        history.append((theta.copy(), value, grad))
+        if callback is not None:
+            callback(it, theta, value, grad)
+        theta = theta - lam * grad
+        if lower is not None or upper is not None:
+            theta = np.clip(theta, lower, upper)
+    return theta, history

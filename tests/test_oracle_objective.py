@@ -1,0 +1,78 @@
+"""Pins of the oracle's design objective (Sec. 4, target-region objective)
+and of its forward-difference gradient, against closed forms and brute force."""
+import math
+
+import numpy as np
+
+from oracle import cell_speed, region_means, region_objective, fd_gradient
+
+
+def faces(nx, ny, nz, u=0.0, v=0.0, w=0.0):
+    return (np.full((nx + 1, ny, nz), u), np.full((nx, ny + 1, nz), v), np.full((nx, ny, nz + 1), w))
+
+
+def test_uniform_flow_closed_form():
+    # every cell moves at |(3, 4, 0)| = 5, so each region mean is 5
+    u, v, w = faces(6, 5, 4, u=3.0, v=4.0)
+    regions = [((0, 6), (0, 5), (0, 4)), ((1, 3), (2, 4), (1, 2)), ((5, 6), (4, 5), (3, 4))]
+    assert np.allclose(region_means(u, v, w, regions), 5.0, rtol=0, atol=1e-15)
+    assert math.isclose(region_objective(u, v, w, regions, 0.55), 3 * (5.0 - 0.55) ** 2, rel_tol=1e-15)
+    # the target itself scores zero
+    assert region_objective(u, v, w, regions, 5.0) == 0.0
+
+
+def test_linear_profiles_have_known_region_means():
+    # face value a*i on the i-th x face: cell i holds a*(i + 1/2), so the mean
+    # over cells i0..i1-1 is a*(i0 + i1)/2; likewise for w along k
+    nx, ny, nz, a = 9, 4, 7, 0.25
+    u, v, w = faces(nx, ny, nz)
+    u[...] = a * np.arange(nx + 1)[:, None, None]
+    m = region_means(u, v, w, [((2, 7), (0, 4), (0, 7)), ((0, 1), (1, 2), (3, 5))])
+    assert np.allclose(m, [a * (2 + 7) / 2, a * 0.5], rtol=1e-15)
+    u[...] = 0.0
+    w[...] = -a * np.arange(nz + 1)[None, None, :]      # speed ignores the sign
+    m = region_means(u, v, w, [((0, 9), (0, 4), (3, 6))])
+    assert np.allclose(m, [a * (3 + 6) / 2], rtol=1e-15)
+
+
+def test_axes_are_not_exchanged():
+    # a y-face profile that grows along j leaves the x extent irrelevant
+    nx, ny, nz = 5, 8, 3
+    u, v, w = faces(nx, ny, nz)
+    v[...] = np.arange(ny + 1)[None, :, None].astype(float)
+    s = cell_speed(u, v, w)
+    assert s.shape == (nx, ny, nz)
+    assert np.allclose(s, (np.arange(ny) + 0.5)[None, :, None])
+
+
+def test_brute_force_on_tiny_random_state():
+    rng = np.random.default_rng(7)
+    nx, ny, nz = 4, 3, 5
+    u = rng.normal(size=(nx + 1, ny, nz))
+    v = rng.normal(size=(nx, ny + 1, nz))
+    w = rng.normal(size=(nx, ny, nz + 1))
+    regions = [((0, 4), (0, 3), (0, 5)), ((1, 2), (0, 2), (2, 5)), ((3, 4), (2, 3), (4, 5))]
+    J = 0.0
+    for (i0, i1), (j0, j1), (k0, k1) in regions:
+        tot, cnt = 0.0, 0
+        for i in range(i0, i1):
+            for j in range(j0, j1):
+                for k in range(k0, k1):
+                    cu = (u[i, j, k] + u[i + 1, j, k]) / 2
+                    cv = (v[i, j, k] + v[i, j + 1, k]) / 2
+                    cw = (w[i, j, k] + w[i, j, k + 1]) / 2
+                    tot += math.sqrt(cu * cu + cv * cv + cw * cw)
+                    cnt += 1
+        J += (tot / cnt - 0.55) ** 2
+    assert math.isclose(region_objective(u, v, w, regions, 0.55), J, rel_tol=1e-13)
+
+
+def test_forward_difference_of_a_quadratic_is_exact_closed_form():
+    # J = sum c_n (t_n - s_n)^2: (J(t + e e_n) - J(t))/e = 2 c_n (t_n - s_n) + c_n e
+    c = np.array([1.0, 2.5, 0.5])
+    s = np.array([0.3, -1.0, 2.0])
+    J = lambda t: float(np.sum(c * (t - s) ** 2))
+    t = np.array([1.0, 0.5, -0.25])
+    j0, g = fd_gradient(J, t, 0.1)
+    assert j0 == J(t)
+    assert np.allclose(g, 2 * c * (t - s) + c * 0.1, rtol=1e-12)
