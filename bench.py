@@ -59,6 +59,16 @@ ALG_BYTES_PER_CELL = {
     "turbulence": 32.0,   # read u, v, w, k, omega; write k, omega, nu_t
 }
 
+# Per step outside the pressure iterations: the face and cell kernels and
+# the right-hand side; per CG iteration: A d, the update and one multigrid
+# application (its coarse levels add about 1/7 of the level-0 kernels).
+STEP_FIXED_KERNELS = ("advect_fwd", "advect_corr", "diffuse", "drag", "project", "turbulence", "cg_init")
+ALG_FIXED_PER_CELL = sum(ALG_BYTES_PER_CELL[k] for k in STEP_FIXED_KERNELS)
+ALG_ITER_PER_CELL = (ALG_BYTES_PER_CELL["cg_Ad"] + ALG_BYTES_PER_CELL["cg_axpy"] +
+                     (ALG_BYTES_PER_CELL["mg_up0"] + ALG_BYTES_PER_CELL["mg_down0"]) * 8.0 / 7.0)
+STEP_PREFIXES = ("k_advect_", "k_diffuse", "k_drag", "k_project", "k_turbulence", "k_cg_init", "k_cg_start")
+ITER_PREFIXES = ("k_cg_Ad", "k_cg_axpy", "k_mg_", "k_cg_precond", "k_ai2_", "k_cg_status")
+
 # Kernels of the library by their profiler names (first match wins) and
 # the names the kernel timer and ALG_BYTES_PER_CELL use.
 PROFILE_NAMES = [
@@ -137,6 +147,25 @@ def traffic_for(kernel, ncells):
     if rec.get("source_sha256") != sources_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def step_traffic(iters_per_step, ms_per_step, ncells):
+    """HBM bytes of a whole step from the committed counter summary
+    (profiles/traffic_step_256x256x64.json) at this iteration count, with
+    the bandwidth they imply over the step's wall time; None when absent or
+    stale."""
+    path = os.path.join(ROOT, "profiles", "traffic_step_256x256x64.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != sources_hash():
+        return None
+    meas = rec["bytes_fixed_per_step"] + iters_per_step * rec["bytes_per_cg_iteration"]
+    alg = (ALG_FIXED_PER_CELL + iters_per_step * ALG_ITER_PER_CELL) * ncells
+    gbs = meas / (ms_per_step / 1e3) / 1e9
+    return {"bytes_per_step": meas, "alg_bytes_per_step": alg, "achieved_GBs": gbs,
+            "alg_GBs": alg / (ms_per_step / 1e3) / 1e9, "frac": gbs / HBM_PEAK_GBS,
+            "source": "profiles/traffic_step_256x256x64.json"}
 
 
 def sources_hash():
@@ -251,6 +280,39 @@ def traffic_summary(run_dir, command):
             "source_sha256": sources_hash(),
             "command": command,
         }
+    # the whole step: every dispatch of the step's kernels, split into the
+    # part per step and the part per CG iteration
+    def short(n):
+        return n.split("(")[0].replace("void ", "").replace("uf::", "")
+    tot = {"step": 0.0, "iter": 0.0}
+    steps = iters = 0
+    for disp, factor in ((fd, f_fetch), (wd, f_write)):
+        for name, _, v in disp:
+            n = short(name)
+            if n.startswith(STEP_PREFIXES):
+                tot["step"] += v * 1024.0 / factor
+            elif n.startswith(ITER_PREFIXES):
+                tot["iter"] += v * 1024.0 / factor
+    for name, _, _ in fd:
+        n = short(name)
+        steps += n.startswith("k_advect_fwd")
+        iters += n.startswith("k_cg_Ad")
+    ncell = 256 * 256 * 64
+    step_rec = {
+        "workload": "256x256x64", "steps": steps, "cg_iterations": iters,
+        "bytes_fixed_per_step": tot["step"] / max(steps, 1),
+        "bytes_per_cg_iteration": tot["iter"] / max(iters, 1),
+        "alg_bytes_fixed_per_step": ALG_FIXED_PER_CELL * ncell,
+        "alg_bytes_per_cg_iteration": ALG_ITER_PER_CELL * ncell,
+        "calibration": {"fetch_factor": f_fetch, "write_factor": f_write},
+        "source_sha256": sources_hash(), "command": command,
+    }
+    with open(os.path.join(ROOT, "profiles", "traffic_step_256x256x64.json"), "w") as f:
+        json.dump(step_rec, f, indent=1)
+        f.write("\n")
+    log("step traffic: %.3e B fixed per step (alg %.3e), %.3e B per CG iteration (alg %.3e)"
+        % (step_rec["bytes_fixed_per_step"], step_rec["alg_bytes_fixed_per_step"],
+           step_rec["bytes_per_cg_iteration"], step_rec["alg_bytes_per_cg_iteration"]))
     for bn, rec in out.items():
         path = os.path.join(ROOT, "profiles", "traffic_%s_256x256x64.json" % bn)
         with open(path, "w") as f:
@@ -471,6 +533,7 @@ def main():
         "config": {"workload": p["workload"], "grid": [nx, ny, nz], "dx_m": cfg["dx"], "dt_s": cfg["dt"],
                    "precond": "multigrid", "cg_tol": cfg["cg_tol"], "turbulence": "k-omega"},
         "cg_iters_per_step": iters / args.steps,
+        "cg_iters_max": st.get("cg_iters_max"),
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
@@ -478,6 +541,8 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
     }
     g.close()
+    if args.workload == "C1":
+        result["step_hbm"] = step_traffic(iters / args.steps, secs / args.steps * 1e3, ncells)
     result["stream_copy_GBs"] = copy_ceiling_gbs(torch)
     if not args.no_cpu_baseline and args.workload == "C1":
         state = {f: v.double().cpu().numpy() for f, v in st_state.items()}

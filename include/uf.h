@@ -111,6 +111,7 @@ typedef struct {
   int32_t converged;            /* 1 if every solve of the call converged       */
   int32_t nonfinite;            /* 1 if a NaN/Inf was seen in a solve           */
   float ms;                     /* wall time of the call on the stream          */
+  int32_t cg_iters_max;         /* largest per-step CG iteration count of the call */
 } uf_step_stats;
 
 /* Create a grid and its state.  The initial state has the inflow profile on

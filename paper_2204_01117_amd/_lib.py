@@ -30,7 +30,7 @@ class uf_config(ctypes.Structure):
 
 class uf_step_stats(ctypes.Structure):
     _fields_ = [("cg_iters", c_int32), ("cg_iters_total", c_int32), ("cg_rel_residual", c_double),
-                ("converged", c_int32), ("nonfinite", c_int32), ("ms", c_float)]
+                ("converged", c_int32), ("nonfinite", c_int32), ("ms", c_float), ("cg_iters_max", c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

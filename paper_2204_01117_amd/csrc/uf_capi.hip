@@ -280,7 +280,7 @@ SolveResult solve_pressure(Grid& g, const Params<T>& P, void* const Qs[3], const
 }
 
 struct StepAccum {
-  int iters_total = 0, last_iters = 0, noconv = 0, nonfinite = 0;
+  int iters_total = 0, last_iters = 0, max_iters = 0, noconv = 0, nonfinite = 0;
   double last_rel = 0;
 };
 
@@ -315,6 +315,7 @@ void run_steps(Grid& g, int nsteps, StepAccum& acc) {
       SolveResult r = solve_pressure<T>(g, P, g.Q[g.cur], nullptr);
       acc.iters_total += r.iters;
       acc.last_iters = r.iters;
+      acc.max_iters = std::max(acc.max_iters, r.iters);
       acc.last_rel = r.rel;
       acc.noconv |= r.noconv;
       acc.nonfinite |= r.nonfinite;
@@ -625,6 +626,7 @@ uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats) {
     stats->converged = !(acc.noconv || acc.nonfinite);
     stats->nonfinite = acc.nonfinite;
     stats->ms = ms;
+    stats->cg_iters_max = acc.max_iters;
   }
   if (acc.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the pressure solve");
   if (acc.noconv) return fail(UF_ENOCONV, "pressure CG reached cg_maxit");
@@ -653,6 +655,7 @@ uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_s
     std::memset(stats, 0, sizeof(*stats));
     stats->cg_iters = r.iters;
     stats->cg_iters_total = r.iters;
+    stats->cg_iters_max = r.iters;
     stats->cg_rel_residual = r.rel;
     stats->converged = !(r.noconv || r.nonfinite);
     stats->nonfinite = r.nonfinite;

@@ -101,3 +101,48 @@ def test_adjoint_reports_enotimpl_and_objective_rejects_null():
     import paper_2204_01117_amd as U
     assert U.uf_adjoint_step(None, None, None, None, None) == 7
     assert U.uf_objective(None, None, None, None) == 1
+
+
+def _header_structs():
+    import re
+    src = open(os.path.join(ROOT, "include", "uf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", src, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = " ".join(decl.split())
+            if not decl:
+                continue
+            parts = decl.split(",")
+            first = parts[0].split()
+            typ = " ".join(first[:-1]).replace("const ", "")
+            names = [first[-1]] + [p.strip() for p in parts[1:]]
+            for n in names:
+                ptr = n.startswith("*") or typ.endswith("*")
+                arr = re.search(r"\[(\d+)\]", n)
+                fields.append((n.strip("*").split("[")[0], typ.rstrip("*").strip(), ptr,
+                               int(arr.group(1)) if arr else 1))
+        out[name] = fields
+    return out
+
+
+def test_ctypes_structs_match_the_header():
+    """Field names, order, scalar types and array lengths of the ctypes
+    mirrors equal the C declarations (a layout mismatch would corrupt every
+    call)."""
+    import ctypes
+    import paper_2204_01117_amd as U
+    ctype_of = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "float": ctypes.c_float}
+    decl = _header_structs()
+    for cname, cls in (("uf_config", U.uf_config), ("uf_step_stats", U.uf_step_stats),
+                       ("uf_objective_spec", U.uf_objective_spec)):
+        hdr = decl[cname]
+        assert [f[0] for f in hdr] == [f[0] for f in cls._fields_], cname
+        for (name, typ, ptr, count), (_, ct) in zip(hdr, cls._fields_):
+            if ptr:
+                assert ct is ctypes.c_void_p or hasattr(ct, "contents") or issubclass(ct, ctypes._Pointer), name
+            elif count > 1:
+                assert ct._length_ == count and ct._type_ is ctype_of[typ], name
+            else:
+                assert ct is ctype_of[typ], (cname, name, typ, ct)
