@@ -30,20 +30,22 @@ def ray_crossings(points, verts, tris):
     v0 = verts[tris[:, 0]]
     e1 = verts[tris[:, 1]] - v0
     e2 = verts[tris[:, 2]] - v0
-    # P = D x E2 with D = (1, 0, 0): (0, -e2z, e2y); det = E1 . P
+    # P = D x E2 with D = (1, 0, 0): (0, -e2z, e2y); det = E1 . P; the
+    # published algorithm scales by the reciprocal of det
     det = -e1[:, 1] * e2[:, 2] + e1[:, 2] * e2[:, 1]
     ok = det != 0.0
     v0, e1, e2, det = v0[ok], e1[ok], e2[ok], det[ok]
+    inv = 1.0 / det
     count = np.zeros(len(p), dtype=np.int64)
     for n in range(len(det)):
         T = p - v0[n]
-        u = (-T[:, 1] * e2[n, 2] + T[:, 2] * e2[n, 1]) / det[n]
+        u = (-T[:, 1] * e2[n, 2] + T[:, 2] * e2[n, 1]) * inv[n]
         # Q = T x E1; v = D . Q; t = E2 . Q
         qx = T[:, 1] * e1[n, 2] - T[:, 2] * e1[n, 1]
         qy = T[:, 2] * e1[n, 0] - T[:, 0] * e1[n, 2]
         qz = T[:, 0] * e1[n, 1] - T[:, 1] * e1[n, 0]
-        v = qx / det[n]
-        t = (e2[n, 0] * qx + e2[n, 1] * qy + e2[n, 2] * qz) / det[n]
+        v = qx * inv[n]
+        t = (e2[n, 0] * qx + e2[n, 1] * qy + e2[n, 2] * qz) * inv[n]
         hit = (u >= 0.0) & (v >= 0.0) & (u + v <= 1.0) & (t > 0.0)
         count += hit
     return count
