@@ -132,6 +132,49 @@ uf_status uf_destroy_grid(uf_grid g);
  * if any value is NaN or outside [0, 1]. */
 uf_status uf_set_porosity(uf_grid g, const void* phi_dev);
 
+/* Objects as closed triangle meshes, for uf_voxelize (Sec. 3, urban model
+ * resolving: the design tool hands over building and tree surfaces as
+ * closed triangle meshes). */
+typedef struct {
+  int32_t nx, ny, nz;          /* grid cells, each >= 1; cell (i, j, k) spans
+                                  [i dx, (i+1) dx) x [j dy, (j+1) dy) x
+                                  [k dz, (k+1) dz), origin at the grid corner  */
+  double dx, dy, dz;           /* cell size, > 0 and finite                     */
+  int32_t sub;                 /* sub-samples per axis and cell, 1 .. 16        */
+  int32_t nobj;                /* objects, >= 0                                 */
+  const int32_t* tri_begin;    /* host, nobj + 1 offsets: object o owns the
+                                  triangles tri_begin[o] .. tri_begin[o+1]-1;
+                                  tri_begin[0] = 0, non-decreasing,
+                                  tri_begin[nobj] = ntris                       */
+  const double* phi_obj;       /* host, nobj porosities inside each object, in
+                                  [0, 1] (0 = solid building, e.g. 0.5 = tree) */
+  int32_t nverts, ntris;
+  const double* verts_dev;     /* device, nverts x 3 coordinates (x, y, z), m   */
+  const int32_t* tris_dev;     /* device, ntris x 3 vertex indices              */
+} uf_mesh_set;
+
+/* Cell porosity of mesh objects (Sec. 3, urban model resolving: a first
+ * pass takes each object's axis-aligned bounding box, a second decides
+ * inside or outside by the even-odd rule on a ray, whose surface crossings
+ * come from the Moller-Trumbore ray/triangle test; cut cells are resolved
+ * by uniform sub-division, phi = fraction of sub-samples outside).  The
+ * sub-samples of cell (i, j, k) sit at ((i + (s + 1/2)/sub) dx, ...), the
+ * rays run along +x, and an object with porosity phi_o gives the cell
+ * 1 - f_in (1 - phi_o) with f_in its fraction of samples inside; overlapping
+ * objects take the smallest value, and 1 is air.  Every cell that an
+ * object's bounding box overlaps is tested.
+ *
+ * phi_dev: nx*ny*nz values (dtype UF_F32 or UF_F64, z fastest, the layout
+ * uf_set_porosity takes), written on `stream` (a hipStream_t, NULL = null
+ * stream); the call synchronises the stream and allocates temporary device
+ * memory.  Inside counts are exact integers and the combination is a
+ * minimum, so the result is deterministic.  Errors, before phi is written:
+ * UF_EINVAL for a NULL or inconsistent argument, sizes or sub out of range,
+ * phi_obj outside [0, 1], a vertex index outside [0, nverts) or a
+ * non-finite coordinate.  UF_EINVAL after the fact (phi then unspecified)
+ * when a sample line crosses one object's surface more than 16 times. */
+uf_status uf_voxelize(const uf_mesh_set* mesh, int32_t dtype, void* phi_dev, void* stream);
+
 /* Overwrite one state field from a device array in the layout given by
  * uf_field_extent (checkpoint restore, parity tests).  Boundary values are
  * re-imposed after the copy.  UF_PHI is the same as uf_set_porosity. */

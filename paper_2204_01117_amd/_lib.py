@@ -52,6 +52,15 @@ def make_objective_spec(regions, u_target):
     return s, keep
 
 
+class uf_mesh_set(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+                ("dx", c_double), ("dy", c_double), ("dz", c_double),
+                ("sub", c_int32), ("nobj", c_int32),
+                ("tri_begin", POINTER(c_int32)), ("phi_obj", POINTER(c_double)),
+                ("nverts", c_int32), ("ntris", c_int32),
+                ("verts_dev", c_void_p), ("tris_dev", c_void_p)]
+
+
 class UFError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (STATUS.get(status, status), message))
@@ -81,6 +90,7 @@ _SIGS = {
     "uf_objective": (c_int32, [c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "uf_adjoint_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "uf_voxelize": (c_int32, [POINTER(uf_mesh_set), c_int32, c_void_p, c_void_p]),
     "uf_kernel_timer_enable": (c_int32, [c_void_p, ctypes.c_uint32]),
     "uf_kernel_timer_read": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "uf_last_error": (c_char_p, []),
@@ -102,6 +112,7 @@ uf_apply_operator = lib.uf_apply_operator
 uf_objective = lib.uf_objective
 uf_adjoint_step = lib.uf_adjoint_step
 uf_set_stream = lib.uf_set_stream
+uf_voxelize = lib.uf_voxelize
 uf_kernel_timer_enable = lib.uf_kernel_timer_enable
 uf_kernel_timer_read = lib.uf_kernel_timer_read
 TIMED_KERNELS = ("cg_Ad", "cg_axpy", "cg_precond", "mg_down0", "mg_up0", "mg_coarse", "cg_init",

@@ -1,0 +1,317 @@
+// Cell porosity of triangle-mesh objects (Sec. 3, urban model resolving):
+// a bounding-box pass per object, then even-odd ray casting with the
+// Moller-Trumbore ray/triangle test, with cut cells resolved by sub-sampling
+// each cell sub x sub x sub times.
+//
+// The rays run along +x.  All sample points of a cell column that share
+// (y, z) lie on one such line, so a thread casts ONE line per object: it
+// tests the object's triangles once, keeps the sorted x of the crossings,
+// and then classifies every sample on the line by the parity of the
+// crossings to its right.  A block owns a tile of (j, k) cells of one
+// object (sub^2 lines per cell, at most 256 lines), walks the object's
+// x-range in chunks of cells, and adds its lines' inside counts per cell in
+// LDS (integers: the result does not depend on the order).  Objects combine
+// by the minimum porosity (an integer atomic min on the bit pattern, valid
+// for non-negative values).
+//
+// Decisions (hit or miss, left or right of a crossing) are taken in FP64
+// with contraction off, so the inside counts are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "uf_internal.h"
+
+namespace uf {
+
+constexpr int kVoxThreads = 256;
+constexpr int kVoxChunk = 128;      // triangles staged in LDS at a time
+constexpr int kVoxMaxCross = 16;    // crossings kept per line and object
+constexpr int kVoxCellChunk = 8;    // x-cells counted per LDS round
+
+struct VoxItem {
+  int obj;
+  int i0, i1;     // x cells of the object's bounding box
+  int j0, j1;     // the tile's y cells
+  int k0, k1;     // the tile's z cells
+};
+
+__global__ __launch_bounds__(kVoxThreads) void k_mesh_check(const double* __restrict__ verts, int nverts,
+                                                           const int* __restrict__ tris, int ntris, int* flag) {
+  int bad = 0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntris; t += stride)
+    for (int c = 0; c < 3; ++c) {
+      const int v = tris[3 * t + c];
+      if (v < 0 || v >= nverts) bad |= 1;
+    }
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nverts; v += stride)
+    for (int c = 0; c < 3; ++c)
+      if (!isfinite(verts[3 * v + c])) bad |= 2;
+  if (bad) atomicOr(flag, bad);
+}
+
+// Bounding box of each object's triangle vertices: one block per object.
+__global__ __launch_bounds__(kVoxThreads) void k_mesh_aabb(const double* __restrict__ verts,
+                                                          const int* __restrict__ tris,
+                                                          const int* __restrict__ tri_begin, double* aabb) {
+  __shared__ double sh[6][kVoxThreads];
+  const int o = blockIdx.x;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int t = tri_begin[o] + threadIdx.x; t < tri_begin[o + 1]; t += blockDim.x)
+    for (int c = 0; c < 3; ++c) {
+      const double* p = verts + 3 * (size_t)tris[3 * t + c];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], p[a]);
+        hi[a] = fmax(hi[a], p[a]);
+      }
+    }
+  for (int a = 0; a < 3; ++a) {
+    sh[a][threadIdx.x] = lo[a];
+    sh[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int a = 0; a < 3; ++a) {
+        sh[a][threadIdx.x] = fmin(sh[a][threadIdx.x], sh[a][threadIdx.x + s]);
+        sh[3 + a][threadIdx.x] = fmax(sh[3 + a][threadIdx.x], sh[3 + a][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) aabb[6 * o + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+template <class T>
+__global__ __launch_bounds__(kVoxThreads) void k_fill_value(T* __restrict__ q, size_t n, T value) {
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
+    q[c] = value;
+}
+
+__device__ __forceinline__ void atomic_min_nonneg(float* p, float v) {
+  atomicMin(reinterpret_cast<unsigned int*>(p), __float_as_uint(v));
+}
+__device__ __forceinline__ void atomic_min_nonneg(double* p, double v) {
+  atomicMin(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+template <class T>
+__global__ __launch_bounds__(kVoxThreads) void k_voxelize(const VoxItem* __restrict__ items,
+                                                         const double* __restrict__ verts,
+                                                         const int* __restrict__ tris,
+                                                         const int* __restrict__ tri_begin,
+                                                         const double* __restrict__ phi_obj, int ny, int nz,
+                                                         double dx, double dy, double dz, int sub,
+                                                         T* __restrict__ phi, int* flag) {
+#pragma clang fp contract(off)
+  __shared__ double s_v0[3][kVoxChunk];
+  __shared__ double s_e1[3][kVoxChunk];
+  __shared__ double s_e2[3][kVoxChunk];
+  __shared__ double s_inv[kVoxChunk];
+  __shared__ int s_ok[kVoxChunk];
+  __shared__ double s_x[kVoxMaxCross][kVoxThreads];
+  __shared__ int s_cnt[kVoxCellChunk][kVoxThreads];
+
+  const VoxItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int cj = it.j1 - it.j0, ck = it.k1 - it.k0;
+  const int LK = ck * sub;
+  const int nlines = cj * sub * LK;
+  const bool act = tid < nlines;
+  const int lj = act ? tid / LK : 0, lk = act ? tid % LK : 0;
+  const int jc = it.j0 + lj / sub, kc = it.k0 + lk / sub;
+  const int cell = (lj / sub) * ck + lk / sub;   // the thread's cell within the tile
+  const double ys = ((double)jc + ((double)(lj % sub) + 0.5) / (double)sub) * dy;
+  const double zs = ((double)kc + ((double)(lk % sub) + 0.5) / (double)sub) * dz;
+
+  // crossings of this line with the object's surface
+  int n = 0;
+  bool over = false;
+  const int t_begin = tri_begin[it.obj], t_end = tri_begin[it.obj + 1];
+  for (int t0 = t_begin; t0 < t_end; t0 += kVoxChunk) {
+    const int m = min(kVoxChunk, t_end - t0);
+    __syncthreads();
+    if (tid < m) {
+      const int* tr = tris + 3 * (size_t)(t0 + tid);
+      const double* a = verts + 3 * (size_t)tr[0];
+      const double* b = verts + 3 * (size_t)tr[1];
+      const double* c = verts + 3 * (size_t)tr[2];
+      double e1[3], e2[3];
+      for (int q = 0; q < 3; ++q) {
+        s_v0[q][tid] = a[q];
+        e1[q] = b[q] - a[q];
+        e2[q] = c[q] - a[q];
+        s_e1[q][tid] = e1[q];
+        s_e2[q][tid] = e2[q];
+      }
+      // P = D x E2 with D = +x; det = E1 . P
+      const double det = -e1[1] * e2[2] + e1[2] * e2[1];
+      s_ok[tid] = det != 0.0;
+      s_inv[tid] = det != 0.0 ? 1.0 / det : 0.0;
+    }
+    __syncthreads();
+    if (act) {
+      for (int q = 0; q < m; ++q) {
+        if (!s_ok[q]) continue;
+        const double inv = s_inv[q];
+        const double ty = ys - s_v0[1][q], tz = zs - s_v0[2][q];
+        const double u = (-ty * s_e2[2][q] + tz * s_e2[1][q]) * inv;
+        const double qx = ty * s_e1[2][q] - tz * s_e1[1][q];
+        const double v = qx * inv;
+        if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
+          const double xc = s_v0[0][q] + u * s_e1[0][q] + v * s_e2[0][q];
+          if (n < kVoxMaxCross) s_x[n][tid] = xc;
+          else over = true;
+          ++n;
+        }
+      }
+    }
+  }
+  if (over) atomicOr(flag, 4);
+  n = min(n, kVoxMaxCross);
+  // sort the crossings (few per line)
+  for (int a = 1; a < n; ++a) {
+    const double x = s_x[a][tid];
+    int b = a - 1;
+    while (b >= 0 && s_x[b][tid] > x) {
+      s_x[b + 1][tid] = s_x[b][tid];
+      --b;
+    }
+    s_x[b + 1][tid] = x;
+  }
+
+  // walk the x cells: a sample is inside when an odd number of crossings
+  // lies to its right
+  const int ncell = cj * ck;
+  const double rsub3 = (double)sub * (double)sub * (double)sub;
+  const double solid = 1.0 - phi_obj[it.obj];
+  int p = 0;
+  for (int c0 = it.i0; c0 < it.i1; c0 += kVoxCellChunk) {
+    const int cm = min(kVoxCellChunk, it.i1 - c0);
+    for (int q = tid; q < kVoxCellChunk * kVoxThreads; q += kVoxThreads) (&s_cnt[0][0])[q] = 0;
+    __syncthreads();
+    if (act) {
+      for (int ii = 0; ii < cm; ++ii) {
+        int cnt = 0;
+        for (int s = 0; s < sub; ++s) {
+          const double xs = ((double)(c0 + ii) + ((double)s + 0.5) / (double)sub) * dx;
+          while (p < n && s_x[p][tid] <= xs) ++p;
+          cnt += (n - p) & 1;
+        }
+        if (cnt) atomicAdd(&s_cnt[ii][cell], cnt);
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < cm * ncell; q += kVoxThreads) {
+      const int ii = q / ncell, cc = q % ncell;
+      const int c = s_cnt[ii][cc];
+      if (!c) continue;
+      const double f = (double)c / rsub3;
+      const T val = (T)(1.0 - f * solid);
+      const int j = it.j0 + cc / ck, k = it.k0 + cc % ck;
+      atomic_min_nonneg(&phi[((size_t)(c0 + ii) * ny + j) * nz + k], val);
+    }
+    __syncthreads();
+  }
+}
+
+namespace {
+struct DevBuf {
+  void* p = nullptr;
+  explicit DevBuf(size_t bytes) {
+    if (bytes) UF_HIP_CHECK(hipMalloc(&p, bytes));
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  template <class X>
+  X* as() const {
+    return static_cast<X*>(p);
+  }
+};
+
+// Cells an interval overlaps, clamped to [0, n] in floating point first (so
+// far-away coordinates cannot overflow the integer conversion).
+int cell_lo(double v, double h, int n) { return (int)std::min(std::max(std::floor(v / h), 0.0), (double)n); }
+int cell_hi(double v, double h, int n) { return (int)std::max(std::min(std::ceil(v / h), (double)n), 0.0); }
+}  // namespace
+
+// Host side of uf_voxelize (arguments validated by the caller).  Returns an
+// empty string, or the message of an input error found on the device.
+std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream) {
+  const size_t ncells = (size_t)m.nx * m.ny * m.nz;
+  const int fill_blocks = (int)std::min<size_t>(4096, (ncells + kVoxThreads - 1) / kVoxThreads);
+  DevBuf flag(sizeof(int));
+  UF_HIP_CHECK(hipMemsetAsync(flag.p, 0, sizeof(int), stream));
+  if (m.ntris > 0 || m.nverts > 0) {
+    const int blocks = std::max(1, std::min(1024, (std::max(m.ntris, m.nverts) + kVoxThreads - 1) / kVoxThreads));
+    hipLaunchKernelGGL(k_mesh_check, dim3(blocks), dim3(kVoxThreads), 0, stream, m.verts_dev, m.nverts,
+                       m.tris_dev, m.ntris, flag.as<int>());
+  }
+  int hflag = 0;
+  UF_HIP_CHECK(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+  UF_HIP_CHECK(hipStreamSynchronize(stream));
+  if (hflag & 1) return "a triangle refers to a vertex index outside [0, nverts)";
+  if (hflag & 2) return "a vertex coordinate is not finite";
+
+  if (dtype == UF_F32)
+    hipLaunchKernelGGL(k_fill_value<float>, dim3(fill_blocks), dim3(kVoxThreads), 0, stream, (float*)phi, ncells,
+                       1.0f);
+  else
+    hipLaunchKernelGGL(k_fill_value<double>, dim3(fill_blocks), dim3(kVoxThreads), 0, stream, (double*)phi, ncells,
+                       1.0);
+  if (m.nobj == 0 || m.ntris == 0) {
+    UF_HIP_CHECK(hipGetLastError());
+    UF_HIP_CHECK(hipStreamSynchronize(stream));
+    return "";
+  }
+
+  // first pass: bounding boxes
+  DevBuf begin(sizeof(int) * (m.nobj + 1)), aabb(sizeof(double) * 6 * m.nobj), pobj(sizeof(double) * m.nobj);
+  UF_HIP_CHECK(hipMemcpyAsync(begin.p, m.tri_begin, sizeof(int) * (m.nobj + 1), hipMemcpyHostToDevice, stream));
+  UF_HIP_CHECK(hipMemcpyAsync(pobj.p, m.phi_obj, sizeof(double) * m.nobj, hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(k_mesh_aabb, dim3(m.nobj), dim3(kVoxThreads), 0, stream, m.verts_dev, m.tris_dev,
+                     begin.as<int>(), aabb.as<double>());
+  UF_HIP_CHECK(hipGetLastError());
+  std::vector<double> box(6 * (size_t)m.nobj);
+  UF_HIP_CHECK(hipMemcpyAsync(box.data(), aabb.p, sizeof(double) * box.size(), hipMemcpyDeviceToHost, stream));
+  UF_HIP_CHECK(hipStreamSynchronize(stream));
+
+  // second pass: one work item per object and tile of (j, k) cells
+  const int tc = std::max(1, 16 / m.sub);   // tile side in cells: (tc sub)^2 <= 256 lines
+  std::vector<VoxItem> items;
+  for (int o = 0; o < m.nobj; ++o) {
+    if (m.tri_begin[o + 1] == m.tri_begin[o]) continue;
+    const double* b = &box[6 * (size_t)o];
+    const int i0 = cell_lo(b[0], m.dx, m.nx), i1 = cell_hi(b[3], m.dx, m.nx);
+    const int j0 = cell_lo(b[1], m.dy, m.ny), j1 = cell_hi(b[4], m.dy, m.ny);
+    const int k0 = cell_lo(b[2], m.dz, m.nz), k1 = cell_hi(b[5], m.dz, m.nz);
+    if (i0 >= i1 || j0 >= j1 || k0 >= k1) continue;
+    for (int j = j0; j < j1; j += tc)
+      for (int k = k0; k < k1; k += tc)
+        items.push_back(VoxItem{o, i0, i1, j, std::min(j + tc, j1), k, std::min(k + tc, k1)});
+  }
+  if (!items.empty()) {
+    DevBuf ditems(sizeof(VoxItem) * items.size());
+    UF_HIP_CHECK(hipMemcpyAsync(ditems.p, items.data(), sizeof(VoxItem) * items.size(), hipMemcpyHostToDevice,
+                                stream));
+    if (dtype == UF_F32)
+      hipLaunchKernelGGL(k_voxelize<float>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream,
+                         ditems.as<VoxItem>(), m.verts_dev, m.tris_dev, begin.as<int>(), pobj.as<double>(), m.ny,
+                         m.nz, m.dx, m.dy, m.dz, m.sub, (float*)phi, flag.as<int>());
+    else
+      hipLaunchKernelGGL(k_voxelize<double>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream,
+                         ditems.as<VoxItem>(), m.verts_dev, m.tris_dev, begin.as<int>(), pobj.as<double>(), m.ny,
+                         m.nz, m.dx, m.dy, m.dz, m.sub, (double*)phi, flag.as<int>());
+    UF_HIP_CHECK(hipGetLastError());
+    UF_HIP_CHECK(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+    UF_HIP_CHECK(hipStreamSynchronize(stream));
+    if (hflag & 4) return "a sample line crosses an object's surface more than 16 times";
+  } else {
+    UF_HIP_CHECK(hipStreamSynchronize(stream));
+  }
+  return "";
+}
+
+}  // namespace uf

@@ -525,6 +525,34 @@ uf_status uf_kernel_timer_read(uf_grid g, int32_t kernel, double* total_ms, int6
   UF_GUARD_END
 }
 
+uf_status uf_voxelize(const uf_mesh_set* m, int32_t dtype, void* phi_dev, void* stream) {
+  if (!m || !phi_dev) return fail(UF_EINVAL, "NULL argument");
+  if (dtype != UF_F32 && dtype != UF_F64) return fail(UF_EINVAL, "dtype must be UF_F32 or UF_F64");
+  if (m->nx < 1 || m->ny < 1 || m->nz < 1) return fail(UF_EINVAL, "grid sizes must be >= 1");
+  if ((double)m->nx * m->ny * m->nz > 4.0e9) return fail(UF_EINVAL, "grid too large");
+  if (!finite_pos(m->dx) || !finite_pos(m->dy) || !finite_pos(m->dz))
+    return fail(UF_EINVAL, "cell sizes must be positive and finite");
+  if (m->sub < 1 || m->sub > 16) return fail(UF_EINVAL, "sub must be in 1..16");
+  if (m->nobj < 0 || m->nverts < 0 || m->ntris < 0) return fail(UF_EINVAL, "negative count");
+  if (m->nobj > 0 && (!m->tri_begin || !m->phi_obj)) return fail(UF_EINVAL, "NULL tri_begin or phi_obj");
+  if (m->ntris > 0 && (!m->tris_dev || !m->verts_dev)) return fail(UF_EINVAL, "NULL mesh arrays");
+  if (m->nobj > 0) {
+    if (m->tri_begin[0] != 0 || m->tri_begin[m->nobj] != m->ntris)
+      return fail(UF_EINVAL, "tri_begin must start at 0 and end at ntris");
+    for (int o = 0; o < m->nobj; ++o) {
+      if (m->tri_begin[o + 1] < m->tri_begin[o]) return fail(UF_EINVAL, "tri_begin must be non-decreasing");
+      if (!(m->phi_obj[o] >= 0.0 && m->phi_obj[o] <= 1.0)) return fail(UF_EINVAL, "phi_obj outside [0, 1]");
+    }
+  } else if (m->ntris != 0) {
+    return fail(UF_EINVAL, "triangles without objects");
+  }
+  UF_GUARD_BEGIN
+  const std::string err = voxelize_run(*m, dtype, phi_dev, (hipStream_t)stream);
+  if (!err.empty()) return fail(UF_EINVAL, err);
+  return UF_OK;
+  UF_GUARD_END
+}
+
 uf_status uf_set_stream(uf_grid g, void* stream) {
   if (!g) return fail(UF_EINVAL, "NULL grid");
   g->stream = (hipStream_t)stream;
