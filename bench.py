@@ -323,12 +323,13 @@ def traffic_summary(run_dir, command):
                rec["bytes_per_launch"] / rec["alg_bytes_per_launch"], f_fetch, f_write))
 
 
-def stats_summary(run_dir, command):
+def stats_summary(run_dir, command, out_name="kernels_256x256x64.md",
+                  title="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)"):
     files = glob.glob(os.path.join(run_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
         raise SystemExit("no *kernel_stats.csv under %s" % run_dir)
     rows = list(csv.DictReader(open(files[0])))
-    lines = ["# Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)", "",
+    lines = ["# " + title, "",
              "Command (from the repository root):", "", "    " + command, "",
              "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
     for r in rows:
@@ -350,7 +351,7 @@ def stats_summary(run_dir, command):
         for (name, blocks), d in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:24]:
             lines.append("| `%s` | %d | %d | %.2f | %.3f |" % (name, blocks, len(d), sum(d) / len(d) / 1e3,
                                                                sum(d) / 1e6))
-    path = os.path.join(ROOT, "profiles", "kernels_256x256x64.md")
+    path = os.path.join(ROOT, "profiles", out_name)
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     log("wrote", path)
@@ -448,6 +449,77 @@ def cpu_baseline(phi, cfg, state):
     }
 
 
+FP64_PEAK_TFLOPS = 78.6
+VOX_FLOPS_PER_TEST = 11   # FP64 operations of one line/triangle test (two
+                          # differences, the scaled u and v numerators, u + v)
+
+
+def voxelize_bench(steps, warmup, with_cpu):
+    """The mesh voxelizer on the 256x256x64 city (40 box buildings, 60 trees
+    as 16-sided prisms, 4x4x4 sub-samples per cell): wall time per call and
+    the ray-casting kernel against the FP64 ALU roof."""
+    import numpy as np
+    import torch
+    import paper_2204_01117_amd as U
+    from uf_layouts import preset, random_city
+    from uf_layouts.meshes import city_meshes
+    p = preset("C1")
+    cfg, lay = p["config"], p["layout"]
+    n, h, sub = (cfg["nx"], cfg["ny"], cfg["nz"]), (cfg["dx"], cfg["dy"], cfg["dz"]), 4
+    boxes, cyls, _ = random_city(*n, *h, lay["seed"], lay["n_boxes"], lay["n_trees"])
+    v, t, b, ph = city_meshes(boxes, cyls)
+    # algorithmic work: every sample line of every object tile against the
+    # object's triangles that are not parallel to the ray
+    tests = 0
+    for o in range(len(ph)):
+        tt = t[b[o]:b[o + 1]]
+        used = v[np.unique(tt)]
+        lo, hi = used.min(axis=0), used.max(axis=0)
+        r = [(max(int(np.floor(lo[a] / h[a])), 0), min(int(np.ceil(hi[a] / h[a])), n[a])) for a in range(3)]
+        if any(x0 >= x1 for x0, x1 in r):
+            continue
+        e1, e2 = v[tt[:, 1]] - v[tt[:, 0]], v[tt[:, 2]] - v[tt[:, 0]]
+        live = int(((-e1[:, 1] * e2[:, 2] + e1[:, 2] * e2[:, 1]) != 0).sum())
+        tests += (r[1][1] - r[1][0]) * sub * (r[2][1] - r[2][0]) * sub * live
+    dev = torch.device("cuda:0")
+    vd = torch.as_tensor(v).to(dev)
+    td = torch.as_tensor(t).to(dev)
+    for _ in range(warmup):
+        U.voxelize(n, h, vd, td, b, ph, sub=sub)
+    torch.cuda.synchronize()
+    cast = []
+    w0 = time.perf_counter()
+    for _ in range(steps):
+        tm = {}
+        U.voxelize(n, h, vd, td, b, ph, sub=sub, timing=tm)
+        cast.append(tm["cast_ms"])
+    torch.cuda.synchronize()
+    call_s = (time.perf_counter() - w0) / steps
+    k_s = sum(cast) / len(cast) / 1e3
+    ncell = n[0] * n[1] * n[2]
+    flops = VOX_FLOPS_PER_TEST * tests
+    res = {
+        "metric": "voxelized cells/s (mesh objects to cell porosity)", "value": ncell / call_s, "unit": "cells/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_call": call_s * 1e3, "higher_is_better": True,
+        "dtype": "f64 decisions, f32 porosity", "data": "synthetic seeded city meshes",
+        "config": {"workload": "256x256x64 dx=2m city: 40 box buildings (12 triangles), 60 trees "
+                               "(16-sided prisms, 64 triangles), 4x4x4 sub-samples per cell",
+                   "triangles": int(len(t)), "objects": int(len(ph))},
+        "roofline": {"bound": "alu", "kernel": "k_voxelize", "achieved": flops / k_s / 1e12,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": flops / k_s / 1e12 / FP64_PEAK_TFLOPS,
+                     "traffic": None, "avg_launch_us": k_s * 1e6, "line_triangle_tests": tests,
+                     "flops_per_test": VOX_FLOPS_PER_TEST},
+    }
+    if with_cpu:
+        from oracle.voxelize import voxelize as oracle_voxelize
+        c0 = time.perf_counter()
+        oracle_voxelize(n, h, v, t, b, ph, sub)
+        cs = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": ncell / cs, "unit": "cells/s", "cores": 1, "kind": "oracle",
+                               "sample": "the whole 256x256x64 city field (%.1f s), NumPy FP64 per-point rays" % cs}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,6 +528,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--precond-study", action="store_true")
+    ap.add_argument("--voxelize", action="store_true", help="time the mesh voxelizer instead of the step")
+    ap.add_argument("--stats-out", default="kernels_256x256x64.md", help="file name under profiles/")
+    ap.add_argument("--stats-title", default="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)")
     ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab"])
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
@@ -464,7 +539,7 @@ def main():
     if args.traffic_summary:
         return traffic_summary(args.traffic_summary, args.command)
     if args.stats_summary:
-        return stats_summary(args.stats_summary, args.command)
+        return stats_summary(args.stats_summary, args.command, args.stats_out, args.stats_title)
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
               "(multi-GPU runs would shard independent cases or x-slabs of the grid)" % args.gpus,
@@ -475,6 +550,8 @@ def main():
         return traffic_probe()
     if args.precond_study:
         return precond_study()
+    if args.voxelize:
+        return voxelize_bench(args.steps, args.warmup, not args.no_cpu_baseline)
 
     import torch
     import paper_2204_01117_amd as U

@@ -172,8 +172,11 @@ typedef struct {
  * UF_EINVAL for a NULL or inconsistent argument, sizes or sub out of range,
  * phi_obj outside [0, 1], a vertex index outside [0, nverts) or a
  * non-finite coordinate.  UF_EINVAL after the fact (phi then unspecified)
- * when a sample line crosses one object's surface more than 16 times. */
-uf_status uf_voxelize(const uf_mesh_set* mesh, int32_t dtype, void* phi_dev, void* stream);
+ * when a sample line crosses one object's surface more than 14 times. */
+uf_status uf_voxelize(const uf_mesh_set* mesh, int32_t dtype, void* phi_dev, void* stream,
+                      double* cast_ms);
+/* cast_ms (nullable): receives the duration of the ray-casting kernel
+ * (events carried in its dispatch), 0 when no object meets the grid. */
 
 /* Overwrite one state field from a device array in the layout given by
  * uf_field_extent (checkpoint restore, parity tests).  Boundary values are

@@ -90,7 +90,7 @@ _SIGS = {
     "uf_objective": (c_int32, [c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "uf_adjoint_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
-    "uf_voxelize": (c_int32, [POINTER(uf_mesh_set), c_int32, c_void_p, c_void_p]),
+    "uf_voxelize": (c_int32, [POINTER(uf_mesh_set), c_int32, c_void_p, c_void_p, POINTER(c_double)]),
     "uf_kernel_timer_enable": (c_int32, [c_void_p, ctypes.c_uint32]),
     "uf_kernel_timer_read": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "uf_last_error": (c_char_p, []),

@@ -26,9 +26,18 @@
 namespace uf {
 
 constexpr int kVoxThreads = 256;
-constexpr int kVoxChunk = 128;      // triangles staged in LDS at a time
-constexpr int kVoxMaxCross = 16;    // crossings kept per line and object
-constexpr int kVoxCellChunk = 8;    // x-cells counted per LDS round
+constexpr int kVoxMaxCross = 14;    // crossings kept per line and object
+constexpr int kVoxCellChunk = 4;    // x-cells counted per LDS round
+constexpr int kVoxChunk = 64;       // triangle records staged in LDS at a time
+constexpr int kTriWords = 11;       // doubles of a record the ray test reads
+
+// One triangle as the ray test uses it: the first vertex, the two edges
+// from it and the reciprocal of the determinant for rays along +x (ok = 0
+// for a triangle parallel to them).  Written once per call, then staged in
+// LDS by the blocks, 64 records at a time, with coalesced loads.
+struct alignas(128) TriRec {
+  double v0[3], e1[3], e2[3], inv, ok, pad[5];
+};
 
 struct VoxItem {
   int obj;
@@ -83,6 +92,29 @@ __global__ __launch_bounds__(kVoxThreads) void k_mesh_aabb(const double* __restr
   if (threadIdx.x < 6) aabb[6 * o + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+__global__ __launch_bounds__(kVoxThreads) void k_mesh_prep(const double* __restrict__ verts,
+                                                          const int* __restrict__ tris, int ntris,
+                                                          TriRec* __restrict__ pre) {
+#pragma clang fp contract(off)
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntris; t += gridDim.x * blockDim.x) {
+    const double* a = verts + 3 * (size_t)tris[3 * t];
+    const double* b = verts + 3 * (size_t)tris[3 * t + 1];
+    const double* c = verts + 3 * (size_t)tris[3 * t + 2];
+    TriRec r;
+    for (int q = 0; q < 3; ++q) {
+      r.v0[q] = a[q];
+      r.e1[q] = b[q] - a[q];
+      r.e2[q] = c[q] - a[q];
+    }
+    // P = D x E2 with D = +x; det = E1 . P
+    const double det = -r.e1[1] * r.e2[2] + r.e1[2] * r.e2[1];
+    r.ok = det != 0.0 ? 1.0 : 0.0;
+    r.inv = det != 0.0 ? 1.0 / det : 0.0;
+    for (int q = 0; q < 5; ++q) r.pad[q] = 0.0;
+    pre[t] = r;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(kVoxThreads) void k_fill_value(T* __restrict__ q, size_t n, T value) {
   for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x)
@@ -98,20 +130,15 @@ __device__ __forceinline__ void atomic_min_nonneg(double* p, double v) {
 
 template <class T>
 __global__ __launch_bounds__(kVoxThreads) void k_voxelize(const VoxItem* __restrict__ items,
-                                                         const double* __restrict__ verts,
-                                                         const int* __restrict__ tris,
+                                                         const TriRec* __restrict__ pre,
                                                          const int* __restrict__ tri_begin,
                                                          const double* __restrict__ phi_obj, int ny, int nz,
                                                          double dx, double dy, double dz, int sub,
                                                          T* __restrict__ phi, int* flag) {
 #pragma clang fp contract(off)
-  __shared__ double s_v0[3][kVoxChunk];
-  __shared__ double s_e1[3][kVoxChunk];
-  __shared__ double s_e2[3][kVoxChunk];
-  __shared__ double s_inv[kVoxChunk];
-  __shared__ int s_ok[kVoxChunk];
   __shared__ double s_x[kVoxMaxCross][kVoxThreads];
   __shared__ int s_cnt[kVoxCellChunk][kVoxThreads];
+  __shared__ double s_tri[kVoxChunk][kTriWords + 1];
 
   const VoxItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
@@ -131,36 +158,22 @@ __global__ __launch_bounds__(kVoxThreads) void k_voxelize(const VoxItem* __restr
   const int t_begin = tri_begin[it.obj], t_end = tri_begin[it.obj + 1];
   for (int t0 = t_begin; t0 < t_end; t0 += kVoxChunk) {
     const int m = min(kVoxChunk, t_end - t0);
-    __syncthreads();
-    if (tid < m) {
-      const int* tr = tris + 3 * (size_t)(t0 + tid);
-      const double* a = verts + 3 * (size_t)tr[0];
-      const double* b = verts + 3 * (size_t)tr[1];
-      const double* c = verts + 3 * (size_t)tr[2];
-      double e1[3], e2[3];
-      for (int q = 0; q < 3; ++q) {
-        s_v0[q][tid] = a[q];
-        e1[q] = b[q] - a[q];
-        e2[q] = c[q] - a[q];
-        s_e1[q][tid] = e1[q];
-        s_e2[q][tid] = e2[q];
-      }
-      // P = D x E2 with D = +x; det = E1 . P
-      const double det = -e1[1] * e2[2] + e1[2] * e2[1];
-      s_ok[tid] = det != 0.0;
-      s_inv[tid] = det != 0.0 ? 1.0 / det : 0.0;
+    __syncthreads();   // the previous chunk is done with
+    for (int w = tid; w < m * kTriWords; w += kVoxThreads) {
+      const int q = w / kTriWords, f = w % kTriWords;
+      s_tri[q][f] = reinterpret_cast<const double*>(pre + t0 + q)[f];
     }
     __syncthreads();
     if (act) {
       for (int q = 0; q < m; ++q) {
-        if (!s_ok[q]) continue;
-        const double inv = s_inv[q];
-        const double ty = ys - s_v0[1][q], tz = zs - s_v0[2][q];
-        const double u = (-ty * s_e2[2][q] + tz * s_e2[1][q]) * inv;
-        const double qx = ty * s_e1[2][q] - tz * s_e1[1][q];
-        const double v = qx * inv;
+        const double* r = s_tri[q];   // v0 (0..2), e1 (3..5), e2 (6..8), inv, ok
+        if (r[10] == 0.0) continue;
+        const double ty = ys - r[1], tz = zs - r[2];
+        const double u = (-ty * r[8] + tz * r[7]) * r[9];
+        const double qx = ty * r[5] - tz * r[4];
+        const double v = qx * r[9];
         if (u >= 0.0 && v >= 0.0 && u + v <= 1.0) {
-          const double xc = s_v0[0][q] + u * s_e1[0][q] + v * s_e2[0][q];
+          const double xc = r[0] + u * r[3] + v * r[6];
           if (n < kVoxMaxCross) s_x[n][tid] = xc;
           else over = true;
           ++n;
@@ -239,7 +252,8 @@ int cell_hi(double v, double h, int n) { return (int)std::max(std::min(std::ceil
 
 // Host side of uf_voxelize (arguments validated by the caller).  Returns an
 // empty string, or the message of an input error found on the device.
-std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream) {
+std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream, double* cast_ms) {
+  if (cast_ms) *cast_ms = 0.0;
   const size_t ncells = (size_t)m.nx * m.ny * m.nz;
   const int fill_blocks = (int)std::min<size_t>(4096, (ncells + kVoxThreads - 1) / kVoxThreads);
   DevBuf flag(sizeof(int));
@@ -267,8 +281,11 @@ std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t
     return "";
   }
 
-  // first pass: bounding boxes
+  // first pass: bounding boxes (and the triangles in the form the ray test reads)
   DevBuf begin(sizeof(int) * (m.nobj + 1)), aabb(sizeof(double) * 6 * m.nobj), pobj(sizeof(double) * m.nobj);
+  DevBuf pre(sizeof(TriRec) * (size_t)m.ntris);
+  hipLaunchKernelGGL(k_mesh_prep, dim3(std::max(1, std::min(4096, (m.ntris + kVoxThreads - 1) / kVoxThreads))),
+                     dim3(kVoxThreads), 0, stream, m.verts_dev, m.tris_dev, m.ntris, pre.as<TriRec>());
   UF_HIP_CHECK(hipMemcpyAsync(begin.p, m.tri_begin, sizeof(int) * (m.nobj + 1), hipMemcpyHostToDevice, stream));
   UF_HIP_CHECK(hipMemcpyAsync(pobj.p, m.phi_obj, sizeof(double) * m.nobj, hipMemcpyHostToDevice, stream));
   hipLaunchKernelGGL(k_mesh_aabb, dim3(m.nobj), dim3(kVoxThreads), 0, stream, m.verts_dev, m.tris_dev,
@@ -296,18 +313,28 @@ std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t
     DevBuf ditems(sizeof(VoxItem) * items.size());
     UF_HIP_CHECK(hipMemcpyAsync(ditems.p, items.data(), sizeof(VoxItem) * items.size(), hipMemcpyHostToDevice,
                                 stream));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (cast_ms)
+      for (auto& e : ev) UF_HIP_CHECK(hipEventCreate(&e));
     if (dtype == UF_F32)
-      hipLaunchKernelGGL(k_voxelize<float>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream,
-                         ditems.as<VoxItem>(), m.verts_dev, m.tris_dev, begin.as<int>(), pobj.as<double>(), m.ny,
-                         m.nz, m.dx, m.dy, m.dz, m.sub, (float*)phi, flag.as<int>());
+      hipExtLaunchKernelGGL(k_voxelize<float>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream, ev[0],
+                            ev[1], 0, ditems.as<VoxItem>(), pre.as<TriRec>(), begin.as<int>(),
+                            pobj.as<double>(), m.ny, m.nz, m.dx, m.dy, m.dz, m.sub, (float*)phi, flag.as<int>());
     else
-      hipLaunchKernelGGL(k_voxelize<double>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream,
-                         ditems.as<VoxItem>(), m.verts_dev, m.tris_dev, begin.as<int>(), pobj.as<double>(), m.ny,
-                         m.nz, m.dx, m.dy, m.dz, m.sub, (double*)phi, flag.as<int>());
+      hipExtLaunchKernelGGL(k_voxelize<double>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream, ev[0],
+                            ev[1], 0, ditems.as<VoxItem>(), pre.as<TriRec>(), begin.as<int>(),
+                            pobj.as<double>(), m.ny, m.nz, m.dx, m.dy, m.dz, m.sub, (double*)phi, flag.as<int>());
     UF_HIP_CHECK(hipGetLastError());
     UF_HIP_CHECK(hipMemcpyAsync(&hflag, flag.p, sizeof(int), hipMemcpyDeviceToHost, stream));
     UF_HIP_CHECK(hipStreamSynchronize(stream));
-    if (hflag & 4) return "a sample line crosses an object's surface more than 16 times";
+    if (cast_ms) {
+      float ms = 0.0f;
+      const hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      for (auto& x : ev) (void)hipEventDestroy(x);
+      UF_HIP_CHECK(e);
+      *cast_ms = ms;
+    }
+    if (hflag & 4) return "a sample line crosses an object's surface more than 14 times";
   } else {
     UF_HIP_CHECK(hipStreamSynchronize(stream));
   }

@@ -525,7 +525,7 @@ uf_status uf_kernel_timer_read(uf_grid g, int32_t kernel, double* total_ms, int6
   UF_GUARD_END
 }
 
-uf_status uf_voxelize(const uf_mesh_set* m, int32_t dtype, void* phi_dev, void* stream) {
+uf_status uf_voxelize(const uf_mesh_set* m, int32_t dtype, void* phi_dev, void* stream, double* cast_ms) {
   if (!m || !phi_dev) return fail(UF_EINVAL, "NULL argument");
   if (dtype != UF_F32 && dtype != UF_F64) return fail(UF_EINVAL, "dtype must be UF_F32 or UF_F64");
   if (m->nx < 1 || m->ny < 1 || m->nz < 1) return fail(UF_EINVAL, "grid sizes must be >= 1");
@@ -547,7 +547,7 @@ uf_status uf_voxelize(const uf_mesh_set* m, int32_t dtype, void* phi_dev, void* 
     return fail(UF_EINVAL, "triangles without objects");
   }
   UF_GUARD_BEGIN
-  const std::string err = voxelize_run(*m, dtype, phi_dev, (hipStream_t)stream);
+  const std::string err = voxelize_run(*m, dtype, phi_dev, (hipStream_t)stream, cast_ms);
   if (!err.empty()) return fail(UF_EINVAL, err);
   return UF_OK;
   UF_GUARD_END

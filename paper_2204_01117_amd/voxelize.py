@@ -10,12 +10,14 @@ import numpy as np
 from . import _lib as L
 
 
-def voxelize(n, h, verts, tris, tri_begin, phi_obj, sub=4, dtype="f32", device="cuda:0"):
+def voxelize(n, h, verts, tris, tri_begin, phi_obj, sub=4, dtype="f32", device="cuda:0", timing=None):
     """Porosity [nx, ny, nz] (a torch tensor on ``device``) of the objects.
 
     ``verts`` [V, 3] and ``tris`` [T, 3] (host arrays or device tensors),
     ``tri_begin`` [nobj + 1] and ``phi_obj`` [nobj] (host) as in
-    ``uf_mesh_set``.  Runs on torch's current stream of ``device``."""
+    ``uf_mesh_set``.  Runs on torch's current stream of ``device``.  Pass a
+    dict as ``timing`` to receive the ray-casting kernel's milliseconds
+    under "cast_ms"."""
     import torch
     dev = torch.device(device)
     tdt = torch.float32 if dtype in ("f32", 0) else torch.float64
@@ -38,6 +40,9 @@ def voxelize(n, h, verts, tris, tri_begin, phi_obj, sub=4, dtype="f32", device="
     m.tris_dev = t.data_ptr() if t.numel() else None
     out = torch.empty(tuple(int(x) for x in n), dtype=tdt, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
+    ms = ctypes.c_double()
     L.check(L.uf_voxelize(ctypes.byref(m), 0 if tdt == torch.float32 else 1, ctypes.c_void_p(out.data_ptr()),
-                          ctypes.c_void_p(stream)))
+                          ctypes.c_void_p(stream), ctypes.byref(ms) if timing is not None else None))
+    if timing is not None:
+        timing["cast_ms"] = ms.value
     return out
