@@ -520,6 +520,51 @@ def voxelize_bench(steps, warmup, with_cpu):
     print(json.dumps(res), flush=True)
 
 
+def batch_bench(steps, warmup):
+    """The sixteen wind-direction cases (8 directions x 2 variants on uneven
+    grids, each on its own stream): the same steps taken case after case
+    with uf_step, then all cases together with uf_step_batch."""
+    import torch
+    import paper_2204_01117_amd as U
+    from uf_layouts import preset, preset_porosity
+    p = preset("C3")
+    cases = [preset_porosity(p, case=c) for c in range(16)]
+    grids = []
+    for phi, cfg in cases:
+        g = U.Grid(cfg, stream=torch.cuda.Stream())
+        g.set_porosity(torch.as_tensor(phi))
+        grids.append(g)
+    cells = sum(c["nx"] * c["ny"] * c["nz"] for _, c in cases)
+    log("C3: %d cases, %d cells in all, shapes %s" % (len(grids), cells,
+        sorted({(c["nx"], c["ny"], c["nz"]) for _, c in cases})))
+    U.step_batch(grids, warmup)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for g in grids:
+        g.step(steps, stats=False)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - w0
+    log("sequential: %.3f ms per step of all cases" % (seq_s / steps * 1e3))
+    w0 = time.perf_counter()
+    st = U.step_batch(grids, steps)
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - w0
+    iters = sum(s["cg_iters_total"] for s in st) / (steps * len(grids))
+    res = {
+        "metric": "cell-updates/s per full RANS step (incl. pressure solve), all cases",
+        "value": cells * steps / bat_s, "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": bat_s / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic seeded city layouts",
+        "config": {"workload": p["workload"] + " (128x128x48, 192x160x48, 256x256x64; 2 m, dt 0.09 s)",
+                   "cases": len(grids), "cells": cells},
+        "sequential_value": cells * steps / seq_s, "batched_speedup": seq_s / bat_s,
+        "cg_iters_per_step": iters,
+    }
+    for g in grids:
+        g.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,7 +576,7 @@ def main():
     ap.add_argument("--voxelize", action="store_true", help="time the mesh voxelizer instead of the step")
     ap.add_argument("--stats-out", default="kernels_256x256x64.md", help="file name under profiles/")
     ap.add_argument("--stats-title", default="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)")
-    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab"])
+    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "C3"])
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
@@ -552,6 +597,8 @@ def main():
         return precond_study()
     if args.voxelize:
         return voxelize_bench(args.steps, args.warmup, not args.no_cpu_baseline)
+    if args.workload == "C3":
+        return batch_bench(args.steps, args.warmup)
 
     import torch
     import paper_2204_01117_amd as U

@@ -201,6 +201,19 @@ int64_t uf_field_extent(const uf_config* cfg, int32_t field, int32_t dims[3]);
  * the state has advanced in either case. */
 uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats);
 
+/* Advance n independent grids by nsteps each (several cases at once: the
+ * wind directions and design variants of Sec. 4 and 5, or the N + 1
+ * simulations of a forward-difference gradient).  Each grid computes exactly
+ * what uf_step computes for it, bit for bit; the work of all grids is
+ * enqueued from the calling thread in rounds (every grid's step up to its
+ * first pressure-CG chunk, then each grid's completion), so that one grid's
+ * host round trip overlaps the others' kernels.  Give each grid its own
+ * stream (uf_config.stream) for the kernels to overlap.  stats, if non-NULL,
+ * has n entries and synchronises like uf_step.  UF_EINVAL (nothing
+ * enqueued) for NULL, n < 1, a NULL grid or a grid listed twice; UF_ENOCONV
+ * or UF_ENONFINITE as uf_step, naming the first such batch entry. */
+uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step_stats* stats);
+
 /* Solve A x = b with the grid's pressure operator (A = -L_h with the
  * boundary rows described above; SPD), preconditioner and tolerance; x_dev
  * holds the initial guess on entry and the solution on exit.  b_dev and

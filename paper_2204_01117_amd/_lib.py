@@ -90,6 +90,7 @@ _SIGS = {
     "uf_objective": (c_int32, [c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "uf_adjoint_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "uf_step_batch": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p]),
     "uf_voxelize": (c_int32, [POINTER(uf_mesh_set), c_int32, c_void_p, c_void_p, POINTER(c_double)]),
     "uf_kernel_timer_enable": (c_int32, [c_void_p, ctypes.c_uint32]),
     "uf_kernel_timer_read": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
@@ -112,6 +113,7 @@ uf_apply_operator = lib.uf_apply_operator
 uf_objective = lib.uf_objective
 uf_adjoint_step = lib.uf_adjoint_step
 uf_set_stream = lib.uf_set_stream
+uf_step_batch = lib.uf_step_batch
 uf_voxelize = lib.uf_voxelize
 uf_kernel_timer_enable = lib.uf_kernel_timer_enable
 uf_kernel_timer_read = lib.uf_kernel_timer_read

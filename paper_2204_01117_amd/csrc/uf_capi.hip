@@ -235,11 +235,14 @@ void free_grid(Grid* g) {
   mg_free(*g);
 }
 
-void sync_status(Grid& g) {
+// Copy the CG status to the host behind the work enqueued so far; the host
+// waits for it in wait_status.
+void post_status(Grid& g) {
   UF_HIP_CHECK(hipMemcpyAsync(g.st_host, g.st, sizeof(CgState), hipMemcpyDeviceToHost, g.stream));
   UF_HIP_CHECK(hipEventRecord(g.ev_status, g.stream));
-  UF_HIP_CHECK(hipEventSynchronize(g.ev_status));
 }
+
+void wait_status(Grid& g) { UF_HIP_CHECK(hipEventSynchronize(g.ev_status)); }
 
 struct SolveResult {
   int iters = 0;
@@ -253,21 +256,37 @@ struct SolveResult {
 // previous solve, so a steady run needs one host round trip per solve;
 // iterations enqueued past convergence return at once.
 template <class T>
-SolveResult solve_pressure(Grid& g, const Params<T>& P, void* const Qs[3], const void* b) {
+void solve_chunk(Grid& g, const Params<T>& P) {
+  const int maxit = g.cfg.cg_maxit;
+  int t = g.cg_t;
+  int m = t == 0 ? (g.last_iters > 0 ? g.last_iters : 4) : std::max(1, t / 8);
+  if (t + m > maxit) m = maxit - t;
+  if (m < 1) m = 1;
+  for (int q = 0; q < m; ++q, ++t) launch_cg_iteration<T>(g, P, t);
+  launch_cg_status(g, t);
+  check_launch();
+  post_status(g);
+  g.cg_t = t;
+}
+
+// Enqueue the start of a solve and its first chunk (no host wait).
+template <class T>
+void solve_begin(Grid& g, const Params<T>& P, void* const Qs[3], const void* b) {
   launch_cg_start<T>(g, P, Qs, b);
   launch_cg_precond<T>(g, P, 0);
   check_launch();
+  g.cg_t = 0;
+  solve_chunk<T>(g, P);
+}
+
+// Wait for the posted status; enqueue further chunks until the solve ends.
+template <class T>
+SolveResult solve_end(Grid& g, const Params<T>& P) {
   const int maxit = g.cfg.cg_maxit;
-  int t = 0;
   while (true) {
-    int m = t == 0 ? (g.last_iters > 0 ? g.last_iters : 4) : std::max(1, t / 8);
-    if (t + m > maxit) m = maxit - t;
-    if (m < 1) m = 1;
-    for (int q = 0; q < m; ++q, ++t) launch_cg_iteration<T>(g, P, t);
-    launch_cg_status(g, t);
-    check_launch();
-    sync_status(g);
-    if (g.st_host->done || t >= maxit) break;
+    wait_status(g);
+    if (g.st_host->done || g.cg_t >= maxit) break;
+    solve_chunk<T>(g, P);
   }
   SolveResult res;
   const CgState& s = *g.st_host;
@@ -277,6 +296,12 @@ SolveResult solve_pressure(Grid& g, const Params<T>& P, void* const Qs[3], const
   res.nonfinite = s.nonfinite;
   g.last_iters = s.iter;
   return res;
+}
+
+template <class T>
+SolveResult solve_pressure(Grid& g, const Params<T>& P, void* const Qs[3], const void* b) {
+  solve_begin<T>(g, P, Qs, b);
+  return solve_end<T>(g, P);
 }
 
 struct StepAccum {
@@ -290,11 +315,13 @@ int free_set(const Grid& g, int avoid) {
   return -1;
 }
 
+// A step in two halves: step_begin enqueues everything up to the first
+// chunk of the pressure solve; step_end waits for the solve and enqueues the
+// projection and the turbulence model.
 template <class T>
-void run_steps(Grid& g, int nsteps, StepAccum& acc) {
-  const Params<T> P = make_params<T>(g);
+void step_begin(Grid& g, const Params<T>& P) {
   const int st = g.cfg.stages;
-  for (int n = 0; n < nsteps; ++n) {
+  {
     if (st & UF_STAGE_ADVECT) {
       const int hat = free_set(g, -1), out = free_set(g, hat);
       launch_advect<T>(g, P, g.Q[g.cur], g.Q[hat], g.Q[out]);
@@ -311,8 +338,16 @@ void run_steps(Grid& g, int nsteps, StepAccum& acc) {
       g.cur = out;
     }
     check_launch();
+    if (st & UF_STAGE_PROJECT) solve_begin<T>(g, P, g.Q[g.cur], nullptr);
+  }
+}
+
+template <class T>
+void step_end(Grid& g, const Params<T>& P, StepAccum& acc) {
+  const int st = g.cfg.stages;
+  {
     if (st & UF_STAGE_PROJECT) {
-      SolveResult r = solve_pressure<T>(g, P, g.Q[g.cur], nullptr);
+      SolveResult r = solve_end<T>(g, P);
       acc.iters_total += r.iters;
       acc.last_iters = r.iters;
       acc.max_iters = std::max(acc.max_iters, r.iters);
@@ -330,6 +365,25 @@ void run_steps(Grid& g, int nsteps, StepAccum& acc) {
     }
     check_launch();
   }
+}
+
+template <class T>
+void run_steps(Grid& g, int nsteps, StepAccum& acc) {
+  const Params<T> P = make_params<T>(g);
+  for (int n = 0; n < nsteps; ++n) {
+    step_begin<T>(g, P);
+    step_end<T>(g, P, acc);
+  }
+}
+
+void fill_stats(uf_step_stats* stats, const StepAccum& acc, float ms) {
+  stats->cg_iters = acc.last_iters;
+  stats->cg_iters_total = acc.iters_total;
+  stats->cg_rel_residual = acc.last_rel;
+  stats->converged = !(acc.noconv || acc.nonfinite);
+  stats->nonfinite = acc.nonfinite;
+  stats->ms = ms;
+  stats->cg_iters_max = acc.max_iters;
 }
 
 template <class T>
@@ -648,16 +702,53 @@ uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats) {
     UF_HIP_CHECK(hipEventSynchronize(g->ev1));
     float ms = 0;
     UF_HIP_CHECK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-    stats->cg_iters = acc.last_iters;
-    stats->cg_iters_total = acc.iters_total;
-    stats->cg_rel_residual = acc.last_rel;
-    stats->converged = !(acc.noconv || acc.nonfinite);
-    stats->nonfinite = acc.nonfinite;
-    stats->ms = ms;
-    stats->cg_iters_max = acc.max_iters;
+    fill_stats(stats, acc, ms);
   }
   if (acc.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the pressure solve");
   if (acc.noconv) return fail(UF_ENOCONV, "pressure CG reached cg_maxit");
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step_stats* stats) {
+  if (!grids || n < 1) return fail(UF_EINVAL, "need at least one grid");
+  if (nsteps < 0) return fail(UF_EINVAL, "nsteps must be >= 0");
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) return fail(UF_EINVAL, "NULL grid in the batch");
+    for (int j = 0; j < i; ++j)
+      if (grids[j] == grids[i]) return fail(UF_EINVAL, "a grid appears twice in the batch");
+  }
+  UF_GUARD_BEGIN
+  std::vector<StepAccum> acc(n);
+  for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(grids[i]->ev0, grids[i]->stream));
+  for (int s = 0; s < nsteps; ++s) {
+    // every case's step up to its first CG chunk, then the waits in order:
+    // while the host waits for one case the others' work runs
+    for (int i = 0; i < n; ++i) {
+      Grid& g = *grids[i];
+      if (g.esize == 4) step_begin<float>(g, make_params<float>(g));
+      else step_begin<double>(g, make_params<double>(g));
+    }
+    for (int i = 0; i < n; ++i) {
+      Grid& g = *grids[i];
+      if (g.esize == 4) step_end<float>(g, make_params<float>(g), acc[i]);
+      else step_end<double>(g, make_params<double>(g), acc[i]);
+    }
+  }
+  for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(grids[i]->ev1, grids[i]->stream));
+  if (stats)
+    for (int i = 0; i < n; ++i) {
+      UF_HIP_CHECK(hipEventSynchronize(grids[i]->ev1));
+      float ms = 0;
+      UF_HIP_CHECK(hipEventElapsedTime(&ms, grids[i]->ev0, grids[i]->ev1));
+      fill_stats(&stats[i], acc[i], ms);
+    }
+  for (int i = 0; i < n; ++i) {
+    if (acc[i].nonfinite)
+      return fail(UF_ENONFINITE, "non-finite value in the pressure solve of batch entry " + std::to_string(i));
+    if (acc[i].noconv)
+      return fail(UF_ENOCONV, "pressure CG reached cg_maxit in batch entry " + std::to_string(i));
+  }
   return UF_OK;
   UF_GUARD_END
 }

@@ -99,6 +99,7 @@ struct Grid {
   void* mg_table = nullptr;     // device copy of the level descriptors
   double mg_omega = 0.8;        // Jacobi weight of the smoother
   int last_iters = 0;
+  int cg_t = 0;                 // CG iterations enqueued in the current solve
   // kernel timer (see uf_kernel_timer_enable)
   uint32_t timer_mask = 0;
   std::vector<hipEvent_t> timer_pool;

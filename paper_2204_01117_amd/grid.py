@@ -10,14 +10,16 @@ class Grid:
     (see ``uf_layouts.default_config``).  All work is enqueued on torch's
     current stream of ``device``."""
 
-    def __init__(self, cfg, device="cuda:0"):
+    def __init__(self, cfg, device="cuda:0", stream=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.cfg = dict(cfg)
         self.dtype = torch.float64 if str(cfg["dtype"]) in ("f64", "1") else torch.float32
-        with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device).cuda_stream
+        # ``stream``: a torch.cuda.Stream of its own (batched cases); by
+        # default torch's current stream
+        self.tstream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = self.tstream.cuda_stream
         c, keep = L.make_config(self.cfg, self.stream)
         self._cstruct = c
         h = c_void_p()
@@ -42,17 +44,21 @@ class Grid:
     # ------------------------------------------------------------------- API
     def set_porosity(self, phi):
         t = self._dev(phi, self.n)
-        L.check(L.uf_set_porosity(self.handle, c_void_p(t.data_ptr())))
         self.torch.cuda.current_stream(self.device).synchronize()
+        L.check(L.uf_set_porosity(self.handle, c_void_p(t.data_ptr())))
+        self.tstream.synchronize()
 
     def set_field(self, name, arr):
         t = self._dev(arr, self.extent(name))
-        L.check(L.uf_set_field(self.handle, L.FIELD_IDS[name], c_void_p(t.data_ptr())))
         self.torch.cuda.current_stream(self.device).synchronize()
+        L.check(L.uf_set_field(self.handle, L.FIELD_IDS[name], c_void_p(t.data_ptr())))
+        self.tstream.synchronize()
 
     def get_field(self, name):
         out = self.torch.empty(self.extent(name), dtype=self.dtype, device=self.device)
         L.check(L.uf_get_field(self.handle, L.FIELD_IDS[name], c_void_p(out.data_ptr())))
+        if self.tstream != self.torch.cuda.current_stream(self.device):
+            self.tstream.synchronize()
         return out
 
     def state(self):
@@ -75,6 +81,7 @@ class Grid:
         b = self._dev(b, self.n)
         x = self._dev(x0 if x0 is not None else self.torch.zeros(self.n), self.n).clone()
         s = L.uf_step_stats()
+        self.torch.cuda.current_stream(self.device).synchronize()
         rc = L.uf_pressure_solve(self.handle, c_void_p(b.data_ptr()), c_void_p(x.data_ptr()), byref(s))
         L.check(rc, allow)
         d = s.as_dict()
@@ -84,7 +91,12 @@ class Grid:
     def apply_operator(self, op, x):
         x = self._dev(x, self.n)
         y = self.torch.empty(self.n, dtype=self.dtype, device=self.device)
+        own = self.tstream != self.torch.cuda.current_stream(self.device)
+        if own:
+            self.torch.cuda.current_stream(self.device).synchronize()
         L.check(L.uf_apply_operator(self.handle, int(op), c_void_p(x.data_ptr()), c_void_p(y.data_ptr())))
+        if own:
+            self.tstream.synchronize()
         return y
 
     def objective(self, regions, u_target):
@@ -120,3 +132,18 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+def step_batch(grids, nsteps=1, stats=True, allow=()):
+    """Advance several grids by ``nsteps`` each through uf_step_batch (give
+    each Grid its own ``stream`` for their kernels to overlap).  Returns one
+    stats dictionary per grid."""
+    n = len(grids)
+    arr = (c_void_p * n)(*[g.handle for g in grids])
+    st = (L.uf_step_stats * n)()
+    rc = L.uf_step_batch(arr, n, int(nsteps), ctypes.cast(st, c_void_p) if stats else None)
+    L.check(rc, allow)
+    out = [st[i].as_dict() if stats else {} for i in range(n)]
+    for d in out:
+        d["status"] = L.STATUS[rc]
+    return out
