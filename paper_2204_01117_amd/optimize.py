@@ -42,16 +42,43 @@ class SimulationObjective:
         self.calls += 1
         return g.objective(self.regions, self.u_target)
 
+    def many(self, thetas):
+        """The objective of several designs, simulated together
+        (uf_step_batch, one grid and stream per design); each value equals
+        what ``__call__`` returns for that design."""
+        import torch
+        from .grid import Grid, step_batch
+        pool = getattr(self, "_pool", [])
+        while len(pool) < len(thetas):
+            pool.append(Grid(self.grid.cfg, device=self.grid.device, stream=torch.cuda.Stream(self.grid.device)))
+        self._pool = pool
+        grids = pool[:len(thetas)]
+        for g, th in zip(grids, thetas):
+            g.set_state(self.initial)
+            g.set_porosity(self.porosity_of(np.asarray(th, dtype=np.float64)))
+        if self.nsteps:
+            step_batch(grids, self.nsteps, stats=False)
+        self.calls += len(thetas)
+        return [g.objective(self.regions, self.u_target) for g in grids]
+
 
 def forward_difference_gradient(J, theta, eps=0.1):
-    """(J(theta), dJ/dtheta) by forward differences: N + 1 evaluations."""
+    """(J(theta), dJ/dtheta) by forward differences: N + 1 evaluations, all
+    at once when J has a ``many`` method (the simulations are independent)."""
     theta = np.array(theta, dtype=np.float64)
-    base = float(J(theta))
-    grad = np.empty_like(theta)
+    points = [theta]
     for n in range(theta.size):
         moved = theta.copy()
         moved.flat[n] += eps
-        grad.flat[n] = (float(J(moved)) - base) / eps
+        points.append(moved)
+    if hasattr(J, "many"):
+        values = [float(v) for v in J.many(points)]
+    else:
+        values = [float(J(p)) for p in points]
+    base = values[0]
+    grad = np.empty_like(theta)
+    for n in range(theta.size):
+        grad.flat[n] = (values[n + 1] - base) / eps
     return base, grad
 
 

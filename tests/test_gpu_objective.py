@@ -160,3 +160,20 @@ def test_forward_difference_descent_matches_oracle_and_descends():
     log("J history", [h[1] for h in hist], J_end)
     assert hist[1][1] < hist[0][1] and J_end < hist[1][1]
     g.close()
+
+
+def test_batched_forward_differences_equal_sequential_ones():
+    """The N + 1 simulations of one gradient run together (uf_step_batch)
+    and give the same objective values, bit for bit, as one after another."""
+    nsteps, ut = 6, 1.0
+    g = U.Grid(_tiny_cfg())
+    J = O.SimulationObjective(g, _phi_of, TARGETS, ut, nsteps)
+    theta = np.array([0.45, 0.8])
+    pts = [theta, theta + [0.1, 0.0], theta + [0.0, 0.1]]
+    seq = [J(p) for p in pts]
+    bat = J.many(pts)
+    assert seq == bat
+    j0, grad = O.forward_difference_gradient(J, theta, 0.1)
+    assert j0 == seq[0]
+    assert np.array_equal(grad, (np.array(seq[1:]) - seq[0]) / 0.1)
+    g.close()
