@@ -226,23 +226,38 @@ uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_s
 enum { UF_OP_POISSON = 0, UF_OP_PRECOND = 1 };
 uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_dev);
 
-/* Design objective of the optimisation routine (Sec. 4, the target-region
- * objective of the Nurnberg study): L = sum_i (s_i - u_target)^2 with s_i the
- * mean wind speed over the cells of target region i, the speed of a cell
- * being |u| of its cell-centre velocity (the mean of its two faces per
- * component).  Regions are boxes of cell indices, half-open:
- * i0 <= i < i1, j0 <= j < j1, k0 <= k < k1. */
+/* Design objectives (Sec. 4: the simulator returns the flow of a design and
+ * an objective scores it).
+ *
+ * UF_OBJ_REGIONS, the target-region objective of the Nurnberg study:
+ * L = sum_i (s_i - u_target)^2 with s_i the mean wind speed over the cells
+ * of target region i, the speed of a cell being |u| of its cell-centre
+ * velocity (the mean of its two faces per component).  Regions are boxes of
+ * cell indices, half-open: i0 <= i < i1, j0 <= j < j1, k0 <= k < k1.
+ *
+ * UF_OBJ_PLANE, pedestrian comfort on a horizontal plane at height z_plane:
+ * L = dx dy sum over columns (i, j) of phi_p [(s - s_target)^2 +
+ * w_penalty max(0, s_min - s)^2], where the cell-centre velocity and the
+ * porosity phi are interpolated linearly in z between the two cell centres
+ * around the plane and s = sqrt(|u_p|^2 + 1e-12) (solid columns weigh 0). */
+enum { UF_OBJ_REGIONS = 0, UF_OBJ_PLANE = 1 };
 typedef struct {
-  int32_t nregions;            /* 1 .. UF_MAX_REGIONS                           */
+  int32_t nregions;            /* UF_OBJ_REGIONS: 1 .. UF_MAX_REGIONS           */
   const int32_t* boxes;        /* host, 6 per region: i0, i1, j0, j1, k0, k1     */
   double u_target;             /* ideal mean speed (0.55 m/s in the paper)       */
+  int32_t kind;                /* UF_OBJ_REGIONS or UF_OBJ_PLANE                 */
+  double z_plane;              /* UF_OBJ_PLANE: height in metres, between the
+                                  first and the last cell centre (nz >= 2)       */
+  double s_target, s_min;      /* comfortable speed, stagnation threshold        */
+  double w_penalty;            /* weight of the stagnation term, >= 0            */
 } uf_objective_spec;
 enum { UF_MAX_REGIONS = 64 };
 
 /* Evaluates L on the current state into *J_host (synchronises the grid's
  * stream).  Speeds are summed in FP64 in a fixed order (deterministic).
- * UF_EINVAL for a NULL argument, a region count out of range, an empty box,
- * a box outside the grid or a non-finite target, before any work.
+ * UF_EINVAL for a NULL argument, an unknown kind, a region count out of
+ * range, an empty box, a box outside the grid, a plane outside the cell
+ * centres or a non-finite or negative parameter, before any work.
  * dJ_dstate_dev (the adjoint seed) must be NULL: the adjoint is not
  * implemented in this version (UF_ENOTIMPL, like uf_adjoint_step). */
 uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev);

@@ -7,8 +7,11 @@ cell is the norm of its cell-centre velocity, each component the mean of the
 cell's two faces on the staggered grid (Sec. 3.1).  Regions are boxes of
 cell indices, half-open on each axis.
 
-Pinned by tests/test_oracle_objective.py (uniform-flow closed form, linear
-profiles with known means, brute force on a tiny grid).
+A second objective scores pedestrian comfort on a horizontal plane (see
+``plane_objective``).
+
+Pinned by tests/test_oracle_objective.py (uniform-flow closed forms, linear
+profiles with known means and plane values, brute force on a tiny grid).
 """
 import numpy as np
 
@@ -35,6 +38,26 @@ def region_objective(u, v, w, regions, u_target):
     """L = sum over regions of (mean speed - u_target)^2."""
     m = region_means(u, v, w, regions)
     return float(np.sum((m - u_target) ** 2))
+
+
+def plane_objective(u, v, w, phi, h, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
+    """Pedestrian comfort on the plane z = z_plane: the cell-centre velocity
+    and the porosity interpolated linearly in z between the two cell centres
+    around the plane, s = sqrt(|u|^2 + 1e-12), and
+    dx dy sum over columns of phi [(s - s_target)^2 + w_penalty max(0, s_min - s)^2]."""
+    u, v, w, phi = (np.asarray(a, np.float64) for a in (u, v, w, phi))
+    nz = phi.shape[2]
+    zc = z_plane / h[2] - 0.5
+    k0 = min(max(int(np.floor(zc)), 0), nz - 2)
+    t = zc - k0
+    uc = 0.5 * (u[:-1, :, :] + u[1:, :, :])
+    vc = 0.5 * (v[:, :-1, :] + v[:, 1:, :])
+    wc = 0.5 * (w[:, :, :-1] + w[:, :, 1:])
+    lerp = lambda a: (1.0 - t) * a[:, :, k0] + t * a[:, :, k0 + 1]
+    up, vp, wp, pp = lerp(uc), lerp(vc), lerp(wc), lerp(phi)
+    s = np.sqrt(up * up + vp * vp + wp * wp + 1e-12)
+    lo = np.maximum(0.0, s_min - s)
+    return float(np.sum(pp * ((s - s_target) ** 2 + w_penalty * lo * lo)) * h[0] * h[1])
 
 
 def fd_gradient(J, theta, eps):

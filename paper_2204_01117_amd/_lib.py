@@ -36,8 +36,13 @@ class uf_step_stats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+OBJ_REGIONS, OBJ_PLANE = 0, 1
+
+
 class uf_objective_spec(ctypes.Structure):
-    _fields_ = [("nregions", c_int32), ("boxes", POINTER(c_int32)), ("u_target", c_double)]
+    _fields_ = [("nregions", c_int32), ("boxes", POINTER(c_int32)), ("u_target", c_double),
+                ("kind", c_int32), ("z_plane", c_double), ("s_target", c_double), ("s_min", c_double),
+                ("w_penalty", c_double)]
 
 
 def make_objective_spec(regions, u_target):
@@ -46,10 +51,19 @@ def make_objective_spec(regions, u_target):
     flat = [int(v) for box in regions for lohi in box for v in lohi]
     keep = (c_int32 * max(len(flat), 1))(*flat)
     s = uf_objective_spec()
+    s.kind = OBJ_REGIONS
     s.nregions = len(regions)
     s.boxes = ctypes.cast(keep, POINTER(c_int32))
     s.u_target = float(u_target)
     return s, keep
+
+
+def make_plane_spec(z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
+    """uf_objective_spec of the pedestrian-plane objective."""
+    s = uf_objective_spec()
+    s.kind = OBJ_PLANE
+    s.z_plane, s.s_target, s.s_min, s.w_penalty = float(z_plane), float(s_target), float(s_min), float(w_penalty)
+    return s
 
 
 class uf_mesh_set(ctypes.Structure):

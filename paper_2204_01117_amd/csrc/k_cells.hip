@@ -154,6 +154,48 @@ __global__ __launch_bounds__(kCellBlock) void k_region_speed(Layout L, const T* 
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
+// Pedestrian-plane objective: per column, the cell-centre velocity and the
+// porosity interpolated in z at weight t between levels k0 and k0 + 1, the
+// speed s = sqrt(|u|^2 + 1e-12), and phi [(s - st)^2 + w max(0, smin - s)^2];
+// one FP64 partial per block.
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_plane_objective(Layout L, const T* __restrict__ U,
+                                                               const T* __restrict__ V, const T* __restrict__ W,
+                                                               const T* __restrict__ PHI, int k0, double t,
+                                                               double st, double smin, double wpen,
+                                                               double* __restrict__ part) {
+  const int n = L.nx * L.ny;
+  double v[1] = {0.0};
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int i = c / L.ny, j = c % L.ny;
+    double uc[2], vc[2], wc[2], ph[2];
+    for (int q = 0; q < 2; ++q) {
+      const long long o = L.at(i, j, k0 + q);
+      uc[q] = 0.5 * ((double)U[o] + (double)U[o + L.SX]);
+      vc[q] = 0.5 * ((double)V[o] + (double)V[o + L.PZ]);
+      wc[q] = 0.5 * ((double)W[o] + (double)W[o + 1]);
+      ph[q] = (double)PHI[((size_t)i * L.ny + j) * L.nz + k0 + q];
+    }
+    const double up = (1.0 - t) * uc[0] + t * uc[1];
+    const double vp = (1.0 - t) * vc[0] + t * vc[1];
+    const double wp = (1.0 - t) * wc[0] + t * wc[1];
+    const double phip = (1.0 - t) * ph[0] + t * ph[1];
+    const double s = sqrt(up * up + vp * vp + wp * wp + 1e-12);
+    const double lo = fmax(0.0, smin - s);
+    v[0] += phip * ((s - st) * (s - st) + wpen * lo * lo);
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <class T>
+void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, double wpen, double* part,
+                            int nblocks) {
+  hipLaunchKernelGGL(k_plane_objective<T>, dim3(nblocks), dim3(kCellBlock), 0, g.stream, g.L,
+                     (const T*)g.Q[g.cur][0], (const T*)g.Q[g.cur][1], (const T*)g.Q[g.cur][2], (const T*)g.PHI, k0,
+                     t, st, smin, wpen, part);
+}
+
 template <class T>
 void launch_region_speed(Grid& g, const int box[6], double* part, int nblocks) {
   hipLaunchKernelGGL(k_region_speed<T>, dim3(nblocks), dim3(kCellBlock), 0, g.stream, g.L, (const T*)g.Q[g.cur][0],
@@ -216,6 +258,8 @@ void launch_check_range(Grid& g, const void* phi, size_t n) {
   hipLaunchKernelGGL(k_check_range<T>, dim3(blocks), dim3(kCellBlock), 0, g.stream, (const T*)phi, n, g.flag);
 }
 
+template void launch_plane_objective<float>(Grid&, int, double, double, double, double, double*, int);
+template void launch_plane_objective<double>(Grid&, int, double, double, double, double, double*, int);
 template void launch_region_speed<float>(Grid&, const int[6], double*, int);
 template void launch_region_speed<double>(Grid&, const int[6], double*, int);
 

@@ -808,6 +808,38 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
   if (!g || !spec || !J_host) return fail(UF_EINVAL, "NULL argument");
   if (dJ_dstate_dev)
     return fail(UF_ENOTIMPL, "the state gradient of the objective (adjoint seed) is not implemented in this version");
+  if (spec->kind == UF_OBJ_PLANE) {
+    const double dz = g->cfg.dz;
+    const int nz = g->L.nz;
+    if (nz < 2) return fail(UF_EINVAL, "the plane objective needs nz >= 2");
+    if (!std::isfinite(spec->z_plane) || spec->z_plane < 0.5 * dz || spec->z_plane > (nz - 0.5) * dz)
+      return fail(UF_EINVAL, "z_plane must lie between the first and the last cell centre");
+    if (!std::isfinite(spec->s_target) || !std::isfinite(spec->s_min) || !std::isfinite(spec->w_penalty) ||
+        spec->w_penalty < 0)
+      return fail(UF_EINVAL, "non-finite or negative plane objective parameter");
+    UF_GUARD_BEGIN
+    constexpr int kBlocks = 256;
+    if (!g->obj_part) g->obj_part = (double*)dalloc(sizeof(double) * kBlocks * UF_MAX_REGIONS);
+    const double zc = spec->z_plane / dz - 0.5;
+    const int k0 = std::min(std::max((int)std::floor(zc), 0), nz - 2);
+    const double t = zc - k0;
+    const long long cols = (long long)g->L.nx * g->L.ny;
+    const int nb = (int)std::min<long long>(kBlocks, (cols + 255) / 256);
+    if (g->esize == 4)
+      launch_plane_objective<float>(*g, k0, t, spec->s_target, spec->s_min, spec->w_penalty, g->obj_part, nb);
+    else
+      launch_plane_objective<double>(*g, k0, t, spec->s_target, spec->s_min, spec->w_penalty, g->obj_part, nb);
+    check_launch();
+    std::vector<double> host(nb);
+    UF_HIP_CHECK(hipMemcpyAsync(host.data(), g->obj_part, nb * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+    double J = 0.0;
+    for (int q = 0; q < nb; ++q) J += host[q];
+    *J_host = J * g->cfg.dx * g->cfg.dy;
+    return UF_OK;
+    UF_GUARD_END
+  }
+  if (spec->kind != UF_OBJ_REGIONS) return fail(UF_EINVAL, "unknown objective kind");
   const int nr = spec->nregions;
   if (nr < 1 || nr > UF_MAX_REGIONS || !spec->boxes) return fail(UF_EINVAL, "region count out of range");
   if (!std::isfinite(spec->u_target)) return fail(UF_EINVAL, "non-finite target speed");

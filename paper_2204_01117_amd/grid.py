@@ -108,6 +108,14 @@ class Grid:
         del keep
         return J.value
 
+    def plane_objective(self, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
+        """Pedestrian-comfort objective on the horizontal plane z = z_plane:
+        dx dy sum phi [(s - s_target)^2 + w_penalty max(0, s_min - s)^2]."""
+        spec = L.make_plane_spec(z_plane, s_target, s_min, w_penalty)
+        J = ctypes.c_double()
+        L.check(L.uf_objective(self.handle, byref(spec), byref(J), None))
+        return J.value
+
     def timer_enable(self, kernels=()):
         """Time every launch of the named kernels (see TIMED_KERNELS)."""
         mask = 0

@@ -14,7 +14,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 from uf_layouts import default_config, preset, preset_porosity
-from oracle import OracleGrid, region_objective, fd_gradient
+from oracle import OracleGrid, region_objective, plane_objective, fd_gradient
 from helpers import to_np, random_small_config, random_porosity
 
 import paper_2204_01117_amd as U
@@ -66,6 +66,31 @@ def test_objective_matches_oracle_on_random_state(seed, dtype):
     g.close()
 
 
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_plane_objective_matches_oracle(seed, dtype):
+    cfg = random_small_config(seed + 20, dtype=dtype)
+    g = U.Grid(cfg)
+    rng = np.random.default_rng(seed)
+    for f in "uvw":
+        g.set_field(f, torch.as_tensor(rng.normal(size=g.extent(f)) * (0.3 if seed == 1 else 1.0)))
+    phi = random_porosity(seed, g.n)
+    g.set_porosity(torch.as_tensor(phi))
+    h = (cfg["dx"], cfg["dy"], cfg["dz"])
+    s = {f: to_np(g.get_field(f)) for f in ("u", "v", "w", "phi")}
+    for zp in (0.5 * h[2], 1.5, 0.37 * g.n[2] * h[2], (g.n[2] - 0.5) * h[2]):
+        if not 0.5 * h[2] <= zp <= (g.n[2] - 0.5) * h[2]:
+            continue
+        J = g.plane_objective(zp)
+        ref = plane_objective(s["u"], s["v"], s["w"], s["phi"], h, zp)
+        assert abs(J - ref) <= OBJ_TOL * abs(ref), (zp, J, ref)
+    with pytest.raises(U.UFError):
+        g.plane_objective(0.49 * h[2])
+    with pytest.raises(U.UFError):
+        g.plane_objective(1.5, w_penalty=-1.0)
+    g.close()
+
+
 def test_objective_rejects_bad_specs_before_work():
     cfg = random_small_config(3, dtype="f32")
     g = U.Grid(cfg)
@@ -111,6 +136,11 @@ def test_objective_full_size_after_steps():
     ref = oracle_J(g, regions, 0.55)
     log("C1 objective", J, ref)
     assert abs(J - ref) <= OBJ_TOL * abs(ref)
+    s = {f: to_np(g.get_field(f)) for f in ("u", "v", "w", "phi")}
+    Jp = g.plane_objective(1.5)
+    refp = plane_objective(s["u"], s["v"], s["w"], s["phi"], (2.0, 2.0, 2.0), 1.5)
+    log("C1 plane objective", Jp, refp)
+    assert abs(Jp - refp) <= OBJ_TOL * abs(refp)
     g.close()
 
 

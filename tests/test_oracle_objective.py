@@ -4,7 +4,7 @@ import math
 
 import numpy as np
 
-from oracle import cell_speed, region_means, region_objective, fd_gradient
+from oracle import cell_speed, region_means, region_objective, plane_objective, fd_gradient
 
 
 def faces(nx, ny, nz, u=0.0, v=0.0, w=0.0):
@@ -76,3 +76,50 @@ def test_forward_difference_of_a_quadratic_is_exact_closed_form():
     j0, g = fd_gradient(J, t, 0.1)
     assert j0 == J(t)
     assert np.allclose(g, 2 * c * (t - s) + c * 0.1, rtol=1e-12)
+
+
+def test_plane_objective_uniform_flow_closed_form():
+    nx, ny, nz, h = 7, 5, 6, (2.0, 3.0, 2.0)
+    for U, ph in ((3.5, 1.0), (0.1, 1.0), (3.5, 0.5)):
+        u, v, w = faces(nx, ny, nz, u=U)
+        phi = np.full((nx, ny, nz), ph)
+        s = math.sqrt(U * U + 1e-12)
+        ref = nx * ny * h[0] * h[1] * ph * ((s - 2.0) ** 2 + 10.0 * max(0.0, 0.3 - s) ** 2)
+        assert math.isclose(plane_objective(u, v, w, phi, h, 1.5), ref, rel_tol=1e-14)
+
+
+def test_plane_objective_interpolates_linear_profiles_exactly():
+    # u faces sit at the cell-centre heights (k + 1/2) dz: a profile a z gives
+    # a z_plane at the plane; the porosity is linear in z as well
+    nx, ny, nz, h, a = 4, 3, 8, (1.0, 1.0, 2.0), 0.7
+    zc = (np.arange(nz) + 0.5) * h[2]
+    u, v, w = faces(nx, ny, nz)
+    u[...] = a * zc[None, None, :]
+    phi = np.broadcast_to(0.05 * zc[None, None, :], (nx, ny, nz)).copy()
+    for zp in (1.0, 1.5, 4.2, 14.9, 15.0):
+        s = math.sqrt((a * zp) ** 2 + 1e-12)
+        ref = nx * ny * h[0] * h[1] * 0.05 * zp * ((s - 2.0) ** 2 + 10.0 * max(0.0, 0.3 - s) ** 2)
+        assert math.isclose(plane_objective(u, v, w, phi, h, zp), ref, rel_tol=1e-12), zp
+
+
+def test_plane_objective_brute_force():
+    rng = np.random.default_rng(11)
+    nx, ny, nz, h = 3, 4, 5, (1.5, 2.0, 1.2)
+    u = rng.normal(size=(nx + 1, ny, nz))
+    v = rng.normal(size=(nx, ny + 1, nz)) * 0.2
+    w = rng.normal(size=(nx, ny, nz + 1)) * 0.2
+    phi = rng.uniform(0, 1, size=(nx, ny, nz))
+    zp = 2.3   # between the centres of k = 1 (1.8) and k = 2 (3.0)
+    t = (zp - 1.8) / 1.2
+    J = 0.0
+    for i in range(nx):
+        for j in range(ny):
+            vec = []
+            for k in (1, 2):
+                vec.append(((u[i, j, k] + u[i + 1, j, k]) / 2, (v[i, j, k] + v[i, j + 1, k]) / 2,
+                            (w[i, j, k] + w[i, j, k + 1]) / 2))
+            p = [(1 - t) * vec[0][c] + t * vec[1][c] for c in range(3)]
+            s = math.sqrt(p[0] ** 2 + p[1] ** 2 + p[2] ** 2 + 1e-12)
+            f = (1 - t) * phi[i, j, 1] + t * phi[i, j, 2]
+            J += f * ((s - 2.0) ** 2 + 10.0 * max(0.0, 0.3 - s) ** 2) * h[0] * h[1]
+    assert math.isclose(plane_objective(u, v, w, phi, h, zp), J, rel_tol=1e-12)
