@@ -50,6 +50,7 @@ ALG_BYTES_PER_CELL = {
     "cg_axpy": 24.0,      # read x, r, d, q; write x, r
     "mg_up0": 8.5,        # read r, the level-1 correction (1/8); write z
     "mg_down0": 4.5,      # read r; write the level-1 residual (1/8)
+    "mg_update0": 24.5,   # read x, r, d, q; write x, r and the level-1 residual (1/8)
     "cg_init": 20.0,      # read u*, v*, w*, p; write r
     "advect_fwd": 24.0,   # read u, v, w; write the forward-traced u, v, w
     "advect_corr": 36.0,  # read u, v, w and the traced fields; write u, v, w
@@ -64,7 +65,7 @@ ALG_BYTES_PER_CELL = {
 # application (its coarse levels add about 1/7 of the level-0 kernels).
 STEP_FIXED_KERNELS = ("advect_fwd", "advect_corr", "diffuse", "drag", "project", "turbulence", "cg_init")
 ALG_FIXED_PER_CELL = sum(ALG_BYTES_PER_CELL[k] for k in STEP_FIXED_KERNELS)
-ALG_ITER_PER_CELL = (ALG_BYTES_PER_CELL["cg_Ad"] + ALG_BYTES_PER_CELL["cg_axpy"] +
+ALG_ITER_PER_CELL = (ALG_BYTES_PER_CELL["cg_Ad"] + ALG_BYTES_PER_CELL["mg_update0"] - ALG_BYTES_PER_CELL["mg_down0"] +
                      (ALG_BYTES_PER_CELL["mg_up0"] + ALG_BYTES_PER_CELL["mg_down0"]) * 8.0 / 7.0)
 STEP_PREFIXES = ("k_advect_", "k_diffuse", "k_drag", "k_project", "k_turbulence", "k_cg_init", "k_cg_start")
 ITER_PREFIXES = ("k_cg_Ad", "k_cg_axpy", "k_mg_", "k_cg_precond", "k_ai2_", "k_cg_status")
@@ -76,6 +77,7 @@ PROFILE_NAMES = [
     ("k_mg_axpy<", "cg_axpy"),
     ("k_cg_axpy<", "cg_axpy"),
     ("k_mg_upsmooth<true", "mg_up0"),
+    ("k_mg_restrict<true", "mg_update0"),
     ("k_cg_init<", "cg_init"),
     ("k_advect_fwd<", "advect_fwd"),
     ("k_advect_corr<", "advect_corr"),
@@ -262,7 +264,7 @@ def traffic_summary(run_dir, command):
         if bn not in best or grid > best[bn][1]:
             best[bn] = (name, grid)
     if "mg_down0" not in best:
-        cands = [(n, gr) for (n, gr) in fetch if "k_mg_restrict<" in n and (n, gr) in write]
+        cands = [(n, gr) for (n, gr) in fetch if "k_mg_restrict<false" in n and (n, gr) in write]
         if cands:
             best["mg_down0"] = max(cands, key=lambda k: k[1])
     out = {}

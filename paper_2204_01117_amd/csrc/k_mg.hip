@@ -252,6 +252,30 @@ __device__ __forceinline__ void stage_box(T* __restrict__ s, const T* __restrict
   });
 }
 
+// The same for the vector a - alpha b (the residual after a CG update),
+// formed exactly as the update forms it.
+template <int DI, int DJ, int DK, int NT, class T, class Scale>
+__device__ __forceinline__ void stage_box_axpy(T* __restrict__ s, const T* __restrict__ a, const T* __restrict__ b,
+                                               T alpha, const Layout& L, int lo0, int lo1, int lo2, Scale scale) {
+  using W = BoxWalk<DI, DJ, DK, NT>;
+  W::run([&](int jj, int kk, int g) {
+    const long long base = (long long)(clampg(lo1 + jj, L.ny) + 1) * L.PZ + (clampg(lo2 + kk, L.nz) + 1);
+    T va[W::U], vb[W::U];
+#pragma unroll
+    for (int u = 0; u < W::U; ++u) {
+      const int ii = g + u * W::STEP;
+      const long long o = (long long)(clampg(lo0 + ii, L.nx) + 1) * L.SX + base;
+      va[u] = ii < DI ? a[o] : T(0);
+      vb[u] = ii < DI ? b[o] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < W::U; ++u) {
+      const int ii = g + u * W::STEP;
+      if (ii < DI) s[(ii * DJ + jj) * DK + kk] = scale(ii, jj, kk) * (va[u] - alpha * vb[u]);
+    }
+  });
+}
+
 // Boundary class of a position along one axis of n cells: bit 0 = first
 // cell (or before), bit 1 = last cell (or after).  A cell's D and om/D
 // depend only on its three classes (64 combinations).
@@ -289,8 +313,8 @@ __device__ __forceinline__ void fill_class_tables(const MgCommon<T>& K, const Mg
 // processed.
 struct TileWalk {
   int t, end, step;
-  __device__ __forceinline__ explicit TileWalk(int nt) {
-    const int G = gridDim.x;
+  // G: the blocks that walk tiles (blocks past them have other work)
+  __device__ __forceinline__ explicit TileWalk(int nt, int G = gridDim.x) {
     if (G >= 8 && (G & 7) == 0) {
       const int xcd = blockIdx.x & 7, lid = blockIdx.x >> 3, per = (nt + 7) >> 3;
       t = xcd * per + lid;
@@ -333,9 +357,23 @@ struct RTile {
 // whether the solve has finished and publishes flags[m] (first kernel of a
 // preconditioner application; after convergence the work here is wasted,
 // not wrong); 2: unconditional.
+// The CG update of iteration t, folded into the level-0 restriction of the
+// preconditioner application that follows it: x += alpha d and
+// r_{t+1} = r_t - alpha q (into F.r) on the fine cells whose parents are in
+// the block's tiles, the r.r partials, and the restriction of the
+// pre-smoothed r_{t+1} formed from r_t and q directly.
 template <class T>
+struct CgUpd {
+  T* X;
+  const T* Rin;   // r_t
+  const T* D;     // d_t
+  const T* Q;     // q = A d_t
+  int t;
+};
+
+template <bool CGU, class T>
 __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, int has_coarse, CgCtl c,
-                                                     int m, int mode, int3 nt3) {
+                                                     int m, int mode, int3 nt3, CgUpd<T> upd) {
   using Rt = RTile<T>;
   constexpr int EI = Rt::EI, EJ = Rt::EJ, EK = Rt::EK;
   constexpr int QI = EI + 2, QJ = EJ + 2, QK = EK + 2;   // e box: the residual box and a 1-cell halo
@@ -344,13 +382,36 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
   __shared__ T tab_omd[64];
   __shared__ T tab_a[64];
   // mode 0: the flag is loaded now and tested once the first box is staged,
-  // so that its latency overlaps the box loads
-  const int skip = mode == 0 ? c.flags[m] : 0;
-  if (mode == 1) {
-    if (blockIdx.x == 0) {
+  // so that its latency overlaps the box loads.  mode 1: one block past the
+  // tile walkers takes the decision, off the tiles' critical path.
+  const int skip = (!CGU && mode == 0) ? c.flags[m] : 0;
+  const int gw = (!CGU && mode == 1 && has_coarse) ? (int)gridDim.x - 1 : (int)gridDim.x;
+  if (!CGU && mode == 1) {
+    if ((int)blockIdx.x == (has_coarse ? gw : 0)) {
       const bool done = precond_skip(c, m);
       if (threadIdx.x == 0) c.flags[m] = done;
     }
+    if ((int)blockIdx.x >= gw) return;
+  }
+  T alpha = T(0);
+  if constexpr (CGU) {
+    // the same decision and alpha as the stand-alone update kernel
+    double rz = 0.0, dq = 0.0;
+    bool run = iteration_open(c, upd.t);
+    if (run) {
+      rz = c.st->rzh[upd.t & 1];
+      run = rz_allows(c, rz);
+    }
+    if (run) {
+      dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb_dq);
+      run = dq > 0.0 && isfinite(dq);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c.exec[upd.t] = run;
+      if (run) c.st->iter = upd.t + 1;
+    }
+    if (!run) return;
+    alpha = (T)(rz / dq);
   }
   if (!has_coarse) return;
   if (threadIdx.x < 64) {
@@ -363,15 +424,41 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
   const int nt = nt3.x * nt3.y * nt3.z;
   // first fine cell of the residual box of a tile with coarse origin X0
   auto box_lo = [&](int X0, int a) { return F.c[a] ? 2 * X0 - 1 : X0; };
-  for (TileWalk w(nt); w.t < w.end; w.t += w.step) {
+  double acc[1] = {0.0};
+  for (TileWalk w(nt, gw); w.t < w.end; w.t += w.step) {
     int X0, Y0, Z0;
     tile_origin(w.t, nt3, ct, X0, Y0, Z0);
     const int lo0 = box_lo(X0, 0), lo1 = box_lo(Y0, 1), lo2 = box_lo(Z0, 2);
     __syncthreads();   // the previous tile is done with the LDS; tables are in place
-    stage_box<QI, QJ, QK, 256>(se, F.r, L, lo0 - 1, lo1 - 1, lo2 - 1, [&](int ii, int jj, int kk) {
-      return tab_omd[cls3(L, lo0 - 1 + ii, lo1 - 1 + jj, lo2 - 1 + kk)];
-    });
+    auto omd_at = [&](int ii, int jj, int kk) { return tab_omd[cls3(L, lo0 - 1 + ii, lo1 - 1 + jj, lo2 - 1 + kk)]; };
+    if constexpr (CGU)
+      stage_box_axpy<QI, QJ, QK, 256>(se, upd.Rin, upd.Q, alpha, L, lo0 - 1, lo1 - 1, lo2 - 1, omd_at);
+    else
+      stage_box<QI, QJ, QK, 256>(se, F.r, L, lo0 - 1, lo1 - 1, lo2 - 1, omd_at);
     if (skip) return;   // the solve has finished (uniform over the grid)
+    if constexpr (CGU) {
+      // the fine cells whose parents are in this tile (the tiles partition
+      // the coarse cells, so these partition the fine ones)
+      const int f0 = F.c[0] ? 2 * X0 : X0, f1 = F.c[1] ? 2 * Y0 : Y0, f2 = F.c[2] ? 2 * Z0 : Z0;
+      const int e0 = min(F.c[0] ? 2 * Rt::CI : Rt::CI, L.nx - f0);
+      const int e1 = min(F.c[1] ? 2 * Rt::CJ : Rt::CJ, L.ny - f1);
+      const int e2 = min(F.c[2] ? 2 * Rt::CK : Rt::CK, L.nz - f2);
+      using WO = BoxWalk<2 * Rt::CI, 2 * Rt::CJ, 2 * Rt::CK, 256>;
+      WO::run([&](int jj, int kk, int g) {
+        if (jj >= e1 || kk >= e2) return;
+        const long long base = (long long)(f1 + jj + 1) * L.PZ + (f2 + kk + 1);
+#pragma unroll
+        for (int u = 0; u < WO::U; ++u) {
+          const int ii = g + u * WO::STEP;
+          if (ii >= e0) break;
+          const long long o = (long long)(f0 + ii + 1) * L.SX + base;
+          upd.X[o] = upd.X[o] + alpha * upd.D[o];
+          const T r = upd.Rin[o] - alpha * upd.Q[o];
+          F.r[o] = r;
+          acc[0] += (double)r * (double)r;
+        }
+      });
+    }
     __syncthreads();
     // residual over the footprint; entries outside the level are never
     // restricted from
@@ -427,6 +514,11 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
       }
       C.r[C.L.at(I, J, Kc)] = out;
     }
+  }
+  if constexpr (CGU) {
+    const int slots[1] = {S_RR};
+    write_partials<1>(acc, c.part, c.stride, slots, (int)blockIdx.x);
+    pad_partials(c, S_RR, (int)blockIdx.x, (int)gridDim.x);
   }
 }
 
@@ -1060,10 +1152,26 @@ static int3 restrict_tiles(const Layout& C) {
 
 template <class T>
 static void launch_restrict(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C, int has_coarse,
-                            const CgCtl& c, int m, int mode) {
+                            const CgCtl& c, int m, int mode, const CgUpd<T>* upd = nullptr) {
   const int3 nt3 = has_coarse ? restrict_tiles<T>(C.L) : make_int3(1, 1, 1);
-  const int G = has_coarse ? level_blocks((long long)nt3.x * nt3.y * nt3.z) : 1;
-  launch_k(g, k_mg_restrict<T>, dim3(G), dim3(256), K, F, C, has_coarse, c, m, mode, nt3);
+  // mode 1 adds the deciding block after the tile walkers
+  const int G = has_coarse ? level_blocks((long long)nt3.x * nt3.y * nt3.z) + (!upd && mode == 1 ? 1 : 0) : 1;
+  if (upd)
+    launch_k(g, k_mg_restrict<true, T>, dim3(G), dim3(256), K, F, C, has_coarse, c, m, mode, nt3, *upd);
+  else
+    launch_k(g, k_mg_restrict<false, T>, dim3(G), dim3(256), K, F, C, has_coarse, c, m, mode, nt3, CgUpd<T>{});
+}
+
+// Blocks of the level-0 restriction when it carries the CG update (the
+// writer of the r.r partials besides the CG kernels), or 0 when the update
+// stays separate: it needs a coarse restriction kernel after it to decide
+// whether the solve has finished.
+size_t mg_fused_blocks(const Grid& g) {
+  const int nl = (int)g.mg.size();
+  if (g.cfg.precond != UF_PC_MG || nl < 3 || std::min(g.mg_lt, nl - 1) < 2) return 0;
+  const Layout& C = g.mg[1].L;
+  const int3 nt3 = g.esize == 4 ? restrict_tiles<float>(C) : restrict_tiles<double>(C);
+  return (size_t)level_blocks((long long)nt3.x * nt3.y * nt3.z);
 }
 
 template <bool FINE, bool COARSE, class Tile, class T>
@@ -1085,7 +1193,8 @@ static void launch_up(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const Mg
 }
 
 template <class T>
-void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int decide) {
+void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int decide,
+               const CgUpd<T>* upd = nullptr) {
   (void)P;
   const MgCommon<T> K = mg_common<T>(g);
   const CgCtl c = make_ctl(g);
@@ -1095,14 +1204,15 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   L0.x = (T*)z;
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
   {
-    TimedLaunch tl(g, UF_TK_MG_DOWN0);
-    launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2);
+    TimedLaunch tl(g, upd ? UF_TK_MG_UPDATE0 : UF_TK_MG_DOWN0);
+    launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2, upd);
   }
   const int lt = std::min(g.mg_lt, nl - 1);
   for (int l = 1; l < lt; ++l) {
     const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);
     TimedLaunch tl(g, UF_TK_MG_COARSE);
-    launch_restrict<T>(g, K, F, C, 1, c, m, 0);
+    // after a fused update the first coarse restriction takes the decision
+    launch_restrict<T>(g, K, F, C, 1, c, m, (upd && l == 1) ? 1 : 0);
   }
   if (nl > 1) {
     {
@@ -1132,6 +1242,14 @@ void mg_precond(Grid& g, const Params<T>& P, int m) {
   mg_launch<T>(g, P, m, resid(g, m), g.Z, 1);
 }
 
+// CG update of iteration t and the preconditioner application that follows
+// (m = t + 1), the update inside the level-0 restriction.
+template <class T>
+void mg_iteration_update(Grid& g, const Params<T>& P, int t, const void* Dnew) {
+  const CgUpd<T> upd{(T*)g.X, (const T*)resid(g, t), (const T*)Dnew, (const T*)g.Qv, t};
+  mg_launch<T>(g, P, t + 1, resid(g, t + 1), g.Z, 1, &upd);
+}
+
 // Stand-alone application z = M^-1 r: uses the spare flag slot past the
 // iteration range and applies the cycle unconditionally.  The r.z partials
 // it writes are not used.
@@ -1144,6 +1262,8 @@ template void mg_setup<float>(Grid&);
 template void mg_setup<double>(Grid&);
 template void mg_precond<float>(Grid&, const Params<float>&, int);
 template void mg_precond<double>(Grid&, const Params<double>&, int);
+template void mg_iteration_update<float>(Grid&, const Params<float>&, int, const void*);
+template void mg_iteration_update<double>(Grid&, const Params<double>&, int, const void*);
 template void mg_apply<float>(Grid&, const Params<float>&, const void*, void*);
 template void mg_apply<double>(Grid&, const Params<double>&, const void*, void*);
 

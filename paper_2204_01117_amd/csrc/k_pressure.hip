@@ -158,12 +158,13 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_init(Params<T> P, const T* __re
   }
   const int slots[2] = {S_BB, S_RR};
   write_partials<2>(v, c.part, c.stride, slots, cg_bid);
+  pad_partials(c, S_RR, cg_bid, c.nb);
 }
 
 // One block: ||b||, the stopping threshold and whether x0 already solves.
 __global__ __launch_bounds__(256) void k_cg_start(CgCtl c, double tol) {
   const double bb = slot_sum(c.part + (size_t)S_BB * c.stride, c.nb);
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb);
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb_rr);
   if (threadIdx.x != 0) return;
   CgState* st = c.st;
   st->bb = bb;
@@ -406,12 +407,13 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_axpy(Params<T> P, T* __restrict
   }
   const int slots[1] = {S_RR};
   write_partials<1>(v, c.part, c.stride, slots, cg_bid);
+  pad_partials(c, S_RR, cg_bid, c.nb);
 }
 
 // One block, after a chunk of iterations ending at t_end: publish the
 // status for the host.
 __global__ __launch_bounds__(256) void k_cg_status(CgCtl c, int t_end) {
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb);
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb_rr);
   CgState* st = c.st;
   const int it = st->iter;
   const double rz = slot_sum(c.part + (size_t)(S_RZ0 + (it & 1)) * c.stride, c.nb_rz);
@@ -472,6 +474,7 @@ CgCtl make_ctl(Grid& g) {
   c.nb = (int)g.cg_nb;
   c.nb_rz = (int)g.cg_nb_rz;
   c.nb_dq = (int)g.cg_nb_dq;
+  c.nb_rr = (int)g.cg_nb_rr;
   c.flags = g.flags;
   c.exec = g.exec;
   c.st = g.st;
@@ -531,6 +534,12 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
     else
       launch_k(g, k_cg_Ad<16, T>, al.grid, dim3(512), P, (const T*)g.Z, (const T*)Dold, (T*)Dnew, (T*)g.Qv, (T*)g.X,
                c, t, al.ilen, al.njt, al.nkt);
+  }
+  if (g.mg_fused) {
+    // the update x += alpha d, r -= alpha q runs inside the multigrid's
+    // first restriction
+    mg_iteration_update<T>(g, P, t, Dnew);
+    return;
   }
   {
     TimedLaunch tl(g, UF_TK_CG_AXPY);

@@ -67,6 +67,7 @@ struct CgCtl {
   int nb;          // blocks of the CG kernels (slots BB, RR, DQ)
   int nb_rz;       // blocks of the kernel writing r.z (slots RZ0, RZ1)
   int nb_dq;       // blocks of the d/q kernel (slot DQ)
+  int nb_rr;       // partials of slot RR (its writers zero the ones past their blocks)
   int* flags;      // flags[m]: the solve finished before iteration m
   int* exec;       // exec[t]: iteration t performed its update
   CgState* st;
@@ -80,10 +81,18 @@ CgCtl make_ctl(Grid& g);
 // Has the solve finished before the preconditioner application that
 // follows iteration t (m = t + 1)?  Evaluated by the first kernel of that
 // application; its block 0 publishes the answer in flags[m].
+// Kernels with different block counts write the r.r partials: each writer
+// zeroes the slots past its own blocks (block b the slots b + n, b + 2n, ...
+// below the total), so that the sum over nb_rr entries is the full sum.
+__device__ __forceinline__ void pad_partials(const CgCtl& c, int slot, int bid, int nwriters) {
+  if (threadIdx.x == 0)
+    for (int q = bid + nwriters; q < c.nb_rr; q += nwriters) c.part[(size_t)slot * c.stride + q] = 0.0;
+}
+
 __device__ __forceinline__ bool precond_skip(const CgCtl& c, int m) {
   if (m == 0) return c.flags[0] != 0;
   if (!c.exec[m - 1]) return true;
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb);
+  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb_rr);
   if (!isfinite(rr)) return true;
   return c.criterion == 0 && rr <= c.st->tol2_bb;
 }

@@ -495,11 +495,9 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     g->cg_nb = (size_t)cl.gx * cl.gy;
     g->cg_nb_rz = cfg->precond == UF_PC_MG ? mg_fine_blocks(L) : g->cg_nb;
     g->cg_nb_dq = (size_t)ad_launch(L).blocks;
-    g->part_stride = std::max(g->cg_nb, std::max(g->cg_nb_rz, g->cg_nb_dq));
-    g->partials = (double*)dalloc(S_NSLOT_HOST * g->part_stride * sizeof(double));
+    g->cg_nb_rr = g->cg_nb;
     g->flags = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
     g->exec = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
-    UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->part_stride * sizeof(double), g->stream));
     UF_HIP_CHECK(hipMemsetAsync(g->flags, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
     UF_HIP_CHECK(hipMemsetAsync(g->exec, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
     g->st = (CgState*)dalloc(sizeof(CgState));
@@ -520,13 +518,23 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     upload_inflow<float>(*g);
     fill_phi_one<float>(*g);
     if (cfg->precond == UF_PC_MG) mg_setup<float>(*g);
-    init_state<float>(*g);
   } else {
     upload_inflow<double>(*g);
     fill_phi_one<double>(*g);
     if (cfg->precond == UF_PC_MG) mg_setup<double>(*g);
-    init_state<double>(*g);
   }
+  // partial-sum slots, sized for every kernel that writes them (the
+  // multigrid hierarchy decides whether the level-0 restriction is one)
+  {
+    const size_t fused = mg_fused_blocks(*g);
+    g->mg_fused = fused > 0;
+    g->cg_nb_rr = std::max(g->cg_nb, fused);
+    g->part_stride = std::max(std::max(g->cg_nb, g->cg_nb_rr), std::max(g->cg_nb_rz, g->cg_nb_dq));
+    g->partials = (double*)dalloc(S_NSLOT_HOST * g->part_stride * sizeof(double));
+    UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->part_stride * sizeof(double), g->stream));
+  }
+  if (g->esize == 4) init_state<float>(*g);
+  else init_state<double>(*g);
   UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   *out = g;
   return UF_OK;

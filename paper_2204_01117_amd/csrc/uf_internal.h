@@ -84,6 +84,8 @@ struct Grid {
   size_t cg_nb = 0;             // blocks of the fine-grid CG kernels
   size_t cg_nb_rz = 0;          // blocks of the kernel that writes the r.z partials
   size_t cg_nb_dq = 0;          // blocks of the d/q kernel
+  size_t cg_nb_rr = 0;          // partials of the r.r slot (the largest of its writers)
+  bool mg_fused = false;        // CG update folded into the level-0 restriction
   int* flags = nullptr;         // [cg_maxit + 2]
   int* exec = nullptr;          // [cg_maxit + 2]
   CgState* st = nullptr;     // device
@@ -141,6 +143,8 @@ void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, d
 std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream, double* cast_ms);
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
+template <class T> void mg_iteration_update(Grid& g, const Params<T>& P, int t, const void* Dnew);
+size_t mg_fused_blocks(const Grid& g);
 template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);
 void mg_free(Grid& g);
 

@@ -119,6 +119,30 @@ def test_pressure_solve_matches_direct(pc, dtype):
     g.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_multigrid_solve_with_update_in_the_restriction(dtype):
+    """48x32x20 has two multigrid levels above the single-workgroup tail, so
+    the CG update runs inside the level-0 restriction and the first coarse
+    restriction decides whether the solve has finished: the solution still
+    equals the direct one, and repeated solves (warm starts, early exits of
+    over-enqueued iterations) stay converged."""
+    cfg = default_config(48, 32, 20, 2.0, dtype=dtype, precond=PC_MG, cg_tol=CG_TOL[dtype], cg_maxit=500,
+                         bc=[BC_INLET, BC_OUTLET, BC_OUTLET, BC_OUTLET, BC_WALL, BC_SLIP])
+    g = gpu_grid(cfg)
+    og = OracleGrid(cfg, solver="direct")
+    for seed in (3, 4):
+        b = np.random.default_rng(seed).normal(size=g.n)
+        xd, _ = og.pressure.solve(b.ravel(), np.zeros(b.size))
+        x, st = g.pressure_solve(torch.tensor(b))
+        log("solve", seed, st["cg_iters"], st["cg_rel_residual"])
+        assert st["converged"] == 1 and st["cg_rel_residual"] <= CG_TOL[dtype]
+        assert rel(to_np(x).ravel(), xd) < (1e-10 if dtype == "f64" else 5e-5)
+        # the same system from the solution: converged at once
+        x2, st2 = g.pressure_solve(torch.tensor(b), x0=x)
+        assert st2["converged"] == 1 and st2["cg_iters"] <= 1
+    g.close()
+
+
 @pytest.mark.parametrize("omega", [1.0, 1.6])
 def test_preconditioner_ordering_and_iterations(omega):
     """Sec. 3 / appendix A.3: with the paper's stopping rule (M^-1 r . r /
