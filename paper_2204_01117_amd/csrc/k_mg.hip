@@ -431,19 +431,34 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
     const int lo0 = box_lo(X0, 0), lo1 = box_lo(Y0, 1), lo2 = box_lo(Z0, 2);
     __syncthreads();   // the previous tile is done with the LDS; tables are in place
     auto omd_at = [&](int ii, int jj, int kk) { return tab_omd[cls3(L, lo0 - 1 + ii, lo1 - 1 + jj, lo2 - 1 + kk)]; };
-    if constexpr (CGU)
+    // CGU: the fine cells whose parents are in this tile (the tiles
+    // partition the coarse cells, so these partition the fine ones); their
+    // x and d are loaded before the box so that the loads overlap
+    using WO = BoxWalk<2 * Rt::CI, 2 * Rt::CJ, 2 * Rt::CK, 256>;
+    int f0 = 0, f1 = 0, f2 = 0, e0 = 0, e1 = 0, e2 = 0;
+    T xv[WO::U], dv[WO::U];
+    if constexpr (CGU) {
+      f0 = F.c[0] ? 2 * X0 : X0;
+      f1 = F.c[1] ? 2 * Y0 : Y0;
+      f2 = F.c[2] ? 2 * Z0 : Z0;
+      e0 = min(F.c[0] ? 2 * Rt::CI : Rt::CI, L.nx - f0);
+      e1 = min(F.c[1] ? 2 * Rt::CJ : Rt::CJ, L.ny - f1);
+      e2 = min(F.c[2] ? 2 * Rt::CK : Rt::CK, L.nz - f2);
+      WO::run([&](int jj, int kk, int g) {
+        const long long base = (long long)(f1 + min(jj, e1 - 1) + 1) * L.PZ + (f2 + min(kk, e2 - 1) + 1);
+#pragma unroll
+        for (int u = 0; u < WO::U; ++u) {
+          const long long o = (long long)(f0 + min(g + u * WO::STEP, e0 - 1) + 1) * L.SX + base;
+          xv[u] = upd.X[o];
+          dv[u] = upd.D[o];
+        }
+      });
       stage_box_axpy<QI, QJ, QK, 256>(se, upd.Rin, upd.Q, alpha, L, lo0 - 1, lo1 - 1, lo2 - 1, omd_at);
-    else
+    } else {
       stage_box<QI, QJ, QK, 256>(se, F.r, L, lo0 - 1, lo1 - 1, lo2 - 1, omd_at);
+    }
     if (skip) return;   // the solve has finished (uniform over the grid)
     if constexpr (CGU) {
-      // the fine cells whose parents are in this tile (the tiles partition
-      // the coarse cells, so these partition the fine ones)
-      const int f0 = F.c[0] ? 2 * X0 : X0, f1 = F.c[1] ? 2 * Y0 : Y0, f2 = F.c[2] ? 2 * Z0 : Z0;
-      const int e0 = min(F.c[0] ? 2 * Rt::CI : Rt::CI, L.nx - f0);
-      const int e1 = min(F.c[1] ? 2 * Rt::CJ : Rt::CJ, L.ny - f1);
-      const int e2 = min(F.c[2] ? 2 * Rt::CK : Rt::CK, L.nz - f2);
-      using WO = BoxWalk<2 * Rt::CI, 2 * Rt::CJ, 2 * Rt::CK, 256>;
       WO::run([&](int jj, int kk, int g) {
         if (jj >= e1 || kk >= e2) return;
         const long long base = (long long)(f1 + jj + 1) * L.PZ + (f2 + kk + 1);
@@ -452,7 +467,7 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
           const int ii = g + u * WO::STEP;
           if (ii >= e0) break;
           const long long o = (long long)(f0 + ii + 1) * L.SX + base;
-          upd.X[o] = upd.X[o] + alpha * upd.D[o];
+          upd.X[o] = xv[u] + alpha * dv[u];
           const T r = upd.Rin[o] - alpha * upd.Q[o];
           F.r[o] = r;
           acc[0] += (double)r * (double)r;
