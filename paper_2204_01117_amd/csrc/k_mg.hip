@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
     // x and d are loaded before the box so that the loads overlap
     using WO = BoxWalk<2 * Rt::CI, 2 * Rt::CJ, 2 * Rt::CK, 256>;
     int f0 = 0, f1 = 0, f2 = 0, e0 = 0, e1 = 0, e2 = 0;
-    T xv[WO::U], dv[WO::U];
+    T xv[WO::U], dv[WO::U], rv[WO::U], qv[WO::U];
     if constexpr (CGU) {
       f0 = F.c[0] ? 2 * X0 : X0;
       f1 = F.c[1] ? 2 * Y0 : Y0;
@@ -451,6 +451,8 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
           const long long o = (long long)(f0 + min(g + u * WO::STEP, e0 - 1) + 1) * L.SX + base;
           xv[u] = upd.X[o];
           dv[u] = upd.D[o];
+          rv[u] = upd.Rin[o];
+          qv[u] = upd.Q[o];
         }
       });
       stage_box_axpy<QI, QJ, QK, 256>(se, upd.Rin, upd.Q, alpha, L, lo0 - 1, lo1 - 1, lo2 - 1, omd_at);
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
           if (ii >= e0) break;
           const long long o = (long long)(f0 + ii + 1) * L.SX + base;
           upd.X[o] = xv[u] + alpha * dv[u];
-          const T r = upd.Rin[o] - alpha * upd.Q[o];
+          const T r = rv[u] - alpha * qv[u];
           F.r[o] = r;
           acc[0] += (double)r * (double)r;
         }
