@@ -200,6 +200,29 @@ def test_one_step_parity_random_grids(seed, stages, dtype):
     g.close()
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 1), (2, 5, 1), (7, 2, 3), (3, 3, 2), (2, 2, 2), (4, 4, 4)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_step_parity_degenerate_grids(shape, dtype):
+    """The smallest grids: single layers, two cells along an axis, no
+    multigrid coarsening at all; every boundary class meets every other."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    kinds = [int(x) for x in rng.choice([BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP], size=6)]
+    kinds[1] = BC_OUTLET
+    cfg = default_config(nx, ny, nz, 2.0, dtype=dtype, dt=0.08, u_ref=4.0, z_ref=3.0, bc=kinds,
+                         wind_dir_deg=float(rng.uniform(0, 360)), precond=PC_MG, cg_tol=CG_TOL[dtype],
+                         cg_maxit=5000)
+    phi = random_porosity(nx + ny + nz, shape)
+    log("case", shape, dtype, kinds)
+    og = _prepared_pair(cfg, phi, 2)
+    g = gpu_grid(cfg, phi, og.state())
+    og.step(1)
+    st = g.step(1)
+    assert st["converged"] == 1
+    assert_close(state_errors(g.state(), og.state()), TOL[dtype], what="grid %s" % (shape,))
+    g.close()
+
+
 @pytest.mark.parametrize("pc", [PC_MG, PC_AI1])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_one_step_parity_c0(pc, dtype):
