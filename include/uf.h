@@ -239,8 +239,13 @@ uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_de
  * L = dx dy sum over columns (i, j) of phi_p [(s - s_target)^2 +
  * w_penalty max(0, s_min - s)^2], where the cell-centre velocity and the
  * porosity phi are interpolated linearly in z between the two cell centres
- * around the plane and s = sqrt(|u_p|^2 + 1e-12) (solid columns weigh 0). */
-enum { UF_OBJ_REGIONS = 0, UF_OBJ_PLANE = 1 };
+ * around the plane and s = sqrt(|u_p|^2 + 1e-12) (solid columns weigh 0).
+ *
+ * UF_OBJ_FIELD, the general form of Sec. 4: L = sum_i ||F_i(u) - F_i(u_t)||_2
+ * with u_t a desired flow and F_i the cell-centre velocities of target
+ * region i (the same boxes as UF_OBJ_REGIONS): per region the Euclidean norm
+ * of the difference over all its cells and components. */
+enum { UF_OBJ_REGIONS = 0, UF_OBJ_PLANE = 1, UF_OBJ_FIELD = 2 };
 typedef struct {
   int32_t nregions;            /* UF_OBJ_REGIONS: 1 .. UF_MAX_REGIONS           */
   const int32_t* boxes;        /* host, 6 per region: i0, i1, j0, j1, k0, k1     */
@@ -250,6 +255,9 @@ typedef struct {
                                   first and the last cell centre (nz >= 2)       */
   double s_target, s_min;      /* comfortable speed, stagnation threshold        */
   double w_penalty;            /* weight of the stagnation term, >= 0            */
+  const void* u_target_dev;    /* UF_OBJ_FIELD: device, 3 * nx*ny*nz desired
+                                  cell-centre velocities in the grid's dtype:
+                                  the u, v, then w block, each z fastest       */
 } uf_objective_spec;
 enum { UF_MAX_REGIONS = 64 };
 

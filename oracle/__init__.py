@@ -12,9 +12,9 @@ everything else is pinned by tests under ``tests/test_oracle_*.py``.
 """
 from .bc import (INLET, OUTLET, WALL, SLIP, Geometry, resolve_bc)
 from .solver import OracleGrid, FIELDS
-from .objective import cell_speed, region_means, region_objective, plane_objective, fd_gradient
+from .objective import cell_speed, region_means, region_objective, plane_objective, field_objective, fd_gradient
 from .voxelize import voxelize, inside, ray_crossings
 
 __all__ = ["INLET", "OUTLET", "WALL", "SLIP", "Geometry", "resolve_bc",
-           "OracleGrid", "FIELDS", "cell_speed", "region_means", "region_objective", "plane_objective", "fd_gradient",
+           "OracleGrid", "FIELDS", "cell_speed", "region_means", "region_objective", "plane_objective", "field_objective", "fd_gradient",
            "voxelize", "inside", "ray_crossings"]

@@ -8,7 +8,8 @@ cell's two faces on the staggered grid (Sec. 3.1).  Regions are boxes of
 cell indices, half-open on each axis.
 
 A second objective scores pedestrian comfort on a horizontal plane (see
-``plane_objective``).
+``plane_objective``), and ``field_objective`` is the general form that
+compares the flow with a desired one region by region.
 
 Pinned by tests/test_oracle_objective.py (uniform-flow closed forms, linear
 profiles with known means and plane values, brute force on a tiny grid).
@@ -38,6 +39,20 @@ def region_objective(u, v, w, regions, u_target):
     """L = sum over regions of (mean speed - u_target)^2."""
     m = region_means(u, v, w, regions)
     return float(np.sum((m - u_target) ** 2))
+
+
+def field_objective(u, v, w, u_target, regions):
+    """The general form of Sec. 4: sum over regions of the Euclidean norm of
+    F_i(u) - F_i(u_t), F_i being the cell-centre velocities (all three
+    components) of the cells of region i; u_target is [3, nx, ny, nz]."""
+    u, v, w = (np.asarray(a, np.float64) for a in (u, v, w))
+    cc = np.stack([0.5 * (u[:-1, :, :] + u[1:, :, :]), 0.5 * (v[:, :-1, :] + v[:, 1:, :]),
+                   0.5 * (w[:, :, :-1] + w[:, :, 1:])])
+    d = cc - np.asarray(u_target, np.float64)
+    total = 0.0
+    for (i0, i1), (j0, j1), (k0, k1) in regions:
+        total += float(np.sqrt(np.sum(d[:, i0:i1, j0:j1, k0:k1] ** 2)))
+    return total
 
 
 def plane_objective(u, v, w, phi, h, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):

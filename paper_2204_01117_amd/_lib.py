@@ -36,13 +36,13 @@ class uf_step_stats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
-OBJ_REGIONS, OBJ_PLANE = 0, 1
+OBJ_REGIONS, OBJ_PLANE, OBJ_FIELD = 0, 1, 2
 
 
 class uf_objective_spec(ctypes.Structure):
     _fields_ = [("nregions", c_int32), ("boxes", POINTER(c_int32)), ("u_target", c_double),
                 ("kind", c_int32), ("z_plane", c_double), ("s_target", c_double), ("s_min", c_double),
-                ("w_penalty", c_double)]
+                ("w_penalty", c_double), ("u_target_dev", c_void_p)]
 
 
 def make_objective_spec(regions, u_target):

@@ -196,6 +196,39 @@ void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, d
                      t, st, smin, wpen, part);
 }
 
+// Squared distance between the cell-centre velocity and a desired one over a
+// box of cells (one FP64 partial per block).
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_region_field_diff(Layout L, const T* __restrict__ U,
+                                                                 const T* __restrict__ V, const T* __restrict__ W,
+                                                                 const T* __restrict__ UT, int i0, int j0, int k0,
+                                                                 int ni, int nj, int nk, double* __restrict__ part) {
+  const long long n = (long long)ni * nj * nk;
+  const size_t N = (size_t)L.nx * L.ny * L.nz;
+  double v[1] = {0.0};
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = k0 + (int)(c % nk);
+    const long long r = c / nk;
+    const int j = j0 + (int)(r % nj);
+    const int i = i0 + (int)(r / nj);
+    const long long o = L.at(i, j, k);
+    const size_t q = ((size_t)i * L.ny + j) * L.nz + k;
+    const double du = 0.5 * ((double)U[o] + (double)U[o + L.SX]) - (double)UT[q];
+    const double dv = 0.5 * ((double)V[o] + (double)V[o + L.PZ]) - (double)UT[N + q];
+    const double dw = 0.5 * ((double)W[o] + (double)W[o + 1]) - (double)UT[2 * N + q];
+    v[0] += du * du + dv * dv + dw * dw;
+  }
+  block_sum<1>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+template <class T>
+void launch_region_field_diff(Grid& g, const int box[6], const void* ut, double* part, int nblocks) {
+  hipLaunchKernelGGL(k_region_field_diff<T>, dim3(nblocks), dim3(kCellBlock), 0, g.stream, g.L,
+                     (const T*)g.Q[g.cur][0], (const T*)g.Q[g.cur][1], (const T*)g.Q[g.cur][2], (const T*)ut, box[0],
+                     box[2], box[4], box[1] - box[0], box[3] - box[2], box[5] - box[4], part);
+}
+
 template <class T>
 void launch_region_speed(Grid& g, const int box[6], double* part, int nblocks) {
   hipLaunchKernelGGL(k_region_speed<T>, dim3(nblocks), dim3(kCellBlock), 0, g.stream, g.L, (const T*)g.Q[g.cur][0],
@@ -260,6 +293,8 @@ void launch_check_range(Grid& g, const void* phi, size_t n) {
 
 template void launch_plane_objective<float>(Grid&, int, double, double, double, double, double*, int);
 template void launch_plane_objective<double>(Grid&, int, double, double, double, double, double*, int);
+template void launch_region_field_diff<float>(Grid&, const int[6], const void*, double*, int);
+template void launch_region_field_diff<double>(Grid&, const int[6], const void*, double*, int);
 template void launch_region_speed<float>(Grid&, const int[6], double*, int);
 template void launch_region_speed<double>(Grid&, const int[6], double*, int);
 

@@ -847,10 +847,12 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
     return UF_OK;
     UF_GUARD_END
   }
-  if (spec->kind != UF_OBJ_REGIONS) return fail(UF_EINVAL, "unknown objective kind");
+  if (spec->kind != UF_OBJ_REGIONS && spec->kind != UF_OBJ_FIELD) return fail(UF_EINVAL, "unknown objective kind");
+  const bool field = spec->kind == UF_OBJ_FIELD;
   const int nr = spec->nregions;
   if (nr < 1 || nr > UF_MAX_REGIONS || !spec->boxes) return fail(UF_EINVAL, "region count out of range");
-  if (!std::isfinite(spec->u_target)) return fail(UF_EINVAL, "non-finite target speed");
+  if (!field && !std::isfinite(spec->u_target)) return fail(UF_EINVAL, "non-finite target speed");
+  if (field && !spec->u_target_dev) return fail(UF_EINVAL, "NULL desired velocity field");
   const int n[3] = {g->L.nx, g->L.ny, g->L.nz};
   for (int r = 0; r < nr; ++r)
     for (int a = 0; a < 3; ++a) {
@@ -865,8 +867,14 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
     const int* b = spec->boxes + 6 * r;
     const long long cells = (long long)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]);
     nb[r] = (int)std::min<long long>(kBlocks, (cells + 255) / 256);
-    if (g->esize == 4) launch_region_speed<float>(*g, b, g->obj_part + (size_t)r * kBlocks, nb[r]);
-    else launch_region_speed<double>(*g, b, g->obj_part + (size_t)r * kBlocks, nb[r]);
+    double* part = g->obj_part + (size_t)r * kBlocks;
+    if (field) {
+      if (g->esize == 4) launch_region_field_diff<float>(*g, b, spec->u_target_dev, part, nb[r]);
+      else launch_region_field_diff<double>(*g, b, spec->u_target_dev, part, nb[r]);
+    } else {
+      if (g->esize == 4) launch_region_speed<float>(*g, b, part, nb[r]);
+      else launch_region_speed<double>(*g, b, part, nb[r]);
+    }
   }
   check_launch();
   std::vector<double> host((size_t)kBlocks * nr);
@@ -878,8 +886,12 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
     const int* b = spec->boxes + 6 * r;
     double s = 0.0;
     for (int q = 0; q < nb[r]; ++q) s += host[(size_t)r * kBlocks + q];
-    const double mean = s / ((double)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]));
-    J += (mean - spec->u_target) * (mean - spec->u_target);
+    if (field) {
+      J += std::sqrt(s);
+    } else {
+      const double mean = s / ((double)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]));
+      J += (mean - spec->u_target) * (mean - spec->u_target);
+    }
   }
   *J_host = J;
   return UF_OK;

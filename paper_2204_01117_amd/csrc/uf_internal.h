@@ -138,6 +138,8 @@ void launch_cg_status(Grid& g, int t_end);
 template <class T> void launch_apply(Grid& g, const Params<T>& P, int op, const void* x, void* y);
 template <class T> void launch_region_speed(Grid& g, const int box[6], double* part, int nblocks);
 template <class T>
+void launch_region_field_diff(Grid& g, const int box[6], const void* ut, double* part, int nblocks);
+template <class T>
 void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, double wpen, double* part,
                             int nblocks);
 std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream, double* cast_ms);

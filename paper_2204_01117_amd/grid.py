@@ -108,6 +108,19 @@ class Grid:
         del keep
         return J.value
 
+    def field_objective(self, regions, u_target):
+        """General objective sum_i ||F_i(u) - F_i(u_t)||_2 with F_i the
+        cell-centre velocities of region i; ``u_target`` is [3, nx, ny, nz]."""
+        ut = self._dev(u_target, (3,) + self.n)
+        spec, keep = L.make_objective_spec(regions, 0.0)
+        spec.kind = L.OBJ_FIELD
+        spec.u_target_dev = ut.data_ptr()
+        self.torch.cuda.current_stream(self.device).synchronize()
+        J = ctypes.c_double()
+        L.check(L.uf_objective(self.handle, byref(spec), byref(J), None))
+        del keep, ut
+        return J.value
+
     def plane_objective(self, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
         """Pedestrian-comfort objective on the horizontal plane z = z_plane:
         dx dy sum phi [(s - s_target)^2 + w_penalty max(0, s_min - s)^2]."""

@@ -14,7 +14,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
 from uf_layouts import default_config, preset, preset_porosity
-from oracle import OracleGrid, region_objective, plane_objective, fd_gradient
+from oracle import OracleGrid, region_objective, plane_objective, field_objective, fd_gradient
 from helpers import to_np, random_small_config, random_porosity
 
 import paper_2204_01117_amd as U
@@ -63,6 +63,31 @@ def test_objective_matches_oracle_on_random_state(seed, dtype):
         J = g.objective(regions, ut)
         ref = oracle_J(g, regions, ut)
         assert abs(J - ref) <= OBJ_TOL * abs(ref), (J, ref)
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_field_objective_matches_oracle(seed, dtype):
+    cfg = random_small_config(seed + 40, dtype=dtype)
+    g = U.Grid(cfg)
+    rng = np.random.default_rng(seed + 7)
+    for f in "uvw":
+        g.set_field(f, torch.as_tensor(rng.normal(size=g.extent(f))))
+    nx, ny, nz = g.n
+    ut = rng.normal(size=(3, nx, ny, nz))
+    if dtype == "f32":
+        ut = ut.astype(np.float32).astype(np.float64)   # the GPU holds it in the grid's dtype
+    regions = random_regions(rng, g.n, 4) + [((0, nx), (0, ny), (0, nz)), ((nx - 1, nx), (ny - 1, ny), (nz - 1, nz))]
+    J = g.field_objective(regions, torch.as_tensor(ut))
+    s = {f: to_np(g.get_field(f)) for f in "uvw"}
+    ref = field_objective(s["u"], s["v"], s["w"], ut, regions)
+    assert abs(J - ref) <= OBJ_TOL * abs(ref), (J, ref)
+    # the desired flow equal to the current one scores 0 (bit for bit in FP64)
+    if dtype == "f64":
+        cc = np.stack([(s["u"][:-1] + s["u"][1:]) / 2, (s["v"][:, :-1] + s["v"][:, 1:]) / 2,
+                       (s["w"][:, :, :-1] + s["w"][:, :, 1:]) / 2])
+        assert g.field_objective(regions, torch.as_tensor(cc)) == 0.0
     g.close()
 
 

@@ -4,7 +4,7 @@ import math
 
 import numpy as np
 
-from oracle import cell_speed, region_means, region_objective, plane_objective, fd_gradient
+from oracle import cell_speed, region_means, region_objective, plane_objective, field_objective, fd_gradient
 
 
 def faces(nx, ny, nz, u=0.0, v=0.0, w=0.0):
@@ -123,3 +123,41 @@ def test_plane_objective_brute_force():
             f = (1 - t) * phi[i, j, 1] + t * phi[i, j, 2]
             J += f * ((s - 2.0) ** 2 + 10.0 * max(0.0, 0.3 - s) ** 2) * h[0] * h[1]
     assert math.isclose(plane_objective(u, v, w, phi, h, zp), J, rel_tol=1e-12)
+
+
+def test_field_objective_closed_forms():
+    nx, ny, nz = 6, 5, 4
+    rng = np.random.default_rng(2)
+    u = rng.normal(size=(nx + 1, ny, nz))
+    v = rng.normal(size=(nx, ny + 1, nz))
+    w = rng.normal(size=(nx, ny, nz + 1))
+    cc = np.stack([(u[:-1] + u[1:]) / 2, (v[:, :-1] + v[:, 1:]) / 2, (w[:, :, :-1] + w[:, :, 1:]) / 2])
+    regions = [((0, 6), (0, 5), (0, 4)), ((1, 3), (2, 5), (1, 2)), ((5, 6), (4, 5), (3, 4))]
+    # the desired flow itself scores 0
+    assert field_objective(u, v, w, cc, regions) == 0.0
+    # a uniform offset delta: each region contributes sqrt(cells) |delta|
+    delta = np.array([0.3, -1.2, 0.4])
+    ref = sum(math.sqrt((b[0][1] - b[0][0]) * (b[1][1] - b[1][0]) * (b[2][1] - b[2][0])) for b in regions)
+    got = field_objective(u, v, w, cc - delta[:, None, None, None], regions)
+    assert math.isclose(got, ref * 1.3, rel_tol=1e-13)   # |delta| = 1.3
+
+
+def test_field_objective_brute_force():
+    nx, ny, nz = 3, 4, 2
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=(nx + 1, ny, nz))
+    v = rng.normal(size=(nx, ny + 1, nz))
+    w = rng.normal(size=(nx, ny, nz + 1))
+    ut = rng.normal(size=(3, nx, ny, nz))
+    regions = [((0, 2), (1, 4), (0, 2)), ((2, 3), (0, 1), (1, 2))]
+    J = 0.0
+    for (i0, i1), (j0, j1), (k0, k1) in regions:
+        ss = 0.0
+        for i in range(i0, i1):
+            for j in range(j0, j1):
+                for k in range(k0, k1):
+                    c = ((u[i, j, k] + u[i + 1, j, k]) / 2, (v[i, j, k] + v[i, j + 1, k]) / 2,
+                         (w[i, j, k] + w[i, j, k + 1]) / 2)
+                    ss += sum((c[q] - ut[q, i, j, k]) ** 2 for q in range(3))
+        J += math.sqrt(ss)
+    assert math.isclose(field_objective(u, v, w, ut, regions), J, rel_tol=1e-13)
