@@ -146,7 +146,7 @@ def traffic_for(kernel, ncells):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != sources_hash():
+    if rec.get("source_sha256") != sources_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -170,10 +170,24 @@ def step_traffic(iters_per_step, ms_per_step, ncells):
             "source": "profiles/traffic_step_256x256x64.json"}
 
 
-def sources_hash():
+# Source files that hold each measured kernel's device code (with the
+# device headers every kernel includes): a counter record is stale when
+# these change, and only then.
+KERNEL_FILES = {
+    "advect_fwd": ["k_momentum.hip"], "advect_corr": ["k_momentum.hip"], "diffuse": ["k_momentum.hip"],
+    "drag": ["k_momentum.hip"], "project": ["k_momentum.hip"], "turbulence": ["k_cells.hip"],
+    "cg_Ad": ["k_pressure.hip"], "cg_axpy": ["k_pressure.hip"], "cg_init": ["k_pressure.hip"],
+    "mg_up0": ["k_mg.hip"], "mg_down0": ["k_mg.hip"], "mg_update0": ["k_mg.hip"],
+}
+DEVICE_HEADERS = ["uf_device.h", "pressure_common.h"]
+
+
+def sources_hash(kernel=None):
+    """sha256 of the sources of one kernel (None: of every step kernel)."""
+    files = KERNEL_FILES.get(kernel) or sorted({f for v in KERNEL_FILES.values() for f in v})
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2204_01117_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(set(files) | set(DEVICE_HEADERS)):
         h.update(name.encode())
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
@@ -279,7 +293,7 @@ def traffic_summary(run_dir, command):
                             "fetch_kib_raw": c_fetch, "write_kib_raw": c_write,
                             "fetch_factor": f_fetch, "write_factor": f_write},
             "alg_bytes_per_launch": ALG_BYTES_PER_CELL[bn] * 256 * 256 * 64,
-            "source_sha256": sources_hash(),
+            "source_sha256": sources_hash(bn),
             "command": command,
         }
     # the whole step: every dispatch of the step's kernels, split into the
