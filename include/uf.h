@@ -204,10 +204,11 @@ uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats);
 /* Advance n independent grids by nsteps each (several cases at once: the
  * wind directions and design variants of Sec. 4 and 5, or the N + 1
  * simulations of a forward-difference gradient).  Each grid computes exactly
- * what uf_step computes for it, bit for bit; the work of all grids is
- * enqueued from the calling thread in rounds (every grid's step up to its
- * first pressure-CG chunk, then each grid's completion), so that one grid's
- * host round trip overlaps the others' kernels.  Give each grid its own
+ * what uf_step computes for it, bit for bit; the work is enqueued by up to
+ * four host threads, each owning every fourth grid, in rounds (every owned
+ * grid's step up to its first pressure-CG chunk, then each one's
+ * completion), so that one grid's host round trip overlaps the others'
+ * kernels.  The call returns when all threads have finished.  Give each grid its own
  * stream (uf_config.stream) for the kernels to overlap.  stats, if non-NULL,
  * has n entries and synchronises like uf_step.  UF_EINVAL (nothing
  * enqueued) for NULL, n < 1, a NULL grid or a grid listed twice; UF_ENOCONV

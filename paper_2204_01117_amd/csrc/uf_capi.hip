@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "uf_internal.h"
@@ -20,6 +21,7 @@ template <class T> void launch_cell_fill(Grid& g, const Params<T>& P, void* q, d
                                          double inlet_value);
 
 static const double kCmu = 0.09, kClim = 7.0 / 8.0;
+static const int kBatchThreads = 4;   // host threads of uf_step_batch
 
 TimedLaunch::TimedLaunch(Grid& g_, int id_) : g(g_), prev(g_.timer_cur) { g.timer_cur = id_; }
 
@@ -729,20 +731,42 @@ uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step
   UF_GUARD_BEGIN
   std::vector<StepAccum> acc(n);
   for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(grids[i]->ev0, grids[i]->stream));
-  for (int s = 0; s < nsteps; ++s) {
-    // every case's step up to its first CG chunk, then the waits in order:
-    // while the host waits for one case the others' work runs
-    for (int i = 0; i < n; ++i) {
-      Grid& g = *grids[i];
-      if (g.esize == 4) step_begin<float>(g, make_params<float>(g));
-      else step_begin<double>(g, make_params<double>(g));
+  // a few host threads, each owning every nw-th grid: each runs the rounds
+  // below on its grids, so that enqueueing the many small kernels of the
+  // cases proceeds in parallel (each grid's kernel sequence is unchanged)
+  const int nw = std::max(1, std::min(n, kBatchThreads));
+  std::vector<std::string> errs(nw);
+  auto work = [&](int w) {
+    try {
+      for (int s = 0; s < nsteps; ++s) {
+        // every owned case's step up to its first CG chunk, then the waits
+        // in order: while the host waits for one case the others' work runs
+        for (int i = w; i < n; i += nw) {
+          Grid& g = *grids[i];
+          if (g.esize == 4) step_begin<float>(g, make_params<float>(g));
+          else step_begin<double>(g, make_params<double>(g));
+        }
+        for (int i = w; i < n; i += nw) {
+          Grid& g = *grids[i];
+          if (g.esize == 4) step_end<float>(g, make_params<float>(g), acc[i]);
+          else step_end<double>(g, make_params<double>(g), acc[i]);
+        }
+      }
+    } catch (const HipError& e) {
+      errs[w] = e.msg;
+    } catch (const std::exception& e) {
+      errs[w] = e.what();
     }
-    for (int i = 0; i < n; ++i) {
-      Grid& g = *grids[i];
-      if (g.esize == 4) step_end<float>(g, make_params<float>(g), acc[i]);
-      else step_end<double>(g, make_params<double>(g), acc[i]);
-    }
+  };
+  if (nw == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nw; ++w) pool.emplace_back(work, w);
+    for (auto& t : pool) t.join();
   }
+  for (const auto& e : errs)
+    if (!e.empty()) return fail(UF_EDEVICE, e);
   for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(grids[i]->ev1, grids[i]->stream));
   if (stats)
     for (int i = 0; i < n; ++i) {

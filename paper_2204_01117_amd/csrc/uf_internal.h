@@ -190,8 +190,10 @@ struct HipError {
 template <typename... Args, typename... A>
 inline void launch_k(Grid& g, void (*kernel)(Args...), dim3 grid, dim3 block, A... args) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  (void)timer_pair(g, &e0, &e1);
-  hipExtLaunchKernelGGL(kernel, grid, block, 0, g.stream, e0, e1, 0, static_cast<Args>(args)...);
+  if (timer_pair(g, &e0, &e1))
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, g.stream, e0, e1, 0, static_cast<Args>(args)...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, g.stream, static_cast<Args>(args)...);
 }
 
 }  // namespace uf
