@@ -178,6 +178,33 @@ uf_status uf_voxelize(const uf_mesh_set* mesh, int32_t dtype, void* phi_dev, voi
 /* cast_ms (nullable): receives the duration of the ray-casting kernel
  * (events carried in its dispatch), 0 when no object meets the grid. */
 
+/* Objects with smoothed faces, for design parameters that move buildings
+ * by fractions of a cell (Sec. 3 motivates the cut-cell volume ratio by the
+ * boundary sliding within a cell during optimisation): each object's
+ * indicator is a product of logistic steps sig(t) = 1 / (1 + e^-t) of width
+ * `width` across its faces, evaluated at cell centres:
+ *   box       prod over axes sig((p - lo) / w) sig((hi - p) / w)
+ *   cylinder  sig((R - rho) / w) sig((z - z0) / w) sig((z1 - z) / w)
+ * (rho: distance from the axis; no lower step when z0 <= 0, so objects on
+ * the ground stay solid down to it), and the porosity of a cell is
+ * min(1, min over objects of 1 - I (1 - phi_o)). */
+typedef struct {
+  int32_t nx, ny, nz;          /* grid cells, each >= 1                         */
+  double dx, dy, dz;           /* cell size, > 0                                */
+  double width;                /* step width in metres, > 0                     */
+  int32_t nboxes;              /* >= 0                                          */
+  const double* boxes;         /* host, 7 per box: x0, x1, y0, y1, z0, z1, phi  */
+  int32_t ncyls;               /* >= 0                                          */
+  const double* cylinders;     /* host, 6 per cylinder: cx, cy, R, z0, z1, phi  */
+} uf_smooth_objects;
+
+/* Porosity of smoothed objects into phi_dev (nx*ny*nz values of dtype
+ * UF_F32/UF_F64, z fastest, the layout uf_set_porosity takes), computed in
+ * FP64 on `stream`; synchronises the stream.  UF_EINVAL (nothing written)
+ * for NULL or inconsistent arguments, non-finite values, phi outside
+ * [0, 1] or a negative radius. */
+uf_status uf_smooth_porosity(const uf_smooth_objects* objects, int32_t dtype, void* phi_dev, void* stream);
+
 /* Overwrite one state field from a device array in the layout given by
  * uf_field_extent (checkpoint restore, parity tests).  Boundary values are
  * re-imposed after the copy.  UF_PHI is the same as uf_set_porosity. */

@@ -75,6 +75,13 @@ class uf_mesh_set(ctypes.Structure):
                 ("verts_dev", c_void_p), ("tris_dev", c_void_p)]
 
 
+class uf_smooth_objects(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+                ("dx", c_double), ("dy", c_double), ("dz", c_double), ("width", c_double),
+                ("nboxes", c_int32), ("boxes", POINTER(c_double)),
+                ("ncyls", c_int32), ("cylinders", POINTER(c_double))]
+
+
 class UFError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (STATUS.get(status, status), message))
@@ -105,6 +112,7 @@ _SIGS = {
     "uf_adjoint_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
     "uf_step_batch": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p]),
+    "uf_smooth_porosity": (c_int32, [POINTER(uf_smooth_objects), c_int32, c_void_p, c_void_p]),
     "uf_voxelize": (c_int32, [POINTER(uf_mesh_set), c_int32, c_void_p, c_void_p, POINTER(c_double)]),
     "uf_kernel_timer_enable": (c_int32, [c_void_p, ctypes.c_uint32]),
     "uf_kernel_timer_read": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
@@ -128,6 +136,7 @@ uf_objective = lib.uf_objective
 uf_adjoint_step = lib.uf_adjoint_step
 uf_set_stream = lib.uf_set_stream
 uf_step_batch = lib.uf_step_batch
+uf_smooth_porosity = lib.uf_smooth_porosity
 uf_voxelize = lib.uf_voxelize
 uf_kernel_timer_enable = lib.uf_kernel_timer_enable
 uf_kernel_timer_read = lib.uf_kernel_timer_read

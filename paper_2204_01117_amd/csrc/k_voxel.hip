@@ -229,6 +229,50 @@ __global__ __launch_bounds__(kVoxThreads) void k_voxelize(const VoxItem* __restr
   }
 }
 
+// Smoothed object indicator (design parameters move object faces within a
+// cell continuously): per cell centre the product of logistic steps of
+// width s across each object's faces (no lower step for objects standing on
+// the ground), and the porosity min(1, min_o 1 - I_o (1 - phi_o)).  Objects:
+// 8 doubles each, kind (0 box: x0 x1 y0 y1 z0 z1 phi; 1 cylinder: cx cy R
+// z0 z1 phi), FP64 throughout.
+__device__ __forceinline__ double logistic(double t) {
+  const double e = exp(-fabs(t));
+  return t >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+}
+
+template <class T>
+__global__ __launch_bounds__(kVoxThreads) void k_smooth_porosity(const double* __restrict__ obj, int nobj, int nx,
+                                                                int ny, int nz, double dx, double dy, double dz,
+                                                                double s, T* __restrict__ phi) {
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(c % nz);
+    const int j = (int)((c / nz) % ny);
+    const int i = (int)(c / ((size_t)nz * ny));
+    const double px = ((double)i + 0.5) * dx, py = ((double)j + 0.5) * dy, pz = ((double)k + 0.5) * dz;
+    double v = 1.0;
+    for (int o = 0; o < nobj; ++o) {
+      const double* a = obj + 8 * o;
+      double ind, po;
+      if (a[7] == 0.0) {
+        const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
+        const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
+        const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
+        ind = fx * fy * fz;
+        po = a[6];
+      } else {
+        const double rho = sqrt((px - a[0]) * (px - a[0]) + (py - a[1]) * (py - a[1]));
+        const double fr = logistic((a[2] - rho) / s);
+        const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
+        ind = fr * fz;
+        po = a[5];
+      }
+      v = fmin(v, 1.0 - ind * (1.0 - po));
+    }
+    phi[c] = (T)v;
+  }
+}
+
 namespace {
 struct DevBuf {
   void* p = nullptr;
@@ -339,6 +383,37 @@ std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t
     UF_HIP_CHECK(hipStreamSynchronize(stream));
   }
   return "";
+}
+
+}  // namespace uf
+
+namespace uf {
+
+void smooth_porosity_run(const uf_smooth_objects& o, int dtype, void* phi, hipStream_t stream) {
+  std::vector<double> obj;
+  for (int b = 0; b < o.nboxes; ++b) {
+    for (int q = 0; q < 7; ++q) obj.push_back(o.boxes[7 * b + q]);
+    obj.push_back(0.0);
+  }
+  for (int c = 0; c < o.ncyls; ++c) {
+    for (int q = 0; q < 6; ++q) obj.push_back(o.cylinders[6 * c + q]);
+    obj.push_back(0.0);
+    obj.push_back(1.0);
+  }
+  const int nobj = o.nboxes + o.ncyls;
+  DevBuf dobj(sizeof(double) * std::max<size_t>(obj.size(), 1));
+  if (!obj.empty())
+    UF_HIP_CHECK(hipMemcpyAsync(dobj.p, obj.data(), sizeof(double) * obj.size(), hipMemcpyHostToDevice, stream));
+  const size_t n = (size_t)o.nx * o.ny * o.nz;
+  const int blocks = (int)std::min<size_t>(8192, (n + kVoxThreads - 1) / kVoxThreads);
+  if (dtype == UF_F32)
+    hipLaunchKernelGGL(k_smooth_porosity<float>, dim3(blocks), dim3(kVoxThreads), 0, stream, dobj.as<double>(), nobj,
+                       o.nx, o.ny, o.nz, o.dx, o.dy, o.dz, o.width, (float*)phi);
+  else
+    hipLaunchKernelGGL(k_smooth_porosity<double>, dim3(blocks), dim3(kVoxThreads), 0, stream, dobj.as<double>(),
+                       nobj, o.nx, o.ny, o.nz, o.dx, o.dy, o.dz, o.width, (double*)phi);
+  UF_HIP_CHECK(hipGetLastError());
+  UF_HIP_CHECK(hipStreamSynchronize(stream));
 }
 
 }  // namespace uf

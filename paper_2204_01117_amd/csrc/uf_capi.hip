@@ -617,6 +617,34 @@ uf_status uf_voxelize(const uf_mesh_set* m, int32_t dtype, void* phi_dev, void* 
   UF_GUARD_END
 }
 
+uf_status uf_smooth_porosity(const uf_smooth_objects* o, int32_t dtype, void* phi_dev, void* stream) {
+  if (!o || !phi_dev) return fail(UF_EINVAL, "NULL argument");
+  if (dtype != UF_F32 && dtype != UF_F64) return fail(UF_EINVAL, "dtype must be UF_F32 or UF_F64");
+  if (o->nx < 1 || o->ny < 1 || o->nz < 1) return fail(UF_EINVAL, "grid sizes must be >= 1");
+  if ((double)o->nx * o->ny * o->nz > 4.0e9) return fail(UF_EINVAL, "grid too large");
+  if (!finite_pos(o->dx) || !finite_pos(o->dy) || !finite_pos(o->dz) || !finite_pos(o->width))
+    return fail(UF_EINVAL, "cell sizes and the step width must be positive and finite");
+  if (o->nboxes < 0 || o->ncyls < 0 || o->nboxes > 65536 || o->ncyls > 65536)
+    return fail(UF_EINVAL, "object count out of range");
+  if ((o->nboxes > 0 && !o->boxes) || (o->ncyls > 0 && !o->cylinders)) return fail(UF_EINVAL, "NULL object array");
+  for (int b = 0; b < o->nboxes; ++b) {
+    for (int q = 0; q < 7; ++q)
+      if (!std::isfinite(o->boxes[7 * b + q])) return fail(UF_EINVAL, "non-finite box value");
+    if (!(o->boxes[7 * b + 6] >= 0.0 && o->boxes[7 * b + 6] <= 1.0)) return fail(UF_EINVAL, "box phi outside [0, 1]");
+  }
+  for (int c = 0; c < o->ncyls; ++c) {
+    for (int q = 0; q < 6; ++q)
+      if (!std::isfinite(o->cylinders[6 * c + q])) return fail(UF_EINVAL, "non-finite cylinder value");
+    if (o->cylinders[6 * c + 2] < 0.0) return fail(UF_EINVAL, "negative cylinder radius");
+    if (!(o->cylinders[6 * c + 5] >= 0.0 && o->cylinders[6 * c + 5] <= 1.0))
+      return fail(UF_EINVAL, "cylinder phi outside [0, 1]");
+  }
+  UF_GUARD_BEGIN
+  smooth_porosity_run(*o, dtype, phi_dev, (hipStream_t)stream);
+  return UF_OK;
+  UF_GUARD_END
+}
+
 uf_status uf_set_stream(uf_grid g, void* stream) {
   if (!g) return fail(UF_EINVAL, "NULL grid");
   g->stream = (hipStream_t)stream;

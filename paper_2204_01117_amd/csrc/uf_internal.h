@@ -143,6 +143,7 @@ template <class T>
 void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, double wpen, double* part,
                             int nblocks);
 std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream, double* cast_ms);
+void smooth_porosity_run(const uf_smooth_objects& o, int dtype, void* phi, hipStream_t stream);
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_iteration_update(Grid& g, const Params<T>& P, int t, const void* Dnew);

@@ -23,11 +23,14 @@ class SimulationObjective:
     target-region objective on the GPU.
     """
 
-    def __init__(self, grid, porosity_of, regions, u_target, nsteps, initial_state=None):
+    def __init__(self, grid, porosity_of, regions=None, u_target=None, nsteps=0, initial_state=None, score=None):
+        """``score(grid) -> float`` replaces the target-region objective when
+        given (e.g. ``lambda g: g.plane_objective(1.5)``)."""
         self.grid = grid
         self.porosity_of = porosity_of
-        self.regions = [tuple(tuple(int(x) for x in lohi) for lohi in box) for box in regions]
-        self.u_target = float(u_target)
+        self.regions = [tuple(tuple(int(x) for x in lohi) for lohi in box) for box in (regions or [])]
+        self.u_target = float(u_target) if u_target is not None else 0.0
+        self.score = score
         self.nsteps = int(nsteps)
         st = initial_state if initial_state is not None else grid.state()
         self.initial = {f: a.clone() if hasattr(a, "clone") else np.array(a) for f, a in st.items()}
@@ -40,7 +43,10 @@ class SimulationObjective:
         if self.nsteps:
             g.step(self.nsteps, stats=False)
         self.calls += 1
-        return g.objective(self.regions, self.u_target)
+        return self._score(g)
+
+    def _score(self, g):
+        return self.score(g) if self.score is not None else g.objective(self.regions, self.u_target)
 
     def many(self, thetas):
         """The objective of several designs, simulated together
@@ -59,7 +65,7 @@ class SimulationObjective:
         if self.nsteps:
             step_batch(grids, self.nsteps, stats=False)
         self.calls += len(thetas)
-        return [g.objective(self.regions, self.u_target) for g in grids]
+        return [self._score(g) for g in grids]
 
 
 def forward_difference_gradient(J, theta, eps=0.1):

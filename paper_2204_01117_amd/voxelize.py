@@ -46,3 +46,28 @@ def voxelize(n, h, verts, tris, tri_begin, phi_obj, sub=4, dtype="f32", device="
     if timing is not None:
         timing["cast_ms"] = ms.value
     return out
+
+
+def smooth_porosity(n, h, boxes, cylinders, width, dtype="f32", device="cuda:0"):
+    """Porosity [nx, ny, nz] of objects with smoothed faces (uf_smooth_porosity):
+    ``boxes`` rows (x0, x1, y0, y1, z0, z1, phi), ``cylinders`` rows
+    (cx, cy, R, z0, z1, phi), logistic steps of ``width`` metres."""
+    import torch
+    dev = torch.device(device)
+    tdt = torch.float32 if dtype in ("f32", 0) else torch.float64
+    bx = [float(v) for row in boxes for v in row]
+    cy = [float(v) for row in cylinders for v in row]
+    bk = (ctypes.c_double * max(len(bx), 1))(*bx)
+    ck = (ctypes.c_double * max(len(cy), 1))(*cy)
+    o = L.uf_smooth_objects()
+    o.nx, o.ny, o.nz = (int(x) for x in n)
+    o.dx, o.dy, o.dz = (float(x) for x in h)
+    o.width = float(width)
+    o.nboxes, o.ncyls = len(boxes), len(cylinders)
+    o.boxes = ctypes.cast(bk, ctypes.POINTER(ctypes.c_double))
+    o.cylinders = ctypes.cast(ck, ctypes.POINTER(ctypes.c_double))
+    out = torch.empty(tuple(int(x) for x in n), dtype=tdt, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    L.check(L.uf_smooth_porosity(ctypes.byref(o), 0 if tdt == torch.float32 else 1, ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(stream)))
+    return out

@@ -136,7 +136,8 @@ def test_ctypes_structs_match_the_header():
     ctype_of = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "float": ctypes.c_float}
     decl = _header_structs()
     for cname, cls in (("uf_config", U.uf_config), ("uf_step_stats", U.uf_step_stats),
-                       ("uf_objective_spec", U.uf_objective_spec), ("uf_mesh_set", U.uf_mesh_set)):
+                       ("uf_objective_spec", U.uf_objective_spec), ("uf_mesh_set", U.uf_mesh_set),
+                       ("uf_smooth_objects", U.uf_smooth_objects)):
         hdr = decl[cname]
         assert [f[0] for f in hdr] == [f[0] for f in cls._fields_], cname
         for (name, typ, ptr, count), (_, ct) in zip(hdr, cls._fields_):
