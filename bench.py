@@ -581,6 +581,57 @@ def batch_bench(steps, warmup):
     print(json.dumps(res), flush=True)
 
 
+def gradient_bench(steps, warmup):
+    """One full design gradient on the 256x256x64 design case: 21 buildings
+    (height and x/y position each) and the trees' porosity, 64 parameters,
+    mapped to porosity by smoothed indicators; pedestrian-comfort objective
+    at 1.5 m after `steps` steps; forward differences (the paper's method,
+    eps = 0.1), i.e. 65 simulations run together through the batched step.
+    Beside it the plain single-case step on the same GPU."""
+    import numpy as np
+    import torch
+    import paper_2204_01117_amd as U
+    from paper_2204_01117_amd import optimize as O
+    from uf_layouts import preset, random_city
+    p = preset("C4")
+    cfg, lay = dict(p["config"]), p["layout"]
+    n, h = (cfg["nx"], cfg["ny"], cfg["nz"]), (cfg["dx"], cfg["dy"], cfg["dz"])
+    boxes, cyls, _ = random_city(*n, *h, lay["seed"], lay["n_boxes"], lay["n_trees"])
+    design = U.BoxDesign(n, h, [(*b.x, *b.y, *b.z, b.phi) for b in boxes],
+                         [(c.cx, c.cy, c.r, *c.z, c.phi) for c in cyls], width=h[0] / 2, dtype="f32")
+    g = U.Grid(cfg)
+    J = O.SimulationObjective(g, design.porosity, nsteps=warmup, score=lambda gg: gg.plane_objective(1.5))
+    theta = design.initial()
+    J.many([theta] * (design.nparams + 1))     # builds the pool of grids (warm-up)
+    torch.cuda.synchronize()
+    J.nsteps = steps
+    t0 = time.perf_counter()
+    j0, grad = O.forward_difference_gradient(J, theta, 0.1)
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    g.set_state(J.initial)
+    g.set_porosity(design.porosity(theta))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps, stats=False)
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t0
+    nsim = design.nparams + 1
+    res = {
+        "metric": "wall time of one full design gradient (forward differences)", "value": grad_s, "unit": "s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": False, "dtype": "f32",
+        "data": "synthetic seeded city, smoothed building indicators",
+        "config": {"workload": "256x256x64 dx=2m, 21 parametrised buildings + 40 trees, 64 parameters, "
+                               "plane objective at 1.5 m, %d-step horizon" % steps,
+                   "simulations": nsim, "method": "forward differences, eps 0.1, batched"},
+        "single_case_ms_per_step": single_s / steps * 1e3,
+        "sequential_estimate_s": nsim * single_s, "speedup_vs_sequential": nsim * single_s / grad_s,
+        "objective": j0, "gradient_norm": float(np.linalg.norm(grad)),
+        "gradient_head": [float(x) for x in grad[:6]], "gradient_tree_porosity": float(grad[-1]),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -592,7 +643,7 @@ def main():
     ap.add_argument("--voxelize", action="store_true", help="time the mesh voxelizer instead of the step")
     ap.add_argument("--stats-out", default="kernels_256x256x64.md", help="file name under profiles/")
     ap.add_argument("--stats-title", default="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)")
-    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "C3"])
+    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "C3", "C4"])
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
@@ -615,6 +666,8 @@ def main():
         return voxelize_bench(args.steps, args.warmup, not args.no_cpu_baseline)
     if args.workload == "C3":
         return batch_bench(args.steps, args.warmup)
+    if args.workload == "C4":
+        return gradient_bench(args.steps, min(args.warmup, 5))
 
     import torch
     import paper_2204_01117_amd as U
