@@ -245,7 +245,9 @@ uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step
 /* Solve A x = b with the grid's pressure operator (A = -L_h with the
  * boundary rows described above; SPD), preconditioner and tolerance; x_dev
  * holds the initial guess on entry and the solution on exit.  b_dev and
- * x_dev are nx*ny*nz device arrays.  Synchronises; stats may be NULL. */
+ * x_dev are nx*ny*nz device arrays.  The grid's state, its pressure
+ * included, is left as it was (the first call allocates one cell array to
+ * keep it).  Synchronises; stats may be NULL. */
 uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_stats* stats);
 
 /* Apply a fixed linear operator of the pressure solve to a cell array:

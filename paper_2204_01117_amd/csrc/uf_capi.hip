@@ -198,6 +198,7 @@ void free_grid(Grid* g) {
   f(g->NUT);
   f(g->C);
   f(g->PHI);
+  f(g->Xsave);
   f(g->inflow);
   f(g->X);
   f(g->R);
@@ -817,6 +818,12 @@ uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_s
   if (!g || !b_dev || !x_dev) return fail(UF_EINVAL, "NULL argument");
   UF_GUARD_BEGIN
   SolveResult r;
+  // the solve runs in the grid's pressure array: keep the state's pressure
+  // and the warm-start chunk length, and put them back afterwards
+  const size_t bytes = g->nelem * g->esize;
+  if (!g->Xsave) g->Xsave = dalloc(bytes);
+  UF_HIP_CHECK(hipMemcpyAsync(g->Xsave, g->X, bytes, hipMemcpyDeviceToDevice, g->stream));
+  const int last_iters = g->last_iters;
   auto go = [&](auto tag) {
     using T = decltype(tag);
     const Params<T> P = make_params<T>(*g);
@@ -829,6 +836,8 @@ uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_s
   };
   if (g->esize == 4) go(float());
   else go(double());
+  UF_HIP_CHECK(hipMemcpyAsync(g->X, g->Xsave, bytes, hipMemcpyDeviceToDevice, g->stream));
+  g->last_iters = last_iters;
   UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));

@@ -77,6 +77,7 @@ struct Grid {
   void* Z = nullptr;
   void* D[2] = {};
   void* Qv = nullptr;
+  void* Xsave = nullptr;        // the pressure state kept across uf_pressure_solve (allocated on first use)
   int dpar = 0;
   double* partials = nullptr;   // 5 slots of part_stride partial sums
   double* obj_part = nullptr;   // objective partials (allocated on first use)

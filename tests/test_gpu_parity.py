@@ -143,6 +143,28 @@ def test_multigrid_solve_with_update_in_the_restriction(dtype):
     g.close()
 
 
+def test_pressure_solve_leaves_the_state_alone():
+    """A stand-alone solve between steps changes nothing the steps see: the
+    stepped state equals that of a grid that never solved, bit for bit."""
+    p = preset("C0")
+    phi, cfg = preset_porosity(p)
+    a, b = gpu_grid(cfg, phi), gpu_grid(cfg, phi)
+    a.step(3)
+    b.step(3)
+    p_before = a.get_field("p").clone()
+    rhs = np.random.default_rng(8).normal(size=a.n)
+    x, st = a.pressure_solve(torch.tensor(rhs))
+    assert st["converged"] == 1
+    assert torch.equal(a.get_field("p"), p_before)
+    a.step(2)
+    b.step(2)
+    sa, sb = a.state(), b.state()
+    for f in sa:
+        assert torch.equal(sa[f], sb[f]), f
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("omega", [1.0, 1.6])
 def test_preconditioner_ordering_and_iterations(omega):
     """Sec. 3 / appendix A.3: with the paper's stopping rule (M^-1 r . r /
