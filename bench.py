@@ -260,7 +260,11 @@ def traffic_probe():
     log("traffic probe done: 6 steps, 3 copies of %d bytes" % COPY_BYTES)
 
 
-def traffic_summary(run_dir, command):
+def traffic_summary(run_dir, command, out_dir=None):
+    """Counter records of every measured kernel and of the whole step from
+    the FETCH_SIZE and WRITE_SIZE runs under run_dir, written to out_dir
+    (default profiles/)."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
     fd = _dispatches(os.path.join(run_dir, "fetch"), "FETCH_SIZE")
     wd = _dispatches(os.path.join(run_dir, "write"), "WRITE_SIZE")
     c_fetch, n_fetch = _copy_calibration(fd)
@@ -323,20 +327,21 @@ def traffic_summary(run_dir, command):
         "calibration": {"fetch_factor": f_fetch, "write_factor": f_write},
         "source_sha256": sources_hash(), "command": command,
     }
-    with open(os.path.join(ROOT, "profiles", "traffic_step_256x256x64.json"), "w") as f:
+    with open(os.path.join(out_dir, "traffic_step_256x256x64.json"), "w") as f:
         json.dump(step_rec, f, indent=1)
         f.write("\n")
     log("step traffic: %.3e B fixed per step (alg %.3e), %.3e B per CG iteration (alg %.3e)"
         % (step_rec["bytes_fixed_per_step"], step_rec["alg_bytes_fixed_per_step"],
            step_rec["bytes_per_cg_iteration"], step_rec["alg_bytes_per_cg_iteration"]))
     for bn, rec in out.items():
-        path = os.path.join(ROOT, "profiles", "traffic_%s_256x256x64.json" % bn)
+        path = os.path.join(out_dir, "traffic_%s_256x256x64.json" % bn)
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
             f.write("\n")
         log("%-12s traffic %.3e B/launch (alg %.3e, ratio %.2f), fetch factor %.3f write factor %.3f"
             % (bn, rec["bytes_per_launch"], rec["alg_bytes_per_launch"],
                rec["bytes_per_launch"] / rec["alg_bytes_per_launch"], f_fetch, f_write))
+    return out, step_rec
 
 
 def stats_summary(run_dir, command, out_name="kernels_256x256x64.md",

@@ -1,0 +1,72 @@
+"""Host logic of the benchmark (no GPU): the counter calibration, the
+per-kernel and per-step byte accounting, and the staleness rule of the
+committed counter records."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def write_counters(path, counter, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "x_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, (name, grid, value) in enumerate(rows):
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": name, "Grid_Size": grid, "Counter_Name": counter,
+                        "Counter_Value": value})
+
+
+def test_traffic_summary_calibrates_and_splits(tmp_path):
+    cb = bench.COPY_BYTES
+    # the copy reads each byte at counter factor 0.5 and writes it at 1.0 (KiB)
+    fetch = [("__amd_rocclr_copyBuffer", 4096, 0.5 * cb / 1024)] * 3 + [("__amd_rocclr_copyBuffer", 16, 1.0)]
+    write = [("__amd_rocclr_copyBuffer", 4096, 1.0 * cb / 1024)] * 3
+    kib = lambda b, f: f * b / 1024.0
+    # two steps, three CG iterations: the fused update (102.76 MB algorithmic)
+    # measured at 1.1x, split 2/3 read, 1/3 written
+    upd = bench.ALG_BYTES_PER_CELL["mg_update0"] * 256 * 256 * 64 * 1.1
+    for _ in range(3):
+        fetch.append(("void uf::k_mg_restrict<true, float>(...)", 262400, kib(upd * 2 / 3, 0.5)))
+        write.append(("void uf::k_mg_restrict<true, float>(...)", 262400, kib(upd / 3, 1.0)))
+        fetch.append(("void uf::k_cg_Ad<64, float>(...)", 262144, kib(7e7, 0.5)))
+        write.append(("void uf::k_cg_Ad<64, float>(...)", 262144, kib(1e6, 1.0)))
+    for _ in range(2):
+        fetch.append(("void uf::k_advect_fwd<float>(...)", 4325376, kib(9e7, 0.5)))
+        write.append(("void uf::k_advect_fwd<float>(...)", 4325376, kib(2e7, 1.0)))
+    write_counters(str(tmp_path / "run" / "fetch"), "FETCH_SIZE", fetch)
+    write_counters(str(tmp_path / "run" / "write"), "WRITE_SIZE", write)
+    out_dir = tmp_path / "out"
+    out_dir.mkdir()
+    recs, step = bench.traffic_summary(str(tmp_path / "run"), "cmd", out_dir=str(out_dir))
+    r = recs["mg_update0"]
+    assert r["calibration"]["fetch_factor"] == pytest.approx(0.5)
+    assert r["calibration"]["write_factor"] == pytest.approx(1.0)
+    assert r["calibration"]["copies"] == [3, 3]          # the small runtime copy is left out
+    assert r["bytes_per_launch"] == pytest.approx(upd)
+    assert r["bytes_per_launch"] / r["alg_bytes_per_launch"] == pytest.approx(1.1)
+    assert step["steps"] == 2 and step["cg_iterations"] == 3
+    assert step["bytes_fixed_per_step"] == pytest.approx(1.1e8)
+    assert step["bytes_per_cg_iteration"] == pytest.approx(upd + 7.1e7)
+    saved = json.load(open(out_dir / "traffic_mg_update0_256x256x64.json"))
+    assert saved["source_sha256"] == bench.sources_hash("mg_update0")
+
+
+def test_records_go_stale_with_their_own_kernel_sources_only():
+    h_upd = bench.sources_hash("mg_update0")
+    assert h_upd == bench.sources_hash("mg_down0")          # same file
+    assert h_upd != bench.sources_hash("advect_fwd")
+    assert bench.sources_hash() not in (h_upd, bench.sources_hash("advect_fwd"))
+
+
+def test_algorithmic_bytes_per_step_add_up():
+    # seven face and cell kernels, and per iteration A d, the fused update,
+    # the level-0 up/smoothing and the coarse levels at 1/7 of level 0
+    assert bench.ALG_FIXED_PER_CELL == 196.0
+    assert bench.ALG_ITER_PER_CELL == pytest.approx(16 + 24.5 + 8.5 + 13.0 / 7)
