@@ -634,6 +634,8 @@ def gradient_bench(steps, warmup):
         "objective": j0, "gradient_norm": float(np.linalg.norm(grad)),
         "gradient_head": [float(x) for x in grad[:6]], "gradient_tree_porosity": float(grad[-1]),
     }
+    J.close()
+    g.close()
     print(json.dumps(res), flush=True)
 
 

@@ -357,9 +357,16 @@ std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t
     DevBuf ditems(sizeof(VoxItem) * items.size());
     UF_HIP_CHECK(hipMemcpyAsync(ditems.p, items.data(), sizeof(VoxItem) * items.size(), hipMemcpyHostToDevice,
                                 stream));
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct Events {
+      hipEvent_t e[2] = {nullptr, nullptr};
+      ~Events() {
+        for (auto& x : e)
+          if (x) (void)hipEventDestroy(x);
+      }
+    } evs;
+    hipEvent_t* ev = evs.e;
     if (cast_ms)
-      for (auto& e : ev) UF_HIP_CHECK(hipEventCreate(&e));
+      for (int q = 0; q < 2; ++q) UF_HIP_CHECK(hipEventCreate(&ev[q]));
     if (dtype == UF_F32)
       hipExtLaunchKernelGGL(k_voxelize<float>, dim3((unsigned)items.size()), dim3(kVoxThreads), 0, stream, ev[0],
                             ev[1], 0, ditems.as<VoxItem>(), pre.as<TriRec>(), begin.as<int>(),
@@ -373,9 +380,7 @@ std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t
     UF_HIP_CHECK(hipStreamSynchronize(stream));
     if (cast_ms) {
       float ms = 0.0f;
-      const hipError_t e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-      for (auto& x : ev) (void)hipEventDestroy(x);
-      UF_HIP_CHECK(e);
+      UF_HIP_CHECK(hipEventElapsedTime(&ms, ev[0], ev[1]));
       *cast_ms = ms;
     }
     if (hflag & 4) return "a sample line crosses an object's surface more than 14 times";

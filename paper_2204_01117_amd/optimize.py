@@ -45,6 +45,12 @@ class SimulationObjective:
         self.calls += 1
         return self._score(g)
 
+    def close(self):
+        """Release the grids made for batched evaluations."""
+        for g in getattr(self, "_pool", []):
+            g.close()
+        self._pool = []
+
     def _score(self, g):
         return self.score(g) if self.score is not None else g.objective(self.regions, self.u_target)
 
