@@ -650,7 +650,7 @@ def main():
     ap.add_argument("--voxelize", action="store_true", help="time the mesh voxelizer instead of the step")
     ap.add_argument("--stats-out", default="kernels_256x256x64.md", help="file name under profiles/")
     ap.add_argument("--stats-title", default="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)")
-    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "C3", "C4"])
+    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "CP", "C3", "C4"])
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")

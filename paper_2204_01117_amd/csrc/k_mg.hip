@@ -148,8 +148,9 @@ __device__ __forceinline__ int rtaps(int I, int c, int nc, int nf, T slo, T shi,
   w[0] = 2 * I - 1 >= 0 ? T(0.125) : T(0);
   f[1] = 2 * I;
   w[1] = T(0.5) * (T(0.75) + (I == 0 ? T(0.25) * slo : T(0)));
-  f[2] = 2 * I + 1;
-  w[2] = T(0.5) * (T(0.75) + (I == nc - 1 ? T(0.25) * shi : T(0)));
+  // an odd fine axis (nf = 2 nc - 1) has no right child under its last coarse cell
+  f[2] = 2 * I + 1 < nf ? 2 * I + 1 : 2 * I;
+  w[2] = 2 * I + 1 < nf ? T(0.5) * (T(0.75) + (I == nc - 1 ? T(0.25) * shi : T(0))) : T(0);
   f[3] = 2 * I + 2 < nf ? 2 * I + 2 : 2 * I + 1;
   w[3] = 2 * I + 2 < nf ? T(0.125) : T(0);
   return 4;
@@ -506,7 +507,7 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
         auto wts = [&](int X, int nc, int nf, T slo, T shi, T (&w)[4]) {
           w[0] = 2 * X - 1 >= 0 ? T(0.125) : T(0);
           w[1] = T(0.5) * (T(0.75) + (X == 0 ? T(0.25) * slo : T(0)));
-          w[2] = T(0.5) * (T(0.75) + (X == nc - 1 ? T(0.25) * shi : T(0)));
+          w[2] = 2 * X + 1 < nf ? T(0.5) * (T(0.75) + (X == nc - 1 ? T(0.25) * shi : T(0))) : T(0);
           w[3] = 2 * X + 2 < nf ? T(0.125) : T(0);
         };
         wts(I, C.L.nx, L.nx, K.sgn[0], K.sgn[1], wi);
@@ -1087,14 +1088,16 @@ void mg_setup(Grid& g) {
     MgLevel& F = g.mg.back();
     const int n[3] = {F.L.nx, F.L.ny, F.L.nz};
     if (ncells(F.L) <= kCoarsestCells) break;
+    // every axis of at least 4 cells is halved; an odd one gets ceil(n/2)
+    // coarse cells, the last of which has a single child
     int c[3], any = 0;
     for (int a = 0; a < 3; ++a) {
-      c[a] = (n[a] % 2 == 0 && n[a] >= 4) ? 1 : 0;
+      c[a] = n[a] >= 4 ? 1 : 0;
       any |= c[a];
     }
     if (!any) break;
     MgLevel C;
-    C.L = level_layout(n[0] >> c[0], n[1] >> c[1], n[2] >> c[2]);
+    C.L = level_layout((n[0] + c[0]) >> c[0], (n[1] + c[1]) >> c[1], (n[2] + c[2]) >> c[2]);
     for (int a = 0; a < 3; ++a) {
       F.coarsen[a] = c[a];
       C.w[a] = F.w[a] / (c[a] ? 4.0 : 1.0);   // re-discretised with the doubled spacing

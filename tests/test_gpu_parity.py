@@ -83,7 +83,8 @@ def test_preconditioner_matches_matrix(seed, pc):
     g.close()
 
 
-@pytest.mark.parametrize("shape", [(64, 32, 16), (12, 10, 6), (13, 7, 5), (40, 24, 3), (16, 16, 1), (3, 3, 3)])
+@pytest.mark.parametrize("shape", [(64, 32, 16), (12, 10, 6), (13, 7, 5), (40, 24, 3), (16, 16, 1), (3, 3, 3),
+                                   (45, 30, 10), (25, 19, 9)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_multigrid_is_symmetric_positive_definite(shape, dtype):
     cfg = default_config(*shape, 2.0, dtype=dtype, precond=PC_MG, dt=0.1)
@@ -140,6 +141,25 @@ def test_multigrid_solve_with_update_in_the_restriction(dtype):
         # the same system from the solution: converged at once
         x2, st2 = g.pressure_solve(torch.tensor(b), x0=x)
         assert st2["converged"] == 1 and st2["cg_iters"] <= 1
+    g.close()
+
+
+@pytest.mark.parametrize("shape", [(45, 30, 10), (57, 38, 5), (33, 17, 9)])
+def test_multigrid_on_odd_axes(shape):
+    """Odd axes are coarsened to ceil(n/2) cells (the last coarse cell has a
+    single child): the solve equals the direct one and needs about as many
+    iterations as an even grid."""
+    cfg = default_config(*shape, 2.0, dtype="f64", precond=PC_MG, cg_tol=1e-10, cg_maxit=500,
+                         bc=[BC_INLET, BC_OUTLET, BC_OUTLET, BC_OUTLET, BC_WALL, BC_SLIP])
+    g = gpu_grid(cfg)
+    og = OracleGrid(cfg, solver="direct")
+    b = np.random.default_rng(5).normal(size=g.n)
+    xd, _ = og.pressure.solve(b.ravel(), np.zeros(b.size))
+    x, st = g.pressure_solve(torch.tensor(b))
+    log("odd grid", shape, st["cg_iters"])
+    assert st["converged"] == 1
+    assert rel(to_np(x).ravel(), xd) < 1e-8
+    assert st["cg_iters"] <= 25
     g.close()
 
 
