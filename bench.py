@@ -174,8 +174,9 @@ def step_traffic(iters_per_step, ms_per_step, ncells):
 # device headers every kernel includes): a counter record is stale when
 # these change, and only then.
 KERNEL_FILES = {
-    "advect_fwd": ["k_momentum.hip"], "advect_corr": ["k_momentum.hip"], "diffuse": ["k_momentum.hip"],
-    "drag": ["k_momentum.hip"], "project": ["k_momentum.hip"], "turbulence": ["k_cells.hip"],
+    "advect_fwd": ["k_momentum.hip", "face_ops.h"], "advect_corr": ["k_momentum.hip", "face_ops.h"],
+    "diffuse": ["k_momentum.hip", "face_ops.h"], "drag": ["k_momentum.hip", "face_ops.h"],
+    "project": ["k_momentum.hip", "face_ops.h"], "turbulence": ["k_cells.hip"],
     "cg_Ad": ["k_pressure.hip"], "cg_axpy": ["k_pressure.hip"], "cg_init": ["k_pressure.hip"],
     "mg_up0": ["k_mg.hip"], "mg_down0": ["k_mg.hip"], "mg_update0": ["k_mg.hip"],
 }

@@ -296,11 +296,47 @@ enum { UF_MAX_REGIONS = 64 };
  * UF_EINVAL for a NULL argument, an unknown kind, a region count out of
  * range, an empty box, a box outside the grid, a plane outside the cell
  * centres or a non-finite or negative parameter, before any work.
- * dJ_dstate_dev (the adjoint seed) must be NULL: the adjoint is not
- * implemented in this version (UF_ENOTIMPL, like uf_adjoint_step). */
+ * dJ_dstate_dev: NULL, or a device buffer (grid dtype) that receives dJ/du
+ * for every face of the current state -- the u block ((nx+1) ny nz), then
+ * the v block (nx (ny+1) nz), then the w block (nx ny (nz+1)), each z
+ * fastest -- the seed of uf_adjoint_step.  Each face is half of the
+ * cell-centre velocity of each adjacent cell; a cell of zero speed
+ * contributes nothing to the mean-speed gradient.  Fixed boundary faces
+ * get their derivative too (the reverse step ignores it).  The plane
+ * objective has no gradient here (UF_ENOTIMPL when dJ_dstate_dev is set). */
 uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev);
-/* One reverse step of the discrete adjoint: not implemented in this
- * version (returns UF_ENOTIMPL). */
+
+/* One reverse step of the discrete adjoint (gradients of a Sec. 4 design
+ * objective, an extension: the paper itself differences the simulator).
+ * Given the state u^n = (u, v, w) a step started from and a = dJ/du^{n+1}
+ * for its result, writes dJ/du^n = (du^{n+1}/du^n)^T a and adds
+ * (du^{n+1}/dphi)^T a into the porosity gradient.  The Jacobian is the
+ * exact derivative of the discrete step the library runs (its enabled
+ * stages), taken at the branch the forward took at every max, min and
+ * clamp (a MacCormack value clamped to its sample range follows that
+ * sample; a face stopped by the drag passes nothing); the pressure solve is
+ * treated as exact, its adjoint being the same projection applied to a
+ * (the step's projection is symmetric), solved to cg_tol with its own warm
+ * start kept in the grid between calls.
+ *   state_n_dev[3]: device, compact (u, v, w) of u^n in the grid's dtype
+ *                   (extents as uf_field_extent); fixed boundary faces are
+ *                   taken from the boundary conditions, as uf_set_field does.
+ *   adj_np1_dev[3]: device, compact dJ/du^{n+1}; values on fixed faces are
+ *                   ignored (those faces are constants).
+ *   adj_n_dev[3]:   device, compact output dJ/du^n (zero on fixed faces);
+ *                   may alias adj_np1_dev.
+ *   dJ_dphi_accum_dev: NULL, or device float64 [nx*ny*nz] (z fastest) to
+ *                   which the porosity derivative is added (chain through
+ *                   the drag coefficient of the porosity map).
+ * The grid's state, pressure and statistics are left as they were; the
+ * porosity and eddy viscosity the step uses are the grid's current ones.
+ * Adds are atomic where the forward gathers, so FP32 results can differ in
+ * the last bits between runs.  First call allocates a workspace of 23
+ * padded fields.  Synchronises the grid's stream.  UF_EINVAL for a NULL
+ * argument; UF_ENOTIMPL with the k-omega model and the turbulence stage
+ * enabled (the model's reverse is not implemented: hold the eddy viscosity
+ * fixed by disabling UF_STAGE_TURB); UF_ENOCONV / UF_ENONFINITE from the
+ * adjoint pressure solve. */
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
                           void* const* adj_n_dev, void* dJ_dphi_accum_dev);
 

@@ -1,0 +1,555 @@
+// Reverse (discrete adjoint) of the momentum stages of one step (Sec. 3),
+// for gradients of a design objective (Sec. 4) with respect to the state
+// and the porosity.  Each kernel is the transpose of the forward kernel's
+// Jacobian at the recomputed forward state, evaluated in the forward's own
+// precision:
+//
+//   * projection: the step's projection is its own transpose (b = -(rho/dt)
+//     div u*, A p = b, u = u* - (dt/rho) grad p with A symmetric and div =
+//     -grad^T), so its reverse runs the forward solve and projection on the
+//     adjoint with homogeneous boundary values (launched by the host);
+//   * drag and MacCormack advection: the transpose scatters into the input
+//     positions with atomic adds (the order of the adds is not fixed, so
+//     the FP32 result may differ in the last bits between runs);
+//   * diffusion: the transpose is a gather over every padded position;
+//   * ghosts: every ghost is written from its nearest interior face by the
+//     side rules (copy, negation at a no-slip wall, a constant at an
+//     inlet), so its adjoint is folded back into that face with the sign of
+//     the rule; fixed boundary faces hold constants and carry no adjoint.
+//
+// An adjoint array holds the derivative of the objective with respect to
+// the interior faces a stage computes; positions outside that set are read
+// as zero (adj_in).
+#include "face_ops.h"
+
+namespace uf {
+
+static inline dim3 adj_face_grid(const Layout& L) { return xcd_grid(face_gx(L), L.nx + 1); }
+
+template <class T>
+__device__ __forceinline__ void add_to(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Adjoint of face (i,j,k) of component C: zero unless it is an interior
+// face whose value the stage computes (inside the face range, not fixed).
+template <int C, class T>
+__device__ __forceinline__ T adj_in(const Params<T>& P, const T* __restrict__ a, int i, int j, int k) {
+  int ext[3];
+  face_ext<C>(P.L, ext);
+  if (i < 0 || j < 0 || k < 0 || i >= ext[0] || j >= ext[1] || k >= ext[2]) return T(0);
+  T v;
+  if (face_dirichlet<C>(P, i, j, k, &v)) return T(0);
+  return a[P.L.at(i, j, k)];
+}
+
+// Reverse of face_velocity: vb[cp] is the adjoint of the velocity component
+// cp seen at the face; it goes back to the stored face (cp == C) or, a
+// quarter each, to the four faces averaged for it.
+template <int C, class T>
+__device__ __forceinline__ void face_velocity_adj(const Layout& L, T* __restrict__ GU, T* __restrict__ GV,
+                                                  T* __restrict__ GW, long long o, const T vb[3]) {
+  T* Gs[3] = {GU, GV, GW};
+  const long long st[3] = {L.SX, (long long)L.PZ, 1LL};
+  const long long sc = st[C];
+#pragma unroll
+  for (int cp = 0; cp < 3; ++cp) {
+    if (vb[cp] == T(0)) continue;
+    if (cp == C) {
+      add_to(Gs[cp] + o, vb[cp]);
+    } else {
+      const T q = T(0.25) * vb[cp];
+      const long long s2 = st[cp];
+      add_to(Gs[cp] + o - sc, q);
+      add_to(Gs[cp] + o - sc + s2, q);
+      add_to(Gs[cp] + o, q);
+      add_to(Gs[cp] + o + s2, q);
+    }
+  }
+}
+
+// Cell and fractions of a sample position, clamped exactly as in sample().
+template <int C, class T>
+struct SamplePos {
+  long long o;      // offset of the lower corner
+  T t[3];           // fractions
+  bool live[3];     // the position was not clamped along this axis
+  __device__ __forceinline__ SamplePos(const Layout& L, T fi, T fj, T fk) {
+    int ext[3];
+    face_ext<C>(L, ext);
+    T f[3] = {fi, fj, fk};
+    int c0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      live[a] = !(f[a] < T(-1) || f[a] > T(ext[a]));
+      f[a] = fmin(fmax(f[a], T(-1)), T(ext[a]));
+      const T lf = fmin(floor(f[a]), T(ext[a] - 1));
+      t[a] = f[a] - lf;
+      c0[a] = (int)lf;
+    }
+    o = L.at(c0[0], c0[1], c0[2]);
+  }
+};
+
+// Reverse of sample(): adds wbar times the trilinear weights into the eight
+// samples of qbar, and returns in grad the derivative of the sampled value
+// with respect to the position (zero along an axis where it was clamped).
+template <int C, class T>
+__device__ __forceinline__ void sample_adj(const Layout& L, const T* __restrict__ q, T* __restrict__ qbar, T fi,
+                                           T fj, T fk, T wbar, T grad[3]) {
+  const SamplePos<C, T> s(L, fi, fj, fk);
+  const long long o = s.o, SX = L.SX, PZ = L.PZ;
+  const T ti = s.t[0], tj = s.t[1], tk = s.t[2];
+  const T s000 = q[o], s100 = q[o + SX], s010 = q[o + PZ], s110 = q[o + SX + PZ];
+  const T s001 = q[o + 1], s101 = q[o + SX + 1], s011 = q[o + PZ + 1], s111 = q[o + SX + PZ + 1];
+  const T ui = T(1) - ti, uj = T(1) - tj, uk = T(1) - tk;
+  grad[0] = s.live[0] ? uj * uk * (s100 - s000) + tj * uk * (s110 - s010) + uj * tk * (s101 - s001) +
+                            tj * tk * (s111 - s011)
+                      : T(0);
+  grad[1] = s.live[1] ? ui * uk * (s010 - s000) + ti * uk * (s110 - s100) + ui * tk * (s011 - s001) +
+                            ti * tk * (s111 - s101)
+                      : T(0);
+  grad[2] = s.live[2] ? ui * uj * (s001 - s000) + ti * uj * (s101 - s100) + ui * tj * (s011 - s010) +
+                            ti * tj * (s111 - s110)
+                      : T(0);
+  if (wbar == T(0)) return;
+  add_to(qbar + o, wbar * ui * uj * uk);
+  add_to(qbar + o + SX, wbar * ti * uj * uk);
+  add_to(qbar + o + PZ, wbar * ui * tj * uk);
+  add_to(qbar + o + SX + PZ, wbar * ti * tj * uk);
+  add_to(qbar + o + 1, wbar * ui * uj * tk);
+  add_to(qbar + o + SX + 1, wbar * ti * uj * tk);
+  add_to(qbar + o + PZ + 1, wbar * ui * tj * tk);
+  add_to(qbar + o + SX + PZ + 1, wbar * ti * tj * tk);
+}
+
+// Offset of the smallest (want_max false) or largest of the eight samples
+// around a position (the first one in corner order on a tie).
+template <int C, class T>
+__device__ __forceinline__ long long sample_extreme(const Layout& L, const T* __restrict__ q, T fi, T fj, T fk,
+                                                    bool want_max) {
+  const SamplePos<C, T> s(L, fi, fj, fk);
+  const long long offs[8] = {0, L.SX, L.PZ, L.SX + L.PZ, 1, L.SX + 1, L.PZ + 1, L.SX + L.PZ + 1};
+  long long best = s.o;
+  T bv = q[s.o];
+#pragma unroll
+  for (int n = 1; n < 8; ++n) {
+    const T v = q[s.o + offs[n]];
+    if (want_max ? v > bv : v < bv) {
+      bv = v;
+      best = s.o + offs[n];
+    }
+  }
+  return best;
+}
+
+// ------------------------------------------------------------- advection --
+// Reverse of the corrector: out = clamp(qh + (q - qc)/2, min, max) with
+// qh sampled from q at the back-traced point and qc from qhat at the
+// forward-traced point.  A clamped output is one of the eight samples of q.
+template <int C, class T>
+__device__ __forceinline__ void advect_corr_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                                const T* __restrict__ W, const T* __restrict__ qhat, T ob,
+                                                T* __restrict__ GU, T* __restrict__ GV, T* __restrict__ GW,
+                                                T* __restrict__ Ghat, long long o, int i, int j, int k) {
+  if (ob == T(0)) return;
+  T vel[3];
+  face_velocity<C>(P.L, U, V, W, o, vel);
+  const T* q = C == 0 ? U : (C == 1 ? V : W);
+  T* Gq = C == 0 ? GU : (C == 1 ? GV : GW);
+  const T di = vel[0] * P.dth[0], dj = vel[1] * P.dth[1], dk = vel[2] * P.dth[2];
+  const T bi = T(i) - di, bj = T(j) - dj, bk = T(k) - dk;
+  const T fi = T(i) + di, fj = T(j) + dj, fk = T(k) + dk;
+  T mn, mx, d0, d1;
+  const T qh = sample<C, true>(P.L, q, bi, bj, bk, &mn, &mx);
+  const T qc = sample<C, false>(P.L, qhat, fi, fj, fk, &d0, &d1);
+  const T qt = qh + T(0.5) * (q[o] - qc);
+  if (qt < mn || qt > mx) {
+    add_to(Gq + sample_extreme<C>(P.L, q, bi, bj, bk, qt > mx), ob);
+    return;
+  }
+  T gb[3], gf[3];
+  sample_adj<C>(P.L, q, Gq, bi, bj, bk, ob, gb);
+  add_to(Gq + o, T(0.5) * ob);
+  sample_adj<C>(P.L, qhat, Ghat, fi, fj, fk, T(-0.5) * ob, gf);
+  const T vb[3] = {-ob * P.dth[0] * (gb[0] + T(0.5) * gf[0]), -ob * P.dth[1] * (gb[1] + T(0.5) * gf[1]),
+                   -ob * P.dth[2] * (gb[2] + T(0.5) * gf[2])};
+  face_velocity_adj<C>(P.L, GU, GV, GW, o, vb);
+}
+
+// Reverse of the predictor: qhat = q sampled at the back-traced point.
+template <int C, class T>
+__device__ __forceinline__ void advect_fwd_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                               const T* __restrict__ W, T ob, T* __restrict__ GU, T* __restrict__ GV,
+                                               T* __restrict__ GW, long long o, int i, int j, int k) {
+  if (ob == T(0)) return;
+  T vel[3];
+  face_velocity<C>(P.L, U, V, W, o, vel);
+  const T* q = C == 0 ? U : (C == 1 ? V : W);
+  T* Gq = C == 0 ? GU : (C == 1 ? GV : GW);
+  T g[3];
+  sample_adj<C>(P.L, q, Gq, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], ob, g);
+  const T vb[3] = {-ob * P.dth[0] * g[0], -ob * P.dth[1] * g[1], -ob * P.dth[2] * g[2]};
+  face_velocity_adj<C>(P.L, GU, GV, GW, o, vb);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_corr_adj(Params<T> P, const T* __restrict__ U,
+                                                                const T* __restrict__ V, const T* __restrict__ W,
+                                                                const T* __restrict__ Uh, const T* __restrict__ Vh,
+                                                                const T* __restrict__ Wh, const T* __restrict__ A0,
+                                                                const T* __restrict__ A1, const T* __restrict__ A2,
+                                                                T* __restrict__ GU, T* __restrict__ GV,
+                                                                T* __restrict__ GW, T* __restrict__ HU,
+                                                                T* __restrict__ HV, T* __restrict__ HW) {
+  UF_FACE_THREAD(P.L);
+  const long long o = P.L.at(i, j, k);
+  advect_corr_adj<0>(P, U, V, W, Uh, adj_in<0>(P, A0, i, j, k), GU, GV, GW, HU, o, i, j, k);
+  advect_corr_adj<1>(P, U, V, W, Vh, adj_in<1>(P, A1, i, j, k), GU, GV, GW, HV, o, i, j, k);
+  advect_corr_adj<2>(P, U, V, W, Wh, adj_in<2>(P, A2, i, j, k), GU, GV, GW, HW, o, i, j, k);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_fwd_adj(Params<T> P, const T* __restrict__ U,
+                                                               const T* __restrict__ V, const T* __restrict__ W,
+                                                               const T* __restrict__ H0, const T* __restrict__ H1,
+                                                               const T* __restrict__ H2, T* __restrict__ GU,
+                                                               T* __restrict__ GV, T* __restrict__ GW) {
+  UF_FACE_THREAD(P.L);
+  const long long o = P.L.at(i, j, k);
+  advect_fwd_adj<0>(P, U, V, W, adj_in<0>(P, H0, i, j, k), GU, GV, GW, o, i, j, k);
+  advect_fwd_adj<1>(P, U, V, W, adj_in<1>(P, H1, i, j, k), GU, GV, GW, o, i, j, k);
+  advect_fwd_adj<2>(P, U, V, W, adj_in<2>(P, H2, i, j, k), GU, GV, GW, o, i, j, k);
+}
+
+// ------------------------------------------------------------- diffusion --
+template <int C, class T>
+__device__ __forceinline__ T face_nu(const Params<T>& P, const T* __restrict__ nut, long long o) {
+  return P.nu + T(0.5) * (nut[o - stride<C>(P.L)] + nut[o]);
+}
+
+// Transpose of out = q + dt nu_f lap(q) at one padded position (interior
+// or ghost) of component C: the position's own row plus the rows of its
+// six neighbours.
+template <int C, class T>
+__device__ __forceinline__ T diffuse_adj_value(const Params<T>& P, const T* __restrict__ a, const T* __restrict__ nut,
+                                               int i, int j, int k) {
+  const Layout& L = P.L;
+  T s = T(0);
+  const T self = adj_in<C>(P, a, i, j, k);
+  if (self != T(0))
+    s += self * (T(1) - T(2) * P.dt * face_nu<C>(P, nut, L.at(i, j, k)) * (P.ih2[0] + P.ih2[1] + P.ih2[2]));
+  const int d[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const int ni = i + sg * d[ax][0], nj = j + sg * d[ax][1], nk = k + sg * d[ax][2];
+      const T an = adj_in<C>(P, a, ni, nj, nk);
+      if (an != T(0)) s += an * P.dt * face_nu<C>(P, nut, L.at(ni, nj, nk)) * P.ih2[ax];
+    }
+  }
+  return s;
+}
+
+// One thread per padded position; every position of the three outputs is
+// written (zero outside [-1, extent] of the component).
+template <class T>
+__global__ __launch_bounds__(256) void k_diffuse_adj(Params<T> P, const T* __restrict__ A0, const T* __restrict__ A1,
+                                                     const T* __restrict__ A2, const T* __restrict__ NUT,
+                                                     T* __restrict__ G0, T* __restrict__ G1, T* __restrict__ G2,
+                                                     long long nelem) {
+  const Layout& L = P.L;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nelem;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / L.SX) - 1;
+    const long long r = p - (long long)(i + 1) * L.SX;
+    const int j = (int)(r / L.PZ) - 1;
+    const int k = (int)(r - (long long)(j + 1) * L.PZ) - 1;
+    const bool in_x = i <= L.nx, in_y = j <= L.ny, in_z = k <= L.nz;   // lower bound -1 always holds
+    // component C reaches index extent along its own axis (extent + 1 = n + 1 for the normal axis)
+    const bool r0 = (i <= L.nx + 1) && in_y && in_z;
+    const bool r1 = in_x && (j <= L.ny + 1) && in_z;
+    const bool r2 = in_x && in_y && (k <= L.nz + 1);
+    G0[p] = r0 ? diffuse_adj_value<0>(P, A0, NUT, i, j, k) : T(0);
+    G1[p] = r1 ? diffuse_adj_value<1>(P, A1, NUT, i, j, k) : T(0);
+    G2[p] = r2 ? diffuse_adj_value<2>(P, A2, NUT, i, j, k) : T(0);
+  }
+}
+
+// ------------------------------------------------------------ porosity drag
+// Reverse of out = max(0, 1 - dt c_f |V|) V_C: the velocity part through
+// face_velocity and the drag-coefficient part, half to each adjacent cell.
+template <int C, class T>
+__device__ __forceinline__ void drag_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                         const T* __restrict__ W, const T* __restrict__ Cc, T ob, T* __restrict__ GU,
+                                         T* __restrict__ GV, T* __restrict__ GW, T* __restrict__ Cbar, long long o) {
+  if (ob == T(0)) return;
+  T vel[3];
+  face_velocity<C>(P.L, U, V, W, o, vel);
+  const T speed = sqrt(vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]);
+  const T cf = T(0.5) * (Cc[o - stride<C>(P.L)] + Cc[o]);
+  const T fac = T(1) - P.dt * cf * speed;
+  if (!(fac > T(0))) return;   // the face is stopped: no dependence on either input
+  const T g = speed > T(0) ? P.dt * cf * vel[C] / speed : T(0);
+  T vb[3] = {-ob * g * vel[0], -ob * g * vel[1], -ob * g * vel[2]};
+  vb[C] += ob * fac;
+  face_velocity_adj<C>(P.L, GU, GV, GW, o, vb);
+  const T cb = T(-0.5) * ob * P.dt * speed * vel[C];
+  if (cb != T(0)) {
+    add_to(Cbar + o - stride<C>(P.L), cb);
+    add_to(Cbar + o, cb);
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_drag_adj(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                         const T* __restrict__ W, const T* __restrict__ Cc,
+                                                         const T* __restrict__ A0, const T* __restrict__ A1,
+                                                         const T* __restrict__ A2, T* __restrict__ GU,
+                                                         T* __restrict__ GV, T* __restrict__ GW, T* __restrict__ Cbar) {
+  UF_FACE_THREAD(P.L);
+  const long long o = P.L.at(i, j, k);
+  drag_adj<0>(P, U, V, W, Cc, adj_in<0>(P, A0, i, j, k), GU, GV, GW, Cbar, o);
+  drag_adj<1>(P, U, V, W, Cc, adj_in<1>(P, A1, i, j, k), GU, GV, GW, Cbar, o);
+  drag_adj<2>(P, U, V, W, Cc, adj_in<2>(P, A2, i, j, k), GU, GV, GW, Cbar, o);
+}
+
+// ---------------------------------------------------------------- ghosts --
+// Sign with which the ghost across side (a, hi) of component c follows its
+// neighbour (see face_rule): +1 for a copy, -1 at a no-slip wall, 0 where it
+// is the inflow constant.
+template <class T>
+__device__ __forceinline__ T rule_sign(const Params<T>& P, int c, int a, int hi) {
+  if (a == c) return T(1);
+  const int kind = P.bc[2 * a + hi];
+  if (kind == INLET) return T(0);
+  if (kind == WALL) return T(-1);
+  return T(1);
+}
+
+// Reverse of store_face for face (i,j,k) of component C: the adjoint held
+// at each ghost written from this face is added to it with the rule's sign
+// and the ghost cleared; a fixed face ends with zero.
+template <int C, class T>
+__device__ __forceinline__ void fold_face(T* __restrict__ q, const Params<T>& P, int i, int j, int k) {
+  const Layout& L = P.L;
+  const long long o = L.at(i, j, k);
+  int ext[3];
+  face_ext<C>(L, ext);
+  const bool lo0 = i == 0, hi0 = i == ext[0] - 1;
+  const bool lo1 = j == 0, hi1 = j == ext[1] - 1;
+  const bool lo2 = k == 0, hi2 = k == ext[2] - 1;
+  T acc = q[o];
+  auto take = [&](long long gpos, T s) {
+    acc += s * q[gpos];
+    q[gpos] = T(0);
+  };
+  if (lo2) take(o - 1, rule_sign(P, C, 2, 0));
+  if (hi2) take(o + 1, rule_sign(P, C, 2, 1));
+  if (lo1) take(o - L.PZ, rule_sign(P, C, 1, 0));
+  if (hi1) take(o + L.PZ, rule_sign(P, C, 1, 1));
+  if (lo0) take(o - L.SX, rule_sign(P, C, 0, 0));
+  if (hi0) take(o + L.SX, rule_sign(P, C, 0, 1));
+  if (int(lo0 | hi0) + int(lo1 | hi1) + int(lo2 | hi2) >= 2) {
+    for (int ox = -1; ox <= 1; ++ox) {
+      if ((ox == -1 && !lo0) || (ox == 1 && !hi0)) continue;
+      for (int oy = -1; oy <= 1; ++oy) {
+        if ((oy == -1 && !lo1) || (oy == 1 && !hi1)) continue;
+        for (int oz = -1; oz <= 1; ++oz) {
+          if ((oz == -1 && !lo2) || (oz == 1 && !hi2)) continue;
+          if (int(ox != 0) + int(oy != 0) + int(oz != 0) < 2) continue;
+          T s = T(1);
+          if (ox) s *= rule_sign(P, C, 0, ox > 0);
+          if (oy) s *= rule_sign(P, C, 1, oy > 0);
+          if (oz) s *= rule_sign(P, C, 2, oz > 0);
+          take(L.at(i + ox, j + oy, k + oz), s);
+        }
+      }
+    }
+  }
+  T fixed;
+  if (face_dirichlet<C>(P, i, j, k, &fixed)) acc = T(0);
+  q[o] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_fold(Params<T> P, T* __restrict__ Q0, T* __restrict__ Q1,
+                                                     T* __restrict__ Q2) {
+  UF_FACE_THREAD(P.L);
+  if (owns_face<0, T>(P.L, i, j, k)) fold_face<0>(Q0, P, i, j, k);
+  if (owns_face<1, T>(P.L, i, j, k)) fold_face<1>(Q1, P, i, j, k);
+  if (owns_face<2, T>(P.L, i, j, k)) fold_face<2>(Q2, P, i, j, k);
+}
+
+// Drag-coefficient adjoint of each cell (its face-adjacent ghosts copy it)
+// chained to the porosity: c = coef ((1 - phi)/(phi + e))^b, evaluated in
+// FP64 (dc/dphi is very large in nearly solid cells), added to phibar.
+template <class T>
+__global__ __launch_bounds__(256) void k_drag_coef_adj(Params<T> P, const T* __restrict__ Cbar,
+                                                       const T* __restrict__ PHI, double* __restrict__ phibar,
+                                                       double coef, double e, double b) {
+  const Layout& L = P.L;
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(c % L.nz);
+    const long long r = c / L.nz;
+    const int j = (int)(r % L.ny);
+    const int i = (int)(r / L.ny);
+    const long long o = L.at(i, j, k);
+    double cb = (double)Cbar[o];
+    if (i == 0) cb += (double)Cbar[o - L.SX];
+    if (i == L.nx - 1) cb += (double)Cbar[o + L.SX];
+    if (j == 0) cb += (double)Cbar[o - L.PZ];
+    if (j == L.ny - 1) cb += (double)Cbar[o + L.PZ];
+    if (k == 0) cb += (double)Cbar[o - 1];
+    if (k == L.nz - 1) cb += (double)Cbar[o + 1];
+    if (cb == 0.0) continue;
+    const double f = (double)PHI[c];
+    const double rr = (1.0 - f) / (f + e);
+    const double dcdphi = -coef * b * pow(rr, b - 1.0) * (1.0 + e) / ((f + e) * (f + e));
+    phibar[c] += cb * dcdphi;
+  }
+}
+
+// ---------------------------------------------------------- objective seed
+// Derivative of a region objective with respect to the faces of the state:
+// each face is half of the cell-centre velocity of its two cells, so
+// dJ/du_f = (dJ/dU_c[C] + dJ/dU_c'[C]) / 2 over the adjacent cells inside
+// the grid.  kind 0 (mean speeds): dJ/dU_c = (sum over the regions holding
+// c of coef_r) U_c / |U_c|; kind 2 (desired field): (sum of coef_r)
+// (U_c - U_target,c).  coef_r is precomputed by the host.
+template <class T>
+__device__ __forceinline__ T seed_cell(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                       const T* __restrict__ W, const int* __restrict__ boxes,
+                                       const double* __restrict__ coef, int nreg, int kind,
+                                       const T* __restrict__ ut, int C, int i, int j, int k) {
+  const Layout& L = P.L;
+  double cs = 0.0;
+  for (int r = 0; r < nreg; ++r) {
+    const int* b = boxes + 6 * r;
+    if (i >= b[0] && i < b[1] && j >= b[2] && j < b[3] && k >= b[4] && k < b[5]) cs += coef[r];
+  }
+  if (cs == 0.0) return T(0);
+  const long long o = L.at(i, j, k);
+  const double uc[3] = {0.5 * ((double)U[o] + (double)U[o + L.SX]), 0.5 * ((double)V[o] + (double)V[o + L.PZ]),
+                        0.5 * ((double)W[o] + (double)W[o + 1])};
+  if (kind == 0) {
+    const double s = sqrt(uc[0] * uc[0] + uc[1] * uc[1] + uc[2] * uc[2]);
+    return s > 0.0 ? T(cs * uc[C] / s) : T(0);
+  }
+  const size_t n = (size_t)L.nx * L.ny * L.nz;
+  const size_t cidx = ((size_t)i * L.ny + j) * L.nz + k;
+  return T(cs * (uc[C] - (double)ut[(size_t)C * n + cidx]));
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_objective_seed(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                        const T* __restrict__ W, const int* __restrict__ boxes,
+                                                        const double* __restrict__ coef, int nreg, int kind,
+                                                        const T* __restrict__ ut, T* __restrict__ out) {
+  const Layout& L = P.L;
+  const long long n0 = (long long)(L.nx + 1) * L.ny * L.nz, n1 = (long long)L.nx * (L.ny + 1) * L.nz;
+  const long long n2 = (long long)L.nx * L.ny * (L.nz + 1);
+  const long long ntot = n0 + n1 + n2;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < ntot;
+       p += (long long)gridDim.x * blockDim.x) {
+    int C = 0;
+    long long q = p;
+    if (q >= n0) {
+      q -= n0;
+      C = 1;
+      if (q >= n1) {
+        q -= n1;
+        C = 2;
+      }
+    }
+    const int e0 = L.nx + (C == 0), e1 = L.ny + (C == 1), e2 = L.nz + (C == 2);
+    (void)e0;
+    const int k = (int)(q % e2);
+    const long long r = q / e2;
+    const int j = (int)(r % e1);
+    const int i = (int)(r / e1);
+    const int idx[3] = {i, j, k};
+    const int nC = C == 0 ? L.nx : (C == 1 ? L.ny : L.nz);
+    T s = T(0);
+    if (idx[C] > 0)
+      s += seed_cell(P, U, V, W, boxes, coef, nreg, kind, ut, C, i - (C == 0), j - (C == 1), k - (C == 2));
+    if (idx[C] < nC) s += seed_cell(P, U, V, W, boxes, coef, nreg, kind, ut, C, i, j, k);
+    out[p] = T(0.5) * s;
+  }
+}
+
+// ----------------------------------------------------------------- launchers
+template <class T>
+void launch_advect_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Aout[3],
+                       void* const Gq[3], void* const Ghat[3]) {
+  const dim3 grid = adj_face_grid(P.L);
+  hipLaunchKernelGGL(k_advect_corr_adj<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)Qhat[0], (const T*)Qhat[1], (const T*)Qhat[2],
+                     (const T*)Aout[0], (const T*)Aout[1], (const T*)Aout[2], (T*)Gq[0], (T*)Gq[1], (T*)Gq[2],
+                     (T*)Ghat[0], (T*)Ghat[1], (T*)Ghat[2]);
+  // qhat's ghosts came from its interior faces: fold them before its reverse
+  hipLaunchKernelGGL(k_fold<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (T*)Ghat[0], (T*)Ghat[1], (T*)Ghat[2]);
+  hipLaunchKernelGGL(k_advect_fwd_adj<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)Ghat[0], (const T*)Ghat[1], (const T*)Ghat[2],
+                     (T*)Gq[0], (T*)Gq[1], (T*)Gq[2]);
+}
+
+template <class T>
+void launch_diffuse_adj(Grid& g, const Params<T>& P, void* const Aout[3], void* const Gin[3]) {
+  const long long n = (long long)g.nelem;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_diffuse_adj<T>, dim3(blocks), dim3(256), 0, g.stream, P, (const T*)Aout[0],
+                     (const T*)Aout[1], (const T*)Aout[2], (const T*)g.NUT, (T*)Gin[0], (T*)Gin[1], (T*)Gin[2], n);
+}
+
+template <class T>
+void launch_drag_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Aout[3], void* const Gin[3],
+                     void* Cbar) {
+  hipLaunchKernelGGL(k_drag_adj<T>, adj_face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)g.C, (const T*)Aout[0], (const T*)Aout[1],
+                     (const T*)Aout[2], (T*)Gin[0], (T*)Gin[1], (T*)Gin[2], (T*)Cbar);
+}
+
+template <class T>
+void launch_fold(Grid& g, const Params<T>& P, void* const A[3]) {
+  hipLaunchKernelGGL(k_fold<T>, adj_face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (T*)A[0], (T*)A[1], (T*)A[2]);
+}
+
+template <class T>
+void launch_drag_coef_adj(Grid& g, const Params<T>& P, const void* Cbar, double* phibar) {
+  const long long n = (long long)P.L.nx * P.L.ny * P.L.nz;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 8192);
+  const uf_config& c = g.cfg;
+  hipLaunchKernelGGL(k_drag_coef_adj<T>, dim3(blocks), dim3(256), 0, g.stream, P, (const T*)Cbar, (const T*)g.PHI,
+                     phibar, c.Cd * c.a, c.e, c.b);
+}
+
+template <class T>
+void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, const double* coef_dev, int nreg,
+                           int kind, const void* ut, void* out) {
+  const Layout& L = P.L;
+  const long long n = (long long)(L.nx + 1) * L.ny * L.nz + (long long)L.nx * (L.ny + 1) * L.nz +
+                      (long long)L.nx * L.ny * (L.nz + 1);
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+  void* const* Q = g.Q[g.cur];
+  hipLaunchKernelGGL(k_objective_seed<T>, dim3(blocks), dim3(256), 0, g.stream, P, (const T*)Q[0], (const T*)Q[1],
+                     (const T*)Q[2], boxes_dev, coef_dev, nreg, kind, (const T*)ut, (T*)out);
+}
+
+#define UF_INST(T)                                                                                             \
+  template void launch_advect_adj<T>(Grid&, const Params<T>&, void* const[3], void* const[3], void* const[3],  \
+                                     void* const[3], void* const[3]);                                           \
+  template void launch_diffuse_adj<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);                \
+  template void launch_drag_adj<T>(Grid&, const Params<T>&, void* const[3], void* const[3], void* const[3],    \
+                                   void*);                                                                      \
+  template void launch_fold<T>(Grid&, const Params<T>&, void* const[3]);                                        \
+  template void launch_drag_coef_adj<T>(Grid&, const Params<T>&, const void*, double*);                        \
+  template void launch_objective_seed<T>(Grid&, const Params<T>&, const int*, const double*, int, int,         \
+                                         const void*, void*);
+UF_INST(float)
+UF_INST(double)
+#undef UF_INST
+
+}  // namespace uf

@@ -207,6 +207,14 @@ void free_grid(Grid* g) {
   f(g->D[0]);
   f(g->D[1]);
   f(g->Qv);
+  for (auto& set : g->AS)
+    for (auto& q : set) f(q);
+  for (auto& set : g->AA)
+    for (auto& q : set) f(q);
+  f(g->Cbar);
+  f(g->XA);
+  f(g->inflow0);
+  f(g->obj_meta);
   void* pp = g->partials;
   f(pp);
   g->partials = nullptr;
@@ -442,6 +450,112 @@ int64_t extent(const uf_config* c, int32_t f, int32_t d[3]) {
     d[2] = e[2];
   }
   return (int64_t)e[0] * e[1] * e[2];
+}
+
+// Reverse of one step (see uf_adjoint_step).  The forward stages before
+// the projection are recomputed from the given state into the adjoint
+// workspace; then each enabled stage is reversed, last first.
+void adjoint_alloc(Grid& g) {
+  if (g.XA) return;
+  const size_t bytes = g.nelem * g.esize;
+  for (auto& set : g.AS)
+    for (auto& q : set) q = dalloc(bytes);
+  for (auto& set : g.AA)
+    for (auto& q : set) q = dalloc(bytes);
+  g.Cbar = dalloc(bytes);
+  g.XA = dalloc(bytes);
+  UF_HIP_CHECK(hipMemsetAsync(g.XA, 0, bytes, g.stream));   // zero start and zero ghosts
+  const size_t tab = 2 * (size_t)(g.L.nz + 2) * g.esize;
+  g.inflow0 = dalloc(tab);
+  UF_HIP_CHECK(hipMemsetAsync(g.inflow0, 0, tab, g.stream));
+}
+
+// The adjoint solve runs in the pressure array with its own warm start:
+// swap it in for the scope and back out on every path.
+struct AdjointPressure {
+  Grid& g;
+  int saved_iters;
+  explicit AdjointPressure(Grid& g_) : g(g_), saved_iters(g_.last_iters) {
+    std::swap(g.X, g.XA);
+    g.last_iters = g.adj_last_iters;
+  }
+  ~AdjointPressure() {
+    g.adj_last_iters = g.last_iters;
+    g.last_iters = saved_iters;
+    std::swap(g.X, g.XA);
+  }
+};
+
+template <class T>
+SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* adj_next, void* const* adj_out,
+                         double* phibar) {
+  adjoint_alloc(g);
+  const Params<T> P = make_params<T>(g);
+  Params<T> P0 = P;   // homogeneous boundary values: fixed faces and inlet ghosts are zero
+  P0.inflow = (const T*)g.inflow0;
+  const int st = g.cfg.stages;
+  const size_t bytes = g.nelem * g.esize;
+  auto zero = [&](void* const set[3]) {
+    for (int c = 0; c < 3; ++c) UF_HIP_CHECK(hipMemsetAsync(set[c], 0, bytes, g.stream));
+  };
+  // forward recompute, as in step_begin
+  for (int c = 0; c < 3; ++c) {
+    launch_pack<T>(g, P, state[c], g.AS[0][c], c, 1);
+    launch_face_bc<T>(g, P, g.AS[0][c], c);
+  }
+  void* const* x = g.AS[0];
+  if (st & UF_STAGE_ADVECT) {
+    launch_advect<T>(g, P, g.AS[0], g.AS[1], g.AS[2]);
+    x = g.AS[2];
+  }
+  if (st & UF_STAGE_DIFFUSE) {
+    launch_diffuse<T>(g, P, x, g.AS[3]);
+    x = g.AS[3];
+  }
+  void* const* drag_in = x;
+  check_launch();
+  // reverse
+  void* const* A0 = g.AA[0];
+  void* const* A1 = g.AA[1];
+  void* const* A2 = g.AA[2];
+  auto other = [&](void* const* a) { return a == A0 ? A1 : A0; };
+  zero(A0);
+  for (int c = 0; c < 3; ++c) launch_pack<T>(g, P, adj_next[c], A0[c], c, 1);
+  launch_fold<T>(g, P, A0);   // no ghosts yet: clears the fixed faces
+  void* const* a = A0;
+  SolveResult res;
+  if (st & UF_STAGE_PROJECT) {
+    AdjointPressure swap(g);
+    res = solve_pressure<T>(g, P0, a, nullptr);
+    launch_project<T>(g, P0, a, A1);
+    a = A1;
+  }
+  if (st & UF_STAGE_DRAG) {
+    void* const* d = other(a);
+    zero(d);
+    UF_HIP_CHECK(hipMemsetAsync(g.Cbar, 0, bytes, g.stream));
+    launch_drag_adj<T>(g, P, drag_in, a, d, g.Cbar);
+    launch_fold<T>(g, P, d);
+    if (phibar) launch_drag_coef_adj<T>(g, P, g.Cbar, phibar);
+    a = d;
+  }
+  if (st & UF_STAGE_DIFFUSE) {
+    void* const* d = other(a);
+    launch_diffuse_adj<T>(g, P, a, d);
+    launch_fold<T>(g, P, d);
+    a = d;
+  }
+  if (st & UF_STAGE_ADVECT) {
+    void* const* h = other(a);
+    zero(A2);
+    zero(h);
+    launch_advect_adj<T>(g, P, g.AS[0], g.AS[1], a, A2, h);
+    launch_fold<T>(g, P, A2);
+    a = A2;
+  }
+  for (int c = 0; c < 3; ++c) launch_pack<T>(g, P, a[c], adj_out[c], c, 0);
+  check_launch();
+  return res;
 }
 
 }  // namespace
@@ -875,8 +989,8 @@ uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_de
 
 uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev) {
   if (!g || !spec || !J_host) return fail(UF_EINVAL, "NULL argument");
-  if (dJ_dstate_dev)
-    return fail(UF_ENOTIMPL, "the state gradient of the objective (adjoint seed) is not implemented in this version");
+  if (dJ_dstate_dev && spec->kind == UF_OBJ_PLANE)
+    return fail(UF_ENOTIMPL, "the state gradient of the plane objective is not implemented in this version");
   if (spec->kind == UF_OBJ_PLANE) {
     const double dz = g->cfg.dz;
     const int nz = g->L.nz;
@@ -943,25 +1057,63 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
                               g->stream));
   UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   double J = 0.0;
+  std::vector<double> coef(nr);   // dJ per unit of the region's cell term (the gradient seed)
   for (int r = 0; r < nr; ++r) {
     const int* b = spec->boxes + 6 * r;
     double s = 0.0;
     for (int q = 0; q < nb[r]; ++q) s += host[(size_t)r * kBlocks + q];
+    const double cells = (double)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]);
     if (field) {
       J += std::sqrt(s);
+      coef[r] = s > 0 ? 1.0 / std::sqrt(s) : 0.0;
     } else {
-      const double mean = s / ((double)(b[1] - b[0]) * (b[3] - b[2]) * (b[5] - b[4]));
+      const double mean = s / cells;
       J += (mean - spec->u_target) * (mean - spec->u_target);
+      coef[r] = 2.0 * (mean - spec->u_target) / cells;
     }
   }
   *J_host = J;
+  if (dJ_dstate_dev) {
+    const size_t meta = UF_MAX_REGIONS * (6 * sizeof(int) + sizeof(double));
+    if (!g->obj_meta) g->obj_meta = dalloc(meta);
+    double* coef_dev = (double*)g->obj_meta;
+    int* boxes_dev = (int*)(coef_dev + UF_MAX_REGIONS);
+    UF_HIP_CHECK(hipMemcpyAsync(coef_dev, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, g->stream));
+    UF_HIP_CHECK(
+        hipMemcpyAsync(boxes_dev, spec->boxes, 6 * nr * sizeof(int), hipMemcpyHostToDevice, g->stream));
+    const int kind = field ? 2 : 0;
+    if (g->esize == 4)
+      launch_objective_seed<float>(*g, make_params<float>(*g), boxes_dev, coef_dev, nr, kind, spec->u_target_dev,
+                                   dJ_dstate_dev);
+    else
+      launch_objective_seed<double>(*g, make_params<double>(*g), boxes_dev, coef_dev, nr, kind,
+                                    spec->u_target_dev, dJ_dstate_dev);
+    check_launch();
+    UF_HIP_CHECK(hipStreamSynchronize(g->stream));   // the host tables above are copied from
+  }
   return UF_OK;
   UF_GUARD_END
 }
 
-uf_status uf_adjoint_step(uf_grid g, const void* const*, const void* const*, void* const*, void*) {
-  (void)g;
-  return fail(UF_ENOTIMPL, "uf_adjoint_step is not implemented in this library version");
+uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
+                          void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
+  if (!g || !state_n_dev || !adj_np1_dev || !adj_n_dev) return fail(UF_EINVAL, "NULL argument");
+  for (int c = 0; c < 3; ++c)
+    if (!state_n_dev[c] || !adj_np1_dev[c] || !adj_n_dev[c]) return fail(UF_EINVAL, "NULL field pointer");
+  if (g->cfg.turb_model == UF_TURB_KOMEGA && (g->cfg.stages & UF_STAGE_TURB))
+    return fail(UF_ENOTIMPL, "the adjoint of the k-omega model is not implemented: run it with the "
+                             "turbulence stage off (eddy viscosity held fixed)");
+  UF_GUARD_BEGIN
+  SolveResult r;
+  if (g->esize == 4)
+    r = adjoint_step<float>(*g, state_n_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
+  else
+    r = adjoint_step<double>(*g, state_n_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
+  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
+  if (r.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the adjoint pressure solve");
+  if (r.noconv) return fail(UF_ENOCONV, "adjoint pressure CG reached cg_maxit");
+  return UF_OK;
+  UF_GUARD_END
 }
 
 }  // extern "C"

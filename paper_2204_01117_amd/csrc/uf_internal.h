@@ -81,6 +81,14 @@ struct Grid {
   int dpar = 0;
   double* partials = nullptr;   // 5 slots of part_stride partial sums
   double* obj_part = nullptr;   // objective partials (allocated on first use)
+  void* obj_meta = nullptr;     // region boxes and seed coefficients of the objective gradient
+  // adjoint workspace (allocated on the first uf_adjoint_step)
+  void* AS[4][3] = {};          // recomputed forward: state n, predictor, advected, diffused
+  void* AA[3][3] = {};          // adjoint work sets
+  void* Cbar = nullptr;         // drag-coefficient adjoint (padded cells)
+  void* XA = nullptr;           // adjoint pressure, the warm start of the next adjoint solve
+  void* inflow0 = nullptr;      // zero inflow table (homogeneous boundary values)
+  int adj_last_iters = 0;
   size_t part_stride = 0;
   size_t cg_nb = 0;             // blocks of the fine-grid CG kernels
   size_t cg_nb_rz = 0;          // blocks of the kernel that writes the r.z partials
@@ -145,6 +153,13 @@ void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, d
                             int nblocks);
 std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream, double* cast_ms);
 void smooth_porosity_run(const uf_smooth_objects& o, int dtype, void* phi, hipStream_t stream);
+// reverse (adjoint) stages
+template <class T> void launch_advect_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Aout[3], void* const Gq[3], void* const Ghat[3]);
+template <class T> void launch_diffuse_adj(Grid& g, const Params<T>& P, void* const Aout[3], void* const Gin[3]);
+template <class T> void launch_drag_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Aout[3], void* const Gin[3], void* Cbar);
+template <class T> void launch_fold(Grid& g, const Params<T>& P, void* const A[3]);
+template <class T> void launch_drag_coef_adj(Grid& g, const Params<T>& P, const void* Cbar, double* phibar);
+template <class T> void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, const double* coef_dev, int nreg, int kind, const void* ut, void* out);
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_iteration_update(Grid& g, const Params<T>& P, int t, const void* Dnew);

@@ -99,27 +99,65 @@ class Grid:
             self.tstream.synchronize()
         return y
 
-    def objective(self, regions, u_target):
-        """Target-region objective sum_i (mean speed of region i - u_target)^2 of
-        the current state; regions are boxes ((i0, i1), (j0, j1), (k0, k1))."""
-        spec, keep = L.make_objective_spec(regions, u_target)
-        J = ctypes.c_double()
-        L.check(L.uf_objective(self.handle, byref(spec), byref(J), None))
-        del keep
-        return J.value
+    def _seed_buffer(self):
+        """Flat device buffer of the three face components (u, v, w blocks)
+        and its per-component views."""
+        ext = [self.extent(f) for f in ("u", "v", "w")]
+        sizes = [e[0] * e[1] * e[2] for e in ext]
+        buf = self.torch.empty(sum(sizes), dtype=self.dtype, device=self.device)
+        views, o = [], 0
+        for e, n in zip(ext, sizes):
+            views.append(buf[o:o + n].view(e))
+            o += n
+        return buf, tuple(views)
 
-    def field_objective(self, regions, u_target):
+    def _objective(self, spec, grad):
+        J = ctypes.c_double()
+        buf, views = self._seed_buffer() if grad else (None, None)
+        self.torch.cuda.current_stream(self.device).synchronize()
+        L.check(L.uf_objective(self.handle, byref(spec), byref(J),
+                               c_void_p(buf.data_ptr()) if grad else None))
+        return (J.value, views) if grad else J.value
+
+    def objective(self, regions, u_target, grad=False):
+        """Target-region objective sum_i (mean speed of region i - u_target)^2 of
+        the current state; regions are boxes ((i0, i1), (j0, j1), (k0, k1)).
+        With ``grad``, also its derivative with respect to the state's faces
+        as (du, dv, dw) tensors (the seed of the adjoint)."""
+        spec, keep = L.make_objective_spec(regions, u_target)
+        out = self._objective(spec, grad)
+        del keep
+        return out
+
+    def field_objective(self, regions, u_target, grad=False):
         """General objective sum_i ||F_i(u) - F_i(u_t)||_2 with F_i the
-        cell-centre velocities of region i; ``u_target`` is [3, nx, ny, nz]."""
+        cell-centre velocities of region i; ``u_target`` is [3, nx, ny, nz].
+        ``grad`` as in ``objective``."""
         ut = self._dev(u_target, (3,) + self.n)
         spec, keep = L.make_objective_spec(regions, 0.0)
         spec.kind = L.OBJ_FIELD
         spec.u_target_dev = ut.data_ptr()
-        self.torch.cuda.current_stream(self.device).synchronize()
-        J = ctypes.c_double()
-        L.check(L.uf_objective(self.handle, byref(spec), byref(J), None))
+        out = self._objective(spec, grad)
         del keep, ut
-        return J.value
+        return out
+
+    def adjoint_step(self, state, adj, phibar=None):
+        """Reverse of one step (uf_adjoint_step): ``state`` is the (u, v, w)
+        the step started from, ``adj`` the derivative of the objective with
+        respect to the step's result (u, v, w); returns the derivative with
+        respect to ``state`` and adds the porosity derivative of this step
+        into ``phibar`` (float64 [nx, ny, nz]) when given."""
+        names = ("u", "v", "w")
+        st = [self._dev(a, self.extent(f)) for a, f in zip(state, names)]
+        ad = [self._dev(a, self.extent(f)) for a, f in zip(adj, names)]
+        out = [self.torch.empty(self.extent(f), dtype=self.dtype, device=self.device) for f in names]
+        if phibar is not None:
+            assert phibar.dtype == self.torch.float64 and tuple(phibar.shape) == self.n and phibar.is_contiguous()
+        ptrs = lambda ts: (c_void_p * 3)(*[t.data_ptr() for t in ts])
+        self.torch.cuda.current_stream(self.device).synchronize()
+        L.check(L.uf_adjoint_step(self.handle, ptrs(st), ptrs(ad), ptrs(out),
+                                  c_void_p(phibar.data_ptr()) if phibar is not None else None))
+        return tuple(out)
 
     def plane_objective(self, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
         """Pedestrian-comfort objective on the horizontal plane z = z_plane:
