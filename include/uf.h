@@ -205,6 +205,19 @@ typedef struct {
  * [0, 1] or a negative radius. */
 uf_status uf_smooth_porosity(const uf_smooth_objects* objects, int32_t dtype, void* phi_dev, void* stream);
 
+/* Reverse of uf_smooth_porosity (the design-parameter chain of the
+ * adjoint): given phibar_dev = dJ/dphi (device, float64, nx*ny*nz, z
+ * fastest), writes dJ/d(object parameter) to grad_host: 7 per box (x0, x1,
+ * y0, y1, z0, z1, phi) then 6 per cylinder (cx, cy, R, z0, z1, phi).  Each
+ * cell follows the first object reaching its minimum (the branch the
+ * forward took); a ground-standing object (z0 <= 0) has no z0 derivative.
+ * FP64; per-block sums use atomic adds, so the last bits may differ
+ * between runs.  Synchronises `stream`.  UF_EINVAL as uf_smooth_porosity,
+ * and for more than UF_MAX_GRAD_OBJECTS objects. */
+enum { UF_MAX_GRAD_OBJECTS = 1024 };
+uf_status uf_smooth_porosity_grad(const uf_smooth_objects* objects, const double* phibar_dev, double* grad_host,
+                                  void* stream);
+
 /* Overwrite one state field from a device array in the layout given by
  * uf_field_extent (checkpoint restore, parity tests).  Boundary values are
  * re-imposed after the copy.  UF_PHI is the same as uf_set_porosity. */

@@ -273,6 +273,93 @@ __global__ __launch_bounds__(kVoxThreads) void k_smooth_porosity(const double* _
   }
 }
 
+// Reverse of k_smooth_porosity.  A cell's porosity follows the first object
+// reaching the minimum (none while it stays 1): phi = 1 - I (1 - phi_o), so
+// dphi/dphi_o = I and dphi/dp = -(1 - phi_o) dI/dp for a face or radius
+// parameter p, where dI/dp = I (1 - L) dt/dp for the logistic factor L(t)
+// that holds p (1 - L(t) = L(-t), no division).  Each block sums
+// phibar dphi/dp per object parameter (8 slots per object) in LDS with
+// FP64 atomic adds -- their order, and so the last bits, are not fixed --
+// and writes its row of partials; the host adds the rows in block order.
+__global__ __launch_bounds__(kVoxThreads) void k_smooth_porosity_grad(const double* __restrict__ obj, int nobj,
+                                                                     int nx, int ny, int nz, double dx, double dy,
+                                                                     double dz, double s,
+                                                                     const double* __restrict__ phibar,
+                                                                     double* __restrict__ part) {
+  extern __shared__ double acc[];
+  const int nslot = 8 * nobj;
+  for (int q = threadIdx.x; q < nslot; q += blockDim.x) acc[q] = 0.0;
+  __syncthreads();
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
+    const double pb = phibar[c];
+    if (pb == 0.0) continue;
+    const int k = (int)(c % nz);
+    const int j = (int)((c / nz) % ny);
+    const int i = (int)(c / ((size_t)nz * ny));
+    const double px = ((double)i + 0.5) * dx, py = ((double)j + 0.5) * dy, pz = ((double)k + 0.5) * dz;
+    double v = 1.0;
+    int best = -1;
+    for (int o = 0; o < nobj; ++o) {
+      const double* a = obj + 8 * o;
+      double ind, po;
+      if (a[7] == 0.0) {
+        const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
+        const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
+        const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
+        ind = fx * fy * fz;
+        po = a[6];
+      } else {
+        const double rho = sqrt((px - a[0]) * (px - a[0]) + (py - a[1]) * (py - a[1]));
+        const double fr = logistic((a[2] - rho) / s);
+        const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
+        ind = fr * fz;
+        po = a[5];
+      }
+      const double val = 1.0 - ind * (1.0 - po);
+      if (val < v) {
+        v = val;
+        best = o;
+      }
+    }
+    if (best < 0) continue;
+    const double* a = obj + 8 * best;
+    double d[7];   // dphi / d(parameter), in the object's parameter order
+    if (a[7] == 0.0) {
+      const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
+      const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
+      const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
+      const double ind = fx * fy * fz, m = -(1.0 - a[6]) * ind / s;
+      d[0] = -m * logistic(-(px - a[0]) / s);
+      d[1] = m * logistic(-(a[1] - px) / s);
+      d[2] = -m * logistic(-(py - a[2]) / s);
+      d[3] = m * logistic(-(a[3] - py) / s);
+      d[4] = a[4] > 0.0 ? -m * logistic(-(pz - a[4]) / s) : 0.0;
+      d[5] = m * logistic(-(a[5] - pz) / s);
+      d[6] = ind;
+    } else {
+      const double ex = px - a[0], ey = py - a[1];
+      const double rho = sqrt(ex * ex + ey * ey);
+      const double fr = logistic((a[2] - rho) / s);
+      const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
+      const double ind = fr * fz, m = -(1.0 - a[5]) * ind / s;
+      const double dr = m * logistic(-(a[2] - rho) / s);   // along R; the centre moves rho by -e/rho
+      d[0] = rho > 0.0 ? dr * ex / rho : 0.0;
+      d[1] = rho > 0.0 ? dr * ey / rho : 0.0;
+      d[2] = dr;
+      d[3] = a[3] > 0.0 ? -m * logistic(-(pz - a[3]) / s) : 0.0;
+      d[4] = m * logistic(-(a[4] - pz) / s);
+      d[5] = ind;
+      d[6] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+      if (d[q] != 0.0) atomicAdd(&acc[8 * best + q], pb * d[q]);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nslot; q += blockDim.x) part[(size_t)blockIdx.x * nslot + q] = acc[q];
+}
+
 namespace {
 struct DevBuf {
   void* p = nullptr;
@@ -419,6 +506,48 @@ void smooth_porosity_run(const uf_smooth_objects& o, int dtype, void* phi, hipSt
                        nobj, o.nx, o.ny, o.nz, o.dx, o.dy, o.dz, o.width, (double*)phi);
   UF_HIP_CHECK(hipGetLastError());
   UF_HIP_CHECK(hipStreamSynchronize(stream));
+}
+
+}  // namespace uf
+
+namespace uf {
+
+// Host side of uf_smooth_porosity_grad (arguments validated by the caller).
+void smooth_porosity_grad_run(const uf_smooth_objects& o, const double* phibar, double* grad, hipStream_t stream) {
+  std::vector<double> obj;
+  for (int b = 0; b < o.nboxes; ++b) {
+    for (int q = 0; q < 7; ++q) obj.push_back(o.boxes[7 * b + q]);
+    obj.push_back(0.0);
+  }
+  for (int c = 0; c < o.ncyls; ++c) {
+    for (int q = 0; q < 6; ++q) obj.push_back(o.cylinders[6 * c + q]);
+    obj.push_back(0.0);
+    obj.push_back(1.0);
+  }
+  const int nobj = o.nboxes + o.ncyls;
+  const int ng = 7 * o.nboxes + 6 * o.ncyls;
+  for (int q = 0; q < ng; ++q) grad[q] = 0.0;
+  if (nobj == 0) return;
+  const size_t n = (size_t)o.nx * o.ny * o.nz;
+  const int blocks = (int)std::min<size_t>(1024, (n + kVoxThreads - 1) / kVoxThreads);
+  const size_t nslot = 8 * (size_t)nobj;
+  DevBuf dobj(sizeof(double) * obj.size());
+  DevBuf dpart(sizeof(double) * nslot * blocks);
+  UF_HIP_CHECK(hipMemcpyAsync(dobj.p, obj.data(), sizeof(double) * obj.size(), hipMemcpyHostToDevice, stream));
+  hipLaunchKernelGGL(k_smooth_porosity_grad, dim3(blocks), dim3(kVoxThreads), sizeof(double) * nslot, stream,
+                     dobj.as<double>(), nobj, o.nx, o.ny, o.nz, o.dx, o.dy, o.dz, o.width, phibar,
+                     dpart.as<double>());
+  UF_HIP_CHECK(hipGetLastError());
+  std::vector<double> part(nslot * blocks);
+  UF_HIP_CHECK(hipMemcpyAsync(part.data(), dpart.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, stream));
+  UF_HIP_CHECK(hipStreamSynchronize(stream));
+  std::vector<double> tot(nslot, 0.0);
+  for (int b = 0; b < blocks; ++b)
+    for (size_t q = 0; q < nslot; ++q) tot[q] += part[(size_t)b * nslot + q];
+  for (int b = 0; b < o.nboxes; ++b)
+    for (int q = 0; q < 7; ++q) grad[7 * b + q] = tot[8 * b + q];
+  for (int c = 0; c < o.ncyls; ++c)
+    for (int q = 0; q < 6; ++q) grad[7 * o.nboxes + 6 * c + q] = tot[8 * (o.nboxes + c) + q];
 }
 
 }  // namespace uf

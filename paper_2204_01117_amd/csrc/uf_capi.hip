@@ -558,6 +558,27 @@ SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* a
   return res;
 }
 
+std::string check_smooth_objects(const uf_smooth_objects* o) {
+  if (o->nx < 1 || o->ny < 1 || o->nz < 1) return "grid sizes must be >= 1";
+  if ((double)o->nx * o->ny * o->nz > 4.0e9) return "grid too large";
+  if (!finite_pos(o->dx) || !finite_pos(o->dy) || !finite_pos(o->dz) || !finite_pos(o->width))
+    return "cell sizes and the step width must be positive and finite";
+  if (o->nboxes < 0 || o->ncyls < 0 || o->nboxes > 65536 || o->ncyls > 65536) return "object count out of range";
+  if ((o->nboxes > 0 && !o->boxes) || (o->ncyls > 0 && !o->cylinders)) return "NULL object array";
+  for (int b = 0; b < o->nboxes; ++b) {
+    for (int q = 0; q < 7; ++q)
+      if (!std::isfinite(o->boxes[7 * b + q])) return "non-finite box value";
+    if (!(o->boxes[7 * b + 6] >= 0.0 && o->boxes[7 * b + 6] <= 1.0)) return "box phi outside [0, 1]";
+  }
+  for (int c = 0; c < o->ncyls; ++c) {
+    for (int q = 0; q < 6; ++q)
+      if (!std::isfinite(o->cylinders[6 * c + q])) return "non-finite cylinder value";
+    if (o->cylinders[6 * c + 2] < 0.0) return "negative cylinder radius";
+    if (!(o->cylinders[6 * c + 5] >= 0.0 && o->cylinders[6 * c + 5] <= 1.0)) return "cylinder phi outside [0, 1]";
+  }
+  return "";
+}
+
 }  // namespace
 
 extern "C" {
@@ -735,27 +756,23 @@ uf_status uf_voxelize(const uf_mesh_set* m, int32_t dtype, void* phi_dev, void* 
 uf_status uf_smooth_porosity(const uf_smooth_objects* o, int32_t dtype, void* phi_dev, void* stream) {
   if (!o || !phi_dev) return fail(UF_EINVAL, "NULL argument");
   if (dtype != UF_F32 && dtype != UF_F64) return fail(UF_EINVAL, "dtype must be UF_F32 or UF_F64");
-  if (o->nx < 1 || o->ny < 1 || o->nz < 1) return fail(UF_EINVAL, "grid sizes must be >= 1");
-  if ((double)o->nx * o->ny * o->nz > 4.0e9) return fail(UF_EINVAL, "grid too large");
-  if (!finite_pos(o->dx) || !finite_pos(o->dy) || !finite_pos(o->dz) || !finite_pos(o->width))
-    return fail(UF_EINVAL, "cell sizes and the step width must be positive and finite");
-  if (o->nboxes < 0 || o->ncyls < 0 || o->nboxes > 65536 || o->ncyls > 65536)
-    return fail(UF_EINVAL, "object count out of range");
-  if ((o->nboxes > 0 && !o->boxes) || (o->ncyls > 0 && !o->cylinders)) return fail(UF_EINVAL, "NULL object array");
-  for (int b = 0; b < o->nboxes; ++b) {
-    for (int q = 0; q < 7; ++q)
-      if (!std::isfinite(o->boxes[7 * b + q])) return fail(UF_EINVAL, "non-finite box value");
-    if (!(o->boxes[7 * b + 6] >= 0.0 && o->boxes[7 * b + 6] <= 1.0)) return fail(UF_EINVAL, "box phi outside [0, 1]");
-  }
-  for (int c = 0; c < o->ncyls; ++c) {
-    for (int q = 0; q < 6; ++q)
-      if (!std::isfinite(o->cylinders[6 * c + q])) return fail(UF_EINVAL, "non-finite cylinder value");
-    if (o->cylinders[6 * c + 2] < 0.0) return fail(UF_EINVAL, "negative cylinder radius");
-    if (!(o->cylinders[6 * c + 5] >= 0.0 && o->cylinders[6 * c + 5] <= 1.0))
-      return fail(UF_EINVAL, "cylinder phi outside [0, 1]");
-  }
+  const std::string bad = check_smooth_objects(o);
+  if (!bad.empty()) return fail(UF_EINVAL, bad);
   UF_GUARD_BEGIN
   smooth_porosity_run(*o, dtype, phi_dev, (hipStream_t)stream);
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_smooth_porosity_grad(const uf_smooth_objects* o, const double* phibar_dev, double* grad_host,
+                                  void* stream) {
+  if (!o || !phibar_dev || !grad_host) return fail(UF_EINVAL, "NULL argument");
+  const std::string bad = check_smooth_objects(o);
+  if (!bad.empty()) return fail(UF_EINVAL, bad);
+  if ((long long)o->nboxes + o->ncyls > UF_MAX_GRAD_OBJECTS)
+    return fail(UF_EINVAL, "more objects than the gradient kernel holds");
+  UF_GUARD_BEGIN
+  smooth_porosity_grad_run(*o, phibar_dev, grad_host, (hipStream_t)stream);
   return UF_OK;
   UF_GUARD_END
 }

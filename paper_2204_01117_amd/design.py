@@ -5,11 +5,12 @@ parameter 3b is the height change of building b, 3b + 1 and 3b + 2 its
 shift along x and y; the last parameter is the porosity shared by all
 trees.  The porosity field comes from ``uf_smooth_porosity`` (logistic
 steps of a given width across object faces), so the objective varies
-continuously with every parameter, on the GPU.
+continuously with every parameter, on the GPU; ``gradient`` chains a
+porosity gradient back to the parameters through its reverse.
 """
 import numpy as np
 
-from .voxelize import smooth_porosity
+from .voxelize import smooth_porosity, smooth_porosity_grad
 
 
 class BoxDesign:
@@ -46,3 +47,19 @@ class BoxDesign:
     def porosity(self, theta):
         b, c = self.objects(theta)
         return smooth_porosity(self.n, self.h, b, c, self.width, self.dtype, self.device)
+
+    def gradient(self, theta, phibar):
+        """dJ/dtheta from phibar = dJ/dphi (float64 [nx, ny, nz] on the GPU):
+        the reverse of the smoothed map (uf_smooth_porosity_grad), then of
+        the parameter shifts in ``objects``."""
+        theta = np.asarray(theta, np.float64)
+        b, c = self.objects(theta)
+        gb, gc = smooth_porosity_grad(self.n, self.h, b, c, self.width, phibar)
+        g = np.zeros(self.nparams)
+        nb = len(b)
+        g[0:3 * nb:3] = gb[:, 5]
+        g[1:3 * nb:3] = gb[:, 0] + gb[:, 1]
+        g[2:3 * nb:3] = gb[:, 2] + gb[:, 3]
+        if len(c) and 0.0 <= theta[-1] <= 1.0:
+            g[-1] = gc[:, 5].sum()
+        return g

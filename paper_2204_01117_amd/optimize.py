@@ -8,6 +8,10 @@ lam times that gradient.  Printed with a plus sign, the update only
 decreases the objective with a minus sign; ``gradient_descent`` takes the
 descent form.  Defaults are the paper's eps = 0.1 and lam = 1.0.
 
+``AdjointObjective`` gives the same gradient from one forward and one
+reverse run (the discrete adjoint, uf_adjoint_step), whatever the number of
+parameters -- an extension: the paper differences the simulator.
+
 Every simulation runs on the GPU through :class:`Grid`; this module is host
 control flow only.
 """
@@ -74,6 +78,77 @@ class SimulationObjective:
         return [self._score(g) for g in grids]
 
 
+class AdjointObjective:
+    """theta -> (J, dJ/dtheta) of the flow after ``nsteps`` steps, the
+    gradient by the discrete adjoint.
+
+    ``design`` maps theta to porosity (``porosity(theta)``) and back
+    (``gradient(theta, phibar)``), as :class:`BoxDesign` does.  The objective
+    is the target-region one (``u_field`` None) or the field one
+    (``u_field`` [3, nx, ny, nz]).  Checkpoint and recompute: the forward
+    pass keeps the state every ``checkpoint`` steps and every state of the
+    last segment; the reverse pass recomputes each earlier segment from its
+    checkpoint (the forward is deterministic, so the recomputed states are
+    the same bits) and runs the reverse steps over it, accumulating dJ/dphi.
+    The grid must run without the turbulence stage (the eddy viscosity held
+    fixed), the case the adjoint covers.
+    """
+
+    def __init__(self, grid, design, regions, u_target=0.55, nsteps=1, initial_state=None, checkpoint=20,
+                 u_field=None):
+        self.grid, self.design = grid, design
+        self.regions = [tuple(tuple(int(x) for x in lohi) for lohi in box) for box in regions]
+        self.u_target = float(u_target)
+        self.u_field = u_field
+        self.nsteps = int(nsteps)
+        self.checkpoint = max(1, int(checkpoint))
+        st = initial_state if initial_state is not None else grid.state()
+        self.initial = {f: a.clone() if hasattr(a, "clone") else np.array(a) for f, a in st.items()}
+        self.calls = 0
+
+    def _objective(self, grad):
+        g = self.grid
+        if self.u_field is not None:
+            return g.field_objective(self.regions, self.u_field, grad=grad)
+        return g.objective(self.regions, self.u_target, grad=grad)
+
+    def _snapshot(self):
+        return {f: self.grid.get_field(f) for f in ("u", "v", "w", "p")}
+
+    def __call__(self, theta):
+        return self.value_and_grad(theta)[0]
+
+    def value_and_grad(self, theta):
+        import torch
+        g, K, N = self.grid, self.checkpoint, self.nsteps
+        theta = np.asarray(theta, dtype=np.float64)
+        g.set_state(self.initial)
+        g.set_porosity(self.design.porosity(theta))
+        last = ((N - 1) // K) * K if N else 0
+        ckpt, tail = {}, []
+        for s in range(N):
+            if s >= last:
+                tail.append([g.get_field(f) for f in ("u", "v", "w")])
+            elif s % K == 0:
+                ckpt[s] = self._snapshot()
+            g.step(1, stats=False)
+        J, lam = self._objective(grad=True)
+        phibar = torch.zeros(g.n, dtype=torch.float64, device=g.device)
+        for st in reversed(tail):
+            lam = g.adjoint_step(st, lam, phibar)
+        for s0 in sorted(ckpt, reverse=True):
+            g.set_state(ckpt[s0])
+            states = []
+            for _ in range(s0, min(s0 + K, N)):
+                states.append([g.get_field(f) for f in ("u", "v", "w")])
+                g.step(1, stats=False)
+            for st in reversed(states):
+                lam = g.adjoint_step(st, lam, phibar)
+        self.calls += 1
+        self.phibar = phibar
+        return J, self.design.gradient(theta, phibar)
+
+
 def forward_difference_gradient(J, theta, eps=0.1):
     """(J(theta), dJ/dtheta) by forward differences: N + 1 evaluations, all
     at once when J has a ``many`` method (the simulations are independent)."""
@@ -95,14 +170,18 @@ def forward_difference_gradient(J, theta, eps=0.1):
 
 
 def gradient_descent(J, theta0, eps=0.1, lam=1.0, iters=10, lower=None, upper=None, callback=None):
-    """Descent theta <- theta - lam * grad with forward-difference gradients,
-    optionally clipped to [lower, upper] (porosity parameters live in [0, 1]).
-    Returns (final theta, history), the history a list of (theta, J(theta),
-    grad) per iteration."""
+    """Descent theta <- theta - lam * grad, optionally clipped to
+    [lower, upper] (porosity parameters live in [0, 1]).  The gradient comes
+    from ``J.value_and_grad`` when J has one (the adjoint), else from
+    forward differences of step eps.  Returns (final theta, history), the
+    history a list of (theta, J(theta), grad) per iteration."""
     theta = np.array(theta0, dtype=np.float64)
     history = []
     for it in range(int(iters)):
-        value, grad = forward_difference_gradient(J, theta, eps)
+        if hasattr(J, "value_and_grad"):
+            value, grad = J.value_and_grad(theta)
+        else:
+            value, grad = forward_difference_gradient(J, theta, eps)
         history.append((theta.copy(), value, grad))
         if callback is not None:
             callback(it, theta, value, grad)

@@ -48,13 +48,8 @@ def voxelize(n, h, verts, tris, tri_begin, phi_obj, sub=4, dtype="f32", device="
     return out
 
 
-def smooth_porosity(n, h, boxes, cylinders, width, dtype="f32", device="cuda:0"):
-    """Porosity [nx, ny, nz] of objects with smoothed faces (uf_smooth_porosity):
-    ``boxes`` rows (x0, x1, y0, y1, z0, z1, phi), ``cylinders`` rows
-    (cx, cy, R, z0, z1, phi), logistic steps of ``width`` metres."""
-    import torch
-    dev = torch.device(device)
-    tdt = torch.float32 if dtype in ("f32", 0) else torch.float64
+def _smooth_objects(n, h, boxes, cylinders, width):
+    """uf_smooth_objects and the host arrays it points to."""
     bx = [float(v) for row in boxes for v in row]
     cy = [float(v) for row in cylinders for v in row]
     bk = (ctypes.c_double * max(len(bx), 1))(*bx)
@@ -66,8 +61,40 @@ def smooth_porosity(n, h, boxes, cylinders, width, dtype="f32", device="cuda:0")
     o.nboxes, o.ncyls = len(boxes), len(cylinders)
     o.boxes = ctypes.cast(bk, ctypes.POINTER(ctypes.c_double))
     o.cylinders = ctypes.cast(ck, ctypes.POINTER(ctypes.c_double))
+    return o, (bk, ck)
+
+
+def smooth_porosity(n, h, boxes, cylinders, width, dtype="f32", device="cuda:0"):
+    """Porosity [nx, ny, nz] of objects with smoothed faces (uf_smooth_porosity):
+    ``boxes`` rows (x0, x1, y0, y1, z0, z1, phi), ``cylinders`` rows
+    (cx, cy, R, z0, z1, phi), logistic steps of ``width`` metres."""
+    import torch
+    dev = torch.device(device)
+    tdt = torch.float32 if dtype in ("f32", 0) else torch.float64
+    o, keep = _smooth_objects(n, h, boxes, cylinders, width)
     out = torch.empty(tuple(int(x) for x in n), dtype=tdt, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
     L.check(L.uf_smooth_porosity(ctypes.byref(o), 0 if tdt == torch.float32 else 1, ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(stream)))
+    del keep
     return out
+
+
+def smooth_porosity_grad(n, h, boxes, cylinders, width, phibar):
+    """Reverse of ``smooth_porosity`` (uf_smooth_porosity_grad): from
+    phibar = dJ/dphi (float64 [nx, ny, nz] on the GPU) to dJ/d(box rows)
+    and dJ/d(cylinder rows), numpy arrays shaped like ``boxes`` (7 columns)
+    and ``cylinders`` (6 columns)."""
+    import numpy as np
+    import torch
+    assert phibar.dtype == torch.float64 and phibar.is_cuda and phibar.is_contiguous()
+    assert tuple(phibar.shape) == tuple(int(x) for x in n)
+    o, keep = _smooth_objects(n, h, boxes, cylinders, width)
+    nb, nc = len(boxes), len(cylinders)
+    out = (ctypes.c_double * max(7 * nb + 6 * nc, 1))()
+    stream = torch.cuda.current_stream(phibar.device).cuda_stream
+    L.check(L.uf_smooth_porosity_grad(ctypes.byref(o), ctypes.c_void_p(phibar.data_ptr()), out,
+                                      ctypes.c_void_p(stream)))
+    del keep
+    g = np.array(out[:7 * nb + 6 * nc], dtype=np.float64)
+    return g[:7 * nb].reshape(nb, 7), g[7 * nb:].reshape(nc, 6)

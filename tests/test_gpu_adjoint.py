@@ -236,3 +236,96 @@ def test_multistep_porosity_gradient_against_oracle(seed):
     assert abs(J - J0) <= 1e-10 * abs(J0)
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
     g.close()
+
+
+# ------------------------------------------------- design-parameter chain ---
+from oracle.smooth import smooth_porosity as oracle_smooth
+
+DESIGN_N, DESIGN_H = (24, 20, 10), (2.0, 2.0, 2.0)
+DESIGN_BOXES = [(8.0, 16.0, 10.0, 20.0, 0.0, 10.0, 0.0), (26.0, 34.0, 22.0, 32.0, 0.0, 14.0, 0.0),
+                (36.0, 42.0, 6.0, 12.0, 4.0, 12.0, 0.3)]
+DESIGN_CYLS = [(20.0, 30.0, 3.0, 0.0, 8.0, 0.5), (40.0, 30.0, 2.5, 2.0, 9.0, 0.5)]
+
+
+def test_smooth_porosity_grad_matches_oracle_differences():
+    """dJ/d(object parameters) for J = <phibar, phi(params)> against central
+    differences of the oracle's smoothed map, every parameter."""
+    n, h, width = DESIGN_N, DESIGN_H, 1.3
+    rng = np.random.default_rng(5)
+    phibar = torch.as_tensor(rng.normal(size=n)).cuda()
+    gb, gc = U.smooth_porosity_grad(n, h, DESIGN_BOXES, DESIGN_CYLS, width, phibar)
+    pb = phibar.cpu().numpy()
+    eps = 1e-5
+    for rows, grad, is_box in ((DESIGN_BOXES, gb, True), (DESIGN_CYLS, gc, False)):
+        for r in range(len(rows)):
+            for q in range(len(rows[r])):
+                if q == (4 if is_box else 3) and rows[r][q] <= 0.0:
+                    continue   # z0 <= 0: no lower step, a switch rather than a slope
+                vals = []
+                for sgn in (1, -1):
+                    moved = [list(x) for x in rows]
+                    moved[r][q] += sgn * eps
+                    b = moved if is_box else DESIGN_BOXES
+                    c = DESIGN_CYLS if is_box else moved
+                    vals.append(float((pb * oracle_smooth(n, h, b, c, width)).sum()))
+                fd = (vals[0] - vals[1]) / (2 * eps)
+                assert abs(fd - grad[r, q]) <= 1e-6 * max(1.0, abs(fd)), (is_box, r, q, fd, grad[r, q])
+    # a ground-standing object has no z0 derivative
+    assert gb[0, 4] == 0.0 and gc[0, 3] == 0.0
+
+
+def _design_case():
+    cfg = random_small_config(0, dtype="f64", precond=PC_MG, cg_tol=1e-13, cg_maxit=5000, turb_model=TURB_OFF,
+                              stages=STAGE_ALL & ~STAGE_TURB)
+    cfg.update(nx=DESIGN_N[0], ny=DESIGN_N[1], nz=DESIGN_N[2], dx=DESIGN_H[0], dy=DESIGN_H[1], dz=DESIGN_H[2],
+               dt=0.08, bc=[0, 1, 3, 3, 2, 3], wind_dir_deg=0.0, u_ref=4.0, z_ref=6.0)
+    regions = [((14, 20), (4, 16), (0, 3)), ((2, 8), (2, 18), (0, 2))]
+    return cfg, regions
+
+
+def _oracle_design_J(cfg, theta, regions, nsteps, width):
+    """The oracle's forward run of the design theta: parameter shifts written
+    out here (height, x and y shift per box, the trees' porosity)."""
+    boxes = [list(b) for b in DESIGN_BOXES]
+    for b in range(len(boxes)):
+        boxes[b][5] += theta[3 * b]
+        boxes[b][0] += theta[3 * b + 1]
+        boxes[b][1] += theta[3 * b + 1]
+        boxes[b][2] += theta[3 * b + 2]
+        boxes[b][3] += theta[3 * b + 2]
+    cyls = [list(c[:5]) + [min(max(theta[-1], 0.0), 1.0)] for c in DESIGN_CYLS]
+    og = OracleGrid(dict(cfg), solver_tol=1e-13)
+    og.set_porosity(oracle_smooth(DESIGN_N, DESIGN_H, boxes, cyls, width))
+    og.step(nsteps)
+    s = og.state()
+    return region_objective(s["u"], s["v"], s["w"], regions, 0.55)
+
+
+def test_design_gradient_by_adjoint_against_oracle():
+    """dJ/dtheta of the region objective after six steps: the adjoint with
+    checkpoints every four steps equals the one without recompute, and
+    matches central differences of the oracle's forward run."""
+    cfg, regions = _design_case()
+    width, nsteps = 1.0, 6
+    d = U.BoxDesign(DESIGN_N, DESIGN_H, DESIGN_BOXES, DESIGN_CYLS, width=width, dtype="f64")
+    g = U.Grid(cfg)
+    theta = d.initial()
+    theta[0], theta[4], theta[-1] = 0.7, -0.4, 0.45
+    A = U.AdjointObjective(g, d, regions, 0.55, nsteps=nsteps, checkpoint=4)
+    J, grad = A.value_and_grad(theta)
+    B = U.AdjointObjective(g, d, regions, 0.55, nsteps=nsteps, checkpoint=100, initial_state=A.initial)
+    J2, grad2 = B.value_and_grad(theta)
+    assert J == J2
+    assert np.allclose(grad, grad2, rtol=1e-10, atol=1e-14 * np.abs(grad).max())
+    Jo = _oracle_design_J(cfg, theta, regions, nsteps, width)
+    log("J gpu %.12e oracle %.12e" % (J, Jo))
+    assert abs(J - Jo) <= 1e-10 * abs(Jo)
+    eps = 1e-4
+    for q in (0, 1, 2, 4, 5, len(theta) - 1):
+        tp, tm = theta.copy(), theta.copy()
+        tp[q] += eps
+        tm[q] -= eps
+        fd = (_oracle_design_J(cfg, tp, regions, nsteps, width) - _oracle_design_J(cfg, tm, regions, nsteps, width)) / (2 * eps)
+        log("  theta[%d]: FD(oracle) %.10e  adjoint %.10e" % (q, fd, grad[q]))
+        assert abs(fd - grad[q]) <= 2e-5 * max(abs(fd), 1e-3 * np.abs(grad).max()), q
+    g.close()
