@@ -640,6 +640,78 @@ def gradient_bench(steps, warmup):
     print(json.dumps(res), flush=True)
 
 
+def adjoint_bench(steps, warmup, with_fd=True):
+    """One full design gradient on the 256x256x64 design case by the discrete
+    adjoint: 21 buildings (height and x/y position each) and the trees'
+    porosity, 64 parameters; target-region objective (six pedestrian-level
+    regions, ideal speed 0.55 m/s) after `steps` steps from a state spun up
+    for `warmup` steps; the turbulence stage off (eddy viscosity held), the
+    case the adjoint covers; checkpoints every 20 steps.  Beside it the same
+    gradient by forward differences (eps 0.1, 65 simulations batched) and a
+    plain forward run of the horizon."""
+    import numpy as np
+    import torch
+    import paper_2204_01117_amd as U
+    from paper_2204_01117_amd import optimize as O
+    from uf_layouts import preset, random_city
+    p = preset("C4")
+    cfg, lay = dict(p["config"], stages=15), p["layout"]
+    n, h = (cfg["nx"], cfg["ny"], cfg["nz"]), (cfg["dx"], cfg["dy"], cfg["dz"])
+    boxes, cyls, _ = random_city(*n, *h, lay["seed"], lay["n_boxes"], lay["n_trees"])
+    design = U.BoxDesign(n, h, [(*b.x, *b.y, *b.z, b.phi) for b in boxes],
+                         [(c.cx, c.cy, c.r, *c.z, c.phi) for c in cyls], width=h[0] / 2, dtype="f32")
+    regions = [((32 + 80 * a, 64 + 80 * a), (40 + 96 * b, 72 + 96 * b), (0, 2)) for a in range(3) for b in range(2)]
+    theta = design.initial()
+    g = U.Grid(cfg)
+    g.set_porosity(design.porosity(theta))
+    g.step(warmup, stats=False)
+    init = g.state()
+    A = O.AdjointObjective(g, design, regions, 0.55, nsteps=steps, initial_state=init, checkpoint=20)
+    A.value_and_grad(theta)                    # allocates the workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, grad = A.value_and_grad(theta)
+    torch.cuda.synchronize()
+    adj_s = time.perf_counter() - t0
+    g.set_state(init)
+    g.set_porosity(design.porosity(theta))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps, stats=False)
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t0
+    if not with_fd:
+        print(json.dumps({"metric": "wall time of one full design gradient (discrete adjoint)", "value": adj_s,
+                          "unit": "s", "steps": steps, "forward_s": fwd_s, "objective": J}), flush=True)
+        g.close()
+        return
+    F = O.SimulationObjective(g, design.porosity, regions, 0.55, nsteps=0, initial_state=init)
+    F.many([theta] * (design.nparams + 1))     # builds the pool of grids
+    F.nsteps = steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    j_fd, g_fd = O.forward_difference_gradient(F, theta, 0.1)
+    torch.cuda.synchronize()
+    fd_s = time.perf_counter() - t0
+    cos = float(np.dot(grad, g_fd) / (np.linalg.norm(grad) * np.linalg.norm(g_fd)))
+    res = {
+        "metric": "wall time of one full design gradient (discrete adjoint)", "value": adj_s, "unit": "s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": False, "dtype": "f32",
+        "data": "synthetic seeded city, smoothed building indicators",
+        "config": {"workload": "256x256x64 dx=2m, 21 parametrised buildings + 40 trees, 64 parameters, "
+                               "six target regions, %d-step horizon, turbulence stage off" % steps,
+                   "method": "discrete adjoint, checkpoints every 20 steps"},
+        "forward_s": fwd_s, "adjoint_over_forward": adj_s / fwd_s,
+        "fd_gradient_s": fd_s, "speedup_vs_fd": fd_s / adj_s,
+        "objective": J, "objective_fd_run": j_fd, "cosine_adjoint_vs_fd": cos,
+        "gradient_norm": float(np.linalg.norm(grad)), "fd_gradient_norm": float(np.linalg.norm(g_fd)),
+        "gradient_head": [float(x) for x in grad[:6]], "fd_gradient_head": [float(x) for x in g_fd[:6]],
+    }
+    F.close()
+    g.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -651,7 +723,8 @@ def main():
     ap.add_argument("--voxelize", action="store_true", help="time the mesh voxelizer instead of the step")
     ap.add_argument("--stats-out", default="kernels_256x256x64.md", help="file name under profiles/")
     ap.add_argument("--stats-title", default="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)")
-    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "CP", "C3", "C4"])
+    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "CP", "C3", "C4", "C4A"])
+    ap.add_argument("--adjoint-only", action="store_true", help="C4A: skip the forward-difference comparison")
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
@@ -676,6 +749,8 @@ def main():
         return batch_bench(args.steps, args.warmup)
     if args.workload == "C4":
         return gradient_bench(args.steps, min(args.warmup, 5))
+    if args.workload == "C4A":
+        return adjoint_bench(args.steps, args.warmup, not args.adjoint_only)
 
     import torch
     import paper_2204_01117_amd as U

@@ -40,3 +40,88 @@ def test_descent_clips_to_bounds():
     step = 0.5 - 5.0 * hist[0][2]
     assert np.array_equal(theta, np.clip(step, 0.0, 1.0))
     assert ((theta >= 0) & (theta <= 1)).all()
+
+
+class _ToyGrid:
+    """A stand-in for Grid with a state-dependent map u <- u + dt (phi - u^3)
+    on the u field (v, w, p carried along), J = sum(u^2) / 2, and the exact
+    reverse of that map: checks the checkpoint-and-recompute schedule of
+    AdjointObjective on the CPU (the reverse steps must see the states of
+    their own forward steps, in reverse order)."""
+
+    def __init__(self, m, dt):
+        import torch
+        self.torch, self.n, self.device, self.dt = torch, (m,), torch.device("cpu"), dt
+        self.f = {k: torch.zeros(m, dtype=torch.float64) for k in ("u", "v", "w", "p", "k", "omega", "nut")}
+        self.phi = torch.zeros(m, dtype=torch.float64)
+        self.steps = 0
+        self.reverse_inputs = []
+
+    def state(self):
+        return {k: v.clone() for k, v in self.f.items()}
+
+    def set_state(self, st):
+        for k, v in st.items():
+            self.f[k] = self.torch.as_tensor(v, dtype=self.torch.float64).clone()
+
+    def set_porosity(self, phi):
+        self.phi = self.torch.as_tensor(phi, dtype=self.torch.float64).clone()
+
+    def get_field(self, name):
+        return self.f[name].clone()
+
+    def step(self, n=1, stats=False):
+        for _ in range(n):
+            u = self.f["u"]
+            self.f["u"] = u + self.dt * (self.phi - u ** 3)
+            self.f["p"] = self.f["p"] + 1.0
+            self.steps += 1
+
+    def objective(self, regions, u_target, grad=False):
+        u = self.f["u"]
+        J = float(0.5 * (u * u).sum())
+        z = self.torch.zeros_like(u)
+        return (J, (u.clone(), z, z)) if grad else J
+
+    def adjoint_step(self, st, lam, phibar):
+        u = st[0]
+        self.reverse_inputs.append(float(u[0]))
+        phibar += self.dt * lam[0]
+        return (lam[0] * (1.0 - 3.0 * self.dt * u ** 2), lam[1], lam[2])
+
+
+class _ToyDesign:
+    def porosity(self, theta):
+        return np.asarray(theta, dtype=np.float64)
+
+    def gradient(self, theta, phibar):
+        return phibar.numpy().copy()
+
+
+def _toy_reference(theta, u0, dt, nsteps):
+    us = [np.array(u0, dtype=np.float64)]
+    for _ in range(nsteps):
+        us.append(us[-1] + dt * (theta - us[-1] ** 3))
+    lam, g = us[-1].copy(), np.zeros_like(theta)
+    for u in reversed(us[:-1]):
+        g += dt * lam
+        lam = lam * (1.0 - 3.0 * dt * u ** 2)
+    return 0.5 * float(np.sum(us[-1] ** 2)), g, [float(u[0]) for u in reversed(us[:-1])]
+
+
+def test_adjoint_objective_checkpoint_schedule():
+    import torch
+    m, dt = 5, 0.1
+    theta = np.linspace(0.2, 1.4, m)
+    u0 = np.linspace(-0.5, 0.7, m)
+    for nsteps, K in ((7, 3), (6, 3), (6, 20), (1, 1), (9, 1), (0, 4)):
+        g = _ToyGrid(m, dt)
+        g.f["u"] = torch.as_tensor(u0)
+        A = O.AdjointObjective(g, _ToyDesign(), [], 0.0, nsteps=nsteps, checkpoint=K)
+        J, grad = A.value_and_grad(theta)
+        J0, g0, order = _toy_reference(theta, u0, dt, nsteps)
+        assert abs(J - J0) <= 1e-14 * max(1.0, abs(J0))
+        assert np.allclose(grad, g0, rtol=1e-13, atol=1e-15)
+        assert g.reverse_inputs == order            # each reverse step saw its own state
+        last = ((nsteps - 1) // K) * K if nsteps else 0
+        assert g.steps == nsteps + last            # only the segments before the last are recomputed
