@@ -344,8 +344,10 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
  * The grid's state, pressure and statistics are left as they were; the
  * porosity and eddy viscosity the step uses are the grid's current ones.
  * Adds are atomic where the forward gathers, so FP32 results can differ in
- * the last bits between runs.  First call allocates a workspace of 23
- * padded fields.  Synchronises the grid's stream.  UF_EINVAL for a NULL
+ * the last bits between runs.  First call allocates a workspace of 32
+ * padded fields.  Work is enqueued on the grid's stream; the call waits
+ * only for the adjoint pressure solve's status, so the kernels after it
+ * may still run when it returns (stream order).  UF_EINVAL for a NULL
  * argument; UF_ENOTIMPL with the k-omega model and the turbulence stage
  * enabled (the model's reverse is not implemented: hold the eddy viscosity
  * fixed by disabling UF_STAGE_TURB); UF_ENOCONV / UF_ENONFINITE from the

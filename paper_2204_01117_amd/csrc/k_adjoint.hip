@@ -8,9 +8,10 @@
 //     div u*, A p = b, u = u* - (dt/rho) grad p with A symmetric and div =
 //     -grad^T), so its reverse runs the forward solve and projection on the
 //     adjoint with homogeneous boundary values (launched by the host);
-//   * drag and MacCormack advection: the transpose scatters into the input
-//     positions with atomic adds (the order of the adds is not fixed, so
-//     the FP32 result may differ in the last bits between runs);
+//   * drag and MacCormack advection: the transpose of the trilinear samples
+//     and of the drag coefficient scatters with atomic adds (their order is
+//     not fixed, so the FP32 result may differ in the last bits between
+//     runs); the velocity-vector part is stored per face and gathered;
 //   * diffusion: the transpose is a gather over every padded position;
 //   * ghosts: every ghost is written from its nearest interior face by the
 //     side rules (copy, negation at a no-slip wall, a constant at an
@@ -43,28 +44,70 @@ __device__ __forceinline__ T adj_in(const Params<T>& P, const T* __restrict__ a,
   return a[P.L.at(i, j, k)];
 }
 
-// Reverse of face_velocity: vb[cp] is the adjoint of the velocity component
-// cp seen at the face; it goes back to the stored face (cp == C) or, a
-// quarter each, to the four faces averaged for it.
+// Reverse of face_velocity in two parts.  A reverse kernel stores, per face
+// of component C, the adjoint vb[cp] of each velocity component the face
+// saw (VelAdj, nine padded arrays, written at every position of the face
+// thread range); k_vel_gather then adds to each face of component cp its own
+// entry and a quarter of the entries of the four faces of each other
+// component that averaged it.  Plain stores and a gather instead of nine
+// atomic adds per face and component.
+template <class T>
+struct VelAdj {
+  T* a[3][3];   // a[C][cp]: adjoint of velocity component cp seen at faces of component C
+};
+
 template <int C, class T>
-__device__ __forceinline__ void face_velocity_adj(const Layout& L, T* __restrict__ GU, T* __restrict__ GV,
-                                                  T* __restrict__ GW, long long o, const T vb[3]) {
-  T* Gs[3] = {GU, GV, GW};
-  const long long st[3] = {L.SX, (long long)L.PZ, 1LL};
-  const long long sc = st[C];
+__device__ __forceinline__ void vel_store(const VelAdj<T>& V, long long o, const T vb[3], bool accumulate) {
 #pragma unroll
   for (int cp = 0; cp < 3; ++cp) {
-    if (vb[cp] == T(0)) continue;
-    if (cp == C) {
-      add_to(Gs[cp] + o, vb[cp]);
-    } else {
-      const T q = T(0.25) * vb[cp];
-      const long long s2 = st[cp];
-      add_to(Gs[cp] + o - sc, q);
-      add_to(Gs[cp] + o - sc + s2, q);
-      add_to(Gs[cp] + o, q);
-      add_to(Gs[cp] + o + s2, q);
-    }
+    T* q = V.a[C][cp] + o;
+    *q = accumulate ? *q + vb[cp] : vb[cp];
+  }
+}
+
+// Inside the face thread range (where VelAdj entries are written)?
+__device__ __forceinline__ bool in_face_range(const Layout& L, int i, int j, int k) {
+  return i >= 0 && j >= 0 && k >= 0 && i <= L.nx && j <= L.ny && k <= L.nz;
+}
+
+template <int CP, class T>
+__device__ __forceinline__ T vel_gather_value(const Layout& L, const VelAdj<T>& V, int i, int j, int k) {
+  T s = T(0);
+  if (in_face_range(L, i, j, k)) s += V.a[CP][CP][L.at(i, j, k)];
+  const int e2[3] = {CP == 0, CP == 1, CP == 2};
+#pragma unroll
+  for (int C = 0; C < 3; ++C) {
+    if (C == CP) continue;
+    const int ec[3] = {C == 0, C == 1, C == 2};
+    // faces o of component C whose average of component CP reads (i,j,k):
+    // o = t + e_C, t + e_C - e_CP, t, t - e_CP
+    const int oi[4] = {i + ec[0], i + ec[0] - e2[0], i, i - e2[0]};
+    const int oj[4] = {j + ec[1], j + ec[1] - e2[1], j, j - e2[1]};
+    const int ok[4] = {k + ec[2], k + ec[2] - e2[2], k, k - e2[2]};
+    T q = T(0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (in_face_range(L, oi[m], oj[m], ok[m])) q += V.a[C][CP][L.at(oi[m], oj[m], ok[m])];
+    s += T(0.25) * q;
+  }
+  return s;
+}
+
+// One thread per padded position: G_cp += the gathered velocity adjoint.
+template <class T>
+__global__ __launch_bounds__(256) void k_vel_gather(Params<T> P, VelAdj<T> V, T* __restrict__ G0,
+                                                    T* __restrict__ G1, T* __restrict__ G2, long long nelem) {
+  const Layout& L = P.L;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nelem;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / L.SX) - 1;
+    const long long r = p - (long long)(i + 1) * L.SX;
+    const int j = (int)(r / L.PZ) - 1;
+    const int k = (int)(r - (long long)(j + 1) * L.PZ) - 1;
+    if (i > L.nx + 1 || j > L.ny + 1 || k > L.nz + 1) continue;
+    G0[p] += vel_gather_value<0>(L, V, i, j, k);
+    G1[p] += vel_gather_value<1>(L, V, i, j, k);
+    G2[p] += vel_gather_value<2>(L, V, i, j, k);
   }
 }
 
@@ -151,7 +194,8 @@ template <int C, class T>
 __device__ __forceinline__ void advect_corr_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
                                                 const T* __restrict__ W, const T* __restrict__ qhat, T ob,
                                                 T* __restrict__ GU, T* __restrict__ GV, T* __restrict__ GW,
-                                                T* __restrict__ Ghat, long long o, int i, int j, int k) {
+                                                T* __restrict__ Ghat, long long o, int i, int j, int k, T vb[3]) {
+  vb[0] = vb[1] = vb[2] = T(0);
   if (ob == T(0)) return;
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
@@ -172,16 +216,17 @@ __device__ __forceinline__ void advect_corr_adj(const Params<T>& P, const T* __r
   sample_adj<C>(P.L, q, Gq, bi, bj, bk, ob, gb);
   add_to(Gq + o, T(0.5) * ob);
   sample_adj<C>(P.L, qhat, Ghat, fi, fj, fk, T(-0.5) * ob, gf);
-  const T vb[3] = {-ob * P.dth[0] * (gb[0] + T(0.5) * gf[0]), -ob * P.dth[1] * (gb[1] + T(0.5) * gf[1]),
-                   -ob * P.dth[2] * (gb[2] + T(0.5) * gf[2])};
-  face_velocity_adj<C>(P.L, GU, GV, GW, o, vb);
+  vb[0] = -ob * P.dth[0] * (gb[0] + T(0.5) * gf[0]);
+  vb[1] = -ob * P.dth[1] * (gb[1] + T(0.5) * gf[1]);
+  vb[2] = -ob * P.dth[2] * (gb[2] + T(0.5) * gf[2]);
 }
 
 // Reverse of the predictor: qhat = q sampled at the back-traced point.
 template <int C, class T>
 __device__ __forceinline__ void advect_fwd_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
                                                const T* __restrict__ W, T ob, T* __restrict__ GU, T* __restrict__ GV,
-                                               T* __restrict__ GW, long long o, int i, int j, int k) {
+                                               T* __restrict__ GW, long long o, int i, int j, int k, T vb[3]) {
+  vb[0] = vb[1] = vb[2] = T(0);
   if (ob == T(0)) return;
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
@@ -189,8 +234,9 @@ __device__ __forceinline__ void advect_fwd_adj(const Params<T>& P, const T* __re
   T* Gq = C == 0 ? GU : (C == 1 ? GV : GW);
   T g[3];
   sample_adj<C>(P.L, q, Gq, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], ob, g);
-  const T vb[3] = {-ob * P.dth[0] * g[0], -ob * P.dth[1] * g[1], -ob * P.dth[2] * g[2]};
-  face_velocity_adj<C>(P.L, GU, GV, GW, o, vb);
+  vb[0] = -ob * P.dth[0] * g[0];
+  vb[1] = -ob * P.dth[1] * g[1];
+  vb[2] = -ob * P.dth[2] * g[2];
 }
 
 template <class T>
@@ -201,12 +247,17 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_corr_adj(Params<T> P, con
                                                                 const T* __restrict__ A1, const T* __restrict__ A2,
                                                                 T* __restrict__ GU, T* __restrict__ GV,
                                                                 T* __restrict__ GW, T* __restrict__ HU,
-                                                                T* __restrict__ HV, T* __restrict__ HW) {
+                                                                T* __restrict__ HV, T* __restrict__ HW,
+                                                                VelAdj<T> VA) {
   UF_FACE_THREAD(P.L);
   const long long o = P.L.at(i, j, k);
-  advect_corr_adj<0>(P, U, V, W, Uh, adj_in<0>(P, A0, i, j, k), GU, GV, GW, HU, o, i, j, k);
-  advect_corr_adj<1>(P, U, V, W, Vh, adj_in<1>(P, A1, i, j, k), GU, GV, GW, HV, o, i, j, k);
-  advect_corr_adj<2>(P, U, V, W, Wh, adj_in<2>(P, A2, i, j, k), GU, GV, GW, HW, o, i, j, k);
+  T vb[3];
+  advect_corr_adj<0>(P, U, V, W, Uh, adj_in<0>(P, A0, i, j, k), GU, GV, GW, HU, o, i, j, k, vb);
+  vel_store<0>(VA, o, vb, false);
+  advect_corr_adj<1>(P, U, V, W, Vh, adj_in<1>(P, A1, i, j, k), GU, GV, GW, HV, o, i, j, k, vb);
+  vel_store<1>(VA, o, vb, false);
+  advect_corr_adj<2>(P, U, V, W, Wh, adj_in<2>(P, A2, i, j, k), GU, GV, GW, HW, o, i, j, k, vb);
+  vel_store<2>(VA, o, vb, false);
 }
 
 template <class T>
@@ -214,12 +265,17 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_fwd_adj(Params<T> P, cons
                                                                const T* __restrict__ V, const T* __restrict__ W,
                                                                const T* __restrict__ H0, const T* __restrict__ H1,
                                                                const T* __restrict__ H2, T* __restrict__ GU,
-                                                               T* __restrict__ GV, T* __restrict__ GW) {
+                                                               T* __restrict__ GV, T* __restrict__ GW,
+                                                               VelAdj<T> VA) {
   UF_FACE_THREAD(P.L);
   const long long o = P.L.at(i, j, k);
-  advect_fwd_adj<0>(P, U, V, W, adj_in<0>(P, H0, i, j, k), GU, GV, GW, o, i, j, k);
-  advect_fwd_adj<1>(P, U, V, W, adj_in<1>(P, H1, i, j, k), GU, GV, GW, o, i, j, k);
-  advect_fwd_adj<2>(P, U, V, W, adj_in<2>(P, H2, i, j, k), GU, GV, GW, o, i, j, k);
+  T vb[3];
+  advect_fwd_adj<0>(P, U, V, W, adj_in<0>(P, H0, i, j, k), GU, GV, GW, o, i, j, k, vb);
+  vel_store<0>(VA, o, vb, true);
+  advect_fwd_adj<1>(P, U, V, W, adj_in<1>(P, H1, i, j, k), GU, GV, GW, o, i, j, k, vb);
+  vel_store<1>(VA, o, vb, true);
+  advect_fwd_adj<2>(P, U, V, W, adj_in<2>(P, H2, i, j, k), GU, GV, GW, o, i, j, k, vb);
+  vel_store<2>(VA, o, vb, true);
 }
 
 // ------------------------------------------------------------- diffusion --
@@ -282,8 +338,9 @@ __global__ __launch_bounds__(256) void k_diffuse_adj(Params<T> P, const T* __res
 // face_velocity and the drag-coefficient part, half to each adjacent cell.
 template <int C, class T>
 __device__ __forceinline__ void drag_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
-                                         const T* __restrict__ W, const T* __restrict__ Cc, T ob, T* __restrict__ GU,
-                                         T* __restrict__ GV, T* __restrict__ GW, T* __restrict__ Cbar, long long o) {
+                                         const T* __restrict__ W, const T* __restrict__ Cc, T ob,
+                                         T* __restrict__ Cbar, long long o, T vb[3]) {
+  vb[0] = vb[1] = vb[2] = T(0);
   if (ob == T(0)) return;
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
@@ -292,9 +349,10 @@ __device__ __forceinline__ void drag_adj(const Params<T>& P, const T* __restrict
   const T fac = T(1) - P.dt * cf * speed;
   if (!(fac > T(0))) return;   // the face is stopped: no dependence on either input
   const T g = speed > T(0) ? P.dt * cf * vel[C] / speed : T(0);
-  T vb[3] = {-ob * g * vel[0], -ob * g * vel[1], -ob * g * vel[2]};
+  vb[0] = -ob * g * vel[0];
+  vb[1] = -ob * g * vel[1];
+  vb[2] = -ob * g * vel[2];
   vb[C] += ob * fac;
-  face_velocity_adj<C>(P.L, GU, GV, GW, o, vb);
   const T cb = T(-0.5) * ob * P.dt * speed * vel[C];
   if (cb != T(0)) {
     add_to(Cbar + o - stride<C>(P.L), cb);
@@ -306,13 +364,17 @@ template <class T>
 __global__ __launch_bounds__(kFaceBlock) void k_drag_adj(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
                                                          const T* __restrict__ W, const T* __restrict__ Cc,
                                                          const T* __restrict__ A0, const T* __restrict__ A1,
-                                                         const T* __restrict__ A2, T* __restrict__ GU,
-                                                         T* __restrict__ GV, T* __restrict__ GW, T* __restrict__ Cbar) {
+                                                         const T* __restrict__ A2, T* __restrict__ Cbar,
+                                                         VelAdj<T> VA) {
   UF_FACE_THREAD(P.L);
   const long long o = P.L.at(i, j, k);
-  drag_adj<0>(P, U, V, W, Cc, adj_in<0>(P, A0, i, j, k), GU, GV, GW, Cbar, o);
-  drag_adj<1>(P, U, V, W, Cc, adj_in<1>(P, A1, i, j, k), GU, GV, GW, Cbar, o);
-  drag_adj<2>(P, U, V, W, Cc, adj_in<2>(P, A2, i, j, k), GU, GV, GW, Cbar, o);
+  T vb[3];
+  drag_adj<0>(P, U, V, W, Cc, adj_in<0>(P, A0, i, j, k), Cbar, o, vb);
+  vel_store<0>(VA, o, vb, false);
+  drag_adj<1>(P, U, V, W, Cc, adj_in<1>(P, A1, i, j, k), Cbar, o, vb);
+  vel_store<1>(VA, o, vb, false);
+  drag_adj<2>(P, U, V, W, Cc, adj_in<2>(P, A2, i, j, k), Cbar, o, vb);
+  vel_store<2>(VA, o, vb, false);
 }
 
 // ---------------------------------------------------------------- ghosts --
@@ -482,18 +544,35 @@ __global__ __launch_bounds__(256) void k_objective_seed(Params<T> P, const T* __
 
 // ----------------------------------------------------------------- launchers
 template <class T>
+static VelAdj<T> vel_adj(const Grid& g) {
+  VelAdj<T> V;
+  for (int c = 0; c < 3; ++c)
+    for (int cp = 0; cp < 3; ++cp) V.a[c][cp] = (T*)g.AV[c][cp];
+  return V;
+}
+
+template <class T>
+static void launch_vel_gather(Grid& g, const Params<T>& P, void* const G[3]) {
+  const long long n = (long long)g.nelem;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_vel_gather<T>, dim3(blocks), dim3(256), 0, g.stream, P, vel_adj<T>(g), (T*)G[0], (T*)G[1],
+                     (T*)G[2], n);
+}
+
+template <class T>
 void launch_advect_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Aout[3],
                        void* const Gq[3], void* const Ghat[3]) {
   const dim3 grid = adj_face_grid(P.L);
   hipLaunchKernelGGL(k_advect_corr_adj<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)Qhat[0], (const T*)Qhat[1], (const T*)Qhat[2],
                      (const T*)Aout[0], (const T*)Aout[1], (const T*)Aout[2], (T*)Gq[0], (T*)Gq[1], (T*)Gq[2],
-                     (T*)Ghat[0], (T*)Ghat[1], (T*)Ghat[2]);
+                     (T*)Ghat[0], (T*)Ghat[1], (T*)Ghat[2], vel_adj<T>(g));
   // qhat's ghosts came from its interior faces: fold them before its reverse
   hipLaunchKernelGGL(k_fold<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (T*)Ghat[0], (T*)Ghat[1], (T*)Ghat[2]);
   hipLaunchKernelGGL(k_advect_fwd_adj<T>, grid, dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)Ghat[0], (const T*)Ghat[1], (const T*)Ghat[2],
-                     (T*)Gq[0], (T*)Gq[1], (T*)Gq[2]);
+                     (T*)Gq[0], (T*)Gq[1], (T*)Gq[2], vel_adj<T>(g));
+  launch_vel_gather<T>(g, P, Gq);
 }
 
 template <class T>
@@ -509,7 +588,8 @@ void launch_drag_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* cons
                      void* Cbar) {
   hipLaunchKernelGGL(k_drag_adj<T>, adj_face_grid(P.L), dim3(kFaceBlock), 0, g.stream, P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)g.C, (const T*)Aout[0], (const T*)Aout[1],
-                     (const T*)Aout[2], (T*)Gin[0], (T*)Gin[1], (T*)Gin[2], (T*)Cbar);
+                     (const T*)Aout[2], (T*)Cbar, vel_adj<T>(g));
+  launch_vel_gather<T>(g, P, Gin);
 }
 
 template <class T>

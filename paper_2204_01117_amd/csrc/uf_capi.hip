@@ -211,6 +211,8 @@ void free_grid(Grid* g) {
     for (auto& q : set) f(q);
   for (auto& set : g->AA)
     for (auto& q : set) f(q);
+  for (auto& set : g->AV)
+    for (auto& q : set) f(q);
   f(g->Cbar);
   f(g->XA);
   f(g->inflow0);
@@ -462,6 +464,11 @@ void adjoint_alloc(Grid& g) {
     for (auto& q : set) q = dalloc(bytes);
   for (auto& set : g.AA)
     for (auto& q : set) q = dalloc(bytes);
+  for (auto& set : g.AV)
+    for (auto& q : set) {
+      q = dalloc(bytes);
+      UF_HIP_CHECK(hipMemsetAsync(q, 0, bytes, g.stream));
+    }
   g.Cbar = dalloc(bytes);
   g.XA = dalloc(bytes);
   UF_HIP_CHECK(hipMemsetAsync(g.XA, 0, bytes, g.stream));   // zero start and zero ghosts
@@ -1126,7 +1133,6 @@ uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void*
     r = adjoint_step<float>(*g, state_n_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
   else
     r = adjoint_step<double>(*g, state_n_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
-  UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (r.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the adjoint pressure solve");
   if (r.noconv) return fail(UF_ENOCONV, "adjoint pressure CG reached cg_maxit");
   return UF_OK;

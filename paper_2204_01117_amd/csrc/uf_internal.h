@@ -85,6 +85,7 @@ struct Grid {
   // adjoint workspace (allocated on the first uf_adjoint_step)
   void* AS[4][3] = {};          // recomputed forward: state n, predictor, advected, diffused
   void* AA[3][3] = {};          // adjoint work sets
+  void* AV[3][3] = {};          // per-face velocity-vector adjoints (zero outside the face thread range)
   void* Cbar = nullptr;         // drag-coefficient adjoint (padded cells)
   void* XA = nullptr;           // adjoint pressure, the warm start of the next adjoint solve
   void* inflow0 = nullptr;      // zero inflow table (homogeneous boundary values)

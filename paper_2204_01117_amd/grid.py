@@ -154,9 +154,13 @@ class Grid:
         if phibar is not None:
             assert phibar.dtype == self.torch.float64 and tuple(phibar.shape) == self.n and phibar.is_contiguous()
         ptrs = lambda ts: (c_void_p * 3)(*[t.data_ptr() for t in ts])
-        self.torch.cuda.current_stream(self.device).synchronize()
+        own = self.tstream != self.torch.cuda.current_stream(self.device)
+        if own:
+            self.torch.cuda.current_stream(self.device).synchronize()
         L.check(L.uf_adjoint_step(self.handle, ptrs(st), ptrs(ad), ptrs(out),
                                   c_void_p(phibar.data_ptr()) if phibar is not None else None))
+        if own:
+            self.tstream.synchronize()
         return tuple(out)
 
     def plane_objective(self, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
