@@ -176,7 +176,7 @@ def step_traffic(iters_per_step, ms_per_step, ncells):
 KERNEL_FILES = {
     "advect_fwd": ["k_momentum.hip", "face_ops.h"], "advect_corr": ["k_momentum.hip", "face_ops.h"],
     "diffuse": ["k_momentum.hip", "face_ops.h"], "drag": ["k_momentum.hip", "face_ops.h"],
-    "project": ["k_momentum.hip", "face_ops.h"], "turbulence": ["k_cells.hip"],
+    "project": ["k_momentum.hip", "face_ops.h"], "turbulence": ["k_cells.hip", "turb_model.h"],
     "cg_Ad": ["k_pressure.hip"], "cg_axpy": ["k_pressure.hip"], "cg_init": ["k_pressure.hip"],
     "mg_up0": ["k_mg.hip"], "mg_down0": ["k_mg.hip"], "mg_update0": ["k_mg.hip"],
 }
@@ -644,9 +644,9 @@ def adjoint_bench(steps, warmup, with_fd=True):
     """One full design gradient on the 256x256x64 design case by the discrete
     adjoint: 21 buildings (height and x/y position each) and the trees'
     porosity, 64 parameters; target-region objective (six pedestrian-level
-    regions, ideal speed 0.55 m/s) after `steps` steps from a state spun up
-    for `warmup` steps; the turbulence stage off (eddy viscosity held), the
-    case the adjoint covers; checkpoints every 20 steps.  Beside it the same
+    regions, ideal speed 0.55 m/s) after `steps` steps of the full step
+    (k-omega included) from a state spun up for `warmup` steps; checkpoints
+    every 20 steps.  Beside it the same
     gradient by forward differences (eps 0.1, 65 simulations batched) and a
     plain forward run of the horizon."""
     import numpy as np
@@ -655,7 +655,7 @@ def adjoint_bench(steps, warmup, with_fd=True):
     from paper_2204_01117_amd import optimize as O
     from uf_layouts import preset, random_city
     p = preset("C4")
-    cfg, lay = dict(p["config"], stages=15), p["layout"]
+    cfg, lay = dict(p["config"]), p["layout"]
     n, h = (cfg["nx"], cfg["ny"], cfg["nz"]), (cfg["dx"], cfg["dy"], cfg["dz"])
     boxes, cyls, _ = random_city(*n, *h, lay["seed"], lay["n_boxes"], lay["n_trees"])
     design = U.BoxDesign(n, h, [(*b.x, *b.y, *b.z, b.phi) for b in boxes],
@@ -699,7 +699,7 @@ def adjoint_bench(steps, warmup, with_fd=True):
         "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": False, "dtype": "f32",
         "data": "synthetic seeded city, smoothed building indicators",
         "config": {"workload": "256x256x64 dx=2m, 21 parametrised buildings + 40 trees, 64 parameters, "
-                               "six target regions, %d-step horizon, turbulence stage off" % steps,
+                               "six target regions, %d-step horizon, full step with k-omega" % steps,
                    "method": "discrete adjoint, checkpoints every 20 steps"},
         "forward_s": fwd_s, "adjoint_over_forward": adj_s / fwd_s,
         "fd_gradient_s": fd_s, "speedup_vs_fd": fd_s / adj_s,

@@ -22,6 +22,7 @@
 // the interior faces a stage computes; positions outside that set are read
 // as zero (adj_in).
 #include "face_ops.h"
+#include "turb_model.h"
 
 namespace uf {
 
@@ -474,6 +475,263 @@ __global__ __launch_bounds__(256) void k_drag_coef_adj(Params<T> P, const T* __r
   }
 }
 
+// -------------------------------------------------------- k-omega reverse
+// Velocity gradients and |S|^2 at cell o, the same expressions as the
+// forward turbulence update.
+template <class T>
+struct Strain {
+  T g[3][3];   // g[c][d] = d u_c / d x_d
+  T S2;
+};
+
+template <class T>
+__device__ __forceinline__ Strain<T> strain_at(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
+                                               const T* __restrict__ W, long long o) {
+  const Layout& L = P.L;
+  const long long SX = L.SX, PZ = L.PZ;
+  const T h0 = T(0.5) * P.ih[0], h1 = T(0.5) * P.ih[1], h2 = T(0.5) * P.ih[2];
+  auto uc = [&](long long q) { return T(0.5) * (U[q] + U[q + SX]); };
+  auto vc = [&](long long q) { return T(0.5) * (V[q] + V[q + PZ]); };
+  auto wc = [&](long long q) { return T(0.5) * (W[q] + W[q + 1]); };
+  Strain<T> s;
+  s.g[0][0] = (U[o + SX] - U[o]) * P.ih[0];
+  s.g[1][1] = (V[o + PZ] - V[o]) * P.ih[1];
+  s.g[2][2] = (W[o + 1] - W[o]) * P.ih[2];
+  s.g[0][1] = (uc(o + PZ) - uc(o - PZ)) * h1;
+  s.g[0][2] = (uc(o + 1) - uc(o - 1)) * h2;
+  s.g[1][0] = (vc(o + SX) - vc(o - SX)) * h0;
+  s.g[1][2] = (vc(o + 1) - vc(o - 1)) * h2;
+  s.g[2][0] = (wc(o + SX) - wc(o - SX)) * h0;
+  s.g[2][1] = (wc(o + PZ) - wc(o - PZ)) * h1;
+  const T s01 = T(0.5) * (s.g[0][1] + s.g[1][0]), s02 = T(0.5) * (s.g[0][2] + s.g[2][0]);
+  const T s12 = T(0.5) * (s.g[1][2] + s.g[2][1]);
+  s.S2 = s.g[0][0] * s.g[0][0] + s.g[1][1] * s.g[1][1] + s.g[2][2] * s.g[2][2] +
+         T(2) * (s01 * s01 + s02 * s02 + s12 * s12);
+  return s;
+}
+
+// Reverse of strain_at: dS2/dg_dd = 2 g_dd, dS2/dg_cd = dS2/dg_dc = 2 s_cd,
+// then each gradient back to the faces it differences.
+template <class T>
+__device__ __forceinline__ void strain_adj(const Params<T>& P, const Strain<T>& s, T s2bar, T* __restrict__ GU,
+                                           T* __restrict__ GV, T* __restrict__ GW, long long o) {
+  if (s2bar == T(0)) return;
+  const Layout& L = P.L;
+  const long long SX = L.SX, PZ = L.PZ;
+  const T h0 = T(0.5) * P.ih[0], h1 = T(0.5) * P.ih[1], h2 = T(0.5) * P.ih[2];
+  const T b00 = T(2) * s.g[0][0] * s2bar, b11 = T(2) * s.g[1][1] * s2bar, b22 = T(2) * s.g[2][2] * s2bar;
+  const T b01 = (s.g[0][1] + s.g[1][0]) * s2bar;   // 2 s01 s2bar, for g01 and g10 alike
+  const T b02 = (s.g[0][2] + s.g[2][0]) * s2bar;
+  const T b12 = (s.g[1][2] + s.g[2][1]) * s2bar;
+  add_to(GU + o + SX, b00 * P.ih[0]);
+  add_to(GU + o, -b00 * P.ih[0]);
+  add_to(GV + o + PZ, b11 * P.ih[1]);
+  add_to(GV + o, -b11 * P.ih[1]);
+  add_to(GW + o + 1, b22 * P.ih[2]);
+  add_to(GW + o, -b22 * P.ih[2]);
+  // a centred difference of cell-centre values, each the mean of two faces
+  auto cdiff = [&](T* G, long long st_face, long long st_dir, T w) {
+    const T q = T(0.5) * w;
+    add_to(G + o + st_dir, q);
+    add_to(G + o + st_dir + st_face, q);
+    add_to(G + o - st_dir, -q);
+    add_to(G + o - st_dir + st_face, -q);
+  };
+  cdiff(GU, SX, PZ, b01 * h1);
+  cdiff(GU, SX, 1, b02 * h2);
+  cdiff(GV, PZ, SX, b01 * h0);
+  cdiff(GV, PZ, 1, b12 * h2);
+  cdiff(GW, 1, SX, b02 * h0);
+  cdiff(GW, 1, PZ, b12 * h1);
+}
+
+// nu_t = min(max(k / max(omega, lim), 0), cap), lim = lim_coef |S|, and its
+// derivatives where it is not clipped.
+template <class T>
+struct Nut {
+  T nut, dk, dw, dS2;
+};
+
+template <class T>
+__device__ __forceinline__ Nut<T> nut_of(const Params<T>& P, T kk, T ww, T S2) {
+  Nut<T> n;
+  const T root = sqrt(S2);
+  const T lim = P.lim_coef * root;
+  const bool den_w = ww != ww || ww > lim;   // which argument nmax returns
+  const T den = den_w ? ww : lim;
+  const T r = kk / den;
+  n.nut = nmin(nmax(r, T(0)), P.cap);
+  const bool live = r > T(0) && r < P.cap;
+  n.dk = live ? T(1) / den : T(0);
+  const T dden = live ? -r / den : T(0);
+  n.dw = den_w ? dden : T(0);
+  n.dS2 = (!den_w && root > T(0)) ? dden * P.lim_coef / (T(2) * root) : T(0);
+  return n;
+}
+
+// Reverse of the k-omega update at one cell (the forward runs on the new
+// velocity U and the old k, omega).  kb, wb, nb: adjoints of the new k,
+// omega and nu_t; writes the adjoints of the old k and omega (atomic: the
+// advection and Laplacian stencils reach the neighbours) and of U.
+template <class T>
+__global__ __launch_bounds__(256) void k_turb_adj(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                  const T* __restrict__ W, const T* __restrict__ K0,
+                                                  const T* __restrict__ W0, const T* __restrict__ KB1,
+                                                  const T* __restrict__ WB1, const T* __restrict__ NB1,
+                                                  T* __restrict__ KB0, T* __restrict__ WB0, T* __restrict__ GU,
+                                                  T* __restrict__ GV, T* __restrict__ GW) {
+  const Layout& L = P.L;
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(c % L.nz);
+    const long long rr = c / L.nz;
+    const int j = (int)(rr % L.ny);
+    const int i = (int)(rr / L.ny);
+    const long long o = L.at(i, j, k);
+    const T kb1 = KB1[o], wb1 = WB1[o], nb1 = NB1[o];
+    if (kb1 == T(0) && wb1 == T(0) && nb1 == T(0)) continue;
+    const long long st[3] = {L.SX, (long long)L.PZ, 1LL};
+    // forward recompute
+    const Strain<T> s = strain_at(P, U, V, W, o);
+    const T kk = K0[o], ww = W0[o];
+    const Nut<T> nu0 = nut_of(P, kk, ww, s.S2);
+    const T vel[3] = {T(0.5) * (U[o] + U[o + L.SX]), T(0.5) * (V[o] + V[o + L.PZ]), T(0.5) * (W[o] + W[o + 1])};
+    auto adv = [&](const T* q) {
+      const T cq = q[o];
+      T a = (nmax(vel[0], T(0)) * (cq - q[o - L.SX]) + nmin(vel[0], T(0)) * (q[o + L.SX] - cq)) * P.ih[0];
+      a += (nmax(vel[1], T(0)) * (cq - q[o - L.PZ]) + nmin(vel[1], T(0)) * (q[o + L.PZ] - cq)) * P.ih[1];
+      a += (nmax(vel[2], T(0)) * (cq - q[o - 1]) + nmin(vel[2], T(0)) * (q[o + 1] - cq)) * P.ih[2];
+      return a;
+    };
+    auto lap = [&](const T* q) {
+      const T cq = q[o];
+      return (q[o + L.SX] - T(2) * cq + q[o - L.SX]) * P.ih2[0] + (q[o + L.PZ] - T(2) * cq + q[o - L.PZ]) * P.ih2[1] +
+             (q[o + 1] - T(2) * cq + q[o - 1]) * P.ih2[2];
+    };
+    const T lapK = lap(K0), lapW = lap(W0);
+    const T knr = kk + P.dt * (-adv(K0) + T(2) * nu0.nut * s.S2 - T(kCmu) * kk * ww +
+                               (P.nu + T(kSigmaStar) * nu0.nut) * lapK);
+    const T wnr = ww + P.dt * (-adv(W0) + T(2 * kAlpha) * s.S2 - T(kBeta) * ww * ww + (P.nu + T(kSigma) * nu0.nut) * lapW);
+    const bool kfree = knr != knr || knr > P.k_min, wfree = wnr != wnr || wnr > P.w_min;
+    const T kn = kfree ? knr : P.k_min, wn = wfree ? wnr : P.w_min;
+    // the new eddy viscosity
+    const Nut<T> nu1 = nut_of(P, kn, wn, s.S2);
+    T s2b = nb1 * nu1.dS2;
+    const T bk = kfree ? kb1 + nb1 * nu1.dk : T(0);
+    const T bw = wfree ? wb1 + nb1 * nu1.dw : T(0);
+    // through the explicit update
+    const T nutb = bk * P.dt * (T(2) * s.S2 + T(kSigmaStar) * lapK) + bw * P.dt * T(kSigma) * lapW;
+    s2b += bk * P.dt * T(2) * nu0.nut + bw * P.dt * T(2 * kAlpha);
+    T kkb = bk * (T(1) - P.dt * T(kCmu) * ww) + nutb * nu0.dk;
+    T wwb = -bk * P.dt * T(kCmu) * kk + bw * (T(1) - P.dt * T(2 * kBeta) * ww) + nutb * nu0.dw;
+    s2b += nutb * nu0.dS2;
+    T velb[3] = {T(0), T(0), T(0)};
+    // advection and Laplacian of q with weight cw = (adjoint) dt and diffusivity dq
+    auto stencil_adj = [&](const T* q, T* QB, T cw, T dq, T& centre) {
+      if (cw == T(0)) return;
+      const T cq = q[o];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T up = nmax(vel[a], T(0)), dn = nmin(vel[a], T(0));
+        centre += cw * (-(up - dn) * P.ih[a] - T(2) * dq * P.ih2[a]);
+        add_to(QB + o - st[a], cw * (up * P.ih[a] + dq * P.ih2[a]));
+        add_to(QB + o + st[a], cw * (-dn * P.ih[a] + dq * P.ih2[a]));
+        const T slope = vel[a] > T(0) ? cq - q[o - st[a]] : (vel[a] < T(0) ? q[o + st[a]] - cq : T(0));
+        velb[a] -= cw * slope * P.ih[a];
+      }
+    };
+    stencil_adj(K0, KB0, bk * P.dt, P.nu + T(kSigmaStar) * nu0.nut, kkb);
+    stencil_adj(W0, WB0, bw * P.dt, P.nu + T(kSigma) * nu0.nut, wwb);
+    add_to(KB0 + o, kkb);
+    add_to(WB0 + o, wwb);
+    // cell-centre velocities back to their faces, then |S|^2
+    add_to(GU + o, T(0.5) * velb[0]);
+    add_to(GU + o + L.SX, T(0.5) * velb[0]);
+    add_to(GV + o, T(0.5) * velb[1]);
+    add_to(GV + o + L.PZ, T(0.5) * velb[1]);
+    add_to(GW + o, T(0.5) * velb[2]);
+    add_to(GW + o + 1, T(0.5) * velb[2]);
+    strain_adj(P, s, s2b, GU, GV, GW, o);
+  }
+}
+
+// Reverse of store_cell for a cell field: each face-adjacent ghost's
+// adjoint goes to its cell, except across an inlet side when the ghost held
+// the inlet constant (use_inlet); ghosts cleared.
+template <class T>
+__global__ __launch_bounds__(256) void k_cell_fold(Params<T> P, T* __restrict__ q, int use_inlet) {
+  const Layout& L = P.L;
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(c % L.nz);
+    const long long rr = c / L.nz;
+    const int j = (int)(rr % L.ny);
+    const int i = (int)(rr / L.ny);
+    const int idx[3] = {i, j, k}, nn[3] = {L.nx, L.ny, L.nz};
+    const long long st[3] = {L.SX, (long long)L.PZ, 1LL};
+    const long long o = L.at(i, j, k);
+    T acc = q[o];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int hi = 0; hi < 2; ++hi) {
+        if (idx[a] != (hi ? nn[a] - 1 : 0)) continue;
+        const long long gpos = o + (hi ? st[a] : -st[a]);
+        if (!(use_inlet && P.bc[2 * a + hi] == INLET)) acc += q[gpos];
+        q[gpos] = T(0);
+      }
+    }
+    q[o] = acc;
+  }
+}
+
+// Adjoint of the eddy viscosity the diffusion read: face f of component C
+// uses nu + (nu_t[c - e_C] + nu_t[c]) / 2 times dt lap(q)_f, so each cell
+// gathers half of dt lap(q)_f a_f from the two faces beside it along each
+// axis; a ghost cell copies its interior neighbour, so a boundary cell also
+// takes the half that went to its ghost.  Writes nb at interior cells.
+template <int C, class T>
+__device__ __forceinline__ T nut_face_term(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ a,
+                                           int i, int j, int k) {
+  const T ab = adj_in<C>(P, a, i, j, k);
+  if (ab == T(0)) return T(0);
+  const Layout& L = P.L;
+  const long long o = L.at(i, j, k);
+  const T qc = q[o];
+  const T lp = (q[o + L.SX] - T(2) * qc + q[o - L.SX]) * P.ih2[0] +
+               (q[o + L.PZ] - T(2) * qc + q[o - L.PZ]) * P.ih2[1] + (q[o + 1] - T(2) * qc + q[o - 1]) * P.ih2[2];
+  return T(0.5) * P.dt * lp * ab;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_diffuse_nut_adj(Params<T> P, const T* __restrict__ Q0,
+                                                         const T* __restrict__ Q1, const T* __restrict__ Q2,
+                                                         const T* __restrict__ A0, const T* __restrict__ A1,
+                                                         const T* __restrict__ A2, T* __restrict__ NB) {
+  const Layout& L = P.L;
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(c % L.nz);
+    const long long rr = c / L.nz;
+    const int j = (int)(rr % L.ny);
+    const int i = (int)(rr / L.ny);
+    T s = T(0);
+    {
+      const T lo = nut_face_term<0>(P, Q0, A0, i, j, k), hi = nut_face_term<0>(P, Q0, A0, i + 1, j, k);
+      s += lo + hi + (i == 0 ? lo : T(0)) + (i == L.nx - 1 ? hi : T(0));
+    }
+    {
+      const T lo = nut_face_term<1>(P, Q1, A1, i, j, k), hi = nut_face_term<1>(P, Q1, A1, i, j + 1, k);
+      s += lo + hi + (j == 0 ? lo : T(0)) + (j == L.ny - 1 ? hi : T(0));
+    }
+    {
+      const T lo = nut_face_term<2>(P, Q2, A2, i, j, k), hi = nut_face_term<2>(P, Q2, A2, i, j, k + 1);
+      s += lo + hi + (k == 0 ? lo : T(0)) + (k == L.nz - 1 ? hi : T(0));
+    }
+    NB[L.at(i, j, k)] = s;
+  }
+}
+
 // ---------------------------------------------------------- objective seed
 // Derivative of a region objective with respect to the faces of the state:
 // each face is half of the cell-centre velocity of its two cells, so
@@ -618,6 +876,31 @@ void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, co
                      (const T*)Q[2], boxes_dev, coef_dev, nreg, kind, (const T*)ut, (T*)out);
 }
 
+static inline int cell_blocks(const Layout& L) {
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  return (int)std::min<long long>((n + 255) / 256, 8192);
+}
+
+template <class T>
+void launch_turb_adj(Grid& g, const Params<T>& P, void* const Unew[3], const void* K0, const void* W0,
+                     const void* KB1, const void* WB1, const void* NB1, void* KB0, void* WB0, void* const G[3]) {
+  hipLaunchKernelGGL(k_turb_adj<T>, dim3(cell_blocks(P.L)), dim3(256), 0, g.stream, P, (const T*)Unew[0],
+                     (const T*)Unew[1], (const T*)Unew[2], (const T*)K0, (const T*)W0, (const T*)KB1, (const T*)WB1,
+                     (const T*)NB1, (T*)KB0, (T*)WB0, (T*)G[0], (T*)G[1], (T*)G[2]);
+}
+
+template <class T>
+void launch_cell_fold(Grid& g, const Params<T>& P, void* q, int use_inlet) {
+  hipLaunchKernelGGL(k_cell_fold<T>, dim3(cell_blocks(P.L)), dim3(256), 0, g.stream, P, (T*)q, use_inlet);
+}
+
+template <class T>
+void launch_diffuse_nut_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Aout[3], void* NB) {
+  hipLaunchKernelGGL(k_diffuse_nut_adj<T>, dim3(cell_blocks(P.L)), dim3(256), 0, g.stream, P, (const T*)Qin[0],
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)Aout[0], (const T*)Aout[1], (const T*)Aout[2],
+                     (T*)NB);
+}
+
 #define UF_INST(T)                                                                                             \
   template void launch_advect_adj<T>(Grid&, const Params<T>&, void* const[3], void* const[3], void* const[3],  \
                                      void* const[3], void* const[3]);                                           \
@@ -627,7 +910,11 @@ void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, co
   template void launch_fold<T>(Grid&, const Params<T>&, void* const[3]);                                        \
   template void launch_drag_coef_adj<T>(Grid&, const Params<T>&, const void*, double*);                        \
   template void launch_objective_seed<T>(Grid&, const Params<T>&, const int*, const double*, int, int,         \
-                                         const void*, void*);
+                                         const void*, void*);                                                   \
+  template void launch_turb_adj<T>(Grid&, const Params<T>&, void* const[3], const void*, const void*,         \
+                                   const void*, const void*, const void*, void*, void*, void* const[3]);        \
+  template void launch_cell_fold<T>(Grid&, const Params<T>&, void*, int);                                      \
+  template void launch_diffuse_nut_adj<T>(Grid&, const Params<T>&, void* const[3], void* const[3], void*);
 UF_INST(float)
 UF_INST(double)
 #undef UF_INST

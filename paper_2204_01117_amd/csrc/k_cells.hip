@@ -2,14 +2,12 @@
 // the projection), the porosity -> drag-coefficient map (Sec. 3 drag law),
 // boundary refresh of cell fields and packing between the padded storage
 // and the compact layouts of the C ABI.
+#include "turb_model.h"
 #include "uf_internal.h"
 
 namespace uf {
 
 constexpr int kCellBlock = 256;
-
-// Table 1 of the paper.
-constexpr double kCmu = 0.09, kAlpha = 0.52, kBeta = 0.0708, kSigma = 0.5, kSigmaStar = 0.6;
 
 __host__ __device__ inline int cell_gx(const Layout& L) { return (L.ny * L.nz + kCellBlock - 1) / kCellBlock; }
 

@@ -213,6 +213,9 @@ void free_grid(Grid* g) {
     for (auto& q : set) f(q);
   for (auto& set : g->AV)
     for (auto& q : set) f(q);
+  for (auto& set : g->AU)
+    for (auto& q : set) f(q);
+  for (auto& q : g->AT) f(q);
   f(g->Cbar);
   f(g->XA);
   f(g->inflow0);
@@ -469,6 +472,10 @@ void adjoint_alloc(Grid& g) {
       q = dalloc(bytes);
       UF_HIP_CHECK(hipMemsetAsync(q, 0, bytes, g.stream));
     }
+  for (auto& set : g.AU)
+    for (auto& q : set) q = dalloc(bytes);
+  for (auto& q : g.AT) q = dalloc(bytes);
+  UF_HIP_CHECK(hipMemsetAsync(g.AT[9], 0, bytes, g.stream));   // recompute pressure: zero start and ghosts
   g.Cbar = dalloc(bytes);
   g.XA = dalloc(bytes);
   UF_HIP_CHECK(hipMemsetAsync(g.XA, 0, bytes, g.stream));   // zero start and zero ghosts
@@ -477,21 +484,35 @@ void adjoint_alloc(Grid& g) {
   UF_HIP_CHECK(hipMemsetAsync(g.inflow0, 0, tab, g.stream));
 }
 
-// The adjoint solve runs in the pressure array with its own warm start:
-// swap it in for the scope and back out on every path.
-struct AdjointPressure {
+// The adjoint solve and the recompute's forward solve run in the pressure
+// array, each with its own warm start: swap one in for the scope and back
+// out on every path.
+struct PressureSwap {
   Grid& g;
+  void*& other;
+  int& other_iters;
   int saved_iters;
-  explicit AdjointPressure(Grid& g_) : g(g_), saved_iters(g_.last_iters) {
-    std::swap(g.X, g.XA);
-    g.last_iters = g.adj_last_iters;
+  PressureSwap(Grid& g_, void*& x, int& iters) : g(g_), other(x), other_iters(iters), saved_iters(g_.last_iters) {
+    std::swap(g.X, other);
+    g.last_iters = other_iters;
   }
-  ~AdjointPressure() {
-    g.adj_last_iters = g.last_iters;
+  ~PressureSwap() {
+    other_iters = g.last_iters;
     g.last_iters = saved_iters;
-    std::swap(g.X, g.XA);
+    std::swap(g.X, other);
   }
 };
+
+// The eddy viscosity the recomputed diffusion reads (the state's own).
+struct NutSwap {
+  Grid& g;
+  void*& other;
+  NutSwap(Grid& g_, void*& n) : g(g_), other(n) { std::swap(g.NUT, other); }
+  ~NutSwap() { std::swap(g.NUT, other); }
+};
+
+// k-omega fields of the reverse step (indices into Grid::AT)
+enum { AT_K = 0, AT_W, AT_NUT, AT_KB1, AT_WB1, AT_NB1, AT_KB0, AT_WB0, AT_NB0, AT_XF };
 
 template <class T>
 SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* adj_next, void* const* adj_out,
@@ -501,25 +522,59 @@ SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* a
   Params<T> P0 = P;   // homogeneous boundary values: fixed faces and inlet ghosts are zero
   P0.inflow = (const T*)g.inflow0;
   const int st = g.cfg.stages;
+  const bool turb = g.cfg.turb_model == UF_TURB_KOMEGA && (st & UF_STAGE_TURB);
   const size_t bytes = g.nelem * g.esize;
   auto zero = [&](void* const set[3]) {
     for (int c = 0; c < 3; ++c) UF_HIP_CHECK(hipMemsetAsync(set[c], 0, bytes, g.stream));
   };
-  // forward recompute, as in step_begin
+  // forward recompute, as in step_begin / step_end
   for (int c = 0; c < 3; ++c) {
     launch_pack<T>(g, P, state[c], g.AS[0][c], c, 1);
     launch_face_bc<T>(g, P, g.AS[0][c], c);
+  }
+  if (turb) {
+    launch_pack<T>(g, P, state[3], g.AT[AT_K], UF_K, 1);
+    launch_cell_bc<T>(g, P, g.AT[AT_K], 1, g.k_in);
+    launch_pack<T>(g, P, state[4], g.AT[AT_W], UF_OMEGA, 1);
+    launch_cell_bc<T>(g, P, g.AT[AT_W], 1, g.w_in);
+    launch_pack<T>(g, P, state[5], g.AT[AT_NUT], UF_NUT, 1);
+    launch_cell_bc<T>(g, P, g.AT[AT_NUT], 0, 0.0);
   }
   void* const* x = g.AS[0];
   if (st & UF_STAGE_ADVECT) {
     launch_advect<T>(g, P, g.AS[0], g.AS[1], g.AS[2]);
     x = g.AS[2];
   }
+  void* const* diff_in = x;
   if (st & UF_STAGE_DIFFUSE) {
-    launch_diffuse<T>(g, P, x, g.AS[3]);
+    if (turb) {
+      NutSwap ns(g, g.AT[AT_NUT]);
+      launch_diffuse<T>(g, P, x, g.AS[3]);
+    } else {
+      launch_diffuse<T>(g, P, x, g.AS[3]);
+    }
     x = g.AS[3];
   }
   void* const* drag_in = x;
+  void* const* unew = x;
+  SolveResult fres;
+  if (turb) {   // the turbulence reverse linearises at u^{n+1}
+    if (st & UF_STAGE_DRAG) {
+      launch_drag<T>(g, P, x, g.AU[0]);
+      x = g.AU[0];
+    }
+    if (st & UF_STAGE_PROJECT) {
+      // from zero, so that the recomputed u^{n+1} -- and every branch the
+      // turbulence reverse takes at it -- depends on this call's inputs only
+      UF_HIP_CHECK(hipMemsetAsync(g.AT[AT_XF], 0, bytes, g.stream));
+      g.fwd_last_iters = 0;
+      PressureSwap ps(g, g.AT[AT_XF], g.fwd_last_iters);
+      fres = solve_pressure<T>(g, P, x, nullptr);
+      launch_project<T>(g, P, x, g.AU[1]);
+      x = g.AU[1];
+    }
+    unew = x;
+  }
   check_launch();
   // reverse
   void* const* A0 = g.AA[0];
@@ -529,10 +584,23 @@ SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* a
   zero(A0);
   for (int c = 0; c < 3; ++c) launch_pack<T>(g, P, adj_next[c], A0[c], c, 1);
   launch_fold<T>(g, P, A0);   // no ghosts yet: clears the fixed faces
+  if (turb) {
+    const int fields[3] = {UF_K, UF_OMEGA, UF_NUT};
+    for (int q = 0; q < 3; ++q) {
+      UF_HIP_CHECK(hipMemsetAsync(g.AT[AT_KB1 + q], 0, bytes, g.stream));
+      launch_pack<T>(g, P, adj_next[3 + q], g.AT[AT_KB1 + q], fields[q], 1);
+    }
+    for (int q = AT_KB0; q <= AT_NB0; ++q) UF_HIP_CHECK(hipMemsetAsync(g.AT[q], 0, bytes, g.stream));
+    launch_turb_adj<T>(g, P, unew, g.AT[AT_K], g.AT[AT_W], g.AT[AT_KB1], g.AT[AT_WB1], g.AT[AT_NB1],
+                       g.AT[AT_KB0], g.AT[AT_WB0], A0);
+    launch_cell_fold<T>(g, P, g.AT[AT_KB0], 1);
+    launch_cell_fold<T>(g, P, g.AT[AT_WB0], 1);
+    launch_fold<T>(g, P, A0);   // ghosts of u^{n+1} that the turbulence update read
+  }
   void* const* a = A0;
   SolveResult res;
   if (st & UF_STAGE_PROJECT) {
-    AdjointPressure swap(g);
+    PressureSwap ps(g, g.XA, g.adj_last_iters);
     res = solve_pressure<T>(g, P0, a, nullptr);
     launch_project<T>(g, P0, a, A1);
     a = A1;
@@ -548,7 +616,13 @@ SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* a
   }
   if (st & UF_STAGE_DIFFUSE) {
     void* const* d = other(a);
-    launch_diffuse_adj<T>(g, P, a, d);
+    if (turb) {
+      launch_diffuse_nut_adj<T>(g, P, diff_in, a, g.AT[AT_NB0]);
+      NutSwap ns(g, g.AT[AT_NUT]);   // the eddy viscosity of step n, not the grid's current one
+      launch_diffuse_adj<T>(g, P, a, d);
+    } else {
+      launch_diffuse_adj<T>(g, P, a, d);
+    }
     launch_fold<T>(g, P, d);
     a = d;
   }
@@ -561,7 +635,14 @@ SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* a
     a = A2;
   }
   for (int c = 0; c < 3; ++c) launch_pack<T>(g, P, a[c], adj_out[c], c, 0);
+  if (turb) {
+    launch_pack<T>(g, P, g.AT[AT_KB0], adj_out[3], UF_K, 0);
+    launch_pack<T>(g, P, g.AT[AT_WB0], adj_out[4], UF_OMEGA, 0);
+    launch_pack<T>(g, P, g.AT[AT_NB0], adj_out[5], UF_NUT, 0);
+  }
   check_launch();
+  res.noconv |= fres.noconv;
+  res.nonfinite |= fres.nonfinite;
   return res;
 }
 
@@ -1122,11 +1203,9 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
                           void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
   if (!g || !state_n_dev || !adj_np1_dev || !adj_n_dev) return fail(UF_EINVAL, "NULL argument");
-  for (int c = 0; c < 3; ++c)
+  const int nf = (g->cfg.turb_model == UF_TURB_KOMEGA && (g->cfg.stages & UF_STAGE_TURB)) ? 6 : 3;
+  for (int c = 0; c < nf; ++c)
     if (!state_n_dev[c] || !adj_np1_dev[c] || !adj_n_dev[c]) return fail(UF_EINVAL, "NULL field pointer");
-  if (g->cfg.turb_model == UF_TURB_KOMEGA && (g->cfg.stages & UF_STAGE_TURB))
-    return fail(UF_ENOTIMPL, "the adjoint of the k-omega model is not implemented: run it with the "
-                             "turbulence stage off (eddy viscosity held fixed)");
   UF_GUARD_BEGIN
   SolveResult r;
   if (g->esize == 4)

@@ -86,6 +86,10 @@ struct Grid {
   void* AS[4][3] = {};          // recomputed forward: state n, predictor, advected, diffused
   void* AA[3][3] = {};          // adjoint work sets
   void* AV[3][3] = {};          // per-face velocity-vector adjoints (zero outside the face thread range)
+  void* AT[10] = {};            // k-omega reverse: k, omega, nu_t of step n; their adjoints at n+1 and
+                                // at n; the pressure of the forward recompute
+  int fwd_last_iters = 0;
+  void* AU[2][3] = {};          // recomputed u* and u^{n+1}
   void* Cbar = nullptr;         // drag-coefficient adjoint (padded cells)
   void* XA = nullptr;           // adjoint pressure, the warm start of the next adjoint solve
   void* inflow0 = nullptr;      // zero inflow table (homogeneous boundary values)
@@ -162,6 +166,9 @@ template <class T> void launch_drag_adj(Grid& g, const Params<T>& P, void* const
 template <class T> void launch_fold(Grid& g, const Params<T>& P, void* const A[3]);
 template <class T> void launch_drag_coef_adj(Grid& g, const Params<T>& P, const void* Cbar, double* phibar);
 template <class T> void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, const double* coef_dev, int nreg, int kind, const void* ut, void* out);
+template <class T> void launch_turb_adj(Grid& g, const Params<T>& P, void* const Unew[3], const void* K0, const void* W0, const void* KB1, const void* WB1, const void* NB1, void* KB0, void* WB0, void* const G[3]);
+template <class T> void launch_cell_fold(Grid& g, const Params<T>& P, void* q, int use_inlet);
+template <class T> void launch_diffuse_nut_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Aout[3], void* NB);
 template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_iteration_update(Grid& g, const Params<T>& P, int t, const void* Dnew);

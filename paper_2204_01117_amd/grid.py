@@ -141,19 +141,27 @@ class Grid:
         del keep, ut
         return out
 
+    def adjoint_fields(self):
+        """Fields of the state the reverse step takes: (u, v, w), plus (k,
+        omega, nut) when the k-omega update runs in the step."""
+        turb = int(self.cfg["turb_model"]) == 1 and int(self.cfg["stages"]) & 16
+        return ("u", "v", "w", "k", "omega", "nut") if turb else ("u", "v", "w")
+
     def adjoint_step(self, state, adj, phibar=None):
-        """Reverse of one step (uf_adjoint_step): ``state`` is the (u, v, w)
-        the step started from, ``adj`` the derivative of the objective with
-        respect to the step's result (u, v, w); returns the derivative with
-        respect to ``state`` and adds the porosity derivative of this step
-        into ``phibar`` (float64 [nx, ny, nz]) when given."""
-        names = ("u", "v", "w")
+        """Reverse of one step (uf_adjoint_step): ``state`` holds the fields
+        of ``adjoint_fields()`` the step started from, ``adj`` the
+        derivative of the objective with respect to the same fields after
+        the step; returns the derivative with respect to ``state`` and adds
+        the porosity derivative of this step into ``phibar`` (float64
+        [nx, ny, nz]) when given."""
+        names = self.adjoint_fields()
+        assert len(state) == len(names) and len(adj) == len(names)
         st = [self._dev(a, self.extent(f)) for a, f in zip(state, names)]
         ad = [self._dev(a, self.extent(f)) for a, f in zip(adj, names)]
         out = [self.torch.empty(self.extent(f), dtype=self.dtype, device=self.device) for f in names]
         if phibar is not None:
             assert phibar.dtype == self.torch.float64 and tuple(phibar.shape) == self.n and phibar.is_contiguous()
-        ptrs = lambda ts: (c_void_p * 3)(*[t.data_ptr() for t in ts])
+        ptrs = lambda ts: (c_void_p * len(ts))(*[t.data_ptr() for t in ts])
         own = self.tstream != self.torch.cuda.current_stream(self.device)
         if own:
             self.torch.cuda.current_stream(self.device).synchronize()

@@ -90,8 +90,8 @@ class AdjointObjective:
     last segment; the reverse pass recomputes each earlier segment from its
     checkpoint (the forward is deterministic, so the recomputed states are
     the same bits) and runs the reverse steps over it, accumulating dJ/dphi.
-    The grid must run without the turbulence stage (the eddy viscosity held
-    fixed), the case the adjoint covers.
+    With the k-omega update in the step the reverse also carries k, omega
+    and nu_t.
     """
 
     def __init__(self, grid, design, regions, u_target=0.55, nsteps=1, initial_state=None, checkpoint=20,
@@ -113,7 +113,7 @@ class AdjointObjective:
         return g.objective(self.regions, self.u_target, grad=grad)
 
     def _snapshot(self):
-        return {f: self.grid.get_field(f) for f in ("u", "v", "w", "p")}
+        return {f: self.grid.get_field(f) for f in ("u", "v", "w", "p", "k", "omega", "nut")}
 
     def __call__(self, theta):
         return self.value_and_grad(theta)[0]
@@ -124,15 +124,17 @@ class AdjointObjective:
         theta = np.asarray(theta, dtype=np.float64)
         g.set_state(self.initial)
         g.set_porosity(self.design.porosity(theta))
+        fields = g.adjoint_fields()
         last = ((N - 1) // K) * K if N else 0
         ckpt, tail = {}, []
         for s in range(N):
             if s >= last:
-                tail.append([g.get_field(f) for f in ("u", "v", "w")])
+                tail.append([g.get_field(f) for f in fields])
             elif s % K == 0:
                 ckpt[s] = self._snapshot()
             g.step(1, stats=False)
         J, lam = self._objective(grad=True)
+        lam = tuple(lam) + tuple(torch.zeros_like(g.get_field(f)) for f in fields[3:])
         phibar = torch.zeros(g.n, dtype=torch.float64, device=g.device)
         for st in reversed(tail):
             lam = g.adjoint_step(st, lam, phibar)
@@ -140,7 +142,7 @@ class AdjointObjective:
             g.set_state(ckpt[s0])
             states = []
             for _ in range(s0, min(s0 + K, N)):
-                states.append([g.get_field(f) for f in ("u", "v", "w")])
+                states.append([g.get_field(f) for f in fields])
                 g.step(1, stats=False)
             for st in reversed(states):
                 lam = g.adjoint_step(st, lam, phibar)

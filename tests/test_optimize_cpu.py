@@ -70,6 +70,9 @@ class _ToyGrid:
     def get_field(self, name):
         return self.f[name].clone()
 
+    def adjoint_fields(self):
+        return ("u", "v", "w")
+
     def step(self, n=1, stats=False):
         for _ in range(n):
             u = self.f["u"]
