@@ -321,37 +321,43 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
 
 /* One reverse step of the discrete adjoint (gradients of a Sec. 4 design
  * objective, an extension: the paper itself differences the simulator).
- * Given the state u^n = (u, v, w) a step started from and a = dJ/du^{n+1}
- * for its result, writes dJ/du^n = (du^{n+1}/du^n)^T a and adds
- * (du^{n+1}/dphi)^T a into the porosity gradient.  The Jacobian is the
- * exact derivative of the discrete step the library runs (its enabled
- * stages), taken at the branch the forward took at every max, min and
- * clamp (a MacCormack value clamped to its sample range follows that
- * sample; a face stopped by the drag passes nothing); the pressure solve is
- * treated as exact, its adjoint being the same projection applied to a
- * (the step's projection is symmetric), solved to cg_tol with its own warm
- * start kept in the grid between calls.
- *   state_n_dev[3]: device, compact (u, v, w) of u^n in the grid's dtype
- *                   (extents as uf_field_extent); fixed boundary faces are
- *                   taken from the boundary conditions, as uf_set_field does.
- *   adj_np1_dev[3]: device, compact dJ/du^{n+1}; values on fixed faces are
+ * The state the reverse carries is (u, v, w) -- plus (k, omega, nu_t) when
+ * the k-omega model runs in the step (turb_model UF_TURB_KOMEGA with
+ * UF_STAGE_TURB); call its field count F (3 or 6).  Given the state x^n a
+ * step started from and a = dJ/dx^{n+1} for its result, writes
+ * dJ/dx^n = (dx^{n+1}/dx^n)^T a and adds (dx^{n+1}/dphi)^T a into the
+ * porosity gradient.  The Jacobian is the exact derivative of the discrete
+ * step the library runs (its enabled stages), taken at the branch the
+ * forward took at every max, min and clamp (a MacCormack value clamped to
+ * its sample range follows that sample; a face stopped by the drag passes
+ * nothing; a floored k or omega and a clipped nu_t pass nothing through the
+ * clipped argument); the pressure solve is treated as exact, its adjoint
+ * being the same projection applied to a (the step's projection is
+ * symmetric), solved to cg_tol with its own warm start kept in the grid
+ * between calls.  nu_t is a state field of its own: the step's diffusion
+ * reads the nu_t given, and the new nu_t is the k-omega update's output.
+ *   state_n_dev[F]: device, compact fields of x^n in the grid's dtype, in
+ *                   the order u, v, w, k, omega, nu_t (extents as
+ *                   uf_field_extent); fixed boundary faces and the inlet
+ *                   ghosts of k and omega follow the boundary conditions, as
+ *                   uf_set_field does.
+ *   adj_np1_dev[F]: device, compact dJ/dx^{n+1}; values on fixed faces are
  *                   ignored (those faces are constants).
- *   adj_n_dev[3]:   device, compact output dJ/du^n (zero on fixed faces);
+ *   adj_n_dev[F]:   device, compact output dJ/dx^n (zero on fixed faces);
  *                   may alias adj_np1_dev.
  *   dJ_dphi_accum_dev: NULL, or device float64 [nx*ny*nz] (z fastest) to
  *                   which the porosity derivative is added (chain through
  *                   the drag coefficient of the porosity map).
  * The grid's state, pressure and statistics are left as they were; the
- * porosity and eddy viscosity the step uses are the grid's current ones.
- * Adds are atomic where the forward gathers, so FP32 results can differ in
- * the last bits between runs.  First call allocates a workspace of 32
- * padded fields.  Work is enqueued on the grid's stream; the call waits
- * only for the adjoint pressure solve's status, so the kernels after it
- * may still run when it returns (stream order).  UF_EINVAL for a NULL
- * argument; UF_ENOTIMPL with the k-omega model and the turbulence stage
- * enabled (the model's reverse is not implemented: hold the eddy viscosity
- * fixed by disabling UF_STAGE_TURB); UF_ENOCONV / UF_ENONFINITE from the
- * adjoint pressure solve. */
+ * porosity is the grid's current one, and without the k-omega update so is
+ * the (then fixed) eddy viscosity.  With the model the step is recomputed
+ * up to x^{n+1}, including a forward pressure solve from zero.  Adds are
+ * atomic where the forward gathers, so FP32 results can differ in the last
+ * bits between runs.  The first call allocates a workspace of 48 padded
+ * fields.  Work is enqueued on the grid's stream; the call waits only for
+ * the pressure solves' status, so the kernels after them may still run
+ * when it returns (stream order).  UF_EINVAL for a NULL argument or field
+ * pointer; UF_ENOCONV / UF_ENONFINITE from a pressure solve. */
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
                           void* const* adj_n_dev, void* dJ_dphi_accum_dev);
 
