@@ -17,12 +17,13 @@ from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_fiel
 from .grid import Grid, step_batch
 from .voxelize import voxelize, smooth_porosity, smooth_porosity_grad
 from .design import BoxDesign
-from .optimize import SimulationObjective, AdjointObjective, forward_difference_gradient, gradient_descent
+from .optimize import (SimulationObjective, AdjointObjective, design_objective, forward_difference_gradient,
+                       gradient_descent)
 
 __all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_config",
            "uf_objective_spec", "make_objective_spec", "uf_mesh_set", "uf_voxelize", "voxelize", "uf_step_batch",
            "step_batch", "uf_smooth_porosity", "uf_smooth_porosity_grad", "uf_smooth_objects", "smooth_porosity",
-           "smooth_porosity_grad", "BoxDesign", "SimulationObjective", "AdjointObjective",
+           "smooth_porosity_grad", "BoxDesign", "SimulationObjective", "AdjointObjective", "design_objective",
            "forward_difference_gradient", "gradient_descent",
            "STATUS", "FIELDS", "FIELD_IDS", "Grid",
            "uf_create_grid", "uf_destroy_grid", "uf_set_porosity", "uf_set_field",

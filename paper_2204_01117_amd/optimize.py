@@ -151,6 +151,28 @@ class AdjointObjective:
         return J, self.design.gradient(theta, phibar)
 
 
+def design_objective(theta, objective):
+    """J(theta) as a differentiable torch scalar: the value and the adjoint
+    gradient come from ``objective.value_and_grad`` (an AdjointObjective) in
+    one call when the value is taken; backward multiplies the stored
+    gradient by the incoming one.  ``theta``: a 1-D float64 tensor."""
+    import torch
+
+    class _Design(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, t):
+            value, grad = objective.value_and_grad(t.detach().cpu().numpy())
+            ctx.save_for_backward(torch.as_tensor(grad, dtype=t.dtype, device=t.device))
+            return t.new_tensor(value)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout * grad
+
+    return _Design.apply(theta)
+
+
 def forward_difference_gradient(J, theta, eps=0.1):
     """(J(theta), dJ/dtheta) by forward differences: N + 1 evaluations, all
     at once when J has a ``many`` method (the simulations are independent)."""

@@ -172,14 +172,17 @@ def test_objective_seed_matches_differences(kind, seed):
     g.close()
 
 
-def test_adjoint_fp32_follows_fp64():
+@pytest.mark.parametrize("turb", [False, True])
+def test_adjoint_fp32_follows_fp64(turb):
     cfg, n, phi = small_case(7)
+    if turb:
+        cfg.update(turb_model=TURB_KOMEGA, stages=STAGE_ALL)
     g64, st = spun_up(cfg, phi)
     g32 = U.Grid(dict(cfg, dtype="f32", cg_tol=1e-7))
     g32.set_porosity(torch.as_tensor(phi))
     g32.set_state(st)
     gen = torch.Generator(device="cpu").manual_seed(7)
-    u0 = [st[f].double() for f in FACES]
+    u0 = [st[f].double() for f in g64.adjoint_fields()]
     lam = [torch.randn(x.shape, generator=gen, dtype=torch.float64).cuda() for x in u0]
     p64 = torch.zeros(n, dtype=torch.float64, device="cuda")
     p32 = torch.zeros(n, dtype=torch.float64, device="cuda")

@@ -128,3 +128,19 @@ def test_adjoint_objective_checkpoint_schedule():
         assert g.reverse_inputs == order            # each reverse step saw its own state
         last = ((nsteps - 1) // K) * K if nsteps else 0
         assert g.steps == nsteps + last            # only the segments before the last are recomputed
+
+
+def test_design_objective_is_a_torch_function():
+    """design_objective wraps AdjointObjective for torch.autograd: the value
+    and the gradient equal value_and_grad's."""
+    import torch
+    m, dt = 4, 0.1
+    theta = torch.linspace(0.3, 1.1, m, dtype=torch.float64, requires_grad=True)
+    g = _ToyGrid(m, dt)
+    g.f["u"] = torch.linspace(-0.2, 0.5, m, dtype=torch.float64)
+    A = O.AdjointObjective(g, _ToyDesign(), [], 0.0, nsteps=5, checkpoint=2)
+    J = O.design_objective(theta, A)
+    (gt,) = torch.autograd.grad(3.0 * J, theta)
+    J0, g0, _ = _toy_reference(theta.detach().numpy(), np.linspace(-0.2, 0.5, m), dt, 5)
+    assert abs(float(J.detach()) - J0) <= 1e-14 * max(1.0, abs(J0))
+    assert np.allclose(gt.numpy(), 3.0 * g0, rtol=1e-13, atol=1e-15)
