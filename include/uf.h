@@ -361,6 +361,17 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
 uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
                           void* const* adj_n_dev, void* dJ_dphi_accum_dev);
 
+/* uf_adjoint_step with the state after the step given: state_np1_dev[3]
+ * (device, compact u, v, w of x^{n+1} -- the result of stepping x^n, as
+ * uf_get_field returns it; the caller running the reverse sweep holds it as
+ * the previous call's state_n_dev).  With the k-omega update in the step
+ * the turbulence reverse linearises at these fields instead of recomputing
+ * them (no forward pressure solve); without it they are not read.  Passing
+ * anything but the step's own result gives a wrong gradient.  Errors as
+ * uf_adjoint_step, and UF_EINVAL for a NULL state_np1_dev. */
+uf_status uf_adjoint_step_at(uf_grid g, const void* const* state_n_dev, const void* const* state_np1_dev,
+                             const void* const* adj_np1_dev, void* const* adj_n_dev, void* dJ_dphi_accum_dev);
+
 /* Kernel timer.  While enabled, every launch of the selected kernels carries
  * a pair of HIP events in its own dispatch (hipExtLaunchKernel start/stop
  * events: the kernel's begin and end, no separate marker packets), and the

@@ -110,6 +110,7 @@ _SIGS = {
     "uf_apply_operator": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "uf_objective": (c_int32, [c_void_p, c_void_p, POINTER(c_double), c_void_p]),
     "uf_adjoint_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "uf_adjoint_step_at": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
     "uf_step_batch": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p]),
     "uf_smooth_porosity": (c_int32, [POINTER(uf_smooth_objects), c_int32, c_void_p, c_void_p]),
@@ -135,6 +136,7 @@ uf_pressure_solve = lib.uf_pressure_solve
 uf_apply_operator = lib.uf_apply_operator
 uf_objective = lib.uf_objective
 uf_adjoint_step = lib.uf_adjoint_step
+uf_adjoint_step_at = lib.uf_adjoint_step_at
 uf_set_stream = lib.uf_set_stream
 uf_step_batch = lib.uf_step_batch
 uf_smooth_porosity = lib.uf_smooth_porosity

@@ -515,8 +515,8 @@ struct NutSwap {
 enum { AT_K = 0, AT_W, AT_NUT, AT_KB1, AT_WB1, AT_NB1, AT_KB0, AT_WB0, AT_NB0, AT_XF };
 
 template <class T>
-SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* adj_next, void* const* adj_out,
-                         double* phibar) {
+SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* state_next,
+                         const void* const* adj_next, void* const* adj_out, double* phibar) {
   adjoint_alloc(g);
   const Params<T> P = make_params<T>(g);
   Params<T> P0 = P;   // homogeneous boundary values: fixed faces and inlet ghosts are zero
@@ -558,7 +558,13 @@ SolveResult adjoint_step(Grid& g, const void* const* state, const void* const* a
   void* const* drag_in = x;
   void* const* unew = x;
   SolveResult fres;
-  if (turb) {   // the turbulence reverse linearises at u^{n+1}
+  if (turb && state_next) {   // u^{n+1} given: the turbulence reverse linearises there
+    for (int c = 0; c < 3; ++c) {
+      launch_pack<T>(g, P, state_next[c], g.AU[1][c], c, 1);
+      launch_face_bc<T>(g, P, g.AU[1][c], c);
+    }
+    unew = g.AU[1];
+  } else if (turb) {   // recompute u^{n+1}
     if (st & UF_STAGE_DRAG) {
       launch_drag<T>(g, P, x, g.AU[0]);
       x = g.AU[0];
@@ -1200,22 +1206,40 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
   UF_GUARD_END
 }
 
-uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
-                          void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
+namespace {
+uf_status adjoint_entry(uf_grid g, const void* const* state_n_dev, const void* const* state_np1_dev,
+                        const void* const* adj_np1_dev, void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
   if (!g || !state_n_dev || !adj_np1_dev || !adj_n_dev) return fail(UF_EINVAL, "NULL argument");
-  const int nf = (g->cfg.turb_model == UF_TURB_KOMEGA && (g->cfg.stages & UF_STAGE_TURB)) ? 6 : 3;
+  const bool turb = g->cfg.turb_model == UF_TURB_KOMEGA && (g->cfg.stages & UF_STAGE_TURB);
+  const int nf = turb ? 6 : 3;
   for (int c = 0; c < nf; ++c)
     if (!state_n_dev[c] || !adj_np1_dev[c] || !adj_n_dev[c]) return fail(UF_EINVAL, "NULL field pointer");
+  if (turb && state_np1_dev)
+    for (int c = 0; c < 3; ++c)
+      if (!state_np1_dev[c]) return fail(UF_EINVAL, "NULL field pointer");
+  if (!turb) state_np1_dev = nullptr;
   UF_GUARD_BEGIN
   SolveResult r;
   if (g->esize == 4)
-    r = adjoint_step<float>(*g, state_n_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
+    r = adjoint_step<float>(*g, state_n_dev, state_np1_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
   else
-    r = adjoint_step<double>(*g, state_n_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
-  if (r.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the adjoint pressure solve");
-  if (r.noconv) return fail(UF_ENOCONV, "adjoint pressure CG reached cg_maxit");
+    r = adjoint_step<double>(*g, state_n_dev, state_np1_dev, adj_np1_dev, adj_n_dev, (double*)dJ_dphi_accum_dev);
+  if (r.nonfinite) return fail(UF_ENONFINITE, "non-finite value in a pressure solve of the reverse step");
+  if (r.noconv) return fail(UF_ENOCONV, "a pressure CG of the reverse step reached cg_maxit");
   return UF_OK;
   UF_GUARD_END
+}
+}  // namespace
+
+uf_status uf_adjoint_step(uf_grid g, const void* const* state_n_dev, const void* const* adj_np1_dev,
+                          void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
+  return adjoint_entry(g, state_n_dev, nullptr, adj_np1_dev, adj_n_dev, dJ_dphi_accum_dev);
+}
+
+uf_status uf_adjoint_step_at(uf_grid g, const void* const* state_n_dev, const void* const* state_np1_dev,
+                             const void* const* adj_np1_dev, void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
+  if (!state_np1_dev) return fail(UF_EINVAL, "NULL argument");
+  return adjoint_entry(g, state_n_dev, state_np1_dev, adj_np1_dev, adj_n_dev, dJ_dphi_accum_dev);
 }
 
 }  // extern "C"

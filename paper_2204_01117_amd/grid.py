@@ -147,16 +147,19 @@ class Grid:
         turb = int(self.cfg["turb_model"]) == 1 and int(self.cfg["stages"]) & 16
         return ("u", "v", "w", "k", "omega", "nut") if turb else ("u", "v", "w")
 
-    def adjoint_step(self, state, adj, phibar=None):
+    def adjoint_step(self, state, adj, phibar=None, after=None):
         """Reverse of one step (uf_adjoint_step): ``state`` holds the fields
         of ``adjoint_fields()`` the step started from, ``adj`` the
         derivative of the objective with respect to the same fields after
         the step; returns the derivative with respect to ``state`` and adds
         the porosity derivative of this step into ``phibar`` (float64
-        [nx, ny, nz]) when given."""
+        [nx, ny, nz]) when given.  ``after``: the (u, v, w, ...) the step
+        produced, when the caller holds it (uf_adjoint_step_at: no
+        recompute of the projection for the k-omega reverse)."""
         names = self.adjoint_fields()
         assert len(state) == len(names) and len(adj) == len(names)
         st = [self._dev(a, self.extent(f)) for a, f in zip(state, names)]
+        nx = [self._dev(a, self.extent(f)) for a, f in zip(after[:3], names)] if after is not None else None
         ad = [self._dev(a, self.extent(f)) for a, f in zip(adj, names)]
         out = [self.torch.empty(self.extent(f), dtype=self.dtype, device=self.device) for f in names]
         if phibar is not None:
@@ -165,8 +168,11 @@ class Grid:
         own = self.tstream != self.torch.cuda.current_stream(self.device)
         if own:
             self.torch.cuda.current_stream(self.device).synchronize()
-        L.check(L.uf_adjoint_step(self.handle, ptrs(st), ptrs(ad), ptrs(out),
-                                  c_void_p(phibar.data_ptr()) if phibar is not None else None))
+        pb = c_void_p(phibar.data_ptr()) if phibar is not None else None
+        if nx is not None:
+            L.check(L.uf_adjoint_step_at(self.handle, ptrs(st), ptrs(nx), ptrs(ad), ptrs(out), pb))
+        else:
+            L.check(L.uf_adjoint_step(self.handle, ptrs(st), ptrs(ad), ptrs(out), pb))
         if own:
             self.tstream.synchronize()
         return tuple(out)

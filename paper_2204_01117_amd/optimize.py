@@ -136,8 +136,12 @@ class AdjointObjective:
         J, lam = self._objective(grad=True)
         lam = tuple(lam) + tuple(torch.zeros_like(g.get_field(f)) for f in fields[3:])
         phibar = torch.zeros(g.n, dtype=torch.float64, device=g.device)
+        # each reverse step also gets the state its step produced: the one
+        # the previous reverse step started from (the final state first)
+        after = [g.get_field(f) for f in ("u", "v", "w")]
         for st in reversed(tail):
-            lam = g.adjoint_step(st, lam, phibar)
+            lam = g.adjoint_step(st, lam, phibar, after=after)
+            after = st
         for s0 in sorted(ckpt, reverse=True):
             g.set_state(ckpt[s0])
             states = []
@@ -145,7 +149,8 @@ class AdjointObjective:
                 states.append([g.get_field(f) for f in fields])
                 g.step(1, stats=False)
             for st in reversed(states):
-                lam = g.adjoint_step(st, lam, phibar)
+                lam = g.adjoint_step(st, lam, phibar, after=after)
+                after = st
         self.calls += 1
         self.phibar = phibar
         return J, self.design.gradient(theta, phibar)

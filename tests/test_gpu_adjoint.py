@@ -200,6 +200,27 @@ def test_adjoint_fp32_follows_fp64(turb):
 TURB_FIELDS = ("u", "v", "w", "k", "omega", "nut")
 
 
+def test_adjoint_step_at_matches_the_recompute():
+    """uf_adjoint_step_at (the step's result given) equals uf_adjoint_step
+    (the result recomputed with a pressure solve) with the k-omega model."""
+    cfg, n, phi = small_case(5, stages=STAGE_ALL)
+    cfg["turb_model"] = TURB_KOMEGA
+    g, st = spun_up(cfg, phi)
+    x0 = [st[f].double() for f in TURB_FIELDS]
+    g.step(1)
+    x1 = [g.get_field(f).double() for f in ("u", "v", "w")]
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    lam = [torch.randn(x.shape, generator=gen, dtype=torch.float64).cuda() for x in x0]
+    p1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    p2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    a1 = g.adjoint_step(x0, lam, p1)
+    a2 = g.adjoint_step(x0, lam, p2, after=x1)
+    for f, x, y in zip(TURB_FIELDS, a1, a2):
+        assert float((x - y).norm()) <= 1e-11 * max(float(x.norm()), 1e-30), f
+    assert float((p1 - p2).norm()) <= 1e-11 * float(p1.norm())
+    g.close()
+
+
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("stages", [16, 31])
 def test_adjoint_dot_product_with_k_omega(seed, stages):
