@@ -260,6 +260,54 @@ def test_adjoint_dot_product_with_k_omega(seed, stages):
     g.close()
 
 
+@pytest.mark.parametrize("shape", [(2, 2, 1), (2, 5, 1), (7, 2, 3), (3, 3, 2), (1, 4, 3)])
+@pytest.mark.parametrize("turb", [False, True])
+def test_adjoint_dot_product_degenerate_grids(shape, turb):
+    """Single layers and two-cell axes: a face range of one makes a face both
+    the first and the last along an axis, so ghosts on both sides and at
+    edges and corners fold into it."""
+    from uf_layouts import default_config
+    from uf_layouts.configs import BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    kinds = [int(x) for x in rng.choice([BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP], size=6)]
+    kinds[1] = BC_OUTLET
+    cfg = default_config(nx, ny, nz, 2.0, dtype="f64", dt=0.08, u_ref=4.0, z_ref=3.0, bc=kinds,
+                         wind_dir_deg=float(rng.uniform(0, 360)), precond=PC_MG, cg_tol=1e-13, cg_maxit=5000,
+                         turb_model=TURB_KOMEGA if turb else TURB_OFF,
+                         stages=STAGE_ALL if turb else STAGE_ALL & ~STAGE_TURB)
+    phi = np.where(random_porosity(nx + ny + nz, shape) == 0.0, 0.02, random_porosity(nx + ny + nz, shape))
+    log("case", shape, turb, kinds)
+    g0 = U.Grid(dict(cfg, stages=STAGE_ALL))
+    g0.set_porosity(torch.as_tensor(phi))
+    g0.step(2)
+    st = g0.state()
+    g0.close()
+    g = U.Grid(cfg)
+    g.set_porosity(torch.as_tensor(phi))
+    fields = g.adjoint_fields()
+    gen = torch.Generator(device="cpu").manual_seed(nx + ny + nz)
+    x0 = [st[f].double() for f in fields]
+    d = [torch.randn(x.shape, generator=gen, dtype=torch.float64).cuda() * (x if f in ("k", "omega", "nut") else 1.0)
+         for f, x in zip(fields, x0)]
+    lam = [torch.randn(x.shape, generator=gen, dtype=torch.float64).cuda() for x in x0]
+
+    def run(xs):
+        g.set_state(dict(st, **dict(zip(fields, xs))))
+        g.step(1)
+        return [g.get_field(f).double() for f in fields]
+
+    h = 1e-6
+    fp = run([a + h * b for a, b in zip(x0, d)])
+    fm = run([a - h * b for a, b in zip(x0, d)])
+    lhs = dot(lam, [(p - m) / (2 * h) for p, m in zip(fp, fm)])
+    g.set_state(st)
+    rhs = dot(g.adjoint_step(x0, lam), d)
+    log("  <a, J d> = %.12e   <J^T a, d> = %.12e" % (lhs, rhs))
+    assert abs(lhs - rhs) <= 2e-6 * max(abs(lhs), 1e-3 * sum(float(x.abs().sum()) for x in lam))
+    g.close()
+
+
 def _oracle_J(cfg, phi, st, regions, nsteps):
     og = OracleGrid(dict(cfg), solver_tol=1e-13)
     og.set_porosity(phi)
