@@ -645,8 +645,9 @@ def adjoint_bench(steps, warmup, with_fd=True):
     adjoint: 21 buildings (height and x/y position each) and the trees'
     porosity, 64 parameters; target-region objective (six pedestrian-level
     regions, ideal speed 0.55 m/s) after `steps` steps of the full step
-    (k-omega included) from a state spun up for `warmup` steps; checkpoints
-    every 20 steps.  Beside it the same
+    (k-omega included) from a state spun up for `warmup` steps; every state
+    of the horizon kept in HBM when it fits (else checkpoints every 20
+    steps).  Beside it the same
     gradient by forward differences (eps 0.1, 65 simulations batched) and a
     plain forward run of the horizon."""
     import numpy as np
@@ -666,7 +667,7 @@ def adjoint_bench(steps, warmup, with_fd=True):
     g.set_porosity(design.porosity(theta))
     g.step(warmup, stats=False)
     init = g.state()
-    A = O.AdjointObjective(g, design, regions, 0.55, nsteps=steps, initial_state=init, checkpoint=20)
+    A = O.AdjointObjective(g, design, regions, 0.55, nsteps=steps, initial_state=init)
     A.value_and_grad(theta)                    # allocates the workspace
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -700,7 +701,8 @@ def adjoint_bench(steps, warmup, with_fd=True):
         "data": "synthetic seeded city, smoothed building indicators",
         "config": {"workload": "256x256x64 dx=2m, 21 parametrised buildings + 40 trees, 64 parameters, "
                                "six target regions, %d-step horizon, full step with k-omega" % steps,
-                   "method": "discrete adjoint, checkpoints every 20 steps"},
+                   "method": "discrete adjoint, %s" % ("every state kept in HBM" if A.segment >= steps else
+                                                        "checkpoints every %d steps" % A.segment)},
         "forward_s": fwd_s, "adjoint_over_forward": adj_s / fwd_s,
         "fd_gradient_s": fd_s, "speedup_vs_fd": fd_s / adj_s,
         "objective": J, "objective_fd_run": j_fd, "cosine_adjoint_vs_fd": cos,

@@ -94,14 +94,19 @@ class AdjointObjective:
     and nu_t.
     """
 
-    def __init__(self, grid, design, regions, u_target=0.55, nsteps=1, initial_state=None, checkpoint=20,
-                 u_field=None):
+    def __init__(self, grid, design, regions, u_target=0.55, nsteps=1, initial_state=None, checkpoint=None,
+                 u_field=None, memory_fraction=0.25):
+        """``checkpoint``: steps per recomputed segment; None keeps every
+        state of the horizon when they fit in ``memory_fraction`` of the
+        GPU's free memory (no recompute at all), else checkpoints every 20
+        steps."""
         self.grid, self.design = grid, design
         self.regions = [tuple(tuple(int(x) for x in lohi) for lohi in box) for box in regions]
         self.u_target = float(u_target)
         self.u_field = u_field
         self.nsteps = int(nsteps)
-        self.checkpoint = max(1, int(checkpoint))
+        self.checkpoint = None if checkpoint is None else max(1, int(checkpoint))
+        self.memory_fraction = float(memory_fraction)
         st = initial_state if initial_state is not None else grid.state()
         self.initial = {f: a.clone() if hasattr(a, "clone") else np.array(a) for f, a in st.items()}
         self.calls = 0
@@ -118,13 +123,26 @@ class AdjointObjective:
     def __call__(self, theta):
         return self.value_and_grad(theta)[0]
 
+    def _auto_checkpoint(self, fields):
+        import torch
+        g, N = self.grid, max(self.nsteps, 1)
+        per_state = 0
+        for f in fields:
+            e = g.extent(f)
+            per_state += e[0] * e[1] * e[2]
+        per_state *= torch.finfo(g.dtype).bits // 8
+        free = torch.cuda.mem_get_info(g.device)[0] if g.device.type == "cuda" else float("inf")
+        return N if N * per_state <= self.memory_fraction * free else 20
+
     def value_and_grad(self, theta):
         import torch
-        g, K, N = self.grid, self.checkpoint, self.nsteps
+        g, N = self.grid, self.nsteps
         theta = np.asarray(theta, dtype=np.float64)
         g.set_state(self.initial)
         g.set_porosity(self.design.porosity(theta))
         fields = g.adjoint_fields()
+        K = self.checkpoint if self.checkpoint is not None else self._auto_checkpoint(fields)
+        self.segment = K
         last = ((N - 1) // K) * K if N else 0
         ckpt, tail = {}, []
         for s in range(N):

@@ -73,6 +73,13 @@ class _ToyGrid:
     def adjoint_fields(self):
         return ("u", "v", "w")
 
+    def extent(self, name):
+        return (self.n[0], 1, 1)
+
+    @property
+    def dtype(self):
+        return self.torch.float64
+
     def step(self, n=1, stats=False):
         for _ in range(n):
             u = self.f["u"]
@@ -146,3 +153,19 @@ def test_design_objective_is_a_torch_function():
     J0, g0, _ = _toy_reference(theta.detach().numpy(), np.linspace(-0.2, 0.5, m), dt, 5)
     assert abs(float(J.detach()) - J0) <= 1e-14 * max(1.0, abs(J0))
     assert np.allclose(gt.numpy(), 3.0 * g0, rtol=1e-13, atol=1e-15)
+
+
+def test_adjoint_objective_keeps_every_state_when_it_fits():
+    """checkpoint=None: the states fit (a host 'device' has no limit), so the
+    sweep keeps them all and recomputes nothing; same gradient."""
+    import torch
+    m, dt, N = 5, 0.1, 7
+    theta = np.linspace(0.2, 1.4, m)
+    u0 = np.linspace(-0.5, 0.7, m)
+    g = _ToyGrid(m, dt)
+    g.f["u"] = torch.as_tensor(u0)
+    A = O.AdjointObjective(g, _ToyDesign(), [], 0.0, nsteps=N)
+    J, grad = A.value_and_grad(theta)
+    J0, g0, order = _toy_reference(theta, u0, dt, N)
+    assert A.segment == N and g.steps == N
+    assert np.allclose(grad, g0, rtol=1e-13, atol=1e-15)
