@@ -510,41 +510,6 @@ __device__ __forceinline__ Strain<T> strain_at(const Params<T>& P, const T* __re
   return s;
 }
 
-// Reverse of strain_at: dS2/dg_dd = 2 g_dd, dS2/dg_cd = dS2/dg_dc = 2 s_cd,
-// then each gradient back to the faces it differences.
-template <class T>
-__device__ __forceinline__ void strain_adj(const Params<T>& P, const Strain<T>& s, T s2bar, T* __restrict__ GU,
-                                           T* __restrict__ GV, T* __restrict__ GW, long long o) {
-  if (s2bar == T(0)) return;
-  const Layout& L = P.L;
-  const long long SX = L.SX, PZ = L.PZ;
-  const T h0 = T(0.5) * P.ih[0], h1 = T(0.5) * P.ih[1], h2 = T(0.5) * P.ih[2];
-  const T b00 = T(2) * s.g[0][0] * s2bar, b11 = T(2) * s.g[1][1] * s2bar, b22 = T(2) * s.g[2][2] * s2bar;
-  const T b01 = (s.g[0][1] + s.g[1][0]) * s2bar;   // 2 s01 s2bar, for g01 and g10 alike
-  const T b02 = (s.g[0][2] + s.g[2][0]) * s2bar;
-  const T b12 = (s.g[1][2] + s.g[2][1]) * s2bar;
-  add_to(GU + o + SX, b00 * P.ih[0]);
-  add_to(GU + o, -b00 * P.ih[0]);
-  add_to(GV + o + PZ, b11 * P.ih[1]);
-  add_to(GV + o, -b11 * P.ih[1]);
-  add_to(GW + o + 1, b22 * P.ih[2]);
-  add_to(GW + o, -b22 * P.ih[2]);
-  // a centred difference of cell-centre values, each the mean of two faces
-  auto cdiff = [&](T* G, long long st_face, long long st_dir, T w) {
-    const T q = T(0.5) * w;
-    add_to(G + o + st_dir, q);
-    add_to(G + o + st_dir + st_face, q);
-    add_to(G + o - st_dir, -q);
-    add_to(G + o - st_dir + st_face, -q);
-  };
-  cdiff(GU, SX, PZ, b01 * h1);
-  cdiff(GU, SX, 1, b02 * h2);
-  cdiff(GV, PZ, SX, b01 * h0);
-  cdiff(GV, PZ, 1, b12 * h2);
-  cdiff(GW, 1, SX, b02 * h0);
-  cdiff(GW, 1, PZ, b12 * h1);
-}
-
 // nu_t = min(max(k / max(omega, lim), 0), cap), lim = lim_coef |S|, and its
 // derivatives where it is not clipped.
 template <class T>
@@ -573,13 +538,16 @@ __device__ __forceinline__ Nut<T> nut_of(const Params<T>& P, T kk, T ww, T S2) {
 // velocity U and the old k, omega).  kb, wb, nb: adjoints of the new k,
 // omega and nu_t; writes the adjoints of the old k and omega (atomic: the
 // advection and Laplacian stencils reach the neighbours) and of U.
+// Writes, per cell, the adjoints of its velocity gradients (SB.a[0]: the
+// diagonal ones times 2 g_dd, SB.a[1]: the symmetric pairs 01, 02, 12 times
+// g_cd + g_dc, all times the |S|^2 adjoint) and of its cell-centre velocity
+// (SB.a[2]); k_strain_gather moves them to the faces.
 template <class T>
 __global__ __launch_bounds__(256) void k_turb_adj(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
                                                   const T* __restrict__ W, const T* __restrict__ K0,
                                                   const T* __restrict__ W0, const T* __restrict__ KB1,
                                                   const T* __restrict__ WB1, const T* __restrict__ NB1,
-                                                  T* __restrict__ KB0, T* __restrict__ WB0, T* __restrict__ GU,
-                                                  T* __restrict__ GV, T* __restrict__ GW) {
+                                                  T* __restrict__ KB0, T* __restrict__ WB0, VelAdj<T> SB) {
   const Layout& L = P.L;
   const long long n = (long long)L.nx * L.ny * L.nz;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
@@ -589,7 +557,11 @@ __global__ __launch_bounds__(256) void k_turb_adj(Params<T> P, const T* __restri
     const int i = (int)(rr / L.ny);
     const long long o = L.at(i, j, k);
     const T kb1 = KB1[o], wb1 = WB1[o], nb1 = NB1[o];
-    if (kb1 == T(0) && wb1 == T(0) && nb1 == T(0)) continue;
+    if (kb1 == T(0) && wb1 == T(0) && nb1 == T(0)) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) SB.a[q / 3][q % 3][o] = T(0);
+      continue;
+    }
     const long long st[3] = {L.SX, (long long)L.PZ, 1LL};
     // forward recompute
     const Strain<T> s = strain_at(P, U, V, W, o);
@@ -644,14 +616,60 @@ __global__ __launch_bounds__(256) void k_turb_adj(Params<T> P, const T* __restri
     stencil_adj(W0, WB0, bw * P.dt, P.nu + T(kSigma) * nu0.nut, wwb);
     add_to(KB0 + o, kkb);
     add_to(WB0 + o, wwb);
-    // cell-centre velocities back to their faces, then |S|^2
-    add_to(GU + o, T(0.5) * velb[0]);
-    add_to(GU + o + L.SX, T(0.5) * velb[0]);
-    add_to(GV + o, T(0.5) * velb[1]);
-    add_to(GV + o + L.PZ, T(0.5) * velb[1]);
-    add_to(GW + o, T(0.5) * velb[2]);
-    add_to(GW + o + 1, T(0.5) * velb[2]);
-    strain_adj(P, s, s2b, GU, GV, GW, o);
+    SB.a[0][0][o] = T(2) * s.g[0][0] * s2b;
+    SB.a[0][1][o] = T(2) * s.g[1][1] * s2b;
+    SB.a[0][2][o] = T(2) * s.g[2][2] * s2b;
+    SB.a[1][0][o] = (s.g[0][1] + s.g[1][0]) * s2b;
+    SB.a[1][1][o] = (s.g[0][2] + s.g[2][0]) * s2b;
+    SB.a[1][2][o] = (s.g[1][2] + s.g[2][1]) * s2b;
+    SB.a[2][0][o] = velb[0];
+    SB.a[2][1][o] = velb[1];
+    SB.a[2][2][o] = velb[2];
+  }
+}
+
+// Transpose of the velocity gradients and cell-centre velocities of
+// k_turb_adj, as a gather over every padded face position t of component C:
+// g_CC of cells t - e_C (+) and t (-); the centred cross differences
+// d u_C / d x_d of cells t -/+ e_d and t -/+ e_d - e_C; the cell-centre
+// velocity of cells t and t - e_C.  Cells outside the grid give nothing.
+template <int C, class T>
+__device__ __forceinline__ T strain_gather_value(const Params<T>& P, const VelAdj<T>& SB, int i, int j, int k) {
+  const Layout& L = P.L;
+  auto val = [&](int a, int b, int ci, int cj, int ck) -> T {
+    if (ci < 0 || cj < 0 || ck < 0 || ci >= L.nx || cj >= L.ny || ck >= L.nz) return T(0);
+    return SB.a[a][b][L.at(ci, cj, ck)];
+  };
+  const int ec[3] = {C == 0, C == 1, C == 2};
+  T s = (val(0, C, i - ec[0], j - ec[1], k - ec[2]) - val(0, C, i, j, k)) * P.ih[C];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d == C) continue;
+    const int pair = (C + d == 1) ? 0 : ((C + d == 2) ? 1 : 2);   // 01, 02, 12
+    const int ed[3] = {d == 0, d == 1, d == 2};
+    const T q = T(0.25) * P.ih[d];
+    s += q * (val(1, pair, i - ed[0], j - ed[1], k - ed[2]) +
+              val(1, pair, i - ed[0] - ec[0], j - ed[1] - ec[1], k - ed[2] - ec[2]) -
+              val(1, pair, i + ed[0], j + ed[1], k + ed[2]) -
+              val(1, pair, i + ed[0] - ec[0], j + ed[1] - ec[1], k + ed[2] - ec[2]));
+  }
+  s += T(0.5) * (val(2, C, i, j, k) + val(2, C, i - ec[0], j - ec[1], k - ec[2]));
+  return s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_strain_gather(Params<T> P, VelAdj<T> SB, T* __restrict__ G0,
+                                                       T* __restrict__ G1, T* __restrict__ G2, long long nelem) {
+  const Layout& L = P.L;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nelem;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(p / L.SX) - 1;
+    const long long r = p - (long long)(i + 1) * L.SX;
+    const int j = (int)(r / L.PZ) - 1;
+    const int k = (int)(r - (long long)(j + 1) * L.PZ) - 1;
+    G0[p] += strain_gather_value<0>(P, SB, i, j, k);
+    G1[p] += strain_gather_value<1>(P, SB, i, j, k);
+    G2[p] += strain_gather_value<2>(P, SB, i, j, k);
   }
 }
 
@@ -884,9 +902,15 @@ static inline int cell_blocks(const Layout& L) {
 template <class T>
 void launch_turb_adj(Grid& g, const Params<T>& P, void* const Unew[3], const void* K0, const void* W0,
                      const void* KB1, const void* WB1, const void* NB1, void* KB0, void* WB0, void* const G[3]) {
+  // the per-cell values go through the velocity-adjoint arrays, which the
+  // next reverse kernel overwrites (its gather reads interior cells only here)
   hipLaunchKernelGGL(k_turb_adj<T>, dim3(cell_blocks(P.L)), dim3(256), 0, g.stream, P, (const T*)Unew[0],
                      (const T*)Unew[1], (const T*)Unew[2], (const T*)K0, (const T*)W0, (const T*)KB1, (const T*)WB1,
-                     (const T*)NB1, (T*)KB0, (T*)WB0, (T*)G[0], (T*)G[1], (T*)G[2]);
+                     (const T*)NB1, (T*)KB0, (T*)WB0, vel_adj<T>(g));
+  const long long n = (long long)g.nelem;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_strain_gather<T>, dim3(blocks), dim3(256), 0, g.stream, P, vel_adj<T>(g), (T*)G[0], (T*)G[1],
+                     (T*)G[2], n);
 }
 
 template <class T>
