@@ -135,38 +135,6 @@ struct SamplePos {
   }
 };
 
-// Reverse of sample(): adds wbar times the trilinear weights into the eight
-// samples of qbar, and returns in grad the derivative of the sampled value
-// with respect to the position (zero along an axis where it was clamped).
-template <int C, class T>
-__device__ __forceinline__ void sample_adj(const Layout& L, const T* __restrict__ q, T* __restrict__ qbar, T fi,
-                                           T fj, T fk, T wbar, T grad[3]) {
-  const SamplePos<C, T> s(L, fi, fj, fk);
-  const long long o = s.o, SX = L.SX, PZ = L.PZ;
-  const T ti = s.t[0], tj = s.t[1], tk = s.t[2];
-  const T s000 = q[o], s100 = q[o + SX], s010 = q[o + PZ], s110 = q[o + SX + PZ];
-  const T s001 = q[o + 1], s101 = q[o + SX + 1], s011 = q[o + PZ + 1], s111 = q[o + SX + PZ + 1];
-  const T ui = T(1) - ti, uj = T(1) - tj, uk = T(1) - tk;
-  grad[0] = s.live[0] ? uj * uk * (s100 - s000) + tj * uk * (s110 - s010) + uj * tk * (s101 - s001) +
-                            tj * tk * (s111 - s011)
-                      : T(0);
-  grad[1] = s.live[1] ? ui * uk * (s010 - s000) + ti * uk * (s110 - s100) + ui * tk * (s011 - s001) +
-                            ti * tk * (s111 - s101)
-                      : T(0);
-  grad[2] = s.live[2] ? ui * uj * (s001 - s000) + ti * uj * (s101 - s100) + ui * tj * (s011 - s010) +
-                            ti * tj * (s111 - s110)
-                      : T(0);
-  if (wbar == T(0)) return;
-  add_to(qbar + o, wbar * ui * uj * uk);
-  add_to(qbar + o + SX, wbar * ti * uj * uk);
-  add_to(qbar + o + PZ, wbar * ui * tj * uk);
-  add_to(qbar + o + SX + PZ, wbar * ti * tj * uk);
-  add_to(qbar + o + 1, wbar * ui * uj * tk);
-  add_to(qbar + o + SX + 1, wbar * ti * uj * tk);
-  add_to(qbar + o + PZ + 1, wbar * ui * tj * tk);
-  add_to(qbar + o + SX + PZ + 1, wbar * ti * tj * tk);
-}
-
 // Offset of the smallest (want_max false) or largest of the eight samples
 // around a position (the first one in corner order on a tie).
 template <int C, class T>
@@ -188,20 +156,89 @@ __device__ __forceinline__ long long sample_extreme(const Layout& L, const T* __
 }
 
 // ------------------------------------------------------------- advection --
+// A trilinear scatter of one lane, made by all lanes of the wavefront
+// together.  Lanes are consecutive along z, so lane L's upper layer of
+// samples (z index k0 + 1) is usually lane L+1's lower layer: when their
+// corners are one apart, L+1 adds L's four upper weights to its own lower
+// ones (one shuffle each) and L skips those atomics -- four atomic adds per
+// sample instead of eight.  Both lanes decide from the same two corners.
+template <class T>
+struct Scatter8 {
+  long long o;   // lower corner
+  T w[8];        // weights times the adjoint, corner order 000 100 010 110 001 101 011 111
+  bool on;
+};
+
+template <int C, class T>
+__device__ __forceinline__ void sample_weights(const Layout& L, const T* __restrict__ q, T fi, T fj, T fk, T wbar,
+                                               T grad[3], Scatter8<T>& sc) {
+  const SamplePos<C, T> s(L, fi, fj, fk);
+  const long long o = s.o, SX = L.SX, PZ = L.PZ;
+  const T ti = s.t[0], tj = s.t[1], tk = s.t[2];
+  const T s000 = q[o], s100 = q[o + SX], s010 = q[o + PZ], s110 = q[o + SX + PZ];
+  const T s001 = q[o + 1], s101 = q[o + SX + 1], s011 = q[o + PZ + 1], s111 = q[o + SX + PZ + 1];
+  const T ui = T(1) - ti, uj = T(1) - tj, uk = T(1) - tk;
+  grad[0] = s.live[0] ? uj * uk * (s100 - s000) + tj * uk * (s110 - s010) + uj * tk * (s101 - s001) +
+                            tj * tk * (s111 - s011)
+                      : T(0);
+  grad[1] = s.live[1] ? ui * uk * (s010 - s000) + ti * uk * (s110 - s100) + ui * tk * (s011 - s001) +
+                            ti * tk * (s111 - s101)
+                      : T(0);
+  grad[2] = s.live[2] ? ui * uj * (s001 - s000) + ti * uj * (s101 - s100) + ui * tj * (s011 - s010) +
+                            ti * tj * (s111 - s110)
+                      : T(0);
+  sc.o = o;
+  sc.on = wbar != T(0);
+  sc.w[0] = wbar * ui * uj * uk;
+  sc.w[1] = wbar * ti * uj * uk;
+  sc.w[2] = wbar * ui * tj * uk;
+  sc.w[3] = wbar * ti * tj * uk;
+  sc.w[4] = wbar * ui * uj * tk;
+  sc.w[5] = wbar * ti * uj * tk;
+  sc.w[6] = wbar * ui * tj * tk;
+  sc.w[7] = wbar * ti * tj * tk;
+}
+
+// Called by every lane of the wavefront (convergent).
+template <class T>
+__device__ __forceinline__ void paired_scatter(T* __restrict__ qbar, const Layout& L, const Scatter8<T>& sc) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const long long mine = sc.on ? sc.o : -2LL;   // corners are >= 0: -2 never matches
+  const long long prev = __shfl_up(mine, 1u);
+  const long long next = __shfl_down(mine, 1u);
+  T r[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = __shfl_up(sc.w[4 + q], 1u);
+  if (!sc.on) return;
+  const bool take = lane > 0 && prev >= 0 && prev + 1 == sc.o;
+  const bool give = lane < 63 && next == sc.o + 1;
+  const long long SX = L.SX, PZ = L.PZ;
+  const long long lo[4] = {0, SX, PZ, SX + PZ};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) add_to(qbar + sc.o + lo[q], take ? sc.w[q] + r[q] : sc.w[q]);
+  if (!give) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) add_to(qbar + sc.o + lo[q] + 1, sc.w[4 + q]);
+  }
+}
+
 // Reverse of the corrector: out = clamp(qh + (q - qc)/2, min, max) with
 // qh sampled from q at the back-traced point and qc from qhat at the
 // forward-traced point.  A clamped output is one of the eight samples of q.
+// The two trilinear scatters are returned (sb into q's adjoint, sf into
+// qhat's); the face's own half goes into vb[C] (gathered back to it).
 template <int C, class T>
 __device__ __forceinline__ void advect_corr_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
                                                 const T* __restrict__ W, const T* __restrict__ qhat, T ob,
-                                                T* __restrict__ GU, T* __restrict__ GV, T* __restrict__ GW,
-                                                T* __restrict__ Ghat, long long o, int i, int j, int k, T vb[3]) {
+                                                T* __restrict__ Gq, long long o, int i, int j, int k, T vb[3],
+                                                Scatter8<T>& sb, Scatter8<T>& sf) {
   vb[0] = vb[1] = vb[2] = T(0);
+  sb = Scatter8<T>();
+  sf = Scatter8<T>();
   if (ob == T(0)) return;
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
-  T* Gq = C == 0 ? GU : (C == 1 ? GV : GW);
   const T di = vel[0] * P.dth[0], dj = vel[1] * P.dth[1], dk = vel[2] * P.dth[2];
   const T bi = T(i) - di, bj = T(j) - dj, bk = T(k) - dk;
   const T fi = T(i) + di, fj = T(j) + dj, fk = T(k) + dk;
@@ -214,31 +251,44 @@ __device__ __forceinline__ void advect_corr_adj(const Params<T>& P, const T* __r
     return;
   }
   T gb[3], gf[3];
-  sample_adj<C>(P.L, q, Gq, bi, bj, bk, ob, gb);
-  add_to(Gq + o, T(0.5) * ob);
-  sample_adj<C>(P.L, qhat, Ghat, fi, fj, fk, T(-0.5) * ob, gf);
+  sample_weights<C>(P.L, q, bi, bj, bk, ob, gb, sb);
+  sample_weights<C>(P.L, qhat, fi, fj, fk, T(-0.5) * ob, gf, sf);
   vb[0] = -ob * P.dth[0] * (gb[0] + T(0.5) * gf[0]);
   vb[1] = -ob * P.dth[1] * (gb[1] + T(0.5) * gf[1]);
   vb[2] = -ob * P.dth[2] * (gb[2] + T(0.5) * gf[2]);
+  vb[C] += T(0.5) * ob;
 }
 
 // Reverse of the predictor: qhat = q sampled at the back-traced point.
 template <int C, class T>
 __device__ __forceinline__ void advect_fwd_adj(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
-                                               const T* __restrict__ W, T ob, T* __restrict__ GU, T* __restrict__ GV,
-                                               T* __restrict__ GW, long long o, int i, int j, int k, T vb[3]) {
+                                               const T* __restrict__ W, T ob, long long o, int i, int j, int k,
+                                               T vb[3], Scatter8<T>& sb) {
   vb[0] = vb[1] = vb[2] = T(0);
+  sb = Scatter8<T>();
   if (ob == T(0)) return;
   T vel[3];
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
-  T* Gq = C == 0 ? GU : (C == 1 ? GV : GW);
   T g[3];
-  sample_adj<C>(P.L, q, Gq, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], ob, g);
+  sample_weights<C>(P.L, q, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], ob, g, sb);
   vb[0] = -ob * P.dth[0] * g[0];
   vb[1] = -ob * P.dth[1] * g[1];
   vb[2] = -ob * P.dth[2] * g[2];
 }
+
+// The face-thread mapping without the early exit of lanes past the last
+// corner (the paired scatter needs every lane of the wavefront): such lanes
+// carry no adjoint and write nothing.
+#define UF_FACE_THREAD_ALL(L)                                        \
+  int f_bx, f_by;                                                    \
+  if (!xcd_block(face_gx(L), (L).nx + 1, f_bx, f_by)) return;        \
+  const int i = f_by;                                                \
+  const int p_raw = f_bx * kFaceBlock + threadIdx.x;                 \
+  const bool lane_valid = p_raw < ((L).ny + 1) * ((L).nz + 1);       \
+  const int p = lane_valid ? p_raw : 0;                              \
+  const int j = p / ((L).nz + 1);                                    \
+  const int k = p - j * ((L).nz + 1);
 
 template <class T>
 __global__ __launch_bounds__(kFaceBlock) void k_advect_corr_adj(Params<T> P, const T* __restrict__ U,
@@ -250,15 +300,22 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_corr_adj(Params<T> P, con
                                                                 T* __restrict__ GW, T* __restrict__ HU,
                                                                 T* __restrict__ HV, T* __restrict__ HW,
                                                                 VelAdj<T> VA) {
-  UF_FACE_THREAD(P.L);
+  UF_FACE_THREAD_ALL(P.L);
   const long long o = P.L.at(i, j, k);
   T vb[3];
-  advect_corr_adj<0>(P, U, V, W, Uh, adj_in<0>(P, A0, i, j, k), GU, GV, GW, HU, o, i, j, k, vb);
-  vel_store<0>(VA, o, vb, false);
-  advect_corr_adj<1>(P, U, V, W, Vh, adj_in<1>(P, A1, i, j, k), GU, GV, GW, HV, o, i, j, k, vb);
-  vel_store<1>(VA, o, vb, false);
-  advect_corr_adj<2>(P, U, V, W, Wh, adj_in<2>(P, A2, i, j, k), GU, GV, GW, HW, o, i, j, k, vb);
-  vel_store<2>(VA, o, vb, false);
+  Scatter8<T> sb, sf;
+  advect_corr_adj<0>(P, U, V, W, Uh, lane_valid ? adj_in<0>(P, A0, i, j, k) : T(0), GU, o, i, j, k, vb, sb, sf);
+  if (lane_valid) vel_store<0>(VA, o, vb, false);
+  paired_scatter(GU, P.L, sb);
+  paired_scatter(HU, P.L, sf);
+  advect_corr_adj<1>(P, U, V, W, Vh, lane_valid ? adj_in<1>(P, A1, i, j, k) : T(0), GV, o, i, j, k, vb, sb, sf);
+  if (lane_valid) vel_store<1>(VA, o, vb, false);
+  paired_scatter(GV, P.L, sb);
+  paired_scatter(HV, P.L, sf);
+  advect_corr_adj<2>(P, U, V, W, Wh, lane_valid ? adj_in<2>(P, A2, i, j, k) : T(0), GW, o, i, j, k, vb, sb, sf);
+  if (lane_valid) vel_store<2>(VA, o, vb, false);
+  paired_scatter(GW, P.L, sb);
+  paired_scatter(HW, P.L, sf);
 }
 
 template <class T>
@@ -268,15 +325,19 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_fwd_adj(Params<T> P, cons
                                                                const T* __restrict__ H2, T* __restrict__ GU,
                                                                T* __restrict__ GV, T* __restrict__ GW,
                                                                VelAdj<T> VA) {
-  UF_FACE_THREAD(P.L);
+  UF_FACE_THREAD_ALL(P.L);
   const long long o = P.L.at(i, j, k);
   T vb[3];
-  advect_fwd_adj<0>(P, U, V, W, adj_in<0>(P, H0, i, j, k), GU, GV, GW, o, i, j, k, vb);
-  vel_store<0>(VA, o, vb, true);
-  advect_fwd_adj<1>(P, U, V, W, adj_in<1>(P, H1, i, j, k), GU, GV, GW, o, i, j, k, vb);
-  vel_store<1>(VA, o, vb, true);
-  advect_fwd_adj<2>(P, U, V, W, adj_in<2>(P, H2, i, j, k), GU, GV, GW, o, i, j, k, vb);
-  vel_store<2>(VA, o, vb, true);
+  Scatter8<T> sb;
+  advect_fwd_adj<0>(P, U, V, W, lane_valid ? adj_in<0>(P, H0, i, j, k) : T(0), o, i, j, k, vb, sb);
+  if (lane_valid) vel_store<0>(VA, o, vb, true);
+  paired_scatter(GU, P.L, sb);
+  advect_fwd_adj<1>(P, U, V, W, lane_valid ? adj_in<1>(P, H1, i, j, k) : T(0), o, i, j, k, vb, sb);
+  if (lane_valid) vel_store<1>(VA, o, vb, true);
+  paired_scatter(GV, P.L, sb);
+  advect_fwd_adj<2>(P, U, V, W, lane_valid ? adj_in<2>(P, H2, i, j, k) : T(0), o, i, j, k, vb, sb);
+  if (lane_valid) vel_store<2>(VA, o, vb, true);
+  paired_scatter(GW, P.L, sb);
 }
 
 // ------------------------------------------------------------- diffusion --
