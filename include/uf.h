@@ -301,6 +301,10 @@ typedef struct {
   const void* u_target_dev;    /* UF_OBJ_FIELD: device, 3 * nx*ny*nz desired
                                   cell-centre velocities in the grid's dtype:
                                   the u, v, then w block, each z fastest       */
+  void* dJ_dphi_accum_dev;     /* UF_OBJ_PLANE with a state gradient: NULL, or
+                                  device float64 nx*ny*nz (z fastest) to which
+                                  the objective's direct porosity derivative
+                                  (its phi weight) is added                    */
 } uf_objective_spec;
 enum { UF_MAX_REGIONS = 64 };
 
@@ -315,8 +319,12 @@ enum { UF_MAX_REGIONS = 64 };
  * fastest -- the seed of uf_adjoint_step.  Each face is half of the
  * cell-centre velocity of each adjacent cell; a cell of zero speed
  * contributes nothing to the mean-speed gradient.  Fixed boundary faces
- * get their derivative too (the reverse step ignores it).  The plane
- * objective has no gradient here (UF_ENOTIMPL when dJ_dstate_dev is set). */
+ * get their derivative too (the reverse step ignores it).  For the plane
+ * objective the two layers around the plane carry it (weights 1 - t and t
+ * of the interpolation), and its direct porosity derivative goes to
+ * spec->dJ_dphi_accum_dev when that is set.  The value is read back
+ * synchronously; the plane gradient's kernels may still run when the call
+ * returns (stream order). */
 uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev);
 
 /* One reverse step of the discrete adjoint (gradients of a Sec. 4 design

@@ -42,7 +42,7 @@ OBJ_REGIONS, OBJ_PLANE, OBJ_FIELD = 0, 1, 2
 class uf_objective_spec(ctypes.Structure):
     _fields_ = [("nregions", c_int32), ("boxes", POINTER(c_int32)), ("u_target", c_double),
                 ("kind", c_int32), ("z_plane", c_double), ("s_target", c_double), ("s_min", c_double),
-                ("w_penalty", c_double), ("u_target_dev", c_void_p)]
+                ("w_penalty", c_double), ("u_target_dev", c_void_p), ("dJ_dphi_accum_dev", c_void_p)]
 
 
 def make_objective_spec(regions, u_target):

@@ -818,12 +818,49 @@ __global__ __launch_bounds__(256) void k_diffuse_nut_adj(Params<T> P, const T* _
 // the grid.  kind 0 (mean speeds): dJ/dU_c = (sum over the regions holding
 // c of coef_r) U_c / |U_c|; kind 2 (desired field): (sum of coef_r)
 // (U_c - U_target,c).  coef_r is precomputed by the host.
+// The plane objective at column (i, j): the cell-centre velocity and the
+// porosity interpolated between layers k0 and k0 + 1 with weight t, and
+// s = sqrt(|u_p|^2 + 1e-12), as the forward evaluates them.
+struct PlaneSeed {
+  int k0;
+  double t, st, smin, wpen, area;
+};
+
+template <class T>
+__device__ __forceinline__ void plane_column(const Layout& L, const T* __restrict__ U, const T* __restrict__ V,
+                                             const T* __restrict__ W, const T* __restrict__ PHI, const PlaneSeed& ps,
+                                             int i, int j, double up[3], double& phip, double& s) {
+  double uc[2], vc[2], wc[2], ph[2];
+  for (int q = 0; q < 2; ++q) {
+    const long long o = L.at(i, j, ps.k0 + q);
+    uc[q] = 0.5 * ((double)U[o] + (double)U[o + L.SX]);
+    vc[q] = 0.5 * ((double)V[o] + (double)V[o + L.PZ]);
+    wc[q] = 0.5 * ((double)W[o] + (double)W[o + 1]);
+    ph[q] = (double)PHI[((size_t)i * L.ny + j) * L.nz + ps.k0 + q];
+  }
+  up[0] = (1.0 - ps.t) * uc[0] + ps.t * uc[1];
+  up[1] = (1.0 - ps.t) * vc[0] + ps.t * vc[1];
+  up[2] = (1.0 - ps.t) * wc[0] + ps.t * wc[1];
+  phip = (1.0 - ps.t) * ph[0] + ps.t * ph[1];
+  s = sqrt(up[0] * up[0] + up[1] * up[1] + up[2] * up[2] + 1e-12);
+}
+
 template <class T>
 __device__ __forceinline__ T seed_cell(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
                                        const T* __restrict__ W, const int* __restrict__ boxes,
                                        const double* __restrict__ coef, int nreg, int kind,
-                                       const T* __restrict__ ut, int C, int i, int j, int k) {
+                                       const T* __restrict__ ut, const PlaneSeed& ps, const T* __restrict__ PHI,
+                                       int C, int i, int j, int k) {
   const Layout& L = P.L;
+  if (kind == 1) {
+    // dJ/ds = area phi_p (2 (s - s_t) - 2 w max(0, s_min - s)), ds/du_p = u_p / s
+    if (k != ps.k0 && k != ps.k0 + 1) return T(0);
+    double up[3], phip, s;
+    plane_column(L, U, V, W, PHI, ps, i, j, up, phip, s);
+    const double lo = fmax(0.0, ps.smin - s);
+    const double dJds = ps.area * phip * (2.0 * (s - ps.st) - 2.0 * ps.wpen * lo);
+    return T((k == ps.k0 ? 1.0 - ps.t : ps.t) * dJds * up[C] / s);
+  }
   double cs = 0.0;
   for (int r = 0; r < nreg; ++r) {
     const int* b = boxes + 6 * r;
@@ -846,7 +883,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_objective_seed(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
                                                         const T* __restrict__ W, const int* __restrict__ boxes,
                                                         const double* __restrict__ coef, int nreg, int kind,
-                                                        const T* __restrict__ ut, T* __restrict__ out) {
+                                                        const T* __restrict__ ut, PlaneSeed ps,
+                                                        const T* __restrict__ PHI, T* __restrict__ out) {
   const Layout& L = P.L;
   const long long n0 = (long long)(L.nx + 1) * L.ny * L.nz, n1 = (long long)L.nx * (L.ny + 1) * L.nz;
   const long long n2 = (long long)L.nx * L.ny * (L.nz + 1);
@@ -873,9 +911,28 @@ __global__ __launch_bounds__(256) void k_objective_seed(Params<T> P, const T* __
     const int nC = C == 0 ? L.nx : (C == 1 ? L.ny : L.nz);
     T s = T(0);
     if (idx[C] > 0)
-      s += seed_cell(P, U, V, W, boxes, coef, nreg, kind, ut, C, i - (C == 0), j - (C == 1), k - (C == 2));
-    if (idx[C] < nC) s += seed_cell(P, U, V, W, boxes, coef, nreg, kind, ut, C, i, j, k);
+      s += seed_cell(P, U, V, W, boxes, coef, nreg, kind, ut, ps, PHI, C, i - (C == 0), j - (C == 1), k - (C == 2));
+    if (idx[C] < nC) s += seed_cell(P, U, V, W, boxes, coef, nreg, kind, ut, ps, PHI, C, i, j, k);
     out[p] = T(0.5) * s;
+  }
+}
+
+// The plane objective's direct porosity weight: dJ/dphi_p = area ((s - s_t)^2
+// + w max(0, s_min - s)^2), split (1 - t) / t onto layers k0 and k0 + 1.
+template <class T>
+__global__ __launch_bounds__(256) void k_plane_phi_seed(Layout L, const T* __restrict__ U, const T* __restrict__ V,
+                                                        const T* __restrict__ W, const T* __restrict__ PHI,
+                                                        PlaneSeed ps, double* __restrict__ phibar) {
+  const int n = L.nx * L.ny;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+    const int i = c / L.ny, j = c % L.ny;
+    double up[3], phip, s;
+    plane_column(L, U, V, W, PHI, ps, i, j, up, phip, s);
+    const double lo = fmax(0.0, ps.smin - s);
+    const double d = ps.area * ((s - ps.st) * (s - ps.st) + ps.wpen * lo * lo);
+    const size_t base = ((size_t)i * L.ny + j) * L.nz + ps.k0;
+    phibar[base] += (1.0 - ps.t) * d;
+    phibar[base + 1] += ps.t * d;
   }
 }
 
@@ -945,14 +1002,21 @@ void launch_drag_coef_adj(Grid& g, const Params<T>& P, const void* Cbar, double*
 
 template <class T>
 void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, const double* coef_dev, int nreg,
-                           int kind, const void* ut, void* out) {
+                           int kind, const void* ut, void* out, const double plane[6], double* phibar) {
   const Layout& L = P.L;
   const long long n = (long long)(L.nx + 1) * L.ny * L.nz + (long long)L.nx * (L.ny + 1) * L.nz +
                       (long long)L.nx * L.ny * (L.nz + 1);
   const int blocks = (int)std::min<long long>((n + 255) / 256, 16384);
   void* const* Q = g.Q[g.cur];
+  PlaneSeed ps{0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (plane) ps = PlaneSeed{(int)plane[0], plane[1], plane[2], plane[3], plane[4], plane[5]};
   hipLaunchKernelGGL(k_objective_seed<T>, dim3(blocks), dim3(256), 0, g.stream, P, (const T*)Q[0], (const T*)Q[1],
-                     (const T*)Q[2], boxes_dev, coef_dev, nreg, kind, (const T*)ut, (T*)out);
+                     (const T*)Q[2], boxes_dev, coef_dev, nreg, kind, (const T*)ut, ps, (const T*)g.PHI, (T*)out);
+  if (plane && phibar) {
+    const int cols = L.nx * L.ny;
+    hipLaunchKernelGGL(k_plane_phi_seed<T>, dim3(std::min(8192, (cols + 255) / 256)), dim3(256), 0, g.stream, L,
+                       (const T*)Q[0], (const T*)Q[1], (const T*)Q[2], (const T*)g.PHI, ps, phibar);
+  }
 }
 
 static inline int cell_blocks(const Layout& L) {
@@ -995,7 +1059,7 @@ void launch_diffuse_nut_adj(Grid& g, const Params<T>& P, void* const Qin[3], voi
   template void launch_fold<T>(Grid&, const Params<T>&, void* const[3]);                                        \
   template void launch_drag_coef_adj<T>(Grid&, const Params<T>&, const void*, double*);                        \
   template void launch_objective_seed<T>(Grid&, const Params<T>&, const int*, const double*, int, int,         \
-                                         const void*, void*);                                                   \
+                                         const void*, void*, const double*, double*);                           \
   template void launch_turb_adj<T>(Grid&, const Params<T>&, void* const[3], const void*, const void*,         \
                                    const void*, const void*, const void*, void*, void*, void* const[3]);        \
   template void launch_cell_fold<T>(Grid&, const Params<T>&, void*, int);                                      \

@@ -1100,8 +1100,6 @@ uf_status uf_apply_operator(uf_grid g, int32_t op, const void* x_dev, void* y_de
 
 uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host, void* dJ_dstate_dev) {
   if (!g || !spec || !J_host) return fail(UF_EINVAL, "NULL argument");
-  if (dJ_dstate_dev && spec->kind == UF_OBJ_PLANE)
-    return fail(UF_ENOTIMPL, "the state gradient of the plane objective is not implemented in this version");
   if (spec->kind == UF_OBJ_PLANE) {
     const double dz = g->cfg.dz;
     const int nz = g->L.nz;
@@ -1130,6 +1128,17 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
     double J = 0.0;
     for (int q = 0; q < nb; ++q) J += host[q];
     *J_host = J * g->cfg.dx * g->cfg.dy;
+    if (dJ_dstate_dev) {
+      const double plane[6] = {(double)k0, t, spec->s_target, spec->s_min, spec->w_penalty, g->cfg.dx * g->cfg.dy};
+      double* phibar = (double*)spec->dJ_dphi_accum_dev;
+      if (g->esize == 4)
+        launch_objective_seed<float>(*g, make_params<float>(*g), nullptr, nullptr, 0, 1, nullptr, dJ_dstate_dev,
+                                     plane, phibar);
+      else
+        launch_objective_seed<double>(*g, make_params<double>(*g), nullptr, nullptr, 0, 1, nullptr, dJ_dstate_dev,
+                                      plane, phibar);
+      check_launch();
+    }
     return UF_OK;
     UF_GUARD_END
   }
@@ -1195,10 +1204,10 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
     const int kind = field ? 2 : 0;
     if (g->esize == 4)
       launch_objective_seed<float>(*g, make_params<float>(*g), boxes_dev, coef_dev, nr, kind, spec->u_target_dev,
-                                   dJ_dstate_dev);
+                                   dJ_dstate_dev, nullptr, nullptr);
     else
       launch_objective_seed<double>(*g, make_params<double>(*g), boxes_dev, coef_dev, nr, kind,
-                                    spec->u_target_dev, dJ_dstate_dev);
+                                    spec->u_target_dev, dJ_dstate_dev, nullptr, nullptr);
     check_launch();
     UF_HIP_CHECK(hipStreamSynchronize(g->stream));   // the host tables above are copied from
   }

@@ -165,7 +165,7 @@ template <class T> void launch_diffuse_adj(Grid& g, const Params<T>& P, void* co
 template <class T> void launch_drag_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Aout[3], void* const Gin[3], void* Cbar);
 template <class T> void launch_fold(Grid& g, const Params<T>& P, void* const A[3]);
 template <class T> void launch_drag_coef_adj(Grid& g, const Params<T>& P, const void* Cbar, double* phibar);
-template <class T> void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, const double* coef_dev, int nreg, int kind, const void* ut, void* out);
+template <class T> void launch_objective_seed(Grid& g, const Params<T>& P, const int* boxes_dev, const double* coef_dev, int nreg, int kind, const void* ut, void* out, const double plane[6], double* phibar);
 template <class T> void launch_turb_adj(Grid& g, const Params<T>& P, void* const Unew[3], const void* K0, const void* W0, const void* KB1, const void* WB1, const void* NB1, void* KB0, void* WB0, void* const G[3]);
 template <class T> void launch_cell_fold(Grid& g, const Params<T>& P, void* q, int use_inlet);
 template <class T> void launch_diffuse_nut_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Aout[3], void* NB);

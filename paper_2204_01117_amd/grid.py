@@ -177,13 +177,16 @@ class Grid:
             self.tstream.synchronize()
         return tuple(out)
 
-    def plane_objective(self, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0):
+    def plane_objective(self, z_plane, s_target=2.0, s_min=0.3, w_penalty=10.0, grad=False, phibar=None):
         """Pedestrian-comfort objective on the horizontal plane z = z_plane:
-        dx dy sum phi [(s - s_target)^2 + w_penalty max(0, s_min - s)^2]."""
+        dx dy sum phi [(s - s_target)^2 + w_penalty max(0, s_min - s)^2].
+        With ``grad`` as in ``objective``; its direct porosity derivative is
+        added into ``phibar`` (float64 [nx, ny, nz]) when given."""
         spec = L.make_plane_spec(z_plane, s_target, s_min, w_penalty)
-        J = ctypes.c_double()
-        L.check(L.uf_objective(self.handle, byref(spec), byref(J), None))
-        return J.value
+        if phibar is not None:
+            assert grad and phibar.dtype == self.torch.float64 and tuple(phibar.shape) == self.n
+            spec.dJ_dphi_accum_dev = phibar.data_ptr()
+        return self._objective(spec, grad)
 
     def timer_enable(self, kernels=()):
         """Time every launch of the named kernels (see TIMED_KERNELS)."""

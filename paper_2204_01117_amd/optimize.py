@@ -95,11 +95,12 @@ class AdjointObjective:
     """
 
     def __init__(self, grid, design, regions, u_target=0.55, nsteps=1, initial_state=None, checkpoint=None,
-                 u_field=None, memory_fraction=0.25):
+                 u_field=None, memory_fraction=0.25, plane=None):
         """``checkpoint``: steps per recomputed segment; None keeps every
         state of the horizon when they fit in ``memory_fraction`` of the
         GPU's free memory (no recompute at all), else checkpoints every 20
-        steps."""
+        steps.  ``plane``: keyword arguments of ``Grid.plane_objective``
+        (z_plane, ...) to score the pedestrian plane instead of regions."""
         self.grid, self.design = grid, design
         self.regions = [tuple(tuple(int(x) for x in lohi) for lohi in box) for box in regions]
         self.u_target = float(u_target)
@@ -107,12 +108,15 @@ class AdjointObjective:
         self.nsteps = int(nsteps)
         self.checkpoint = None if checkpoint is None else max(1, int(checkpoint))
         self.memory_fraction = float(memory_fraction)
+        self.plane = dict(plane) if plane is not None else None
         st = initial_state if initial_state is not None else grid.state()
         self.initial = {f: a.clone() if hasattr(a, "clone") else np.array(a) for f, a in st.items()}
         self.calls = 0
 
-    def _objective(self, grad):
+    def _objective(self, grad, phibar=None):
         g = self.grid
+        if self.plane is not None:
+            return g.plane_objective(grad=grad, phibar=phibar, **self.plane)
         if self.u_field is not None:
             return g.field_objective(self.regions, self.u_field, grad=grad)
         return g.objective(self.regions, self.u_target, grad=grad)
@@ -151,9 +155,9 @@ class AdjointObjective:
             elif s % K == 0:
                 ckpt[s] = self._snapshot()
             g.step(1, stats=False)
-        J, lam = self._objective(grad=True)
-        lam = tuple(lam) + tuple(torch.zeros_like(g.get_field(f)) for f in fields[3:])
         phibar = torch.zeros(g.n, dtype=torch.float64, device=g.device)
+        J, lam = self._objective(grad=True, phibar=phibar)
+        lam = tuple(lam) + tuple(torch.zeros_like(g.get_field(f)) for f in fields[3:])
         # each reverse step also gets the state its step produced: the one
         # the previous reverse step started from (the final state first)
         after = [g.get_field(f) for f in ("u", "v", "w")]

@@ -130,7 +130,7 @@ def test_adjoint_porosity_gradient_one_step(seed):
     g.close()
 
 
-@pytest.mark.parametrize("kind", ["regions", "field"])
+@pytest.mark.parametrize("kind", ["regions", "field", "plane"])
 @pytest.mark.parametrize("seed", range(3))
 def test_objective_seed_matches_differences(kind, seed):
     cfg, n, phi = small_case(seed)
@@ -145,9 +145,13 @@ def test_objective_seed_matches_differences(kind, seed):
         regions.append(tuple(box))
     ut = torch.as_tensor(rng.normal(0.0, 1.0, size=(3,) + n))
 
+    zp = min(max(0.37 * n[2], 0.6), n[2] - 0.6) * cfg["dz"]
+
     def J(grad=False):
         if kind == "regions":
             return g.objective(regions, 0.55, grad=grad)
+        if kind == "plane":
+            return g.plane_objective(zp, s_target=1.0, s_min=0.8, w_penalty=3.0, grad=grad)
         return g.field_objective(regions, ut, grad=grad)
 
     J0, seed_t = J(grad=True)
@@ -168,6 +172,30 @@ def test_objective_seed_matches_differences(kind, seed):
     lhs = (vals[0] - vals[1]) / (2 * h)
     rhs = dot(seed_t, d)
     log(kind, seed, "J %.6e  FD %.12e  seed %.12e" % (J0, lhs, rhs))
+    assert abs(lhs - rhs) <= 1e-7 * max(abs(lhs), 1.0)
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_plane_objective_porosity_term(seed):
+    """The plane objective's direct porosity weight: <phibar, dphi> against
+    differences of the objective with the state held."""
+    cfg, n, phi = small_case(seed)
+    g, st = spun_up(cfg, phi)
+    zp = min(max(0.37 * n[2], 0.6), n[2] - 0.6) * cfg["dz"]
+    pb = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g.plane_objective(zp, s_target=1.0, s_min=0.8, w_penalty=3.0, grad=True, phibar=pb)
+    rng = np.random.default_rng(seed)
+    dphi = rng.normal(size=n) * ((phi > 0.05) & (phi < 0.95))
+    h = 1e-6
+    vals = []
+    for sgn in (1, -1):
+        g.set_porosity(torch.as_tensor(phi + sgn * h * dphi))
+        g.set_state(st)
+        vals.append(g.plane_objective(zp, s_target=1.0, s_min=0.8, w_penalty=3.0))
+    lhs = (vals[0] - vals[1]) / (2 * h)
+    rhs = float((pb.cpu().numpy() * dphi).sum())
+    log("case", seed, "FD %.12e  seed %.12e" % (lhs, rhs))
     assert abs(lhs - rhs) <= 1e-7 * max(abs(lhs), 1.0)
     g.close()
 
@@ -350,6 +378,7 @@ def test_multistep_porosity_gradient_against_oracle(seed):
 
 # ------------------------------------------------- design-parameter chain ---
 from oracle.smooth import smooth_porosity as oracle_smooth
+from oracle.objective import plane_objective as oracle_plane
 
 DESIGN_N, DESIGN_H = (24, 20, 10), (2.0, 2.0, 2.0)
 DESIGN_BOXES = [(8.0, 16.0, 10.0, 20.0, 0.0, 10.0, 0.0), (26.0, 34.0, 22.0, 32.0, 0.0, 14.0, 0.0),
@@ -409,6 +438,50 @@ def _oracle_design_J(cfg, theta, regions, nsteps, width):
     og.step(nsteps)
     s = og.state()
     return region_objective(s["u"], s["v"], s["w"], regions, 0.55)
+
+
+def _oracle_design_plane_J(cfg, theta, zp, nsteps, width):
+    boxes = [list(b) for b in DESIGN_BOXES]
+    for b in range(len(boxes)):
+        boxes[b][5] += theta[3 * b]
+        boxes[b][0] += theta[3 * b + 1]
+        boxes[b][1] += theta[3 * b + 1]
+        boxes[b][2] += theta[3 * b + 2]
+        boxes[b][3] += theta[3 * b + 2]
+    cyls = [list(c[:5]) + [min(max(theta[-1], 0.0), 1.0)] for c in DESIGN_CYLS]
+    phi = oracle_smooth(DESIGN_N, DESIGN_H, boxes, cyls, width)
+    og = OracleGrid(dict(cfg), solver_tol=1e-13)
+    og.set_porosity(phi)
+    og.step(nsteps)
+    s = og.state()
+    return oracle_plane(s["u"], s["v"], s["w"], phi, DESIGN_H, zp, 1.0, 0.8, 3.0)
+
+
+def test_design_gradient_of_the_plane_objective_against_oracle():
+    """The plane objective through the adjoint: its state seed and its
+    direct porosity weight, against central differences of the oracle."""
+    cfg, _ = _design_case()
+    width, nsteps, zp = 1.0, 5, 3.0
+    d = U.BoxDesign(DESIGN_N, DESIGN_H, DESIGN_BOXES, DESIGN_CYLS, width=width, dtype="f64")
+    g = U.Grid(cfg)
+    theta = d.initial()
+    theta[0], theta[4], theta[-1] = 0.7, -0.4, 0.45
+    A = U.AdjointObjective(g, d, [], nsteps=nsteps,
+                           plane=dict(z_plane=zp, s_target=1.0, s_min=0.8, w_penalty=3.0))
+    J, grad = A.value_and_grad(theta)
+    Jo = _oracle_design_plane_J(cfg, theta, zp, nsteps, width)
+    log("J gpu %.12e oracle %.12e" % (J, Jo))
+    assert abs(J - Jo) <= 1e-10 * abs(Jo)
+    eps = 1e-4
+    for q in (0, 1, 2, 4, len(theta) - 1):
+        tp, tm = theta.copy(), theta.copy()
+        tp[q] += eps
+        tm[q] -= eps
+        fd = (_oracle_design_plane_J(cfg, tp, zp, nsteps, width) -
+              _oracle_design_plane_J(cfg, tm, zp, nsteps, width)) / (2 * eps)
+        log("  theta[%d]: FD(oracle) %.10e  adjoint %.10e" % (q, fd, grad[q]))
+        assert abs(fd - grad[q]) <= 2e-5 * max(abs(fd), 1e-3 * np.abs(grad).max()), q
+    g.close()
 
 
 @pytest.mark.parametrize("turb", [False, True])
