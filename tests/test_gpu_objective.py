@@ -131,15 +131,15 @@ def test_objective_rejects_bad_specs_before_work():
     with pytest.raises(U.UFError) as e:
         g.objective([ok], float("nan"))
     assert e.value.name == "UF_EINVAL"
-    # the plane objective has no state gradient: refused before any work
+    # a bad plane is refused before its gradient buffer is touched
     import ctypes
     from paper_2204_01117_amd import _lib
-    pspec = _lib.make_plane_spec(1.5 * cfg["dz"])
     J = ctypes.c_double()
     ext = [g.extent(f) for f in ("u", "v", "w")]
     buf = torch.zeros(sum(e[0] * e[1] * e[2] for e in ext), dtype=g.dtype, device="cuda")
+    pspec = _lib.make_plane_spec(0.1 * cfg["dz"])
     rc = U.uf_objective(g.handle, ctypes.byref(pspec), ctypes.byref(J), ctypes.c_void_p(buf.data_ptr()))
-    assert U.STATUS[rc] == "UF_ENOTIMPL"
+    assert U.STATUS[rc] == "UF_EINVAL"
     assert not buf.any()
     # 64 regions is the maximum and works
     assert g.objective([ok] * 64, 0.55) >= 0.0
