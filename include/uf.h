@@ -122,6 +122,15 @@ typedef struct {
  * enums), UF_ENOMEM, UF_EDEVICE.  *out is set only on success. */
 uf_status uf_create_grid(const uf_config* cfg, uf_grid* out);
 
+/* The side kinds a configuration resolves to, sides ordered -x, +x, -y, +y,
+ * -z, +z: explicit kinds as given, UF_BC_AUTO replaced by the rule above (a
+ * vertical side is an inlet when the inward normal's dot product with the
+ * wind direction (cos, sin of wind_dir_deg) exceeds 1e-12, an outlet
+ * otherwise; the ground a wall, the sky a slip surface).  Host only, no
+ * device work.  UF_EINVAL for NULL arguments, a non-finite wind direction or
+ * an unknown kind. */
+uf_status uf_resolve_bc(const uf_config* cfg, int32_t out[6]);
+
 /* Release a grid and all of its device memory (synchronises its stream). */
 uf_status uf_destroy_grid(uf_grid g);
 

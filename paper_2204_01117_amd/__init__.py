@@ -10,7 +10,7 @@ this package fails when libuf.so is missing.
 from ._lib import (lib, LIB_PATH, UFError, uf_config, uf_step_stats, make_config,
                    uf_objective_spec, make_objective_spec, uf_mesh_set, STATUS, FIELDS, FIELD_IDS)
 from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_field,
-                   uf_get_field, uf_field_extent, uf_step, uf_pressure_solve,
+                   uf_get_field, uf_field_extent, uf_resolve_bc, uf_step, uf_pressure_solve,
                    uf_apply_operator, uf_objective, uf_adjoint_step, uf_adjoint_step_at, uf_set_stream,
                    uf_kernel_timer_enable, uf_kernel_timer_read, uf_last_error, TIMED_KERNELS,
                    uf_voxelize, uf_step_batch, uf_smooth_porosity, uf_smooth_porosity_grad, uf_smooth_objects)
@@ -27,6 +27,6 @@ __all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_con
            "forward_difference_gradient", "gradient_descent",
            "STATUS", "FIELDS", "FIELD_IDS", "Grid",
            "uf_create_grid", "uf_destroy_grid", "uf_set_porosity", "uf_set_field",
-           "uf_get_field", "uf_field_extent", "uf_step", "uf_pressure_solve",
+           "uf_get_field", "uf_field_extent", "uf_resolve_bc", "uf_step", "uf_pressure_solve",
            "uf_apply_operator", "uf_objective", "uf_adjoint_step", "uf_adjoint_step_at", "uf_set_stream",
            "uf_kernel_timer_enable", "uf_kernel_timer_read", "uf_last_error", "TIMED_KERNELS"]

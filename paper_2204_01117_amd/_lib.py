@@ -105,6 +105,7 @@ _SIGS = {
     "uf_set_field": (c_int32, [c_void_p, c_int32, c_void_p]),
     "uf_get_field": (c_int32, [c_void_p, c_int32, c_void_p]),
     "uf_field_extent": (c_int64, [POINTER(uf_config), c_int32, POINTER(c_int32)]),
+    "uf_resolve_bc": (c_int32, [POINTER(uf_config), POINTER(c_int32)]),
     "uf_step": (c_int32, [c_void_p, c_int32, POINTER(uf_step_stats)]),
     "uf_pressure_solve": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(uf_step_stats)]),
     "uf_apply_operator": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
@@ -131,6 +132,7 @@ uf_set_porosity = lib.uf_set_porosity
 uf_set_field = lib.uf_set_field
 uf_get_field = lib.uf_get_field
 uf_field_extent = lib.uf_field_extent
+uf_resolve_bc = lib.uf_resolve_bc
 uf_step = lib.uf_step
 uf_pressure_solve = lib.uf_pressure_solve
 uf_apply_operator = lib.uf_apply_operator

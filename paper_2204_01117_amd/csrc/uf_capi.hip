@@ -679,6 +679,17 @@ extern "C" {
 
 const char* uf_last_error(void) { return g_last_error.c_str(); }
 
+uf_status uf_resolve_bc(const uf_config* cfg, int32_t out[6]) {
+  if (!cfg || !out) return fail(UF_EINVAL, "NULL argument");
+  if (!std::isfinite(cfg->wind_dir_deg)) return fail(UF_EINVAL, "wind_dir_deg must be finite");
+  for (int s = 0; s < 6; ++s)
+    if (cfg->bc[s] < UF_BC_AUTO || cfg->bc[s] > UF_BC_SLIP) return fail(UF_EINVAL, "unknown boundary kind");
+  int bc[6];
+  resolve_bc(*cfg, bc);
+  for (int s = 0; s < 6; ++s) out[s] = bc[s];
+  return UF_OK;
+}
+
 int64_t uf_field_extent(const uf_config* cfg, int32_t field, int32_t dims[3]) {
   if (!cfg) return -1;
   return extent(cfg, field, dims);

@@ -147,3 +147,40 @@ def test_ctypes_structs_match_the_header():
                 assert ct._length_ == count and ct._type_ is ctype_of[typ], name
             else:
                 assert ct is ctype_of[typ], (cname, name, typ, ct)
+
+
+@pytest.mark.parametrize("deg,expect", [
+    (0.0, [0, 1, 1, 1, 2, 3]),          # wind +x enters through -x
+    (90.0, [1, 1, 0, 1, 2, 3]),         # cos 90 deg ~ 6e-17: tangential to the x sides
+    (180.0, [1, 0, 1, 1, 2, 3]),
+    (225.0, [1, 0, 1, 0, 2, 3]),        # through +x and +y
+    (270.0, [1, 1, 1, 0, 2, 3]),
+    (30.0, [0, 1, 0, 1, 2, 3]),
+])
+def test_library_resolves_auto_sides_like_the_hand_table(deg, expect):
+    """The library's side-kind rule against the same hand table the oracle's
+    rule is pinned to (inlet where the wind enters, ground wall, sky slip)."""
+    import ctypes
+    import paper_2204_01117_amd as U
+    from uf_layouts import default_config
+    c, keep = U.make_config(default_config(8, 6, 4, 1.0, wind_dir_deg=deg))
+    out = (ctypes.c_int32 * 6)()
+    assert U.uf_resolve_bc(ctypes.byref(c), out) == 0
+    assert list(out) == expect
+
+
+def test_library_resolve_bc_explicit_and_errors():
+    import ctypes
+    import math
+    import paper_2204_01117_amd as U
+    from uf_layouts import default_config
+    out = (ctypes.c_int32 * 6)()
+    c, _ = U.make_config(default_config(8, 6, 4, 1.0, wind_dir_deg=45.0, bc=[1, -1, 2, -1, 3, -1]))
+    assert U.uf_resolve_bc(ctypes.byref(c), out) == 0 and list(out) == [1, 1, 2, 1, 3, 3]
+    c, _ = U.make_config(default_config(8, 6, 4, 1.0, wind_dir_deg=math.degrees(math.acos(1e-9))))
+    assert U.uf_resolve_bc(ctypes.byref(c), out) == 0 and out[0] == 0
+    c, _ = U.make_config(default_config(8, 6, 4, 1.0, wind_dir_deg=math.degrees(math.acos(1e-13))))
+    assert U.uf_resolve_bc(ctypes.byref(c), out) == 0 and out[0] == 1
+    c, _ = U.make_config(default_config(8, 6, 4, 1.0, wind_dir_deg=float("nan")))
+    assert U.uf_resolve_bc(ctypes.byref(c), out) == 1
+    assert U.uf_resolve_bc(None, out) == 1
