@@ -16,6 +16,7 @@ from .configs import (BC_AUTO, BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP,
                       default_config, preset, PRESETS)
 from .porosity import (Box, Cylinder, porosity_field, random_city,
                        preset_porosity)
+from .fields import smooth_noise, perturbed_state
 from .meshes import (box_mesh, prism_mesh, ring_mesh, uv_sphere_mesh, meshes_of,
                      city_meshes)
 
