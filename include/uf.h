@@ -29,6 +29,7 @@
 #ifndef UF_H
 #define UF_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -43,7 +44,7 @@ typedef enum {
   UF_ENOMEM = 2,      /* device allocation failed                               */
   UF_EDEVICE = 3,     /* a HIP runtime call failed                              */
   UF_ENOCONV = 4,     /* pressure CG stopped at cg_maxit; the step completed    */
-  UF_ENONFINITE = 5,  /* a NaN/Inf appeared in the pressure solve; step completed */
+  UF_ENONFINITE = 5,  /* a NaN/Inf appeared in the state; the step completed   */
   UF_ESTATE = 6,      /* call not valid in the handle's current state          */
   UF_ENOTIMPL = 7     /* entry point declared but not implemented in this version */
 } uf_status;
@@ -102,6 +103,17 @@ typedef struct {
   int32_t cg_criterion;
   int32_t stages;               /* UF_STAGE_* mask                              */
   void* stream;                 /* hipStream_t used for all work; NULL = null stream */
+  /* Device allocator of every buffer the grid owns (state fields, the
+   * pressure solve's vectors and partial sums, multigrid levels, the adjoint
+   * workspace): alloc(bytes, alloc_ctx) returns device memory of the current
+   * device usable on `stream`, or NULL (the call then fails with UF_ENOMEM);
+   * free(ptr, alloc_ctx) releases it, from uf_destroy_grid after the stream
+   * has been synchronised.  Set both or neither; NULL means hipMalloc and
+   * hipFree.  A framework's caching allocator (PyTorch's) plugs in here, so
+   * the grid's memory is pooled and accounted with the caller's tensors. */
+  void* (*alloc)(size_t bytes, void* alloc_ctx);
+  void (*free)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
 } uf_config;
 
 typedef struct {
@@ -109,9 +121,22 @@ typedef struct {
   int32_t cg_iters_total;       /* summed over the steps of the call            */
   double cg_rel_residual;       /* ||r|| / ||b|| at exit of the last solve      */
   int32_t converged;            /* 1 if every solve of the call converged       */
-  int32_t nonfinite;            /* 1 if a NaN/Inf was seen in a solve           */
+  int32_t nonfinite;            /* 1 if a NaN/Inf was seen in a solve, or in the
+                                   velocity the drag stage wrote or the k, omega
+                                   the k-omega update wrote (see uf_step)       */
   float ms;                     /* wall time of the call on the stream          */
   int32_t cg_iters_max;         /* largest per-step CG iteration count of the call */
+  /* Diagnostics of the state at the end of the call (one extra pass over the
+   * grid, made only when stats are requested): */
+  double max_div;               /* max over cells of |div_h u| (1/s): the
+                                   projection's residual divergence             */
+  double max_cfl;               /* max over cells of dt sum_d |u_d| / h_d with
+                                   cell-centre velocities: the stability number
+                                   of the upwind k-omega advection (Sec. 3 time
+                                   step restriction)                            */
+  double nut_clip_frac;         /* fraction of cells whose eddy viscosity sits
+                                   at the limiter nu_max - nu (Sec. 3 viscosity
+                                   limiter); 0 without the k-omega model       */
 } uf_step_stats;
 
 /* Create a grid and its state.  The initial state has the inflow profile on
@@ -247,7 +272,12 @@ int64_t uf_field_extent(const uf_config* cfg, int32_t field, int32_t dims[3]);
  * been observed to finish; later kernels may still be in flight unless
  * stats is non-NULL, which synchronises and fills it.  Returns UF_ENOCONV or
  * UF_ENONFINITE if some solve did not converge or saw a non-finite value;
- * the state has advanced in either case. */
+ * the state has advanced in either case.  The drag and k-omega stages also
+ * raise a device flag when they write a NaN/Inf; it is read with each solve's
+ * status and, with stats, at the end of the call (without stats, a flag the
+ * last step's k-omega update raised is reported by the next call).  The flag
+ * stays set, and every uf_step returns UF_ENONFINITE, until uf_set_field or
+ * uf_set_porosity overwrites the state. */
 uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats);
 
 /* Advance n independent grids by nsteps each (several cases at once: the

@@ -25,12 +25,14 @@ class uf_config(ctypes.Structure):
         ("precond", c_int32), ("ai_omega", c_double), ("cg_tol", c_double),
         ("cg_maxit", c_int32), ("cg_criterion", c_int32), ("stages", c_int32),
         ("stream", c_void_p),
+        ("alloc", c_void_p), ("free", c_void_p), ("alloc_ctx", c_void_p),
     ]
 
 
 class uf_step_stats(ctypes.Structure):
     _fields_ = [("cg_iters", c_int32), ("cg_iters_total", c_int32), ("cg_rel_residual", c_double),
-                ("converged", c_int32), ("nonfinite", c_int32), ("ms", c_float), ("cg_iters_max", c_int32)]
+                ("converged", c_int32), ("nonfinite", c_int32), ("ms", c_float), ("cg_iters_max", c_int32),
+                ("max_div", c_double), ("max_cfl", c_double), ("nut_clip_frac", c_double)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -163,7 +165,7 @@ def make_config(cfg, stream=None):
     Returns (struct, keepalive) -- keep the second alive while the struct is used."""
     c = uf_config()
     for name, typ in uf_config._fields_:
-        if name in ("bc", "inflow_profile", "stream", "dtype"):
+        if name in ("bc", "inflow_profile", "stream", "dtype", "alloc", "free", "alloc_ctx"):
             continue
         setattr(c, name, cfg[name])
     dt = cfg["dtype"]
@@ -176,3 +178,23 @@ def make_config(cfg, stream=None):
         c.inflow_profile = ctypes.cast(keep, POINTER(c_double))
     c.stream = stream
     return c, keep
+
+
+# Device allocator callbacks of uf_config (alloc, free).
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+def torch_allocator(device, stream):
+    """(alloc, free) callbacks that take the grid's memory from PyTorch's
+    caching allocator on ``device`` for ``stream`` (a torch.cuda.Stream).
+    Keep the returned pair alive as long as the grid."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)

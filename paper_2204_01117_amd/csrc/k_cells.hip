@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T*
                                                            const T* __restrict__ V, const T* __restrict__ W,
                                                            const T* __restrict__ K0, const T* __restrict__ W0,
                                                            T* __restrict__ K1, T* __restrict__ W1,
-                                                           T* __restrict__ NUT, int update_kw) {
+                                                           T* __restrict__ NUT, int update_kw, int* nf) {
   const Layout& L = P.L;
   UF_CELL_THREAD(L);
   const long long SX = L.SX, PZ = L.PZ;
@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T*
   T wn = ww + P.dt * (-adv(W0) + T(2 * kAlpha) * S2 - T(kBeta) * ww * ww + (P.nu + T(kSigma) * nut) * lap(W0));
   kn = nmax(kn, P.k_min);
   wn = nmax(wn, P.w_min);
+  if (!(isfinite(kn) && isfinite(wn))) *nf = 1;   // every writer stores 1: no atomic needed
   const T nut_new = nmin(nmax(kn / nmax(wn, lim), T(0)), P.cap);
   store_cell(K1, P, i, j, k, kn, true, P.k_in);
   store_cell(W1, P, i, j, k, wn, true, P.w_in);
@@ -251,7 +252,66 @@ void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, 
                  void* NUT, int update_kw) {
   TimedLaunch tl(g, UF_TK_TURB);
   launch_k(g, k_turbulence<T>, cell_grid(P.L), dim3(kCellBlock), P, (const T*)Q[0],
-                     (const T*)Q[1], (const T*)Q[2], (const T*)K0, (const T*)W0, (T*)K1, (T*)W1, (T*)NUT, update_kw);
+                     (const T*)Q[1], (const T*)Q[2], (const T*)K0, (const T*)W0, (T*)K1, (T*)W1, (T*)NUT, update_kw,
+                     nf_word(g));
+}
+
+// Diagnostics of a state, one partial per block and quantity: the largest
+// |div_h u| over the cells, the largest dt sum_d |u_d| / h_d with the
+// cell-centre velocity (the stability number of the upwind k-omega
+// advection), and the number of cells whose eddy viscosity sits at the cap.
+// NaN propagates into the maxima.
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_diag(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
+                                                     const T* __restrict__ W, const T* __restrict__ NUT, int turb,
+                                                     double* __restrict__ part) {
+  const Layout& L = P.L;
+  const long long n = (long long)L.nx * L.ny * L.nz;
+  double mdiv = 0.0, mcfl = 0.0, clip = 0.0;
+  const double ih0 = 1.0 / (double)P.h[0], ih1 = 1.0 / (double)P.h[1], ih2 = 1.0 / (double)P.h[2];
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(c % L.nz);
+    const long long r = c / L.nz;
+    const int j = (int)(r % L.ny);
+    const int i = (int)(r / L.ny);
+    const long long o = L.at(i, j, k);
+    const double u0 = U[o], u1 = U[o + L.SX], v0 = V[o], v1 = V[o + L.PZ], w0 = W[o], w1 = W[o + 1];
+    const double div = (u1 - u0) * ih0 + (v1 - v0) * ih1 + (w1 - w0) * ih2;
+    mdiv = nmax(fabs(div), mdiv);
+    const double cfl = (double)P.dt * (0.5 * fabs(u0 + u1) * ih0 + 0.5 * fabs(v0 + v1) * ih1 + 0.5 * fabs(w0 + w1) * ih2);
+    mcfl = nmax(cfl, mcfl);
+    if (turb && NUT[o] >= P.cap) clip += 1.0;
+  }
+  __shared__ double sh[3][kCellBlock / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    mdiv = nmax(__shfl_xor(mdiv, o, 64), mdiv);
+    mcfl = nmax(__shfl_xor(mcfl, o, 64), mcfl);
+    clip += __shfl_xor(clip, o, 64);
+  }
+  if (lane == 0) {
+    sh[0][wv] = mdiv;
+    sh[1][wv] = mcfl;
+    sh[2][wv] = clip;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kCellBlock / 64; ++q) {
+      mdiv = nmax(sh[0][q], mdiv);
+      mcfl = nmax(sh[1][q], mcfl);
+      clip += sh[2][q];
+    }
+    part[blockIdx.x] = mdiv;
+    part[kDiagBlocks + blockIdx.x] = mcfl;
+    part[2 * kDiagBlocks + blockIdx.x] = clip;
+  }
+}
+
+template <class T>
+void launch_diag(Grid& g, const Params<T>& P) {
+  const int turb = g.cfg.turb_model == UF_TURB_KOMEGA;
+  hipLaunchKernelGGL(k_diag<T>, dim3(kDiagBlocks), dim3(kCellBlock), 0, g.stream, P, (const T*)g.Q[g.cur][0],
+                     (const T*)g.Q[g.cur][1], (const T*)g.Q[g.cur][2], (const T*)g.NUT, turb, g.diag);
 }
 
 template <class T>
@@ -299,6 +359,7 @@ template void launch_region_speed<double>(Grid&, const int[6], double*, int);
 #define UF_INST(T)                                                                                            \
   template void launch_turb<T>(Grid&, const Params<T>&, void* const[3], const void*, const void*, void*, void*, \
                                void*, int);                                                                 \
+  template void launch_diag<T>(Grid&, const Params<T>&);                                                     \
   template void launch_porosity<T>(Grid&, const Params<T>&, const void*);                                    \
   template void launch_cell_bc<T>(Grid&, const Params<T>&, void*, int, double);                              \
   template void launch_pack<T>(Grid&, const Params<T>&, const void*, void*, int, int);                       \

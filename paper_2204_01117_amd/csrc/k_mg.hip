@@ -994,14 +994,14 @@ static MgLvl<T> mg_level(const Grid& g, int l) {
 
 void mg_free(Grid& g) {
   for (size_t l = 1; l < g.mg.size(); ++l) {
-    if (g.mg[l].r) (void)hipFree(g.mg[l].r);
-    if (g.mg[l].x) (void)hipFree(g.mg[l].x);
-    if (g.mg[l].t) (void)hipFree(g.mg[l].t);
+    gfree(g, g.mg[l].r);
+    gfree(g, g.mg[l].x);
+    gfree(g, g.mg[l].t);
   }
   g.mg.clear();
-  if (g.mg_cinv) (void)hipFree(g.mg_cinv);
+  gfree(g, g.mg_cinv);
   g.mg_cinv = nullptr;
-  if (g.mg_table) (void)hipFree(g.mg_table);
+  gfree(g, g.mg_table);
   g.mg_table = nullptr;
 }
 
@@ -1104,8 +1104,8 @@ void mg_setup(Grid& g) {
     }
     const size_t bytes = (size_t)(C.L.nx + 3) * C.L.SX * es;
     for (void** q : {&C.r, &C.x, &C.t}) {
-      if (hipMalloc(q, bytes) != hipSuccess) throw HipError("hipMalloc failed (multigrid level)");
-      UF_HIP_CHECK(hipMemset(*q, 0, bytes));
+      *q = galloc(g, bytes);
+      UF_HIP_CHECK(hipMemsetAsync(*q, 0, bytes, g.stream));
     }
     g.mg.push_back(C);
   }
@@ -1132,14 +1132,14 @@ void mg_setup(Grid& g) {
   {
     std::vector<MgLvl<T>> tab(nl);
     for (int l = 0; l < nl; ++l) tab[l] = mg_level<T>(g, l);
-    UF_HIP_CHECK(hipMalloc(&g.mg_table, tab.size() * sizeof(MgLvl<T>)));
+    g.mg_table = galloc(g, tab.size() * sizeof(MgLvl<T>));
     UF_HIP_CHECK(hipMemcpy(g.mg_table, tab.data(), tab.size() * sizeof(MgLvl<T>), hipMemcpyHostToDevice));
   }
   if (nl > 1) {
     std::vector<double> inv;
     if (dense_inverse(last, g.bc, inv)) {
       std::vector<T> tv(inv.begin(), inv.end());
-      UF_HIP_CHECK(hipMalloc(&g.mg_cinv, tv.size() * es));
+      g.mg_cinv = galloc(g, tv.size() * es);
       UF_HIP_CHECK(hipMemcpy(g.mg_cinv, tv.data(), tv.size() * es, hipMemcpyHostToDevice));
     }
   }

@@ -111,12 +111,18 @@ __device__ __forceinline__ T drag_value(const Params<T>& P, const T* __restrict_
 template <class T>
 __global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
                                                      const T* __restrict__ W, const T* __restrict__ Cc,
-                                                     T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+                                                     T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo,
+                                                     int* nf) {
   UF_FACE_THREAD(P.L);
   const long long o = P.L.at(i, j, k);
   const T a0 = drag_value<0>(P, U, V, W, Cc, o);
   const T a1 = drag_value<1>(P, U, V, W, Cc, o);
   const T a2 = drag_value<2>(P, U, V, W, Cc, o);
+  // a NaN/Inf in an owned face raises the state's non-finite flag (every
+  // writer stores 1, so the race is benign)
+  if ((owns_face<0, T>(P.L, i, j, k) && !isfinite(a0)) || (owns_face<1, T>(P.L, i, j, k) && !isfinite(a1)) ||
+      (owns_face<2, T>(P.L, i, j, k) && !isfinite(a2)))
+    *nf = 1;
   finish_face<0>(P, Uo, i, j, k, a0);
   finish_face<1>(P, Vo, i, j, k, a1);
   finish_face<2>(P, Wo, i, j, k, a2);
@@ -193,7 +199,7 @@ template <class T>
 void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
   TimedLaunch tl(g, UF_TK_DRAG);
   launch_k(g, k_drag<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
-                     (const T*)Qin[2], (const T*)g.C, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
+                     (const T*)Qin[2], (const T*)g.C, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2], nf_word(g));
 }
 
 template <class T>

@@ -80,6 +80,24 @@ Params<T> make_params(const Grid& g) {
   return P;
 }
 
+void* galloc(Grid& g, size_t bytes) {
+  void* p = nullptr;
+  if (g.cfg.alloc) {
+    p = g.cfg.alloc(bytes, g.cfg.alloc_ctx);
+    if (!p) throw HipError("the grid's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    return p;
+  }
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw HipError(std::string("hipMalloc: ") + hipGetErrorString(e));
+  return p;
+}
+
+void gfree(Grid& g, void* p) {
+  if (!p) return;
+  if (g.cfg.free) g.cfg.free(p, g.cfg.alloc_ctx);
+  else (void)hipFree(p);
+}
+
 }  // namespace uf
 
 using namespace uf;
@@ -176,19 +194,13 @@ std::string validate(const uf_config& c) {
   if (c.cg_maxit < 1 || c.cg_maxit > 1000000) return "cg_maxit must be in [1, 1e6]";
   if (c.cg_criterion != 0 && c.cg_criterion != 1) return "cg_criterion must be 0 or 1";
   if (c.stages < 0 || c.stages > UF_STAGE_ALL) return "unknown stage bits";
+  if ((c.alloc == nullptr) != (c.free == nullptr)) return "set both alloc and free, or neither";
   return "";
 }
 
-void* dalloc(size_t bytes) {
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) throw HipError(std::string("hipMalloc: ") + hipGetErrorString(e));
-  return p;
-}
-
 void free_grid(Grid* g) {
-  auto f = [](void*& p) {
-    if (p) (void)hipFree(p);
+  auto f = [g](void*& p) {
+    if (p) gfree(*g, p);
     p = nullptr;
   };
   for (auto& s : g->Q)
@@ -238,6 +250,11 @@ void free_grid(Grid* g) {
   void* pf = g->flag;
   f(pf);
   g->flag = nullptr;
+  void* pd = g->diag;
+  f(pd);
+  g->diag = nullptr;
+  if (g->diag_host) (void)hipHostFree(g->diag_host);
+  g->diag_host = nullptr;
   if (g->st_host) (void)hipHostFree(g->st_host);
   if (g->flag_host) (void)hipHostFree(g->flag_host);
   g->st_host = nullptr;
@@ -264,6 +281,7 @@ struct SolveResult {
   int iters = 0;
   double rel = 0;
   int noconv = 0, nonfinite = 0;
+  int nf_state = 0;   // the state's non-finite flag as of this solve's status
 };
 
 // Pressure solve: r0 = b - A x0 and the stopping threshold, the first
@@ -310,6 +328,7 @@ SolveResult solve_end(Grid& g, const Params<T>& P) {
   res.rel = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
   res.noconv = s.noconv;
   res.nonfinite = s.nonfinite;
+  res.nf_state = s.nf_state;
   g.last_iters = s.iter;
   return res;
 }
@@ -322,6 +341,7 @@ SolveResult solve_pressure(Grid& g, const Params<T>& P, void* const Qs[3], const
 
 struct StepAccum {
   int iters_total = 0, last_iters = 0, max_iters = 0, noconv = 0, nonfinite = 0;
+  int nf_state = 0;   // non-finite value written by the drag or k-omega stage
   double last_rel = 0;
 };
 
@@ -370,6 +390,7 @@ void step_end(Grid& g, const Params<T>& P, StepAccum& acc) {
       acc.last_rel = r.rel;
       acc.noconv |= r.noconv;
       acc.nonfinite |= r.nonfinite;
+      acc.nf_state |= r.nf_state;
       const int out = free_set(g, -1);
       launch_project<T>(g, P, g.Q[g.cur], g.Q[out]);
       g.cur = out;
@@ -392,14 +413,37 @@ void run_steps(Grid& g, int nsteps, StepAccum& acc) {
   }
 }
 
-void fill_stats(uf_step_stats* stats, const StepAccum& acc, float ms) {
+// Enqueue the end-of-call diagnostics and the copy of the non-finite flag
+// (read by finish_stats once the stream has reached them).
+void post_diag(Grid& g) {
+  if (g.esize == 4) launch_diag<float>(g, make_params<float>(g));
+  else launch_diag<double>(g, make_params<double>(g));
+  check_launch();
+  UF_HIP_CHECK(hipMemcpyAsync(g.diag_host, g.diag, 3 * kDiagBlocks * sizeof(double), hipMemcpyDeviceToHost,
+                              g.stream));
+  UF_HIP_CHECK(hipMemcpyAsync(g.flag_host, nf_word(g), sizeof(int), hipMemcpyDeviceToHost, g.stream));
+}
+
+void fill_stats(uf_step_stats* stats, StepAccum& acc, float ms, const Grid& g) {
+  // the stream has passed post_diag: the partials and the flag are on the host
+  double mdiv = 0, mcfl = 0, clip = 0;
+  for (int b = 0; b < kDiagBlocks; ++b) {
+    const double d = g.diag_host[b], c = g.diag_host[kDiagBlocks + b];
+    mdiv = (d != d || d > mdiv) ? d : mdiv;
+    mcfl = (c != c || c > mcfl) ? c : mcfl;
+    clip += g.diag_host[2 * kDiagBlocks + b];
+  }
+  acc.nf_state |= *g.flag_host;
   stats->cg_iters = acc.last_iters;
   stats->cg_iters_total = acc.iters_total;
   stats->cg_rel_residual = acc.last_rel;
   stats->converged = !(acc.noconv || acc.nonfinite);
-  stats->nonfinite = acc.nonfinite;
+  stats->nonfinite = acc.nonfinite || acc.nf_state;
   stats->ms = ms;
   stats->cg_iters_max = acc.max_iters;
+  stats->max_div = mdiv;
+  stats->max_cfl = mcfl;
+  stats->nut_clip_frac = clip / ((double)g.L.nx * g.L.ny * g.L.nz);
 }
 
 template <class T>
@@ -464,23 +508,23 @@ void adjoint_alloc(Grid& g) {
   if (g.XA) return;
   const size_t bytes = g.nelem * g.esize;
   for (auto& set : g.AS)
-    for (auto& q : set) q = dalloc(bytes);
+    for (auto& q : set) q = galloc(g, bytes);
   for (auto& set : g.AA)
-    for (auto& q : set) q = dalloc(bytes);
+    for (auto& q : set) q = galloc(g, bytes);
   for (auto& set : g.AV)
     for (auto& q : set) {
-      q = dalloc(bytes);
+      q = galloc(g, bytes);
       UF_HIP_CHECK(hipMemsetAsync(q, 0, bytes, g.stream));
     }
   for (auto& set : g.AU)
-    for (auto& q : set) q = dalloc(bytes);
-  for (auto& q : g.AT) q = dalloc(bytes);
+    for (auto& q : set) q = galloc(g, bytes);
+  for (auto& q : g.AT) q = galloc(g, bytes);
   UF_HIP_CHECK(hipMemsetAsync(g.AT[9], 0, bytes, g.stream));   // recompute pressure: zero start and ghosts
-  g.Cbar = dalloc(bytes);
-  g.XA = dalloc(bytes);
+  g.Cbar = galloc(g, bytes);
+  g.XA = galloc(g, bytes);
   UF_HIP_CHECK(hipMemsetAsync(g.XA, 0, bytes, g.stream));   // zero start and zero ghosts
   const size_t tab = 2 * (size_t)(g.L.nz + 2) * g.esize;
-  g.inflow0 = dalloc(tab);
+  g.inflow0 = galloc(g, tab);
   UF_HIP_CHECK(hipMemsetAsync(g.inflow0, 0, tab, g.stream));
 }
 
@@ -729,22 +773,23 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
   for (void** q : {&g->NUT, &g->C, &g->X, &g->R, &g->R2, &g->Z, &g->D[0], &g->D[1], &g->Qv}) bufs.push_back(q);
   try {
     for (void** q : bufs) {
-      *q = dalloc(bytes);
+      *q = galloc(*g, bytes);
       UF_HIP_CHECK(hipMemsetAsync(*q, 0, bytes, g->stream));
     }
-    g->PHI = dalloc((size_t)cfg->nx * cfg->ny * cfg->nz * g->esize);
-    g->inflow = dalloc(2 * (cfg->nz + 2) * g->esize);
+    g->PHI = galloc(*g, (size_t)cfg->nx * cfg->ny * cfg->nz * g->esize);
+    g->inflow = galloc(*g, 2 * (cfg->nz + 2) * g->esize);
     const CgLaunch cl = cg_launch(L);
     g->cg_nb = (size_t)cl.gx * cl.gy;
     g->cg_nb_rz = cfg->precond == UF_PC_MG ? mg_fine_blocks(L) : g->cg_nb;
     g->cg_nb_dq = (size_t)ad_launch(L).blocks;
     g->cg_nb_rr = g->cg_nb;
-    g->flags = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
-    g->exec = (int*)dalloc(sizeof(int) * (cfg->cg_maxit + 2));
+    g->flags = (int*)galloc(*g, sizeof(int) * (cfg->cg_maxit + 2));
+    g->exec = (int*)galloc(*g, sizeof(int) * (cfg->cg_maxit + 2));
     UF_HIP_CHECK(hipMemsetAsync(g->flags, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
     UF_HIP_CHECK(hipMemsetAsync(g->exec, 0, sizeof(int) * (cfg->cg_maxit + 2), g->stream));
-    g->st = (CgState*)dalloc(sizeof(CgState));
-    g->flag = (int*)dalloc(sizeof(int));
+    g->st = (CgState*)galloc(*g, sizeof(CgState));
+    g->flag = (int*)galloc(*g, sizeof(int));
+    g->diag = (double*)galloc(*g, 3 * kDiagBlocks * sizeof(double));
   } catch (const HipError& e) {
     free_grid(g);
     delete g;
@@ -753,6 +798,7 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
   UF_HIP_CHECK(hipMemsetAsync(g->st, 0, sizeof(CgState), g->stream));
   UF_HIP_CHECK(hipHostMalloc((void**)&g->st_host, sizeof(CgState), hipHostMallocDefault));
   UF_HIP_CHECK(hipHostMalloc((void**)&g->flag_host, sizeof(int), hipHostMallocDefault));
+  UF_HIP_CHECK(hipHostMalloc((void**)&g->diag_host, 3 * kDiagBlocks * sizeof(double), hipHostMallocDefault));
   UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_status, hipEventDisableTiming));
   UF_HIP_CHECK(hipEventCreate(&g->ev0));
   UF_HIP_CHECK(hipEventCreate(&g->ev1));
@@ -773,7 +819,7 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     g->mg_fused = fused > 0;
     g->cg_nb_rr = std::max(g->cg_nb, fused);
     g->part_stride = std::max(std::max(g->cg_nb, g->cg_nb_rr), std::max(g->cg_nb_rz, g->cg_nb_dq));
-    g->partials = (double*)dalloc(S_NSLOT_HOST * g->part_stride * sizeof(double));
+    g->partials = (double*)galloc(*g, S_NSLOT_HOST * g->part_stride * sizeof(double));
     UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->part_stride * sizeof(double), g->stream));
   }
   if (g->esize == 4) init_state<float>(*g);
@@ -902,6 +948,7 @@ uf_status uf_set_porosity(uf_grid g, const void* phi_dev) {
   if (g->esize == 4) launch_porosity<float>(*g, make_params<float>(*g), phi_dev);
   else launch_porosity<double>(*g, make_params<double>(*g), phi_dev);
   check_launch();
+  UF_HIP_CHECK(hipMemsetAsync(nf_word(*g), 0, sizeof(int), g->stream));
   return UF_OK;
   UF_GUARD_END
 }
@@ -931,6 +978,7 @@ uf_status uf_set_field(uf_grid g, int32_t field, const void* src) {
   if (g->esize == 4) go(float());
   else go(double());
   check_launch();
+  UF_HIP_CHECK(hipMemsetAsync(nf_word(*g), 0, sizeof(int), g->stream));
   return UF_OK;
   UF_GUARD_END
 }
@@ -974,12 +1022,14 @@ uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats) {
   else run_steps<double>(*g, nsteps, acc);
   UF_HIP_CHECK(hipEventRecord(g->ev1, g->stream));
   if (stats) {
-    UF_HIP_CHECK(hipEventSynchronize(g->ev1));
+    post_diag(*g);
+    UF_HIP_CHECK(hipStreamSynchronize(g->stream));
     float ms = 0;
     UF_HIP_CHECK(hipEventElapsedTime(&ms, g->ev0, g->ev1));
-    fill_stats(stats, acc, ms);
+    fill_stats(stats, acc, ms, *g);
   }
   if (acc.nonfinite) return fail(UF_ENONFINITE, "non-finite value in the pressure solve");
+  if (acc.nf_state) return fail(UF_ENONFINITE, "non-finite value written by the drag or k-omega stage");
   if (acc.noconv) return fail(UF_ENOCONV, "pressure CG reached cg_maxit");
   return UF_OK;
   UF_GUARD_END
@@ -1033,16 +1083,21 @@ uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step
   for (const auto& e : errs)
     if (!e.empty()) return fail(UF_EDEVICE, e);
   for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(grids[i]->ev1, grids[i]->stream));
-  if (stats)
+  if (stats) {
+    for (int i = 0; i < n; ++i) post_diag(*grids[i]);
     for (int i = 0; i < n; ++i) {
-      UF_HIP_CHECK(hipEventSynchronize(grids[i]->ev1));
+      UF_HIP_CHECK(hipStreamSynchronize(grids[i]->stream));
       float ms = 0;
       UF_HIP_CHECK(hipEventElapsedTime(&ms, grids[i]->ev0, grids[i]->ev1));
-      fill_stats(&stats[i], acc[i], ms);
+      fill_stats(&stats[i], acc[i], ms, *grids[i]);
     }
+  }
   for (int i = 0; i < n; ++i) {
     if (acc[i].nonfinite)
       return fail(UF_ENONFINITE, "non-finite value in the pressure solve of batch entry " + std::to_string(i));
+    if (acc[i].nf_state)
+      return fail(UF_ENONFINITE, "non-finite value written by the drag or k-omega stage of batch entry " +
+                                     std::to_string(i));
     if (acc[i].noconv)
       return fail(UF_ENOCONV, "pressure CG reached cg_maxit in batch entry " + std::to_string(i));
   }
@@ -1057,7 +1112,7 @@ uf_status uf_pressure_solve(uf_grid g, const void* b_dev, void* x_dev, uf_step_s
   // the solve runs in the grid's pressure array: keep the state's pressure
   // and the warm-start chunk length, and put them back afterwards
   const size_t bytes = g->nelem * g->esize;
-  if (!g->Xsave) g->Xsave = dalloc(bytes);
+  if (!g->Xsave) g->Xsave = galloc(*g, bytes);
   UF_HIP_CHECK(hipMemcpyAsync(g->Xsave, g->X, bytes, hipMemcpyDeviceToDevice, g->stream));
   const int last_iters = g->last_iters;
   auto go = [&](auto tag) {
@@ -1122,7 +1177,7 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
       return fail(UF_EINVAL, "non-finite or negative plane objective parameter");
     UF_GUARD_BEGIN
     constexpr int kBlocks = 256;
-    if (!g->obj_part) g->obj_part = (double*)dalloc(sizeof(double) * kBlocks * UF_MAX_REGIONS);
+    if (!g->obj_part) g->obj_part = (double*)galloc(*g, sizeof(double) * kBlocks * UF_MAX_REGIONS);
     const double zc = spec->z_plane / dz - 0.5;
     const int k0 = std::min(std::max((int)std::floor(zc), 0), nz - 2);
     const double t = zc - k0;
@@ -1167,7 +1222,7 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
     }
   UF_GUARD_BEGIN
   constexpr int kBlocks = 256;
-  if (!g->obj_part) g->obj_part = (double*)dalloc(sizeof(double) * kBlocks * UF_MAX_REGIONS);
+  if (!g->obj_part) g->obj_part = (double*)galloc(*g, sizeof(double) * kBlocks * UF_MAX_REGIONS);
   std::vector<int> nb(nr);
   for (int r = 0; r < nr; ++r) {
     const int* b = spec->boxes + 6 * r;
@@ -1206,7 +1261,7 @@ uf_status uf_objective(uf_grid g, const uf_objective_spec* spec, double* J_host,
   *J_host = J;
   if (dJ_dstate_dev) {
     const size_t meta = UF_MAX_REGIONS * (6 * sizeof(int) + sizeof(double));
-    if (!g->obj_meta) g->obj_meta = dalloc(meta);
+    if (!g->obj_meta) g->obj_meta = galloc(*g, meta);
     double* coef_dev = (double*)g->obj_meta;
     int* boxes_dev = (int*)(coef_dev + UF_MAX_REGIONS);
     UF_HIP_CHECK(hipMemcpyAsync(coef_dev, coef.data(), nr * sizeof(double), hipMemcpyHostToDevice, g->stream));

@@ -25,7 +25,7 @@ struct CgState {
   int zero_rhs;      // b == 0: the solution is 0
   int maxit;
   int criterion;
-  int pad;
+  int nf_state;      // 1 once the drag or k-omega stage wrote a NaN/Inf (sticky; the solves leave it)
 };
 
 // One level of the multigrid hierarchy (level 0 is the fine grid).
@@ -106,6 +106,8 @@ struct Grid {
   CgState* st_host = nullptr;  // pinned
   int* flag = nullptr;       // device int used by validation kernels
   int* flag_host = nullptr;  // pinned
+  double* diag = nullptr;    // [3][kDiagBlocks] partials of the end-of-call diagnostics
+  double* diag_host = nullptr;  // pinned copy
   hipEvent_t ev_status = nullptr, ev0 = nullptr, ev1 = nullptr;
   std::vector<MgLevel> mg;
   int mg_lt = 0;                // first level of the single-workgroup kernel
@@ -128,6 +130,14 @@ struct Grid {
   double k_in = 0, w_in = 0, nu_max = 0;
 };
 
+// Device memory of the grid: its configured allocator, else hipMalloc.
+void* galloc(Grid& g, size_t bytes);
+void gfree(Grid& g, void* p);
+
+// End-of-call diagnostics (uf_step_stats.max_div, max_cfl, nut_clip_frac).
+constexpr int kDiagBlocks = 512;
+template <class T> void launch_diag(Grid& g, const Params<T>& P);
+
 // Residual buffer after m CG updates.
 inline void* resid(const Grid& g, int m) { return (m & 1) ? g.R2 : g.R; }
 
@@ -139,6 +149,8 @@ template <class T> void launch_drag(Grid& g, const Params<T>& P, void* const Qin
 template <class T> void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
 template <class T> void launch_face_bc(Grid& g, const Params<T>& P, void* q, int comp);
 template <class T> void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1, void* NUT, int update_kw);
+// device word the drag and k-omega kernels set on a non-finite output
+inline int* nf_word(Grid& g) { return &g.st->nf_state; }
 template <class T> void launch_cell_bc(Grid& g, const Params<T>& P, void* q, int use_inlet, double inlet_value);
 template <class T> void launch_porosity(Grid& g, const Params<T>& P, const void* phi);
 template <class T> void launch_pack(Grid& g, const Params<T>& P, const void* src_padded, void* dst, int field, int unpack);

@@ -10,7 +10,7 @@ class Grid:
     (see ``uf_layouts.default_config``).  All work is enqueued on torch's
     current stream of ``device``."""
 
-    def __init__(self, cfg, device="cuda:0", stream=None):
+    def __init__(self, cfg, device="cuda:0", stream=None, torch_memory=True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -21,6 +21,12 @@ class Grid:
         self.tstream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = self.tstream.cuda_stream
         c, keep = L.make_config(self.cfg, self.stream)
+        # the grid's buffers come from torch's caching allocator (uf_config
+        # alloc/free), unless torch_memory is False (then hipMalloc)
+        self._allocator = L.torch_allocator(self.device, self.tstream) if torch_memory else None
+        if self._allocator is not None:
+            c.alloc = ctypes.cast(self._allocator[0], c_void_p)
+            c.free = ctypes.cast(self._allocator[1], c_void_p)
         self._cstruct = c
         h = c_void_p()
         L.check(L.uf_create_grid(byref(c), byref(h)))

@@ -114,6 +114,10 @@ def _header_structs():
             decl = " ".join(decl.split())
             if not decl:
                 continue
+            fn = re.search(r"\(\*(\w+)\)\s*\(", decl)
+            if fn:                                   # a function pointer field
+                fields.append((fn.group(1), "fnptr", True, 1))
+                continue
             parts = decl.split(",")
             first = parts[0].split()
             typ = " ".join(first[:-1]).replace("const ", "")
@@ -184,3 +188,14 @@ def test_library_resolve_bc_explicit_and_errors():
     c, _ = U.make_config(default_config(8, 6, 4, 1.0, wind_dir_deg=float("nan")))
     assert U.uf_resolve_bc(ctypes.byref(c), out) == 1
     assert U.uf_resolve_bc(None, out) == 1
+
+
+def test_allocator_hook_needs_both_functions():
+    import paper_2204_01117_amd as U
+    from uf_layouts import default_config
+    c, _ = U.make_config(default_config(8, 6, 4, 2.0, dt=0.2))
+    fn = U._lib.ALLOC_FN(lambda n, ctx: 0)
+    c.alloc = ctypes.cast(fn, ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    assert U.uf_create_grid(ctypes.byref(c), ctypes.byref(h)) == 1
+    assert "alloc" in U.uf_last_error().decode() and not h.value
