@@ -1,33 +1,35 @@
 """Benchmark: cell-updates/s of the full RANS step (incl. the pressure solve).
 
-Workload: the 256x256x64 city (2 m cells, 40 buildings and 60 porous trees
-drawn from the seeded generator, log-law inflow of 6 m/s at 10 m along +x),
-FP32 with FP64 reductions, multigrid-preconditioned CG to a relative
-residual of 1e-6.  Inputs are resident on the GPU before the timed region.
+Workload (default): the 512x512x128 city (1 m cells, 200 buildings and 400
+porous trees drawn from the seeded generator, log-law inflow of 6 m/s at
+10 m from a seeded random direction), FP32 with FP64 reductions,
+multigrid-preconditioned CG to a relative residual of 1e-6.  Inputs are
+resident on the GPU before the timed region.  --workload C1 selects the
+256x256x64 city.
 
 Prints one JSON line:  value = cells x steps / seconds over K timed steps
 (bracketed by device synchronisation), the roofline figure of the kernel
 with the largest share of the step time, measured live with HIP events
-around each of its launches, and the FP64 oracle timed on this host on a
-bounded sample of the same workload.
+around each of its launches, the whole step's HBM traffic from the
+committed counter summary, and the FP64 oracle timed on this host on a
+bounded sample of the same workload (before the GPU is touched).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 Profiling helpers (the commands are recorded in the files they write):
-    python bench.py --traffic-probe
+    python bench.py --traffic-probe [--workload W]
         a few steps of the workload, then a plain copy of COPY_BYTES: the
         program run under rocprofv3 --pmc FETCH_SIZE and, separately,
         --pmc WRITE_SIZE (csv output under <dir>/fetch and <dir>/write)
-    python bench.py --traffic-summary <dir>
+    python bench.py --traffic-summary <dir> [--workload W]
         HBM bytes per launch of each kernel from those two runs, scaled by
         what the counters read for the copy, into
-        profiles/traffic_<kernel>_256x256x64.json
+        profiles/traffic_<kernel>_<grid>.json
     python bench.py --precond-study
         the pressure system of the workload solved with each preconditioner
         (iterations and solve time per case, one JSON line each)
-    python bench.py --stats-summary <dir> --command "<rocprofv3 command>"
-        profiles/kernels_256x256x64.md from a rocprofv3 --kernel-trace
-        --stats csv run
+    python bench.py --stats-summary <dir> --command "<rocprofv3 command>" --stats-out <name>
+        profiles/<name> from a rocprofv3 --kernel-trace --stats csv run
 """
 import argparse
 import csv
@@ -90,19 +92,16 @@ PROFILE_NAMES = [
 # Calibration copy of the counter runs: bytes read (and written) once.
 COPY_BYTES = 1 << 30
 
-# Oracle CPU baseline: PCG iterations its solver (AI1-preconditioned, FP64)
-# needs for one warm-started pressure solve of this workload at relative
-# residual 1e-6 (second step from the initial state; deterministic, so the
-# same on any host).
-ORACLE_WARM_ITERS = 507
+# Grid tag of each step workload (names of the counter and kernel summaries).
+GRID_TAG = {"C1": "256x256x64", "C2": "512x512x128", "slab": "64x512x128", "CP": "450x300x40"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name="C1"):
-    """C1: the 256x256x64 city (the default).  C2: the 512x512x128 city.
+def workload(name="C2"):
+    """C2: the 512x512x128 city (the default).  C1: the 256x256x64 city.
     slab: one GPU's share of C2 split eight ways along x (64x512x128, the
     first slab of C2's layout, with the domain's own side conditions where
     a split run would exchange halos)."""
@@ -138,11 +137,11 @@ def copy_ceiling_gbs(torch, nbytes=1 << 30, reps=5):
     return gbs
 
 
-def traffic_for(kernel, ncells):
+def traffic_for(kernel, tag):
     """HBM bytes per launch from the committed counter summary of this kernel
-    (profiles/traffic_<kernel>_256x256x64.json), or None when there is none
-    or the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_256x256x64.json" % kernel)
+    (profiles/traffic_<kernel>_<tag>.json), or None when there is none or
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, tag))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -151,12 +150,12 @@ def traffic_for(kernel, ncells):
     return rec.get("bytes_per_launch")
 
 
-def step_traffic(iters_per_step, ms_per_step, ncells):
+def step_traffic(iters_per_step, ms_per_step, ncells, tag):
     """HBM bytes of a whole step from the committed counter summary
-    (profiles/traffic_step_256x256x64.json) at this iteration count, with
-    the bandwidth they imply over the step's wall time; None when absent or
+    (profiles/traffic_step_<tag>.json) at this iteration count, with the
+    bandwidth they imply over the step's wall time; None when absent or
     stale."""
-    path = os.path.join(ROOT, "profiles", "traffic_step_256x256x64.json")
+    path = os.path.join(ROOT, "profiles", "traffic_step_%s.json" % tag)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -167,7 +166,7 @@ def step_traffic(iters_per_step, ms_per_step, ncells):
     gbs = meas / (ms_per_step / 1e3) / 1e9
     return {"bytes_per_step": meas, "alg_bytes_per_step": alg, "achieved_GBs": gbs,
             "alg_GBs": alg / (ms_per_step / 1e3) / 1e9, "frac": gbs / HBM_PEAK_GBS,
-            "source": "profiles/traffic_step_256x256x64.json"}
+            "source": "profiles/traffic_step_%s.json" % tag}
 
 
 # Source files that hold each measured kernel's device code (with the
@@ -241,12 +240,12 @@ def _copy_calibration(disp):
     return sum(big) / len(big), len(big)
 
 
-def traffic_probe():
+def traffic_probe(name):
     """The program profiled for the traffic counters: the workload for a
     few steps, then a plain device copy of COPY_BYTES (the calibration)."""
     import torch
     import paper_2204_01117_amd as U
-    _, phi, cfg = workload()
+    _, phi, cfg = workload(name)
     g = U.Grid(cfg, device="cuda:0")
     g.set_porosity(torch.as_tensor(phi))
     g.step(3)
@@ -261,11 +260,14 @@ def traffic_probe():
     log("traffic probe done: 6 steps, 3 copies of %d bytes" % COPY_BYTES)
 
 
-def traffic_summary(run_dir, command, out_dir=None):
-    """Counter records of every measured kernel and of the whole step from
-    the FETCH_SIZE and WRITE_SIZE runs under run_dir, written to out_dir
-    (default profiles/)."""
+def traffic_summary(run_dir, command, out_dir=None, name="C2"):
+    """Counter records of every measured kernel and of the whole step of
+    workload ``name`` from the FETCH_SIZE and WRITE_SIZE runs under run_dir,
+    written to out_dir (default profiles/)."""
     out_dir = out_dir or os.path.join(ROOT, "profiles")
+    tag = GRID_TAG[name]
+    _, _, wcfg = workload(name)
+    ncell = wcfg["nx"] * wcfg["ny"] * wcfg["nz"]
     fd = _dispatches(os.path.join(run_dir, "fetch"), "FETCH_SIZE")
     wd = _dispatches(os.path.join(run_dir, "write"), "WRITE_SIZE")
     c_fetch, n_fetch = _copy_calibration(fd)
@@ -291,13 +293,13 @@ def traffic_summary(run_dir, command, out_dir=None):
         fb = fetch[key] * 1024.0 / f_fetch
         wb = write[key] * 1024.0 / f_write
         out[bn] = {
-            "kernel": bn, "profiler_name": key[0].split("(")[0], "grid_size": key[1], "workload": "256x256x64",
+            "kernel": bn, "profiler_name": key[0].split("(")[0], "grid_size": key[1], "workload": tag,
             "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
             "fetch_kib_raw": fetch[key], "write_kib_raw": write[key],
             "calibration": {"copy_bytes": COPY_BYTES, "copies": [n_fetch, n_write],
                             "fetch_kib_raw": c_fetch, "write_kib_raw": c_write,
                             "fetch_factor": f_fetch, "write_factor": f_write},
-            "alg_bytes_per_launch": ALG_BYTES_PER_CELL[bn] * 256 * 256 * 64,
+            "alg_bytes_per_launch": ALG_BYTES_PER_CELL[bn] * ncell,
             "source_sha256": sources_hash(bn),
             "command": command,
         }
@@ -318,9 +320,8 @@ def traffic_summary(run_dir, command, out_dir=None):
         n = short(name)
         steps += n.startswith("k_advect_fwd")
         iters += n.startswith("k_cg_Ad")
-    ncell = 256 * 256 * 64
     step_rec = {
-        "workload": "256x256x64", "steps": steps, "cg_iterations": iters,
+        "workload": tag, "steps": steps, "cg_iterations": iters,
         "bytes_fixed_per_step": tot["step"] / max(steps, 1),
         "bytes_per_cg_iteration": tot["iter"] / max(iters, 1),
         "alg_bytes_fixed_per_step": ALG_FIXED_PER_CELL * ncell,
@@ -328,14 +329,14 @@ def traffic_summary(run_dir, command, out_dir=None):
         "calibration": {"fetch_factor": f_fetch, "write_factor": f_write},
         "source_sha256": sources_hash(), "command": command,
     }
-    with open(os.path.join(out_dir, "traffic_step_256x256x64.json"), "w") as f:
+    with open(os.path.join(out_dir, "traffic_step_%s.json" % tag), "w") as f:
         json.dump(step_rec, f, indent=1)
         f.write("\n")
     log("step traffic: %.3e B fixed per step (alg %.3e), %.3e B per CG iteration (alg %.3e)"
         % (step_rec["bytes_fixed_per_step"], step_rec["alg_bytes_fixed_per_step"],
            step_rec["bytes_per_cg_iteration"], step_rec["alg_bytes_per_cg_iteration"]))
     for bn, rec in out.items():
-        path = os.path.join(out_dir, "traffic_%s_256x256x64.json" % bn)
+        path = os.path.join(out_dir, "traffic_%s_%s.json" % (bn, tag))
         with open(path, "w") as f:
             json.dump(rec, f, indent=1)
             f.write("\n")
@@ -389,7 +390,7 @@ def precond_study():
     import torch
     import paper_2204_01117_amd as U
     from uf_layouts.configs import PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG
-    _, _, cfg = workload()
+    _, _, cfg = workload("C1")
     shape = (cfg["nx"], cfg["ny"], cfg["nz"])
     b = torch.tensor(np.random.default_rng(7).normal(size=shape), dtype=torch.float32, device="cuda:0")
     cases = [("CG", PC_NONE, 1.6), ("Jacobi", PC_JACOBI, 1.6), ("AI1", PC_AI1, 1.0), ("AI1", PC_AI1, 1.6),
@@ -413,61 +414,92 @@ def precond_study():
                               "converged": st["converged"], "grid": list(shape)}), flush=True)
 
 
-def cpu_baseline(phi, cfg, state):
-    """The FP64 oracle on a bounded sample of the same workload: from the
-    GPU's state, the oracle's advection, diffusion, drag and k-omega stages
-    once on the full grid and a fixed number of iterations of its
-    AI1-preconditioned CG on the full pressure system.  One step's time is
-    the stage time plus the per-iteration time x ORACLE_WARM_ITERS."""
-    import numpy as np
-    from oracle import OracleGrid
-    from oracle import step as S
-    from oracle.pressure import ai_preconditioner
+# The oracle's sample for the CPU baseline: one complete oracle step on x-slab
+# s (of 8) of the workload, a 1/8 share of its cells with the domain's own
+# side conditions (as the slab workload).  Set in the parent before the
+# worker processes are forked, so that they share it.
+_SAMPLE = {}
 
-    og = OracleGrid(dict(cfg, stages=31), solver="none")
-    og.set_porosity(phi)
-    for f, v in state.items():
-        og.set_field(f, v)
-    g = og.g
-    t0 = time.perf_counter()
-    Q = S.advect(g, og.Q)
-    Q = S.diffuse(g, Q, og.NUT, float(cfg["nu"]))
-    Q = S.drag(g, Q, og.C)
-    b = (-(cfg["rho"] / cfg["dt"]) * S.divergence(g, Q)).ravel()
-    t_local = time.perf_counter() - t0
-    A = og.pressure.A
-    M, _ = ai_preconditioner(A, cfg["ai_omega"])
-    x = og.p.ravel().copy()
-    r = b - A @ x
-    z = M @ r
-    d = z.copy()
-    rz = float(r @ z)
-    n_it = 150
-    t1 = time.perf_counter()
-    for _ in range(n_it):
-        q = A @ d
-        alpha = rz / float(d @ q)
-        x += alpha * d
-        r -= alpha * q
-        z = M @ r
-        rz_new = float(r @ z)
-        d = z + (rz_new / rz) * d
-        rz = rz_new
-    t_iter = (time.perf_counter() - t1) / n_it
-    t2 = time.perf_counter()
-    S.turbulence(g, S.project(g, Q, og.p, cfg["rho"]), og.K, og.W, og.cfg)
-    t_local += time.perf_counter() - t2
-    step_s = t_local + t_iter * ORACLE_WARM_ITERS
-    ncells = g.ncell
-    # NumPy element-wise work and SciPy sparse products run on one thread
-    # (the oracle uses no BLAS routine)
+
+def _slab(phi, cfg, s):
+    nx = cfg["nx"] // 8
+    return phi[s * nx:(s + 1) * nx].copy(), dict(cfg, nx=nx, dtype="f64")
+
+
+def _oracle_slab_step(s, barrier=None):
+    """Set up the oracle on slab s, wait at the barrier (so that concurrent
+    workers time the same interval), time one step; returns seconds."""
+    from threadpoolctl import threadpool_limits
+    from oracle import OracleGrid
+    with threadpool_limits(1):
+        phi, cfg = _slab(_SAMPLE["phi"], _SAMPLE["cfg"], s % 8)
+        og = OracleGrid(cfg)
+        og.set_porosity(phi)
+        if barrier is not None:
+            barrier.wait()
+        t0 = time.perf_counter()
+        og.step(1)
+        return time.perf_counter() - t0
+
+
+def _slab_worker(s, q):
+    try:
+        q.put(_oracle_slab_step(s, _SAMPLE["barrier"]))
+    except Exception:
+        q.put(None)
+        raise
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, phi, cfg):
+    """The FP64 oracle, as it is, on a bounded sample of the workload: one
+    complete step (advection, diffusion, drag, the exact pressure solve and
+    projection, k-omega) on a 1/8 x-slab of the grid, timed on one core, then
+    on every core of this host's share at once (one process per core, each
+    stepping a slab; the oracle's NumPy/SciPy work is single-threaded, so
+    processes are how it uses several cores).  Runs before the GPU is
+    touched (the workers are forked)."""
+    import multiprocessing as mp
+    _SAMPLE.update(phi=phi, cfg=cfg)
+    ncell = (cfg["nx"] // 8) * cfg["ny"] * cfg["nz"]
+    t1 = _oracle_slab_step(0)
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    # at most 16 workers (one GPU's share of a host), each holding about
+    # 3 GB for a 64x512x128 slab
+    nproc = max(1, min(ncpu, 16))
+    ctx = mp.get_context("fork")
+    _SAMPLE["barrier"] = ctx.Barrier(nproc)      # inherited by the forked workers
+    q = ctx.Queue()
+    procs = [ctx.Process(target=_slab_worker, args=(s, q)) for s in range(nproc)]
+    for pr in procs:
+        pr.start()
+    times = [q.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+    if any(t is None for t in times):
+        raise RuntimeError("an oracle worker of the CPU baseline failed")
+    t_all = max(times)
     return {
-        "value": ncells / step_s, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-        "sample": ("256x256x64 workload state after the GPU warm-up: oracle advection, diffusion, drag, "
-                   "projection and k-omega stages once on the full grid (%.1f s) plus %d full-size "
-                   "AI1-PCG iterations (%.2f s each), step = stages + %d iterations (its warm-started "
-                   "solve to 1e-6); NumPy/SciPy FP64" % (t_local, n_it, t_iter, ORACLE_WARM_ITERS)),
-        "seconds_per_step": step_s,
+        "value": nproc * ncell / t_all, "unit": "cell-updates/s", "cores": nproc, "kind": "oracle",
+        "sample": ("one complete oracle step (FP64 NumPy/SciPy; exact fast-diagonalisation pressure solve) on a "
+                   "%dx%dx%d x-slab (1/8) of the %s workload per process, %d processes at once (one per core); "
+                   "%.1f s per slab step on all cores, %.1f s on one core alone"
+                   % (cfg["nx"] // 8, cfg["ny"], cfg["nz"], GRID_TAG.get(name, name), nproc, t_all, t1)),
+        "seconds_per_step": t_all * 8.0 / nproc,
+        "one_core": {"value": ncell / t1, "seconds_per_slab_step": t1, "seconds_per_step": t1 * 8.0},
+        "host": {"nproc": ncpu, "cpu_model": _cpu_model()},
     }
 
 
@@ -723,16 +755,16 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true")
     ap.add_argument("--precond-study", action="store_true")
     ap.add_argument("--voxelize", action="store_true", help="time the mesh voxelizer instead of the step")
-    ap.add_argument("--stats-out", default="kernels_256x256x64.md", help="file name under profiles/")
-    ap.add_argument("--stats-title", default="Kernel time, 256x256x64 city workload (FP32, multigrid-preconditioned CG)")
-    ap.add_argument("--workload", default="C1", choices=["C1", "C2", "slab", "CP", "C3", "C4", "C4A"])
+    ap.add_argument("--stats-out", default="kernels_512x512x128.md", help="file name under profiles/")
+    ap.add_argument("--stats-title", default="Kernel time, 512x512x128 city workload (FP32, multigrid-preconditioned CG)")
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "slab", "CP", "C3", "C4", "C4A"])
     ap.add_argument("--adjoint-only", action="store_true", help="C4A: skip the forward-difference comparison")
     ap.add_argument("--traffic-summary", metavar="DIR")
     ap.add_argument("--stats-summary", metavar="DIR")
     ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
     args = ap.parse_args()
     if args.traffic_summary:
-        return traffic_summary(args.traffic_summary, args.command)
+        return traffic_summary(args.traffic_summary, args.command, name=args.workload)
     if args.stats_summary:
         return stats_summary(args.stats_summary, args.command, args.stats_out, args.stats_title)
     if args.gpus != 1:
@@ -742,7 +774,7 @@ def main():
         sys.exit(2)
 
     if args.traffic_probe:
-        return traffic_probe()
+        return traffic_probe(args.workload)
     if args.precond_study:
         return precond_study()
     if args.voxelize:
@@ -754,10 +786,18 @@ def main():
     if args.workload == "C4A":
         return adjoint_bench(args.steps, args.warmup, not args.adjoint_only)
 
+    p, phi, cfg = workload(args.workload)
+    tag = GRID_TAG[args.workload]
+    # the oracle's baseline first: its worker processes are forked, which
+    # must happen before this process initialises the GPU
+    cpu = None
+    if not args.no_cpu_baseline and args.workload in ("C1", "C2"):
+        cpu = cpu_baseline(args.workload, phi, cfg)
+        log("cpu baseline:", json.dumps(cpu))
+
     import torch
     import paper_2204_01117_amd as U
 
-    p, phi, cfg = workload(args.workload)
     nx, ny, nz = cfg["nx"], cfg["ny"], cfg["nz"]
     ncells = nx * ny * nz
     dev = torch.device("cuda:0")
@@ -791,10 +831,6 @@ def main():
     alg_bytes = ALG_BYTES_PER_CELL[dominant] * ncells
     avg_s = k_ms / 1e3 / max(k_n, 1)        # over every launch, as rocprof averages
     achieved = alg_bytes / avg_s / 1e9
-    # counter figures exist for the default workload only
-    traffic = traffic_for(dominant, ncells) if args.workload == "C1" else None
-
-    st_state = g.state() if (not args.no_cpu_baseline and args.workload == "C1") else {}
     result = {
         "metric": "cell-updates/s per full RANS step (incl. pressure solve)",
         "value": ncells * args.steps / secs,
@@ -809,22 +845,23 @@ def main():
         "dtype": "f32",
         "data": "synthetic seeded city layout (porosity field), random-free initial state",
         "config": {"workload": p["workload"], "grid": [nx, ny, nz], "dx_m": cfg["dx"], "dt_s": cfg["dt"],
-                   "precond": "multigrid", "cg_tol": cfg["cg_tol"], "turbulence": "k-omega"},
+                   "wind_dir_deg": cfg["wind_dir_deg"], "precond": "multigrid", "cg_tol": cfg["cg_tol"],
+                   "turbulence": "k-omega"},
         "cg_iters_per_step": iters / args.steps,
         "cg_iters_max": st.get("cg_iters_max"),
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
+                     "traffic": traffic_for(dominant, tag),
                      "avg_launch_us": avg_s * 1e6, "launches": k_n,
                      "alg_bytes_per_launch": alg_bytes},
+        "diagnostics": {"max_div_per_s": st.get("max_div"), "max_cfl": st.get("max_cfl"),
+                        "nut_clip_frac": st.get("nut_clip_frac")},
     }
     g.close()
-    if args.workload == "C1":
-        result["step_hbm"] = step_traffic(iters / args.steps, secs / args.steps * 1e3, ncells)
+    result["step_hbm"] = step_traffic(iters / args.steps, secs / args.steps * 1e3, ncells, tag)
     result["stream_copy_GBs"] = copy_ceiling_gbs(torch)
-    if not args.no_cpu_baseline and args.workload == "C1":
-        state = {f: v.double().cpu().numpy() for f, v in st_state.items()}
-        result["cpu_baseline"] = cpu_baseline(phi, cfg, state)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

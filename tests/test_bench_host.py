@@ -44,7 +44,7 @@ def test_traffic_summary_calibrates_and_splits(tmp_path):
     write_counters(str(tmp_path / "run" / "write"), "WRITE_SIZE", write)
     out_dir = tmp_path / "out"
     out_dir.mkdir()
-    recs, step = bench.traffic_summary(str(tmp_path / "run"), "cmd", out_dir=str(out_dir))
+    recs, step = bench.traffic_summary(str(tmp_path / "run"), "cmd", out_dir=str(out_dir), name="C1")
     r = recs["mg_update0"]
     assert r["calibration"]["fetch_factor"] == pytest.approx(0.5)
     assert r["calibration"]["write_factor"] == pytest.approx(1.0)
@@ -70,3 +70,14 @@ def test_algorithmic_bytes_per_step_add_up():
     # the level-0 up/smoothing and the coarse levels at 1/7 of level 0
     assert bench.ALG_FIXED_PER_CELL == 196.0
     assert bench.ALG_ITER_PER_CELL == pytest.approx(16 + 24.5 + 8.5 + 13.0 / 7)
+
+
+def test_cpu_baseline_slab_is_an_eighth_of_the_workload():
+    """The oracle's sample: x-slab s of 8 of the workload, the porosity's own
+    cells, the configuration otherwise unchanged (FP64)."""
+    import numpy as np
+    p, phi, cfg = bench.workload("C1")
+    ph, c = bench._slab(phi, cfg, 3)
+    assert c["nx"] * 8 == cfg["nx"] and c["ny"] == cfg["ny"] and c["nz"] == cfg["nz"] and c["dtype"] == "f64"
+    assert np.array_equal(ph, phi[3 * c["nx"]:4 * c["nx"]])
+    assert c["wind_dir_deg"] == cfg["wind_dir_deg"] and c["bc"] == cfg["bc"]
