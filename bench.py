@@ -251,13 +251,21 @@ def traffic_probe(name):
     g.step(3)
     g.step(3)
     torch.cuda.synchronize()
+    # two streaming kernels of known footprint besides the copy: the layout
+    # conversion (compact <-> padded, 8 B per cell each way) and the 7-point
+    # operator (read x, write A x: 8 B per cell)
+    n = (cfg["nx"], cfg["ny"], cfg["nz"])
+    xin = torch.rand(n, dtype=torch.float32, device="cuda:0")
+    g.apply_operator(0, xin)
+    torch.cuda.synchronize()
     g.close()
+    del xin
     x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
     y = torch.empty_like(x)
     for _ in range(3):
         y.copy_(x)
     torch.cuda.synchronize()
-    log("traffic probe done: 6 steps, 3 copies of %d bytes" % COPY_BYTES)
+    log("traffic probe done: 6 steps, one operator application, 3 copies of %d bytes" % COPY_BYTES)
 
 
 def traffic_summary(run_dir, command, out_dir=None, name="C2"):
@@ -329,6 +337,22 @@ def traffic_summary(run_dir, command, out_dir=None, name="C2"):
         "calibration": {"fetch_factor": f_fetch, "write_factor": f_write},
         "source_sha256": sources_hash(), "command": command,
     }
+    # the copy calibration applied to the known-footprint kernels of the
+    # probe (8 B per cell each): how far it transfers to other patterns
+    # (per kernel, the launch that moved the most: the probe's full-grid one)
+    checks = {}
+    for (kname, grid), fv in fetch.items():
+        short_name = kname.split("(")[0].replace("void ", "").replace("uf::", "")
+        if not short_name.startswith(("k_pack<", "k_apply<")) or (kname, grid) not in write:
+            continue
+        meas = fv * 1024.0 / f_fetch + write[(kname, grid)] * 1024.0 / f_write
+        foot = 8.0 * ncell
+        if short_name not in checks or meas > checks[short_name]["bytes_per_launch"]:
+            checks[short_name] = {"bytes_per_launch": meas, "footprint_bytes": foot, "ratio": meas / foot,
+                                  "grid_size": grid}
+    step_rec["calibration_checks"] = checks
+    for k, v in checks.items():
+        log("calibration check %-36s counters/footprint %.3f" % (k, v["ratio"]))
     with open(os.path.join(out_dir, "traffic_step_%s.json" % tag), "w") as f:
         json.dump(step_rec, f, indent=1)
         f.write("\n")
@@ -675,13 +699,15 @@ def gradient_bench(steps, warmup):
 def adjoint_bench(steps, warmup, with_fd=True):
     """One full design gradient on the 256x256x64 design case by the discrete
     adjoint: 21 buildings (height and x/y position each) and the trees'
-    porosity, 64 parameters; target-region objective (six pedestrian-level
-    regions, ideal speed 0.55 m/s) after `steps` steps of the full step
-    (k-omega included) from a state spun up for `warmup` steps; every state
-    of the horizon kept in HBM when it fits (else checkpoints every 20
-    steps).  Beside it the same
-    gradient by forward differences (eps 0.1, 65 simulations batched) and a
-    plain forward run of the horizon."""
+    porosity, 64 parameters; pedestrian-plane objective ((|u| - 2 m/s)^2 at
+    1.5 m plus the stagnation penalty below 0.3 m/s) after `steps` steps of
+    the full step (k-omega included) from a state spun up for `warmup`
+    steps, with the states checkpointed every 20 steps and each segment
+    recomputed in the reverse pass (the timed row).  Beside it: the same
+    gradient with every state of the horizon kept in HBM, a plain forward
+    run of the horizon, and (unless adjoint_only) the check of the gradient
+    in FP64: central differences with h = 1e-3 on 8 seeded parameters (16
+    simulations batched) against the FP64 adjoint, parameter by parameter."""
     import numpy as np
     import torch
     import paper_2204_01117_amd as U
@@ -691,21 +717,27 @@ def adjoint_bench(steps, warmup, with_fd=True):
     cfg, lay = dict(p["config"]), p["layout"]
     n, h = (cfg["nx"], cfg["ny"], cfg["nz"]), (cfg["dx"], cfg["dy"], cfg["dz"])
     boxes, cyls, _ = random_city(*n, *h, lay["seed"], lay["n_boxes"], lay["n_trees"])
-    design = U.BoxDesign(n, h, [(*b.x, *b.y, *b.z, b.phi) for b in boxes],
-                         [(c.cx, c.cy, c.r, *c.z, c.phi) for c in cyls], width=h[0] / 2, dtype="f32")
-    regions = [((32 + 80 * a, 64 + 80 * a), (40 + 96 * b, 72 + 96 * b), (0, 2)) for a in range(3) for b in range(2)]
+    rows_b = [(*b.x, *b.y, *b.z, b.phi) for b in boxes]
+    rows_c = [(c.cx, c.cy, c.r, *c.z, c.phi) for c in cyls]
+    design = U.BoxDesign(n, h, rows_b, rows_c, width=h[0] / 2, dtype="f32")
+    plane = dict(z_plane=1.5)
     theta = design.initial()
     g = U.Grid(cfg)
     g.set_porosity(design.porosity(theta))
     g.step(warmup, stats=False)
     init = g.state()
-    A = O.AdjointObjective(g, design, regions, 0.55, nsteps=steps, initial_state=init)
-    A.value_and_grad(theta)                    # allocates the workspace
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J, grad = A.value_and_grad(theta)
-    torch.cuda.synchronize()
-    adj_s = time.perf_counter() - t0
+
+    def timed_gradient(checkpoint):
+        A = O.AdjointObjective(g, design, [], nsteps=steps, initial_state=init, checkpoint=checkpoint, plane=plane)
+        A.value_and_grad(theta)                # allocates the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, grad = A.value_and_grad(theta)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, J, grad, A.segment
+
+    adj_s, J, grad, seg = timed_gradient(20)
+    hbm_s, J_hbm, grad_hbm, seg_hbm = timed_gradient(None)
     g.set_state(init)
     g.set_porosity(design.porosity(theta))
     torch.cuda.synchronize()
@@ -713,36 +745,55 @@ def adjoint_bench(steps, warmup, with_fd=True):
     g.step(steps, stats=False)
     torch.cuda.synchronize()
     fwd_s = time.perf_counter() - t0
-    if not with_fd:
-        print(json.dumps({"metric": "wall time of one full design gradient (discrete adjoint)", "value": adj_s,
-                          "unit": "s", "steps": steps, "forward_s": fwd_s, "objective": J}), flush=True)
-        g.close()
-        return
-    F = O.SimulationObjective(g, design.porosity, regions, 0.55, nsteps=0, initial_state=init)
-    F.many([theta] * (design.nparams + 1))     # builds the pool of grids
-    F.nsteps = steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    j_fd, g_fd = O.forward_difference_gradient(F, theta, 0.1)
-    torch.cuda.synchronize()
-    fd_s = time.perf_counter() - t0
-    cos = float(np.dot(grad, g_fd) / (np.linalg.norm(grad) * np.linalg.norm(g_fd)))
     res = {
         "metric": "wall time of one full design gradient (discrete adjoint)", "value": adj_s, "unit": "s",
         "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": False, "dtype": "f32",
         "data": "synthetic seeded city, smoothed building indicators",
         "config": {"workload": "256x256x64 dx=2m, 21 parametrised buildings + 40 trees, 64 parameters, "
-                               "six target regions, %d-step horizon, full step with k-omega" % steps,
-                   "method": "discrete adjoint, %s" % ("every state kept in HBM" if A.segment >= steps else
-                                                        "checkpoints every %d steps" % A.segment)},
+                               "pedestrian plane at 1.5 m, %d-step horizon, full step with k-omega" % steps,
+                   "method": "discrete adjoint, checkpoints every %d steps, segments recomputed" % seg},
         "forward_s": fwd_s, "adjoint_over_forward": adj_s / fwd_s,
-        "fd_gradient_s": fd_s, "speedup_vs_fd": fd_s / adj_s,
-        "objective": J, "objective_fd_run": j_fd, "cosine_adjoint_vs_fd": cos,
-        "gradient_norm": float(np.linalg.norm(grad)), "fd_gradient_norm": float(np.linalg.norm(g_fd)),
-        "gradient_head": [float(x) for x in grad[:6]], "fd_gradient_head": [float(x) for x in g_fd[:6]],
+        "all_states_in_hbm": {"s": hbm_s, "segment": seg_hbm,
+                              "max_abs_diff_vs_checkpointed": float(np.abs(grad_hbm - grad).max())},
+        "objective": J, "gradient_norm": float(np.linalg.norm(grad)),
+        "gradient_head": [float(x) for x in grad[:6]],
     }
-    F.close()
     g.close()
+    if with_fd:
+        cfg64 = dict(cfg, dtype="f64", cg_tol=1e-12, cg_maxit=4000)
+        d64 = U.BoxDesign(n, h, rows_b, rows_c, width=h[0] / 2, dtype="f64")
+        g64 = U.Grid(cfg64)
+        init64 = {f: v.double() for f, v in init.items()}
+        A64 = O.AdjointObjective(g64, d64, [], nsteps=steps, initial_state=init64, checkpoint=20, plane=plane)
+        t0 = time.perf_counter()
+        J64, grad64 = A64.value_and_grad(theta)
+        torch.cuda.synchronize()
+        adj64_s = time.perf_counter() - t0
+        idx = sorted(int(i) for i in np.random.default_rng(4).choice(d64.nparams, 8, replace=False))
+        hstep = 1e-3
+        thetas = []
+        for i in idx:
+            for sgn in (1.0, -1.0):
+                t = theta.copy()
+                t[i] += sgn * hstep
+                thetas.append(t)
+        F = O.SimulationObjective(g64, d64.porosity, nsteps=steps, initial_state=init64,
+                                  score=lambda gg: gg.plane_objective(**plane))
+        t0 = time.perf_counter()
+        vals = F.many(thetas)
+        torch.cuda.synchronize()
+        fd_s = time.perf_counter() - t0
+        fd = [(vals[2 * q] - vals[2 * q + 1]) / (2 * hstep) for q in range(len(idx))]
+        res["fd_check_fp64"] = {
+            "h": hstep, "parameters": idx, "objective": J64, "adjoint_s": adj64_s, "fd_s": fd_s,
+            "adjoint": [float(grad64[i]) for i in idx], "central_difference": [float(x) for x in fd],
+            "rel_err": [float(abs(grad64[i] - x) / max(abs(x), 1e-300)) for i, x in zip(idx, fd)],
+            "fp32_adjoint": [float(grad[i]) for i in idx],
+            "fp32_rel_err_vs_fp64_adjoint": [float(abs(grad[i] - grad64[i]) / max(abs(grad64[i]), 1e-300))
+                                             for i in idx],
+        }
+        F.close()
+        g64.close()
     print(json.dumps(res), flush=True)
 
 

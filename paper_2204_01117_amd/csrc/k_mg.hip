@@ -1,7 +1,8 @@
 // Geometric multigrid V-cycle used as the CG preconditioner.
 //
-// Cell-centred hierarchy: an axis is halved while its cell count is even
-// and at least 4; levels stop at <= 64 cells (or when no axis halves).
+// Cell-centred hierarchy: every axis of at least 4 cells is halved (an odd
+// axis of n cells gets ceil(n/2) coarse cells, the last one with a single
+// child); levels stop at <= 64 cells (or when no axis halves).
 // Prolongation P is trilinear between cell centres (per halved axis: 3/4 of
 // the parent and 1/4 of the parent's neighbour on the child's side; past a
 // domain side the neighbour is the parent's mirror image, + for a Neumann

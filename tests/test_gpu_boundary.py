@@ -13,8 +13,6 @@ pytestmark = [pytest.mark.gpu,
 from uf_layouts import default_config, preset, preset_porosity, perturbed_state
 from uf_layouts.configs import BC_INLET, BC_OUTLET, BC_SLIP, INFLOW_UNIFORM, TURB_OFF
 from oracle import OracleGrid
-from oracle import step as S
-from oracle import bc as B
 from helpers import to_np, random_small_config, random_porosity
 
 import paper_2204_01117_amd as U
@@ -40,27 +38,33 @@ def test_torch_allocator_and_hipmalloc_give_identical_steps():
         g.step(5)
         g.adjoint_step([g.get_field(f) for f in g.adjoint_fields()],
                        [torch.zeros_like(g.get_field(f)) for f in g.adjoint_fields()])
-    for f, v in a.state().items():
-        assert torch.equal(v, b.state()[f]), f
+    sa, sb = a.state(), b.state()
+    for f in sa:
+        assert torch.equal(sa[f], sb[f]), f
+    # the compared copies are the test's own tensors: release them before
+    # counting what the grids leave behind
+    del sa, sb
     a.close()
     b.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() <= before + 1024
 
 
-def _oracle_diag(cfg, st):
-    """max |div u|, max dt sum |u_c| / h and the capped fraction of nu_t,
-    from the oracle's own arrays of a state."""
+def _state_diag(cfg, st):
+    """max |div u|, max dt sum |u_c| / h and the capped fraction of nu_t of
+    the stored face and cell arrays exactly as they are (no boundary value
+    re-imposed), in FP64 with the grid's spacing, time step and cap in its
+    own dtype (the values the library holds)."""
+    cast = np.float32 if cfg["dtype"] == "f32" else np.float64
+    h = [float(cast(cfg[a])) for a in ("dx", "dy", "dz")]
+    dt = float(cast(cfg["dt"]))
+    u, v, w = st["u"], st["v"], st["w"]
+    div = np.diff(u, axis=0) / h[0] + np.diff(v, axis=1) / h[1] + np.diff(w, axis=2) / h[2]
+    cen = [0.5 * np.abs(u[1:] + u[:-1]), 0.5 * np.abs(v[:, 1:] + v[:, :-1]), 0.5 * np.abs(w[:, :, 1:] + w[:, :, :-1])]
+    cfl = dt * (cen[0] / h[0] + cen[1] / h[1] + cen[2] / h[2])
     og = OracleGrid(dict(cfg, dtype="f64"), solver="none")
-    for f, v in st.items():
-        og.set_field(f, v)
-    g = og.g
-    div = S.divergence(g, og.Q)
-    n = g.n
-    cen = [0.5 * (B.win(og.Q[c], n) + B.win(og.Q[c], n, B.unit(c, 1))) for c in range(3)]
-    cfl = g.dt * sum(np.abs(cen[c]) / g.h[c] for c in range(3))
-    cap = g.nu_max() - cfg["nu"]
-    clip = float((og.get_field("nut") >= cap).mean()) if cfg["turb_model"] else 0.0
+    cap = float(cast(og.g.nu_max() - cfg["nu"]))
+    clip = float((st["nut"] >= cap).mean()) if cfg["turb_model"] else 0.0
     return float(np.abs(div).max()), float(cfl.max()), clip, cap
 
 
@@ -77,11 +81,13 @@ def test_step_stats_diagnostics_match_the_state(dtype):
     g.set_state({f: torch.as_tensor(v) for f, v in st0.items()})
     s = g.step(1)
     out = {f: to_np(v) for f, v in g.state().items()}
-    mdiv, mcfl, clip, cap = _oracle_diag(cfg, out)
+    mdiv, mcfl, clip, cap = _state_diag(cfg, out)
     log(dtype, "stats", {k: s[k] for k in ("max_div", "max_cfl", "nut_clip_frac")}, "oracle", mdiv, mcfl, clip)
-    tol = 1e-12 if dtype == "f64" else 1e-5
+    # both sides evaluate the same FP32 (or FP64) values in FP64: only the
+    # order of the three additions may differ
+    tol = 1e-12
     assert abs(s["max_cfl"] - mcfl) <= tol * mcfl
-    assert abs(s["max_div"] - mdiv) <= max(tol * mdiv, 1e-12 * mcfl / cfg["dt"])
+    assert abs(s["max_div"] - mdiv) <= max(tol * mdiv, 1e-14 * mcfl / cfg["dt"])
     assert abs(s["nut_clip_frac"] - clip) <= 1.0 / np.prod(n)
     # after a projection the divergence is at the solver's tolerance
     assert s["max_div"] * cfg["dt"] < (1e-9 if dtype == "f64" else 1e-3)
@@ -104,15 +110,18 @@ def _flag_case(stages):
 
 def test_drag_stage_raises_the_nonfinite_flag():
     g = _flag_case(4)                      # drag only: no solve sees the value
-    u = to_np(g.get_field("u"))
+    clean = {f: to_np(g.get_field(f)) for f in "uvw"}
+    u = clean["u"].copy()
     u[4, 2, 2] = np.inf
     g.set_field("u", u)
     st = g.step(1, allow=(5,))
     assert st["status"] == "UF_ENONFINITE" and st["nonfinite"] == 1
     # sticky until the state is overwritten
     assert g.step(1, allow=(5,))["status"] == "UF_ENONFINITE"
-    u[4, 2, 2] = 2.0
-    g.set_field("u", u)
+    # the drag spread the value into neighbouring faces of every component:
+    # a clean state clears the flag
+    for f in "uvw":
+        g.set_field(f, clean[f])
     st = g.step(1)
     assert st["status"] == "UF_OK" and st["nonfinite"] == 0
     g.close()

@@ -285,8 +285,9 @@ def test_maccormack_clamp_active_gpu(dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_nut_cap_active_gpu(dtype):
-    """k / omega far above the explicit-diffusion bound in most cells: the
-    capped eddy viscosity drives the diffusion of the next step."""
+    """k / omega far above the explicit-diffusion bound in a large share of
+    the cells (the rest stay below it, so both branches of the clip run):
+    the capped eddy viscosity drives the diffusion of the next step."""
     cfg = random_small_config(33, dtype=dtype, precond=PC_MG, cg_tol=1e-13 if dtype == "f64" else 1e-7,
                               cg_maxit=5000, nu=0.01)
     n = (cfg["nx"], cfg["ny"], cfg["nz"])
@@ -306,9 +307,9 @@ def test_nut_cap_active_gpu(dtype):
     assert s["converged"] == 1
     so = og.state()
     frac = float((so["nut"] >= cap * (1 - 1e-12)).mean())
-    assert frac > 0.5, frac
     errs = state_errors(np_state(g), so)
     log("nu_t cap active in %.2f of the cells" % frac, dtype, errs)
+    assert 0.3 < frac < 0.9, frac
     assert_close(errs, 1e-11 if dtype == "f64" else 1e-5, fields=("vel", "p", "k", "omega", "nut"),
                  what="capped nu_t")
     g.close()
