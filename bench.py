@@ -82,7 +82,9 @@ PROFILE_NAMES = [
     ("k_mg_restrict<true", "mg_update0"),
     ("k_cg_init<", "cg_init"),
     ("k_advect_fwd<", "advect_fwd"),
+    ("k_advect_fwd32<", "advect_fwd"),
     ("k_advect_corr<", "advect_corr"),
+    ("k_advect_corr32<", "advect_corr"),
     ("k_diffuse<", "diffuse"),
     ("k_drag<", "drag"),
     ("k_project<", "project"),

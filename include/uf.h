@@ -268,7 +268,8 @@ int64_t uf_field_extent(const uf_config* cfg, int32_t field, int32_t dims[3]);
  * porosity drag, pressure projection, then the k-omega update (Sec. 3
  * "Discretization and Numerical Integration": terms integrated one by one,
  * turbulence after the projection).  The pressure solve starts from the
- * previous pressure.  The call returns after the last step's solve has
+ * previous pressure, or from zero when that is the worse start (its
+ * residual longer than the right-hand side).  The call returns after the last step's solve has
  * been observed to finish; later kernels may still be in flight unless
  * stats is non-NULL, which synchronises and fills it.  Returns UF_ENOCONV or
  * UF_ENONFINITE if some solve did not converge or saw a non-finite value;
@@ -296,7 +297,8 @@ uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step
 
 /* Solve A x = b with the grid's pressure operator (A = -L_h with the
  * boundary rows described above; SPD), preconditioner and tolerance; x_dev
- * holds the initial guess on entry and the solution on exit.  b_dev and
+ * holds the initial guess on entry and the solution on exit (a guess whose
+ * residual is longer than b is replaced by zero, as in uf_step's solves).  b_dev and
  * x_dev are nx*ny*nz device arrays.  The grid's state, its pressure
  * included, is left as it was (the first call allocates one cell array to
  * keep it).  Synchronises; stats may be NULL. */

@@ -183,10 +183,14 @@ def pcg(A, b, x0, M=None, tol=1e-12, maxit=20000, criterion=0):
 
     criterion 0 stops at ||r||_2 <= tol ||b||_2; criterion 1 is the paper's
     test (M^-1 r . r) / ||b||^2 < tol (appendix, "Efficiency of the AI
-    Preconditioner").  Returns (x, iterations)."""
+    Preconditioner").  An initial guess whose residual is longer than b
+    (a worse start than zero) is replaced by zero.  Returns (x, iterations)."""
     x = x0.copy()
     r = b - A @ x
     bb = float(b @ b)
+    if float(r @ r) > bb:
+        x = np.zeros_like(x)
+        r = b.copy()
     z = M @ r if M is not None else r.copy()
     rz = float(r @ z)
 

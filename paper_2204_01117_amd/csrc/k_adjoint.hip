@@ -112,35 +112,31 @@ __global__ __launch_bounds__(256) void k_vel_gather(Params<T> P, VelAdj<T> V, T*
   }
 }
 
-// Cell and fractions of a sample position, clamped exactly as in sample().
+// Cell and fractions of a trace position (i + si, j + sj, k + sk), clamped
+// exactly as in sample().
 template <int C, class T>
 struct SamplePos {
   long long o;      // offset of the lower corner
   T t[3];           // fractions
   bool live[3];     // the position was not clamped along this axis
-  __device__ __forceinline__ SamplePos(const Layout& L, T fi, T fj, T fk) {
-    int ext[3];
-    face_ext<C>(L, ext);
-    T f[3] = {fi, fj, fk};
-    int c0[3];
+  __device__ __forceinline__ SamplePos(const Layout& L, int i, int j, int k, T si, T sj, T sk) {
+    AxisPos<T> a[3];
+    trace_pos<C>(L, i, j, k, si, sj, sk, a);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      live[a] = !(f[a] < T(-1) || f[a] > T(ext[a]));
-      f[a] = fmin(fmax(f[a], T(-1)), T(ext[a]));
-      const T lf = fmin(floor(f[a]), T(ext[a] - 1));
-      t[a] = f[a] - lf;
-      c0[a] = (int)lf;
+    for (int q = 0; q < 3; ++q) {
+      t[q] = a[q].t;
+      live[q] = a[q].live;
     }
-    o = L.at(c0[0], c0[1], c0[2]);
+    o = L.at(a[0].c, a[1].c, a[2].c);
   }
 };
 
 // Offset of the smallest (want_max false) or largest of the eight samples
 // around a position (the first one in corner order on a tie).
 template <int C, class T>
-__device__ __forceinline__ long long sample_extreme(const Layout& L, const T* __restrict__ q, T fi, T fj, T fk,
-                                                    bool want_max) {
-  const SamplePos<C, T> s(L, fi, fj, fk);
+__device__ __forceinline__ long long sample_extreme(const Layout& L, const T* __restrict__ q, int i, int j, int k,
+                                                    T si, T sj, T sk, bool want_max) {
+  const SamplePos<C, T> s(L, i, j, k, si, sj, sk);
   const long long offs[8] = {0, L.SX, L.PZ, L.SX + L.PZ, 1, L.SX + 1, L.PZ + 1, L.SX + L.PZ + 1};
   long long best = s.o;
   T bv = q[s.o];
@@ -170,9 +166,9 @@ struct Scatter8 {
 };
 
 template <int C, class T>
-__device__ __forceinline__ void sample_weights(const Layout& L, const T* __restrict__ q, T fi, T fj, T fk, T wbar,
-                                               T grad[3], Scatter8<T>& sc) {
-  const SamplePos<C, T> s(L, fi, fj, fk);
+__device__ __forceinline__ void sample_weights(const Layout& L, const T* __restrict__ q, int i, int j, int k, T si,
+                                               T sj, T sk, T wbar, T grad[3], Scatter8<T>& sc) {
+  const SamplePos<C, T> s(L, i, j, k, si, sj, sk);
   const long long o = s.o, SX = L.SX, PZ = L.PZ;
   const T ti = s.t[0], tj = s.t[1], tk = s.t[2];
   const T s000 = q[o], s100 = q[o + SX], s010 = q[o + PZ], s110 = q[o + SX + PZ];
@@ -240,19 +236,17 @@ __device__ __forceinline__ void advect_corr_adj(const Params<T>& P, const T* __r
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
   const T di = vel[0] * P.dth[0], dj = vel[1] * P.dth[1], dk = vel[2] * P.dth[2];
-  const T bi = T(i) - di, bj = T(j) - dj, bk = T(k) - dk;
-  const T fi = T(i) + di, fj = T(j) + dj, fk = T(k) + dk;
   T mn, mx, d0, d1;
-  const T qh = sample<C, true>(P.L, q, bi, bj, bk, &mn, &mx);
-  const T qc = sample<C, false>(P.L, qhat, fi, fj, fk, &d0, &d1);
+  const T qh = sample<C, true>(P.L, q, i, j, k, -di, -dj, -dk, &mn, &mx);
+  const T qc = sample<C, false>(P.L, qhat, i, j, k, di, dj, dk, &d0, &d1);
   const T qt = qh + T(0.5) * (q[o] - qc);
   if (qt < mn || qt > mx) {
-    add_to(Gq + sample_extreme<C>(P.L, q, bi, bj, bk, qt > mx), ob);
+    add_to(Gq + sample_extreme<C>(P.L, q, i, j, k, -di, -dj, -dk, qt > mx), ob);
     return;
   }
   T gb[3], gf[3];
-  sample_weights<C>(P.L, q, bi, bj, bk, ob, gb, sb);
-  sample_weights<C>(P.L, qhat, fi, fj, fk, T(-0.5) * ob, gf, sf);
+  sample_weights<C>(P.L, q, i, j, k, -di, -dj, -dk, ob, gb, sb);
+  sample_weights<C>(P.L, qhat, i, j, k, di, dj, dk, T(-0.5) * ob, gf, sf);
   vb[0] = -ob * P.dth[0] * (gb[0] + T(0.5) * gf[0]);
   vb[1] = -ob * P.dth[1] * (gb[1] + T(0.5) * gf[1]);
   vb[2] = -ob * P.dth[2] * (gb[2] + T(0.5) * gf[2]);
@@ -271,7 +265,7 @@ __device__ __forceinline__ void advect_fwd_adj(const Params<T>& P, const T* __re
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
   T g[3];
-  sample_weights<C>(P.L, q, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], ob, g, sb);
+  sample_weights<C>(P.L, q, i, j, k, -(vel[0] * P.dth[0]), -(vel[1] * P.dth[1]), -(vel[2] * P.dth[2]), ob, g, sb);
   vb[0] = -ob * P.dth[0] * g[0];
   vb[1] = -ob * P.dth[1] * g[1];
   vb[2] = -ob * P.dth[2] * g[2];
@@ -282,7 +276,7 @@ __device__ __forceinline__ void advect_fwd_adj(const Params<T>& P, const T* __re
 // carry no adjoint and write nothing.
 #define UF_FACE_THREAD_ALL(L)                                        \
   int f_bx, f_by;                                                    \
-  if (!xcd_block(face_gx(L), (L).nx + 1, f_bx, f_by)) return;        \
+  if (!face_block((L), f_bx, f_by)) return;                          \
   const int i = f_by;                                                \
   const int p_raw = f_bx * kFaceBlock + threadIdx.x;                 \
   const bool lane_valid = p_raw < ((L).ny + 1) * ((L).nz + 1);       \

@@ -19,7 +19,7 @@ __device__ __forceinline__ T advect_fwd_value(const Params<T>& P, const T* __res
   face_velocity<C>(P.L, U, V, W, o, vel);
   const T* q = C == 0 ? U : (C == 1 ? V : W);
   T mn, mx;
-  return sample<C, false>(P.L, q, T(i) - vel[0] * P.dth[0], T(j) - vel[1] * P.dth[1], T(k) - vel[2] * P.dth[2], &mn,
+  return sample<C, false>(P.L, q, i, j, k, -(vel[0] * P.dth[0]), -(vel[1] * P.dth[1]), -(vel[2] * P.dth[2]), &mn,
                           &mx);
 }
 
@@ -33,9 +33,9 @@ __device__ __forceinline__ T advect_corr_value(const Params<T>& P, const T* __re
   const T di = vel[0] * P.dth[0], dj = vel[1] * P.dth[1], dk = vel[2] * P.dth[2];
   T mn, mx;
   // forward trace again: same value as stored in qhat, plus the sample range
-  const T qh = sample<C, true>(P.L, q, T(i) - di, T(j) - dj, T(k) - dk, &mn, &mx);
+  const T qh = sample<C, true>(P.L, q, i, j, k, -di, -dj, -dk, &mn, &mx);
   T d0, d1;
-  const T qc = sample<C, false>(P.L, qhat, T(i) + di, T(j) + dj, T(k) + dk, &d0, &d1);
+  const T qc = sample<C, false>(P.L, qhat, i, j, k, di, dj, dk, &d0, &d1);
   const T qt = qh + T(0.5) * (q[o] - qc);
   return nmin(nmax(qt, mn), mx);
 }
@@ -64,6 +64,84 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_corr(Params<T> P, const T
   const T a0 = advect_corr_value<0>(P, U, V, W, Uh, o, i, j, k);
   const T a1 = advect_corr_value<1>(P, U, V, W, Vh, o, i, j, k);
   const T a2 = advect_corr_value<2>(P, U, V, W, Wh, o, i, j, k);
+  finish_face<0>(P, Uo, i, j, k, a0);
+  finish_face<1>(P, Vo, i, j, k, a1);
+  finish_face<2>(P, Wo, i, j, k, a2);
+}
+
+// The advection kernels with 32-bit offsets (arrays below 4 GiB).  The
+// predictor gathers the face velocities of the thread's three faces, then
+// issues the trilinear loads of all three components at once, then
+// evaluates: two memory round trips instead of one per component.
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_fwd32(Params<T> P, const T* __restrict__ U,
+                                                             const T* __restrict__ V, const T* __restrict__ W,
+                                                             T* __restrict__ Uh, T* __restrict__ Vh,
+                                                             T* __restrict__ Wh) {
+  UF_FACE_THREAD(P.L);
+  const Layout& L = P.L;
+  const unsigned o = (unsigned)L.at(i, j, k);
+  T v0[3], v1[3], v2[3];
+  face_velocity32<0>(L, U, V, W, o, v0);
+  face_velocity32<1>(L, U, V, W, o, v1);
+  face_velocity32<2>(L, U, V, W, o, v2);
+  const Tri<T> t0 = tri_corner<0>(L, i, j, k, -(v0[0] * P.dth[0]), -(v0[1] * P.dth[1]), -(v0[2] * P.dth[2]));
+  const Tri<T> t1 = tri_corner<1>(L, i, j, k, -(v1[0] * P.dth[0]), -(v1[1] * P.dth[1]), -(v1[2] * P.dth[2]));
+  const Tri<T> t2 = tri_corner<2>(L, i, j, k, -(v2[0] * P.dth[0]), -(v2[1] * P.dth[1]), -(v2[2] * P.dth[2]));
+  T s0[8], s1[8], s2[8];
+  tri_load(U, L, t0.o, s0);
+  tri_load(V, L, t1.o, s1);
+  tri_load(W, L, t2.o, s2);
+  // NaN for a NaN velocity, added rather than selected: a select would let
+  // the compiler move the loads under a branch
+  const T a0 = tri_eval(t0, s0) + nan_if<T>(any_nan3(v0));
+  const T a1 = tri_eval(t1, s1) + nan_if<T>(any_nan3(v1));
+  const T a2 = tri_eval(t2, s2) + nan_if<T>(any_nan3(v2));
+  finish_face<0>(P, Uh, i, j, k, a0);
+  finish_face<1>(P, Vh, i, j, k, a1);
+  finish_face<2>(P, Wh, i, j, k, a2);
+}
+
+// The corrector with 32-bit offsets, one component after another (all
+// three at once would hold 48 samples in registers and halve the resident
+// wavefronts): the forward trace again (its value and the range of its
+// eight samples), the reverse trace through the traced field, the
+// correction and the clamp.
+template <int C, class T>
+__device__ __forceinline__ T advect_corr32_value(const Params<T>& P, const T* __restrict__ U,
+                                                 const T* __restrict__ V, const T* __restrict__ W,
+                                                 const T* __restrict__ qhat, unsigned o, int i, int j, int k) {
+  T vel[3];
+  face_velocity32<C>(P.L, U, V, W, o, vel);
+  const T* q = C == 0 ? U : (C == 1 ? V : W);
+  const T di = vel[0] * P.dth[0], dj = vel[1] * P.dth[1], dk = vel[2] * P.dth[2];
+  const Tri<T> fw = tri_corner<C>(P.L, i, j, k, -di, -dj, -dk);
+  const Tri<T> bw = tri_corner<C>(P.L, i, j, k, di, dj, dk);
+  T sf[8], sb[8];
+  tri_load(q, P.L, fw.o, sf);
+  tri_load(qhat, P.L, bw.o, sb);
+  T mn, mx;
+  tri_range(sf, mn, mx);
+  const T qh = tri_eval(fw, sf);
+  const T qc = tri_eval(bw, sb);
+  const T qt = qh + T(0.5) * (vel[C] - qc);
+  return nmin(nmax(qt, mn), mx) + nan_if<T>(any_nan3(vel));
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_corr32(Params<T> P, const T* __restrict__ U,
+                                                              const T* __restrict__ V, const T* __restrict__ W,
+                                                              const T* __restrict__ Uh, const T* __restrict__ Vh,
+                                                              const T* __restrict__ Wh, T* __restrict__ Uo,
+                                                              T* __restrict__ Vo, T* __restrict__ Wo) {
+  UF_FACE_THREAD(P.L);
+  const unsigned o = (unsigned)P.L.at(i, j, k);
+  // scheduling barriers keep the components apart (fewer live registers)
+  const T a0 = advect_corr32_value<0>(P, U, V, W, Uh, o, i, j, k);
+  __builtin_amdgcn_sched_barrier(0);
+  const T a1 = advect_corr32_value<1>(P, U, V, W, Vh, o, i, j, k);
+  __builtin_amdgcn_sched_barrier(0);
+  const T a2 = advect_corr32_value<2>(P, U, V, W, Wh, o, i, j, k);
   finish_face<0>(P, Uo, i, j, k, a0);
   finish_face<1>(P, Vo, i, j, k, a1);
   finish_face<2>(P, Wo, i, j, k, a2);
@@ -177,6 +255,18 @@ static inline dim3 face_grid(const Layout& L) { return xcd_grid(face_gx(L), L.nx
 template <class T>
 void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Qout[3]) {
   const dim3 grid = face_grid(P.L);
+  if (offsets_fit_32(P.L, sizeof(T))) {
+    {
+      TimedLaunch tl(g, UF_TK_ADVECT_FWD);
+      launch_k(g, k_advect_fwd32<T>, grid, dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
+               (const T*)Qin[2], (T*)Qhat[0], (T*)Qhat[1], (T*)Qhat[2]);
+    }
+    TimedLaunch tl(g, UF_TK_ADVECT_CORR);
+    launch_k(g, k_advect_corr32<T>, grid, dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
+             (const T*)Qin[2], (const T*)Qhat[0], (const T*)Qhat[1], (const T*)Qhat[2], (T*)Qout[0], (T*)Qout[1],
+             (T*)Qout[2]);
+    return;
+  }
   {
     TimedLaunch tl(g, UF_TK_ADVECT_FWD);
     launch_k(g, k_advect_fwd<T>, grid, dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],

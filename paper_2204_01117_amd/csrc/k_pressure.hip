@@ -162,11 +162,19 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_init(Params<T> P, const T* __re
 }
 
 // One block: ||b||, the stopping threshold and whether x0 already solves.
+// An initial guess whose residual is larger than b itself (the warm start
+// of a step after a sudden change of the flow) is dropped for x0 = 0: the
+// iterate is then accumulated from zero, so its rounding is relative to
+// the new solution rather than to the larger old one; k_cg_restart resets
+// x and r.
 __global__ __launch_bounds__(256) void k_cg_start(CgCtl c, double tol) {
   const double bb = slot_sum(c.part + (size_t)S_BB * c.stride, c.nb);
-  const double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb_rr);
+  double rr = slot_sum(c.part + (size_t)S_RR * c.stride, c.nb_rr);
   if (threadIdx.x != 0) return;
   CgState* st = c.st;
+  const bool restart = isfinite(bb) && isfinite(rr) && rr > bb;
+  if (restart) rr = bb;
+  st->restart = restart;
   st->bb = bb;
   st->rr = rr;
   st->iter = 0;
@@ -178,6 +186,30 @@ __global__ __launch_bounds__(256) void k_cg_start(CgCtl c, double tol) {
   st->tol2_bb = c.criterion == 0 ? tol * tol * bb : tol * bb;
   st->done = st->nonfinite || st->zero_rhs || (c.criterion == 0 && rr <= st->tol2_bb);
   c.flags[0] = st->done;
+}
+
+// x = 0 and r = b when k_cg_start dropped the initial guess (b formed as
+// k_cg_init forms it); nothing otherwise.
+template <class T>
+__global__ __launch_bounds__(kCgBlock) void k_cg_restart(Params<T> P, const T* __restrict__ U,
+                                                         const T* __restrict__ V, const T* __restrict__ W,
+                                                         const T* __restrict__ bin, T* __restrict__ X,
+                                                         T* __restrict__ R, CgCtl c, int ilen) {
+  if (!c.st->restart) return;
+  const Layout& L = P.L;
+  UF_CG_RANGE(L, ilen);
+  for (int i = i0; i < i1; ++i) {
+    const long long o = L.at(i, j, k);
+    T b;
+    if (bin) {
+      b = bin[o];
+    } else {
+      const T div = (U[o + L.SX] - U[o]) * P.ih[0] + (V[o + L.PZ] - V[o]) * P.ih[1] + (W[o + 1] - W[o]) * P.ih[2];
+      b = -P.rho_dt * div;
+    }
+    R[o] = b;
+    X[o] = T(0);
+  }
 }
 
 // Preconditioner application m (m = 0 after init, m = t+1 after iteration
@@ -493,6 +525,8 @@ void launch_cg_start(Grid& g, const Params<T>& P, void* const Qs[3], const void*
                      (const T*)Qs[2], (const T*)b, (const T*)g.X, (T*)resid(g, 0), c, cl.ilen);
   }
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(256), 0, g.stream, c, g.cfg.cg_tol);
+  hipLaunchKernelGGL(k_cg_restart<T>, cl.grid, dim3(kCgBlock), 0, g.stream, P, (const T*)Qs[0], (const T*)Qs[1],
+                     (const T*)Qs[2], (const T*)b, (T*)g.X, (T*)resid(g, 0), c, cl.ilen);
 }
 
 template <class T>

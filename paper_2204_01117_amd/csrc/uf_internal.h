@@ -26,6 +26,7 @@ struct CgState {
   int maxit;
   int criterion;
   int nf_state;      // 1 once the drag or k-omega stage wrote a NaN/Inf (sticky; the solves leave it)
+  int restart;       // 1 when the initial guess was worse than zero and the solve started from x = 0
 };
 
 // One level of the multigrid hierarchy (level 0 is the fine grid).

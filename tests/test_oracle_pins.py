@@ -390,6 +390,27 @@ def test_p11_pcg_matches_direct():
     assert it > 0 and np.abs(xc - xd).max() < 1e-10 * np.abs(xd).max()
 
 
+def test_pcg_drops_an_initial_guess_worse_than_zero():
+    """A warm start whose residual is longer than b is replaced by zero: the
+    same iterates (so the same count) as a zero start, the same solution;
+    a guess closer than zero is kept (fewer iterations than from zero)."""
+    cfg = default_config(10, 8, 6, 1.0)
+    og = OracleGrid(cfg)
+    A = og.pressure.A
+    b = np.random.default_rng(2).normal(size=A.shape[0])
+    xd, _ = og.pressure.solve(b, np.zeros_like(b))
+    M, _ = ai_preconditioner(A, 1.6)
+    x0, it0 = pcg(A, b, np.zeros_like(b), M, tol=1e-10)
+    bad = -10.0 * xd                        # residual 11 |b|
+    assert np.linalg.norm(b - A @ bad) > np.linalg.norm(b)
+    xb, itb = pcg(A, b, bad, M, tol=1e-10)
+    assert itb == it0 and np.array_equal(xb, x0)
+    good = xd * (1.0 + 1e-3 * np.random.default_rng(3).normal(size=xd.shape))
+    assert np.linalg.norm(b - A @ good) < np.linalg.norm(b)
+    xg, itg = pcg(A, b, good, M, tol=1e-10)
+    assert itg < it0 and np.abs(xg - xd).max() < 1e-8 * np.abs(xd).max()
+
+
 # --------------------------------------------------- P12 AI preconditioner ----
 def _dense_ai(Ad, omega, order):
     """K from its definition with dense matrices."""
