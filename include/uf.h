@@ -252,6 +252,22 @@ enum { UF_MAX_GRAD_OBJECTS = 1024 };
 uf_status uf_smooth_porosity_grad(const uf_smooth_objects* objects, const double* phibar_dev, double* grad_host,
                                   void* stream);
 
+/* uf_smooth_porosity_grad without allocating: for callers that cannot
+ * allocate device memory (code under stream or graph capture, serving loops,
+ * hosts that forbid hipMalloc).  Same arguments, result and errors as
+ * uf_smooth_porosity_grad (the sums may differ in the last bits: per-block
+ * partials are summed on the device, with fewer blocks when many objects
+ * fill the rows), for at most UF_NOALLOC_MAX_OBJECTS boxes and cylinders
+ * together (UF_EINVAL beyond, nothing enqueued).  The work memory is one
+ * fixed 8 MiB device array per GPU, kept by the library until the process
+ * ends; every call on a GPU reuses it, so calls that overlap on one GPU
+ * (other host threads, or streams not ordered with this one) race.  The
+ * current device must be the stream's (UF_EINVAL otherwise).  Copies the
+ * object rows from host memory on `stream` and synchronises it. */
+enum { UF_NOALLOC_MAX_OBJECTS = 1024 };
+uf_status uf_smooth_porosity_grad_noalloc(const uf_smooth_objects* objects, const double* phibar_dev,
+                                          double* grad_host, void* stream);
+
 /* Overwrite one state field from a device array in the layout given by
  * uf_field_extent (checkpoint restore, parity tests).  Boundary values are
  * re-imposed after the copy.  UF_PHI is the same as uf_set_porosity. */

@@ -118,6 +118,8 @@ _SIGS = {
     "uf_step_batch": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p]),
     "uf_smooth_porosity": (c_int32, [POINTER(uf_smooth_objects), c_int32, c_void_p, c_void_p]),
     "uf_smooth_porosity_grad": (c_int32, [POINTER(uf_smooth_objects), c_void_p, POINTER(c_double), c_void_p]),
+    "uf_smooth_porosity_grad_noalloc": (c_int32, [POINTER(uf_smooth_objects), c_void_p, POINTER(c_double),
+                                                  c_void_p]),
     "uf_voxelize": (c_int32, [POINTER(uf_mesh_set), c_int32, c_void_p, c_void_p, POINTER(c_double)]),
     "uf_kernel_timer_enable": (c_int32, [c_void_p, ctypes.c_uint32]),
     "uf_kernel_timer_read": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
@@ -145,6 +147,7 @@ uf_set_stream = lib.uf_set_stream
 uf_step_batch = lib.uf_step_batch
 uf_smooth_porosity = lib.uf_smooth_porosity
 uf_smooth_porosity_grad = lib.uf_smooth_porosity_grad
+uf_smooth_porosity_grad_noalloc = lib.uf_smooth_porosity_grad_noalloc
 uf_voxelize = lib.uf_voxelize
 uf_kernel_timer_enable = lib.uf_kernel_timer_enable
 uf_kernel_timer_read = lib.uf_kernel_timer_read

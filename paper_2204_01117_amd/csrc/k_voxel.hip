@@ -17,6 +17,7 @@
 // Decisions (hit or miss, left or right of a crossing) are taken in FP64
 // with contraction off, so the inside counts are reproducible bit for bit.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -548,6 +549,113 @@ void smooth_porosity_grad_run(const uf_smooth_objects& o, const double* phibar, 
     for (int q = 0; q < 7; ++q) grad[7 * b + q] = tot[8 * b + q];
   for (int c = 0; c < o.ncyls; ++c)
     for (int q = 0; q < 6; ++q) grad[7 * o.nboxes + 6 * c + q] = tot[8 * (o.nboxes + c) + q];
+}
+
+}  // namespace uf
+
+// ------------------------------------------ allocation-free porosity gradient
+// uf_smooth_porosity_grad_noalloc works in one fixed device array per GPU
+// instead of allocating: the caller's box and cylinder rows, the packed
+// objects the gradient kernel reads, the per-block partial rows and the
+// summed gradient.  8 MiB, held by each GPU the library runs on until the
+// process ends.  Every call on a GPU reuses it, so calls that overlap on one
+// GPU (several host threads, or streams not ordered with each other) race.
+namespace uf {
+
+constexpr size_t kScratchDoubles = size_t(1) << 20;
+constexpr size_t kScrMaxObj = UF_NOALLOC_MAX_OBJECTS;
+constexpr size_t kScrBoxes = 0;                         // 7 per box, as the caller passes them
+constexpr size_t kScrCyls = kScrBoxes + 7 * kScrMaxObj; // 6 per cylinder
+constexpr size_t kScrPacked = kScrCyls + 6 * kScrMaxObj;  // 8 per object
+constexpr size_t kScrGrad = kScrPacked + 8 * kScrMaxObj;  // 7 per box, then 6 per cylinder
+constexpr size_t kScrPart = 32 * kScrMaxObj;            // partial rows, to the end
+static_assert(kScrGrad + 7 * kScrMaxObj <= kScrPart, "scratch regions overlap");
+static_assert(kScrPart % 32 == 0, "partial rows start 256-byte aligned");
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// The objects in the form k_smooth_porosity_grad reads: a box is its seven
+// values and a zero, a cylinder its six values, a zero and a one (the mark
+// that tells the two kinds apart).
+__global__ __launch_bounds__(kVoxThreads) void k_pack_objects(const double* __restrict__ boxes, int nb,
+                                                              const double* __restrict__ cyls, int nc,
+                                                              double* __restrict__ obj) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nb + nc) return;
+  double* dst = obj + 8 * (size_t)o;
+  if (o < nb) {
+    for (int q = 0; q < 7; ++q) dst[q] = boxes[7 * (size_t)o + q];
+    dst[7] = 0.0;
+  } else {
+    const double* src = cyls + 6 * (size_t)(o - nb);
+    for (int q = 0; q < 6; ++q) dst[q] = src[q];
+    dst[6] = 0.0;
+    dst[7] = 1.0;
+  }
+}
+
+// Sum of the partial rows, block by block in block order (one thread per
+// gradient entry), into the caller's order: 7 per box, then 6 per cylinder.
+__global__ __launch_bounds__(kVoxThreads) void k_sum_rows(const double* __restrict__ part, int rows, int nslot,
+                                                          int nb, int nc, double* __restrict__ grad) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ng = 7 * nb + 6 * nc;
+  if (q >= ng) return;
+  const int slot = q < 7 * nb ? 8 * (q / 7) + q % 7 : 8 * (nb + (q - 7 * nb) / 6) + (q - 7 * nb) % 6;
+  double s = 0.0;
+  for (int b = 0; b < rows; ++b) s += part[(size_t)b * nslot + slot];
+  grad[q] = s;
+}
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of this GPU's scratch, looked up once per device with that
+// device current.  Host code uses this address only: the array's own name
+// is a host-side stand-in.
+double* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) throw HipError("device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    UF_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError("hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+}  // namespace
+
+// Host side of uf_smooth_porosity_grad_noalloc (arguments validated by the
+// caller, at most kScrMaxObj objects; the current device is the stream's).
+void smooth_porosity_grad_noalloc_run(const uf_smooth_objects& o, const double* phibar, double* grad,
+                                      hipStream_t stream) {
+  const int nb = o.nboxes, nc = o.ncyls, nobj = nb + nc;
+  const int ng = 7 * nb + 6 * nc;
+  for (int q = 0; q < ng; ++q) grad[q] = 0.0;
+  if (nobj == 0) return;
+  int dev = 0;
+  UF_HIP_CHECK(hipGetDevice(&dev));
+  double* s = scratch_on(dev);
+  const size_t n = (size_t)o.nx * o.ny * o.nz;
+  const size_t nslot = 8 * (size_t)nobj;
+  const size_t fit = (kScratchDoubles - kScrPart) / nslot;   // partial rows the scratch holds (>= 124)
+  const int blocks = (int)std::min<size_t>(std::min<size_t>(1024, (n + kVoxThreads - 1) / kVoxThreads), fit);
+  if (nb) UF_HIP_CHECK(hipMemcpyAsync(s + kScrBoxes, o.boxes, sizeof(double) * 7 * nb, hipMemcpyHostToDevice, stream));
+  if (nc)
+    UF_HIP_CHECK(hipMemcpyAsync(s + kScrCyls, o.cylinders, sizeof(double) * 6 * nc, hipMemcpyHostToDevice, stream));
+  const int ob = (nobj + kVoxThreads - 1) / kVoxThreads;
+  hipLaunchKernelGGL(k_pack_objects, dim3(ob), dim3(kVoxThreads), 0, stream, s + kScrBoxes, nb, s + kScrCyls, nc,
+                     s + kScrPacked);
+  hipLaunchKernelGGL(k_smooth_porosity_grad, dim3(blocks), dim3(kVoxThreads), sizeof(double) * nslot, stream,
+                     s + kScrPacked, nobj, o.nx, o.ny, o.nz, o.dx, o.dy, o.dz, o.width, phibar, s + kScrPart);
+  hipLaunchKernelGGL(k_sum_rows, dim3((ng + kVoxThreads - 1) / kVoxThreads), dim3(kVoxThreads), 0, stream,
+                     s + kScrPart, blocks, (int)nslot, nb, nc, s + kScrGrad);
+  UF_HIP_CHECK(hipGetLastError());
+  UF_HIP_CHECK(hipMemcpyAsync(grad, s + kScrGrad, sizeof(double) * ng, hipMemcpyDeviceToHost, stream));
+  UF_HIP_CHECK(hipStreamSynchronize(stream));
 }
 
 }  // namespace uf

@@ -928,6 +928,25 @@ uf_status uf_smooth_porosity_grad(const uf_smooth_objects* o, const double* phib
   UF_GUARD_END
 }
 
+uf_status uf_smooth_porosity_grad_noalloc(const uf_smooth_objects* o, const double* phibar_dev, double* grad_host,
+                                          void* stream) {
+  if (!o || !phibar_dev || !grad_host) return fail(UF_EINVAL, "NULL argument");
+  const std::string bad = check_smooth_objects(o);
+  if (!bad.empty()) return fail(UF_EINVAL, bad);
+  if ((long long)o->nboxes + o->ncyls > UF_NOALLOC_MAX_OBJECTS)
+    return fail(UF_EINVAL, "more objects than the allocation-free gradient's scratch holds (UF_NOALLOC_MAX_OBJECTS)");
+  UF_GUARD_BEGIN
+  if (stream) {
+    int sdev = -1, cur = -1;
+    UF_HIP_CHECK(hipStreamGetDevice((hipStream_t)stream, &sdev));
+    UF_HIP_CHECK(hipGetDevice(&cur));
+    if (sdev != cur) return fail(UF_EINVAL, "the stream belongs to another device than the current one");
+  }
+  smooth_porosity_grad_noalloc_run(*o, phibar_dev, grad_host, (hipStream_t)stream);
+  return UF_OK;
+  UF_GUARD_END
+}
+
 uf_status uf_set_stream(uf_grid g, void* stream) {
   if (!g) return fail(UF_EINVAL, "NULL grid");
   g->stream = (hipStream_t)stream;

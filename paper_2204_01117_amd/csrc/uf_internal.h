@@ -172,6 +172,8 @@ void launch_plane_objective(Grid& g, int k0, double t, double st, double smin, d
 std::string voxelize_run(const uf_mesh_set& m, int dtype, void* phi, hipStream_t stream, double* cast_ms);
 void smooth_porosity_run(const uf_smooth_objects& o, int dtype, void* phi, hipStream_t stream);
 void smooth_porosity_grad_run(const uf_smooth_objects& o, const double* phibar, double* grad, hipStream_t stream);
+void smooth_porosity_grad_noalloc_run(const uf_smooth_objects& o, const double* phibar, double* grad,
+                                      hipStream_t stream);
 // reverse (adjoint) stages
 template <class T> void launch_advect_adj(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Aout[3], void* const Gq[3], void* const Ghat[3]);
 template <class T> void launch_diffuse_adj(Grid& g, const Params<T>& P, void* const Aout[3], void* const Gin[3]);

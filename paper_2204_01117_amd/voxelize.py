@@ -80,11 +80,12 @@ def smooth_porosity(n, h, boxes, cylinders, width, dtype="f32", device="cuda:0")
     return out
 
 
-def smooth_porosity_grad(n, h, boxes, cylinders, width, phibar):
+def smooth_porosity_grad(n, h, boxes, cylinders, width, phibar, noalloc=False):
     """Reverse of ``smooth_porosity`` (uf_smooth_porosity_grad): from
     phibar = dJ/dphi (float64 [nx, ny, nz] on the GPU) to dJ/d(box rows)
     and dJ/d(cylinder rows), numpy arrays shaped like ``boxes`` (7 columns)
-    and ``cylinders`` (6 columns)."""
+    and ``cylinders`` (6 columns).  ``noalloc`` calls
+    uf_smooth_porosity_grad_noalloc, which allocates no device memory."""
     import numpy as np
     import torch
     assert phibar.dtype == torch.float64 and phibar.is_cuda and phibar.is_contiguous()
@@ -93,8 +94,8 @@ def smooth_porosity_grad(n, h, boxes, cylinders, width, phibar):
     nb, nc = len(boxes), len(cylinders)
     out = (ctypes.c_double * max(7 * nb + 6 * nc, 1))()
     stream = torch.cuda.current_stream(phibar.device).cuda_stream
-    L.check(L.uf_smooth_porosity_grad(ctypes.byref(o), ctypes.c_void_p(phibar.data_ptr()), out,
-                                      ctypes.c_void_p(stream)))
+    fn = L.uf_smooth_porosity_grad_noalloc if noalloc else L.uf_smooth_porosity_grad
+    L.check(fn(ctypes.byref(o), ctypes.c_void_p(phibar.data_ptr()), out, ctypes.c_void_p(stream)))
     del keep
     g = np.array(out[:7 * nb + 6 * nc], dtype=np.float64)
     return g[:7 * nb].reshape(nb, 7), g[7 * nb:].reshape(nc, 6)
