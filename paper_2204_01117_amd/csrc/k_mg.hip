@@ -541,6 +541,241 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
   }
 }
 
+// ------------------------- level-0 update and restriction, marching in x ---
+// The CG update of iteration t and the level-0 restriction of the
+// application that follows -- what k_mg_restrict<true> computes -- with the
+// work laid out as a march along x: a block owns CJ x CK coarse (j, k)
+// columns (their 2CJ x 2CK fine children) over a chunk of coarse x-planes
+// and walks the fine planes in order.  Per fine plane it forms
+// e = om D^-1 (r_t - alpha q) on the fine columns and two cells around them
+// (its own cells from the values the update loads anyway), keeps the last
+// three e planes in LDS, forms the residual of the pre-smoothed problem one
+// plane behind, and adds that plane's y/z restriction into the two coarse
+// planes it belongs to (x weights in tap order, as restrict_at adds them).
+// r_t and q are read once per plane and band (the 3-D boxes of
+// k_mg_restrict read them 2.5 times), and the block's working set is three
+// planes.  Every axis must be halved towards the coarse level.
+template <class T>
+struct XTile {
+  static constexpr int CJ = 8, CK = 32;            // coarse columns, one per thread
+  static constexpr int FJ = 2 * CJ, FK = 2 * CK;   // fine columns, four per thread
+  static constexpr int EJ = FJ + 4, EK = FK + 4;   // e plane: 2 cells around
+  static constexpr int RJ = FJ + 2, RK = FK + 2;   // residual plane: 1 cell around
+  static constexpr int NE = EJ * EK, NR = RJ * RK;
+  static constexpr int NRING = NE - FJ * FK;       // e entries around the fine columns
+  static constexpr int ROWS = 256 / FK;            // fine rows a pass of the block covers
+};
+
+// Restriction weights along one halved axis for coarse index X (taps 2X-1 ..
+// 2X+2; those past the level get 0), as k_mg_restrict's.
+template <class T>
+__device__ __forceinline__ void rweights(int X, int nc, int nf, T slo, T shi, T w[4]) {
+  w[0] = 2 * X - 1 >= 0 ? T(0.125) : T(0);
+  w[1] = T(0.5) * (T(0.75) + (X == 0 ? T(0.25) * slo : T(0)));
+  w[2] = 2 * X + 1 < nf ? T(0.5) * (T(0.75) + (X == nc - 1 ? T(0.25) * shi : T(0))) : T(0);
+  w[3] = 2 * X + 2 < nf ? T(0.125) : T(0);
+}
+
+// Position (ej, ek) in the e plane of ring entry q (the entries that are
+// not the block's fine columns): two full rows on each side, then two
+// entries at each end of the rows in between.
+template <class T>
+__device__ __forceinline__ void ring_pos(int q, int& ej, int& ek) {
+  using X = XTile<T>;
+  if (q < 2 * X::EK) {
+    ej = q / X::EK;
+    ek = q - ej * X::EK;
+  } else if (q < 4 * X::EK) {
+    const int r = q - 2 * X::EK;
+    ej = X::EJ - 2 + r / X::EK;
+    ek = r % X::EK;
+  } else {
+    const int r = q - 4 * X::EK, c4 = r & 3;
+    ej = 2 + (r >> 2);
+    ek = c4 < 2 ? c4 : X::EK - 4 + c4;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c,
+                                                         CgUpd<T> upd, int nci, int nkt, int nchunk, int ntot) {
+  using X = XTile<T>;
+  __shared__ T se[3][X::NE];
+  __shared__ T sres[X::NR];
+  __shared__ T tab_omd[64];
+  __shared__ T tab_a[64];
+  // the same decision and alpha as the stand-alone update kernel
+  double rz = 0.0, dq = 0.0;
+  bool run = iteration_open(c, upd.t);
+  if (run) {
+    rz = c.st->rzh[upd.t & 1];
+    run = rz_allows(c, rz);
+  }
+  if (run) {
+    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb_dq);
+    run = dq > 0.0 && isfinite(dq);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.exec[upd.t] = run;
+    if (run) c.st->iter = upd.t + 1;
+  }
+  if (!run) return;
+  const T alpha = (T)(rz / dq);
+  if (threadIdx.x < 64) {
+    const T D = class_diag(K, F, threadIdx.x);
+    tab_omd[threadIdx.x] = D > T(0) ? K.om / D : T(0);
+    tab_a[threadIdx.x] = (T(1) - K.om) * D / K.om;
+  }
+  const Layout& L = F.L;
+  double acc_rr[1] = {0.0};
+  // logical block: XCD-contiguous ranges of (j tile, k tile, chunk)
+  const int per = (int)(gridDim.x >> 3);
+  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (lb < ntot) {
+    const int tile = lb / nchunk, ch = lb - tile * nchunk;
+    const int jt = tile / nkt, kt = tile - jt * nkt;
+    const int J0 = jt * X::CJ, K0 = kt * X::CK;
+    const int j0 = 2 * J0, k0 = 2 * K0;
+    const int I0 = ch * nci, I1 = min(C.L.nx, I0 + nci);
+    const int own0 = 2 * I0, own1 = min(2 * I1, L.nx);   // fine planes this block updates
+    const int tid = threadIdx.x;
+    const int kk = tid % X::FK, jr = tid / X::FK;
+    const int k = k0 + kk;
+    const int kg = clampg(k, L.nz);
+    const bool kin = k < L.nz;
+    // own column rows j0 + jr + ROWS u
+    int jg[4];
+    bool jin[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + jr + X::ROWS * u;
+      jg[u] = clampg(j, L.ny);
+      jin[u] = j < L.ny;
+    }
+    // ring entries of this thread (at most two)
+    int rq[2], rjg[2], rkg[2], rpos[2];
+    bool ron[2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int q = tid + 256 * v;
+      ron[v] = q < X::NRING;
+      int ej = 0, ek = 0;
+      if (ron[v]) ring_pos<T>(q, ej, ek);
+      rq[v] = q;
+      rjg[v] = clampg(j0 - 2 + ej, L.ny);
+      rkg[v] = clampg(k0 - 2 + ek, L.nz);
+      rpos[v] = ej * X::EK + ek;
+    }
+    // the coarse column of the restriction
+    const int tj = tid / X::CK, tk = tid - tj * X::CK;
+    const int J = J0 + tj, Kc = K0 + tk;
+    const bool cin = J < C.L.ny && Kc < C.L.nz;
+    T wj[4], wk[4];
+    rweights(J, C.L.ny, L.ny, K.sgn[2], K.sgn[3], wj);
+    rweights(Kc, C.L.nz, L.nz, K.sgn[4], K.sgn[5], wk);
+    // plane values in registers: own r_t, q (and x, d on updated planes), ring r_t, q
+    T orr[4], oq[4], ox[4], od[4], rr_[2], rq_[2];
+    auto load_plane = [&](int f) {
+      const int fg = clampg(f, L.nx);
+      const bool upd_plane = f >= own0 && f < own1;
+      const long long base = (long long)(fg + 1) * L.SX;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long o = base + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
+        orr[u] = upd.Rin[o];
+        oq[u] = upd.Q[o];
+        const bool live = upd_plane && jin[u] && kin;
+        ox[u] = live ? upd.X[o] : T(0);
+        od[u] = live ? upd.D[o] : T(0);
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const long long o = base + (long long)(rjg[v] + 1) * L.PZ + (rkg[v] + 1);
+        rr_[v] = ron[v] ? upd.Rin[o] : T(0);
+        rq_[v] = ron[v] ? upd.Q[o] : T(0);
+      }
+    };
+    const int fe0 = 2 * I0 - 2, fe1 = 2 * I1 + 1;   // e planes
+    load_plane(fe0);
+    __syncthreads();   // tables in place
+    T wi_cur[4], wi_prev[4];
+    int Icur = I0;
+    rweights(Icur, C.L.nx, L.nx, K.sgn[0], K.sgn[1], wi_cur);
+    rweights(Icur - 1, C.L.nx, L.nx, K.sgn[0], K.sgn[1], wi_prev);
+    T acc_cur = T(0), acc_prev = T(0);
+    for (int f = fe0; f <= fe1; ++f) {
+      T* e = se[(f + 3) % 3];
+      const int cx = bclass(f, L.nx) << 4;
+      const bool upd_plane = f >= own0 && f < own1;
+      // own cells: the update, then e from the updated residual
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T r = orr[u] - alpha * oq[u];
+        const int jj = jr + X::ROWS * u;
+        const int cl = cx | (bclass(j0 + jj, L.ny) << 2) | bclass(k, L.nz);
+        e[(jj + 2) * X::EK + kk + 2] = tab_omd[cl] * r;
+        if (upd_plane && jin[u] && kin) {
+          const long long o = (long long)(f + 1) * L.SX + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
+          upd.X[o] = ox[u] + alpha * od[u];
+          F.r[o] = r;
+          acc_rr[0] += (double)r * (double)r;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (!ron[v]) continue;
+        const int ej = rpos[v] / X::EK, ek = rpos[v] - ej * X::EK;
+        const int cl = cx | (bclass(j0 - 2 + ej, L.ny) << 2) | bclass(k0 - 2 + ek, L.nz);
+        e[rpos[v]] = tab_omd[cl] * (rr_[v] - alpha * rq_[v]);
+      }
+      if (f < fe1) load_plane(f + 1);
+      __syncthreads();
+      // residual of plane f - 1 from the e planes f - 2, f - 1, f
+      const int fr = f - 1;
+      if (fr < 2 * I0 - 1) continue;
+      {
+        const T* em = se[(fr + 2) % 3];
+        const T* ec = se[(fr + 3) % 3];
+        const T* ep = e;
+        const int crx = bclass(fr, L.nx) << 4;
+        for (int q = tid; q < X::NR; q += 256) {
+          const int rj = q / X::RK, rk = q - rj * X::RK;
+          const int pe = (rj + 1) * X::EK + rk + 1;
+          const int cl = crx | (bclass(j0 - 1 + rj, L.ny) << 2) | bclass(k0 - 1 + rk, L.nz);
+          sres[q] = tab_a[cl] * ec[pe] + F.w[0] * (ep[pe] + em[pe]) + F.w[1] * (ec[pe + X::EK] + ec[pe - X::EK]) +
+                    F.w[2] * (ec[pe + 1] + ec[pe - 1]);
+        }
+      }
+      __syncthreads();
+      // y/z restriction of the residual plane, added to its two coarse planes
+      const int In = (fr + 1) >> 1;
+      if (In != Icur) {
+        // coarse plane Icur - 1 has all four taps
+        if (cin && Icur - 1 >= I0 && Icur - 1 < I1) C.r[C.L.at(Icur - 1, J, Kc)] = acc_prev;
+        acc_prev = acc_cur;
+        acc_cur = T(0);
+        Icur = In;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) wi_prev[a] = wi_cur[a];
+        rweights(Icur, C.L.nx, L.nx, K.sgn[0], K.sgn[1], wi_cur);
+      }
+      T sa = T(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const T* row = sres + (2 * tj + b) * X::RK + 2 * tk;
+        sa += wj[b] * (wk[0] * row[0] + wk[1] * row[1] + wk[2] * row[2] + wk[3] * row[3]);
+      }
+      const int a = fr + 1 - 2 * Icur;   // 0 or 1 for Icur, a + 2 for Icur - 1
+      acc_cur += wi_cur[a] * sa;
+      acc_prev += wi_prev[a + 2] * sa;
+    }
+    if (cin && Icur - 1 >= I0 && Icur - 1 < I1) C.r[C.L.at(Icur - 1, J, Kc)] = acc_prev;
+  }
+  const int slots[1] = {S_RR};
+  write_partials<1>(acc_rr, c.part, c.stride, slots, (int)blockIdx.x);
+  pad_partials(c, S_RR, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // Tile of the up/smoothing kernel (cells of its level per block of 256).
 template <int TI_, int TJ_, int TK_>
 struct UpTile {
@@ -1183,6 +1418,29 @@ static void launch_restrict(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, co
     launch_k(g, k_mg_restrict<false, T>, dim3(G), dim3(256), K, F, C, has_coarse, c, m, mode, nt3, CgUpd<T>{});
 }
 
+// Launch geometry of the marching update + restriction: coarse column
+// tiles of 8 x 32, x-chunks of nci coarse planes, about 1024 blocks.  It
+// is taken when every axis of level 0 is halved and the coarse level is at
+// least 32 cells deep (narrower tiles would leave most threads idle).
+struct MarchGeom {
+  int nci = 0, nkt = 0, nchunk = 0, ntot = 0;
+  bool use = false;
+};
+
+static MarchGeom march_geom(const MgLevel& F, const MgLevel& C) {
+  MarchGeom m;
+  if (!(F.coarsen[0] && F.coarsen[1] && F.coarsen[2]) || C.L.nz < 32) return m;
+  const int njt = (C.L.ny + 7) / 8, nkt = (C.L.nz + 31) / 32;
+  const int tiles = njt * nkt;
+  const int want = std::max(1, std::min(C.L.nx, (1024 + tiles - 1) / tiles));
+  m.nci = (C.L.nx + want - 1) / want;
+  m.nchunk = (C.L.nx + m.nci - 1) / m.nci;
+  m.nkt = nkt;
+  m.ntot = tiles * m.nchunk;
+  m.use = true;
+  return m;
+}
+
 // Blocks of the level-0 restriction when it carries the CG update (the
 // writer of the r.r partials besides the CG kernels), or 0 when the update
 // stays separate: it needs a coarse restriction kernel after it to decide
@@ -1190,6 +1448,8 @@ static void launch_restrict(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, co
 size_t mg_fused_blocks(const Grid& g) {
   const int nl = (int)g.mg.size();
   if (g.cfg.precond != UF_PC_MG || nl < 3 || std::min(g.mg_lt, nl - 1) < 2) return 0;
+  const MarchGeom mg = march_geom(g.mg[0], g.mg[1]);
+  if (mg.use) return (size_t)(8 * ((mg.ntot + 7) / 8));
   const Layout& C = g.mg[1].L;
   const int3 nt3 = g.esize == 4 ? restrict_tiles<float>(C) : restrict_tiles<double>(C);
   return (size_t)level_blocks((long long)nt3.x * nt3.y * nt3.z);
@@ -1226,7 +1486,12 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
   {
     TimedLaunch tl(g, upd ? UF_TK_MG_UPDATE0 : UF_TK_MG_DOWN0);
-    launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2, upd);
+    const MarchGeom mgeo = (upd && nl > 1) ? march_geom(g.mg[0], g.mg[1]) : MarchGeom{};
+    if (mgeo.use)
+      launch_k(g, k_mg_update_march<T>, dim3(8 * ((mgeo.ntot + 7) / 8)), dim3(256), K, L0, L1, c, *upd, mgeo.nci,
+               mgeo.nkt, mgeo.nchunk, mgeo.ntot);
+    else
+      launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2, upd);
   }
   const int lt = std::min(g.mg_lt, nl - 1);
   for (int l = 1; l < lt; ++l) {
