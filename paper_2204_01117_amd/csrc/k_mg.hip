@@ -923,6 +923,205 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
   }
 }
 
+// ---------------- level-0 prolongation and post-smoothing, marching in x ---
+// What k_mg_upsmooth<true, true, true> computes on level 0, laid out as a
+// march along x: a block owns 16 x 64 fine (j, k) columns over a chunk of
+// planes.  Per coarse plane I it forms the y/z interpolation Y(I) of the
+// correction on the columns and one cell around (the coarse taps of each
+// position fixed for the whole march), keeping three such planes in LDS;
+// per fine plane it forms t = om D^-1 r + P x_c from the two Y planes of
+// its parent and the parent's neighbour, keeping three t planes in LDS
+// (the own columns' t also in registers), and one plane behind it the
+// smoothed z = t + om D^-1 (r - A t) and the r.z partial.  r is read once
+// per plane and band, and one barrier separates the planes.
+struct UTile {
+  static constexpr int FJ = 16, FK = 64;           // fine columns, four per thread
+  static constexpr int TJ = FJ + 2, TK = FK + 2;   // t and Y planes: 1 cell around
+  static constexpr int NT = TJ * TK;
+  static constexpr int ROWS = 256 / FK;
+  static constexpr int PER = (NT + 255) / 256;     // region entries per thread
+};
+
+// The march applies to level 0 when every axis halves towards level 1 and
+// the columns fill the tile's depth.
+static bool up_march(const Layout& L) {
+  return L.nx >= 4 && L.ny >= 4 && L.nz >= UTile::FK && (long long)L.nx * L.ny * L.nz > kCoarsestCells;
+}
+
+struct UpGeom {
+  int nfi, nkt, nchunk, ntot;
+};
+
+static UpGeom up_geom(const Layout& L) {
+  UpGeom u;
+  const int njt = (L.ny + UTile::FJ - 1) / UTile::FJ;
+  u.nkt = (L.nz + UTile::FK - 1) / UTile::FK;
+  const int tiles = njt * u.nkt;
+  const int want = std::max(1, std::min(L.nx, (1024 + tiles - 1) / tiles));
+  u.nfi = (L.nx + want - 1) / want;
+  u.nchunk = (L.nx + u.nfi - 1) / u.nfi;
+  u.ntot = tiles * u.nchunk;
+  return u;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m,
+                                                           int nfi, int nkt, int nchunk, int ntot) {
+  using U = UTile;
+  constexpr int NRING = U::NT - U::FJ * U::FK;   // region entries around the fine columns
+  __shared__ T sy[3][U::NT];
+  __shared__ T st[3][U::NT];
+  __shared__ T tab_d[64];
+  __shared__ T tab_omd[64];
+  // coarse taps of the region's rows (y) and columns (z): offsets and weights
+  __shared__ int rt_o[U::TJ][2];
+  __shared__ T rt_w[U::TJ][2];
+  __shared__ int ct_o[U::TK][2];
+  __shared__ T ct_w[U::TK][2];
+  if (c.flags[m]) return;   // the solve has finished (uniform over the grid)
+  fill_class_tables<T>(K, F, tab_d, tab_omd);
+  const Layout& L = F.L;
+  const Layout& CL = C.L;
+  double acc[1] = {0.0};
+  const int per = (int)(gridDim.x >> 3);
+  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (lb < ntot) {
+    const int tile = lb / nchunk, ch = lb - tile * nchunk;
+    const int jt = tile / nkt, kt = tile - jt * nkt;
+    const int j0 = jt * U::FJ, k0 = kt * U::FK;
+    const int i0 = ch * nfi, i1 = min(L.nx, i0 + nfi);
+    const int tid = threadIdx.x;
+    if (tid < U::TJ) {
+      const Tap2<T> b = ptap(j0 - 1 + tid, 1, CL.ny, K.sgn[2], K.sgn[3]);
+      rt_o[tid][0] = (clampg(b.i0, CL.ny) + 1) * CL.PZ;
+      rt_o[tid][1] = (clampg(b.i1, CL.ny) + 1) * CL.PZ;
+      rt_w[tid][0] = b.w0;
+      rt_w[tid][1] = b.w1;
+    } else if (tid >= 64 && tid < 64 + U::TK) {
+      const Tap2<T> e = ptap(k0 - 1 + tid - 64, 1, CL.nz, K.sgn[4], K.sgn[5]);
+      ct_o[tid - 64][0] = clampg(e.i0, CL.nz) + 1;
+      ct_o[tid - 64][1] = clampg(e.i1, CL.nz) + 1;
+      ct_w[tid - 64][0] = e.w0;
+      ct_w[tid - 64][1] = e.w1;
+    }
+    // the thread's region entries: its four fine columns (rows jr + ROWS u)
+    // and at most one entry of the ring around them
+    const int kk = tid % U::FK, jr = tid / U::FK;
+    int ej[5], ek[5];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ej[u] = jr + U::ROWS * u + 1;
+      ek[u] = kk + 1;
+    }
+    const bool ring = tid < NRING;
+    {
+      const int q = ring ? tid : 0;
+      if (q < U::TK) {
+        ej[4] = 0;
+        ek[4] = q;
+      } else if (q < 2 * U::TK) {
+        ej[4] = U::TJ - 1;
+        ek[4] = q - U::TK;
+      } else {
+        const int r = q - 2 * U::TK;
+        ej[4] = 1 + (r >> 1);
+        ek[4] = (r & 1) ? U::TK - 1 : 0;
+      }
+    }
+    int pos[5], cyz[5];
+    bool in[5];
+    long long ro[5];   // offset of (j, k) within a fine plane (clamped into the ghosts)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const int j = j0 - 1 + ej[v], k = k0 - 1 + ek[v];
+      pos[v] = ej[v] * U::TK + ek[v];
+      cyz[v] = (bclass(j, L.ny) << 2) | bclass(k, L.nz);
+      in[v] = (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz && (v < 4 || ring);
+      ro[v] = (long long)(clampg(j, L.ny) + 1) * L.PZ + (clampg(k, L.nz) + 1);
+    }
+    __syncthreads();   // tap tables in place
+    // Y(I) at the region: the y/z interpolation of coarse plane I
+    auto make_y = [&](int I) {
+      T* y = sy[(I + 3) % 3];
+      const T* xc = C.x + (long long)(clampg(I, CL.nx) + 1) * CL.SX;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        if (v == 4 && !ring) continue;
+        const int r0 = rt_o[ej[v]][0], r1 = rt_o[ej[v]][1], q0 = ct_o[ek[v]][0], q1 = ct_o[ek[v]][1];
+        const T bw0 = rt_w[ej[v]][0], bw1 = rt_w[ej[v]][1], ew0 = ct_w[ek[v]][0], ew1 = ct_w[ek[v]][1];
+        y[pos[v]] = bw0 * (ew0 * xc[r0 + q0] + ew1 * xc[r0 + q1]) + bw1 * (ew0 * xc[r1 + q0] + ew1 * xc[r1 + q1]);
+      }
+    };
+    T rv[5];
+    auto load_r = [&](int i) {
+      const T* rp = F.r + (long long)(clampg(i, L.nx) + 1) * L.SX;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) rv[v] = (v < 4 || ring) ? rp[ro[v]] : T(0);
+    };
+    const int ts = i0 - 1, te = i1;   // t planes of the chunk
+    int ymax = (ts >> 1) + 1;
+    for (int I = (ts >> 1) - 1; I <= ymax; ++I) make_y(I);
+    load_r(ts);
+    T tm[4], tc[4], tn[4], rc[4], rn[4];   // own t(i-2), t(i-1), t(i); own r(i-1), r(i)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tm[u] = tc[u] = tn[u] = rc[u] = rn[u] = T(0);
+    for (int i = ts; i <= te; ++i) {
+      __syncthreads();   // the Y planes of plane i are in place; t slot i % 3 is free
+      const Tap2<T> a = ptap(i, 1, CL.nx, K.sgn[0], K.sgn[1]);
+      const T* ya = sy[(a.i0 + 3) % 3];
+      const T* yb = sy[(a.i1 + 3) % 3];
+      T* t = st[(i + 3) % 3];
+      const bool iin = (unsigned)i < (unsigned)L.nx;
+      const int cx = bclass(i, L.nx) << 4;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        if (v == 4 && !ring) continue;
+        const T tv = (iin && in[v]) ? tab_omd[cx | cyz[v]] * rv[v] + a.w0 * ya[pos[v]] + a.w1 * yb[pos[v]] : T(0);
+        t[pos[v]] = tv;
+        if (v < 4) {
+          tn[v] = tv;
+          rn[v] = rv[v];
+        }
+      }
+      if (i < te) {
+        load_r(i + 1);
+        // an odd next plane needs the coarse plane past the ones held
+        const int need = ((i + 1) & 1) ? ((i + 1) >> 1) + 1 : ((i + 1) >> 1);
+        if (need > ymax) {
+          ymax = need;
+          make_y(ymax);
+        }
+      }
+      __syncthreads();
+      // z of plane i - 1 on the own columns, from t(i-2), t(i-1), t(i)
+      const int iz = i - 1;
+      if (iz >= i0 && iz < i1) {
+        const T* tp = st[(iz + 3) % 3];
+        const int czx = bclass(iz, L.nx) << 4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!in[u]) continue;
+          const int cl = czx | cyz[u];
+          const int q = pos[u];
+          const T At = tab_d[cl] * tc[u] - F.w[0] * (tn[u] + tm[u]) - F.w[1] * (tp[q + U::TK] + tp[q - U::TK]) -
+                       F.w[2] * (tp[q + 1] + tp[q - 1]);
+          const T z = tc[u] + tab_omd[cl] * (rc[u] - At);
+          F.x[(long long)(iz + 1) * L.SX + ro[u]] = z;
+          acc[0] += (double)rc[u] * (double)z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        tm[u] = tc[u];
+        tc[u] = tn[u];
+        rc[u] = rn[u];
+      }
+    }
+  }
+  const int slots[1] = {S_RZ0 + (m & 1)};
+  write_partials<1>(acc, c.part, c.stride, slots, (int)blockIdx.x);
+}
+
 // Levels of at most `cells` cells run in the single-workgroup kernel, with
 // r, x and t of all of them in an LDS pool of `pool` cells per array (a
 // hierarchy whose small levels need more takes the global-memory variant).
@@ -1396,6 +1595,7 @@ static int level_blocks(long long nt) {
 
 // Blocks of the fine up/smoothing kernel (one r.z partial each).
 size_t mg_fine_blocks(const Layout& L) {
+  if (up_march(L)) return (size_t)(8 * ((up_geom(L).ntot + 7) / 8));
   const int3 t = big_tile(L) ? up_tiles<UpBig>(L) : up_tiles<UpSmall>(L);
   return (size_t)level_blocks((long long)t.x * t.y * t.z);
 }
@@ -1517,7 +1717,11 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
     }
   }
   TimedLaunch tl(g, UF_TK_MG_UP0);
-  if (nl > 1)
+  if (nl > 1 && up_march(L0.L)) {
+    const UpGeom u = up_geom(L0.L);
+    launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(256), K, L0, L1, c, m, u.nfi, u.nkt,
+             u.nchunk, u.ntot);
+  } else if (nl > 1)
     launch_up<true, true, T>(g, K, L0, L1, c, m);
   else
     launch_up<true, false, T>(g, K, L0, L1, c, m);
