@@ -311,6 +311,49 @@ uf_status uf_step(uf_grid g, int32_t nsteps, uf_step_stats* stats);
  * or UF_ENONFINITE as uf_step, naming the first such batch entry. */
 uf_status uf_step_batch(const uf_grid* grids, int32_t n, int32_t nsteps, uf_step_stats* stats);
 
+/* A batch: n grids advanced together with one launch per stage for all of
+ * them (the same cases as uf_step_batch; the paper's wind-direction and
+ * design studies, Sec. 4 and 5).  Each face stage of the step (MacCormack
+ * predictor and corrector, diffusion, drag, projection) and the k-omega
+ * update is one kernel walking a single queue of every case's blocks.
+ * Each case's pressure solve (its start from the drag output and a
+ * captured number of CG iterations -- the last solve's count plus two;
+ * iterations past convergence return at once) is a hipGraph of its own,
+ * replayed on the case's own stream so that the cases' solves overlap; the
+ * face stages before it and the projection and k-omega update after it are
+ * two more hipGraphs.  Between the solves and the back half the host reads
+ * every case's solve status and enqueues further iterations for a case
+ * that needs them (that case's solve is then captured again, longer).  Each
+ * grid computes exactly what uf_step computes for it, bit for bit.
+ *
+ * uf_batch_create: 1 to UF_BATCH_MAX_GRIDS grids (not owned; they must
+ * outlive the batch and keep their buffers) that share one dtype, run
+ * every stage of the step, all with or all without the k-omega update, and
+ * have fields below 4 GiB; UF_EINVAL otherwise (nothing created).  The batch makes its own streams;
+ * a call orders them after each grid's stream and the grid's stream after
+ * them.  uf_batch_step: nsteps steps; the grids must hold their state as
+ * full steps leave it (uf_step or uf_batch_step with every stage) and have
+ * kernel timers off (UF_EINVAL otherwise); stats as uf_step_batch.
+ * uf_batch_autotune: times each stage's launch for band widths of 4, 8 and
+ * 16 blocks (blocks of one band of the (j, k) points walk x together) and
+ * for persistent grids of 2, 4 or 8 blocks per compute unit or one block
+ * per queue entry, on the sets a step overwrites (the state is only read),
+ * keeps the fastest of three runs for each stage, and reports the choice
+ * (stages: predictor, corrector, diffusion, drag, projection, k-omega;
+ * blocks 0 = one per queue entry) when out is non-NULL.  Until it is
+ * called every stage uses bands of 8 and one block per queue entry. */
+#define UF_BATCH_MAX_GRIDS 64
+typedef struct uf_batch_s* uf_batch;
+typedef struct {
+  int32_t band[6];
+  int32_t blocks[6];
+  float ms[6];
+} uf_batch_tuning;
+uf_status uf_batch_create(const uf_grid* grids, int32_t n, uf_batch* out);
+uf_status uf_batch_autotune(uf_batch b, uf_batch_tuning* out);
+uf_status uf_batch_step(uf_batch b, int32_t nsteps, uf_step_stats* stats);
+uf_status uf_batch_destroy(uf_batch b);
+
 /* Solve A x = b with the grid's pressure operator (A = -L_h with the
  * boundary rows described above; SPD), preconditioner and tolerance; x_dev
  * holds the initial guess on entry and the solution on exit (a guess whose

@@ -14,8 +14,9 @@ from ._lib import (uf_create_grid, uf_destroy_grid, uf_set_porosity, uf_set_fiel
                    uf_apply_operator, uf_objective, uf_adjoint_step, uf_adjoint_step_at, uf_set_stream,
                    uf_kernel_timer_enable, uf_kernel_timer_read, uf_last_error, TIMED_KERNELS,
                    uf_voxelize, uf_step_batch, uf_smooth_porosity, uf_smooth_porosity_grad,
-                   uf_smooth_porosity_grad_noalloc, uf_smooth_objects)
-from .grid import Grid, step_batch
+                   uf_smooth_porosity_grad_noalloc, uf_smooth_objects, uf_batch_create, uf_batch_autotune,
+                   uf_batch_step, uf_batch_destroy, uf_batch_tuning)
+from .grid import Grid, step_batch, Batch
 from .voxelize import voxelize, smooth_porosity, smooth_porosity_grad
 from .design import BoxDesign
 from .optimize import (SimulationObjective, AdjointObjective, design_objective, forward_difference_gradient,
@@ -24,7 +25,8 @@ from .optimize import (SimulationObjective, AdjointObjective, design_objective, 
 __all__ = ["lib", "LIB_PATH", "UFError", "uf_config", "uf_step_stats", "make_config",
            "uf_objective_spec", "make_objective_spec", "uf_mesh_set", "uf_voxelize", "voxelize", "uf_step_batch",
            "step_batch", "uf_smooth_porosity", "uf_smooth_porosity_grad", "uf_smooth_porosity_grad_noalloc",
-           "uf_smooth_objects", "smooth_porosity",
+           "uf_smooth_objects", "uf_batch_create", "uf_batch_autotune", "uf_batch_step", "uf_batch_destroy",
+           "uf_batch_tuning", "Batch", "smooth_porosity",
            "smooth_porosity_grad", "BoxDesign", "SimulationObjective", "AdjointObjective", "design_objective",
            "forward_difference_gradient", "gradient_descent",
            "STATUS", "FIELDS", "FIELD_IDS", "Grid",

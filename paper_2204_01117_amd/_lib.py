@@ -38,6 +38,10 @@ class uf_step_stats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class uf_batch_tuning(ctypes.Structure):
+    _fields_ = [("band", c_int32 * 6), ("blocks", c_int32 * 6), ("ms", c_float * 6)]
+
+
 OBJ_REGIONS, OBJ_PLANE, OBJ_FIELD = 0, 1, 2
 
 
@@ -116,6 +120,10 @@ _SIGS = {
     "uf_adjoint_step_at": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "uf_set_stream": (c_int32, [c_void_p, c_void_p]),
     "uf_step_batch": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p]),
+    "uf_batch_create": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p)]),
+    "uf_batch_autotune": (c_int32, [c_void_p, POINTER(uf_batch_tuning)]),
+    "uf_batch_step": (c_int32, [c_void_p, c_int32, c_void_p]),
+    "uf_batch_destroy": (c_int32, [c_void_p]),
     "uf_smooth_porosity": (c_int32, [POINTER(uf_smooth_objects), c_int32, c_void_p, c_void_p]),
     "uf_smooth_porosity_grad": (c_int32, [POINTER(uf_smooth_objects), c_void_p, POINTER(c_double), c_void_p]),
     "uf_smooth_porosity_grad_noalloc": (c_int32, [POINTER(uf_smooth_objects), c_void_p, POINTER(c_double),
@@ -145,6 +153,10 @@ uf_adjoint_step = lib.uf_adjoint_step
 uf_adjoint_step_at = lib.uf_adjoint_step_at
 uf_set_stream = lib.uf_set_stream
 uf_step_batch = lib.uf_step_batch
+uf_batch_create = lib.uf_batch_create
+uf_batch_autotune = lib.uf_batch_autotune
+uf_batch_step = lib.uf_batch_step
+uf_batch_destroy = lib.uf_batch_destroy
 uf_smooth_porosity = lib.uf_smooth_porosity
 uf_smooth_porosity_grad = lib.uf_smooth_porosity_grad
 uf_smooth_porosity_grad_noalloc = lib.uf_smooth_porosity_grad_noalloc

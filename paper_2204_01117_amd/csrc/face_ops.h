@@ -211,11 +211,10 @@ constexpr int kFaceBand = 8;
 
 // Logical block (bx, i) of a face kernel launched on xcd_grid(face_gx, nx
 // + 1): every XCD takes a contiguous range of the logical order, as
-// xcd_block(), but that order walks the planes i of one band of kFaceBand
-// blocks (2048 (j, k) points, the last band narrower) before the next band.
-// The blocks in flight on an XCD then cover a few dozen planes of one band,
-// and the neighbouring planes a trace or stencil reads stay in that XCD's
-// L2 (plane by plane over the whole (j, k) range, the six arrays of three
+// xcd_block(), and that order is band-major (band_map), so the blocks in
+// flight on an XCD cover a few dozen planes of one band and the
+// neighbouring planes a trace or stencil reads stay in that XCD's L2
+// (plane by plane over the whole (j, k) range, the six arrays of three
 // neighbouring planes of a 512x128 cross-section are 4.8 MB, more than the
 // 4 MB L2).  False for padding blocks.
 __device__ __forceinline__ bool face_block(const Layout& L, int& bx, int& i) {
@@ -223,30 +222,24 @@ __device__ __forceinline__ bool face_block(const Layout& L, int& bx, int& i) {
   const int per = (int)(gridDim.x >> 3);
   const int b = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
   if (b >= gx * gy) return false;
-  const int bw = min(kFaceBand, gx);
-  const int nfull = gx / bw;                 // bands of bw blocks
-  const int full = nfull * bw * gy;          // logical blocks in them
-  if (b < full) {
-    const int band = b / (bw * gy), rem = b - band * bw * gy;
-    i = rem / bw;
-    bx = band * bw + (rem - i * bw);
-  } else {
-    const int wl = gx - nfull * bw, rem = b - full;   // the last, narrower band
-    i = rem / wl;
-    bx = nfull * bw + (rem - i * wl);
-  }
+  band_map(gx, gy, kFaceBand, b, bx, i);
   return true;
 }
 
-// A thread owns the three faces at corner (i, j, k); logical block (bx, i).
-#define UF_FACE_THREAD(L)                                            \
-  int f_bx, f_by;                                                    \
-  if (!face_block((L), f_bx, f_by)) return;                          \
-  const int i = f_by;                                                \
-  const int p = f_bx * kFaceBlock + threadIdx.x;                     \
+// A thread owns the three faces at corner (i, j, k) of logical block (bx,
+// iplane); threads past the plane's corners return.
+#define UF_FACE_POINT(L, bx, iplane)                                 \
+  const int i = (iplane);                                            \
+  const int p = (bx) * kFaceBlock + threadIdx.x;                     \
   if (p >= ((L).ny + 1) * ((L).nz + 1)) return;                      \
   const int j = p / ((L).nz + 1);                                    \
   const int k = p - j * ((L).nz + 1);
+
+// The same for a kernel of one grid (the logical block from face_block).
+#define UF_FACE_THREAD(L)                                            \
+  int f_bx, f_by;                                                    \
+  if (!face_block((L), f_bx, f_by)) return;                          \
+  UF_FACE_POINT(L, f_bx, f_by)
 
 // Each kernel computes the values of the thread's three faces first, with
 // every load unconditional (all positions read lie in the padded arrays,

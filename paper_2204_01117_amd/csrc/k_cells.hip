@@ -11,15 +11,32 @@ constexpr int kCellBlock = 256;
 
 __host__ __device__ inline int cell_gx(const Layout& L) { return (L.ny * L.nz + kCellBlock - 1) / kCellBlock; }
 
-// A thread owns cell (i, j, k); logical block (bx, i).
-#define UF_CELL_THREAD(L)                                            \
-  int c_bx, c_by;                                                    \
-  if (!xcd_block(cell_gx(L), (L).nx, c_bx, c_by)) return;            \
-  const int i = c_by;                                                \
-  const int p = c_bx * kCellBlock + threadIdx.x;                     \
+// Logical block (bx, i) of a cell kernel launched on xcd_grid(cell_gx, nx):
+// XCD-contiguous ranges of the band-major order (band_map), as the face
+// kernels, so that the x-neighbours a stencil reads stay in the XCD's L2.
+constexpr int kCellBand = 8;
+__device__ __forceinline__ bool cell_block(const Layout& L, int& bx, int& i) {
+  const int gx = cell_gx(L), gy = L.nx;
+  const int per = (int)(gridDim.x >> 3);
+  const int b = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (b >= gx * gy) return false;
+  band_map(gx, gy, kCellBand, b, bx, i);
+  return true;
+}
+
+// A thread owns cell (i, j, k) of logical block (bx, iplane); threads past
+// the plane's cells return.
+#define UF_CELL_POINT(L, bx, iplane)                                 \
+  const int i = (iplane);                                            \
+  const int p = (bx) * kCellBlock + threadIdx.x;                     \
   if (p >= (L).ny * (L).nz) return;                                  \
   const int j = p / (L).nz;                                          \
   const int k = p - j * (L).nz;
+
+#define UF_CELL_THREAD(L)                                            \
+  int c_bx, c_by;                                                    \
+  if (!cell_block((L), c_bx, c_by)) return;                          \
+  UF_CELL_POINT(L, c_bx, c_by)
 
 // k-omega step at one cell.  Velocity gradients: normal derivatives from the
 // cell's two faces, cross derivatives as central differences of cell-centred
@@ -30,13 +47,9 @@ __host__ __device__ inline int cell_gx(const Layout& L) { return (L.ny * L.nz + 
 // viscosity limiter).  Forward Euler with first-order upwind advection and
 // central Laplacians.
 template <class T>
-__global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T* __restrict__ U,
-                                                           const T* __restrict__ V, const T* __restrict__ W,
-                                                           const T* __restrict__ K0, const T* __restrict__ W0,
-                                                           T* __restrict__ K1, T* __restrict__ W1,
-                                                           T* __restrict__ NUT, int update_kw, int* nf) {
+__device__ __forceinline__ void turb_cells(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ K0, const T* __restrict__ W0, T* __restrict__ K1, T* __restrict__ W1, T* __restrict__ NUT, int update_kw, int* nf, int bx, int ib) {
   const Layout& L = P.L;
-  UF_CELL_THREAD(L);
+  UF_CELL_POINT(L, bx, ib);
   const long long SX = L.SX, PZ = L.PZ;
   const long long o = L.at(i, j, k);
   const T h0 = T(0.5) * P.ih[0], h1 = T(0.5) * P.ih[1], h2 = T(0.5) * P.ih[2];
@@ -84,6 +97,13 @@ __global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T*
   store_cell(K1, P, i, j, k, kn, true, P.k_in);
   store_cell(W1, P, i, j, k, wn, true, P.w_in);
   store_cell(NUT, P, i, j, k, nut_new, false, T(0));
+}
+
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ K0, const T* __restrict__ W0, T* __restrict__ K1, T* __restrict__ W1, T* __restrict__ NUT, int update_kw, int* nf) {
+  int bx, ib;
+  if (!cell_block(P.L, bx, ib)) return;
+  turb_cells(P, U, V, W, K0, W0, K1, W1, NUT, update_kw, nf, bx, ib);
 }
 
 // Drag coefficient of each cell: C_d a ((1 - phi)/(phi + e))^b (Sec. 3 drag
@@ -256,6 +276,41 @@ void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, 
                      nf_word(g));
 }
 
+// The k-omega update of every case of a batch in one persistent launch
+// (the cell queue: case c owns [cell0, cell0 + cell_gx * nx)); velocity
+// from set sq, k and omega of case c from slot kcs[c] to the other slot,
+// nu_t into the case's own array, or into set nut_set's u array when
+// nut_set >= 0 (a trial run that leaves the state alone).
+template <class T>
+__global__ __launch_bounds__(kCellBlock) void k_turb_multi(const MultiCase<T>* __restrict__ mc, CaseStarts cs,
+                                                          int band, int sq, const int* __restrict__ kcs,
+                                                          int nut_set) {
+  const int nb = (int)(gridDim.x >> 3);
+  const int xcd = (int)(blockIdx.x & 7u), lid = (int)(blockIdx.x >> 3);
+  const int total = cs.start[cs.n];
+  const int share = (total + 7) >> 3;
+  const int lo = xcd * share, hi = min(total, lo + share);
+  for (int lb = lo + lid; lb < hi; lb += nb) {
+    const int c = find_case(cs, lb);
+    const MultiCase<T>& A = mc[c];
+    int bx, ib;
+    band_map(cell_gx(A.P.L), A.P.L.nx, band, lb - cs.start[c], bx, ib);
+    T* nut = nut_set >= 0 ? A.q[nut_set][0] : A.nut;
+    const int kc = kcs[c] & 1;
+    turb_cells(A.P, A.q[sq][0], A.q[sq][1], A.q[sq][2], A.k[kc], A.w[kc], A.k[kc ^ 1], A.w[kc ^ 1], nut, 1, A.nf,
+               bx, ib);
+  }
+}
+
+template <class T>
+void launch_turb_multi(const MultiCase<T>* mc, const CaseStarts& cs, int band, int blocks, int sq, const int* kcs,
+                       int nut_set, hipStream_t stream) {
+  hipLaunchKernelGGL(k_turb_multi<T>, dim3((unsigned)blocks), dim3(kCellBlock), 0, stream, mc, cs, band, sq, kcs,
+                     nut_set);
+}
+
+int cell_queue_blocks(const Layout& L) { return cell_gx(L) * L.nx; }
+
 // Diagnostics of a state, one partial per block and quantity: the largest
 // |div_h u| over the cells, the largest dt sum_d |u_d| / h_d with the
 // cell-centre velocity (the stability number of the upwind k-omega
@@ -364,7 +419,8 @@ template void launch_region_speed<double>(Grid&, const int[6], double*, int);
   template void launch_cell_bc<T>(Grid&, const Params<T>&, void*, int, double);                              \
   template void launch_pack<T>(Grid&, const Params<T>&, const void*, void*, int, int);                       \
   template void launch_check_range<T>(Grid&, const void*, size_t);                                           \
-  template void launch_cell_fill<T>(Grid&, const Params<T>&, void*, double, int, double);
+  template void launch_cell_fill<T>(Grid&, const Params<T>&, void*, double, int, double);                    \
+  template void launch_turb_multi<T>(const MultiCase<T>*, const CaseStarts&, int, int, int, const int*, int, hipStream_t);
 UF_INST(float)
 UF_INST(double)
 #undef UF_INST

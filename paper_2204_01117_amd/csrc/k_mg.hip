@@ -133,8 +133,10 @@ __device__ __forceinline__ T prolong(const MgCommon<T>& K, const MgLvl<T>& F, co
 
 // Restriction weights along one axis for coarse index I: fine cells
 // f = 2I-1 .. 2I+2 with weight P(f, I) / 2 on a halved axis (taps past the
-// level get weight 0 and a clamped index), or f = I alone.  Fixed tap
-// positions keep the arrays in registers.
+// level get weight 0 and an index clamped into the level, so that a reader
+// of a compact array without ghosts never leaves it: a value read there
+// from memory nobody wrote, if NaN, would survive the zero weight), or
+// f = I alone.  Fixed tap positions keep the arrays in registers.
 template <class T>
 __device__ __forceinline__ int rtaps(int I, int c, int nc, int nf, T slo, T shi, int f[4], T w[4]) {
   if (!c) {
@@ -152,7 +154,7 @@ __device__ __forceinline__ int rtaps(int I, int c, int nc, int nf, T slo, T shi,
   // an odd fine axis (nf = 2 nc - 1) has no right child under its last coarse cell
   f[2] = 2 * I + 1 < nf ? 2 * I + 1 : 2 * I;
   w[2] = 2 * I + 1 < nf ? T(0.5) * (T(0.75) + (I == nc - 1 ? T(0.25) * shi : T(0))) : T(0);
-  f[3] = 2 * I + 2 < nf ? 2 * I + 2 : 2 * I + 1;
+  f[3] = 2 * I + 2 < nf ? 2 * I + 2 : f[2];
   w[3] = 2 * I + 2 < nf ? T(0.125) : T(0);
   return 4;
 }
@@ -1568,14 +1570,14 @@ void mg_setup(Grid& g) {
     std::vector<MgLvl<T>> tab(nl);
     for (int l = 0; l < nl; ++l) tab[l] = mg_level<T>(g, l);
     g.mg_table = galloc(g, tab.size() * sizeof(MgLvl<T>));
-    UF_HIP_CHECK(hipMemcpy(g.mg_table, tab.data(), tab.size() * sizeof(MgLvl<T>), hipMemcpyHostToDevice));
+    upload(g, g.mg_table, tab.data(), tab.size() * sizeof(MgLvl<T>));
   }
   if (nl > 1) {
     std::vector<double> inv;
     if (dense_inverse(last, g.bc, inv)) {
       std::vector<T> tv(inv.begin(), inv.end());
       g.mg_cinv = galloc(g, tv.size() * es);
-      UF_HIP_CHECK(hipMemcpy(g.mg_cinv, tv.data(), tv.size() * es, hipMemcpyHostToDevice));
+      upload(g, g.mg_cinv, tv.data(), tv.size() * es);
     }
   }
 }

@@ -74,11 +74,8 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_corr(Params<T> P, const T
 // issues the trilinear loads of all three components at once, then
 // evaluates: two memory round trips instead of one per component.
 template <class T>
-__global__ __launch_bounds__(kFaceBlock) void k_advect_fwd32(Params<T> P, const T* __restrict__ U,
-                                                             const T* __restrict__ V, const T* __restrict__ W,
-                                                             T* __restrict__ Uh, T* __restrict__ Vh,
-                                                             T* __restrict__ Wh) {
-  UF_FACE_THREAD(P.L);
+__device__ __forceinline__ void advect_fwd32_faces(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, T* __restrict__ Uh, T* __restrict__ Vh, T* __restrict__ Wh, int bx, int ib) {
+  UF_FACE_POINT(P.L, bx, ib);
   const Layout& L = P.L;
   const unsigned o = (unsigned)L.at(i, j, k);
   T v0[3], v1[3], v2[3];
@@ -100,6 +97,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_fwd32(Params<T> P, const 
   finish_face<0>(P, Uh, i, j, k, a0);
   finish_face<1>(P, Vh, i, j, k, a1);
   finish_face<2>(P, Wh, i, j, k, a2);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_fwd32(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, T* __restrict__ Uh, T* __restrict__ Vh, T* __restrict__ Wh) {
+  int bx, ib;
+  if (!face_block(P.L, bx, ib)) return;
+  advect_fwd32_faces(P, U, V, W, Uh, Vh, Wh, bx, ib);
 }
 
 // The corrector with 32-bit offsets, one component after another (all
@@ -129,12 +133,8 @@ __device__ __forceinline__ T advect_corr32_value(const Params<T>& P, const T* __
 }
 
 template <class T>
-__global__ __launch_bounds__(kFaceBlock) void k_advect_corr32(Params<T> P, const T* __restrict__ U,
-                                                              const T* __restrict__ V, const T* __restrict__ W,
-                                                              const T* __restrict__ Uh, const T* __restrict__ Vh,
-                                                              const T* __restrict__ Wh, T* __restrict__ Uo,
-                                                              T* __restrict__ Vo, T* __restrict__ Wo) {
-  UF_FACE_THREAD(P.L);
+__device__ __forceinline__ void advect_corr32_faces(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Uh, const T* __restrict__ Vh, const T* __restrict__ Wh, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo, int bx, int ib) {
+  UF_FACE_POINT(P.L, bx, ib);
   const unsigned o = (unsigned)P.L.at(i, j, k);
   // scheduling barriers keep the components apart (fewer live registers)
   const T a0 = advect_corr32_value<0>(P, U, V, W, Uh, o, i, j, k);
@@ -145,6 +145,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_advect_corr32(Params<T> P, const
   finish_face<0>(P, Uo, i, j, k, a0);
   finish_face<1>(P, Vo, i, j, k, a1);
   finish_face<2>(P, Wo, i, j, k, a2);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_advect_corr32(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Uh, const T* __restrict__ Vh, const T* __restrict__ Wh, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  int bx, ib;
+  if (!face_block(P.L, bx, ib)) return;
+  advect_corr32_faces(P, U, V, W, Uh, Vh, Wh, Uo, Vo, Wo, bx, ib);
 }
 
 // ------------------------------------------------------------- diffusion --
@@ -161,10 +168,8 @@ __device__ __forceinline__ T diffuse_value(const Params<T>& P, const T* __restri
 }
 
 template <class T>
-__global__ __launch_bounds__(kFaceBlock) void k_diffuse(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
-                                                        const T* __restrict__ W, const T* __restrict__ NUT,
-                                                        T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
-  UF_FACE_THREAD(P.L);
+__device__ __forceinline__ void diffuse_faces(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ NUT, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo, int bx, int ib) {
+  UF_FACE_POINT(P.L, bx, ib);
   const long long o = P.L.at(i, j, k);
   const T a0 = diffuse_value<0>(P, U, NUT, o);
   const T a1 = diffuse_value<1>(P, V, NUT, o);
@@ -172,6 +177,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_diffuse(Params<T> P, const T* __
   finish_face<0>(P, Uo, i, j, k, a0);
   finish_face<1>(P, Vo, i, j, k, a1);
   finish_face<2>(P, Wo, i, j, k, a2);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_diffuse(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ NUT, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  int bx, ib;
+  if (!face_block(P.L, bx, ib)) return;
+  diffuse_faces(P, U, V, W, NUT, Uo, Vo, Wo, bx, ib);
 }
 
 // ------------------------------------------------------------ porosity drag
@@ -187,11 +199,8 @@ __device__ __forceinline__ T drag_value(const Params<T>& P, const T* __restrict_
 }
 
 template <class T>
-__global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
-                                                     const T* __restrict__ W, const T* __restrict__ Cc,
-                                                     T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo,
-                                                     int* nf) {
-  UF_FACE_THREAD(P.L);
+__device__ __forceinline__ void drag_faces(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Cc, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo, int* nf, int bx, int ib) {
+  UF_FACE_POINT(P.L, bx, ib);
   const long long o = P.L.at(i, j, k);
   const T a0 = drag_value<0>(P, U, V, W, Cc, o);
   const T a1 = drag_value<1>(P, U, V, W, Cc, o);
@@ -206,6 +215,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __res
   finish_face<2>(P, Wo, i, j, k, a2);
 }
 
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Cc, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo, int* nf) {
+  int bx, ib;
+  if (!face_block(P.L, bx, ib)) return;
+  drag_faces(P, U, V, W, Cc, Uo, Vo, Wo, nf, bx, ib);
+}
+
 // ------------------------------------------------ projection (velocity part)
 template <int C, class T>
 __device__ __forceinline__ T project_value(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ p,
@@ -215,10 +231,8 @@ __device__ __forceinline__ T project_value(const Params<T>& P, const T* __restri
 }
 
 template <class T>
-__global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
-                                                        const T* __restrict__ W, const T* __restrict__ Pp,
-                                                        T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
-  UF_FACE_THREAD(P.L);
+__device__ __forceinline__ void project_faces(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Pp, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo, int bx, int ib) {
+  UF_FACE_POINT(P.L, bx, ib);
   const long long o = P.L.at(i, j, k);
   const T a0 = project_value<0>(P, U, Pp, o);
   const T a1 = project_value<1>(P, V, Pp, o);
@@ -226,6 +240,13 @@ __global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __
   finish_face<0>(P, Uo, i, j, k, a0);
   finish_face<1>(P, Vo, i, j, k, a1);
   finish_face<2>(P, Wo, i, j, k, a2);
+}
+
+template <class T>
+__global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Pp, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  int bx, ib;
+  if (!face_block(P.L, bx, ib)) return;
+  project_faces(P, U, V, W, Pp, Uo, Vo, Wo, bx, ib);
 }
 
 // ------------------------------------------------ boundary refresh (in place)
@@ -247,6 +268,67 @@ __global__ __launch_bounds__(kFaceBlock) void k_face_init(Params<T> P, T* __rest
   T val;
   if (!face_dirichlet<C>(P, i, j, k, &val)) val = inflow_comp(P, C, k);
   store_face<C>(q, P, i, j, k, val);
+}
+
+// ------------------------------------------------- several grids at once --
+// One launch of a face stage for every case of a batch: the cases' logical
+// blocks form one queue (case c owns [face0, face0 + face_gx * (nx + 1))),
+// which a persistent grid walks -- every XCD takes a contiguous share and
+// its blocks stride through it -- each block running the stage's per-block
+// body with its case's parameters and buffers (read from the case table).
+// Sets: sin is read, saux is the predictor's output the corrector reads,
+// sout is written.
+template <int S, class T>
+__global__ __launch_bounds__(kFaceBlock) void k_faces_multi(const MultiCase<T>* __restrict__ mc, CaseStarts cs,
+                                                            int band, int sin, int saux, int sout) {
+  const int nb = (int)(gridDim.x >> 3);
+  const int xcd = (int)(blockIdx.x & 7u), lid = (int)(blockIdx.x >> 3);
+  const int total = cs.start[cs.n];
+  const int share = (total + 7) >> 3;
+  const int lo = xcd * share, hi = min(total, lo + share);
+  for (int lb = lo + lid; lb < hi; lb += nb) {
+    const int c = find_case(cs, lb);
+    const MultiCase<T>& A = mc[c];
+    int bx, ib;
+    band_map(face_gx(A.P.L), A.P.L.nx + 1, band, lb - cs.start[c], bx, ib);
+    T* const* qi = A.q[sin];
+    T* const* qo = A.q[sout];
+    if (S == MS_ADVECT_FWD) {
+      advect_fwd32_faces(A.P, qi[0], qi[1], qi[2], qo[0], qo[1], qo[2], bx, ib);
+    } else if (S == MS_ADVECT_CORR) {
+      T* const* qa = A.q[saux];
+      advect_corr32_faces(A.P, qi[0], qi[1], qi[2], qa[0], qa[1], qa[2], qo[0], qo[1], qo[2], bx, ib);
+    } else if (S == MS_DIFFUSE) {
+      diffuse_faces(A.P, qi[0], qi[1], qi[2], A.nut, qo[0], qo[1], qo[2], bx, ib);
+    } else if (S == MS_DRAG) {
+      drag_faces(A.P, qi[0], qi[1], qi[2], A.cc, qo[0], qo[1], qo[2], A.nf, bx, ib);
+    } else {
+      project_faces(A.P, qi[0], qi[1], qi[2], A.x, qo[0], qo[1], qo[2], bx, ib);
+    }
+  }
+}
+
+template <class T>
+void launch_faces_multi(int stage, const MultiCase<T>* mc, const CaseStarts& cs, int band, int blocks, int sin,
+                        int saux, int sout, hipStream_t stream) {
+  const dim3 grid((unsigned)blocks), blk(kFaceBlock);
+  switch (stage) {
+    case MS_ADVECT_FWD:
+      hipLaunchKernelGGL((k_faces_multi<MS_ADVECT_FWD, T>), grid, blk, 0, stream, mc, cs, band, sin, saux, sout);
+      break;
+    case MS_ADVECT_CORR:
+      hipLaunchKernelGGL((k_faces_multi<MS_ADVECT_CORR, T>), grid, blk, 0, stream, mc, cs, band, sin, saux, sout);
+      break;
+    case MS_DIFFUSE:
+      hipLaunchKernelGGL((k_faces_multi<MS_DIFFUSE, T>), grid, blk, 0, stream, mc, cs, band, sin, saux, sout);
+      break;
+    case MS_DRAG:
+      hipLaunchKernelGGL((k_faces_multi<MS_DRAG, T>), grid, blk, 0, stream, mc, cs, band, sin, saux, sout);
+      break;
+    default:
+      hipLaunchKernelGGL((k_faces_multi<MS_PROJECT, T>), grid, blk, 0, stream, mc, cs, band, sin, saux, sout);
+      break;
+  }
 }
 
 // ----------------------------------------------------------------- launchers
@@ -321,7 +403,8 @@ void launch_face_init(Grid& g, const Params<T>& P, void* const Q[3]) {
   template void launch_drag<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);             \
   template void launch_project<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);          \
   template void launch_face_bc<T>(Grid&, const Params<T>&, void*, int);                             \
-  template void launch_face_init<T>(Grid&, const Params<T>&, void* const[3]);
+  template void launch_face_init<T>(Grid&, const Params<T>&, void* const[3]);                      \
+  template void launch_faces_multi<T>(int, const MultiCase<T>*, const CaseStarts&, int, int, int, int, int, hipStream_t);
 UF_INST(float)
 UF_INST(double)
 #undef UF_INST

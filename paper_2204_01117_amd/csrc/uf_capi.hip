@@ -8,6 +8,7 @@
 #include <thread>
 #include <vector>
 
+#include "face_ops.h"
 #include "uf_internal.h"
 
 namespace uf {
@@ -90,6 +91,11 @@ void* galloc(Grid& g, size_t bytes) {
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) throw HipError(std::string("hipMalloc: ") + hipGetErrorString(e));
   return p;
+}
+
+void upload(Grid& g, void* dst, const void* src, size_t bytes) {
+  UF_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, g.stream));
+  UF_HIP_CHECK(hipStreamSynchronize(g.stream));
 }
 
 void gfree(Grid& g, void* p) {
@@ -480,13 +486,13 @@ void upload_inflow(Grid& g) {
     tab[0 * (nz + 2) + (k + 1)] = T(s * dir[0]);
     tab[1 * (nz + 2) + (k + 1)] = T(s * dir[1]);
   }
-  UF_HIP_CHECK(hipMemcpy(g.inflow, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice));
+  upload(g, g.inflow, tab.data(), tab.size() * sizeof(T));
 }
 
 template <class T>
 void fill_phi_one(Grid& g) {
   std::vector<T> ones((size_t)g.L.nx * g.L.ny * g.L.nz, T(1));
-  UF_HIP_CHECK(hipMemcpy(g.PHI, ones.data(), ones.size() * sizeof(T), hipMemcpyHostToDevice));
+  upload(g, g.PHI, ones.data(), ones.size() * sizeof(T));
 }
 
 int64_t extent(const uf_config* c, int32_t f, int32_t d[3]) {
@@ -718,6 +724,329 @@ std::string check_smooth_objects(const uf_smooth_objects* o) {
 }
 
 }  // namespace
+
+namespace {
+// ------------------------------------------------------------- batches ---
+// A batch advances several grids together.  Each face stage of the step
+// (predictor, corrector, diffusion, drag, projection) and the k-omega
+// update is one launch for every case, walking one queue of the cases'
+// blocks (k_faces_multi, k_turb_multi).  Each case's pressure solve (its
+// start and a fixed number of CG iterations, iterations past convergence
+// returning at once) is a hipGraph of its own, replayed on the case's own
+// stream so that the solves of the cases overlap; the face stages before
+// the solve and the projection and k-omega update after it are two more
+// graphs on the batch's stream.  Between them the host reads every case's
+// solve status and enqueues further iterations for a case that needs them,
+// and re-captures a case's solve when its iteration count moves away from
+// the captured one.  The stage launches' band width and grid size come
+// from uf_batch_autotune.
+struct BatchTune {
+  int band[6];
+  int blocks[6];   // 0: one block per logical block (no persistent walk)
+  float ms[6];
+};
+
+struct Batch {
+  std::vector<Grid*> g;
+  size_t esize = 4;
+  hipStream_t origin = nullptr;
+  std::vector<hipStream_t> cs;     // one stream per case (its solve)
+  std::vector<hipStream_t> own;    // the grids' streams while a call runs on the batch's
+  std::vector<hipEvent_t> ev_case;
+  hipEvent_t ev_fork = nullptr, ev_end = nullptr;
+  void* table = nullptr;           // MultiCase<T>[n] on the device
+  CaseStarts faces{}, cells{};     // the cases' blocks in the face and cell queues
+  int turb = 0;
+  BatchTune tune{};
+  std::vector<int> kcap;           // CG iterations in each case's solve graph
+  int* kc_dev = nullptr;           // each case's k/omega slot, read by the k-omega launch
+  int* kc_host = nullptr;          // pinned staging of the slots
+  hipGraphExec_t front = nullptr, back = nullptr;
+  std::vector<hipGraphExec_t> solve;
+};
+
+int stage_blocks(const BatchTune& t, int s, int total) {
+  const int want = t.blocks[s] > 0 ? t.blocks[s] : total;
+  return 8 * ((std::min(want, total) + 7) / 8);
+}
+
+void drop_solve(Batch& b, size_t c) {
+  if (b.solve[c]) (void)hipGraphExecDestroy(b.solve[c]);
+  b.solve[c] = nullptr;
+}
+
+void drop_graphs(Batch& b) {
+  if (b.front) (void)hipGraphExecDestroy(b.front);
+  if (b.back) (void)hipGraphExecDestroy(b.back);
+  b.front = b.back = nullptr;
+  for (size_t c = 0; c < b.solve.size(); ++c) drop_solve(b, c);
+}
+
+// Release the batch's streams, events, graphs and case table.
+void release_batch(Batch* b) {
+  drop_graphs(*b);
+  for (auto s : b->cs)
+    if (s) (void)hipStreamDestroy(s);
+  for (auto e : b->ev_case)
+    if (e) (void)hipEventDestroy(e);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_end) (void)hipEventDestroy(b->ev_end);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  if (b->table) (void)hipFree(b->table);
+  if (b->kc_dev) (void)hipFree(b->kc_dev);
+  if (b->kc_host) (void)hipHostFree(b->kc_host);
+  b->kc_dev = nullptr;
+  b->kc_host = nullptr;
+  b->cs.clear();
+  b->ev_case.clear();
+  b->ev_fork = b->ev_end = nullptr;
+  b->origin = nullptr;
+  b->table = nullptr;
+}
+
+template <class T>
+void build_table(Batch& b) {
+  std::vector<MultiCase<T>> tab(b.g.size());
+  int face = 0, cell = 0;
+  b.faces.n = b.cells.n = (int)b.g.size();
+  for (size_t c = 0; c < b.g.size(); ++c) {
+    Grid& g = *b.g[c];
+    MultiCase<T>& m = tab[c];
+    m.P = make_params<T>(g);
+    for (int s2 = 0; s2 < 3; ++s2)
+      for (int q = 0; q < 3; ++q) m.q[s2][q] = (T*)g.Q[s2][q];
+    m.nut = (T*)g.NUT;
+    m.cc = (const T*)g.C;
+    m.x = (const T*)g.X;
+    for (int q = 0; q < 2; ++q) {
+      m.k[q] = (T*)g.K[q];
+      m.w[q] = (T*)g.Wo[q];
+    }
+    m.nf = nf_word(g);
+    b.faces.start[c] = face;
+    b.cells.start[c] = cell;
+    face += face_gx(g.L) * (g.L.nx + 1);
+    cell += cell_queue_blocks(g.L);
+  }
+  b.faces.start[b.g.size()] = face;
+  b.cells.start[b.g.size()] = cell;
+  UF_HIP_CHECK(hipMalloc(&b.table, sizeof(MultiCase<T>) * tab.size()));
+  UF_HIP_CHECK(hipMemcpyAsync(b.table, tab.data(), sizeof(MultiCase<T>) * tab.size(), hipMemcpyHostToDevice,
+                              b.origin));
+  UF_HIP_CHECK(hipStreamSynchronize(b.origin));
+}
+
+// The face stages of a step or of a trial run: (stage, in, aux, out) sets.
+struct FaceRun {
+  int stage, sin, saux, sout;
+};
+const FaceRun kFront[4] = {{MS_ADVECT_FWD, 0, 0, 1}, {MS_ADVECT_CORR, 0, 1, 2}, {MS_DIFFUSE, 2, 0, 0},
+                           {MS_DRAG, 0, 0, 1}};
+const FaceRun kTrial[5] = {{MS_ADVECT_FWD, 0, 0, 1}, {MS_ADVECT_CORR, 0, 1, 2}, {MS_DIFFUSE, 2, 0, 1},
+                           {MS_DRAG, 1, 0, 2}, {MS_PROJECT, 2, 0, 1}};
+
+template <class T>
+void enqueue_face(Batch& b, const FaceRun& r, hipStream_t st) {
+  launch_faces_multi<T>(r.stage, (const MultiCase<T>*)b.table, b.faces, b.tune.band[r.stage],
+                        stage_blocks(b.tune, r.stage, b.faces.start[b.faces.n]), r.sin, r.saux, r.sout, st);
+}
+
+template <class T>
+void enqueue_turb(Batch& b, int nut_set, hipStream_t st) {
+  launch_turb_multi<T>((const MultiCase<T>*)b.table, b.cells, b.tune.band[5],
+                       stage_blocks(b.tune, 5, b.cells.start[b.cells.n]), 0, b.kc_dev, nut_set, st);
+}
+
+// Each case's k/omega slot to the device, behind the work on the origin stream.
+void post_slots(Batch& b) {
+  for (size_t c = 0; c < b.g.size(); ++c) b.kc_host[c] = b.g[c]->kcur;
+  UF_HIP_CHECK(hipMemcpyAsync(b.kc_dev, b.kc_host, sizeof(int) * b.g.size(), hipMemcpyHostToDevice, b.origin));
+}
+
+// Capture what `body` enqueues on stream st into *exec.
+template <class F>
+void capture(hipStream_t st, hipGraphExec_t* exec, F body) {
+  hipGraph_t graph = nullptr;
+  UF_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  UF_HIP_CHECK(hipStreamEndCapture(st, &graph));
+  const hipError_t e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  UF_HIP_CHECK(e);
+}
+
+// Front of a step: the face stages up to the drag (the state in set 0, the
+// drag output in set 1).
+template <class T>
+void capture_front(Batch& b) {
+  capture(b.origin, &b.front, [&] {
+    for (const FaceRun& r : kFront) enqueue_face<T>(b, r, b.origin);
+  });
+}
+
+// Case c's solve on its stream: the start from the drag output, the first
+// preconditioner application, kcap[c] iterations, the status to the host.
+template <class T>
+void capture_solve(Batch& b, size_t c) {
+  Grid& g = *b.g[c];
+  capture(b.cs[c], &b.solve[c], [&] {
+    const Params<T> P = make_params<T>(g);
+    launch_cg_start<T>(g, P, g.Q[1], nullptr);
+    launch_cg_precond<T>(g, P, 0);
+    for (int t = 0; t < b.kcap[c]; ++t) launch_cg_iteration<T>(g, P, t);
+    launch_cg_status(g, b.kcap[c]);
+    UF_HIP_CHECK(hipMemcpyAsync(g.st_host, g.st, sizeof(CgState), hipMemcpyDeviceToHost, b.cs[c]));
+  });
+}
+
+// Back of a step: the projection (set 1 to set 0) and the k-omega update
+// from each case's current slot.
+template <class T>
+void capture_back(Batch& b) {
+  capture(b.origin, &b.back, [&] {
+    enqueue_face<T>(b, FaceRun{MS_PROJECT, 1, 0, 0}, b.origin);
+    if (b.turb) enqueue_turb<T>(b, -1, b.origin);
+  });
+}
+
+// The grids run on the batch's streams for the duration of a call (the
+// captured kernels are bound to them); their own streams are ordered
+// before and after it.
+void enter_batch(Batch& b) {
+  for (size_t c = 0; c < b.g.size(); ++c) {
+    Grid& g = *b.g[c];
+    b.own[c] = g.stream;
+    UF_HIP_CHECK(hipEventRecord(b.ev_case[c], g.stream));
+    UF_HIP_CHECK(hipStreamWaitEvent(b.origin, b.ev_case[c], 0));
+    g.stream = b.cs[c];
+  }
+}
+
+void leave_batch(Batch& b) {
+  UF_HIP_CHECK(hipEventRecord(b.ev_end, b.origin));
+  for (size_t c = 0; c < b.g.size(); ++c) {
+    Grid& g = *b.g[c];
+    UF_HIP_CHECK(hipStreamWaitEvent(b.cs[c], b.ev_end, 0));
+    UF_HIP_CHECK(hipEventRecord(b.ev_case[c], b.cs[c]));
+    g.stream = b.own[c];
+    UF_HIP_CHECK(hipStreamWaitEvent(g.stream, b.ev_case[c], 0));
+  }
+}
+
+template <class T>
+void batch_steps(Batch& b, int nsteps, std::vector<StepAccum>& acc) {
+  const int n = (int)b.g.size();
+  for (int s2 = 0; s2 < nsteps; ++s2) {
+    if (!b.front) capture_front<T>(b);
+    if (!b.back) capture_back<T>(b);
+    for (int c = 0; c < n; ++c)
+      if (!b.solve[c]) capture_solve<T>(b, c);
+    UF_HIP_CHECK(hipGraphLaunch(b.front, b.origin));
+    UF_HIP_CHECK(hipEventRecord(b.ev_fork, b.origin));
+    for (int c = 0; c < n; ++c) {
+      UF_HIP_CHECK(hipStreamWaitEvent(b.cs[c], b.ev_fork, 0));
+      UF_HIP_CHECK(hipGraphLaunch(b.solve[c], b.cs[c]));
+      UF_HIP_CHECK(hipEventRecord(b.ev_case[c], b.cs[c]));
+    }
+    for (int c = 0; c < n; ++c) {
+      Grid& g = *b.g[c];
+      const Params<T> P = make_params<T>(g);
+      UF_HIP_CHECK(hipEventSynchronize(b.ev_case[c]));
+      g.cg_t = b.kcap[c];
+      // further iterations past the captured ones, as the single-grid loop runs them
+      while (!g.st_host->done && g.cg_t < g.cfg.cg_maxit) {
+        solve_chunk<T>(g, P);
+        wait_status(g);
+      }
+      const CgState& st = *g.st_host;
+      g.last_iters = st.iter;
+      acc[c].iters_total += st.iter;
+      acc[c].last_iters = st.iter;
+      acc[c].max_iters = std::max(acc[c].max_iters, st.iter);
+      acc[c].last_rel = st.bb > 0 ? std::sqrt(st.rr / st.bb) : 0.0;
+      acc[c].noconv |= st.noconv;
+      acc[c].nonfinite |= st.nonfinite;
+      acc[c].nf_state |= st.nf_state;
+      // a solve graph too short (or far too long) for this case is captured again
+      if (st.iter > b.kcap[c] || st.iter + 4 < b.kcap[c]) {
+        b.kcap[c] = std::min(g.cfg.cg_maxit, st.iter + 2);
+        UF_HIP_CHECK(hipStreamSynchronize(b.cs[c]));
+        drop_solve(b, c);
+      }
+      UF_HIP_CHECK(hipEventRecord(b.ev_case[c], b.cs[c]));
+      UF_HIP_CHECK(hipStreamWaitEvent(b.origin, b.ev_case[c], 0));
+    }
+    post_slots(b);
+    UF_HIP_CHECK(hipGraphLaunch(b.back, b.origin));
+    for (int c = 0; c < n; ++c) b.g[c]->kcur ^= 1;
+  }
+}
+
+// Trial launches of every stage with each candidate band width and grid
+// size, on the sets a step overwrites anyway (set 0, k, omega, nu_t and the
+// pressure are only read); the fastest of three runs of each is kept.
+template <class T>
+void autotune(Batch& b) {
+  const int bands[3] = {4, 8, 16};
+  const int per_cu[4] = {2, 4, 8, 0};
+  hipEvent_t e0, e1;
+  UF_HIP_CHECK(hipEventCreate(&e0));
+  UF_HIP_CHECK(hipEventCreate(&e1));
+  try {
+    post_slots(b);
+    for (int st = 0; st < 6; ++st) {
+      if (st == 5 && !b.turb) {
+        b.tune.ms[5] = 0.f;
+        continue;
+      }
+      float best = 1e30f;
+      int bb = 8, bp = 0;
+      for (int band : bands)
+        for (int pc : per_cu) {
+          BatchTune t = b.tune;
+          t.band[st] = band;
+          t.blocks[st] = pc ? pc * 256 : 0;
+          std::swap(t, b.tune);
+          float fastest = 1e30f;
+          for (int rep = 0; rep < 3; ++rep) {
+            UF_HIP_CHECK(hipEventRecord(e0, b.origin));
+            if (st < 5) enqueue_face<T>(b, kTrial[st], b.origin);
+            else enqueue_turb<T>(b, 2, b.origin);
+            UF_HIP_CHECK(hipEventRecord(e1, b.origin));
+            UF_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            UF_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            fastest = std::min(fastest, ms);
+          }
+          std::swap(t, b.tune);
+          if (fastest < best) {
+            best = fastest;
+            bb = band;
+            bp = pc ? pc * 256 : 0;
+          }
+        }
+      b.tune.band[st] = bb;
+      b.tune.blocks[st] = bp;
+      b.tune.ms[st] = best;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+}  // namespace
+
+struct uf_batch_s : public Batch {};
 
 extern "C" {
 
@@ -1334,6 +1663,146 @@ uf_status uf_adjoint_step_at(uf_grid g, const void* const* state_n_dev, const vo
                              const void* const* adj_np1_dev, void* const* adj_n_dev, void* dJ_dphi_accum_dev) {
   if (!state_np1_dev) return fail(UF_EINVAL, "NULL argument");
   return adjoint_entry(g, state_n_dev, state_np1_dev, adj_np1_dev, adj_n_dev, dJ_dphi_accum_dev);
+}
+
+uf_status uf_batch_create(const uf_grid* grids, int32_t n, uf_batch* out) {
+  if (!grids || !out || n < 1) return fail(UF_EINVAL, "need at least one grid and an output handle");
+  if (n > kMaxBatchCases)
+    return fail(UF_EINVAL, "a batch holds at most " + std::to_string(kMaxBatchCases) + " grids");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!grids[i]) return fail(UF_EINVAL, "NULL grid in the batch");
+    for (int j = 0; j < i; ++j)
+      if (grids[j] == grids[i]) return fail(UF_EINVAL, "a grid appears twice in the batch");
+    const Grid& g = *grids[i];
+    const Grid& g0 = *grids[0];
+    if (g.esize != g0.esize) return fail(UF_EINVAL, "the grids of a batch share one dtype");
+    const int all = UF_STAGE_ADVECT | UF_STAGE_DIFFUSE | UF_STAGE_DRAG | UF_STAGE_PROJECT;
+    if ((g.cfg.stages & all) != all) return fail(UF_EINVAL, "a batch runs the full step (every stage)");
+    if (((g.cfg.stages & UF_STAGE_TURB) && g.cfg.turb_model == UF_TURB_KOMEGA) !=
+        ((g0.cfg.stages & UF_STAGE_TURB) && g0.cfg.turb_model == UF_TURB_KOMEGA))
+      return fail(UF_EINVAL, "the grids of a batch all run the k-omega update, or none does");
+    if (!offsets_fit_32(g.L, g.esize)) return fail(UF_EINVAL, "a grid of the batch is too large (4 GiB per field)");
+  }
+  UF_GUARD_BEGIN
+  uf_batch_s* b = new uf_batch_s();
+  try {
+    for (int i = 0; i < n; ++i) b->g.push_back(grids[i]);
+    b->esize = grids[0]->esize;
+    b->turb = (grids[0]->cfg.stages & UF_STAGE_TURB) && grids[0]->cfg.turb_model == UF_TURB_KOMEGA;
+    b->cs.assign(n, nullptr);
+    b->own.assign(n, nullptr);
+    b->ev_case.assign(n, nullptr);
+    b->solve.assign(n, nullptr);
+    UF_HIP_CHECK(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking));
+    for (int i = 0; i < n; ++i) {
+      UF_HIP_CHECK(hipStreamCreateWithFlags(&b->cs[i], hipStreamNonBlocking));
+      UF_HIP_CHECK(hipEventCreateWithFlags(&b->ev_case[i], hipEventDisableTiming));
+    }
+    UF_HIP_CHECK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    UF_HIP_CHECK(hipEventCreateWithFlags(&b->ev_end, hipEventDisableTiming));
+    for (int st = 0; st < 6; ++st) {
+      b->tune.band[st] = 8;
+      b->tune.blocks[st] = 0;
+      b->tune.ms[st] = 0.f;
+    }
+    for (int i = 0; i < n; ++i) b->kcap.push_back(std::max(4, grids[i]->last_iters + 2));
+    UF_HIP_CHECK(hipMalloc(&b->kc_dev, sizeof(int) * n));
+    UF_HIP_CHECK(hipHostMalloc(&b->kc_host, sizeof(int) * n, hipHostMallocDefault));
+    if (b->esize == 4) build_table<float>(*b);
+    else build_table<double>(*b);
+  } catch (...) {
+    release_batch(b);
+    delete b;
+    throw;
+  }
+  *out = b;
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_batch_destroy(uf_batch b) {
+  if (!b) return fail(UF_EINVAL, "NULL batch");
+  (void)hipStreamSynchronize(b->origin);
+  release_batch(b);
+  delete b;
+  return UF_OK;
+}
+
+// The state must sit in set 0 with the same k/omega slot in every grid
+// (grids stepped only by full steps are).
+static std::string batch_ready(const Batch& b) {
+  for (const Grid* g : b.g) {
+    if (g->cur != 0) return "a grid of the batch holds its state outside the first set";
+    if (g->timer_mask) return "kernel timers must be off for batched steps";
+  }
+  return "";
+}
+
+uf_status uf_batch_autotune(uf_batch b, uf_batch_tuning* out) {
+  if (!b) return fail(UF_EINVAL, "NULL batch");
+  const std::string bad = batch_ready(*b);
+  if (!bad.empty()) return fail(UF_EINVAL, bad);
+  UF_GUARD_BEGIN
+  enter_batch(*b);
+  try {
+    if (b->esize == 4) autotune<float>(*b);
+    else autotune<double>(*b);
+  } catch (...) {
+    leave_batch(*b);
+    throw;
+  }
+  leave_batch(*b);
+  drop_graphs(*b);   // captured with the previous parameters
+  if (out)
+    for (int st = 0; st < 6; ++st) {
+      out->band[st] = b->tune.band[st];
+      out->blocks[st] = b->tune.blocks[st];
+      out->ms[st] = b->tune.ms[st];
+    }
+  return UF_OK;
+  UF_GUARD_END
+}
+
+uf_status uf_batch_step(uf_batch b, int32_t nsteps, uf_step_stats* stats) {
+  if (!b) return fail(UF_EINVAL, "NULL batch");
+  if (nsteps < 0) return fail(UF_EINVAL, "nsteps must be >= 0");
+  const std::string bad = batch_ready(*b);
+  if (!bad.empty()) return fail(UF_EINVAL, bad);
+  UF_GUARD_BEGIN
+  const int n = (int)b->g.size();
+  std::vector<StepAccum> acc(n);
+  for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(b->g[i]->ev0, b->g[i]->stream));
+  enter_batch(*b);
+  try {
+    if (b->esize == 4) batch_steps<float>(*b, nsteps, acc);
+    else batch_steps<double>(*b, nsteps, acc);
+  } catch (...) {
+    leave_batch(*b);
+    throw;
+  }
+  leave_batch(*b);
+  for (int i = 0; i < n; ++i) UF_HIP_CHECK(hipEventRecord(b->g[i]->ev1, b->g[i]->stream));
+  if (stats) {
+    for (int i = 0; i < n; ++i) post_diag(*b->g[i]);
+    for (int i = 0; i < n; ++i) {
+      UF_HIP_CHECK(hipStreamSynchronize(b->g[i]->stream));
+      float ms = 0;
+      UF_HIP_CHECK(hipEventElapsedTime(&ms, b->g[i]->ev0, b->g[i]->ev1));
+      fill_stats(&stats[i], acc[i], ms, *b->g[i]);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    if (acc[i].nonfinite)
+      return fail(UF_ENONFINITE, "non-finite value in the pressure solve of batch entry " + std::to_string(i));
+    if (acc[i].nf_state)
+      return fail(UF_ENONFINITE, "non-finite value written by the drag or k-omega stage of batch entry " +
+                                     std::to_string(i));
+    if (acc[i].noconv)
+      return fail(UF_ENOCONV, "pressure CG reached cg_maxit in batch entry " + std::to_string(i));
+  }
+  return UF_OK;
+  UF_GUARD_END
 }
 
 }  // extern "C"

@@ -216,6 +216,24 @@ __device__ __forceinline__ bool xcd_block(int gx, int gy, int& bx, int& by) {
   return true;
 }
 
+// Logical block b of a gx x gy grid of blocks (gy planes of gx blocks) in
+// band-major order: the planes of one band of `band` consecutive blocks (the
+// last band narrower) before the next band.
+__device__ __forceinline__ void band_map(int gx, int gy, int band, int b, int& bx, int& by) {
+  const int bw = min(band, gx);
+  const int nfull = gx / bw;                 // bands of bw blocks
+  const int full = nfull * bw * gy;          // logical blocks in them
+  if (b < full) {
+    const int bd = b / (bw * gy), rem = b - bd * bw * gy;
+    by = rem / bw;
+    bx = bd * bw + (rem - by * bw);
+  } else {
+    const int wl = gx - nfull * bw, rem = b - full;   // the last, narrower band
+    by = rem / wl;
+    bx = nfull * bw + (rem - by * wl);
+  }
+}
+
 inline dim3 xcd_grid(int gx, int gy) {
   const long long n = (long long)gx * gy;
   return dim3((unsigned)(8 * ((n + 7) / 8)));

@@ -53,6 +53,44 @@ struct CgLaunch {
   int gx, gy;
 };
 
+// One case of a batched launch (uf_batch): its step parameters and buffers.
+template <class T>
+struct MultiCase {
+  Params<T> P;
+  T* q[3][3];        // the grid's three (u, v, w) sets
+  T* nut;
+  const T* cc;       // drag coefficient per cell
+  const T* x;        // pressure
+  T* k[2];
+  T* w[2];
+  int* nf;           // the state's non-finite flag
+};
+
+// Face stages of the batched launch.
+enum { MS_ADVECT_FWD = 0, MS_ADVECT_CORR, MS_DIFFUSE, MS_DRAG, MS_PROJECT, MS_NFACE };
+
+// Most cases of one batch.
+constexpr int kMaxBatchCases = UF_BATCH_MAX_GRIDS;
+
+// Where each case's logical blocks start in a batched launch's queue
+// (ascending, start[n] = all blocks).  Passed by value, so that a block
+// finds its case in the kernel's argument segment.
+struct CaseStarts {
+  int n;
+  int start[kMaxBatchCases + 1];
+};
+
+// The case owning logical block lb: the largest c with start[c] <= lb.
+__host__ __device__ inline int find_case(const CaseStarts& cs, int lb) {
+  int lo = 0, hi = cs.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cs.start[mid] <= lb) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 struct Grid {
   uf_config cfg{};
   std::vector<double> profile;
@@ -134,6 +172,10 @@ struct Grid {
 // Device memory of the grid: its configured allocator, else hipMalloc.
 void* galloc(Grid& g, size_t bytes);
 void gfree(Grid& g, void* p);
+// Host data to the grid's device memory, in order on the grid's stream;
+// returns when the copy is complete.  (A plain hipMemcpy runs on the null
+// stream, which is not ordered with a non-blocking grid stream.)
+void upload(Grid& g, void* dst, const void* src, size_t bytes);
 
 // End-of-call diagnostics (uf_step_stats.max_div, max_cfl, nut_clip_frac).
 constexpr int kDiagBlocks = 512;
@@ -153,6 +195,14 @@ template <class T> void launch_turb(Grid& g, const Params<T>& P, void* const Q[3
 // device word the drag and k-omega kernels set on a non-finite output
 inline int* nf_word(Grid& g) { return &g.st->nf_state; }
 template <class T> void launch_cell_bc(Grid& g, const Params<T>& P, void* q, int use_inlet, double inlet_value);
+// batched launches (one persistent launch for every case of a batch)
+template <class T>
+void launch_faces_multi(int stage, const MultiCase<T>* mc, const CaseStarts& cs, int band, int blocks, int sin,
+                        int saux, int sout, hipStream_t stream);
+template <class T>
+void launch_turb_multi(const MultiCase<T>* mc, const CaseStarts& cs, int band, int blocks, int sq, const int* kcs,
+                       int nut_set, hipStream_t stream);
+int cell_queue_blocks(const Layout& L);
 template <class T> void launch_porosity(Grid& g, const Params<T>& P, const void* phi);
 template <class T> void launch_pack(Grid& g, const Params<T>& P, const void* src_padded, void* dst, int field, int unpack);
 template <class T> void launch_check_range(Grid& g, const void* phi, size_t n);

@@ -10,7 +10,7 @@ class Grid:
     (see ``uf_layouts.default_config``).  All work is enqueued on torch's
     current stream of ``device``."""
 
-    def __init__(self, cfg, device="cuda:0", stream=None, torch_memory=True):
+    def __init__(self, cfg, device="cuda:0", stream=None, torch_memory=True, allocator=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -21,9 +21,13 @@ class Grid:
         self.tstream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = self.tstream.cuda_stream
         c, keep = L.make_config(self.cfg, self.stream)
-        # the grid's buffers come from torch's caching allocator (uf_config
-        # alloc/free), unless torch_memory is False (then hipMalloc)
-        self._allocator = L.torch_allocator(self.device, self.tstream) if torch_memory else None
+        # the grid's buffers come from ``allocator`` (an (alloc, free) pair of
+        # uf_config callbacks, L.ALLOC_FN / L.FREE_FN) when given, else from
+        # torch's caching allocator, unless torch_memory is False (hipMalloc)
+        if allocator is not None:
+            self._allocator = allocator
+        else:
+            self._allocator = L.torch_allocator(self.device, self.tstream) if torch_memory else None
         if self._allocator is not None:
             c.alloc = ctypes.cast(self._allocator[0], c_void_p)
             c.free = ctypes.cast(self._allocator[1], c_void_p)
@@ -233,3 +237,53 @@ def step_batch(grids, nsteps=1, stats=True, allow=()):
     for d in out:
         d["status"] = L.STATUS[rc]
     return out
+
+
+STAGE_NAMES = ("predictor", "corrector", "diffusion", "drag", "projection", "k-omega")
+
+
+class Batch:
+    """Several grids advanced together (uf_batch): one persistent launch per
+    stage for all of them, each step replayed from two hipGraphs.  The grids
+    stay usable on their own between calls."""
+
+    def __init__(self, grids):
+        n = len(grids)
+        self.grids = list(grids)
+        arr = (c_void_p * n)(*[g.handle for g in grids])
+        h = c_void_p()
+        L.check(L.uf_batch_create(arr, n, byref(h)))
+        self.handle = h
+
+    def autotune(self):
+        """Time every stage's launch for each band width and grid size (on
+        scratch sets) and keep the fastest; returns the choice per stage."""
+        t = L.uf_batch_tuning()
+        L.check(L.uf_batch_autotune(self.handle, byref(t)))
+        return {name: {"band": t.band[i], "blocks": t.blocks[i], "ms": t.ms[i]}
+                for i, name in enumerate(STAGE_NAMES)}
+
+    def step(self, nsteps=1, stats=True, allow=()):
+        n = len(self.grids)
+        arr = (L.uf_step_stats * n)() if stats else None
+        rc = L.uf_batch_step(self.handle, int(nsteps), arr)
+        L.check(rc, allow)
+        if not stats:
+            return [{"status": L.STATUS[rc]} for _ in range(n)]
+        out = []
+        for s in arr:
+            d = s.as_dict()
+            d["status"] = L.STATUS[rc]
+            out.append(d)
+        return out
+
+    def close(self):
+        if self.handle:
+            L.uf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

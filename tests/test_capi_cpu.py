@@ -141,7 +141,7 @@ def test_ctypes_structs_match_the_header():
     decl = _header_structs()
     for cname, cls in (("uf_config", U.uf_config), ("uf_step_stats", U.uf_step_stats),
                        ("uf_objective_spec", U.uf_objective_spec), ("uf_mesh_set", U.uf_mesh_set),
-                       ("uf_smooth_objects", U.uf_smooth_objects)):
+                       ("uf_smooth_objects", U.uf_smooth_objects), ("uf_batch_tuning", U.uf_batch_tuning)):
         hdr = decl[cname]
         assert [f[0] for f in hdr] == [f[0] for f in cls._fields_], cname
         for (name, typ, ptr, count), (_, ct) in zip(hdr, cls._fields_):
@@ -199,3 +199,24 @@ def test_allocator_hook_needs_both_functions():
     h = ctypes.c_void_p()
     assert U.uf_create_grid(ctypes.byref(c), ctypes.byref(h)) == 1
     assert "alloc" in U.uf_last_error().decode() and not h.value
+
+
+def test_batch_calls_reject_bad_arguments_without_a_device():
+    """uf_batch_create checks its list before touching the device: NULL
+    list or handle, no grids, more than UF_BATCH_MAX_GRIDS, a NULL entry;
+    the other batch calls reject a NULL batch."""
+    import ctypes
+    import paper_2204_01117_amd as U
+    h = ctypes.c_void_p()
+    assert U.uf_batch_create(None, 1, ctypes.byref(h)) == 1
+    arr = (ctypes.c_void_p * 65)()
+    assert U.uf_batch_create(arr, 1, None) == 1
+    assert U.uf_batch_create(arr, 0, ctypes.byref(h)) == 1
+    assert U.uf_batch_create(arr, 65, ctypes.byref(h)) == 1
+    assert b"at most 64" in U.uf_last_error()
+    assert U.uf_batch_create(arr, 2, ctypes.byref(h)) == 1
+    assert b"NULL grid" in U.uf_last_error()
+    assert not h.value
+    assert U.uf_batch_step(None, 1, None) == 1
+    assert U.uf_batch_autotune(None, None) == 1
+    assert U.uf_batch_destroy(None) == 1

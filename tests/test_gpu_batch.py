@@ -82,3 +82,173 @@ def test_batch_of_uneven_city_cases():
         gs.close()
     for g in batched:
         g.close()
+
+
+# ------------------------------------------- uf_batch: persistent launches + graphs
+def _grid_cases(dtype):
+    """Uneven grids of one dtype: small ragged ones (the tile kernels of the
+    multigrid) and a 64x48x64 city (the marching level-0 kernels)."""
+    from uf_layouts import default_config, random_city, porosity_field
+    cases = []
+    for seed in (1, 5, 9):
+        cfg = random_small_config(seed, dtype=dtype, cg_tol=1e-6 if dtype == "f32" else 1e-12)
+        cases.append((cfg, random_porosity(seed, (cfg["nx"], cfg["ny"], cfg["nz"]))))
+    nx, ny, nz, h = 64, 48, 64, 2.0
+    cfg = default_config(nx, ny, nz, h, dt=0.09, u_ref=6.0, z_ref=10.0, dtype=dtype, cg_maxit=2000,
+                         cg_tol=1e-6 if dtype == "f32" else 1e-12, wind_dir_deg=30.0)
+    boxes, cyls, _ = random_city(nx, ny, nz, h, h, h, seed=77, n_boxes=6, n_trees=10)
+    cases.append((cfg, porosity_field(nx, ny, nz, h, h, h, boxes, cyls)))
+    return cases
+
+
+def _states_equal(ga, gb):
+    sa, sb = ga.state(), gb.state()
+    for f in sa:
+        assert torch.equal(sa[f], sb[f]), f
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_graph_equals_single_grid_steps(dtype):
+    """uf_batch (one launch per stage for all cases, graph replays, CG
+    branches re-captured as iteration counts change) against uf_step on
+    copies of the same grids: bit-identical states and iteration counts;
+    the autotuner's trial launches leave the state alone and a tuned batch
+    still computes the same bits."""
+    cases = _grid_cases(dtype)
+    batched = [make(c, p, False) for c, p in cases]
+    single = [make(c, p, False) for c, p in cases]
+    B = U.Batch(batched)
+    sb = B.step(6)
+    for g, s in zip(single, sb):
+        ss = g.step(6)
+        assert s["converged"] == 1
+        assert ss["cg_iters_total"] == s["cg_iters_total"] and ss["cg_iters_max"] == s["cg_iters_max"]
+    for gb, gs in zip(batched, single):
+        _states_equal(gb, gs)
+    tune = B.autotune()
+    log(dtype, "tuning", tune)
+    for gb, gs in zip(batched, single):
+        _states_equal(gb, gs)
+    assert all(v["band"] in (4, 8, 16) and v["ms"] >= 0 for v in tune.values())
+    B.step(3)
+    for g in single:
+        g.step(3)
+    for gb, gs in zip(batched, single):
+        _states_equal(gb, gs)
+    # a grid stepped on its own in between, then batched again
+    batched[0].step(1)
+    single[0].step(1)
+    B.step(1)
+    for g in single:
+        g.step(1)
+    for gb, gs in zip(batched, single):
+        _states_equal(gb, gs)
+    B.close()
+    for g in batched + single:
+        g.close()
+
+
+def test_batch_graph_case_matches_oracle():
+    """The smallest of the sixteen wind-direction cases and two ragged grids
+    in one uf_batch, each from a seeded state: one step against the oracle."""
+    from oracle import OracleGrid
+    from uf_layouts import perturbed_state
+    from helpers import state_errors, to_np
+    p = preset("C3")
+    cases = []
+    for c in range(16):
+        phi, cfg = preset_porosity(p, case=c)
+        if (cfg["nx"], cfg["ny"], cfg["nz"]) == (128, 128, 48):
+            cases.append((phi, dict(cfg, cg_tol=1e-6, cg_maxit=2000)))
+            break
+    for seed in (41, 42):
+        cfg = random_small_config(seed, dtype="f32", cg_tol=1e-7, cg_maxit=5000)
+        cases.append((random_porosity(seed, (cfg["nx"], cfg["ny"], cfg["nz"])), cfg))
+    grids, oracles = [], []
+    for q, (phi, cfg) in enumerate(cases):
+        og = OracleGrid(dict(cfg, dtype="f64"))
+        og.set_porosity(phi)
+        st = perturbed_state(og.state(), seed=60 + q)
+        for f, v in st.items():
+            og.set_field(f, v)
+        oracles.append(og)
+        g = U.Grid(cfg)
+        g.set_porosity(torch.as_tensor(phi))
+        g.set_state({f: torch.as_tensor(v) for f, v in st.items()})
+        grids.append(g)
+    B = U.Batch(grids)
+    stats = B.step(1)
+    assert all(s["converged"] for s in stats), stats
+    for g, og, (phi, cfg) in zip(grids, oracles, cases):
+        og.step(1)
+        errs = state_errors({f: to_np(v) for f, v in g.state().items()}, og.state())
+        log("uf_batch case", (cfg["nx"], cfg["ny"], cfg["nz"]), errs)
+        bad = {f: e for f, e in errs.items() if f in ("vel", "p", "k", "omega") and not e <= 1e-5}
+        assert not bad, (cfg["nx"], cfg["ny"], cfg["nz"], errs)
+    B.close()
+    for g in grids:
+        g.close()
+
+
+def test_batch_graph_rejects_what_it_cannot_run():
+    a = U.Grid(random_small_config(3, dtype="f32"))
+    b = U.Grid(random_small_config(4, dtype="f64"))
+    c = U.Grid(dict(random_small_config(5, dtype="f32"), stages=1 | 2 | 4))
+    for bad in ([a, b], [a, a], [a, c], []):
+        with pytest.raises(U.UFError) as e:
+            U.Batch(bad)
+        assert e.value.name == "UF_EINVAL"
+    B = U.Batch([a])
+    a.timer_enable(["advect_fwd"])
+    with pytest.raises(U.UFError) as e:
+        B.step(1)
+    assert e.value.name == "UF_EINVAL" and "timers" in str(e.value)
+    a.timer_enable([])
+    assert B.step(1)[0]["converged"] == 1
+    B.close()
+    for g in (a, b, c):
+        g.close()
+
+
+def _hash_p(g):
+    import hashlib
+    return hashlib.md5(g.get_field("p").cpu().numpy().tobytes()).hexdigest()
+
+
+def test_copies_stepped_together_agree_bit_for_bit():
+    """Copies of one case stepped together (uf_step_batch, each on its own
+    stream, beside other cases) against a copy stepped alone, step by step:
+    the same CG counts and the same pressure bits.  Kernels of the other
+    cases run at the same time, so what a kernel finds in its LDS when it
+    starts differs from run to run: a read of an LDS entry the kernel did
+    not write shows up here (a multigrid restriction tap one past an odd
+    level once did, stopping some copies' solves early)."""
+    from uf_layouts import default_config, random_city, porosity_field
+    cfg5 = random_small_config(5, dtype="f32")
+    phi5 = random_porosity(5, (cfg5["nx"], cfg5["ny"], cfg5["nz"]))
+    nx, ny, nz, h = 64, 48, 64, 2.0
+    cfgc = default_config(nx, ny, nz, h, dt=0.09, u_ref=6.0, z_ref=10.0, dtype="f32", cg_maxit=2000,
+                          cg_tol=1e-6, wind_dir_deg=30.0)
+    boxes, cyls, _ = random_city(nx, ny, nz, h, h, h, seed=77, n_boxes=6, n_trees=10)
+    phic = porosity_field(nx, ny, nz, h, h, h, boxes, cyls)
+    others = []
+    for seed, dt in ((1, "f32"), (2, "f64"), (7, "f64"), (9, "f32")):
+        c = random_small_config(seed, dtype=dt)
+        others.append((c, random_porosity(seed, (c["nx"], c["ny"], c["nz"]))))
+    off = []
+    for trial in range(4):
+        copies = [make(cfg5, phi5, True) for _ in range(4)] + [make(cfgc, phic, True) for _ in range(2)]
+        oth = [make(c, p, True) for c, p in others]
+        alone = [make(cfg5, phi5, False), make(cfgc, phic, False)]
+        grids = copies[:2] + oth[:2] + copies[2:4] + oth[2:] + copies[4:]
+        idx = {0: 0, 1: 0, 4: 0, 5: 0, 8: 1, 9: 1}
+        for s in range(8):
+            st = U.step_batch(grids, 1)
+            sa = [g.step(1) for g in alone]
+            ha = [_hash_p(g) for g in alone]
+            for i, a in idx.items():
+                if st[i]["cg_iters_total"] != sa[a]["cg_iters_total"] or _hash_p(grids[i]) != ha[a]:
+                    off.append((trial, s, i))
+        for g in grids + alone:
+            g.close()
+    assert not off, off
