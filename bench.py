@@ -79,7 +79,9 @@ PROFILE_NAMES = [
     ("k_mg_axpy<", "cg_axpy"),
     ("k_cg_axpy<", "cg_axpy"),
     ("k_mg_upsmooth<true", "mg_up0"),
+    ("k_mg_upsmooth_march<", "mg_up0"),
     ("k_mg_restrict<true", "mg_update0"),
+    ("k_mg_update_march<", "mg_update0"),
     ("k_cg_init<", "cg_init"),
     ("k_advect_fwd<", "advect_fwd"),
     ("k_advect_fwd32<", "advect_fwd"),
@@ -728,8 +730,10 @@ def adjoint_bench(steps, warmup, with_fd=True):
     recomputed in the reverse pass (the timed row).  Beside it: the same
     gradient with every state of the horizon kept in HBM, a plain forward
     run of the horizon, and (unless adjoint_only) the check of the gradient
-    in FP64: central differences with h = 1e-3 on 8 seeded parameters (16
-    simulations batched) against the FP64 adjoint, parameter by parameter."""
+    in FP64: central differences with h = 1e-3 and 1e-4 on 8 seeded
+    parameters (32 simulations batched) against the FP64 adjoint, parameter
+    by parameter, with the spread between the two step sizes (large where a
+    limiter or clip switches inside the step)."""
     import numpy as np
     import torch
     import paper_2204_01117_amd as U
@@ -792,24 +796,36 @@ def adjoint_bench(steps, warmup, with_fd=True):
         torch.cuda.synchronize()
         adj64_s = time.perf_counter() - t0
         idx = sorted(int(i) for i in np.random.default_rng(4).choice(d64.nparams, 8, replace=False))
-        hstep = 1e-3
+        # two step sizes: the limiter, the nu_t cap and the k/omega floors
+        # switch somewhere along the design space, so the objective is only
+        # piecewise smooth; central differences across such a switch differ
+        # from the derivative on either side, and more so the wider the step
+        hsteps = (1e-3, 1e-4)
         thetas = []
-        for i in idx:
-            for sgn in (1.0, -1.0):
-                t = theta.copy()
-                t[i] += sgn * hstep
-                thetas.append(t)
+        for hstep in hsteps:
+            for i in idx:
+                for sgn in (1.0, -1.0):
+                    t = theta.copy()
+                    t[i] += sgn * hstep
+                    thetas.append(t)
         F = O.SimulationObjective(g64, d64.porosity, nsteps=steps, initial_state=init64,
                                   score=lambda gg: gg.plane_objective(**plane))
         t0 = time.perf_counter()
         vals = F.many(thetas)
         torch.cuda.synchronize()
         fd_s = time.perf_counter() - t0
-        fd = [(vals[2 * q] - vals[2 * q + 1]) / (2 * hstep) for q in range(len(idx))]
+        nq = len(idx)
+        fd = {hs: [(vals[2 * (k * nq + q)] - vals[2 * (k * nq + q) + 1]) / (2 * hs) for q in range(nq)]
+              for k, hs in enumerate(hsteps)}
+        rel = {hs: [float(abs(grad64[i] - x) / max(abs(x), 1e-300)) for i, x in zip(idx, fd[hs])] for hs in hsteps}
         res["fd_check_fp64"] = {
-            "h": hstep, "parameters": idx, "objective": J64, "adjoint_s": adj64_s, "fd_s": fd_s,
-            "adjoint": [float(grad64[i]) for i in idx], "central_difference": [float(x) for x in fd],
-            "rel_err": [float(abs(grad64[i] - x) / max(abs(x), 1e-300)) for i, x in zip(idx, fd)],
+            "h": list(hsteps), "parameters": idx, "objective": J64, "adjoint_s": adj64_s, "fd_s": fd_s,
+            "adjoint": [float(grad64[i]) for i in idx],
+            "central_difference": {str(hs): [float(x) for x in fd[hs]] for hs in hsteps},
+            "rel_err": {str(hs): rel[hs] for hs in hsteps},
+            "rel_err_best_h": [min(rel[hs][q] for hs in hsteps) for q in range(nq)],
+            "fd_spread": [float(abs(fd[hsteps[0]][q] - fd[hsteps[1]][q]) / max(abs(fd[hsteps[1]][q]), 1e-300))
+                          for q in range(nq)],
             "fp32_adjoint": [float(grad[i]) for i in idx],
             "fp32_rel_err_vs_fp64_adjoint": [float(abs(grad[i] - grad64[i]) / max(abs(grad64[i]), 1e-300))
                                              for i in idx],
