@@ -935,13 +935,17 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth(MgCommon<T> K, MgLvl<T> F, 
 // its parent and the parent's neighbour, keeping three t planes in LDS
 // (the own columns' t also in registers), and one plane behind it the
 // smoothed z = t + om D^-1 (r - A t) and the r.z partial.  r is read once
-// per plane and band, and one barrier separates the planes.
+// per plane and band, and one barrier separates the planes.  The kernel is
+// bound by the latency of its per-plane steps: 512 threads of two columns
+// each keep twice the wavefronts of 256 threads of four in flight (64
+// registers instead of 93; 112 -> 98 us per launch at 512x512x128).
 struct UTile {
-  static constexpr int FJ = 16, FK = 64;           // fine columns, four per thread
+  static constexpr int NTH = 512;                  // threads of a block
+  static constexpr int FJ = 16, FK = 64;           // fine columns, NU per thread
   static constexpr int TJ = FJ + 2, TK = FK + 2;   // t and Y planes: 1 cell around
   static constexpr int NT = TJ * TK;
-  static constexpr int ROWS = 256 / FK;
-  static constexpr int PER = (NT + 255) / 256;     // region entries per thread
+  static constexpr int ROWS = NTH / FK;
+  static constexpr int NU = FJ / ROWS;
 };
 
 // The march applies to level 0 when every axis halves towards level 1 and
@@ -967,7 +971,7 @@ static UpGeom up_geom(const Layout& L) {
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m,
+__global__ __launch_bounds__(UTile::NTH) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c, int m,
                                                            int nfi, int nkt, int nchunk, int ntot) {
   using U = UTile;
   constexpr int NRING = U::NT - U::FJ * U::FK;   // region entries around the fine columns
@@ -1006,12 +1010,13 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<
       ct_w[tid - 64][0] = e.w0;
       ct_w[tid - 64][1] = e.w1;
     }
-    // the thread's region entries: its four fine columns (rows jr + ROWS u)
-    // and at most one entry of the ring around them
+    // the thread's region entries: its NU fine columns (rows jr + ROWS u)
+    // and at most one entry of the ring around them (entry NU)
+    constexpr int NU = U::NU, NV = NU + 1;
     const int kk = tid % U::FK, jr = tid / U::FK;
-    int ej[5], ek[5];
+    int ej[NV], ek[NV];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NU; ++u) {
       ej[u] = jr + U::ROWS * u + 1;
       ek[u] = kk + 1;
     }
@@ -1019,26 +1024,26 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<
     {
       const int q = ring ? tid : 0;
       if (q < U::TK) {
-        ej[4] = 0;
-        ek[4] = q;
+        ej[NU] = 0;
+        ek[NU] = q;
       } else if (q < 2 * U::TK) {
-        ej[4] = U::TJ - 1;
-        ek[4] = q - U::TK;
+        ej[NU] = U::TJ - 1;
+        ek[NU] = q - U::TK;
       } else {
         const int r = q - 2 * U::TK;
-        ej[4] = 1 + (r >> 1);
-        ek[4] = (r & 1) ? U::TK - 1 : 0;
+        ej[NU] = 1 + (r >> 1);
+        ek[NU] = (r & 1) ? U::TK - 1 : 0;
       }
     }
-    int pos[5], cyz[5];
-    bool in[5];
-    long long ro[5];   // offset of (j, k) within a fine plane (clamped into the ghosts)
+    int pos[NV], cyz[NV];
+    bool in[NV];
+    long long ro[NV];   // offset of (j, k) within a fine plane (clamped into the ghosts)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < NV; ++v) {
       const int j = j0 - 1 + ej[v], k = k0 - 1 + ek[v];
       pos[v] = ej[v] * U::TK + ek[v];
       cyz[v] = (bclass(j, L.ny) << 2) | bclass(k, L.nz);
-      in[v] = (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz && (v < 4 || ring);
+      in[v] = (unsigned)j < (unsigned)L.ny && (unsigned)k < (unsigned)L.nz && (v < NU || ring);
       ro[v] = (long long)(clampg(j, L.ny) + 1) * L.PZ + (clampg(k, L.nz) + 1);
     }
     __syncthreads();   // tap tables in place
@@ -1047,26 +1052,26 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<
       T* y = sy[(I + 3) % 3];
       const T* xc = C.x + (long long)(clampg(I, CL.nx) + 1) * CL.SX;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        if (v == 4 && !ring) continue;
+      for (int v = 0; v < NV; ++v) {
+        if (v == NU && !ring) continue;
         const int r0 = rt_o[ej[v]][0], r1 = rt_o[ej[v]][1], q0 = ct_o[ek[v]][0], q1 = ct_o[ek[v]][1];
         const T bw0 = rt_w[ej[v]][0], bw1 = rt_w[ej[v]][1], ew0 = ct_w[ek[v]][0], ew1 = ct_w[ek[v]][1];
         y[pos[v]] = bw0 * (ew0 * xc[r0 + q0] + ew1 * xc[r0 + q1]) + bw1 * (ew0 * xc[r1 + q0] + ew1 * xc[r1 + q1]);
       }
     };
-    T rv[5];
+    T rv[NV];
     auto load_r = [&](int i) {
       const T* rp = F.r + (long long)(clampg(i, L.nx) + 1) * L.SX;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) rv[v] = (v < 4 || ring) ? rp[ro[v]] : T(0);
+      for (int v = 0; v < NV; ++v) rv[v] = (v < NU || ring) ? rp[ro[v]] : T(0);
     };
     const int ts = i0 - 1, te = i1;   // t planes of the chunk
     int ymax = (ts >> 1) + 1;
     for (int I = (ts >> 1) - 1; I <= ymax; ++I) make_y(I);
     load_r(ts);
-    T tm[4], tc[4], tn[4], rc[4], rn[4];   // own t(i-2), t(i-1), t(i); own r(i-1), r(i)
+    T tm[NU], tc[NU], tn[NU], rc[NU], rn[NU];   // own t(i-2), t(i-1), t(i); own r(i-1), r(i)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) tm[u] = tc[u] = tn[u] = rc[u] = rn[u] = T(0);
+    for (int u = 0; u < NU; ++u) tm[u] = tc[u] = tn[u] = rc[u] = rn[u] = T(0);
     for (int i = ts; i <= te; ++i) {
       __syncthreads();   // the Y planes of plane i are in place; t slot i % 3 is free
       const Tap2<T> a = ptap(i, 1, CL.nx, K.sgn[0], K.sgn[1]);
@@ -1076,11 +1081,11 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<
       const bool iin = (unsigned)i < (unsigned)L.nx;
       const int cx = bclass(i, L.nx) << 4;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        if (v == 4 && !ring) continue;
+      for (int v = 0; v < NV; ++v) {
+        if (v == NU && !ring) continue;
         const T tv = (iin && in[v]) ? tab_omd[cx | cyz[v]] * rv[v] + a.w0 * ya[pos[v]] + a.w1 * yb[pos[v]] : T(0);
         t[pos[v]] = tv;
-        if (v < 4) {
+        if (v < NU) {
           tn[v] = tv;
           rn[v] = rv[v];
         }
@@ -1101,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<
         const T* tp = st[(iz + 3) % 3];
         const int czx = bclass(iz, L.nx) << 4;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < NU; ++u) {
           if (!in[u]) continue;
           const int cl = czx | cyz[u];
           const int q = pos[u];
@@ -1113,7 +1118,7 @@ __global__ __launch_bounds__(256) void k_mg_upsmooth_march(MgCommon<T> K, MgLvl<
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < NU; ++u) {
         tm[u] = tc[u];
         tc[u] = tn[u];
         rc[u] = rn[u];
@@ -1721,7 +1726,7 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   TimedLaunch tl(g, UF_TK_MG_UP0);
   if (nl > 1 && up_march(L0.L)) {
     const UpGeom u = up_geom(L0.L);
-    launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(256), K, L0, L1, c, m, u.nfi, u.nkt,
+    launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(UTile::NTH), K, L0, L1, c, m, u.nfi, u.nkt,
              u.nchunk, u.ntot);
   } else if (nl > 1)
     launch_up<true, true, T>(g, K, L0, L1, c, m);

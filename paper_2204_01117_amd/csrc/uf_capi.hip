@@ -847,8 +847,10 @@ const FaceRun kTrial[5] = {{MS_ADVECT_FWD, 0, 0, 1}, {MS_ADVECT_CORR, 0, 1, 2}, 
 
 template <class T>
 void enqueue_face(Batch& b, const FaceRun& r, hipStream_t st) {
+  // the corrector's queue has three entries per face block (one per component)
+  const int entries = (r.stage == MS_ADVECT_CORR ? 3 : 1) * b.faces.start[b.faces.n];
   launch_faces_multi<T>(r.stage, (const MultiCase<T>*)b.table, b.faces, b.tune.band[r.stage],
-                        stage_blocks(b.tune, r.stage, b.faces.start[b.faces.n]), r.sin, r.saux, r.sout, st);
+                        stage_blocks(b.tune, r.stage, entries), r.sin, r.saux, r.sout, st);
 }
 
 template <class T>
