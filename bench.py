@@ -81,7 +81,8 @@ PROFILE_NAMES = [
     ("k_mg_upsmooth<true", "mg_up0"),
     ("k_mg_upsmooth_march<", "mg_up0"),
     ("k_mg_restrict<true", "mg_update0"),
-    ("k_mg_update_march<", "mg_update0"),
+    ("k_mg_update_march<true", "mg_update0"),
+    ("k_mg_update_march<false", "mg_down0"),
     ("k_cg_init<", "cg_init"),
     ("k_advect_fwd<", "advect_fwd"),
     ("k_advect_fwd32<", "advect_fwd"),
@@ -296,6 +297,7 @@ def traffic_summary(run_dir, command, out_dir=None, name="C2"):
             continue
         if bn not in best or grid > best[bn][1]:
             best[bn] = (name, grid)
+    # the first restriction of a solve, when tiled: the largest tiled restriction
     if "mg_down0" not in best:
         cands = [(n, gr) for (n, gr) in fetch if "k_mg_restrict<false" in n and (n, gr) in write]
         if cands:

@@ -598,31 +598,49 @@ __device__ __forceinline__ void ring_pos(int q, int& ej, int& ek) {
   }
 }
 
-template <class T>
+// CGU false: the plain restriction of level F's r (what k_mg_restrict<false>
+// computes), with k_mg_restrict's modes -- 0: skip when flags[m] is set;
+// 1: the block past the tile walkers (logical block ntot) decides whether
+// the solve has finished and publishes flags[m], the others work
+// unconditionally; 2: unconditional.
+template <bool CGU, class T>
 __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T> F, MgLvl<T> C, CgCtl c,
-                                                         CgUpd<T> upd, int nci, int nkt, int nchunk, int ntot) {
+                                                         CgUpd<T> upd, int nci, int nkt, int nchunk, int ntot,
+                                                         int m, int mode) {
   using X = XTile<T>;
   __shared__ T se[3][X::NE];
   __shared__ T sres[X::NR];
   __shared__ T tab_omd[64];
   __shared__ T tab_a[64];
-  // the same decision and alpha as the stand-alone update kernel
-  double rz = 0.0, dq = 0.0;
-  bool run = iteration_open(c, upd.t);
-  if (run) {
-    rz = c.st->rzh[upd.t & 1];
-    run = rz_allows(c, rz);
+  const int per = (int)(gridDim.x >> 3);
+  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  T alpha = T(0);
+  if constexpr (CGU) {
+    // the same decision and alpha as the stand-alone update kernel
+    double rz = 0.0, dq = 0.0;
+    bool run = iteration_open(c, upd.t);
+    if (run) {
+      rz = c.st->rzh[upd.t & 1];
+      run = rz_allows(c, rz);
+    }
+    if (run) {
+      dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb_dq);
+      run = dq > 0.0 && isfinite(dq);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c.exec[upd.t] = run;
+      if (run) c.st->iter = upd.t + 1;
+    }
+    if (!run) return;
+    alpha = (T)(rz / dq);
+  } else {
+    if (mode == 1 && lb == ntot) {
+      const bool done = precond_skip(c, m);
+      if (threadIdx.x == 0) c.flags[m] = done;
+      return;
+    }
+    if (mode == 0 && c.flags[m]) return;   // the solve has finished (uniform over the grid)
   }
-  if (run) {
-    dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb_dq);
-    run = dq > 0.0 && isfinite(dq);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    c.exec[upd.t] = run;
-    if (run) c.st->iter = upd.t + 1;
-  }
-  if (!run) return;
-  const T alpha = (T)(rz / dq);
   if (threadIdx.x < 64) {
     const T D = class_diag(K, F, threadIdx.x);
     tab_omd[threadIdx.x] = D > T(0) ? K.om / D : T(0);
@@ -630,9 +648,7 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
   }
   const Layout& L = F.L;
   double acc_rr[1] = {0.0};
-  // logical block: XCD-contiguous ranges of (j tile, k tile, chunk)
-  const int per = (int)(gridDim.x >> 3);
-  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  // logical block lb: XCD-contiguous ranges of (j tile, k tile, chunk)
   if (lb < ntot) {
     const int tile = lb / nchunk, ch = lb - tile * nchunk;
     const int jt = tile / nkt, kt = tile - jt * nkt;
@@ -677,6 +693,8 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
     rweights(Kc, C.L.nz, L.nz, K.sgn[4], K.sgn[5], wk);
     // plane values in registers: own r_t, q (and x, d on updated planes), ring r_t, q
     T orr[4], oq[4], ox[4], od[4], rr_[2], rq_[2];
+    // the residual read: r_t (with q for the update) or level F's r
+    const T* __restrict__ rin = CGU ? upd.Rin : F.r;
     auto load_plane = [&](int f) {
       const int fg = clampg(f, L.nx);
       const bool upd_plane = f >= own0 && f < own1;
@@ -684,17 +702,19 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const long long o = base + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
-        orr[u] = upd.Rin[o];
-        oq[u] = upd.Q[o];
-        const bool live = upd_plane && jin[u] && kin;
-        ox[u] = live ? upd.X[o] : T(0);
-        od[u] = live ? upd.D[o] : T(0);
+        orr[u] = rin[o];
+        if constexpr (CGU) {
+          oq[u] = upd.Q[o];
+          const bool live = upd_plane && jin[u] && kin;
+          ox[u] = live ? upd.X[o] : T(0);
+          od[u] = live ? upd.D[o] : T(0);
+        }
       }
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         const long long o = base + (long long)(rjg[v] + 1) * L.PZ + (rkg[v] + 1);
-        rr_[v] = ron[v] ? upd.Rin[o] : T(0);
-        rq_[v] = ron[v] ? upd.Q[o] : T(0);
+        rr_[v] = ron[v] ? rin[o] : T(0);
+        if constexpr (CGU) rq_[v] = ron[v] ? upd.Q[o] : T(0);
       }
     };
     const int fe0 = 2 * I0 - 2, fe1 = 2 * I1 + 1;   // e planes
@@ -712,11 +732,11 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
       // own cells: the update, then e from the updated residual
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const T r = orr[u] - alpha * oq[u];
+        const T r = CGU ? orr[u] - alpha * oq[u] : orr[u];
         const int jj = jr + X::ROWS * u;
         const int cl = cx | (bclass(j0 + jj, L.ny) << 2) | bclass(k, L.nz);
         e[(jj + 2) * X::EK + kk + 2] = tab_omd[cl] * r;
-        if (upd_plane && jin[u] && kin) {
+        if (CGU && upd_plane && jin[u] && kin) {
           const long long o = (long long)(f + 1) * L.SX + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
           upd.X[o] = ox[u] + alpha * od[u];
           F.r[o] = r;
@@ -728,7 +748,7 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
         if (!ron[v]) continue;
         const int ej = rpos[v] / X::EK, ek = rpos[v] - ej * X::EK;
         const int cl = cx | (bclass(j0 - 2 + ej, L.ny) << 2) | bclass(k0 - 2 + ek, L.nz);
-        e[rpos[v]] = tab_omd[cl] * (rr_[v] - alpha * rq_[v]);
+        e[rpos[v]] = tab_omd[cl] * (CGU ? rr_[v] - alpha * rq_[v] : rr_[v]);
       }
       if (f < fe1) load_plane(f + 1);
       __syncthreads();
@@ -773,9 +793,11 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
     }
     if (cin && Icur - 1 >= I0 && Icur - 1 < I1) C.r[C.L.at(Icur - 1, J, Kc)] = acc_prev;
   }
-  const int slots[1] = {S_RR};
-  write_partials<1>(acc_rr, c.part, c.stride, slots, (int)blockIdx.x);
-  pad_partials(c, S_RR, (int)blockIdx.x, (int)gridDim.x);
+  if constexpr (CGU) {
+    const int slots[1] = {S_RR};
+    write_partials<1>(acc_rr, c.part, c.stride, slots, (int)blockIdx.x);
+    pad_partials(c, S_RR, (int)blockIdx.x, (int)gridDim.x);
+  }
 }
 
 // Tile of the up/smoothing kernel (cells of its level per block of 256).
@@ -1648,6 +1670,20 @@ static MarchGeom march_geom(const MgLevel& F, const MgLevel& C) {
   return m;
 }
 
+// Launch size of a marching restriction: 8 * ceil(n / 8) blocks for the
+// ntot walkers and, in mode 1, the deciding block (logical block ntot).
+static int march_blocks(const MarchGeom& m, int mode) {
+  const int n = m.ntot + (mode == 1 ? 1 : 0);
+  return 8 * ((n + 7) / 8);
+}
+
+template <class T>
+static void launch_march_restrict(Grid& g, const MgCommon<T>& K, const MgLvl<T>& F, const MgLvl<T>& C,
+                                  const MarchGeom& mgeo, const CgCtl& c, int m, int mode) {
+  launch_k(g, k_mg_update_march<false, T>, dim3(march_blocks(mgeo, mode)), dim3(256), K, F, C, c, CgUpd<T>{},
+           mgeo.nci, mgeo.nkt, mgeo.nchunk, mgeo.ntot, m, mode);
+}
+
 // Blocks of the level-0 restriction when it carries the CG update (the
 // writer of the r.r partials besides the CG kernels), or 0 when the update
 // stays separate: it needs a coarse restriction kernel after it to decide
@@ -1656,7 +1692,7 @@ size_t mg_fused_blocks(const Grid& g) {
   const int nl = (int)g.mg.size();
   if (g.cfg.precond != UF_PC_MG || nl < 3 || std::min(g.mg_lt, nl - 1) < 2) return 0;
   const MarchGeom mg = march_geom(g.mg[0], g.mg[1]);
-  if (mg.use) return (size_t)(8 * ((mg.ntot + 7) / 8));
+  if (mg.use) return (size_t)march_blocks(mg, 0);
   const Layout& C = g.mg[1].L;
   const int3 nt3 = g.esize == 4 ? restrict_tiles<float>(C) : restrict_tiles<double>(C);
   return (size_t)level_blocks((long long)nt3.x * nt3.y * nt3.z);
@@ -1693,10 +1729,12 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
   {
     TimedLaunch tl(g, upd ? UF_TK_MG_UPDATE0 : UF_TK_MG_DOWN0);
-    const MarchGeom mgeo = (upd && nl > 1) ? march_geom(g.mg[0], g.mg[1]) : MarchGeom{};
-    if (mgeo.use)
-      launch_k(g, k_mg_update_march<T>, dim3(8 * ((mgeo.ntot + 7) / 8)), dim3(256), K, L0, L1, c, *upd, mgeo.nci,
-               mgeo.nkt, mgeo.nchunk, mgeo.ntot);
+    const MarchGeom mgeo = nl > 1 ? march_geom(g.mg[0], g.mg[1]) : MarchGeom{};
+    if (mgeo.use && upd)
+      launch_k(g, k_mg_update_march<true, T>, dim3(march_blocks(mgeo, 0)), dim3(256), K, L0, L1, c, *upd,
+               mgeo.nci, mgeo.nkt, mgeo.nchunk, mgeo.ntot, m, 0);
+    else if (mgeo.use)
+      launch_march_restrict<T>(g, K, L0, L1, mgeo, c, m, decide ? 1 : 2);
     else
       launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2, upd);
   }
@@ -1705,6 +1743,8 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
     const MgLvl<T> F = mg_level<T>(g, l), C = mg_level<T>(g, l + 1);
     TimedLaunch tl(g, UF_TK_MG_COARSE);
     // after a fused update the first coarse restriction takes the decision
+    // (the coarse levels keep the tiled kernel: their x-chunks of a few
+    // planes would re-read as much as they restrict)
     launch_restrict<T>(g, K, F, C, 1, c, m, (upd && l == 1) ? 1 : 0);
   }
   if (nl > 1) {
@@ -1726,8 +1766,8 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   TimedLaunch tl(g, UF_TK_MG_UP0);
   if (nl > 1 && up_march(L0.L)) {
     const UpGeom u = up_geom(L0.L);
-    launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(UTile::NTH), K, L0, L1, c, m, u.nfi, u.nkt,
-             u.nchunk, u.ntot);
+    launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(UTile::NTH), K, L0, L1, c, m, u.nfi,
+             u.nkt, u.nchunk, u.ntot);
   } else if (nl > 1)
     launch_up<true, true, T>(g, K, L0, L1, c, m);
   else
