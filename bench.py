@@ -411,22 +411,27 @@ def stats_summary(run_dir, command, out_name="kernels_256x256x64.md",
 
 
 def precond_study():
-    """Pressure solves on the 256x256x64 system for each preconditioner (the
-    paper's comparison, Sec. 3 and its Tables 2-3, on this grid): seeded
-    normal right-hand side, zero initial guess, the paper's stopping rule
-    (M^-1 r . r / ||b||^2 < 1e-5) and the default one (||r|| <= 1e-6 ||b||).
-    One JSON line per case: iterations and GPU time of the solve."""
+    """Pressure solves for each preconditioner (the paper's comparison, Sec. 3
+    and its Tables 2-3) on the 256x256x64 system and on the 2-D 128x192
+    system of Table 3 (inlet and outlet across x, walls and slip sides
+    elsewhere): seeded normal right-hand side, zero initial guess, the
+    paper's stopping rule (M^-1 r . r / ||b||^2 < 1e-5) and the default one
+    (||r|| <= 1e-6 ||b||).  One JSON line per case: iterations and GPU time
+    of the solve."""
     import numpy as np
     import torch
     import paper_2204_01117_amd as U
-    from uf_layouts.configs import PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG
-    _, _, cfg = workload("C1")
-    shape = (cfg["nx"], cfg["ny"], cfg["nz"])
-    b = torch.tensor(np.random.default_rng(7).normal(size=shape), dtype=torch.float32, device="cuda:0")
+    from uf_layouts import default_config
+    from uf_layouts.configs import PC_NONE, PC_JACOBI, PC_AI1, PC_AI2, PC_MG, BC_INLET, BC_OUTLET, BC_WALL, BC_SLIP
+    _, _, cfg3 = workload("C1")
+    cfg2 = default_config(128, 192, 1, 1.0, dtype="f32",
+                          bc=[BC_INLET, BC_OUTLET, BC_WALL, BC_WALL, BC_SLIP, BC_SLIP])
     cases = [("CG", PC_NONE, 1.6), ("Jacobi", PC_JACOBI, 1.6), ("AI1", PC_AI1, 1.0), ("AI1", PC_AI1, 1.6),
              ("AI1", PC_AI1, 1.8), ("AI2", PC_AI2, 1.0), ("AI2", PC_AI2, 1.6), ("AI2", PC_AI2, 1.8),
              ("MG", PC_MG, 1.6)]
-    for crit, tol in ((1, 1e-5), (0, 1e-6)):
+    for cfg, crit, tol in ((cfg2, 1, 1e-5), (cfg3, 1, 1e-5), (cfg3, 0, 1e-6)):
+        shape = (cfg["nx"], cfg["ny"], cfg["nz"])
+        b = torch.tensor(np.random.default_rng(7).normal(size=shape), dtype=torch.float32, device="cuda:0")
         for name, pc, om in cases:
             g = U.Grid(dict(cfg, precond=pc, ai_omega=om, cg_criterion=crit, cg_tol=tol, cg_maxit=20000),
                        device="cuda:0")

@@ -151,12 +151,20 @@ __device__ __forceinline__ void advect_corr32_component(const Params<T>& P, cons
   }
 }
 
-// Single grid: the component is blockIdx.y.
+// Single grid, launched on xcd_grid(3 face_gx, nx + 1): the three
+// components of a face block are neighbours in the logical order, so they
+// run together on one XCD and share the velocity and sample loads in its
+// L2 (with the component as a grid dimension of its own each array was
+// fetched from HBM three times).
 template <class T>
 __global__ __launch_bounds__(kFaceBlock) void k_advect_corr32(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Uh, const T* __restrict__ Vh, const T* __restrict__ Wh, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+  const int gx = face_gx(P.L), gy = P.L.nx + 1;
+  const int per = (int)(gridDim.x >> 3);
+  const int e = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (e >= 3 * gx * gy) return;
   int bx, ib;
-  if (!face_block(P.L, bx, ib)) return;
-  advect_corr32_component(P, U, V, W, Uh, Vh, Wh, Uo, Vo, Wo, (int)blockIdx.y, bx, ib);
+  band_map(gx, gy, kFaceBand, e / 3, bx, ib);
+  advect_corr32_component(P, U, V, W, Uh, Vh, Wh, Uo, Vo, Wo, e % 3, bx, ib);
 }
 
 // ------------------------------------------------------------- diffusion --
@@ -353,7 +361,7 @@ void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const 
                (const T*)Qin[2], (T*)Qhat[0], (T*)Qhat[1], (T*)Qhat[2]);
     }
     TimedLaunch tl(g, UF_TK_ADVECT_CORR);
-    launch_k(g, k_advect_corr32<T>, dim3(grid.x, 3), dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
+    launch_k(g, k_advect_corr32<T>, xcd_grid(3 * face_gx(P.L), P.L.nx + 1), dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
              (const T*)Qin[2], (const T*)Qhat[0], (const T*)Qhat[1], (const T*)Qhat[2], (T*)Qout[0], (T*)Qout[1],
              (T*)Qout[2]);
     return;
