@@ -970,15 +970,19 @@ struct UTile {
   static constexpr int NU = FJ / ROWS;
 };
 
-// The march applies to level 0 when every axis halves towards level 1 and
-// the columns fill the tile's depth.
-static bool up_march(const Layout& L) {
-  return L.nx >= 4 && L.ny >= 4 && L.nz >= UTile::FK && (long long)L.nx * L.ny * L.nz > kCoarsestCells;
-}
-
 struct UpGeom {
   int nfi, nkt, nchunk, ntot;
 };
+
+static UpGeom up_geom(const Layout& L);
+
+// The march applies to level 0 when every axis halves towards level 1, the
+// columns fill the tile's depth and a chunk is at least 16 planes long (it
+// forms t on two planes past its own).
+static bool up_march(const Layout& L) {
+  return L.nx >= 4 && L.ny >= 4 && L.nz >= UTile::FK && (long long)L.nx * L.ny * L.nz > kCoarsestCells &&
+         up_geom(L).nfi >= 16;
+}
 
 static UpGeom up_geom(const Layout& L) {
   UpGeom u;
@@ -1666,7 +1670,9 @@ static MarchGeom march_geom(const MgLevel& F, const MgLevel& C) {
   m.nchunk = (C.L.nx + m.nci - 1) / m.nci;
   m.nkt = nkt;
   m.ntot = tiles * m.nchunk;
-  m.use = true;
+  // a chunk re-reads four fine planes around its own: below 8 coarse planes
+  // per chunk (256x256x64: 2) the tiled kernel moves fewer bytes
+  m.use = m.nci >= 8;
   return m;
 }
 

@@ -220,6 +220,34 @@ def test_c2_projection_whole_grid(c2_case):
     errs = state_errors(out, ref)
     log("C2 projection: cg", s["cg_iters"], errs)
     assert errs["vel"] <= 1e-5 and errs["p"] <= 1e-5, errs
+    # a preconditioner broken but still positive definite would converge too,
+    # only slowly: from the perturbed state's warm start this takes about 10
+    assert s["cg_iters"] <= 25, s
+
+
+@pytest.mark.timeout(300)
+def test_c2_multigrid_marching_kernels_are_a_symmetric_operator(c2_case):
+    """At 512x512x128 level 0 of the multigrid cycle runs the marching
+    kernels (the update-free restriction march of a stand-alone application,
+    the prolongation/smoothing march; chunks of 16 coarse and 32 fine planes):
+    in FP64 the preconditioner they form is symmetric (y.Mx = x.My to 1e-12)
+    and positive, and applying it twice gives the same bits.  A restriction
+    that is not the transpose of the prolongation, a dropped halo entry or a
+    misplaced plane breaks the symmetry."""
+    _, cfg, _ = c2_case
+    g = gpu_grid(dict(cfg, dtype="f64", precond=PC_MG))
+    rng = np.random.default_rng(11)
+    x = torch.tensor(rng.normal(size=g.n))
+    y = torch.tensor(rng.normal(size=g.n))
+    mx, my = to_np(g.apply_operator(1, x)), to_np(g.apply_operator(1, y))
+    xn, yn = x.numpy(), y.numpy()
+    a, b = float((yn * mx).sum()), float((xn * my).sum())
+    xmx, ymy = float((xn * mx).sum()), float((yn * my).sum())
+    log("C2 multigrid: y.Mx", a, "x.My", b, "x.Mx", xmx)
+    assert xmx > 0 and ymy > 0
+    assert abs(a - b) <= 1e-12 * np.sqrt(xmx * ymy)
+    assert np.array_equal(mx, to_np(g.apply_operator(1, x)))
+    g.close()
 
 
 # ------------------------------------------------------ CFL at and near 1 ---
