@@ -616,81 +616,6 @@ __global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __
   project_faces(P, U, V, W, Pp, Uo, Vo, Wo, bx, ib);
 }
 
-// Projection as an x-march, in the layout of k_diffuse_march: a face reads
-// only its own velocity and the pressures of its two cells, so the thread
-// keeps p of cells i - 1 and i in registers and plane i's pressures (with
-// the cells j - 1 and k - 1) in LDS.  Each value is what project_value
-// computes; the top w faces go to k_project_top, the sides to k_face_sides.
-template <class T>
-__global__ __launch_bounds__(DTile::NTH) void k_project_march(Params<T> P, const T* __restrict__ U,
-                                                              const T* __restrict__ V, const T* __restrict__ W,
-                                                              const T* __restrict__ Pp, T* __restrict__ Uo,
-                                                              T* __restrict__ Vo, T* __restrict__ Wo) {
-  using D = DTile;
-  __shared__ T sp[2][D::NJ * D::NK];
-  const Layout& L = P.L;
-  const int ntj = dtiles_j(L), ntk = dtiles_k(L), nch = dchunks(L);
-  const int ntile = ntj * ntk;
-  const int per = (int)(gridDim.x >> 3);
-  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-  if (lb >= ntile * nch) return;
-  const int ch = lb / ntile, tile = lb - ch * ntile;
-  const int jt = tile / ntk, kt = tile - jt * ntk;
-  const int j0 = jt * D::DJ, k0 = kt * D::DK;
-  const int i0 = ch * D::ILEN, i1 = min(L.nx + 1, i0 + D::ILEN);
-  const int tid = threadIdx.x;
-  const int kk = tid % D::DK, jj = tid / D::DK;
-  const int j = j0 + jj, k = k0 + kk;
-  const bool live = j <= L.ny && k < L.nz;
-  const long long SX = L.SX, PZ = L.PZ;
-  const long long ocol = (long long)(min(j, L.ny + 1) + 1) * PZ + (min(k, L.nz + 1) + 1);
-  int npos = -1;
-  long long noff = 0;
-  if (tid < D::NNH) {
-    const int nj = tid < D::NK ? 0 : 1 + (tid - D::NK), nk = tid < D::NK ? tid : 0;
-    npos = nj * D::NK + nk;
-    noff = (long long)(min(j0 - 1 + nj, L.ny + 1) + 1) * PZ + (min(k0 - 1 + nk, L.nz + 1) + 1);
-  }
-  const int nown = (jj + 1) * D::NK + kk + 1;
-  auto pl = [&](int i) { return (long long)(min(i, L.nx + 1) + 1) * SX; };
-  T pm = Pp[pl(i0 - 1) + ocol], pc = Pp[pl(i0) + ocol];
-  T qu = U[pl(i0) + ocol], qv = V[pl(i0) + ocol], qw = W[pl(i0) + ocol];
-  for (int i = i0; i < i1; ++i) {
-    T* s = sp[i & 1];
-    s[nown] = pc;
-    if (npos >= 0) s[npos] = Pp[pl(i) + noff];
-    const T pn = Pp[pl(i + 1) + ocol];
-    const T nu_ = U[pl(i + 1) + ocol], nv = V[pl(i + 1) + ocol], nw = W[pl(i + 1) + ocol];
-    __syncthreads();
-    if (live) {
-      const T a0 = qu - P.dt_rho * ((pc - pm) * P.ih[0]);
-      const T a1 = qv - P.dt_rho * ((pc - s[nown - D::NK]) * P.ih[1]);
-      const T a2 = qw - P.dt_rho * ((pc - s[nown - 1]) * P.ih[2]);
-      const long long o = L.at(i, j, k);
-      if (j < L.ny) Uo[o] = a0;
-      if (i < L.nx) Vo[o] = a1;
-      if (i < L.nx && j < L.ny) Wo[o] = a2;
-    }
-    pm = pc;
-    pc = pn;
-    qu = nu_;
-    qv = nv;
-    qw = nw;
-  }
-}
-
-// The top w faces (k = nz) of the projection march (raw values).
-template <class T>
-__global__ __launch_bounds__(256) void k_project_top(Params<T> P, const T* __restrict__ W, const T* __restrict__ Pp,
-                                                     T* __restrict__ Wo) {
-  const Layout& L = P.L;
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (p >= L.nx * L.ny) return;
-  const int i = p / L.ny, j = p - i * L.ny;
-  const long long o = L.at(i, j, L.nz);
-  Wo[o] = project_value<2>(P, W, Pp, o);
-}
-
 // ------------------------------------------------ boundary refresh (in place)
 template <int C, class T>
 __global__ __launch_bounds__(kFaceBlock) void k_face_bc(Params<T> P, T* __restrict__ q) {
@@ -852,21 +777,6 @@ void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qo
 
 template <class T>
 void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
-  const Layout& L = P.L;
-  if (L.nz >= DTile::DK) {
-    {
-      TimedLaunch tl(g, UF_TK_PROJECT);
-      launch_k(g, k_project_march<T>, xcd_grid(dtiles_j(L) * dtiles_k(L), dchunks(L)), dim3(DTile::NTH), P,
-               (const T*)Qin[0], (const T*)Qin[1], (const T*)Qin[2], (const T*)g.X, (T*)Qout[0], (T*)Qout[1],
-               (T*)Qout[2]);
-    }
-    launch_k(g, k_project_top<T>, dim3((unsigned)((L.nx * L.ny + 255) / 256)), dim3(256), P, (const T*)Qin[2],
-             (const T*)g.X, (T*)Qout[2]);
-    launch_face_sides<0, T>(g, P, Qout[0]);
-    launch_face_sides<1, T>(g, P, Qout[1]);
-    launch_face_sides<2, T>(g, P, Qout[2]);
-    return;
-  }
   TimedLaunch tl(g, UF_TK_PROJECT);
   launch_k(g, k_project<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)g.X, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
