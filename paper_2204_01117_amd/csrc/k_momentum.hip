@@ -441,154 +441,6 @@ __global__ __launch_bounds__(kFaceBlock) void k_drag(Params<T> P, const T* __res
   drag_faces(P, U, V, W, Cc, Uo, Vo, Wo, nf, bx, ib);
 }
 
-// Drag as an x-march, in the layout of k_diffuse_march.  The velocity vector
-// at a face reads the other components one face back along its own axis and
-// one forward along theirs, so planes i - 1, i and i + 1 of u, v and w are in
-// LDS (a ring of four planes: one barrier per plane), with the drag
-// coefficient of cells i - 1 and i in registers and of plane i's cells j - 1
-// and k - 1 in LDS.  Each value is what drag_value computes, in the same
-// order; the top w faces go to k_drag_top, the sides to k_face_sides.
-template <class T>
-__global__ __launch_bounds__(DTile::NTH) void k_drag_march(Params<T> P, const T* __restrict__ U,
-                                                           const T* __restrict__ V, const T* __restrict__ W,
-                                                           const T* __restrict__ Cc, T* __restrict__ Uo,
-                                                           T* __restrict__ Vo, T* __restrict__ Wo, int* nf) {
-  using D = DTile;
-  constexpr int PN = D::HJ * D::HK;
-  __shared__ T sq[4][3][PN];
-  __shared__ T sc[2][D::NJ * D::NK];
-  const Layout& L = P.L;
-  const int ntj = dtiles_j(L), ntk = dtiles_k(L), nch = dchunks(L);
-  const int ntile = ntj * ntk;
-  const int per = (int)(gridDim.x >> 3);
-  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-  if (lb >= ntile * nch) return;
-  const int ch = lb / ntile, tile = lb - ch * ntile;
-  const int jt = tile / ntk, kt = tile - jt * ntk;
-  const int j0 = jt * D::DJ, k0 = kt * D::DK;
-  const int i0 = ch * D::ILEN, i1 = min(L.nx + 1, i0 + D::ILEN);
-  const int tid = threadIdx.x;
-  const int kk = tid % D::DK, jj = tid / D::DK;
-  const int j = j0 + jj, k = k0 + kk;
-  const bool live = j <= L.ny && k < L.nz;
-  const long long SX = L.SX, PZ = L.PZ;
-  const long long ocol = (long long)(min(j, L.ny + 1) + 1) * PZ + (min(k, L.nz + 1) + 1);
-  int hpos = -1, npos = -1;
-  long long hoff = 0, noff = 0;
-  if (tid < D::NH) {
-    int hj, hk;
-    if (tid < D::HK) {
-      hj = 0;
-      hk = tid;
-    } else if (tid < 2 * D::HK) {
-      hj = D::HJ - 1;
-      hk = tid - D::HK;
-    } else {
-      const int r = tid - 2 * D::HK;
-      hj = 1 + (r >> 1);
-      hk = (r & 1) ? D::HK - 1 : 0;
-    }
-    hpos = hj * D::HK + hk;
-    hoff = (long long)(min(j0 - 1 + hj, L.ny + 1) + 1) * PZ + (min(k0 - 1 + hk, L.nz + 1) + 1);
-  } else if (tid - D::NH < D::NNH) {
-    const int r = tid - D::NH;
-    const int nj = r < D::NK ? 0 : 1 + (r - D::NK), nk = r < D::NK ? r : 0;
-    npos = nj * D::NK + nk;
-    noff = (long long)(min(j0 - 1 + nj, L.ny + 1) + 1) * PZ + (min(k0 - 1 + nk, L.nz + 1) + 1);
-  }
-  const int own = (jj + 1) * D::HK + kk + 1;
-  const int nown = (jj + 1) * D::NK + kk + 1;
-  const T* Q[3] = {U, V, W};
-  auto pl = [&](int i) { return (long long)(min(i, L.nx + 1) + 1) * SX; };
-  // planes i0 - 1 and i0 into their slots
-  for (int i = i0 - 1; i <= i0; ++i) {
-    const int s = i & 3;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      sq[s][c][own] = Q[c][pl(i) + ocol];
-      if (hpos >= 0) sq[s][c][hpos] = Q[c][pl(i) + hoff];
-    }
-  }
-  T qn[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) qn[c] = Q[c][pl(i0 + 1) + ocol];
-  T cm = Cc[pl(i0 - 1) + ocol], cc = Cc[pl(i0) + ocol];
-  for (int i = i0; i < i1; ++i) {
-    // plane i + 1 into its slot (the slot of plane i - 3, read before the last barrier)
-    const int sn_ = (i + 1) & 3;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      sq[sn_][c][own] = qn[c];
-      if (hpos >= 0) sq[sn_][c][hpos] = Q[c][pl(i + 1) + hoff];
-    }
-    T* scb = sc[i & 1];
-    scb[nown] = cc;
-    if (npos >= 0) scb[npos] = Cc[pl(i) + noff];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) qn[c] = Q[c][pl(i + 2) + ocol];
-    const T cn = Cc[pl(i + 1) + ocol];
-    __syncthreads();
-    if (live) {
-      const T* u0 = sq[i & 3][0];
-      const T* v0 = sq[i & 3][1];
-      const T* w0 = sq[i & 3][2];
-      const T* vm = sq[(i - 1) & 3][1];
-      const T* wm = sq[(i - 1) & 3][2];
-      const T* up = sq[(i + 1) & 3][0];
-      constexpr int J = D::HK;   // one row of the LDS plane
-      // u face: v and w one plane back and here, j / k forward
-      T a0, a1, a2;
-      {
-        const T vel0 = u0[own];
-        const T vel1 = T(0.25) * (vm[own] + vm[own + J] + v0[own] + v0[own + J]);
-        const T vel2 = T(0.25) * (wm[own] + wm[own + 1] + w0[own] + w0[own + 1]);
-        const T speed = sqrt(vel0 * vel0 + vel1 * vel1 + vel2 * vel2);
-        const T cf = T(0.5) * (cm + cc);
-        a0 = nmax(T(0), T(1) - P.dt * cf * speed) * vel0;
-      }
-      {
-        const T vel0 = T(0.25) * (u0[own - J] + up[own - J] + u0[own] + up[own]);
-        const T vel1 = v0[own];
-        const T vel2 = T(0.25) * (w0[own - J] + w0[own - J + 1] + w0[own] + w0[own + 1]);
-        const T speed = sqrt(vel0 * vel0 + vel1 * vel1 + vel2 * vel2);
-        const T cf = T(0.5) * (scb[nown - D::NK] + cc);
-        a1 = nmax(T(0), T(1) - P.dt * cf * speed) * vel1;
-      }
-      {
-        const T vel0 = T(0.25) * (u0[own - 1] + up[own - 1] + u0[own] + up[own]);
-        const T vel1 = T(0.25) * (v0[own - 1] + v0[own - 1 + J] + v0[own] + v0[own + J]);
-        const T vel2 = w0[own];
-        const T speed = sqrt(vel0 * vel0 + vel1 * vel1 + vel2 * vel2);
-        const T cf = T(0.5) * (scb[nown - 1] + cc);
-        a2 = nmax(T(0), T(1) - P.dt * cf * speed) * vel2;
-      }
-      const bool ou = j < L.ny, ov = i < L.nx, ow = i < L.nx && j < L.ny;
-      if ((ou && !isfinite(a0)) || (ov && !isfinite(a1)) || (ow && !isfinite(a2))) *nf = 1;
-      const long long o = L.at(i, j, k);
-      if (ou) Uo[o] = a0;
-      if (ov) Vo[o] = a1;
-      if (ow) Wo[o] = a2;
-    }
-    cm = cc;
-    cc = cn;
-  }
-}
-
-// The top w faces (k = nz) of the drag march (raw values).
-template <class T>
-__global__ __launch_bounds__(256) void k_drag_top(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
-                                                  const T* __restrict__ W, const T* __restrict__ Cc,
-                                                  T* __restrict__ Wo, int* nf) {
-  const Layout& L = P.L;
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (p >= L.nx * L.ny) return;
-  const int i = p / L.ny, j = p - i * L.ny;
-  const long long o = L.at(i, j, L.nz);
-  const T a = drag_value<2>(P, U, V, W, Cc, o);
-  if (!isfinite(a)) *nf = 1;
-  Wo[o] = a;
-}
-
 // ------------------------------------------------ projection (velocity part)
 template <int C, class T>
 __device__ __forceinline__ T project_value(const Params<T>& P, const T* __restrict__ q, const T* __restrict__ p,
@@ -755,21 +607,6 @@ void launch_diffuse(Grid& g, const Params<T>& P, void* const Qin[3], void* const
 
 template <class T>
 void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
-  const Layout& L = P.L;
-  if (L.nz >= DTile::DK) {
-    {
-      TimedLaunch tl(g, UF_TK_DRAG);
-      launch_k(g, k_drag_march<T>, xcd_grid(dtiles_j(L) * dtiles_k(L), dchunks(L)), dim3(DTile::NTH), P,
-               (const T*)Qin[0], (const T*)Qin[1], (const T*)Qin[2], (const T*)g.C, (T*)Qout[0], (T*)Qout[1],
-               (T*)Qout[2], nf_word(g));
-    }
-    launch_k(g, k_drag_top<T>, dim3((unsigned)((L.nx * L.ny + 255) / 256)), dim3(256), P, (const T*)Qin[0],
-             (const T*)Qin[1], (const T*)Qin[2], (const T*)g.C, (T*)Qout[2], nf_word(g));
-    launch_face_sides<0, T>(g, P, Qout[0]);
-    launch_face_sides<1, T>(g, P, Qout[1]);
-    launch_face_sides<2, T>(g, P, Qout[2]);
-    return;
-  }
   TimedLaunch tl(g, UF_TK_DRAG);
   launch_k(g, k_drag<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0], (const T*)Qin[1],
                      (const T*)Qin[2], (const T*)g.C, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2], nf_word(g));
