@@ -199,212 +199,6 @@ __global__ __launch_bounds__(kFaceBlock) void k_diffuse(Params<T> P, const T* __
   diffuse_faces(P, U, V, W, NUT, Uo, Vo, Wo, bx, ib);
 }
 
-// Diffusion as a march along x.  A block owns DJ x DK cell corners (j, k),
-// k below nz, over a chunk of x-planes; a thread keeps its corner's three
-// components on planes i - 1, i, i + 1 in registers (the x neighbours of
-// the Laplacian) and nu_t of cells i - 1 and i, and publishes plane i in
-// LDS with a one-corner halo (the y and z neighbours; halo entries are
-// loaded by the threads past the corners, clamped into the padded array
-// where a partial tile reaches past it).  One barrier per plane (the LDS
-// planes alternate).  Each value is what diffuse_value computes, in the
-// same order.  The corners at k = nz carry only the top w faces:
-// k_diffuse_top.
-struct DTile {
-  static constexpr int NTH = 512;                  // threads of a block, one corner each
-  static constexpr int DJ = 8, DK = 64;
-  static constexpr int HJ = DJ + 2, HK = DK + 2;   // plane with the halo
-  static constexpr int NH = HJ * HK - DJ * DK;     // halo entries of a component plane
-  static constexpr int NJ = DJ + 1, NK = DK + 1;   // nu_t: cells j - 1 .. and k - 1 ..
-  static constexpr int NNH = NJ * NK - DJ * DK;    // their halo entries
-  static constexpr int ILEN = 16;                  // x-planes of a chunk
-  static_assert(DJ * DK == NTH && NH + NNH <= NTH, "one corner and at most one halo entry per thread");
-};
-
-__host__ __device__ inline int dtiles_j(const Layout& L) { return (L.ny + 1 + DTile::DJ - 1) / DTile::DJ; }
-__host__ __device__ inline int dtiles_k(const Layout& L) { return (L.nz + DTile::DK - 1) / DTile::DK; }
-__host__ __device__ inline int dchunks(const Layout& L) { return (L.nx + 1 + DTile::ILEN - 1) / DTile::ILEN; }
-
-template <class T>
-__global__ __launch_bounds__(DTile::NTH) void k_diffuse_march(Params<T> P, const T* __restrict__ U, const T* __restrict__ V,
-                                                       const T* __restrict__ W, const T* __restrict__ NUT,
-                                                       T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
-  using D = DTile;
-  __shared__ T sq[2][3][D::HJ * D::HK];
-  __shared__ T sn[2][D::NJ * D::NK];
-  const Layout& L = P.L;
-  const int ntj = dtiles_j(L), ntk = dtiles_k(L), nch = dchunks(L);
-  const int ntile = ntj * ntk;
-  const int per = (int)(gridDim.x >> 3);
-  const int lb = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
-  if (lb >= ntile * nch) return;
-  // chunk-major: the tiles of one chunk are neighbours in the logical order
-  const int ch = lb / ntile, tile = lb - ch * ntile;
-  const int jt = tile / ntk, kt = tile - jt * ntk;
-  const int j0 = jt * D::DJ, k0 = kt * D::DK;
-  const int i0 = ch * D::ILEN, i1 = min(L.nx + 1, i0 + D::ILEN);
-  const int tid = threadIdx.x;
-  const int kk = tid % D::DK, jj = tid / D::DK;
-  const int j = j0 + jj, k = k0 + kk;
-  const bool live = j <= L.ny && k < L.nz;
-  const long long SX = L.SX, PZ = L.PZ;
-  // own column (clamped into the padded array for the corners past the grid)
-  const long long ocol = (long long)(min(j, L.ny + 1) + 1) * PZ + (min(k, L.nz + 1) + 1);
-  // halo entry of this thread, if any: position in the LDS plane and offset in a padded plane
-  int hpos = -1, npos = -1;
-  long long hoff = 0, noff = 0;
-  if (tid < D::NH) {
-    int hj, hk;
-    if (tid < D::HK) {
-      hj = 0;
-      hk = tid;
-    } else if (tid < 2 * D::HK) {
-      hj = D::HJ - 1;
-      hk = tid - D::HK;
-    } else {
-      const int r = tid - 2 * D::HK;
-      hj = 1 + (r >> 1);
-      hk = (r & 1) ? D::HK - 1 : 0;
-    }
-    hpos = hj * D::HK + hk;
-    hoff = (long long)(min(j0 - 1 + hj, L.ny + 1) + 1) * PZ + (min(k0 - 1 + hk, L.nz + 1) + 1);
-  } else if (tid - D::NH < D::NNH) {
-    const int r = tid - D::NH;
-    int nj, nk;
-    if (r < D::NK) {
-      nj = 0;
-      nk = r;
-    } else {
-      nj = 1 + (r - D::NK);
-      nk = 0;
-    }
-    npos = nj * D::NK + nk;
-    noff = (long long)(min(j0 - 1 + nj, L.ny + 1) + 1) * PZ + (min(k0 - 1 + nk, L.nz + 1) + 1);
-  }
-  const int own = (jj + 1) * D::HK + kk + 1;
-  const int nown = (jj + 1) * D::NK + kk + 1;
-  const T* Q[3] = {U, V, W};
-  T qm[3], qc[3], qp[3], nm, nc;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    qm[c] = Q[c][(long long)i0 * SX + ocol];         // plane i0 - 1
-    qc[c] = Q[c][(long long)(i0 + 1) * SX + ocol];   // plane i0
-    qp[c] = Q[c][(long long)(i0 + 2) * SX + ocol];   // plane i0 + 1 (at most nx + 1: a ghost)
-  }
-  nm = NUT[(long long)i0 * SX + ocol];
-  nc = NUT[(long long)(i0 + 1) * SX + ocol];
-  for (int i = i0; i < i1; ++i) {
-    const int b = i & 1;
-    const long long pi = (long long)(i + 1) * SX;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sq[b][c][own] = qc[c];
-    sn[b][nown] = nc;
-    if (hpos >= 0) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) sq[b][c][hpos] = Q[c][pi + hoff];
-    }
-    if (npos >= 0) sn[b][npos] = NUT[pi + noff];
-    // next plane's values, loaded before the barrier so that they are in flight
-    T qn[3], nn;
-    const long long pn = (long long)(min(i + 2, L.nx + 1) + 1) * SX;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) qn[c] = Q[c][pn + ocol];
-    nn = NUT[(long long)(min(i + 1, L.nx + 1) + 1) * SX + ocol];
-    __syncthreads();
-    if (live) {
-      const T* s0 = sq[b][0];
-      const T* s1 = sq[b][1];
-      const T* s2 = sq[b][2];
-      const T* sN = sn[b];
-      T a[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T* sc = c == 0 ? s0 : (c == 1 ? s1 : s2);
-        const T q0 = qc[c];
-        const T lap = (qp[c] - T(2) * q0 + qm[c]) * P.ih2[0] + (sc[own + D::HK] - T(2) * q0 + sc[own - D::HK]) * P.ih2[1] +
-                      (sc[own + 1] - T(2) * q0 + sc[own - 1]) * P.ih2[2];
-        const T nb = c == 0 ? nm : (c == 1 ? sN[nown - D::NK] : sN[nown - 1]);
-        const T nuf = P.nu + T(0.5) * (nb + nc);
-        a[c] = q0 + P.dt * nuf * lap;
-      }
-      // the raw values of the owned faces; k_face_sides then fixes the faces
-      // on the sides and writes the ghosts (finish_face inlined here held
-      // three times the registers of the loop)
-      const long long o = L.at(i, j, k);
-      if (j < L.ny) Uo[o] = a[0];
-      if (i < L.nx) Vo[o] = a[1];
-      if (i < L.nx && j < L.ny) Wo[o] = a[2];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      qm[c] = qc[c];
-      qc[c] = qp[c];
-      qp[c] = qn[c];
-    }
-    nm = nc;
-    nc = nn;
-  }
-}
-
-// The top w faces (k = nz) of the march above (raw values).
-template <class T>
-__global__ __launch_bounds__(256) void k_diffuse_top(Params<T> P, const T* __restrict__ W, const T* __restrict__ NUT,
-                                                     T* __restrict__ Wo) {
-  const Layout& L = P.L;
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (p >= L.nx * L.ny) return;
-  const int i = p / L.ny, j = p - i * L.ny;
-  const long long o = L.at(i, j, L.nz);
-  Wo[o] = diffuse_value<2>(P, W, NUT, o);
-}
-
-// What finish_face adds to a raw value, for every owned face of component
-// C on the six sides of its extent: the fixed value of a Dirichlet face and
-// the ghosts (store_face).  Thread t of [0, 2 e1 e2) takes the x sides,
-// then the y sides, then the z sides; a face on an edge is taken twice,
-// with the same result.
-template <int C, class T>
-__global__ __launch_bounds__(256) void k_face_sides(Params<T> P, T* __restrict__ q) {
-  int e[3];
-  face_ext<C>(P.L, e);
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k;
-  const long long nx_ = 2LL * e[1] * e[2], ny_ = 2LL * e[0] * e[2], nz_ = 2LL * e[0] * e[1];
-  if (t < nx_) {
-    const int side = (int)(t / ((long long)e[1] * e[2]));
-    const long long r = t - (long long)side * e[1] * e[2];
-    i = side ? e[0] - 1 : 0;
-    j = (int)(r / e[2]);
-    k = (int)(r - (long long)j * e[2]);
-  } else if ((t -= nx_) < ny_) {
-    const int side = (int)(t / ((long long)e[0] * e[2]));
-    const long long r = t - (long long)side * e[0] * e[2];
-    j = side ? e[1] - 1 : 0;
-    i = (int)(r / e[2]);
-    k = (int)(r - (long long)i * e[2]);
-  } else if ((t -= ny_) < nz_) {
-    const int side = (int)(t / ((long long)e[0] * e[1]));
-    const long long r = t - (long long)side * e[0] * e[1];
-    k = side ? e[2] - 1 : 0;
-    i = (int)(r / e[1]);
-    j = (int)(r - (long long)i * e[1]);
-  } else {
-    return;
-  }
-  if (!owns_face<C, T>(P.L, i, j, k)) return;
-  const long long o = P.L.at(i, j, k);
-  T v = q[o];
-  T val;
-  if (face_dirichlet<C>(P, i, j, k, &val)) v = val;
-  store_face<C>(q, P, i, j, k, v);
-}
-
-template <int C, class T>
-static void launch_face_sides(Grid& g, const Params<T>& P, void* q) {
-  int e[3] = {P.L.nx + (C == 0), P.L.ny + (C == 1), P.L.nz + (C == 2)};
-  const long long n = 2LL * ((long long)e[1] * e[2] + (long long)e[0] * e[2] + (long long)e[0] * e[1]);
-  launch_k(g, k_face_sides<C, T>, dim3((unsigned)((n + 255) / 256)), dim3(256), P, (T*)q);
-}
-
 // ------------------------------------------------------------ porosity drag
 template <int C, class T>
 __device__ __forceinline__ T drag_value(const Params<T>& P, const T* __restrict__ U, const T* __restrict__ V,
@@ -585,21 +379,6 @@ void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const 
 
 template <class T>
 void launch_diffuse(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
-  const Layout& L = P.L;
-  if (L.nz >= DTile::DK) {
-    {
-      TimedLaunch tl(g, UF_TK_DIFFUSE);
-      launch_k(g, k_diffuse_march<T>, xcd_grid(dtiles_j(L) * dtiles_k(L), dchunks(L)), dim3(DTile::NTH), P,
-               (const T*)Qin[0], (const T*)Qin[1], (const T*)Qin[2], (const T*)g.NUT, (T*)Qout[0], (T*)Qout[1],
-               (T*)Qout[2]);
-    }
-    launch_k(g, k_diffuse_top<T>, dim3((unsigned)((L.nx * L.ny + 255) / 256)), dim3(256), P, (const T*)Qin[2],
-             (const T*)g.NUT, (T*)Qout[2]);
-    launch_face_sides<0, T>(g, P, Qout[0]);
-    launch_face_sides<1, T>(g, P, Qout[1]);
-    launch_face_sides<2, T>(g, P, Qout[2]);
-    return;
-  }
   TimedLaunch tl(g, UF_TK_DIFFUSE);
   launch_k(g, k_diffuse<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0],
                      (const T*)Qin[1], (const T*)Qin[2], (const T*)g.NUT, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
