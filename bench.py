@@ -53,6 +53,8 @@ ALG_BYTES_PER_CELL = {
     "mg_up0": 8.5,        # read r, the level-1 correction (1/8); write z
     "mg_down0": 4.5,      # read r; write the level-1 residual (1/8)
     "mg_update0": 24.5,   # read x, r, d, q; write x, r and the level-1 residual (1/8)
+    "mg_rupd0": 12.5,     # marching form: read r, q; write r and the level-1 residual (1/8)
+    "cg_xupd": 12.0,      # read x, d; write x (beside the coarse levels, with the marching form)
     "cg_init": 20.0,      # read u*, v*, w*, p; write r
     "advect_fwd": 24.0,   # read u, v, w; write the forward-traced u, v, w
     "advect_corr": 36.0,  # read u, v, w and the traced fields; write u, v, w
@@ -67,10 +69,11 @@ ALG_BYTES_PER_CELL = {
 # application (its coarse levels add about 1/7 of the level-0 kernels).
 STEP_FIXED_KERNELS = ("advect_fwd", "advect_corr", "diffuse", "drag", "project", "turbulence", "cg_init")
 ALG_FIXED_PER_CELL = sum(ALG_BYTES_PER_CELL[k] for k in STEP_FIXED_KERNELS)
+# (the marching form's split into mg_rupd0 + cg_xupd moves the same bytes as mg_update0)
 ALG_ITER_PER_CELL = (ALG_BYTES_PER_CELL["cg_Ad"] + ALG_BYTES_PER_CELL["mg_update0"] - ALG_BYTES_PER_CELL["mg_down0"] +
                      (ALG_BYTES_PER_CELL["mg_up0"] + ALG_BYTES_PER_CELL["mg_down0"]) * 8.0 / 7.0)
 STEP_PREFIXES = ("k_advect_", "k_diffuse", "k_drag", "k_project", "k_turbulence", "k_cg_init", "k_cg_start")
-ITER_PREFIXES = ("k_cg_Ad", "k_cg_axpy", "k_mg_", "k_cg_precond", "k_ai2_", "k_cg_status")
+ITER_PREFIXES = ("k_cg_Ad", "k_cg_axpy", "k_cg_xupd", "k_mg_", "k_cg_precond", "k_ai2_", "k_cg_status")
 
 # Kernels of the library by their profiler names (first match wins) and
 # the names the kernel timer and ALG_BYTES_PER_CELL use.
@@ -81,7 +84,8 @@ PROFILE_NAMES = [
     ("k_mg_upsmooth<true", "mg_up0"),
     ("k_mg_upsmooth_march<", "mg_up0"),
     ("k_mg_restrict<true", "mg_update0"),
-    ("k_mg_update_march<true", "mg_update0"),
+    ("k_mg_update_march<true", "mg_rupd0"),
+    ("k_cg_xupd<", "cg_xupd"),
     ("k_mg_update_march<false", "mg_down0"),
     ("k_cg_init<", "cg_init"),
     ("k_advect_fwd<", "advect_fwd"),
@@ -182,7 +186,8 @@ KERNEL_FILES = {
     "diffuse": ["k_momentum.hip", "face_ops.h"], "drag": ["k_momentum.hip", "face_ops.h"],
     "project": ["k_momentum.hip", "face_ops.h"], "turbulence": ["k_cells.hip", "turb_model.h"],
     "cg_Ad": ["k_pressure.hip"], "cg_axpy": ["k_pressure.hip"], "cg_init": ["k_pressure.hip"],
-    "mg_up0": ["k_mg.hip"], "mg_down0": ["k_mg.hip"], "mg_update0": ["k_mg.hip"],
+    "mg_up0": ["k_mg.hip"], "mg_down0": ["k_mg.hip"], "mg_update0": ["k_mg.hip"], "mg_rupd0": ["k_mg.hip"],
+    "cg_xupd": ["k_mg.hip"],
 }
 DEVICE_HEADERS = ["uf_device.h", "pressure_common.h"]
 

@@ -486,15 +486,17 @@ uf_status uf_adjoint_step_at(uf_grid g, const void* const* state_n_dev, const vo
  * elapsed times are accumulated (for the benchmark's per-kernel bandwidth
  * figures).  UF_TK_MG_COARSE covers every multigrid kernel below the finest
  * level; UF_TK_MG_UPDATE0 is the level-0 restriction that also performs the
- * CG update (the multigrid preconditioner inside the iterations), and
- * UF_TK_MG_DOWN0 the plain one.  mask: bit UF_TK_* per kernel; 0 disables.  Enabling resets the
+ * CG update (the multigrid preconditioner inside the iterations),
+ * UF_TK_MG_RUPD0 its marching form on large grids, which performs the
+ * residual update only (x += alpha d runs on the solve's second stream and
+ * is not timed), and UF_TK_MG_DOWN0 the plain restriction.  mask: bit UF_TK_* per kernel; 0 disables.  Enabling resets the
  * totals.  uf_kernel_timer_read synchronises and returns the total
  * milliseconds and the number of launches of one kernel since the timer
  * was enabled. */
 enum { UF_TK_CG_AD = 0, UF_TK_CG_AXPY = 1, UF_TK_CG_PRECOND = 2, UF_TK_MG_DOWN0 = 3, UF_TK_MG_UP0 = 4,
        UF_TK_MG_COARSE = 5, UF_TK_CG_INIT = 6, UF_TK_ADVECT_FWD = 7, UF_TK_ADVECT_CORR = 8,
        UF_TK_DIFFUSE = 9, UF_TK_DRAG = 10, UF_TK_PROJECT = 11, UF_TK_TURB = 12, UF_TK_MG_UPDATE0 = 13,
-       UF_TK_COUNT = 14 };
+       UF_TK_MG_RUPD0 = 14, UF_TK_COUNT = 15 };
 uf_status uf_kernel_timer_enable(uf_grid g, uint32_t mask);
 uf_status uf_kernel_timer_read(uf_grid g, int32_t kernel, double* total_ms, int64_t* launches);
 

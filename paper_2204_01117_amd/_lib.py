@@ -164,7 +164,8 @@ uf_voxelize = lib.uf_voxelize
 uf_kernel_timer_enable = lib.uf_kernel_timer_enable
 uf_kernel_timer_read = lib.uf_kernel_timer_read
 TIMED_KERNELS = ("cg_Ad", "cg_axpy", "cg_precond", "mg_down0", "mg_up0", "mg_coarse", "cg_init",
-                 "advect_fwd", "advect_corr", "diffuse", "drag", "project", "turbulence", "mg_update0")
+                 "advect_fwd", "advect_corr", "diffuse", "drag", "project", "turbulence", "mg_update0",
+                 "mg_rupd0")
 uf_last_error = lib.uf_last_error
 
 

@@ -365,7 +365,8 @@ struct RTile {
 // preconditioner application that follows it: x += alpha d and
 // r_{t+1} = r_t - alpha q (into F.r) on the fine cells whose parents are in
 // the block's tiles, the r.r partials, and the restriction of the
-// pre-smoothed r_{t+1} formed from r_t and q directly.
+// pre-smoothed r_{t+1} formed from r_t and q directly.  (The marching
+// kernel below leaves x += alpha d to k_cg_xupd.)
 template <class T>
 struct CgUpd {
   T* X;
@@ -544,8 +545,9 @@ __global__ __launch_bounds__(256) void k_mg_restrict(MgCommon<T> K, MgLvl<T> F, 
 }
 
 // ------------------------- level-0 update and restriction, marching in x ---
-// The CG update of iteration t and the level-0 restriction of the
-// application that follows -- what k_mg_restrict<true> computes -- with the
+// The residual update of iteration t and the level-0 restriction of the
+// application that follows -- what k_mg_restrict<true> computes but x +=
+// alpha d, which k_cg_xupd does beside the coarse levels -- with the
 // work laid out as a march along x: a block owns CJ x CK coarse (j, k)
 // columns (their 2CJ x 2CK fine children) over a chunk of coarse x-planes
 // and walks the fine planes in order.  Per fine plane it forms
@@ -598,6 +600,10 @@ __device__ __forceinline__ void ring_pos(int q, int& ej, int& ek) {
   }
 }
 
+// CGU true: the residual update r -= alpha q of CG iteration upd.t (its
+// decision and alpha as k_mg_restrict<true>'s), then the restriction of the
+// pre-smoothed new residual; the iterate's update x += alpha d is left to
+// k_cg_xupd, which runs beside the coarse levels.
 // CGU false: the plain restriction of level F's r (what k_mg_restrict<false>
 // computes), with k_mg_restrict's modes -- 0: skip when flags[m] is set;
 // 1: the block past the tile walkers (logical block ntot) decides whether
@@ -691,24 +697,18 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
     T wj[4], wk[4];
     rweights(J, C.L.ny, L.ny, K.sgn[2], K.sgn[3], wj);
     rweights(Kc, C.L.nz, L.nz, K.sgn[4], K.sgn[5], wk);
-    // plane values in registers: own r_t, q (and x, d on updated planes), ring r_t, q
-    T orr[4], oq[4], ox[4], od[4], rr_[2], rq_[2];
+    // plane values in registers: own r_t, q, ring r_t, q
+    T orr[4], oq[4], rr_[2], rq_[2];
     // the residual read: r_t (with q for the update) or level F's r
     const T* __restrict__ rin = CGU ? upd.Rin : F.r;
     auto load_plane = [&](int f) {
       const int fg = clampg(f, L.nx);
-      const bool upd_plane = f >= own0 && f < own1;
       const long long base = (long long)(fg + 1) * L.SX;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const long long o = base + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
         orr[u] = rin[o];
-        if constexpr (CGU) {
-          oq[u] = upd.Q[o];
-          const bool live = upd_plane && jin[u] && kin;
-          ox[u] = live ? upd.X[o] : T(0);
-          od[u] = live ? upd.D[o] : T(0);
-        }
+        if constexpr (CGU) oq[u] = upd.Q[o];
       }
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
@@ -738,7 +738,6 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
         e[(jj + 2) * X::EK + kk + 2] = tab_omd[cl] * r;
         if (CGU && upd_plane && jin[u] && kin) {
           const long long o = (long long)(f + 1) * L.SX + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
-          upd.X[o] = ox[u] + alpha * od[u];
           F.r[o] = r;
           acc_rr[0] += (double)r * (double)r;
         }
@@ -797,6 +796,37 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
     const int slots[1] = {S_RR};
     write_partials<1>(acc_rr, c.part, c.stride, slots, (int)blockIdx.x);
     pad_partials(c, S_RR, (int)blockIdx.x, (int)gridDim.x);
+  }
+}
+
+// x += alpha d of CG iteration t over the interior cells of level 0, the
+// update the marching restriction leaves out: the decision (exec[t], which
+// that kernel published) and alpha come from the same values as there, and
+// the partial-sum reduction has the same 256-thread shape, so x gets the
+// same bits as an update inside the restriction.  Launched on a stream of
+// its own after the restriction; the iteration's end waits for it.
+template <class T>
+__global__ __launch_bounds__(256) void k_cg_xupd(Layout L, T* __restrict__ X, const T* __restrict__ D, CgCtl c,
+                                                 int t) {
+  if (!c.exec[t]) return;
+  const double rz = c.st->rzh[t & 1];
+  const double dq = slot_sum(c.part + (size_t)S_DQ * c.stride, c.nb_dq);
+  const T alpha = (T)(rz / dq);
+  // work items: 64-cell pieces of the (i, j) rows, one per wavefront at a
+  // time (a grid has fewer than 2^31 padded cells: 32-bit indices)
+  const unsigned nz = (unsigned)L.nz, ny = (unsigned)L.ny;
+  const unsigned kc = (nz + 63u) >> 6;
+  const unsigned items = (unsigned)L.nx * ny * kc;
+  const unsigned lane = threadIdx.x & 63u;
+  const unsigned nw = gridDim.x * 4u;
+  for (unsigned it = blockIdx.x * 4u + (threadIdx.x >> 6); it < items; it += nw) {
+    const unsigned w = __builtin_amdgcn_readfirstlane(it);
+    const unsigned row = w / kc, k = (w - row * kc) * 64u + lane;
+    const unsigned i = row / ny, j = row - i * ny;
+    if (k < nz) {
+      const long long o = L.at((int)i, (int)j, (int)k);
+      X[o] = X[o] + alpha * D[o];
+    }
   }
 }
 
@@ -1733,9 +1763,10 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   L0.r = (T*)r;
   L0.x = (T*)z;
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
+  bool xfork = false;   // x += alpha d runs on the second stream
+  const MarchGeom mgeo = nl > 1 ? march_geom(g.mg[0], g.mg[1]) : MarchGeom{};
   {
-    TimedLaunch tl(g, upd ? UF_TK_MG_UPDATE0 : UF_TK_MG_DOWN0);
-    const MarchGeom mgeo = nl > 1 ? march_geom(g.mg[0], g.mg[1]) : MarchGeom{};
+    TimedLaunch tl(g, upd ? (mgeo.use ? UF_TK_MG_RUPD0 : UF_TK_MG_UPDATE0) : UF_TK_MG_DOWN0);
     if (mgeo.use && upd)
       launch_k(g, k_mg_update_march<true, T>, dim3(march_blocks(mgeo, 0)), dim3(256), K, L0, L1, c, *upd,
                mgeo.nci, mgeo.nkt, mgeo.nchunk, mgeo.ntot, m, 0);
@@ -1743,6 +1774,17 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
       launch_march_restrict<T>(g, K, L0, L1, mgeo, c, m, decide ? 1 : 2);
     else
       launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2, upd);
+  }
+  if (mgeo.use && upd) {
+    // x += alpha d of the iteration on the second stream, beside the
+    // coarse levels; joined at the end of this application (at 256x256x64,
+    // where the tiled kernel keeps the update, a separate pass and the
+    // stream switch cost more than they save: 1.34 -> 1.43 ms per step)
+    UF_HIP_CHECK(hipEventRecord(g.ev_xfork, g.stream));
+    UF_HIP_CHECK(hipStreamWaitEvent(g.xstream, g.ev_xfork, 0));
+    hipLaunchKernelGGL(k_cg_xupd<T>, dim3(1024), dim3(256), 0, g.xstream, L0.L, upd->X, upd->D, c, upd->t);
+    UF_HIP_CHECK(hipEventRecord(g.ev_xjoin, g.xstream));
+    xfork = true;
   }
   const int lt = std::min(g.mg_lt, nl - 1);
   for (int l = 1; l < lt; ++l) {
@@ -1769,15 +1811,18 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
       launch_up<false, true, T>(g, K, F, C, c, m);
     }
   }
-  TimedLaunch tl(g, UF_TK_MG_UP0);
-  if (nl > 1 && up_march(L0.L)) {
-    const UpGeom u = up_geom(L0.L);
-    launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(UTile::NTH), K, L0, L1, c, m, u.nfi,
-             u.nkt, u.nchunk, u.ntot);
-  } else if (nl > 1)
-    launch_up<true, true, T>(g, K, L0, L1, c, m);
-  else
-    launch_up<true, false, T>(g, K, L0, L1, c, m);
+  {
+    TimedLaunch tl(g, UF_TK_MG_UP0);
+    if (nl > 1 && up_march(L0.L)) {
+      const UpGeom u = up_geom(L0.L);
+      launch_k(g, k_mg_upsmooth_march<T>, dim3(8 * ((u.ntot + 7) / 8)), dim3(UTile::NTH), K, L0, L1, c, m, u.nfi,
+               u.nkt, u.nchunk, u.ntot);
+    } else if (nl > 1)
+      launch_up<true, true, T>(g, K, L0, L1, c, m);
+    else
+      launch_up<true, false, T>(g, K, L0, L1, c, m);
+  }
+  if (xfork) UF_HIP_CHECK(hipStreamWaitEvent(g.stream, g.ev_xjoin, 0));
 }
 
 template <class T>

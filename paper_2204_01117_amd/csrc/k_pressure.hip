@@ -570,8 +570,8 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
                c, t, al.ilen, al.njt, al.nkt);
   }
   if (g.mg_fused) {
-    // the update x += alpha d, r -= alpha q runs inside the multigrid's
-    // first restriction
+    // r -= alpha q runs inside the multigrid's first restriction, x +=
+    // alpha d beside its coarse levels
     mg_iteration_update<T>(g, P, t, Dnew);
     return;
   }

@@ -269,6 +269,11 @@ void free_grid(Grid* g) {
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
   g->ev_status = g->ev0 = g->ev1 = nullptr;
+  if (g->ev_xfork) (void)hipEventDestroy(g->ev_xfork);
+  if (g->ev_xjoin) (void)hipEventDestroy(g->ev_xjoin);
+  g->ev_xfork = g->ev_xjoin = nullptr;
+  if (g->xstream) (void)hipStreamDestroy(g->xstream);
+  g->xstream = nullptr;
   for (hipEvent_t e : g->timer_pool) (void)hipEventDestroy(e);
   g->timer_pool.clear();
   mg_free(*g);
@@ -1133,6 +1138,9 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
   UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_status, hipEventDisableTiming));
   UF_HIP_CHECK(hipEventCreate(&g->ev0));
   UF_HIP_CHECK(hipEventCreate(&g->ev1));
+  UF_HIP_CHECK(hipStreamCreateWithFlags(&g->xstream, hipStreamNonBlocking));
+  UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_xfork, hipEventDisableTiming));
+  UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_xjoin, hipEventDisableTiming));
   UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (g->esize == 4) {
     upload_inflow<float>(*g);

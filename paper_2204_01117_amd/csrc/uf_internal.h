@@ -148,6 +148,11 @@ struct Grid {
   double* diag = nullptr;    // [3][kDiagBlocks] partials of the end-of-call diagnostics
   double* diag_host = nullptr;  // pinned copy
   hipEvent_t ev_status = nullptr, ev0 = nullptr, ev1 = nullptr;
+  // second stream of the pressure solve: the iterate's update x += alpha d
+  // of a CG iteration runs there beside the coarse multigrid levels, forked
+  // after the level-0 restriction and joined before the next iteration
+  hipStream_t xstream = nullptr;
+  hipEvent_t ev_xfork = nullptr, ev_xjoin = nullptr;
   std::vector<MgLevel> mg;
   int mg_lt = 0;                // first level of the single-workgroup kernel
   bool mg_tail_lds = true;      // the small levels fit the LDS pool of the single-workgroup kernel
