@@ -252,3 +252,32 @@ def test_copies_stepped_together_agree_bit_for_bit():
         for g in grids + alone:
             g.close()
     assert not off, off
+
+
+def test_large_grids_with_the_second_solve_stream_batched():
+    """512x512x128 grids take the marching level-0 restriction, whose CG
+    iterations fork the iterate's update onto a second stream and join it
+    back: inside uf_batch's captured solve graphs and under uf_step_batch's
+    interleaving, two copies of the workload match a copy stepped alone bit
+    for bit."""
+    p = preset("C2")
+    phi, cfg = preset_porosity(p)
+    alone = make(cfg, phi, False)
+    graph = [make(cfg, phi, False) for _ in range(2)]
+    inter = [make(cfg, phi, True) for _ in range(2)]
+    log("512x512x128 grids made")
+    B = U.Batch(graph)
+    sb = B.step(2)
+    si = U.step_batch(inter, 2)
+    sa = alone.step(2)
+    log("iterations", sa["cg_iters_total"], [s["cg_iters_total"] for s in sb], [s["cg_iters_total"] for s in si])
+    for s in sb + si:
+        assert s["converged"] == 1 and s["cg_iters_total"] == sa["cg_iters_total"]
+    ref = alone.state()
+    for g in graph + inter:
+        st = g.state()
+        for f in ref:
+            assert torch.equal(st[f], ref[f]), f
+    B.close()
+    for g in graph + inter + [alone]:
+        g.close()
