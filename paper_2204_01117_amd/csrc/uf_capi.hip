@@ -1177,6 +1177,9 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
 uf_status uf_destroy_grid(uf_grid g) {
   if (!g) return fail(UF_EINVAL, "NULL grid");
   (void)hipStreamSynchronize(g->stream);
+  // every fork onto the second solve stream is joined back into the grid's
+  // stream within the enqueueing call, unless that call failed half-way
+  if (g->xstream) (void)hipStreamSynchronize(g->xstream);
   free_grid(g);
   delete g;
   return UF_OK;
