@@ -1764,12 +1764,13 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   L0.x = (T*)z;
   const MgLvl<T> L1 = nl > 1 ? mg_level<T>(g, 1) : L0;
   bool xfork = false;   // x += alpha d runs on the second stream
+  hipEvent_t fork = nullptr;   // completed by the restriction's dispatch
   const MarchGeom mgeo = nl > 1 ? march_geom(g.mg[0], g.mg[1]) : MarchGeom{};
   {
     TimedLaunch tl(g, upd ? (mgeo.use ? UF_TK_MG_RUPD0 : UF_TK_MG_UPDATE0) : UF_TK_MG_DOWN0);
     if (mgeo.use && upd)
-      launch_k(g, k_mg_update_march<true, T>, dim3(march_blocks(mgeo, 0)), dim3(256), K, L0, L1, c, *upd,
-               mgeo.nci, mgeo.nkt, mgeo.nchunk, mgeo.ntot, m, 0);
+      fork = launch_k_done(g, g.ev_xfork, k_mg_update_march<true, T>, dim3(march_blocks(mgeo, 0)), dim3(256), K,
+                           L0, L1, c, *upd, mgeo.nci, mgeo.nkt, mgeo.nchunk, mgeo.ntot, m, 0);
     else if (mgeo.use)
       launch_march_restrict<T>(g, K, L0, L1, mgeo, c, m, decide ? 1 : 2);
     else
@@ -1780,8 +1781,7 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
     // coarse levels; joined at the end of this application (at 256x256x64,
     // where the tiled kernel keeps the update, a separate pass and the
     // stream switch cost more than they save: 1.34 -> 1.43 ms per step)
-    UF_HIP_CHECK(hipEventRecord(g.ev_xfork, g.stream));
-    UF_HIP_CHECK(hipStreamWaitEvent(g.xstream, g.ev_xfork, 0));
+    UF_HIP_CHECK(hipStreamWaitEvent(g.xstream, fork, 0));
     hipLaunchKernelGGL(k_cg_xupd<T>, dim3(1024), dim3(256), 0, g.xstream, L0.L, upd->X, upd->D, c, upd->t);
     UF_HIP_CHECK(hipEventRecord(g.ev_xjoin, g.xstream));
     xfork = true;

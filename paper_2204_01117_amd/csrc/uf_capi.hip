@@ -1139,7 +1139,7 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
   UF_HIP_CHECK(hipEventCreate(&g->ev0));
   UF_HIP_CHECK(hipEventCreate(&g->ev1));
   UF_HIP_CHECK(hipStreamCreateWithFlags(&g->xstream, hipStreamNonBlocking));
-  UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_xfork, hipEventDisableTiming));
+  UF_HIP_CHECK(hipEventCreate(&g->ev_xfork));   // completed inside a dispatch (hipExtLaunchKernel)
   UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_xjoin, hipEventDisableTiming));
   UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (g->esize == 4) {

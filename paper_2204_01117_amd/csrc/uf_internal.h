@@ -292,4 +292,28 @@ inline void launch_k(Grid& g, void (*kernel)(Args...), dim3 grid, dim3 block, A.
     hipLaunchKernelGGL(kernel, grid, block, 0, g.stream, static_cast<Args>(args)...);
 }
 
+// launch_k whose dispatch also completes an event, for another stream to
+// wait on: `done`, or the timer's stop event when the kernel timer covers
+// the launch (returned).  Outside stream capture the event travels in the
+// dispatch itself; a separate record would put a marker packet between
+// this kernel and the next one on g.stream (about 6 us at the queue).
+template <typename... Args, typename... A>
+inline hipEvent_t launch_k_done(Grid& g, hipEvent_t done, void (*kernel)(Args...), dim3 grid, dim3 block,
+                                A... args) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  UF_HIP_CHECK(hipStreamIsCapturing(g.stream, &cap));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timer_pair(g, &e0, &e1)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, g.stream, e0, e1, 0, static_cast<Args>(args)...);
+    return e1;
+  }
+  if (cap != hipStreamCaptureStatusNone) {
+    hipLaunchKernelGGL(kernel, grid, block, 0, g.stream, static_cast<Args>(args)...);
+    UF_HIP_CHECK(hipEventRecord(done, g.stream));
+  } else {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, g.stream, nullptr, done, 0, static_cast<Args>(args)...);
+  }
+  return done;
+}
+
 }  // namespace uf
