@@ -1778,7 +1778,7 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
   }
   if (mgeo.use && upd) {
     // x += alpha d of the iteration on the second stream, beside the
-    // coarse levels; joined at the end of this application (at 256x256x64,
+    // coarse levels; joined before the next iteration (at 256x256x64,
     // where the tiled kernel keeps the update, a separate pass and the
     // stream switch cost more than they save: 1.34 -> 1.43 ms per step)
     UF_HIP_CHECK(hipStreamWaitEvent(g.xstream, fork, 0));
@@ -1822,7 +1822,7 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
     else
       launch_up<true, false, T>(g, K, L0, L1, c, m);
   }
-  if (xfork) UF_HIP_CHECK(hipStreamWaitEvent(g.stream, g.ev_xjoin, 0));
+  if (xfork) g.xpending = true;   // joined by the next d/q kernel or the solve's end
 }
 
 template <class T>

@@ -556,6 +556,7 @@ void launch_cg_iteration(Grid& g, const Params<T>& P, int t) {
   const CgCtl c = make_ctl(g);
   void* Dold = g.D[t & 1];
   void* Dnew = g.D[(t + 1) & 1];
+  join_x(g);
   {
     TimedLaunch tl(g, UF_TK_CG_AD);
     const AdLaunch al = ad_launch(P.L);

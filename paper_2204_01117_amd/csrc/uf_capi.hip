@@ -93,6 +93,12 @@ void* galloc(Grid& g, size_t bytes) {
   return p;
 }
 
+void join_x(Grid& g) {
+  if (!g.xpending) return;
+  UF_HIP_CHECK(hipStreamWaitEvent(g.stream, g.ev_xjoin, 0));
+  g.xpending = false;
+}
+
 void upload(Grid& g, void* dst, const void* src, size_t bytes) {
   UF_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, g.stream));
   UF_HIP_CHECK(hipStreamSynchronize(g.stream));
@@ -333,6 +339,7 @@ SolveResult solve_end(Grid& g, const Params<T>& P) {
     if (g.st_host->done || g.cg_t >= maxit) break;
     solve_chunk<T>(g, P);
   }
+  join_x(g);
   SolveResult res;
   const CgState& s = *g.st_host;
   res.iters = s.iter;
@@ -909,6 +916,7 @@ void capture_solve(Batch& b, size_t c) {
     for (int t = 0; t < b.kcap[c]; ++t) launch_cg_iteration<T>(g, P, t);
     launch_cg_status(g, b.kcap[c]);
     UF_HIP_CHECK(hipMemcpyAsync(g.st_host, g.st, sizeof(CgState), hipMemcpyDeviceToHost, b.cs[c]));
+    join_x(g);
   });
 }
 
@@ -971,6 +979,7 @@ void batch_steps(Batch& b, int nsteps, std::vector<StepAccum>& acc) {
         solve_chunk<T>(g, P);
         wait_status(g);
       }
+      join_x(g);
       const CgState& st = *g.st_host;
       g.last_iters = st.iter;
       acc[c].iters_total += st.iter;

@@ -153,6 +153,7 @@ struct Grid {
   // after the level-0 restriction and joined before the next iteration
   hipStream_t xstream = nullptr;
   hipEvent_t ev_xfork = nullptr, ev_xjoin = nullptr;
+  bool xpending = false;        // an update on xstream not yet joined (join_x)
   std::vector<MgLevel> mg;
   int mg_lt = 0;                // first level of the single-workgroup kernel
   bool mg_tail_lds = true;      // the small levels fit the LDS pool of the single-workgroup kernel
@@ -173,6 +174,13 @@ struct Grid {
   int k_in_valid = 1;
   double k_in = 0, w_in = 0, nu_max = 0;
 };
+
+// Make the grid's stream wait for the iterate update last forked onto the
+// second solve stream, if it has not yet: before the next iteration's d/q
+// kernel (which overwrites the d that update reads) and before anything
+// reads the pressure after a solve.  The solve's status check runs before
+// the join, beside the last update.
+void join_x(Grid& g);
 
 // Device memory of the grid: its configured allocator, else hipMalloc.
 void* galloc(Grid& g, size_t bytes);
