@@ -245,8 +245,8 @@ uf_status uf_smooth_porosity(const uf_smooth_objects* objects, int32_t dtype, vo
  * y0, y1, z0, z1, phi) then 6 per cylinder (cx, cy, R, z0, z1, phi).  Each
  * cell follows the first object reaching its minimum (the branch the
  * forward took); a ground-standing object (z0 <= 0) has no z0 derivative.
- * FP64; per-block sums use atomic adds, so the last bits may differ
- * between runs.  Synchronises `stream`.  UF_EINVAL as uf_smooth_porosity,
+ * FP64, summed in a fixed order (the same bits on every run).  Synchronises
+ * `stream`.  UF_EINVAL as uf_smooth_porosity,
  * and for more than UF_MAX_GRAD_OBJECTS objects. */
 enum { UF_MAX_GRAD_OBJECTS = 1024 };
 uf_status uf_smooth_porosity_grad(const uf_smooth_objects* objects, const double* phibar_dev, double* grad_host,

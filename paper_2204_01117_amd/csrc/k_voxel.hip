@@ -279,83 +279,112 @@ __global__ __launch_bounds__(kVoxThreads) void k_smooth_porosity(const double* _
 // dphi/dphi_o = I and dphi/dp = -(1 - phi_o) dI/dp for a face or radius
 // parameter p, where dI/dp = I (1 - L) dt/dp for the logistic factor L(t)
 // that holds p (1 - L(t) = L(-t), no division).  Each block sums
-// phibar dphi/dp per object parameter (8 slots per object) in LDS with
-// FP64 atomic adds -- their order, and so the last bits, are not fixed --
-// and writes its row of partials; the host adds the rows in block order.
+// phibar dphi/dp per object parameter (8 slots per object) in LDS and
+// writes its row of partials; the host adds the rows in block order.  The
+// sums take a fixed order, so the result is the same bits on every run: the
+// block takes 256 cells at a time, each cell's object and seven terms go to
+// LDS, and for each object present the first cell that holds it adds the
+// terms of all its cells, in cell order, to that object's slots (no two
+// threads write one slot).
 __global__ __launch_bounds__(kVoxThreads) void k_smooth_porosity_grad(const double* __restrict__ obj, int nobj,
                                                                      int nx, int ny, int nz, double dx, double dy,
                                                                      double dz, double s,
                                                                      const double* __restrict__ phibar,
                                                                      double* __restrict__ part) {
   extern __shared__ double acc[];
+  __shared__ int sb[kVoxThreads];           // object of each cell of the round (-1: none)
+  __shared__ double sv[7][kVoxThreads];     // its seven terms phibar dphi/dp
   const int nslot = 8 * nobj;
   for (int q = threadIdx.x; q < nslot; q += blockDim.x) acc[q] = 0.0;
-  __syncthreads();
   const size_t n = (size_t)nx * ny * nz;
-  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (size_t)gridDim.x * blockDim.x) {
-    const double pb = phibar[c];
-    if (pb == 0.0) continue;
-    const int k = (int)(c % nz);
-    const int j = (int)((c / nz) % ny);
-    const int i = (int)(c / ((size_t)nz * ny));
-    const double px = ((double)i + 0.5) * dx, py = ((double)j + 0.5) * dy, pz = ((double)k + 0.5) * dz;
-    double v = 1.0;
-    int best = -1;
-    for (int o = 0; o < nobj; ++o) {
-      const double* a = obj + 8 * o;
-      double ind, po;
-      if (a[7] == 0.0) {
-        const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
-        const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
-        const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
-        ind = fx * fy * fz;
-        po = a[6];
-      } else {
-        const double rho = sqrt((px - a[0]) * (px - a[0]) + (py - a[1]) * (py - a[1]));
-        const double fr = logistic((a[2] - rho) / s);
-        const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
-        ind = fr * fz;
-        po = a[5];
+  const int t = threadIdx.x;
+  for (size_t base = (size_t)blockIdx.x * blockDim.x; base < n; base += (size_t)gridDim.x * blockDim.x) {
+    const size_t c = base + t;
+    int bsel = -1;
+    double term[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double pb = c < n ? phibar[c] : 0.0;
+    if (pb != 0.0) {
+      const int k = (int)(c % nz);
+      const int j = (int)((c / nz) % ny);
+      const int i = (int)(c / ((size_t)nz * ny));
+      const double px = ((double)i + 0.5) * dx, py = ((double)j + 0.5) * dy, pz = ((double)k + 0.5) * dz;
+      double v = 1.0;
+      int best = -1;
+      for (int o = 0; o < nobj; ++o) {
+        const double* a = obj + 8 * o;
+        double ind, po;
+        if (a[7] == 0.0) {
+          const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
+          const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
+          const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
+          ind = fx * fy * fz;
+          po = a[6];
+        } else {
+          const double rho = sqrt((px - a[0]) * (px - a[0]) + (py - a[1]) * (py - a[1]));
+          const double fr = logistic((a[2] - rho) / s);
+          const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
+          ind = fr * fz;
+          po = a[5];
+        }
+        const double val = 1.0 - ind * (1.0 - po);
+        if (val < v) {
+          v = val;
+          best = o;
+        }
       }
-      const double val = 1.0 - ind * (1.0 - po);
-      if (val < v) {
-        v = val;
-        best = o;
-      }
-    }
-    if (best < 0) continue;
-    const double* a = obj + 8 * best;
-    double d[7];   // dphi / d(parameter), in the object's parameter order
-    if (a[7] == 0.0) {
-      const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
-      const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
-      const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
-      const double ind = fx * fy * fz, m = -(1.0 - a[6]) * ind / s;
-      d[0] = -m * logistic(-(px - a[0]) / s);
-      d[1] = m * logistic(-(a[1] - px) / s);
-      d[2] = -m * logistic(-(py - a[2]) / s);
-      d[3] = m * logistic(-(a[3] - py) / s);
-      d[4] = a[4] > 0.0 ? -m * logistic(-(pz - a[4]) / s) : 0.0;
-      d[5] = m * logistic(-(a[5] - pz) / s);
-      d[6] = ind;
-    } else {
-      const double ex = px - a[0], ey = py - a[1];
-      const double rho = sqrt(ex * ex + ey * ey);
-      const double fr = logistic((a[2] - rho) / s);
-      const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
-      const double ind = fr * fz, m = -(1.0 - a[5]) * ind / s;
-      const double dr = m * logistic(-(a[2] - rho) / s);   // along R; the centre moves rho by -e/rho
-      d[0] = rho > 0.0 ? dr * ex / rho : 0.0;
-      d[1] = rho > 0.0 ? dr * ey / rho : 0.0;
-      d[2] = dr;
-      d[3] = a[3] > 0.0 ? -m * logistic(-(pz - a[3]) / s) : 0.0;
-      d[4] = m * logistic(-(a[4] - pz) / s);
-      d[5] = ind;
-      d[6] = 0.0;
-    }
+      if (best >= 0) {
+        const double* a = obj + 8 * best;
+        double d[7];   // dphi / d(parameter), in the object's parameter order
+        if (a[7] == 0.0) {
+          const double fx = logistic((px - a[0]) / s) * logistic((a[1] - px) / s);
+          const double fy = logistic((py - a[2]) / s) * logistic((a[3] - py) / s);
+          const double fz = logistic((a[5] - pz) / s) * (a[4] > 0.0 ? logistic((pz - a[4]) / s) : 1.0);
+          const double ind = fx * fy * fz, m = -(1.0 - a[6]) * ind / s;
+          d[0] = -m * logistic(-(px - a[0]) / s);
+          d[1] = m * logistic(-(a[1] - px) / s);
+          d[2] = -m * logistic(-(py - a[2]) / s);
+          d[3] = m * logistic(-(a[3] - py) / s);
+          d[4] = a[4] > 0.0 ? -m * logistic(-(pz - a[4]) / s) : 0.0;
+          d[5] = m * logistic(-(a[5] - pz) / s);
+          d[6] = ind;
+        } else {
+          const double ex = px - a[0], ey = py - a[1];
+          const double rho = sqrt(ex * ex + ey * ey);
+          const double fr = logistic((a[2] - rho) / s);
+          const double fz = logistic((a[4] - pz) / s) * (a[3] > 0.0 ? logistic((pz - a[3]) / s) : 1.0);
+          const double ind = fr * fz, m = -(1.0 - a[5]) * ind / s;
+          const double dr = m * logistic(-(a[2] - rho) / s);   // along R; the centre moves rho by -e/rho
+          d[0] = rho > 0.0 ? dr * ex / rho : 0.0;
+          d[1] = rho > 0.0 ? dr * ey / rho : 0.0;
+          d[2] = dr;
+          d[3] = a[3] > 0.0 ? -m * logistic(-(pz - a[3]) / s) : 0.0;
+          d[4] = m * logistic(-(a[4] - pz) / s);
+          d[5] = ind;
+          d[6] = 0.0;
+        }
 #pragma unroll
-    for (int q = 0; q < 7; ++q)
-      if (d[q] != 0.0) atomicAdd(&acc[8 * best + q], pb * d[q]);
+        for (int q = 0; q < 7; ++q) term[q] = pb * d[q];
+        bsel = best;
+      }
+    }
+    __syncthreads();   // the previous round's reduction is done with sb, sv
+    sb[t] = bsel;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) sv[q][t] = term[q];
+    __syncthreads();
+    // the first cell of the round holding its object reduces that object
+    bool lead = bsel >= 0 && (t == 0 || sb[t - 1] != bsel);
+    for (int u = 0; lead && u < t - 1; ++u) lead = sb[u] != bsel;
+    if (lead) {
+      double sum[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int u = t; u < (int)blockDim.x; ++u) {
+        if (sb[u] != bsel) continue;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) sum[q] += sv[q][u];
+      }
+#pragma unroll
+      for (int q = 0; q < 7; ++q) acc[8 * bsel + q] += sum[q];
+    }
   }
   __syncthreads();
   for (int q = threadIdx.x; q < nslot; q += blockDim.x) part[(size_t)blockIdx.x * nslot + q] = acc[q];

@@ -71,3 +71,32 @@ def test_design_map_moves_objects_continuously():
     t2[1] += 0.05
     mid = d.porosity(t2).cpu().numpy()
     assert np.abs(mid - phi0).max() < diff.max()
+
+
+def _many_objects(seed, n, h, nb, nc):
+    rng = np.random.default_rng(seed)
+    ext = [n[a] * h[a] for a in range(3)]
+    boxes = []
+    for _ in range(nb):
+        x0, y0 = rng.uniform(0, 0.8 * ext[0]), rng.uniform(0, 0.8 * ext[1])
+        boxes.append([x0, x0 + rng.uniform(2, 0.3 * ext[0]), y0, y0 + rng.uniform(2, 0.3 * ext[1]),
+                      0.0, rng.uniform(2, 0.7 * ext[2]), rng.uniform(0.0, 0.8)])
+    cyls = [[rng.uniform(0, ext[0]), rng.uniform(0, ext[1]), rng.uniform(1, 0.2 * min(ext[:2])), 0.0,
+             rng.uniform(2, 0.6 * ext[2]), rng.uniform(0.2, 0.8)] for _ in range(nc)]
+    return np.array(boxes).reshape(-1, 7), np.array(cyls).reshape(-1, 6)
+
+
+@pytest.mark.parametrize("nb,nc", [(6, 5), (700, 324)])
+def test_smooth_porosity_grad_is_the_same_bits_every_run(nb, nc):
+    """The design-porosity gradient sums its per-cell terms in a fixed
+    order: repeated calls (and repeated calls of the allocation-free
+    variant) give the same bits, up to the object limit."""
+    n, h = (48, 40, 24), (2.0, 2.0, 1.5)
+    boxes, cyls = _many_objects(11, n, h, nb, nc)
+    gen = torch.Generator().manual_seed(5)
+    phibar = torch.randn(n, dtype=torch.float64, generator=gen).to("cuda:0")
+    for noalloc in (False, True):
+        runs = [U.smooth_porosity_grad(n, h, boxes, cyls, 1.0, phibar, noalloc=noalloc) for _ in range(3)]
+        for gb, gc in runs[1:]:
+            assert np.array_equal(gb, runs[0][0]) and np.array_equal(gc, runs[0][1])
+        assert np.count_nonzero(runs[0][0]) > 0
