@@ -719,6 +719,25 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
     };
     const int fe0 = 2 * I0 - 2, fe1 = 2 * I1 + 1;   // e planes
     load_plane(fe0);
+    // the (j, k) part of the boundary classes of the thread's own and ring
+    // entries and of its residual entries, and the residual entries' e
+    // positions: fixed for the whole march
+    constexpr int NRU = (X::NR + 255) / 256;
+    int ocyz[4], gcyz[2], qcyz[NRU], qpe[NRU];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ocyz[u] = (bclass(j0 + jr + X::ROWS * u, L.ny) << 2) | bclass(k, L.nz);
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int ej = rpos[v] / X::EK, ek = rpos[v] - ej * X::EK;
+      gcyz[v] = (bclass(j0 - 2 + ej, L.ny) << 2) | bclass(k0 - 2 + ek, L.nz);
+    }
+#pragma unroll
+    for (int u = 0; u < NRU; ++u) {
+      const int q = min(tid + 256 * u, X::NR - 1);
+      const int rj = q / X::RK, rk = q - rj * X::RK;
+      qpe[u] = (rj + 1) * X::EK + rk + 1;
+      qcyz[u] = (bclass(j0 - 1 + rj, L.ny) << 2) | bclass(k0 - 1 + rk, L.nz);
+    }
     __syncthreads();   // tables in place
     T wi_cur[4], wi_prev[4];
     int Icur = I0;
@@ -734,8 +753,7 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
       for (int u = 0; u < 4; ++u) {
         const T r = CGU ? orr[u] - alpha * oq[u] : orr[u];
         const int jj = jr + X::ROWS * u;
-        const int cl = cx | (bclass(j0 + jj, L.ny) << 2) | bclass(k, L.nz);
-        e[(jj + 2) * X::EK + kk + 2] = tab_omd[cl] * r;
+        e[(jj + 2) * X::EK + kk + 2] = tab_omd[cx | ocyz[u]] * r;
         if (CGU && upd_plane && jin[u] && kin) {
           const long long o = (long long)(f + 1) * L.SX + (long long)(jg[u] + 1) * L.PZ + (kg + 1);
           F.r[o] = r;
@@ -745,9 +763,7 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         if (!ron[v]) continue;
-        const int ej = rpos[v] / X::EK, ek = rpos[v] - ej * X::EK;
-        const int cl = cx | (bclass(j0 - 2 + ej, L.ny) << 2) | bclass(k0 - 2 + ek, L.nz);
-        e[rpos[v]] = tab_omd[cl] * (CGU ? rr_[v] - alpha * rq_[v] : rr_[v]);
+        e[rpos[v]] = tab_omd[cx | gcyz[v]] * (CGU ? rr_[v] - alpha * rq_[v] : rr_[v]);
       }
       if (f < fe1) load_plane(f + 1);
       __syncthreads();
@@ -759,12 +775,13 @@ __global__ __launch_bounds__(256) void k_mg_update_march(MgCommon<T> K, MgLvl<T>
         const T* ec = se[(fr + 3) % 3];
         const T* ep = e;
         const int crx = bclass(fr, L.nx) << 4;
-        for (int q = tid; q < X::NR; q += 256) {
-          const int rj = q / X::RK, rk = q - rj * X::RK;
-          const int pe = (rj + 1) * X::EK + rk + 1;
-          const int cl = crx | (bclass(j0 - 1 + rj, L.ny) << 2) | bclass(k0 - 1 + rk, L.nz);
-          sres[q] = tab_a[cl] * ec[pe] + F.w[0] * (ep[pe] + em[pe]) + F.w[1] * (ec[pe + X::EK] + ec[pe - X::EK]) +
-                    F.w[2] * (ec[pe + 1] + ec[pe - 1]);
+#pragma unroll
+        for (int u = 0; u < NRU; ++u) {
+          const int q = tid + 256 * u;
+          if (q >= X::NR) break;
+          const int pe = qpe[u];
+          sres[q] = tab_a[crx | qcyz[u]] * ec[pe] + F.w[0] * (ep[pe] + em[pe]) +
+                    F.w[1] * (ec[pe + X::EK] + ec[pe - X::EK]) + F.w[2] * (ec[pe + 1] + ec[pe - 1]);
         }
       }
       __syncthreads();
