@@ -1723,6 +1723,10 @@ static MarchGeom march_geom(const MgLevel& F, const MgLevel& C) {
   return m;
 }
 
+bool mg_splits_update(const Grid& g) {
+  return g.mg_fused && g.mg.size() > 1 && march_geom(g.mg[0], g.mg[1]).use;
+}
+
 // Launch size of a marching restriction: 8 * ceil(n / 8) blocks for the
 // ntot walkers and, in mode 1, the deciding block (logical block ntot).
 static int march_blocks(const MarchGeom& m, int mode) {
@@ -1794,6 +1798,7 @@ void mg_launch(Grid& g, const Params<T>& P, int m, const void* r, void* z, int d
       launch_restrict<T>(g, K, L0, L1, nl > 1 ? 1 : 0, c, m, decide ? 1 : 2, upd);
   }
   if (mgeo.use && upd) {
+    if (!g.xstream) throw HipError("the second solve stream is missing");   // made with the grid (mg_splits_update)
     // x += alpha d of the iteration on the second stream, beside the
     // coarse levels; joined before the next iteration (at 256x256x64,
     // where the tiled kernel keeps the update, a separate pass and the

@@ -1147,9 +1147,6 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
   UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_status, hipEventDisableTiming));
   UF_HIP_CHECK(hipEventCreate(&g->ev0));
   UF_HIP_CHECK(hipEventCreate(&g->ev1));
-  UF_HIP_CHECK(hipStreamCreateWithFlags(&g->xstream, hipStreamNonBlocking));
-  UF_HIP_CHECK(hipEventCreate(&g->ev_xfork));   // completed inside a dispatch (hipExtLaunchKernel)
-  UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_xjoin, hipEventDisableTiming));
   UF_HIP_CHECK(hipStreamSynchronize(g->stream));
   if (g->esize == 4) {
     upload_inflow<float>(*g);
@@ -1169,6 +1166,14 @@ uf_status uf_create_grid(const uf_config* cfg, uf_grid* out) {
     g->part_stride = std::max(std::max(g->cg_nb, g->cg_nb_rr), std::max(g->cg_nb_rz, g->cg_nb_dq));
     g->partials = (double*)galloc(*g, S_NSLOT_HOST * g->part_stride * sizeof(double));
     UF_HIP_CHECK(hipMemsetAsync(g->partials, 0, S_NSLOT_HOST * g->part_stride * sizeof(double), g->stream));
+  }
+  if (mg_splits_update(*g)) {
+    // only grids whose iterations use it get the second stream: every
+    // stream takes one of the process's few hardware queues, and a batch of
+    // grids with idle second streams left fewer queues to its case streams
+    UF_HIP_CHECK(hipStreamCreateWithFlags(&g->xstream, hipStreamNonBlocking));
+    UF_HIP_CHECK(hipEventCreate(&g->ev_xfork));   // completed inside a dispatch (hipExtLaunchKernel)
+    UF_HIP_CHECK(hipEventCreateWithFlags(&g->ev_xjoin, hipEventDisableTiming));
   }
   if (g->esize == 4) init_state<float>(*g);
   else init_state<double>(*g);

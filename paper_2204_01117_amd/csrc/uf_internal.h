@@ -251,6 +251,9 @@ template <class T> void mg_setup(Grid& g);
 template <class T> void mg_precond(Grid& g, const Params<T>& P, int m);
 template <class T> void mg_iteration_update(Grid& g, const Params<T>& P, int t, const void* Dnew);
 size_t mg_fused_blocks(const Grid& g);
+// Whether the CG iterations run x += alpha d on the second solve stream
+// (the level-0 restriction marches and carries the residual update only).
+bool mg_splits_update(const Grid& g);
 template <class T> void mg_apply(Grid& g, const Params<T>& P, const void* r, void* z);
 void mg_free(Grid& g);
 
