@@ -81,3 +81,34 @@ def test_cpu_baseline_slab_is_an_eighth_of_the_workload():
     assert c["nx"] * 8 == cfg["nx"] and c["ny"] == cfg["ny"] and c["nz"] == cfg["nz"] and c["dtype"] == "f64"
     assert np.array_equal(ph, phi[3 * c["nx"]:4 * c["nx"]])
     assert c["wind_dir_deg"] == cfg["wind_dir_deg"] and c["bc"] == cfg["bc"]
+
+
+def test_every_profiled_kernel_has_bytes_and_sources():
+    """Each kernel name the profiler summaries map to has an algorithmic byte
+    count and source files (so its counter record can go stale), and the
+    marching split moves the fused update's bytes: residual update plus the
+    iterate update on the second stream."""
+    names = {n for _, n in bench.PROFILE_NAMES}
+    for n in names:
+        assert n in bench.ALG_BYTES_PER_CELL, n
+        assert n in bench.KERNEL_FILES, n
+    assert bench.profile_name("void uf::k_mg_update_march<true, float>(...)") == "mg_rupd0"
+    assert bench.profile_name("void uf::k_cg_xupd<float>(...)") == "cg_xupd"
+    assert bench.profile_name("void uf::k_mg_restrict<true, float>(...)") == "mg_update0"
+    b = bench.ALG_BYTES_PER_CELL
+    assert b["mg_rupd0"] + b["cg_xupd"] == pytest.approx(b["mg_update0"])
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(ROOT, "paper_2204_01117_amd", "libuf.so")),
+                    reason="libuf.so not built")
+def test_timer_names_follow_the_header_enum():
+    """The binding's kernel-timer names are indexed by the UF_TK_* ids of
+    include/uf.h."""
+    import re
+    import paper_2204_01117_amd as U
+    src = open(os.path.join(ROOT, "include", "uf.h")).read()
+    ids = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"UF_TK_(\w+) = (\d+)", src))
+    assert len(U.TIMED_KERNELS) == ids["COUNT"]
+    assert U.TIMED_KERNELS[ids["MG_RUPD0"]] == "mg_rupd0"
+    assert U.TIMED_KERNELS[ids["MG_UPDATE0"]] == "mg_update0"
+    assert U.TIMED_KERNELS[ids["CG_AD"]] == "cg_Ad"
