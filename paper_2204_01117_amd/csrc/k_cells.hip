@@ -99,8 +99,10 @@ __device__ __forceinline__ void turb_cells(const Params<T>& P, const T* __restri
   store_cell(NUT, P, i, j, k, nut_new, false, T(0));
 }
 
+// gate: as k_project's (the step's k-omega update enqueued with it).
 template <class T>
-__global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ K0, const T* __restrict__ W0, T* __restrict__ K1, T* __restrict__ W1, T* __restrict__ NUT, int update_kw, int* nf) {
+__global__ __launch_bounds__(kCellBlock) void k_turbulence(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ K0, const T* __restrict__ W0, T* __restrict__ K1, T* __restrict__ W1, T* __restrict__ NUT, int update_kw, int* nf, const int* __restrict__ gate) {
+  if (gate && !*gate) return;
   int bx, ib;
   if (!cell_block(P.L, bx, ib)) return;
   turb_cells(P, U, V, W, K0, W0, K1, W1, NUT, update_kw, nf, bx, ib);
@@ -269,11 +271,11 @@ static inline dim3 cell_grid(const Layout& L) { return xcd_grid(cell_gx(L), L.nx
 
 template <class T>
 void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1,
-                 void* NUT, int update_kw) {
+                 void* NUT, int update_kw, const int* gate) {
   TimedLaunch tl(g, UF_TK_TURB);
   launch_k(g, k_turbulence<T>, cell_grid(P.L), dim3(kCellBlock), P, (const T*)Q[0],
                      (const T*)Q[1], (const T*)Q[2], (const T*)K0, (const T*)W0, (T*)K1, (T*)W1, (T*)NUT, update_kw,
-                     nf_word(g));
+                     nf_word(g), gate);
 }
 
 // The k-omega update of every case of a batch in one persistent launch
@@ -413,7 +415,7 @@ template void launch_region_speed<double>(Grid&, const int[6], double*, int);
 
 #define UF_INST(T)                                                                                            \
   template void launch_turb<T>(Grid&, const Params<T>&, void* const[3], const void*, const void*, void*, void*, \
-                               void*, int);                                                                 \
+                               void*, int, const int*);                                                     \
   template void launch_diag<T>(Grid&, const Params<T>&);                                                     \
   template void launch_porosity<T>(Grid&, const Params<T>&, const void*);                                    \
   template void launch_cell_bc<T>(Grid&, const Params<T>&, void*, int, double);                              \

@@ -255,8 +255,11 @@ __device__ __forceinline__ void project_faces(const Params<T>& P, const T* __res
   finish_face<2>(P, Wo, i, j, k, a2);
 }
 
+// gate: when given, the launch does nothing unless *gate is set (a step's
+// projection enqueued before the host has read whether the solve ended).
 template <class T>
-__global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Pp, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo) {
+__global__ __launch_bounds__(kFaceBlock) void k_project(Params<T> P, const T* __restrict__ U, const T* __restrict__ V, const T* __restrict__ W, const T* __restrict__ Pp, T* __restrict__ Uo, T* __restrict__ Vo, T* __restrict__ Wo, const int* __restrict__ gate) {
+  if (gate && !*gate) return;
   int bx, ib;
   if (!face_block(P.L, bx, ib)) return;
   project_faces(P, U, V, W, Pp, Uo, Vo, Wo, bx, ib);
@@ -392,10 +395,10 @@ void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qo
 }
 
 template <class T>
-void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]) {
+void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3], const int* gate) {
   TimedLaunch tl(g, UF_TK_PROJECT);
   launch_k(g, k_project<T>, face_grid(P.L), dim3(kFaceBlock), P, (const T*)Qin[0],
-                     (const T*)Qin[1], (const T*)Qin[2], (const T*)g.X, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2]);
+                     (const T*)Qin[1], (const T*)Qin[2], (const T*)g.X, (T*)Qout[0], (T*)Qout[1], (T*)Qout[2], gate);
 }
 
 template <class T>
@@ -418,7 +421,7 @@ void launch_face_init(Grid& g, const Params<T>& P, void* const Q[3]) {
   template void launch_advect<T>(Grid&, const Params<T>&, void* const[3], void* const[3], void* const[3]); \
   template void launch_diffuse<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);          \
   template void launch_drag<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);             \
-  template void launch_project<T>(Grid&, const Params<T>&, void* const[3], void* const[3]);          \
+  template void launch_project<T>(Grid&, const Params<T>&, void* const[3], void* const[3], const int*); \
   template void launch_face_bc<T>(Grid&, const Params<T>&, void*, int);                             \
   template void launch_face_init<T>(Grid&, const Params<T>&, void* const[3]);                      \
   template void launch_faces_multi<T>(int, const MultiCase<T>*, const CaseStarts&, int, int, int, int, int, hipStream_t);

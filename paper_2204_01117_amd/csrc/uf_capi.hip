@@ -299,6 +299,7 @@ struct SolveResult {
   double rel = 0;
   int noconv = 0, nonfinite = 0;
   int nf_state = 0;   // the state's non-finite flag as of this solve's status
+  bool first_final = false;   // the first chunk's status already ended the solve
 };
 
 // Pressure solve: r0 = b - A x0 and the stopping threshold, the first
@@ -334,13 +335,17 @@ void solve_begin(Grid& g, const Params<T>& P, void* const Qs[3], const void* b) 
 template <class T>
 SolveResult solve_end(Grid& g, const Params<T>& P) {
   const int maxit = g.cfg.cg_maxit;
+  bool first = true, first_final = false;
   while (true) {
     wait_status(g);
+    if (first) first_final = g.st_host->done != 0;
+    first = false;
     if (g.st_host->done || g.cg_t >= maxit) break;
     solve_chunk<T>(g, P);
   }
   join_x(g);
   SolveResult res;
+  res.first_final = first_final;
   const CgState& s = *g.st_host;
   res.iters = s.iter;
   res.rel = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
@@ -399,8 +404,20 @@ void step_begin(Grid& g, const Params<T>& P) {
 template <class T>
 void step_end(Grid& g, const Params<T>& P, StepAccum& acc) {
   const int st = g.cfg.stages;
+  const bool turb = (st & UF_STAGE_TURB) && g.cfg.turb_model == UF_TURB_KOMEGA;
   {
     if (st & UF_STAGE_PROJECT) {
+      // The projection and the k-omega update are enqueued before the host
+      // reads whether the first chunk of iterations ended the solve, gated
+      // on the device's verdict (the status the host then reads): in the
+      // usual case they run without waiting for that read; when the solve
+      // goes on they skip, and run again after it.
+      const int out = free_set(g, -1);
+      const int kn = g.kcur ^ 1;
+      const int* gate = &g.st->done;
+      join_x(g);
+      launch_project<T>(g, P, g.Q[g.cur], g.Q[out], gate);
+      if (turb) launch_turb<T>(g, P, g.Q[out], g.K[g.kcur], g.Wo[g.kcur], g.K[kn], g.Wo[kn], g.NUT, 1, gate);
       SolveResult r = solve_end<T>(g, P);
       acc.iters_total += r.iters;
       acc.last_iters = r.iters;
@@ -409,11 +426,13 @@ void step_end(Grid& g, const Params<T>& P, StepAccum& acc) {
       acc.noconv |= r.noconv;
       acc.nonfinite |= r.nonfinite;
       acc.nf_state |= r.nf_state;
-      const int out = free_set(g, -1);
-      launch_project<T>(g, P, g.Q[g.cur], g.Q[out]);
+      if (!r.first_final) {
+        launch_project<T>(g, P, g.Q[g.cur], g.Q[out]);
+        if (turb) launch_turb<T>(g, P, g.Q[out], g.K[g.kcur], g.Wo[g.kcur], g.K[kn], g.Wo[kn], g.NUT, 1);
+      }
       g.cur = out;
-    }
-    if ((st & UF_STAGE_TURB) && g.cfg.turb_model == UF_TURB_KOMEGA) {
+      if (turb) g.kcur = kn;
+    } else if (turb) {
       const int kn = g.kcur ^ 1;
       launch_turb<T>(g, P, g.Q[g.cur], g.K[g.kcur], g.Wo[g.kcur], g.K[kn], g.Wo[kn], g.NUT, 1);
       g.kcur = kn;

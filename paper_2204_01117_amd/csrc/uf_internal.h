@@ -202,9 +202,9 @@ template <class T> Params<T> make_params(const Grid& g);
 template <class T> void launch_advect(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qhat[3], void* const Qout[3]);
 template <class T> void launch_diffuse(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
 template <class T> void launch_drag(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
-template <class T> void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3]);
+template <class T> void launch_project(Grid& g, const Params<T>& P, void* const Qin[3], void* const Qout[3], const int* gate = nullptr);
 template <class T> void launch_face_bc(Grid& g, const Params<T>& P, void* q, int comp);
-template <class T> void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1, void* NUT, int update_kw);
+template <class T> void launch_turb(Grid& g, const Params<T>& P, void* const Q[3], const void* K0, const void* W0, void* K1, void* W1, void* NUT, int update_kw, const int* gate = nullptr);
 // device word the drag and k-omega kernels set on a non-finite output
 inline int* nf_word(Grid& g) { return &g.st->nf_state; }
 template <class T> void launch_cell_bc(Grid& g, const Params<T>& P, void* q, int use_inlet, double inlet_value);
