@@ -231,11 +231,19 @@ def _dispatches(run_dir, counter):
 
 
 def _per_kernel(disp):
-    """Average per dispatch by (kernel name, grid size)."""
+    """Average per dispatch by (kernel name, grid size).  Dispatches below 5%
+    of the largest of their group are left out: launches that returned at
+    once (a step's projection and k-omega update enqueued before the solve's
+    end was known skip when the solve went on, and run again after it)."""
     per = {}
     for name, grid, v in disp:
         per.setdefault((name, grid), []).append(v)
-    return {k: sum(v) / len(v) for k, v in per.items()}
+    out = {}
+    for k, v in per.items():
+        top = max(v)
+        kept = [x for x in v if x >= 0.05 * top] if top > 0 else v
+        out[k] = sum(kept) / len(kept)
+    return out
 
 
 def _copy_calibration(disp):
@@ -387,15 +395,37 @@ def stats_summary(run_dir, command, out_name="kernels_256x256x64.md",
     if not files:
         raise SystemExit("no *kernel_stats.csv under %s" % run_dir)
     rows = list(csv.DictReader(open(files[0])))
-    lines = ["# " + title, "",
-             "Command (from the repository root):", "", "    " + command, "",
-             "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
-    for r in rows:
-        name = r["Name"].split("(")[0].replace("void ", "").replace("uf::", "")
-        lines.append("| `%s` | %s | %.2f | %.3f | %.1f |" % (
-            name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
-            float(r["Percentage"])))
     traces = glob.glob(os.path.join(run_dir, "**", "*kernel_trace.csv"), recursive=True)
+    lines = ["# " + title, "",
+             "Command (from the repository root):", "", "    " + command, ""]
+    if traces:
+        # from the trace, without the launches that returned at once (under 15%
+        # of their kernel's median: CG iterations enqueued past convergence,
+        # and a step's projection and k-omega update enqueued before the
+        # solve's end was known, which skip when it went on)
+        per = {}
+        for r in csv.DictReader(open(traces[0])):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("uf::", "")
+            per.setdefault(name, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        kept, skipped = {}, 0
+        for name, d in per.items():
+            med = sorted(d)[len(d) // 2]
+            k = [x for x in d if x >= 0.15 * med]
+            skipped += len(d) - len(k)
+            kept[name] = k
+        total = sum(sum(k) for k in kept.values())
+        lines += ["Launches that returned at once (left out): %d." % skipped, "",
+                  "| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+        for name, d in sorted(kept.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("| `%s` | %d | %.2f | %.3f | %.1f |" % (name, len(d), sum(d) / len(d) / 1e3, sum(d) / 1e6,
+                                                                100.0 * sum(d) / total))
+    else:
+        lines += ["| kernel | calls | avg us | total ms | % |", "|---|---:|---:|---:|---:|"]
+        for r in rows:
+            name = r["Name"].split("(")[0].replace("void ", "").replace("uf::", "")
+            lines.append("| `%s` | %s | %.2f | %.3f | %.1f |" % (
+                name, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
+                float(r["Percentage"])))
     if traces:
         groups = {}
         for r in csv.DictReader(open(traces[0])):
